@@ -1,0 +1,243 @@
+"""TEST INFRASTRUCTURE ONLY: ctypes wrapper around the plain FP64 CPU oracle.
+
+The oracle (``oracle.c``) runs the Gibbs sampler of Algorithm 1 with the
+slice sampler of Algorithm 2 in the printed order, in double precision, with
+no grouping, blocking or reordering.  Only ``tests/``, the package smoke check
+and the benchmark's CPU-baseline leg may import this module.
+"""
+from __future__ import annotations
+
+import ctypes as C
+import os
+import subprocess
+
+import numpy as np
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+_SO = os.path.join(_HERE, "liboracle.so")
+
+KIND_EPS, KIND_GAMMA, KIND_NU, KIND_TAU, KIND_BETA, KIND_THETA, KIND_SIG2 = 1, 2, 3, 4, 5, 6, 7
+UPDATE_ALL = 0xFE
+
+
+def _so_path(mutant: int) -> str:
+    if mutant == 0:
+        return _SO
+    return os.path.join(_HERE, "build", f"liboracle_mutant{mutant}.so")
+
+
+def build(force: bool = True, mutant: int = 0) -> str:
+    """Compile liboracle.so with gcc (plain -O2, no fast-math, OpenMP over genes).
+
+    mutant > 0 builds a deliberately wrong variant (tests of the pins only)."""
+    so = _so_path(mutant)
+    if force or not os.path.exists(so):
+        os.makedirs(os.path.dirname(so), exist_ok=True)
+        cmd = ["gcc", "-O2", "-std=gnu11", "-fPIC", "-shared", "-fopenmp",
+               "-fno-fast-math", "-ffp-contract=off", f"-DOR_MUTANT={int(mutant)}",
+               os.path.join(_HERE, "oracle.c"), "-o", so + ".tmp", "-lm"]
+        subprocess.run(cmd, check=True)
+        os.replace(so + ".tmp", so)
+    return so
+
+
+class _Cfg(C.Structure):
+    _fields_ = [("G", C.c_int32), ("N", C.c_int32), ("L", C.c_int32),
+                ("y", C.POINTER(C.c_int32)), ("X", C.POINTER(C.c_double)),
+                ("h", C.POINTER(C.c_double)),
+                ("a", C.c_double), ("b", C.c_double), ("d", C.c_double),
+                ("c", C.POINTER(C.c_double)), ("s", C.POINTER(C.c_double)),
+                ("seed", C.c_uint64), ("chain", C.c_int32),
+                ("burnin", C.c_int64), ("tune_start", C.c_int64),
+                ("K", C.c_int32), ("w0", C.c_double), ("update_mask", C.c_uint32),
+                ("shrink_cap", C.c_int32)]
+
+
+_libs = {}
+
+
+def lib(path: str | None = None):
+    path = path or _SO
+    if path not in _libs:
+        if not os.path.exists(path):
+            build()
+        L = C.CDLL(path)
+        dp = C.POINTER(C.c_double)
+        ip = C.POINTER(C.c_int32)
+        L.or_create.argtypes = [C.POINTER(C.c_void_p), C.POINTER(_Cfg)]
+        L.or_destroy.argtypes = [C.c_void_p]
+        L.or_destroy.restype = None
+        L.or_set_counts.argtypes = [C.c_void_p, ip]
+        L.or_set_update_mask.argtypes = [C.c_void_p, C.c_uint32]
+        L.or_set_threads.argtypes = [C.c_void_p, C.c_int32]
+        L.or_init_default.argtypes = [C.c_void_p]
+        L.or_get_state.argtypes = [C.c_void_p] + [dp] * 12 + [C.POINTER(C.c_int64)]
+        L.or_set_state.argtypes = [C.c_void_p] + [dp] * 12 + [C.c_int64]
+        L.or_sweep.argtypes = [C.c_void_p, C.c_int64]
+        L.or_get_moments.argtypes = [C.c_void_p] + [dp] * 8 + [C.POINTER(C.c_int64)]
+        L.or_get_counts.argtypes = [C.c_void_p] + [ip] * 4 + [dp] * 4
+        L.or_error_count.argtypes = [C.c_void_p]
+        L.or_error_count.restype = C.c_int64
+        L.or_get_reductions.argtypes = [C.c_void_p, dp]
+        L.or_philox4x32_10.argtypes = [C.POINTER(C.c_uint32), C.POINTER(C.c_uint32),
+                                       C.POINTER(C.c_uint32)]
+        L.or_philox4x32_10.restype = None
+        L.or_slice_test.argtypes = [C.c_int32, dp, dp, dp, C.c_int64, C.c_double, C.c_int32,
+                                    C.c_uint64, C.c_uint32, ip]
+        _libs[path] = L
+    return _libs[path]
+
+
+def _p(a, t=C.c_double):
+    return None if a is None else a.ctypes.data_as(C.POINTER(t))
+
+
+def philox(ctr, key, _lib=None) -> np.ndarray:
+    c = (C.c_uint32 * 4)(*[int(v) & 0xFFFFFFFF for v in ctr])
+    k = (C.c_uint32 * 2)(*[int(v) & 0xFFFFFFFF for v in key])
+    o = (C.c_uint32 * 4)()
+    (_lib or lib()).or_philox4x32_10(c, k, o)
+    return np.array(list(o), dtype=np.uint32)
+
+
+def slice_test(target: int, params, x0, w: float, K: int = 15, seed: int = 1, m: int = 1,
+               with_counts: bool = False, _lib=None):
+    x0 = np.ascontiguousarray(x0, dtype=np.float64)
+    x1 = np.empty_like(x0)
+    prm = np.ascontiguousarray(np.resize(np.asarray(params, dtype=np.float64), 3))
+    cnt = np.zeros((x0.size, 4), dtype=np.int32) if with_counts else None
+    rc = (_lib or lib()).or_slice_test(target, _p(prm), _p(x0), _p(x1), x0.size, float(w), K, seed, m,
+                             _p(cnt, C.c_int32))
+    if rc not in (0, -4):
+        raise RuntimeError(f"or_slice_test rc={rc}")
+    return (x1, cnt) if with_counts else x1
+
+
+class State(dict):
+    """eps [G,N], gam [G], beta [G,L], hyp [2+2L], slice widths and m."""
+
+
+class Oracle:
+    """One chain of the plain sampler on one dataset."""
+
+    def __init__(self, y, X, h, *, a=1.0, b=1.0, d=1000.0, c=None, s=None, seed=1, chain=0,
+                 burnin=0, tune_start=0, K=15, w0=1.0, update_mask=UPDATE_ALL, shrink_cap=200,
+                 threads=1, init=True, _lib=None):
+        self._L = _lib or lib()
+        self.y = np.ascontiguousarray(y, dtype=np.int32)
+        self.X = np.ascontiguousarray(X, dtype=np.float64)
+        self.h = np.ascontiguousarray(h, dtype=np.float64)
+        self.G, self.N = self.y.shape
+        self.L = self.X.shape[1]
+        L = self.L
+        self.c = np.ascontiguousarray(np.full(L, 10.0) if c is None else c, dtype=np.float64)
+        self.s = np.ascontiguousarray(np.full(L, 100.0) if s is None else s, dtype=np.float64)
+        cfg = _Cfg(self.G, self.N, L, _p(self.y, C.c_int32), _p(self.X), _p(self.h),
+                   a, b, d, _p(self.c), _p(self.s), seed, chain, burnin, tune_start, K, w0,
+                   update_mask, shrink_cap)
+        self._h = C.c_void_p()
+        rc = self._L.or_create(C.byref(self._h), C.byref(cfg))
+        if rc != 0:
+            raise ValueError(f"or_create failed rc={rc}")
+        self.burnin = burnin
+        if threads != 1:
+            self._L.or_set_threads(self._h, threads)
+        if init:
+            self._L.or_init_default(self._h)
+
+    def close(self):
+        if self._h:
+            self._L.or_destroy(self._h)
+            self._h = C.c_void_p()
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    def set_threads(self, n: int):
+        self._L.or_set_threads(self._h, int(n))
+
+    def set_counts(self, y):
+        self.y = np.ascontiguousarray(y, dtype=np.int32)
+        self._L.or_set_counts(self._h, _p(self.y, C.c_int32))
+
+    def set_update_mask(self, mask: int):
+        self._L.or_set_update_mask(self._h, mask)
+
+    def sweep(self, n: int = 1) -> int:
+        return self._L.or_sweep(self._h, int(n))
+
+    def errors(self) -> int:
+        return self._L.or_error_count(self._h)
+
+    def get_state(self) -> State:
+        G, N, L = self.G, self.N, self.L
+        s = State(eps=np.empty((G, N)), gam=np.empty(G), beta=np.empty((G, L)),
+                  hyp=np.empty(2 + 2 * L), w_eps=np.empty((G, N)), waux_eps=np.empty((G, N)),
+                  w_gam=np.empty(G), waux_gam=np.empty(G), w_beta=np.empty((G, L)),
+                  waux_beta=np.empty((G, L)), w_hyp=np.empty(2 + L), waux_hyp=np.empty(2 + L))
+        m = C.c_int64()
+        self._L.or_get_state(self._h, *[_p(s[k]) for k in
+                                      ("eps", "gam", "beta", "hyp", "w_eps", "waux_eps", "w_gam",
+                                       "waux_gam", "w_beta", "waux_beta", "w_hyp", "waux_hyp")],
+                           C.byref(m))
+        s["m"] = int(m.value)
+        return s
+
+    def set_state(self, s):
+        keys = ("eps", "gam", "beta", "hyp", "w_eps", "waux_eps", "w_gam", "waux_gam", "w_beta",
+                "waux_beta", "w_hyp", "waux_hyp")
+        arrs = [None if s.get(k) is None else np.ascontiguousarray(s[k], dtype=np.float64)
+                for k in keys]
+        rc = self._L.or_set_state(self._h, *[_p(a) for a in arrs], int(s["m"]))
+        if rc != 0:
+            raise ValueError("or_set_state failed")
+
+    @property
+    def hyper(self):
+        st = self.get_state()
+        L = self.L
+        return dict(nu=st["hyp"][0], tau=st["hyp"][1], theta=st["hyp"][2:2 + L],
+                    sig2=st["hyp"][2 + L:])
+
+    def moments(self):
+        G, N, L = self.G, self.N, self.L
+        out = dict(mean_eps=np.empty((G, N)), msq_eps=np.empty((G, N)), mean_gam=np.empty(G),
+                   msq_gam=np.empty(G), mean_beta=np.empty((G, L)), msq_beta=np.empty((G, L)),
+                   mean_hyp=np.empty(2 + 2 * L), msq_hyp=np.empty(2 + 2 * L))
+        k = C.c_int64()
+        self._L.or_get_moments(self._h, *[_p(out[n]) for n in
+                                        ("mean_eps", "msq_eps", "mean_gam", "msq_gam", "mean_beta",
+                                         "msq_beta", "mean_hyp", "msq_hyp")], C.byref(k))
+        out["count"] = int(k.value)
+        return out
+
+    def counts(self):
+        G, N, L = self.G, self.N, self.L
+        out = dict(eps=np.empty((G, N, 4), np.int32), gam=np.empty((G, 4), np.int32),
+                   beta=np.empty((G, L, 4), np.int32), hyp=np.empty((2 + L, 4), np.int32),
+                   mrg_eps=np.empty((G, N)), mrg_gam=np.empty(G), mrg_beta=np.empty((G, L)),
+                   mrg_hyp=np.empty(2 + L))
+        self._L.or_get_counts(self._h, *[_p(out[k], C.c_int32) for k in ("eps", "gam", "beta", "hyp")],
+                            *[_p(out[k]) for k in ("mrg_eps", "mrg_gam", "mrg_beta", "mrg_hyp")])
+        return out
+
+    def reductions(self):
+        out = np.empty(2 + 2 * self.L)
+        self._L.or_get_reductions(self._h, _p(out))
+        return out
+
+
+def variant(mutant: int):
+    """A namespace like this module whose calls go to mutant library `mutant`."""
+    import functools
+    import types
+    L = lib(build(force=False, mutant=mutant))
+    return types.SimpleNamespace(
+        Oracle=functools.partial(Oracle, _lib=L),
+        slice_test=functools.partial(slice_test, _lib=L),
+        philox=functools.partial(philox, _lib=L),
+        KIND_EPS=KIND_EPS, KIND_GAMMA=KIND_GAMMA, KIND_NU=KIND_NU, KIND_TAU=KIND_TAU,
+        KIND_BETA=KIND_BETA, KIND_THETA=KIND_THETA, KIND_SIG2=KIND_SIG2, UPDATE_ALL=UPDATE_ALL)

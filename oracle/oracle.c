@@ -1,0 +1,780 @@
+/*
+ * oracle.c -- TEST INFRASTRUCTURE ONLY: the plain FP64 CPU sampler.
+ *
+ * Landau & Niemi, "A fully Bayesian strategy for high-dimensional hierarchical
+ * modeling using massively parallel computing" (arXiv 1606.06659).
+ *   Model:        Section 4.1, Fig. 3.
+ *   Gibbs order:  Algorithm 1 (steps 1-7), Section 4.2.
+ *   Slice draws:  Algorithm 2 (Appendix A), done in log space.
+ *   Moments:      Section 3.1 (Welford's one-pass mean and mean of squares).
+ *
+ * Everything is written the plain way: each log density is the full conditional
+ * evaluated term by term (sums over all n, no grouping), each reduction is a
+ * serial loop, and the steps run in the printed order of Algorithm 1:
+ * eps (all g, n), gamma (all g), nu, tau, beta (l = 1..L), theta, sigma^2.
+ *
+ * Readings where the paper is silent or garbled (each is also listed in the
+ * design notes of the repository):
+ *  - nu (Algorithm 1 step 3): the printed density carries nu/gamma_g inside the
+ *    sum; the product of InvGamma(nu/2, nu tau/2) densities gives tau/gamma_g,
+ *    which is used here, together with the U(0, d) support.
+ *  - gamma_g: InvGamma(nu/2 + N/2, nu tau/2 + sum_n eps_gn^2 / 2) (scale form).
+ *  - theta_l: Normal full conditional drawn directly (only non-normal
+ *    conditionals are slice sampled, Section 4.2).
+ *  - sigma_l: the prior is uniform on sigma_l, so sigma_l^2 has the truncated
+ *    InvGamma((G-1)/2, sum_g (beta_gl - theta_l)^2 / 2) conditional on
+ *    (0, s_l^2); it is slice sampled and sigma_l^2 is what is stored.
+ *  - tau: the Gamma conditional of step 4 is slice sampled like the other
+ *    gamma-family conditionals (Section 4.2).
+ *  - Algorithm 2 step 4 keeps scanning after the first failed step; stopping
+ *    at the first failure gives the same interval and is what is done here.
+ *  - The shrink loop is capped at shrink_cap candidates; on the cap the draw
+ *    keeps x0 and an error is counted.
+ *  - Tuning (step 7) uses the sweep index m, and a computed width that is not a
+ *    positive finite number leaves w unchanged.
+ *  - Moments cover sweeps m > M_B with divisor m - M_B.
+ */
+#include "oracle.h"
+
+/* OR_MUTANT selects a deliberately wrong variant of one formula.  Mutant
+ * libraries are built only by the tests, to show that each pin fails on a
+ * plausible mistake; the default build (OR_MUTANT = 0) is the oracle. */
+#ifndef OR_MUTANT
+#define OR_MUTANT 0
+#endif
+
+#include <math.h>
+#include <stdlib.h>
+#include <string.h>
+#ifdef _OPENMP
+#include <omp.h>
+#endif
+
+/* ------------------------------------------------------------------ */
+/* Philox4x32-10 (Salmon, Moraes, Dror & Shaw, SC'11)                  */
+/* ------------------------------------------------------------------ */
+#define PHILOX_M0 0xD2511F53u
+#define PHILOX_M1 0xCD9E8D57u
+#define PHILOX_W0 0x9E3779B9u
+#define PHILOX_W1 0xBB67AE85u
+
+void or_philox4x32_10(const uint32_t ctr[4], const uint32_t key[2], uint32_t out[4])
+{
+    uint32_t x0 = ctr[0], x1 = ctr[1], x2 = ctr[2], x3 = ctr[3];
+    uint32_t k0 = key[0], k1 = key[1];
+    for (int r = 0; r < 10; ++r) {
+        uint64_t p0 = (uint64_t)PHILOX_M0 * x0;
+        uint64_t p1 = (uint64_t)PHILOX_M1 * x2;
+        uint32_t hi0 = (uint32_t)(p0 >> 32), lo0 = (uint32_t)p0;
+        uint32_t hi1 = (uint32_t)(p1 >> 32), lo1 = (uint32_t)p1;
+        x0 = hi1 ^ x1 ^ k0;
+        x1 = lo1;
+        x2 = hi0 ^ x3 ^ k1;
+        x3 = lo0;
+        k0 += PHILOX_W0;
+        k1 += PHILOX_W1;
+    }
+    out[0] = x0; out[1] = x1; out[2] = x2; out[3] = x3;
+}
+
+static double u01(uint32_t r) { return ((double)r + 0.5) * 0x1p-32; }
+
+/* The random words of one draw: a lazily extended Philox stream. */
+typedef struct {
+    uint32_t key[2];
+    uint32_t ctr[4];     /* block index lives in the low 16 bits of ctr[3] */
+    uint32_t block;      /* block currently in buf */
+    uint32_t buf[4];
+} rstream;
+
+static void rs_init(rstream *s, uint64_t seed, uint32_t g, uint32_t kind, uint32_t sub,
+                    uint32_t m, uint32_t chain)
+{
+    s->key[0] = (uint32_t)seed;
+    s->key[1] = (uint32_t)(seed >> 32);
+    s->ctr[0] = g;
+    s->ctr[1] = (kind << 24) | sub;
+    s->ctr[2] = m;
+    s->ctr[3] = chain << 16;
+    s->block = 0;
+    or_philox4x32_10(s->ctr, s->key, s->buf);
+}
+
+static uint32_t rs_word(rstream *s, uint32_t q)
+{
+    uint32_t blk = q >> 2;
+    if (blk != s->block) {
+        uint32_t c[4] = { s->ctr[0], s->ctr[1], s->ctr[2], (s->ctr[3] & 0xFFFF0000u) | blk };
+        or_philox4x32_10(c, s->key, s->buf);
+        s->block = blk;
+    }
+    return s->buf[q & 3];
+}
+
+/* ------------------------------------------------------------------ */
+/* Algorithm 2: stepping-out slice sampler with tuning, in log space   */
+/* ------------------------------------------------------------------ */
+typedef double (*logf_fn)(double x, const void *arg);
+
+typedef struct {
+    int32_t kl, nl, nr, nc;
+    double margin;
+    int bad;
+} draw_info;
+
+static void note_margin(draw_info *di, double fx, double z)
+{
+    double d = fabs(fx - z);
+    if (isnan(d)) d = INFINITY;
+    if (d < di->margin) di->margin = d;
+}
+
+static double slice_draw(logf_fn f, const void *arg, double x0, double *w, double *waux,
+                         int64_t m, int64_t burnin, int64_t tune_start, int K, int cap,
+                         rstream *rs, draw_info *di)
+{
+    di->margin = INFINITY;
+    di->bad = 0;
+    /* step 1: u ~ U(0, f(x0)), kept as z = log f(x0) - E with E ~ Exp(1) */
+    double fx0 = f(x0, arg);
+    if (!isfinite(fx0)) { di->bad = 1; di->kl = di->nl = di->nr = di->nc = 0; return x0; }
+    double E = -log(u01(rs_word(rs, 0)));
+    double z = fx0 - E;
+    /* step 2: window of width w placed at random around x0 */
+    uint32_t r1 = rs_word(rs, 1);
+    double uv = ((double)(r1 >> 4) + 0.5) * 0x1p-28;
+    double v = (*w) * uv;
+    if (OR_MUTANT == 4) v = *w;           /* window not placed at random */
+    double L = x0 - v;
+    double R = L + (*w);
+    /* step 3: K_L uniform on {0..K}, K_R = K - K_L */
+    int KL = (int)(r1 & (uint32_t)K);
+    int KR = K - KL;
+    di->kl = KL;
+    /* step 4: step out */
+    int nl = 0, nr = 0;
+    while (nl < KL) {
+        double fl = f(L, arg);
+        note_margin(di, fl, z);
+        if (!(fl > z)) break;
+        L = L - (*w);
+        ++nl;
+    }
+    while (nr < KR) {
+        double fr = f(R, arg);
+        note_margin(di, fr, z);
+        if (!(fr > z)) break;
+        R = R + (*w);
+        ++nr;
+    }
+    di->nl = nl;
+    di->nr = nr;
+    /* steps 5-6: shrink until a candidate lies in the slice */
+    double x1 = x0;
+    int t = 1, ok = 0;
+    for (; t <= cap; ++t) {
+        double u = u01(rs_word(rs, (uint32_t)(t + 1)));
+        double xs = L + u * (R - L);
+        double fs = f(xs, arg);
+        note_margin(di, fs, z);
+        if (fs > z) { x1 = xs; ok = 1; break; }
+        if (xs > x0) R = xs; else L = xs;
+    }
+    di->nc = ok ? t : cap;
+    if (!ok) { di->bad = 1; x1 = x0; }
+    /* step 7: tune w during burn-in */
+    if (m <= burnin) {
+        *waux += (double)m * fabs(x1 - x0);
+        if (m > tune_start) {
+            double wn = *waux / (0.5 * (double)m * (double)(m + 1));
+            if (wn > 0.0 && isfinite(wn)) *w = wn;
+        }
+    }
+    return x1;
+}
+
+/* ------------------------------------------------------------------ */
+/* Context                                                             */
+/* ------------------------------------------------------------------ */
+struct or_ctx {
+    or_config cfg;
+    int32_t *y;            /* [G][N] */
+    double *X, *h, *c, *s; /* copies */
+    /* state */
+    double *eps, *gam, *beta;      /* [G][N], [G], [G][L] */
+    double nu, tau, *theta, *sig2; /* [L], [L] */
+    double *w_eps, *wa_eps, *w_gam, *wa_gam, *w_beta, *wa_beta;
+    double w_nu, wa_nu, w_tau, wa_tau, *w_sig2, *wa_sig2;
+    int64_t m;
+    /* moments over parameters in the order eps, gamma, beta, hyp */
+    double *mean, *msq;
+    int64_t count;
+    /* last-sweep records */
+    int32_t *cnt;          /* 4 per slice draw, same order (hyp: nu, tau, sig2) */
+    double *mrg;
+    int64_t errors;
+    double red[2 + 2 * 64];
+    int nthreads;
+};
+
+static int64_t n_params(const or_ctx *c)
+{
+    int64_t G = c->cfg.G, N = c->cfg.N, L = c->cfg.L;
+    return G * N + G + G * L + 2 + 2 * L;
+}
+
+static int64_t n_slice(const or_ctx *c)
+{
+    int64_t G = c->cfg.G, N = c->cfg.N, L = c->cfg.L;
+    return G * N + G + G * L + 2 + L;
+}
+
+static void *xcalloc(size_t n, size_t sz) { return calloc(n ? n : 1, sz); }
+
+int or_create(or_ctx **out, const or_config *cfg)
+{
+    if (!out || !cfg) return -1;
+    *out = NULL;
+    if (cfg->G < 1 || cfg->N < 1 || cfg->L < 1 || cfg->L > 64) return -1;
+    if (!(cfg->K == 0 || cfg->K == 1 || cfg->K == 3 || cfg->K == 7 || cfg->K == 15)) return -1;
+    if (cfg->shrink_cap < 1) return -1;
+    or_ctx *c = (or_ctx *)xcalloc(1, sizeof(or_ctx));
+    if (!c) return -2;
+    c->cfg = *cfg;
+    int64_t G = cfg->G, N = cfg->N, L = cfg->L;
+    c->y = (int32_t *)xcalloc((size_t)(G * N), sizeof(int32_t));
+    c->X = (double *)xcalloc((size_t)(N * L), sizeof(double));
+    c->h = (double *)xcalloc((size_t)N, sizeof(double));
+    c->c = (double *)xcalloc((size_t)L, sizeof(double));
+    c->s = (double *)xcalloc((size_t)L, sizeof(double));
+    memcpy(c->y, cfg->y, sizeof(int32_t) * (size_t)(G * N));
+    memcpy(c->X, cfg->X, sizeof(double) * (size_t)(N * L));
+    memcpy(c->h, cfg->h, sizeof(double) * (size_t)N);
+    memcpy(c->c, cfg->c, sizeof(double) * (size_t)L);
+    memcpy(c->s, cfg->s, sizeof(double) * (size_t)L);
+    c->cfg.y = c->y; c->cfg.X = c->X; c->cfg.h = c->h; c->cfg.c = c->c; c->cfg.s = c->s;
+    c->eps = (double *)xcalloc((size_t)(G * N), sizeof(double));
+    c->gam = (double *)xcalloc((size_t)G, sizeof(double));
+    c->beta = (double *)xcalloc((size_t)(G * L), sizeof(double));
+    c->theta = (double *)xcalloc((size_t)L, sizeof(double));
+    c->sig2 = (double *)xcalloc((size_t)L, sizeof(double));
+    c->w_eps = (double *)xcalloc((size_t)(G * N), sizeof(double));
+    c->wa_eps = (double *)xcalloc((size_t)(G * N), sizeof(double));
+    c->w_gam = (double *)xcalloc((size_t)G, sizeof(double));
+    c->wa_gam = (double *)xcalloc((size_t)G, sizeof(double));
+    c->w_beta = (double *)xcalloc((size_t)(G * L), sizeof(double));
+    c->wa_beta = (double *)xcalloc((size_t)(G * L), sizeof(double));
+    c->w_sig2 = (double *)xcalloc((size_t)L, sizeof(double));
+    c->wa_sig2 = (double *)xcalloc((size_t)L, sizeof(double));
+    c->mean = (double *)xcalloc((size_t)n_params(c), sizeof(double));
+    c->msq = (double *)xcalloc((size_t)n_params(c), sizeof(double));
+    c->cnt = (int32_t *)xcalloc((size_t)(4 * n_slice(c)), sizeof(int32_t));
+    c->mrg = (double *)xcalloc((size_t)n_slice(c), sizeof(double));
+    c->nthreads = 1;
+    if (!c->y || !c->eps || !c->mean || !c->msq || !c->cnt || !c->mrg) { or_destroy(c); return -2; }
+    for (int64_t i = 0; i < G * N; ++i) c->w_eps[i] = cfg->w0;
+    for (int64_t i = 0; i < G; ++i) c->w_gam[i] = cfg->w0;
+    for (int64_t i = 0; i < G * L; ++i) c->w_beta[i] = cfg->w0;
+    for (int64_t l = 0; l < L; ++l) c->w_sig2[l] = cfg->w0;
+    c->w_nu = cfg->w0;
+    c->w_tau = cfg->w0;
+    *out = c;
+    return 0;
+}
+
+void or_destroy(or_ctx *c)
+{
+    if (!c) return;
+    free(c->y); free(c->X); free(c->h); free(c->c); free(c->s);
+    free(c->eps); free(c->gam); free(c->beta); free(c->theta); free(c->sig2);
+    free(c->w_eps); free(c->wa_eps); free(c->w_gam); free(c->wa_gam);
+    free(c->w_beta); free(c->wa_beta); free(c->w_sig2); free(c->wa_sig2);
+    free(c->mean); free(c->msq); free(c->cnt); free(c->mrg);
+    free(c);
+}
+
+int or_set_counts(or_ctx *c, const int32_t *y)
+{
+    if (!c || !y) return -1;
+    memcpy(c->y, y, sizeof(int32_t) * (size_t)c->cfg.G * (size_t)c->cfg.N);
+    return 0;
+}
+
+int or_set_update_mask(or_ctx *c, uint32_t mask) { if (!c) return -1; c->cfg.update_mask = mask; return 0; }
+
+int or_set_threads(or_ctx *c, int32_t nthreads)
+{
+    if (!c || nthreads < 1) return -1;
+    c->nthreads = nthreads;
+    return 0;
+}
+
+int64_t or_error_count(const or_ctx *c) { return c ? c->errors : -1; }
+
+/* ------------------------------------------------------------------ */
+/* Full conditionals (log densities up to a constant)                  */
+/* ------------------------------------------------------------------ */
+typedef struct { const or_ctx *c; int64_t g; int n; } eps_arg;
+
+/* eps_gn: y_gn eps - exp(h_n + eps + X_n beta_g) - eps^2 / (2 gamma_g) */
+static double logf_eps(double x, const void *p)
+{
+    const eps_arg *a = (const eps_arg *)p;
+    const or_ctx *c = a->c;
+    int L = c->cfg.L, N = c->cfg.N;
+    double eta = c->h[a->n];
+    for (int l = 0; l < L; ++l) eta += c->X[a->n * L + l] * c->beta[a->g * L + l];
+    double y = (double)c->y[a->g * N + a->n];
+    if (OR_MUTANT == 6) return y * x - exp(eta - x) - x * x / (2.0 * c->gam[a->g]);
+    return y * x - exp(eta + x) - x * x / (2.0 * c->gam[a->g]);
+}
+
+typedef struct { double alpha1, scale; } gam_arg;   /* alpha + 1, scale */
+
+/* gamma_g: InvGamma(nu/2 + N/2, nu tau/2 + S_g/2) */
+static double logf_gam(double x, const void *p)
+{
+    const gam_arg *a = (const gam_arg *)p;
+    if (!(x > 0.0)) return -INFINITY;
+    return -a->alpha1 * log(x) - a->scale / x;
+}
+
+typedef struct { double G, tau, sum_log, sum_inv, d; } nu_arg;
+
+/* nu: -G lgamma(nu/2) + (G nu / 2) log(nu tau / 2) - (nu/2)(sum log gamma + tau sum 1/gamma) */
+static double logf_nu(double x, const void *p)
+{
+    const nu_arg *a = (const nu_arg *)p;
+    if (!(x > 0.0) || !(x < a->d)) return -INFINITY;
+    return -a->G * lgamma(0.5 * x) + 0.5 * a->G * x * log(0.5 * x * a->tau)
+           - 0.5 * x * (a->sum_log + (OR_MUTANT == 1 ? x : a->tau) * a->sum_inv);
+}
+
+typedef struct { double shape_m1, rate; } tau_arg;
+
+/* tau: Gamma(a + G nu / 2, rate b + (nu/2) sum 1/gamma) */
+static double logf_tau(double x, const void *p)
+{
+    const tau_arg *a = (const tau_arg *)p;
+    if (!(x > 0.0)) return -INFINITY;
+    return a->shape_m1 * log(x) - a->rate * x;
+}
+
+typedef struct { const or_ctx *c; int64_t g; int l; double Yl; double *bwork; } beta_arg;
+
+/* beta_gl: beta Y_gl - sum_n exp(h_n + eps_gn + X_n beta_g) - (beta - theta_l)^2 / (2 sigma_l^2) */
+static double logf_beta(double x, const void *p)
+{
+    const beta_arg *a = (const beta_arg *)p;
+    const or_ctx *c = a->c;
+    int L = c->cfg.L, N = c->cfg.N;
+    a->bwork[a->l] = x;
+    double sum = 0.0;
+    for (int n = 0; n < N; ++n) {
+        double eta = c->h[n] + c->eps[a->g * N + n];
+        for (int l = 0; l < L; ++l) eta += c->X[n * L + l] * a->bwork[l];
+        sum += exp(eta);
+    }
+    double dt = x - c->theta[a->l];
+    return x * a->Yl - sum - dt * dt / (2.0 * c->sig2[a->l]);
+}
+
+typedef struct { double halfGp1, S, upper; } sig_arg;
+
+/* sigma_l^2: -((G+1)/2) log v - S / (2 v) on 0 < v < s_l^2 */
+static double logf_sig2(double x, const void *p)
+{
+    const sig_arg *a = (const sig_arg *)p;
+    if (!(x > 0.0) || !(x < a->upper)) return -INFINITY;
+    return -a->halfGp1 * log(x) - a->S / (2.0 * x);
+}
+
+/* ------------------------------------------------------------------ */
+/* One sweep (Algorithm 1)                                             */
+/* ------------------------------------------------------------------ */
+static void record(or_ctx *c, int64_t idx, const draw_info *di)
+{
+    c->cnt[4 * idx + 0] = di->kl;
+    c->cnt[4 * idx + 1] = di->nl;
+    c->cnt[4 * idx + 2] = di->nr;
+    c->cnt[4 * idx + 3] = di->nc;
+    c->mrg[idx] = di->margin;
+}
+
+static void welford(double *mean, double *msq, double x, int64_t k)
+{
+    *mean += (x - *mean) / (double)k;
+    *msq += (x * x - *msq) / (double)k;
+}
+
+static int64_t sweep_once(or_ctx *c)
+{
+    const or_config *cf = &c->cfg;
+    const int64_t G = cf->G;
+    const int N = cf->N, L = cf->L;
+    const int64_t m = c->m + 1;
+    const uint32_t mm = (uint32_t)m;
+    const uint32_t mask = cf->update_mask;
+    int64_t errs = 0;
+    const int64_t off_gam = G * N, off_beta = G * N + G, off_hyp = G * N + G + G * L;
+
+    /* Step 1: in parallel, eps_gn */
+    if (mask & (1u << OR_KIND_EPS)) {
+#pragma omp parallel for schedule(static) reduction(+:errs) num_threads(c->nthreads)
+        for (int64_t g = 0; g < G; ++g) {
+            for (int n = 0; n < N; ++n) {
+                eps_arg a = { c, g, n };
+                rstream rs;
+                draw_info di;
+                rs_init(&rs, cf->seed, (uint32_t)g, OR_KIND_EPS, (uint32_t)n, mm, (uint32_t)cf->chain);
+                int64_t i = g * N + n;
+                c->eps[i] = slice_draw(logf_eps, &a, c->eps[i], &c->w_eps[i], &c->wa_eps[i], m,
+                                       cf->burnin, cf->tune_start, cf->K, cf->shrink_cap, &rs, &di);
+                record(c, i, &di);
+                errs += di.bad;
+            }
+        }
+    }
+    /* Step 2: in parallel, gamma_g */
+    if (mask & (1u << OR_KIND_GAMMA)) {
+#pragma omp parallel for schedule(static) reduction(+:errs) num_threads(c->nthreads)
+        for (int64_t g = 0; g < G; ++g) {
+            double S = 0.0;
+            for (int n = 0; n < N; ++n) S += c->eps[g * N + n] * c->eps[g * N + n];
+            gam_arg a = { 0.5 * c->nu + (OR_MUTANT == 2 ? 1.0 : 0.5) * N + 1.0,
+                          0.5 * c->nu * c->tau + 0.5 * S };
+            rstream rs;
+            draw_info di;
+            rs_init(&rs, cf->seed, (uint32_t)g, OR_KIND_GAMMA, 0, mm, (uint32_t)cf->chain);
+            c->gam[g] = slice_draw(logf_gam, &a, c->gam[g], &c->w_gam[g], &c->wa_gam[g], m,
+                                   cf->burnin, cf->tune_start, cf->K, cf->shrink_cap, &rs, &di);
+            record(c, off_gam + g, &di);
+            errs += di.bad;
+        }
+    }
+    /* Step 3: reduction, then nu */
+    double sum_log = 0.0, sum_inv = 0.0;
+    for (int64_t g = 0; g < G; ++g) { sum_log += log(c->gam[g]); sum_inv += 1.0 / c->gam[g]; }
+    c->red[0] = sum_log;
+    c->red[1] = sum_inv;
+    if (mask & (1u << OR_KIND_NU)) {
+        nu_arg a = { (double)G, c->tau, sum_log, sum_inv, cf->d };
+        rstream rs;
+        draw_info di;
+        rs_init(&rs, cf->seed, 0, OR_KIND_NU, 0, mm, (uint32_t)cf->chain);
+        c->nu = slice_draw(logf_nu, &a, c->nu, &c->w_nu, &c->wa_nu, m, cf->burnin,
+                           cf->tune_start, cf->K, cf->shrink_cap, &rs, &di);
+        record(c, off_beta + G * L, &di);
+        errs += di.bad;
+    }
+    /* Step 4: reduction, then tau */
+    if (mask & (1u << OR_KIND_TAU)) {
+        tau_arg a = { cf->a + 0.5 * (double)G * c->nu - 1.0,
+                      cf->b + (OR_MUTANT == 8 ? 1.0 : 0.5) * c->nu * sum_inv };
+        rstream rs;
+        draw_info di;
+        rs_init(&rs, cf->seed, 0, OR_KIND_TAU, 0, mm, (uint32_t)cf->chain);
+        c->tau = slice_draw(logf_tau, &a, c->tau, &c->w_tau, &c->wa_tau, m, cf->burnin,
+                            cf->tune_start, cf->K, cf->shrink_cap, &rs, &di);
+        record(c, off_beta + G * L + 1, &di);
+        errs += di.bad;
+    }
+    /* Step 5: for l = 1..L, in parallel over g, beta_gl */
+    if (mask & (1u << OR_KIND_BETA)) {
+        for (int l = 0; l < L; ++l) {
+#pragma omp parallel for schedule(static) reduction(+:errs) num_threads(c->nthreads)
+            for (int64_t g = 0; g < G; ++g) {
+                double bwork[64];
+                for (int i = 0; i < L; ++i) bwork[i] = c->beta[g * L + i];
+                double Yl = 0.0;
+                int lx = OR_MUTANT == 5 ? (l + 1) % L : l;
+                for (int n = 0; n < N; ++n) Yl += (double)c->y[g * N + n] * c->X[n * L + lx];
+                beta_arg a = { c, g, l, Yl, bwork };
+                rstream rs;
+                draw_info di;
+                rs_init(&rs, cf->seed, (uint32_t)g, OR_KIND_BETA, (uint32_t)l, mm, (uint32_t)cf->chain);
+                int64_t i = g * L + l;
+                double x1 = slice_draw(logf_beta, &a, c->beta[i], &c->w_beta[i], &c->wa_beta[i], m,
+                                       cf->burnin, cf->tune_start, cf->K, cf->shrink_cap, &rs, &di);
+                c->beta[i] = x1;
+                record(c, off_gam + G + i, &di);
+                errs += di.bad;
+            }
+        }
+    }
+    /* Steps 6 and 7: reductions, then theta_l (Normal) and sigma_l^2 (slice) */
+    for (int l = 0; l < L; ++l) {
+        double sb = 0.0;
+        for (int64_t g = 0; g < G; ++g) sb += c->beta[g * L + l];
+        c->red[2 + 2 * l] = sb;
+        if (mask & (1u << OR_KIND_THETA)) {
+            double prec = (double)G / c->sig2[l] + 1.0 / (c->c[l] * c->c[l]);
+            double mean = (sb / c->sig2[l]) / prec;
+            uint32_t ctr[4] = { 0, ((uint32_t)OR_KIND_THETA << 24) | (uint32_t)l, mm,
+                                (uint32_t)cf->chain << 16 };
+            uint32_t key[2] = { (uint32_t)cf->seed, (uint32_t)(cf->seed >> 32) };
+            uint32_t r[4];
+            or_philox4x32_10(ctr, key, r);
+            double zn = sqrt(-2.0 * log(u01(r[0]))) * cos(2.0 * M_PI * u01(r[1]));
+            c->theta[l] = mean + zn / (OR_MUTANT == 7 ? prec : sqrt(prec));
+        }
+        double S = 0.0;
+        for (int64_t g = 0; g < G; ++g) {
+            double dv = c->beta[g * L + l] - c->theta[l];
+            S += dv * dv;
+        }
+        c->red[3 + 2 * l] = S;
+        if (mask & (1u << OR_KIND_SIG2)) {
+            sig_arg a = { 0.5 * ((double)G + (OR_MUTANT == 3 ? 2.0 : 1.0)), S, c->s[l] * c->s[l] };
+            rstream rs;
+            draw_info di;
+            rs_init(&rs, cf->seed, 0, OR_KIND_SIG2, (uint32_t)l, mm, (uint32_t)cf->chain);
+            c->sig2[l] = slice_draw(logf_sig2, &a, c->sig2[l], &c->w_sig2[l], &c->wa_sig2[l], m,
+                                    cf->burnin, cf->tune_start, cf->K, cf->shrink_cap, &rs, &di);
+            record(c, off_beta + G * L + 2 + l, &di);
+            errs += di.bad;
+        }
+    }
+    (void)off_hyp;
+    /* Running means and means of squares (Section 3.1) after burn-in */
+    if (m > cf->burnin) {
+        int64_t k = m - cf->burnin;
+        double *mu = c->mean, *sq = c->msq;
+        for (int64_t i = 0; i < G * N; ++i) welford(&mu[i], &sq[i], c->eps[i], k);
+        for (int64_t g = 0; g < G; ++g) welford(&mu[off_gam + g], &sq[off_gam + g], c->gam[g], k);
+        for (int64_t i = 0; i < G * L; ++i) welford(&mu[off_beta + i], &sq[off_beta + i], c->beta[i], k);
+        int64_t o = off_beta + G * L;
+        welford(&mu[o], &sq[o], c->nu, k);
+        welford(&mu[o + 1], &sq[o + 1], c->tau, k);
+        for (int l = 0; l < L; ++l) welford(&mu[o + 2 + l], &sq[o + 2 + l], c->theta[l], k);
+        for (int l = 0; l < L; ++l) welford(&mu[o + 2 + L + l], &sq[o + 2 + L + l], c->sig2[l], k);
+        c->count = k;
+    }
+    c->m = m;
+    return errs;
+}
+
+int or_sweep(or_ctx *c, int64_t n)
+{
+    if (!c || n < 0) return -1;
+    int64_t errs = 0;
+    for (int64_t i = 0; i < n; ++i) errs += sweep_once(c);
+    c->errors += errs;
+    return errs ? -4 : 0;
+}
+
+/* ------------------------------------------------------------------ */
+/* State access                                                        */
+/* ------------------------------------------------------------------ */
+static void cp(double *dst, const double *src, int64_t n)
+{
+    if (dst && src) memcpy(dst, src, sizeof(double) * (size_t)n);
+}
+
+int or_get_state(const or_ctx *c, double *eps, double *gam, double *beta, double *hyp,
+                 double *w_eps, double *waux_eps, double *w_gam, double *waux_gam,
+                 double *w_beta, double *waux_beta, double *w_hyp, double *waux_hyp, int64_t *m)
+{
+    if (!c) return -1;
+    int64_t G = c->cfg.G, N = c->cfg.N, L = c->cfg.L;
+    cp(eps, c->eps, G * N); cp(gam, c->gam, G); cp(beta, c->beta, G * L);
+    if (hyp) {
+        hyp[0] = c->nu; hyp[1] = c->tau;
+        for (int l = 0; l < L; ++l) { hyp[2 + l] = c->theta[l]; hyp[2 + L + l] = c->sig2[l]; }
+    }
+    cp(w_eps, c->w_eps, G * N); cp(waux_eps, c->wa_eps, G * N);
+    cp(w_gam, c->w_gam, G); cp(waux_gam, c->wa_gam, G);
+    cp(w_beta, c->w_beta, G * L); cp(waux_beta, c->wa_beta, G * L);
+    if (w_hyp) { w_hyp[0] = c->w_nu; w_hyp[1] = c->w_tau; for (int l = 0; l < L; ++l) w_hyp[2 + l] = c->w_sig2[l]; }
+    if (waux_hyp) { waux_hyp[0] = c->wa_nu; waux_hyp[1] = c->wa_tau; for (int l = 0; l < L; ++l) waux_hyp[2 + l] = c->wa_sig2[l]; }
+    if (m) *m = c->m;
+    return 0;
+}
+
+static void cpin(double *dst, const double *src, int64_t n)
+{
+    if (dst && src) memcpy(dst, src, sizeof(double) * (size_t)n);
+}
+
+int or_set_state(or_ctx *c, const double *eps, const double *gam, const double *beta,
+                 const double *hyp, const double *w_eps, const double *waux_eps,
+                 const double *w_gam, const double *waux_gam, const double *w_beta,
+                 const double *waux_beta, const double *w_hyp, const double *waux_hyp, int64_t m)
+{
+    if (!c || m < 0) return -1;
+    int64_t G = c->cfg.G, N = c->cfg.N, L = c->cfg.L;
+    cpin(c->eps, eps, G * N); cpin(c->gam, gam, G); cpin(c->beta, beta, G * L);
+    if (hyp) {
+        c->nu = hyp[0]; c->tau = hyp[1];
+        for (int l = 0; l < L; ++l) { c->theta[l] = hyp[2 + l]; c->sig2[l] = hyp[2 + L + l]; }
+    }
+    cpin(c->w_eps, w_eps, G * N); cpin(c->wa_eps, waux_eps, G * N);
+    cpin(c->w_gam, w_gam, G); cpin(c->wa_gam, waux_gam, G);
+    cpin(c->w_beta, w_beta, G * L); cpin(c->wa_beta, waux_beta, G * L);
+    if (w_hyp) { c->w_nu = w_hyp[0]; c->w_tau = w_hyp[1]; for (int l = 0; l < L; ++l) c->w_sig2[l] = w_hyp[2 + l]; }
+    if (waux_hyp) { c->wa_nu = waux_hyp[0]; c->wa_tau = waux_hyp[1]; for (int l = 0; l < L; ++l) c->wa_sig2[l] = waux_hyp[2 + l]; }
+    c->m = m;
+    return 0;
+}
+
+int or_get_moments(const or_ctx *c, double *mean_eps, double *msq_eps, double *mean_gam,
+                   double *msq_gam, double *mean_beta, double *msq_beta, double *mean_hyp,
+                   double *msq_hyp, int64_t *count)
+{
+    if (!c) return -1;
+    int64_t G = c->cfg.G, N = c->cfg.N, L = c->cfg.L;
+    int64_t og = G * N, ob = og + G, oh = ob + G * L;
+    cp(mean_eps, c->mean, G * N); cp(msq_eps, c->msq, G * N);
+    cp(mean_gam, c->mean + og, G); cp(msq_gam, c->msq + og, G);
+    cp(mean_beta, c->mean + ob, G * L); cp(msq_beta, c->msq + ob, G * L);
+    cp(mean_hyp, c->mean + oh, 2 + 2 * L); cp(msq_hyp, c->msq + oh, 2 + 2 * L);
+    if (count) *count = c->count;
+    return 0;
+}
+
+int or_get_counts(const or_ctx *c, int32_t *cnt_eps, int32_t *cnt_gam, int32_t *cnt_beta,
+                  int32_t *cnt_hyp, double *mrg_eps, double *mrg_gam, double *mrg_beta,
+                  double *mrg_hyp)
+{
+    if (!c) return -1;
+    int64_t G = c->cfg.G, N = c->cfg.N, L = c->cfg.L;
+    int64_t og = G * N, ob = og + G, oh = ob + G * L;
+    if (cnt_eps) memcpy(cnt_eps, c->cnt, sizeof(int32_t) * 4 * (size_t)(G * N));
+    if (cnt_gam) memcpy(cnt_gam, c->cnt + 4 * og, sizeof(int32_t) * 4 * (size_t)G);
+    if (cnt_beta) memcpy(cnt_beta, c->cnt + 4 * ob, sizeof(int32_t) * 4 * (size_t)(G * L));
+    if (cnt_hyp) memcpy(cnt_hyp, c->cnt + 4 * oh, sizeof(int32_t) * 4 * (size_t)(2 + L));
+    cp(mrg_eps, c->mrg, G * N); cp(mrg_gam, c->mrg + og, G);
+    cp(mrg_beta, c->mrg + ob, G * L); cp(mrg_hyp, c->mrg + oh, 2 + L);
+    return 0;
+}
+
+int or_get_reductions(const or_ctx *c, double *out)
+{
+    if (!c || !out) return -1;
+    memcpy(out, c->red, sizeof(double) * (size_t)(2 + 2 * c->cfg.L));
+    return 0;
+}
+
+/* ------------------------------------------------------------------ */
+/* Default starting values                                             */
+/* ------------------------------------------------------------------ */
+/* Solve the L x L system A x = r by Gaussian elimination with partial pivoting. */
+static int solve(double *A, double *r, int L)
+{
+    for (int k = 0; k < L; ++k) {
+        int p = k;
+        for (int i = k + 1; i < L; ++i) if (fabs(A[i * L + k]) > fabs(A[p * L + k])) p = i;
+        if (fabs(A[p * L + k]) < 1e-12) return -1;
+        if (p != k) {
+            for (int j = 0; j < L; ++j) { double t = A[k * L + j]; A[k * L + j] = A[p * L + j]; A[p * L + j] = t; }
+            double t = r[k]; r[k] = r[p]; r[p] = t;
+        }
+        for (int i = k + 1; i < L; ++i) {
+            double f = A[i * L + k] / A[k * L + k];
+            for (int j = k; j < L; ++j) A[i * L + j] -= f * A[k * L + j];
+            r[i] -= f * r[k];
+        }
+    }
+    for (int k = L - 1; k >= 0; --k) {
+        double s = r[k];
+        for (int j = k + 1; j < L; ++j) s -= A[k * L + j] * r[j];
+        r[k] = s / A[k * L + k];
+    }
+    return 0;
+}
+
+int or_init_default(or_ctx *c)
+{
+    if (!c) return -1;
+    const int64_t G = c->cfg.G;
+    const int N = c->cfg.N, L = c->cfg.L;
+    double XtX[64 * 64];
+    for (int i = 0; i < L; ++i)
+        for (int j = 0; j < L; ++j) {
+            double s = 0.0;
+            for (int n = 0; n < N; ++n) s += c->X[n * L + i] * c->X[n * L + j];
+            XtX[i * L + j] = s + (i == j ? 1e-8 : 0.0);
+        }
+    double sb[64] = { 0 }, sbb[64] = { 0 }, sg = 0.0;
+    for (int64_t g = 0; g < G; ++g) {
+        double A[64 * 64], r[64];
+        memcpy(A, XtX, sizeof(double) * (size_t)(L * L));
+        for (int l = 0; l < L; ++l) {
+            double s = 0.0;
+            for (int n = 0; n < N; ++n)
+                s += c->X[n * L + l] * (log1p((double)c->y[g * N + n]) - c->h[n]);
+            r[l] = s;
+        }
+        if (solve(A, r, L) != 0) for (int l = 0; l < L; ++l) r[l] = 0.0;
+        double rss = 0.0;
+        for (int n = 0; n < N; ++n) {
+            double e = log1p((double)c->y[g * N + n]) - c->h[n];
+            for (int l = 0; l < L; ++l) e -= c->X[n * L + l] * r[l];
+            rss += e * e;
+        }
+        double gm = N > L ? rss / (double)(N - L) : 0.1;
+        if (gm < 0.01) gm = 0.01;
+        c->gam[g] = gm;
+        sg += gm;
+        for (int l = 0; l < L; ++l) {
+            c->beta[g * L + l] = r[l];
+            sb[l] += r[l];
+            sbb[l] += r[l] * r[l];
+        }
+        for (int n = 0; n < N; ++n) c->eps[g * N + n] = 0.0;
+    }
+    for (int l = 0; l < L; ++l) {
+        double mu = sb[l] / (double)G;
+        double v = sbb[l] / (double)G - mu * mu;
+        double hi = 0.25 * c->s[l] * c->s[l];
+        if (!(v > 1e-4)) v = 1e-4;
+        if (v > hi) v = hi;
+        c->theta[l] = mu;
+        c->sig2[l] = v;
+    }
+    c->tau = sg / (double)G;
+    c->nu = 10.0 < 0.5 * c->cfg.d ? 10.0 : 0.5 * c->cfg.d;
+    c->m = 0;
+    c->count = 0;
+    return 0;
+}
+
+/* ------------------------------------------------------------------ */
+/* Slice sampler on textbook targets (tests of Algorithm 2 alone)      */
+/* ------------------------------------------------------------------ */
+typedef struct { int kind; double p0, p1, p2; } test_arg;
+
+static double logf_test(double x, const void *p)
+{
+    const test_arg *a = (const test_arg *)p;
+    switch (a->kind) {
+    case 0: { double z = (x - a->p0) / a->p1; return -0.5 * z * z; }
+    case 1: if (!(x > 0.0)) return -INFINITY; return (a->p0 - 1.0) * log(x) - a->p1 * x;
+    case 2: if (!(x > 0.0)) return -INFINITY; return -(a->p0 + 1.0) * log(x) - a->p1 / x;
+    case 3: if (!(x > 0.0) || !(x < a->p2)) return -INFINITY; return -(a->p0 + 1.0) * log(x) - a->p1 / x;
+    default: return NAN;
+    }
+}
+
+int or_slice_test(int32_t target, const double *params, const double *x0, double *x1,
+                  int64_t n, double w, int32_t K, uint64_t seed, uint32_t m, int32_t *counts)
+{
+    if (!params || !x0 || !x1 || n < 0 || target < 0 || target > 3) return -1;
+    if (!(K == 0 || K == 1 || K == 3 || K == 7 || K == 15)) return -1;
+    test_arg a = { target, params[0], params[1], target == 3 ? params[2] : 0.0 };
+    int64_t errs = 0;
+    for (int64_t i = 0; i < n; ++i) {
+        rstream rs;
+        draw_info di;
+        double ww = w, wa = 0.0;
+        rs_init(&rs, seed, (uint32_t)i, OR_KIND_TEST, 0, m, 0);
+        /* burnin = 0: w stays frozen */
+        x1[i] = slice_draw(logf_test, &a, x0[i], &ww, &wa, (int64_t)m, 0, 0, K, 1000, &rs, &di);
+        if (counts) {
+            counts[4 * i + 0] = di.kl; counts[4 * i + 1] = di.nl;
+            counts[4 * i + 2] = di.nr; counts[4 * i + 3] = di.nc;
+        }
+        errs += di.bad;
+    }
+    return errs ? -4 : 0;
+}

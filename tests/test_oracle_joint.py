@@ -1,0 +1,113 @@
+"""Whole-sweep pins of the oracle (CPU only).
+
+* Geweke (2004) "getting it right": alternating data simulation from the model
+  and one Gibbs sweep must leave the prior invariant.  nu is held fixed so that
+  every moment below is finite; its own step is pinned by quadrature elsewhere.
+* Posterior recovery on the two-group workload: the simulated truth lies in
+  the normal-approximation 95% intervals at about the nominal rate.
+"""
+import numpy as np
+import pytest
+
+from paper_1606_06659_amd import datagen, diagnostics
+
+
+def _mcse(x):
+    """Monte Carlo standard error of each column mean (ESS-based)."""
+    x = np.asarray(x)
+    ess = diagnostics.ess_many(x)
+    return x.std(axis=0) / np.sqrt(ess)
+
+
+def test_geweke_getting_it_right(oracle_lib):
+    rng = np.random.default_rng(99)
+    G, N = 6, 4
+    X = datagen.design_two_groups(2)
+    h = np.array([0.1, -0.1, 0.05, -0.05])
+    a, b, c, s, nu = 20.0, 200.0, 1.0, 1.0, 10.0
+    L = X.shape[1]
+    # one draw from the prior
+    tau = rng.gamma(a, 1.0 / b)
+    gam = (nu * tau / 2) / rng.gamma(nu / 2, 1.0, size=G)
+    theta = rng.normal(0, c, size=L)
+    sig = rng.uniform(0, s, size=L)
+    beta = theta + sig * rng.standard_normal((G, L))
+    eps = rng.standard_normal((G, N)) * np.sqrt(gam)[:, None]
+    y = rng.poisson(np.exp(h + eps + beta @ X.T)).astype(np.int32)
+    mask = oracle_lib.UPDATE_ALL & ~(1 << oracle_lib.KIND_NU)
+    o = oracle_lib.Oracle(y, X, h, a=a, b=b, c=np.full(L, c), s=np.full(L, s), seed=5,
+                          update_mask=mask, init=False, w0=1.0)
+    st = o.get_state()
+    st.update(eps=eps, gam=gam, beta=beta, m=0)
+    st["hyp"][:] = np.concatenate([[nu, tau], theta, sig ** 2])
+    st["w_eps"][:] = 1.0
+    st["w_gam"][:] = 0.1
+    st["w_beta"][:] = 0.5
+    st["w_hyp"][:] = [1.0, 0.05, 0.3, 0.3]
+    o.set_state(st)
+    T = 60000
+    rec = np.empty((T, 10))
+    for t in range(T):
+        s_ = o.get_state()
+        y = rng.poisson(np.exp(h + s_["eps"] + s_["beta"] @ X.T)).astype(np.int32)
+        o.set_counts(y)
+        assert o.sweep(1) == 0
+        s_ = o.get_state()
+        hp = s_["hyp"]
+        rec[t] = [hp[1], hp[2], hp[3], hp[4], hp[5], s_["gam"][0], s_["beta"][0, 0],
+                  s_["beta"][1, 1], s_["eps"][0, 0], s_["eps"][2, 3]]
+    f = np.concatenate([rec, rec ** 2], axis=1)
+    Etau = a / b
+    Egam = nu * Etau / (nu - 2)
+    Eb2 = c ** 2 + s ** 2 / 3
+    expect = np.array([Etau, 0, 0, s ** 2 / 3, s ** 2 / 3, Egam, 0, 0, 0, 0,
+                       Etau ** 2 + a / b ** 2, c ** 2, c ** 2, s ** 4 / 5, s ** 4 / 5,
+                       nu ** 2 / 4 * (a * (a + 1) / b ** 2) / ((nu / 2 - 1) * (nu / 2 - 2)),
+                       Eb2, Eb2, Egam, Egam])
+    burn = 2000
+    z = (f[burn:].mean(0) - expect) / _mcse(f[burn:])
+    assert np.all(np.abs(z) < 4.5), z
+
+
+def test_posterior_recovery_two_group(oracle_lib):
+    ds = datagen.small_two_group(G=1000, seed=0)
+    o = oracle_lib.Oracle(ds.y, ds.X, ds.h, seed=1, burnin=500, tune_start=50, threads=4)
+    assert o.sweep(2000) == 0
+    mo = o.moments()
+    lo, hi = diagnostics.normal_interval(mo["mean_beta"], mo["msq_beta"])
+    cover = np.mean((ds.beta >= lo) & (ds.beta <= hi), axis=0)
+    assert np.all((cover > 0.90) & (cover < 0.99)), cover
+    lo, hi = diagnostics.normal_interval(mo["mean_gam"], mo["msq_gam"])
+    assert 0.85 < np.mean((ds.gamma >= lo) & (ds.gamma <= hi)) < 0.995
+    # hyperparameters: truth within 4 posterior sd
+    L = ds.L
+    truth = np.concatenate([[ds.nu, ds.tau], ds.theta, ds.sigma ** 2])
+    sd = np.sqrt(mo["msq_hyp"] - mo["mean_hyp"] ** 2)
+    # theta and sigma^2 are estimated from the 1000 simulated beta: compare with those
+    truth[2:2 + L] = ds.beta.mean(0)
+    truth[2 + L:] = ds.beta.var(0)
+    assert np.all(np.abs(mo["mean_hyp"] - truth) < 4 * sd + 1e-3), (mo["mean_hyp"], truth, sd)
+
+
+def test_rhat_and_ess_on_known_chains():
+    rng = np.random.default_rng(3)
+    C, M = 4, 4000
+    iid = rng.standard_normal((C, M))
+    r = diagnostics.rhat_from_moments(iid.mean(1), (iid ** 2).mean(1), M)
+    assert abs(r - 1.0) < 0.01
+    # shifted chain -> R-hat well above 1
+    bad = iid.copy()
+    bad[0] += 1.0
+    assert diagnostics.rhat_from_moments(bad.mean(1), (bad ** 2).mean(1), M) > 1.1
+    assert 0.85 * C * M < diagnostics.ess(iid) < 1.15 * C * M
+    rho = 0.9
+    ar = np.empty((C, 40000))
+    ar[:, 0] = rng.standard_normal(C)
+    e = rng.standard_normal((C, 40000)) * np.sqrt(1 - rho ** 2)
+    for t in range(1, 40000):
+        ar[:, t] = rho * ar[:, t - 1] + e[:, t]
+    want = C * 40000 * (1 - rho) / (1 + rho)
+    got = diagnostics.ess(ar)
+    assert 0.8 * want < got < 1.2 * want, (got, want)
+    lo, hi = diagnostics.normal_interval(0.0, 1.0)
+    assert abs(hi - 1.96) < 1e-3 and abs(lo + 1.96) < 1e-3

@@ -1,0 +1,29 @@
+"""The oracle's pins have power: each plausible mistake planted in the oracle
+(a compile-time switch, built only here, on the CPU) makes its pin fail."""
+import pytest
+
+from tests import test_oracle_pins as P
+
+MUTANTS = [
+    # (switch, what is wrong, the pin that must fail)
+    (1, "nu density as printed: nu/gamma_g in the sum", lambda o: P.test_nu_conditional(o)),
+    (2, "gamma shape nu/2 + N instead of nu/2 + N/2", lambda o: P.test_gamma_conditional(o)),
+    (3, "sigma^2 shape G/2: the Jacobian of the U(0, s) prior on sigma dropped",
+     lambda o: P.test_sigma2_conditional(o, 100.0, 6)),
+    (4, "slice window not placed at random around x0",
+     lambda o: P.test_slice_step_is_stationary(o, *P.TARGETS[0])),
+    (5, "beta sufficient statistic taken from the wrong design column",
+     lambda o: P.test_beta_conditional(o, "cell_means")),
+    (6, "eps likelihood with exp(eta - eps)", lambda o: P.test_eps_conditional(o)),
+    (7, "theta drawn with sd 1/precision instead of 1/sqrt(precision)",
+     lambda o: P.test_theta_conditional(o)),
+    (8, "tau rate b + nu sum 1/gamma instead of b + (nu/2) sum 1/gamma",
+     lambda o: P.test_tau_conditional(o)),
+]
+
+
+@pytest.mark.parametrize("k,what,pin", MUTANTS, ids=[f"mutant{m[0]}" for m in MUTANTS])
+def test_pin_catches_mutant(oracle_lib, k, what, pin):
+    o = oracle_lib.variant(k)
+    with pytest.raises(AssertionError):
+        pin(o)
