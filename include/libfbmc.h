@@ -1,0 +1,228 @@
+/*
+ * libfbmc -- fully Bayesian MCMC for the Poisson-lognormal RNA-seq model on
+ * AMD Instinct MI355X (gfx950).
+ *
+ * Landau & Niemi, "A fully Bayesian strategy for high-dimensional hierarchical
+ * modeling using massively parallel computing", arXiv 1606.06659.
+ *
+ * Model (Section 4.1, Fig. 3), for genes g = 1..G and samples n = 1..N:
+ *   y_gn | eps_gn, beta_g ~ Poisson(exp(h_n + eps_gn + X_n beta_g))
+ *   eps_gn | gamma_g      ~ Normal(0, gamma_g)            (variance)
+ *   gamma_g | nu, tau     ~ InvGamma(nu/2, nu tau/2)      (shape, scale)
+ *   nu ~ Uniform(0, d),   tau ~ Gamma(a, rate b)
+ *   beta_gl | theta_l, sigma_l ~ Normal(theta_l, sigma_l^2)
+ *   theta_l ~ Normal(0, c_l^2),  sigma_l ~ Uniform(0, s_l)
+ *
+ * One sweep (Algorithm 1) draws every eps_gn, gamma_g and beta_gl from its full
+ * conditional with the stepping-out slice sampler of Algorithm 2 (Appendix A),
+ * in parallel over genes, forms the sufficient sums of gamma and beta by
+ * parallel reductions (Section 2.2), draws nu, tau (slice), theta_l (Normal)
+ * and sigma_l^2 (slice), and updates the running mean and mean of squares of
+ * every parameter on the device (Section 3.1).  All random numbers come from
+ * Philox4x32-10 with the counter (gene, kind << 24 | index, sweep,
+ * chain << 16 | block) under the 64-bit seed, so every draw is reproducible.
+ *
+ * Conventions for every function below
+ * ------------------------------------
+ *  - Host pointers, row-major arrays, caller-owned.  The library copies every
+ *    input it keeps and never retains a caller pointer after the call returns.
+ *  - Status codes: FB_OK (0) or a negative FB_E* code; nothing is thrown across
+ *    the ABI.  fb_last_error() returns a message for the last failure on a
+ *    context (fb_last_error(NULL) covers fb_create failures, per thread).
+ *  - A context is not thread-safe; calls on one context must not overlap.
+ *  - Work is enqueued on the context's HIP stream (fb_options.stream, or a
+ *    stream the library creates).  fb_sweep returns once the work is enqueued;
+ *    device-side errors surface on a later synchronising call
+ *    (fb_sync, fb_get_state, fb_summaries, fb_trace, fb_debug_counts).
+ */
+#ifndef LIBFBMC_H
+#define LIBFBMC_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+#define FB_OK        0
+#define FB_EINVAL   (-1)  /* invalid argument or unsupported shape */
+#define FB_ENOMEM   (-2)  /* device or host allocation failed */
+#define FB_EDEVICE  (-3)  /* a HIP runtime call failed */
+#define FB_ENUMERIC (-4)  /* a draw met a non-finite log density or hit the shrink cap (sticky) */
+#define FB_ESTATE   (-5)  /* call not valid in the context's current state */
+
+/* Limits of this build. */
+#define FB_MAX_N        64   /* samples per dataset */
+#define FB_MAX_L        8    /* model-matrix columns */
+#define FB_MAX_ROWS     8    /* distinct rows of X */
+#define FB_MAX_COLVALS  4    /* distinct non-zero values in one column of X */
+
+enum fb_precision {
+    FB_FP64 = 0,   /* every draw in double precision */
+    FB_FP32 = 1    /* eps/gamma/beta log densities in float; reductions, moments,
+                      hyperparameters in double */
+};
+
+enum fb_kind {     /* Philox counter kinds, also bit positions of update_mask */
+    FB_KIND_EPS = 1, FB_KIND_GAMMA = 2, FB_KIND_NU = 3, FB_KIND_TAU = 4,
+    FB_KIND_BETA = 5, FB_KIND_THETA = 6, FB_KIND_SIG2 = 7, FB_KIND_IMH = 8
+};
+#define FB_UPDATE_ALL 0xFEu
+
+/* Prior constants of Section 4.1: tau ~ Gamma(a, rate b), nu ~ U(0, d),
+ * theta_l ~ N(0, c[l]^2), sigma_l ~ U(0, s[l]).  The paper uses
+ * a = b = 1, d = 1000, c_l = 10, s_l = 100 (fb_default_priors). */
+typedef struct {
+    double a, b, d;
+    const double *c;   /* [L] */
+    const double *s;   /* [L] */
+} fb_priors;
+
+typedef struct {
+    int32_t chains;         /* independent chains per dataset (>= 1); chain k uses counter word chain = k */
+    int64_t burnin;         /* M_B: sweeps 1..M_B tune the slice widths; moments use sweeps > M_B */
+    int64_t tune_start;     /* M_C < M_B: widths are recomputed only for M_C < m <= M_B */
+    int32_t max_steps;      /* K of Algorithm 2: one of 0, 1, 3, 7, 15 */
+    double w0;              /* initial slice width of every parameter (> 0) */
+    int32_t shrink_cap;     /* maximum shrink candidates per draw (>= 1) */
+    int32_t precision;      /* enum fb_precision */
+    uint32_t update_mask;   /* bit (1 << kind) enables that Gibbs step; FB_UPDATE_ALL */
+    int32_t thin;           /* record a trace point every `thin` sweeps; 0 = no trace */
+    int32_t trace_genes;    /* genes per segment whose gamma and beta are traced */
+    int32_t trace_after_burnin; /* 1: record only sweeps m > M_B */
+    int64_t trace_capacity; /* trace points kept on the device per segment */
+    int32_t debug_counts;   /* 1: keep per-draw integer records of the last sweep */
+    int32_t jitter;         /* 1: chains > 0 start from seeded jittered values */
+    void *stream;           /* hipStream_t to use, or NULL */
+} fb_options;
+
+/* One dataset of a batch: counts [G][N] (row g = gene), X [N][L], h [N]. */
+typedef struct {
+    const int32_t *counts;
+    int64_t G;
+    int32_t N;
+    const double *X;
+    int32_t L;
+    const double *h;
+    const fb_priors *priors;  /* NULL = the paper's constants */
+    uint64_t seed;
+} fb_dataset;
+
+typedef struct fb_ctx fb_ctx;
+
+/* Fill *o with the defaults: 1 chain, M_B = 1000, M_C = 100, K = 15, w0 = 1,
+ * shrink_cap = 200, FP64, all steps, no trace, no debug records. */
+void fb_default_options(fb_options *o);
+
+/* Create a sampler for one dataset (Section 4.1).
+ *   counts: [G][N] int32 >= 0;  X: [N][L] finite;  h: [N] finite offsets;
+ *   pri: NULL for the paper's constants;  seed: Philox key;  opt: NULL = defaults.
+ * Requires 1 <= L <= N <= FB_MAX_N, L <= FB_MAX_L, at most FB_MAX_ROWS distinct
+ * rows in X and FB_MAX_COLVALS distinct non-zero values per column; a, b, d,
+ * c_l, s_l > 0.  Starting values: per-gene least squares of log(1 + y) - h on X
+ * for beta, eps = 0, gamma from the residual variance, theta and sigma^2 from
+ * the spread of the beta, tau = mean gamma, nu = 10 (jittered for chains > 0 if
+ * opt->jitter).  The chains of one dataset form its segments 0..C-1.
+ * Errors: FB_EINVAL, FB_ENOMEM, FB_EDEVICE; *out is NULL on failure. */
+int fb_create(fb_ctx **out, const int32_t *counts, int64_t G, int32_t N, const double *X,
+              int32_t L, const double *h, const fb_priors *pri, uint64_t seed,
+              const fb_options *opt);
+
+/* Create one sampler over n_datasets datasets (each with opt->chains chains)
+ * that advance together: segment k * chains + c is chain c of dataset k. */
+int fb_create_batch(fb_ctx **out, const fb_dataset *ds, int32_t n_datasets,
+                    const fb_options *opt);
+
+/* Free everything; fb_destroy(NULL) is a no-op. */
+void fb_destroy(fb_ctx *c);
+
+/* Enqueue n >= 0 sweeps of Algorithm 1 on every segment (sweep index m advances
+ * by n).  Returns FB_ENUMERIC if an earlier sweep raised the numeric flag. */
+int fb_sweep(fb_ctx *c, int64_t n);
+
+/* Wait for all enqueued work; returns the sticky error status. */
+int fb_sync(fb_ctx *c);
+
+/* Number of segments, and the shape of segment seg. */
+int32_t fb_num_segments(const fb_ctx *c);
+int fb_segment_dims(const fb_ctx *c, int32_t seg, int64_t *G, int32_t *N, int32_t *L,
+                    int32_t *dataset, int32_t *chain);
+
+/* Full state of one segment in row-major host arrays (any pointer may be NULL to
+ * skip that block):  eps [G][N], gamma [G], beta [G][L],
+ * hyp [2 + 2L] = (nu, tau, theta_1..L, sigma^2_1..L); slice widths w and their
+ * tuning sums waux with the same shapes, and for the hyperparameters
+ * w_hyp / waux_hyp [2 + L] = (nu, tau, sigma^2_1..L).  m = sweeps completed. */
+typedef struct {
+    double *eps, *gam, *beta, *hyp;
+    double *w_eps, *waux_eps, *w_gam, *waux_gam, *w_beta, *waux_beta, *w_hyp, *waux_hyp;
+    int64_t m;
+} fb_state;
+
+int fb_get_state(fb_ctx *c, int32_t seg, fb_state *s);
+/* Writes every non-NULL block and sets the sweep counter of the whole context
+ * to s->m.  Rejects values outside the support (gamma, tau, sigma^2, widths
+ * must be > 0, 0 < nu < d, sigma^2_l < s_l^2, everything finite). */
+int fb_set_state(fb_ctx *c, int32_t seg, const fb_state *s);
+
+/* Running means and means of squares (FP64) of one segment, same shapes as
+ * fb_state; count = number of sweeps averaged (m - M_B once m > M_B).  Clears
+ * nothing.  NULL pointers skip a block. */
+typedef struct {
+    double *mean_eps, *msq_eps, *mean_gam, *msq_gam, *mean_beta, *msq_beta;
+    double *mean_hyp, *msq_hyp;
+    int64_t count;
+} fb_summary;
+
+int fb_summaries(fb_ctx *c, int32_t seg, fb_summary *s);
+
+/* Trace (Section 3.1: thinned samples of the hyperparameters and of a few
+ * genes).  Each point of segment seg holds 2 + 2L + T (L + 1) floats:
+ * hyp (nu, tau, theta, sigma^2), then for each traced gene gamma, beta_1..L.
+ * Points are recorded on sweeps m with m % thin == 0 (and m > M_B when
+ * trace_after_burnin), into rows 0, 1, ... of a device buffer of
+ * trace_capacity points shared in numbering by all segments.
+ * fb_trace_genes writes the T traced gene indices (ascending).
+ * fb_trace copies the first min(recorded, cap) points of segment seg into buf
+ * ([points][2 + 2L + T (L + 1)] floats) and sets *n_out (with buf = NULL it
+ * only reports the number recorded); *dropped counts sweeps not recorded
+ * because the buffer was full.  fb_trace_reset forgets every recorded point. */
+int fb_trace_genes(const fb_ctx *c, int32_t seg, int64_t *genes, int32_t *T);
+int fb_trace(fb_ctx *c, int32_t seg, float *buf, int64_t cap, int64_t *n_out,
+             int64_t *dropped);
+int fb_trace_reset(fb_ctx *c);
+
+/* Per-draw integer records of the last sweep when opt.debug_counts = 1:
+ * 4 int32 per slice draw (K_L, left moves, right moves, shrink candidates):
+ * eps [G][N][4], gamma [G][4], beta [G][L][4], hyp [2 + L][4] (nu, tau, sigma^2). */
+int fb_debug_counts(fb_ctx *c, int32_t seg, int32_t *eps, int32_t *gam, int32_t *beta,
+                    int32_t *hyp);
+
+/* The reductions the last hyperparameter step used (FP64):
+ * [sum log gamma, sum 1/gamma, then per l: sum beta_l, sum (beta_l - theta_l)^2]. */
+int fb_reductions(fb_ctx *c, int32_t seg, double *out);
+
+/* Philox4x32-10 words computed on the device: ctr [n][4], key [n][2], out [n][4]. */
+int fb_philox(const uint32_t *ctr, const uint32_t *key, uint32_t *out, int64_t n);
+
+/* Time of the last fb_sweep batch measured with HIP events around the gene and
+ * hyperparameter kernels (milliseconds), and the number of sweeps in it. */
+int fb_last_sweep_time(fb_ctx *c, double *ms, int64_t *sweeps);
+
+/* Sampled kernel timing with HIP events on the context's stream: from now on,
+ * the gene and hyperparameter launches of every `every`-th sweep are bracketed
+ * by events, for at most max_samples sweeps (every = 0 turns it off).
+ * fb_kernel_times waits for the stream, returns the mean duration of the
+ * sampled gene-kernel launches and hyperparameter-kernel launches (ms) and the
+ * number of samples, and starts a new sample set. */
+int fb_profile(fb_ctx *c, int32_t every, int32_t max_samples);
+int fb_kernel_times(fb_ctx *c, double *gene_ms, double *hyper_ms, int64_t *samples);
+
+const char *fb_last_error(const fb_ctx *c);
+const char *fb_strerror(int code);
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* LIBFBMC_H */

@@ -1,0 +1,965 @@
+// fbmc_host.cpp -- host runtime behind the libfbmc C ABI (include/libfbmc.h).
+//
+// Owns the device buffers of every segment (one dataset x one chain), validates
+// and analyses the design matrix, computes starting values, launches the two
+// sweep kernels per sweep on the context's stream, and copies state, moments,
+// traces and per-draw records back on request.
+#include "libfbmc.h"
+
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <cmath>
+#include <cstdio>
+#include <cstring>
+#include <string>
+#include <vector>
+
+#include "fbmc_device.hpp"
+#include "fbmc_types.hpp"
+
+namespace fbmc {
+hipError_t launch_gene(int precision, const SegInfo *segs, const int2 *tiles, int ntiles,
+                       const SweepArgs &a, int *err, hipStream_t st);
+hipError_t launch_hyper(const SegInfo *segs, int nseg, const SweepArgs &a, int *err, hipStream_t st);
+hipError_t launch_philox(const uint4 *ctr, const uint2 *key, uint4 *out, int64_t n, hipStream_t st);
+}  // namespace fbmc
+
+using namespace fbmc;
+
+namespace {
+
+thread_local std::string g_thread_err;
+
+struct Design {
+    int R = 0;
+    std::vector<int> row_of;            // [N]
+    std::vector<double> Xrow;           // [R][L]
+    std::vector<int> nv;                // [L]
+    std::vector<double> vals;           // [L][kMaxVals]
+    std::vector<int> xidx;              // [R][L]
+};
+
+struct DatasetH {
+    int64_t G = 0, Gp = 0;
+    int N = 0, L = 0;
+    std::vector<int32_t> y;   // [G][N]
+    std::vector<double> X, h, c, s;
+    double a = 1, b = 1, d = 1000;
+    uint64_t seed = 0;
+    Design des;
+    int32_t *d_y = nullptr;   // [N][Gp]
+};
+
+struct SegmentH {
+    int dataset = 0, chain = 0;
+    int64_t G = 0, Gp = 0, ntiles = 0;
+    int N = 0, L = 0;
+    SegInfo info{};
+    HyperState *d_hyp = nullptr;
+    std::vector<int64_t> trace_genes;
+};
+
+}  // namespace
+
+struct fb_ctx {
+    fb_options opt{};
+    int prec = 0;
+    size_t esz = 8;
+    std::vector<DatasetH> ds;
+    std::vector<SegmentH> seg;
+    SegInfo *d_segs = nullptr;
+    int2 *d_tiles = nullptr;
+    int ntiles = 0;
+    hipStream_t st = nullptr;
+    bool own_stream = false;
+    int *d_err = nullptr;
+    int sticky = FB_OK;
+    int64_t m = 0;
+    int64_t trace_n = 0, trace_dropped = 0;
+    int trace_stride_max = 0;
+    std::string err;
+    std::vector<void *> allocs;
+    hipEvent_t ev0 = nullptr, ev1 = nullptr;
+    int64_t last_n = 0;
+    // sampled per-kernel timing: events around the gene and hyper launches of
+    // every `prof_every`-th sweep
+    int32_t prof_every = 0, prof_cap = 0, prof_n = 0;
+    int64_t prof_count = 0;
+    std::vector<hipEvent_t> prof_ev;   // 4 per sample
+};
+
+namespace {
+
+int fail(fb_ctx *c, int code, const std::string &msg)
+{
+    if (c) c->err = msg;
+    else g_thread_err = msg;
+    return code;
+}
+
+#define HIPCHK(ctx, expr)                                                                   \
+    do {                                                                                    \
+        hipError_t e_ = (expr);                                                             \
+        if (e_ != hipSuccess)                                                               \
+            return fail((ctx), FB_EDEVICE, std::string(#expr) + ": " + hipGetErrorString(e_)); \
+    } while (0)
+
+int dalloc(fb_ctx *c, void **p, size_t bytes)
+{
+    *p = nullptr;
+    if (bytes == 0) bytes = 256;
+    hipError_t e = hipMalloc(p, bytes);
+    if (e != hipSuccess) {
+        *p = nullptr;
+        return fail(c, FB_ENOMEM, std::string("hipMalloc: ") + hipGetErrorString(e));
+    }
+    c->allocs.push_back(*p);
+    e = hipMemset(*p, 0, bytes);
+    if (e != hipSuccess) return fail(c, FB_EDEVICE, std::string("hipMemset: ") + hipGetErrorString(e));
+    return FB_OK;
+}
+
+bool finite_all(const double *p, size_t n)
+{
+    for (size_t i = 0; i < n; ++i)
+        if (!std::isfinite(p[i])) return false;
+    return true;
+}
+
+// Distinct rows of X and, per column, the distinct non-zero values.
+int analyse_design(const std::vector<double> &X, int N, int L, Design &D, std::string &msg)
+{
+    D.row_of.assign(N, -1);
+    D.Xrow.clear();
+    for (int n = 0; n < N; ++n) {
+        int found = -1;
+        for (int r = 0; r < (int)(D.Xrow.size() / L); ++r) {
+            bool same = true;
+            for (int l = 0; l < L; ++l)
+                if (D.Xrow[r * L + l] != X[n * L + l]) { same = false; break; }
+            if (same) { found = r; break; }
+        }
+        if (found < 0) {
+            found = (int)(D.Xrow.size() / L);
+            for (int l = 0; l < L; ++l) D.Xrow.push_back(X[n * L + l]);
+        }
+        D.row_of[n] = found;
+    }
+    D.R = (int)(D.Xrow.size() / L);
+    if (D.R > kMaxRows) {
+        msg = "the design matrix has " + std::to_string(D.R) + " distinct rows; at most " +
+              std::to_string(kMaxRows) + " are supported";
+        return FB_EINVAL;
+    }
+    D.nv.assign(L, 0);
+    D.vals.assign((size_t)L * kMaxVals, 0.0);
+    D.xidx.assign((size_t)D.R * L, -1);
+    for (int l = 0; l < L; ++l) {
+        for (int r = 0; r < D.R; ++r) {
+            const double v = D.Xrow[r * L + l];
+            if (v == 0.0) continue;
+            int k = -1;
+            for (int j = 0; j < D.nv[l]; ++j)
+                if (D.vals[l * kMaxVals + j] == v) { k = j; break; }
+            if (k < 0) {
+                if (D.nv[l] == kMaxVals) {
+                    msg = "column " + std::to_string(l) + " of X has more than " +
+                          std::to_string(kMaxVals) + " distinct non-zero values";
+                    return FB_EINVAL;
+                }
+                k = D.nv[l]++;
+                D.vals[l * kMaxVals + k] = v;
+            }
+            D.xidx[r * L + l] = k;
+        }
+    }
+    return FB_OK;
+}
+
+// Solve the symmetric positive definite system A x = b (Cholesky), n <= kMaxL.
+bool chol_solve(std::vector<double> A, std::vector<double> &b, int n)
+{
+    for (int j = 0; j < n; ++j) {
+        double s = A[j * n + j];
+        for (int k = 0; k < j; ++k) s -= A[j * n + k] * A[j * n + k];
+        if (!(s > 0)) return false;
+        const double dj = std::sqrt(s);
+        A[j * n + j] = dj;
+        for (int i = j + 1; i < n; ++i) {
+            double t = A[i * n + j];
+            for (int k = 0; k < j; ++k) t -= A[i * n + k] * A[j * n + k];
+            A[i * n + j] = t / dj;
+        }
+    }
+    for (int i = 0; i < n; ++i) {
+        double t = b[i];
+        for (int k = 0; k < i; ++k) t -= A[i * n + k] * b[k];
+        b[i] = t / A[i * n + i];
+    }
+    for (int i = n - 1; i >= 0; --i) {
+        double t = b[i];
+        for (int k = i + 1; k < n; ++k) t -= A[k * n + i] * b[k];
+        b[i] = t / A[i * n + i];
+    }
+    return true;
+}
+
+double std_normal(uint64_t seed, uint32_t g, uint32_t sub, uint32_t chain)
+{
+    const uint4 r = philox4x32_10(draw_counter(g, 9, sub, 0, chain, 0), (uint32_t)seed, (uint32_t)(seed >> 32));
+    const double u0 = ((double)r.x + 0.5) * 0x1p-32, u1 = ((double)r.y + 0.5) * 0x1p-32;
+    return std::sqrt(-2.0 * std::log(u0)) * std::cos(6.283185307179586 * u1);
+}
+
+struct HostState {
+    std::vector<double> eps, gam, beta;   // row-major [G][N], [G], [G][L]
+    double nu = 10, tau = 0.1;
+    std::vector<double> theta, sig2;
+};
+
+// Starting values: per-gene least squares of log(1 + y) - h on X.
+void default_start(const DatasetH &D, int chain, bool jitter, HostState &S)
+{
+    const int64_t G = D.G;
+    const int N = D.N, L = D.L;
+    std::vector<double> XtX((size_t)L * L, 0.0);
+    for (int i = 0; i < L; ++i)
+        for (int j = 0; j < L; ++j) {
+            double s = (i == j) ? 1e-8 : 0.0;
+            for (int n = 0; n < N; ++n) s += D.X[n * L + i] * D.X[n * L + j];
+            XtX[i * L + j] = s;
+        }
+    S.eps.assign((size_t)G * N, 0.0);
+    S.gam.assign(G, 0.1);
+    S.beta.assign((size_t)G * L, 0.0);
+    std::vector<double> rhs(L), z(N);
+    for (int64_t g = 0; g < G; ++g) {
+        for (int n = 0; n < N; ++n) z[n] = std::log1p((double)D.y[g * N + n]) - D.h[n];
+        for (int l = 0; l < L; ++l) {
+            double s = 0;
+            for (int n = 0; n < N; ++n) s += D.X[n * L + l] * z[n];
+            rhs[l] = s;
+        }
+        if (!chol_solve(XtX, rhs, L)) std::fill(rhs.begin(), rhs.end(), 0.0);
+        double rss = 0;
+        for (int n = 0; n < N; ++n) {
+            double e = z[n];
+            for (int l = 0; l < L; ++l) e -= D.X[n * L + l] * rhs[l];
+            rss += e * e;
+        }
+        S.gam[g] = std::max(N > L ? rss / (N - L) : 0.1, 0.01);
+        for (int l = 0; l < L; ++l) S.beta[g * L + l] = rhs[l];
+    }
+    std::vector<double> mean(L, 0.0), var(L, 0.0);
+    for (int64_t g = 0; g < G; ++g)
+        for (int l = 0; l < L; ++l) mean[l] += S.beta[g * L + l];
+    for (int l = 0; l < L; ++l) mean[l] /= (double)G;
+    for (int64_t g = 0; g < G; ++g)
+        for (int l = 0; l < L; ++l) {
+            const double dv = S.beta[g * L + l] - mean[l];
+            var[l] += dv * dv;
+        }
+    for (int l = 0; l < L; ++l) var[l] = G > 1 ? var[l] / (double)(G - 1) : 1.0;
+    if (jitter && chain > 0) {
+        // overdispersed start: shift every beta by one across-gene sd, scale gamma
+        for (int64_t g = 0; g < G; ++g) {
+            for (int l = 0; l < L; ++l)
+                S.beta[g * L + l] += std::sqrt(var[l]) * std_normal(D.seed, (uint32_t)g, (uint32_t)l, chain);
+            S.gam[g] *= std::exp(0.5 * std_normal(D.seed, (uint32_t)g, 100, chain));
+        }
+    }
+    S.theta.assign(L, 0.0);
+    S.sig2.assign(L, 0.0);
+    for (int64_t g = 0; g < G; ++g)
+        for (int l = 0; l < L; ++l) S.theta[l] += S.beta[g * L + l];
+    for (int l = 0; l < L; ++l) S.theta[l] /= (double)G;
+    for (int64_t g = 0; g < G; ++g)
+        for (int l = 0; l < L; ++l) {
+            const double dv = S.beta[g * L + l] - S.theta[l];
+            S.sig2[l] += dv * dv;
+        }
+    for (int l = 0; l < L; ++l) {
+        double v = S.sig2[l] / (double)G;
+        v = std::max(v, 1e-4);
+        v = std::min(v, 0.25 * D.s[l] * D.s[l]);
+        S.sig2[l] = v;
+    }
+    double tm = 0;
+    for (int64_t g = 0; g < G; ++g) tm += S.gam[g];
+    S.tau = tm / (double)G;
+    S.nu = std::min(10.0, 0.5 * D.d);
+    if (jitter && chain > 0) S.nu *= std::exp(0.3 * std_normal(D.seed, 0, 200, chain));
+    S.nu = std::min(S.nu, 0.9 * D.d);
+}
+
+// Host row-major [G][K] doubles -> device [K][Gp] in the working precision.
+void to_soa(const double *src, int64_t G, int K, int64_t Gp, int prec, std::vector<char> &buf,
+            double pad)
+{
+    const size_t esz = prec == 0 ? 8 : 4;
+    buf.assign((size_t)K * Gp * esz, 0);
+    for (int k = 0; k < K; ++k)
+        for (int64_t g = 0; g < Gp; ++g) {
+            const double v = g < G ? src[g * K + k] : pad;
+            if (prec == 0) reinterpret_cast<double *>(buf.data())[k * Gp + g] = v;
+            else reinterpret_cast<float *>(buf.data())[k * Gp + g] = (float)v;
+        }
+}
+
+void from_soa(const std::vector<char> &buf, int64_t G, int K, int64_t Gp, int prec, double *dst)
+{
+    for (int k = 0; k < K; ++k)
+        for (int64_t g = 0; g < G; ++g)
+            dst[g * K + k] = prec == 0 ? reinterpret_cast<const double *>(buf.data())[k * Gp + g]
+                                       : (double)reinterpret_cast<const float *>(buf.data())[k * Gp + g];
+}
+
+int upload_array(fb_ctx *c, void *dst, const double *src, int64_t G, int K, int64_t Gp, double pad)
+{
+    std::vector<char> buf;
+    to_soa(src, G, K, Gp, c->prec, buf, pad);
+    HIPCHK(c, hipMemcpy(dst, buf.data(), buf.size(), hipMemcpyHostToDevice));
+    return FB_OK;
+}
+
+int download_array(fb_ctx *c, const void *srcdev, int64_t G, int K, int64_t Gp, double *dst)
+{
+    std::vector<char> buf((size_t)K * Gp * c->esz);
+    HIPCHK(c, hipMemcpy(buf.data(), srcdev, buf.size(), hipMemcpyDeviceToHost));
+    from_soa(buf, G, K, Gp, c->prec, dst);
+    return FB_OK;
+}
+
+int validate_options(const fb_options &o, std::string &msg)
+{
+    if (o.chains < 1 || o.chains > 65535) { msg = "chains must be in 1..65535"; return FB_EINVAL; }
+    if (o.burnin < 0 || o.tune_start < 0 || o.tune_start > o.burnin) {
+        msg = "need 0 <= tune_start <= burnin";
+        return FB_EINVAL;
+    }
+    if (!(o.max_steps == 0 || o.max_steps == 1 || o.max_steps == 3 || o.max_steps == 7 || o.max_steps == 15)) {
+        msg = "max_steps must be 0, 1, 3, 7 or 15";
+        return FB_EINVAL;
+    }
+    if (!(o.w0 > 0) || !std::isfinite(o.w0)) { msg = "w0 must be a positive finite number"; return FB_EINVAL; }
+    if (o.shrink_cap < 1) { msg = "shrink_cap must be >= 1"; return FB_EINVAL; }
+    if (o.precision != FB_FP64 && o.precision != FB_FP32) { msg = "unknown precision"; return FB_EINVAL; }
+    if (o.thin < 0 || o.trace_genes < 0 || o.trace_capacity < 0) { msg = "negative trace option"; return FB_EINVAL; }
+    return FB_OK;
+}
+
+int validate_dataset(const fb_dataset &d, std::string &msg)
+{
+    if (!d.counts || !d.X || !d.h) { msg = "counts, X and h must not be NULL"; return FB_EINVAL; }
+    if (d.G < 1 || d.G > ((int64_t)1 << 31) - kTile) { msg = "G out of range"; return FB_EINVAL; }
+    if (d.N < 1 || d.N > kMaxN) { msg = "N must be in 1.." + std::to_string(kMaxN); return FB_EINVAL; }
+    if (d.L < 1 || d.L > kMaxL || d.L > d.N) { msg = "need 1 <= L <= min(N, " + std::to_string(kMaxL) + ")"; return FB_EINVAL; }
+    for (int64_t i = 0; i < d.G * d.N; ++i)
+        if (d.counts[i] < 0) { msg = "counts must be >= 0"; return FB_EINVAL; }
+    if (!finite_all(d.X, (size_t)d.N * d.L) || !finite_all(d.h, d.N)) { msg = "X and h must be finite"; return FB_EINVAL; }
+    if (d.priors) {
+        const fb_priors &p = *d.priors;
+        if (!(p.a > 0) || !(p.b > 0) || !(p.d > 0) || !std::isfinite(p.a) || !std::isfinite(p.b) || !std::isfinite(p.d)) {
+            msg = "priors a, b, d must be positive and finite";
+            return FB_EINVAL;
+        }
+        if (!p.c || !p.s) { msg = "priors c and s must not be NULL"; return FB_EINVAL; }
+        for (int l = 0; l < d.L; ++l)
+            if (!(p.c[l] > 0) || !(p.s[l] > 0) || !std::isfinite(p.c[l]) || !std::isfinite(p.s[l])) {
+                msg = "priors c_l and s_l must be positive and finite";
+                return FB_EINVAL;
+            }
+    }
+    return FB_OK;
+}
+
+int write_state(fb_ctx *c, SegmentH &S, const HostState &hs)
+{
+    const DatasetH &D = c->ds[S.dataset];
+    const int N = D.N, L = D.L;
+    int rc;
+    if ((rc = upload_array(c, S.info.eps, hs.eps.data(), S.G, N, S.Gp, 0.0))) return rc;
+    if ((rc = upload_array(c, S.info.gam, hs.gam.data(), S.G, 1, S.Gp, 1.0))) return rc;
+    if ((rc = upload_array(c, S.info.beta, hs.beta.data(), S.G, L, S.Gp, 0.0))) return rc;
+    HyperState H{};
+    HIPCHK(c, hipMemcpy(&H, S.d_hyp, sizeof(H), hipMemcpyDeviceToHost));
+    H.nu = hs.nu;
+    H.tau = hs.tau;
+    for (int l = 0; l < L; ++l) { H.theta[l] = hs.theta[l]; H.sig2[l] = hs.sig2[l]; }
+    HIPCHK(c, hipMemcpy(S.d_hyp, &H, sizeof(H), hipMemcpyHostToDevice));
+    return FB_OK;
+}
+
+int build_context(fb_ctx *c, const fb_dataset *dsv, int nds)
+{
+    int rc;
+    std::string msg;
+    c->prec = c->opt.precision;
+    c->esz = c->prec == 0 ? 8 : 4;
+    // datasets
+    c->ds.resize(nds);
+    for (int k = 0; k < nds; ++k) {
+        const fb_dataset &in = dsv[k];
+        DatasetH &D = c->ds[k];
+        D.G = in.G;
+        D.N = in.N;
+        D.L = in.L;
+        D.Gp = (in.G + kTile - 1) / kTile * kTile;
+        D.y.assign(in.counts, in.counts + in.G * in.N);
+        D.X.assign(in.X, in.X + in.N * in.L);
+        D.h.assign(in.h, in.h + in.N);
+        D.a = in.priors ? in.priors->a : 1.0;
+        D.b = in.priors ? in.priors->b : 1.0;
+        D.d = in.priors ? in.priors->d : 1000.0;
+        D.c.assign(in.L, 10.0);
+        D.s.assign(in.L, 100.0);
+        if (in.priors)
+            for (int l = 0; l < in.L; ++l) { D.c[l] = in.priors->c[l]; D.s[l] = in.priors->s[l]; }
+        D.seed = in.seed;
+        if ((rc = analyse_design(D.X, D.N, D.L, D.des, msg))) return fail(c, rc, msg);
+        // counts, gene-contiguous
+        std::vector<int32_t> yt((size_t)D.N * D.Gp, 0);
+        for (int64_t g = 0; g < D.G; ++g)
+            for (int n = 0; n < D.N; ++n) yt[(size_t)n * D.Gp + g] = D.y[g * D.N + n];
+        if ((rc = dalloc(c, (void **)&D.d_y, yt.size() * sizeof(int32_t)))) return rc;
+        HIPCHK(c, hipMemcpy(D.d_y, yt.data(), yt.size() * sizeof(int32_t), hipMemcpyHostToDevice));
+    }
+    // segments
+    const int C = c->opt.chains;
+    c->seg.resize((size_t)nds * C);
+    std::vector<int2> tiles;
+    for (int k = 0; k < nds; ++k) {
+        const DatasetH &D = c->ds[k];
+        for (int ch = 0; ch < C; ++ch) {
+            SegmentH &S = c->seg[(size_t)k * C + ch];
+            S.dataset = k;
+            S.chain = ch;
+            S.G = D.G;
+            S.Gp = D.Gp;
+            S.ntiles = D.Gp / kTile;
+            S.N = D.N;
+            S.L = D.L;
+            SegInfo &I = S.info;
+            I.G = D.G; I.Gp = D.Gp; I.ntiles = S.ntiles;
+            I.N = D.N; I.L = D.L; I.R = D.des.R;
+            I.chain = ch;
+            I.key0 = (uint32_t)D.seed;
+            I.key1 = (uint32_t)(D.seed >> 32);
+            I.dataset = k;
+            for (int n = 0; n < D.N; ++n) {
+                for (int l = 0; l < D.L; ++l) I.X[n * kMaxL + l] = D.X[n * D.L + l];
+                I.h[n] = D.h[n];
+                I.eh[n] = std::exp(D.h[n]);
+                I.row_of[n] = D.des.row_of[n];
+            }
+            for (int r = 0; r < D.des.R; ++r)
+                for (int l = 0; l < D.L; ++l) {
+                    I.Xrow[r * kMaxL + l] = D.des.Xrow[r * D.L + l];
+                    I.xidx[r * kMaxL + l] = D.des.xidx[r * D.L + l];
+                }
+            for (int l = 0; l < D.L; ++l) {
+                I.nv[l] = D.des.nv[l];
+                for (int j = 0; j < kMaxVals; ++j) I.vals[l * kMaxVals + j] = D.des.vals[l * kMaxVals + j];
+                I.c[l] = D.c[l];
+                I.s[l] = D.s[l];
+            }
+            I.a = D.a; I.b = D.b; I.d = D.d;
+            I.y = D.d_y;
+            const size_t e = c->esz, Gp = (size_t)D.Gp, N = D.N, L = D.L;
+            void **arrs_nk[] = {&I.eps, &I.w_eps, &I.wa_eps};
+            for (void **p : arrs_nk) if ((rc = dalloc(c, p, N * Gp * e))) return rc;
+            void **arrs_1[] = {&I.gam, &I.w_gam, &I.wa_gam};
+            for (void **p : arrs_1) if ((rc = dalloc(c, p, Gp * e))) return rc;
+            void **arrs_l[] = {&I.beta, &I.w_beta, &I.wa_beta};
+            for (void **p : arrs_l) if ((rc = dalloc(c, p, L * Gp * e))) return rc;
+            if ((rc = dalloc(c, (void **)&I.mom_eps, N * Gp * sizeof(double2)))) return rc;
+            if ((rc = dalloc(c, (void **)&I.mom_gam, Gp * sizeof(double2)))) return rc;
+            if ((rc = dalloc(c, (void **)&I.mom_beta, L * Gp * sizeof(double2)))) return rc;
+            if ((rc = dalloc(c, (void **)&I.partials, (size_t)S.ntiles * kMaxParts * sizeof(double)))) return rc;
+            if ((rc = dalloc(c, (void **)&S.d_hyp, sizeof(HyperState)))) return rc;
+            I.hyp = S.d_hyp;
+            if (c->opt.debug_counts) {
+                if ((rc = dalloc(c, (void **)&I.dbg_eps, N * Gp * sizeof(int4)))) return rc;
+                if ((rc = dalloc(c, (void **)&I.dbg_gam, Gp * sizeof(int4)))) return rc;
+                if ((rc = dalloc(c, (void **)&I.dbg_beta, L * Gp * sizeof(int4)))) return rc;
+            }
+            // trace
+            const int64_t T = std::min<int64_t>(c->opt.trace_genes, D.G);
+            S.trace_genes.clear();
+            for (int64_t i = 0; i < T; ++i) S.trace_genes.push_back(i * D.G / T);
+            I.trace_T = (int32_t)T;
+            I.trace_stride = (int32_t)(2 + 2 * L + T * (L + 1));
+            c->trace_stride_max = std::max(c->trace_stride_max, I.trace_stride);
+            std::vector<int32_t> slot(Gp, -1);
+            for (int64_t i = 0; i < T; ++i) slot[S.trace_genes[i]] = (int32_t)i;
+            if ((rc = dalloc(c, (void **)&I.trace_slot, Gp * sizeof(int32_t)))) return rc;
+            HIPCHK(c, hipMemcpy(I.trace_slot, slot.data(), Gp * sizeof(int32_t), hipMemcpyHostToDevice));
+            if (c->opt.thin > 0 && c->opt.trace_capacity > 0) {
+                if ((rc = dalloc(c, (void **)&I.trace, (size_t)c->opt.trace_capacity * I.trace_stride * sizeof(float))))
+                    return rc;
+            }
+            // widths and hyperparameter widths
+            std::vector<double> w0v((size_t)D.G * std::max(D.N, D.L), c->opt.w0);
+            if ((rc = upload_array(c, I.w_eps, w0v.data(), D.G, D.N, D.Gp, 1.0))) return rc;
+            if ((rc = upload_array(c, I.w_gam, w0v.data(), D.G, 1, D.Gp, 1.0))) return rc;
+            if ((rc = upload_array(c, I.w_beta, w0v.data(), D.G, D.L, D.Gp, 1.0))) return rc;
+            HyperState H{};
+            H.w_nu = H.w_tau = c->opt.w0;
+            for (int l = 0; l < kMaxL; ++l) H.w_sig2[l] = c->opt.w0;
+            HIPCHK(c, hipMemcpy(S.d_hyp, &H, sizeof(H), hipMemcpyHostToDevice));
+            HostState hs;
+            default_start(D, ch, c->opt.jitter != 0, hs);
+            if ((rc = write_state(c, S, hs))) return rc;
+            for (int64_t t = 0; t < S.ntiles; ++t) tiles.push_back(make_int2((int)(k * C + ch), (int)t));
+        }
+    }
+    c->ntiles = (int)tiles.size();
+    if ((rc = dalloc(c, (void **)&c->d_tiles, tiles.size() * sizeof(int2)))) return rc;
+    HIPCHK(c, hipMemcpy(c->d_tiles, tiles.data(), tiles.size() * sizeof(int2), hipMemcpyHostToDevice));
+    std::vector<SegInfo> infos;
+    for (auto &S : c->seg) infos.push_back(S.info);
+    if ((rc = dalloc(c, (void **)&c->d_segs, infos.size() * sizeof(SegInfo)))) return rc;
+    HIPCHK(c, hipMemcpy(c->d_segs, infos.data(), infos.size() * sizeof(SegInfo), hipMemcpyHostToDevice));
+    if ((rc = dalloc(c, (void **)&c->d_err, sizeof(int)))) return rc;
+    if (c->opt.stream) {
+        c->st = (hipStream_t)c->opt.stream;
+    } else {
+        HIPCHK(c, hipStreamCreateWithFlags(&c->st, hipStreamNonBlocking));
+        c->own_stream = true;
+    }
+    HIPCHK(c, hipEventCreate(&c->ev0));
+    HIPCHK(c, hipEventCreate(&c->ev1));
+    return FB_OK;
+}
+
+bool valid_seg(const fb_ctx *c, int32_t seg) { return c && seg >= 0 && seg < (int32_t)c->seg.size(); }
+
+}  // namespace
+
+// ===========================================================================
+// C ABI
+// ===========================================================================
+extern "C" {
+
+void fb_default_options(fb_options *o)
+{
+    if (!o) return;
+    std::memset(o, 0, sizeof(*o));
+    o->chains = 1;
+    o->burnin = 1000;
+    o->tune_start = 100;
+    o->max_steps = 15;
+    o->w0 = 1.0;
+    o->shrink_cap = 200;
+    o->precision = FB_FP64;
+    o->update_mask = FB_UPDATE_ALL;
+    o->thin = 0;
+    o->trace_genes = 0;
+    o->trace_after_burnin = 1;
+    o->trace_capacity = 0;
+    o->debug_counts = 0;
+    o->jitter = 1;
+    o->stream = nullptr;
+}
+
+int fb_create_batch(fb_ctx **out, const fb_dataset *ds, int32_t n_datasets, const fb_options *opt)
+{
+    if (!out) return fail(nullptr, FB_EINVAL, "out must not be NULL");
+    *out = nullptr;
+    if (!ds || n_datasets < 1) return fail(nullptr, FB_EINVAL, "need at least one dataset");
+    fb_options o;
+    fb_default_options(&o);
+    if (opt) o = *opt;
+    std::string msg;
+    int rc = validate_options(o, msg);
+    if (rc) return fail(nullptr, rc, msg);
+    for (int k = 0; k < n_datasets; ++k)
+        if ((rc = validate_dataset(ds[k], msg))) return fail(nullptr, rc, "dataset " + std::to_string(k) + ": " + msg);
+    fb_ctx *c = new (std::nothrow) fb_ctx();
+    if (!c) return fail(nullptr, FB_ENOMEM, "out of host memory");
+    c->opt = o;
+    rc = build_context(c, ds, n_datasets);
+    if (rc) {
+        g_thread_err = c->err;
+        fb_destroy(c);
+        return rc;
+    }
+    *out = c;
+    return FB_OK;
+}
+
+int fb_create(fb_ctx **out, const int32_t *counts, int64_t G, int32_t N, const double *X, int32_t L,
+              const double *h, const fb_priors *pri, uint64_t seed, const fb_options *opt)
+{
+    fb_dataset d{counts, G, N, X, L, h, pri, seed};
+    return fb_create_batch(out, &d, 1, opt);
+}
+
+void fb_destroy(fb_ctx *c)
+{
+    if (!c) return;
+    if (c->st) (void)hipStreamSynchronize(c->st);
+    for (hipEvent_t e : c->prof_ev) (void)hipEventDestroy(e);
+    for (void *p : c->allocs) (void)hipFree(p);
+    if (c->ev0) (void)hipEventDestroy(c->ev0);
+    if (c->ev1) (void)hipEventDestroy(c->ev1);
+    if (c->own_stream && c->st) (void)hipStreamDestroy(c->st);
+    delete c;
+}
+
+int fb_sweep(fb_ctx *c, int64_t n)
+{
+    if (!c) return fail(nullptr, FB_EINVAL, "NULL context");
+    if (n < 0) return fail(c, FB_EINVAL, "n must be >= 0");
+    if (c->sticky) return c->sticky;
+    const fb_options &o = c->opt;
+    HIPCHK(c, hipEventRecord(c->ev0, c->st));
+    for (int64_t i = 0; i < n; ++i) {
+        SweepArgs a{};
+        a.m = c->m + 1;
+        a.burnin = o.burnin;
+        a.tune_start = o.tune_start;
+        a.K = o.max_steps;
+        a.cap = o.shrink_cap;
+        a.mask = o.update_mask;
+        a.dbg = o.debug_counts;
+        a.trace_point = -1;
+        if (o.thin > 0 && o.trace_capacity > 0 && a.m % o.thin == 0 && (!o.trace_after_burnin || a.m > o.burnin)) {
+            if (c->trace_n < o.trace_capacity) a.trace_point = (int32_t)c->trace_n++;
+            else ++c->trace_dropped;
+        }
+        const bool prof = c->prof_every > 0 && c->prof_n < c->prof_cap && (c->prof_count++ % c->prof_every) == 0;
+        hipEvent_t *pe = prof ? &c->prof_ev[4 * (size_t)c->prof_n++] : nullptr;
+        if (pe) HIPCHK(c, hipEventRecord(pe[0], c->st));
+        HIPCHK(c, launch_gene(c->prec, c->d_segs, c->d_tiles, c->ntiles, a, c->d_err, c->st));
+        if (pe) HIPCHK(c, hipEventRecord(pe[1], c->st));
+        if (pe) HIPCHK(c, hipEventRecord(pe[2], c->st));
+        HIPCHK(c, launch_hyper(c->d_segs, (int)c->seg.size(), a, c->d_err, c->st));
+        if (pe) HIPCHK(c, hipEventRecord(pe[3], c->st));
+        c->m = a.m;
+    }
+    HIPCHK(c, hipEventRecord(c->ev1, c->st));
+    c->last_n = n;
+    return FB_OK;
+}
+
+int fb_sync(fb_ctx *c)
+{
+    if (!c) return fail(nullptr, FB_EINVAL, "NULL context");
+    HIPCHK(c, hipStreamSynchronize(c->st));
+    int flag = 0;
+    HIPCHK(c, hipMemcpy(&flag, c->d_err, sizeof(int), hipMemcpyDeviceToHost));
+    if (flag && !c->sticky) {
+        c->sticky = FB_ENUMERIC;
+        c->err = "a slice draw reached the shrink cap or met a non-finite log density";
+    }
+    return c->sticky;
+}
+
+int32_t fb_num_segments(const fb_ctx *c) { return c ? (int32_t)c->seg.size() : 0; }
+
+int fb_segment_dims(const fb_ctx *c, int32_t seg, int64_t *G, int32_t *N, int32_t *L, int32_t *dataset,
+                    int32_t *chain)
+{
+    if (!valid_seg(c, seg)) return fail(const_cast<fb_ctx *>(c), FB_EINVAL, "bad segment");
+    const SegmentH &S = c->seg[seg];
+    if (G) *G = S.G;
+    if (N) *N = S.N;
+    if (L) *L = S.L;
+    if (dataset) *dataset = S.dataset;
+    if (chain) *chain = S.chain;
+    return FB_OK;
+}
+
+int fb_get_state(fb_ctx *c, int32_t seg, fb_state *s)
+{
+    if (!valid_seg(c, seg) || !s) return fail(c, FB_EINVAL, "bad segment or NULL state");
+    int rc = fb_sync(c);
+    if (rc && rc != FB_ENUMERIC) return rc;
+    SegmentH &S = c->seg[seg];
+    const int N = S.N, L = S.L;
+    const SegInfo &I = S.info;
+    struct { double *dst; const void *src; int K; } blocks[] = {
+        {s->eps, I.eps, N}, {s->w_eps, I.w_eps, N}, {s->waux_eps, I.wa_eps, N},
+        {s->gam, I.gam, 1}, {s->w_gam, I.w_gam, 1}, {s->waux_gam, I.wa_gam, 1},
+        {s->beta, I.beta, L}, {s->w_beta, I.w_beta, L}, {s->waux_beta, I.wa_beta, L}};
+    for (auto &b : blocks)
+        if (b.dst && (rc = download_array(c, b.src, S.G, b.K, S.Gp, b.dst))) return rc;
+    HyperState H;
+    HIPCHK(c, hipMemcpy(&H, S.d_hyp, sizeof(H), hipMemcpyDeviceToHost));
+    if (s->hyp) {
+        s->hyp[0] = H.nu;
+        s->hyp[1] = H.tau;
+        for (int l = 0; l < L; ++l) { s->hyp[2 + l] = H.theta[l]; s->hyp[2 + L + l] = H.sig2[l]; }
+    }
+    if (s->w_hyp) {
+        s->w_hyp[0] = H.w_nu; s->w_hyp[1] = H.w_tau;
+        for (int l = 0; l < L; ++l) s->w_hyp[2 + l] = H.w_sig2[l];
+    }
+    if (s->waux_hyp) {
+        s->waux_hyp[0] = H.wa_nu; s->waux_hyp[1] = H.wa_tau;
+        for (int l = 0; l < L; ++l) s->waux_hyp[2 + l] = H.wa_sig2[l];
+    }
+    s->m = c->m;
+    return c->sticky;
+}
+
+int fb_set_state(fb_ctx *c, int32_t seg, const fb_state *s)
+{
+    if (!valid_seg(c, seg) || !s) return fail(c, FB_EINVAL, "bad segment or NULL state");
+    if (s->m < 0) return fail(c, FB_EINVAL, "m must be >= 0");
+    SegmentH &S = c->seg[seg];
+    const DatasetH &D = c->ds[S.dataset];
+    const int N = S.N, L = S.L;
+    const int64_t G = S.G;
+    auto all_pos = [](const double *p, size_t n) {
+        for (size_t i = 0; i < n; ++i) if (!(p[i] > 0) || !std::isfinite(p[i])) return false;
+        return true;
+    };
+    if (s->eps && !finite_all(s->eps, (size_t)G * N)) return fail(c, FB_EINVAL, "eps must be finite");
+    if (s->beta && !finite_all(s->beta, (size_t)G * L)) return fail(c, FB_EINVAL, "beta must be finite");
+    if (s->gam && !all_pos(s->gam, G)) return fail(c, FB_EINVAL, "gamma must be > 0");
+    if (s->w_eps && !all_pos(s->w_eps, (size_t)G * N)) return fail(c, FB_EINVAL, "widths must be > 0");
+    if (s->w_gam && !all_pos(s->w_gam, G)) return fail(c, FB_EINVAL, "widths must be > 0");
+    if (s->w_beta && !all_pos(s->w_beta, (size_t)G * L)) return fail(c, FB_EINVAL, "widths must be > 0");
+    if (s->w_hyp && !all_pos(s->w_hyp, 2 + L)) return fail(c, FB_EINVAL, "widths must be > 0");
+    if (s->waux_eps && !finite_all(s->waux_eps, (size_t)G * N)) return fail(c, FB_EINVAL, "waux must be finite");
+    if (s->waux_gam && !finite_all(s->waux_gam, G)) return fail(c, FB_EINVAL, "waux must be finite");
+    if (s->waux_beta && !finite_all(s->waux_beta, (size_t)G * L)) return fail(c, FB_EINVAL, "waux must be finite");
+    if (s->waux_hyp && !finite_all(s->waux_hyp, 2 + L)) return fail(c, FB_EINVAL, "waux must be finite");
+    if (s->hyp) {
+        if (!finite_all(s->hyp, 2 + 2 * L)) return fail(c, FB_EINVAL, "hyperparameters must be finite");
+        if (!(s->hyp[0] > 0 && s->hyp[0] < D.d)) return fail(c, FB_EINVAL, "need 0 < nu < d");
+        if (!(s->hyp[1] > 0)) return fail(c, FB_EINVAL, "need tau > 0");
+        for (int l = 0; l < L; ++l)
+            if (!(s->hyp[2 + L + l] > 0 && s->hyp[2 + L + l] < D.s[l] * D.s[l]))
+                return fail(c, FB_EINVAL, "need 0 < sigma^2_l < s_l^2");
+    }
+    HIPCHK(c, hipStreamSynchronize(c->st));
+    const SegInfo &I = S.info;
+    int rc;
+    struct { const double *src; void *dst; int K; double pad; } blocks[] = {
+        {s->eps, I.eps, N, 0.0}, {s->w_eps, I.w_eps, N, 1.0}, {s->waux_eps, I.wa_eps, N, 0.0},
+        {s->gam, I.gam, 1, 1.0}, {s->w_gam, I.w_gam, 1, 1.0}, {s->waux_gam, I.wa_gam, 1, 0.0},
+        {s->beta, I.beta, L, 0.0}, {s->w_beta, I.w_beta, L, 1.0}, {s->waux_beta, I.wa_beta, L, 0.0}};
+    for (auto &b : blocks)
+        if (b.src && (rc = upload_array(c, b.dst, b.src, G, b.K, S.Gp, b.pad))) return rc;
+    HyperState H;
+    HIPCHK(c, hipMemcpy(&H, S.d_hyp, sizeof(H), hipMemcpyDeviceToHost));
+    if (s->hyp) {
+        H.nu = s->hyp[0];
+        H.tau = s->hyp[1];
+        for (int l = 0; l < L; ++l) { H.theta[l] = s->hyp[2 + l]; H.sig2[l] = s->hyp[2 + L + l]; }
+    }
+    if (s->w_hyp) {
+        H.w_nu = s->w_hyp[0]; H.w_tau = s->w_hyp[1];
+        for (int l = 0; l < L; ++l) H.w_sig2[l] = s->w_hyp[2 + l];
+    }
+    if (s->waux_hyp) {
+        H.wa_nu = s->waux_hyp[0]; H.wa_tau = s->waux_hyp[1];
+        for (int l = 0; l < L; ++l) H.wa_sig2[l] = s->waux_hyp[2 + l];
+    }
+    HIPCHK(c, hipMemcpy(S.d_hyp, &H, sizeof(H), hipMemcpyHostToDevice));
+    c->m = s->m;
+    return FB_OK;
+}
+
+int fb_summaries(fb_ctx *c, int32_t seg, fb_summary *s)
+{
+    if (!valid_seg(c, seg) || !s) return fail(c, FB_EINVAL, "bad segment or NULL summary");
+    int rc = fb_sync(c);
+    if (rc && rc != FB_ENUMERIC) return rc;
+    SegmentH &S = c->seg[seg];
+    const int N = S.N, L = S.L;
+    const int64_t G = S.G, Gp = S.Gp;
+    auto get = [&](const double2 *src, int K, double *mean, double *msq) -> int {
+        if (!mean && !msq) return FB_OK;
+        std::vector<double2> buf((size_t)K * Gp);
+        HIPCHK(c, hipMemcpy(buf.data(), src, buf.size() * sizeof(double2), hipMemcpyDeviceToHost));
+        for (int k = 0; k < K; ++k)
+            for (int64_t g = 0; g < G; ++g) {
+                if (mean) mean[g * K + k] = buf[(size_t)k * Gp + g].x;
+                if (msq) msq[g * K + k] = buf[(size_t)k * Gp + g].y;
+            }
+        return FB_OK;
+    };
+    if ((rc = get(S.info.mom_eps, N, s->mean_eps, s->msq_eps))) return rc;
+    if ((rc = get(S.info.mom_gam, 1, s->mean_gam, s->msq_gam))) return rc;
+    if ((rc = get(S.info.mom_beta, L, s->mean_beta, s->msq_beta))) return rc;
+    HyperState H;
+    HIPCHK(c, hipMemcpy(&H, S.d_hyp, sizeof(H), hipMemcpyDeviceToHost));
+    for (int j = 0; j < 2 + 2 * L; ++j) {
+        if (s->mean_hyp) s->mean_hyp[j] = H.mom[j].x;
+        if (s->msq_hyp) s->msq_hyp[j] = H.mom[j].y;
+    }
+    s->count = c->m > c->opt.burnin ? c->m - c->opt.burnin : 0;
+    return c->sticky;
+}
+
+int fb_trace_genes(const fb_ctx *c, int32_t seg, int64_t *genes, int32_t *T)
+{
+    if (!valid_seg(c, seg)) return fail(const_cast<fb_ctx *>(c), FB_EINVAL, "bad segment");
+    const SegmentH &S = c->seg[seg];
+    if (T) *T = (int32_t)S.trace_genes.size();
+    if (genes) std::copy(S.trace_genes.begin(), S.trace_genes.end(), genes);
+    return FB_OK;
+}
+
+int fb_trace(fb_ctx *c, int32_t seg, float *buf, int64_t cap, int64_t *n_out, int64_t *dropped)
+{
+    if (!valid_seg(c, seg) || cap < 0) return fail(c, FB_EINVAL, "bad segment or capacity");
+    int rc = fb_sync(c);
+    if (rc && rc != FB_ENUMERIC) return rc;
+    SegmentH &S = c->seg[seg];
+    const int64_t n = std::min<int64_t>(c->trace_n, cap);
+    if (n > 0 && buf) {
+        if (!S.info.trace) return fail(c, FB_ESTATE, "tracing is off");
+        HIPCHK(c, hipMemcpy(buf, S.info.trace, (size_t)n * S.info.trace_stride * sizeof(float),
+                            hipMemcpyDeviceToHost));
+    }
+    if (n_out) *n_out = buf ? n : c->trace_n;
+    if (dropped) *dropped = c->trace_dropped;
+    return c->sticky;
+}
+
+int fb_trace_reset(fb_ctx *c)
+{
+    if (!c) return fail(nullptr, FB_EINVAL, "NULL context");
+    HIPCHK(c, hipStreamSynchronize(c->st));
+    c->trace_n = 0;
+    c->trace_dropped = 0;
+    return FB_OK;
+}
+
+int fb_debug_counts(fb_ctx *c, int32_t seg, int32_t *eps, int32_t *gam, int32_t *beta, int32_t *hyp)
+{
+    if (!valid_seg(c, seg)) return fail(c, FB_EINVAL, "bad segment");
+    if (!c->opt.debug_counts) return fail(c, FB_ESTATE, "debug_counts is off");
+    int rc = fb_sync(c);
+    if (rc && rc != FB_ENUMERIC) return rc;
+    SegmentH &S = c->seg[seg];
+    const int N = S.N, L = S.L;
+    const int64_t G = S.G, Gp = S.Gp;
+    auto get = [&](const int4 *src, int K, int32_t *dst) -> int {
+        if (!dst) return FB_OK;
+        std::vector<int4> buf((size_t)K * Gp);
+        HIPCHK(c, hipMemcpy(buf.data(), src, buf.size() * sizeof(int4), hipMemcpyDeviceToHost));
+        for (int k = 0; k < K; ++k)
+            for (int64_t g = 0; g < G; ++g) {
+                const int4 v = buf[(size_t)k * Gp + g];
+                int32_t *o = dst + 4 * (g * K + k);
+                o[0] = v.x; o[1] = v.y; o[2] = v.z; o[3] = v.w;
+            }
+        return FB_OK;
+    };
+    if ((rc = get(S.info.dbg_eps, N, eps))) return rc;
+    if ((rc = get(S.info.dbg_gam, 1, gam))) return rc;
+    if ((rc = get(S.info.dbg_beta, L, beta))) return rc;
+    if (hyp) {
+        HyperState H;
+        HIPCHK(c, hipMemcpy(&H, S.d_hyp, sizeof(H), hipMemcpyDeviceToHost));
+        for (int j = 0; j < 2 + L; ++j) {
+            hyp[4 * j] = H.dbg[j].x; hyp[4 * j + 1] = H.dbg[j].y;
+            hyp[4 * j + 2] = H.dbg[j].z; hyp[4 * j + 3] = H.dbg[j].w;
+        }
+    }
+    return c->sticky;
+}
+
+int fb_reductions(fb_ctx *c, int32_t seg, double *out)
+{
+    if (!valid_seg(c, seg) || !out) return fail(c, FB_EINVAL, "bad segment or NULL output");
+    int rc = fb_sync(c);
+    if (rc && rc != FB_ENUMERIC) return rc;
+    HyperState H;
+    HIPCHK(c, hipMemcpy(&H, c->seg[seg].d_hyp, sizeof(H), hipMemcpyDeviceToHost));
+    std::copy(H.red, H.red + 2 + 2 * c->seg[seg].L, out);
+    return c->sticky;
+}
+
+int fb_philox(const uint32_t *ctr, const uint32_t *key, uint32_t *out, int64_t n)
+{
+    if (n < 0 || (n > 0 && (!ctr || !key || !out))) return fail(nullptr, FB_EINVAL, "bad arguments");
+    if (n == 0) return FB_OK;
+    void *dc = nullptr, *dk = nullptr, *dout = nullptr;
+    auto cleanup = [&]() { (void)hipFree(dc); (void)hipFree(dk); (void)hipFree(dout); };
+    if (hipMalloc(&dc, n * 16) != hipSuccess || hipMalloc(&dk, n * 8) != hipSuccess ||
+        hipMalloc(&dout, n * 16) != hipSuccess) {
+        cleanup();
+        return fail(nullptr, FB_ENOMEM, "hipMalloc failed");
+    }
+    hipError_t e = hipMemcpy(dc, ctr, n * 16, hipMemcpyHostToDevice);
+    if (e == hipSuccess) e = hipMemcpy(dk, key, n * 8, hipMemcpyHostToDevice);
+    if (e == hipSuccess) e = launch_philox((const uint4 *)dc, (const uint2 *)dk, (uint4 *)dout, n, nullptr);
+    if (e == hipSuccess) e = hipMemcpy(out, dout, n * 16, hipMemcpyDeviceToHost);
+    cleanup();
+    if (e != hipSuccess) return fail(nullptr, FB_EDEVICE, std::string("fb_philox: ") + hipGetErrorString(e));
+    return FB_OK;
+}
+
+int fb_last_sweep_time(fb_ctx *c, double *ms, int64_t *sweeps)
+{
+    if (!c) return fail(nullptr, FB_EINVAL, "NULL context");
+    HIPCHK(c, hipEventSynchronize(c->ev1));
+    float t = 0;
+    HIPCHK(c, hipEventElapsedTime(&t, c->ev0, c->ev1));
+    if (ms) *ms = t;
+    if (sweeps) *sweeps = c->last_n;
+    return FB_OK;
+}
+
+int fb_profile(fb_ctx *c, int32_t every, int32_t max_samples)
+{
+    if (!c) return fail(nullptr, FB_EINVAL, "NULL context");
+    if (every < 0 || max_samples < 0) return fail(c, FB_EINVAL, "every and max_samples must be >= 0");
+    HIPCHK(c, hipStreamSynchronize(c->st));
+    const size_t need = 4 * (size_t)max_samples;
+    while (c->prof_ev.size() < need) {
+        hipEvent_t e;
+        HIPCHK(c, hipEventCreate(&e));
+        c->prof_ev.push_back(e);
+    }
+    c->prof_every = every;
+    c->prof_cap = max_samples;
+    c->prof_n = 0;
+    c->prof_count = 0;
+    return FB_OK;
+}
+
+int fb_kernel_times(fb_ctx *c, double *gene_ms, double *hyper_ms, int64_t *samples)
+{
+    if (!c) return fail(nullptr, FB_EINVAL, "NULL context");
+    HIPCHK(c, hipStreamSynchronize(c->st));
+    double tg = 0, th = 0;
+    for (int32_t i = 0; i < c->prof_n; ++i) {
+        float a = 0, b = 0;
+        HIPCHK(c, hipEventElapsedTime(&a, c->prof_ev[4 * i], c->prof_ev[4 * i + 1]));
+        HIPCHK(c, hipEventElapsedTime(&b, c->prof_ev[4 * i + 2], c->prof_ev[4 * i + 3]));
+        tg += a;
+        th += b;
+    }
+    if (gene_ms) *gene_ms = c->prof_n ? tg / c->prof_n : 0.0;
+    if (hyper_ms) *hyper_ms = c->prof_n ? th / c->prof_n : 0.0;
+    if (samples) *samples = c->prof_n;
+    c->prof_n = 0;
+    c->prof_count = 0;
+    return FB_OK;
+}
+
+const char *fb_last_error(const fb_ctx *c) { return c ? c->err.c_str() : g_thread_err.c_str(); }
+
+const char *fb_strerror(int code)
+{
+    switch (code) {
+    case FB_OK: return "ok";
+    case FB_EINVAL: return "invalid argument";
+    case FB_ENOMEM: return "out of memory";
+    case FB_EDEVICE: return "HIP runtime error";
+    case FB_ENUMERIC: return "numeric failure in a draw";
+    case FB_ESTATE: return "call not valid in this state";
+    default: return "unknown error";
+    }
+}
+
+}  // extern "C"

@@ -1,0 +1,81 @@
+// fbmc_types.hpp -- device-visible tables of libfbmc, shared by host and kernels.
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+namespace fbmc {
+
+constexpr int kMaxN = 64;      // samples per dataset
+constexpr int kMaxL = 8;       // model-matrix columns
+constexpr int kMaxRows = 8;    // distinct rows of X
+constexpr int kMaxVals = 4;    // distinct non-zero values per column
+constexpr int kTile = 64;      // genes per wavefront tile
+constexpr int kMaxParts = 2 + 2 * kMaxL;
+
+// Per-segment (dataset x chain) description.  Lives in device memory and is
+// read with wavefront-uniform loads.  Arrays of state are gene-contiguous
+// (structure of arrays): element (k, g) of a [K][Gp] array sits at k*Gp + g.
+struct SegInfo {
+    int64_t G;          // genes
+    int64_t Gp;         // padded to a multiple of kTile
+    int64_t ntiles;     // Gp / kTile
+    int32_t N, L, R;    // samples, columns, distinct rows of X
+    int32_t chain;
+    uint32_t key0, key1;          // Philox key = the dataset seed
+    int32_t dataset;
+    int32_t trace_T;              // traced genes
+    int32_t trace_stride;         // floats per trace point
+    int32_t pad0;
+    // design, in the kernel's working precision-independent form
+    double X[kMaxN * kMaxL];      // [N][L]
+    double h[kMaxN];
+    double eh[kMaxN];             // exp(h_n)
+    int32_t row_of[kMaxN];        // distinct-row index of sample n
+    double Xrow[kMaxRows * kMaxL];// [R][L] distinct rows
+    int32_t xidx[kMaxRows * kMaxL];// [R][L]: index of X_rl among the column's non-zero values, -1 if 0
+    int32_t nv[kMaxL];            // distinct non-zero values of column l
+    double vals[kMaxL * kMaxVals];// [L][kMaxVals]
+    // prior constants (Section 4.1)
+    double a, b, d;
+    double c[kMaxL], s[kMaxL];
+    // device pointers
+    const int32_t *y;             // [N][Gp]
+    void *eps, *w_eps, *wa_eps;   // [N][Gp] (float or double)
+    void *gam, *w_gam, *wa_gam;   // [Gp]
+    void *beta, *w_beta, *wa_beta;// [L][Gp]
+    double2 *mom_eps;             // [N][Gp]  (mean, mean of squares)
+    double2 *mom_gam;             // [Gp]
+    double2 *mom_beta;            // [L][Gp]
+    double *partials;             // [ntiles][kMaxParts]
+    int32_t *trace_slot;          // [Gp] slot of traced genes, -1 otherwise
+    float *trace;                 // [capacity][trace_stride]
+    int4 *dbg_eps, *dbg_gam, *dbg_beta;  // per-draw records [N][Gp], [Gp], [L][Gp]
+    struct HyperState *hyp;
+};
+
+// FP64 hyperparameter state of one segment.
+struct HyperState {
+    double nu, tau;
+    double theta[kMaxL], sig2[kMaxL];
+    double w_nu, wa_nu, w_tau, wa_tau;
+    double w_sig2[kMaxL], wa_sig2[kMaxL];
+    double2 mom[2 + 2 * kMaxL];   // nu, tau, theta[L], sig2[L]
+    double red[kMaxParts];        // reductions used by the last hyper step
+    int4 dbg[2 + kMaxL];          // records of nu, tau, sig2[L]
+};
+
+// Arguments of one sweep that change from sweep to sweep.
+struct SweepArgs {
+    int64_t m;            // sweep index (1-based)
+    int64_t burnin;       // M_B
+    int64_t tune_start;   // M_C
+    int32_t K;            // step-out budget
+    int32_t cap;          // shrink cap
+    uint32_t mask;        // update mask
+    int32_t trace_point;  // trace row to write this sweep, or -1
+    int32_t dbg;          // write per-draw records
+    int32_t pad;
+};
+
+}  // namespace fbmc

@@ -100,3 +100,31 @@ def ess_many(draws) -> np.ndarray:
 def mcse(sd, ess_value):
     """Monte Carlo standard error of a posterior mean."""
     return np.asarray(sd) / np.sqrt(np.asarray(ess_value))
+
+
+def ess_batch(x, chunk: int = 256) -> np.ndarray:
+    """ESS of many single-chain series at once: x is [P, M] (one row per
+    parameter).  Same estimator as ``ess`` with C = 1, vectorised over rows."""
+    x = np.asarray(x, dtype=np.float64)
+    P, M = x.shape
+    out = np.empty(P)
+    npairs = M // 2
+    for s in range(0, P, chunk):
+        xb = x[s:s + chunk]
+        acov = _autocov(xb)                              # [B, M]
+        var0 = acov[:, :1]
+        with np.errstate(invalid="ignore", divide="ignore"):
+            rho = acov / var0
+        rho[:, 0] = 1.0
+        pairs = rho[:, 0:2 * npairs:2] + rho[:, 1:2 * npairs:2]   # [B, npairs]
+        neg = pairs < 0
+        first_neg = np.where(neg.any(axis=1), neg.argmax(axis=1), npairs)
+        mono = np.minimum.accumulate(np.where(np.isnan(pairs), 0.0, pairs), axis=1)
+        keep = np.arange(npairs)[None, :] < first_neg[:, None]
+        total = np.sum(np.where(keep, mono, 0.0), axis=1)
+        tau = -1.0 + 2.0 * total
+        tau = np.maximum(tau, 1.0 / np.log10(max(M, 10)))
+        e = M / tau
+        e[~np.isfinite(var0[:, 0]) | (var0[:, 0] <= 0)] = np.nan
+        out[s:s + chunk] = e
+    return out

@@ -1,0 +1,385 @@
+"""Python binding of libfbmc (include/libfbmc.h): argument marshalling only.
+
+Every function keeps the C name (``fb_create``, ``fb_sweep``, ...) and takes
+numpy arrays; ``Sampler`` is a small convenience wrapper over one context.
+All sampling runs in the HIP kernels of libfbmc.so; there is no fallback, and
+importing this module fails loudly when the library has not been built.
+"""
+from __future__ import annotations
+
+import ctypes as C
+import os
+
+import numpy as np
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(_HERE, "libfbmc.so")
+
+FB_OK, FB_EINVAL, FB_ENOMEM, FB_EDEVICE, FB_ENUMERIC, FB_ESTATE = 0, -1, -2, -3, -4, -5
+FB_FP64, FB_FP32 = 0, 1
+FB_KIND_EPS, FB_KIND_GAMMA, FB_KIND_NU, FB_KIND_TAU = 1, 2, 3, 4
+FB_KIND_BETA, FB_KIND_THETA, FB_KIND_SIG2, FB_KIND_IMH = 5, 6, 7, 8
+FB_UPDATE_ALL = 0xFE
+FB_MAX_N, FB_MAX_L, FB_MAX_ROWS, FB_MAX_COLVALS = 64, 8, 8, 4
+
+
+class FbError(RuntimeError):
+    def __init__(self, code, msg):
+        super().__init__(f"{msg} (code {code})")
+        self.code = code
+
+
+class fb_priors(C.Structure):
+    _fields_ = [("a", C.c_double), ("b", C.c_double), ("d", C.c_double),
+                ("c", C.POINTER(C.c_double)), ("s", C.POINTER(C.c_double))]
+
+
+class fb_options(C.Structure):
+    _fields_ = [("chains", C.c_int32), ("burnin", C.c_int64), ("tune_start", C.c_int64),
+                ("max_steps", C.c_int32), ("w0", C.c_double), ("shrink_cap", C.c_int32),
+                ("precision", C.c_int32), ("update_mask", C.c_uint32), ("thin", C.c_int32),
+                ("trace_genes", C.c_int32), ("trace_after_burnin", C.c_int32),
+                ("trace_capacity", C.c_int64), ("debug_counts", C.c_int32),
+                ("jitter", C.c_int32), ("stream", C.c_void_p)]
+
+
+class fb_dataset(C.Structure):
+    _fields_ = [("counts", C.POINTER(C.c_int32)), ("G", C.c_int64), ("N", C.c_int32),
+                ("X", C.POINTER(C.c_double)), ("L", C.c_int32), ("h", C.POINTER(C.c_double)),
+                ("priors", C.POINTER(fb_priors)), ("seed", C.c_uint64)]
+
+
+_DP = C.POINTER(C.c_double)
+
+
+class fb_state(C.Structure):
+    _fields_ = [(k, _DP) for k in ("eps", "gam", "beta", "hyp", "w_eps", "waux_eps", "w_gam",
+                                   "waux_gam", "w_beta", "waux_beta", "w_hyp", "waux_hyp")] + \
+               [("m", C.c_int64)]
+
+
+class fb_summary(C.Structure):
+    _fields_ = [(k, _DP) for k in ("mean_eps", "msq_eps", "mean_gam", "msq_gam", "mean_beta",
+                                   "msq_beta", "mean_hyp", "msq_hyp")] + [("count", C.c_int64)]
+
+
+EXPORTS = [
+    "fb_default_options", "fb_create", "fb_create_batch", "fb_destroy", "fb_sweep", "fb_sync",
+    "fb_num_segments", "fb_segment_dims", "fb_get_state", "fb_set_state", "fb_summaries",
+    "fb_trace_genes", "fb_trace", "fb_trace_reset", "fb_debug_counts", "fb_reductions",
+    "fb_philox", "fb_last_sweep_time", "fb_profile", "fb_kernel_times", "fb_last_error",
+    "fb_strerror",
+]
+
+_lib = None
+
+
+def load() -> C.CDLL:
+    """Load libfbmc.so (built in-tree); raises if it is missing."""
+    global _lib
+    if _lib is not None:
+        return _lib
+    if not os.path.exists(LIB_PATH):
+        raise RuntimeError(f"{LIB_PATH} is not built: run paper_1606_06659_amd.build.build() "
+                           "(hipcc, gfx950) first")
+    L = C.CDLL(LIB_PATH)
+    vp, i32, i64, u32 = C.c_void_p, C.c_int32, C.c_int64, C.c_uint32
+    L.fb_default_options.argtypes = [C.POINTER(fb_options)]
+    L.fb_default_options.restype = None
+    L.fb_create.argtypes = [C.POINTER(vp), C.POINTER(C.c_int32), i64, i32, _DP, i32, _DP,
+                            C.POINTER(fb_priors), C.c_uint64, C.POINTER(fb_options)]
+    L.fb_create_batch.argtypes = [C.POINTER(vp), C.POINTER(fb_dataset), i32, C.POINTER(fb_options)]
+    L.fb_destroy.argtypes = [vp]
+    L.fb_destroy.restype = None
+    L.fb_sweep.argtypes = [vp, i64]
+    L.fb_sync.argtypes = [vp]
+    L.fb_num_segments.argtypes = [vp]
+    L.fb_segment_dims.argtypes = [vp, i32, C.POINTER(i64), C.POINTER(i32), C.POINTER(i32),
+                                  C.POINTER(i32), C.POINTER(i32)]
+    L.fb_get_state.argtypes = [vp, i32, C.POINTER(fb_state)]
+    L.fb_set_state.argtypes = [vp, i32, C.POINTER(fb_state)]
+    L.fb_summaries.argtypes = [vp, i32, C.POINTER(fb_summary)]
+    L.fb_trace_genes.argtypes = [vp, i32, C.POINTER(i64), C.POINTER(i32)]
+    L.fb_trace.argtypes = [vp, i32, C.POINTER(C.c_float), i64, C.POINTER(i64), C.POINTER(i64)]
+    L.fb_trace_reset.argtypes = [vp]
+    ip = C.POINTER(C.c_int32)
+    L.fb_debug_counts.argtypes = [vp, i32, ip, ip, ip, ip]
+    L.fb_reductions.argtypes = [vp, i32, _DP]
+    up = C.POINTER(u32)
+    L.fb_philox.argtypes = [up, up, up, i64]
+    L.fb_last_sweep_time.argtypes = [vp, _DP, C.POINTER(i64)]
+    L.fb_profile.argtypes = [vp, i32, i32]
+    L.fb_kernel_times.argtypes = [vp, _DP, _DP, C.POINTER(i64)]
+    L.fb_last_error.argtypes = [vp]
+    L.fb_last_error.restype = C.c_char_p
+    L.fb_strerror.argtypes = [i32]
+    L.fb_strerror.restype = C.c_char_p
+    _lib = L
+    return L
+
+
+def _p(a, t=C.c_double):
+    return None if a is None else a.ctypes.data_as(C.POINTER(t))
+
+
+def _check(rc, ctx=None, allow=()):
+    """Raise FbError for a failing status; codes in `allow` pass (the data of a
+    read is valid even when a sweep raised the sticky numeric flag)."""
+    if rc != FB_OK and rc not in allow:
+        msg = load().fb_last_error(ctx)
+        raise FbError(rc, (msg or b"").decode() or load().fb_strerror(rc).decode())
+    return rc
+
+
+def fb_default_options(**kw) -> fb_options:
+    o = fb_options()
+    load().fb_default_options(C.byref(o))
+    for k, v in kw.items():
+        if not hasattr(o, k):
+            raise TypeError(f"unknown option {k}")
+        setattr(o, k, v)
+    return o
+
+
+def _priors_struct(priors, L, keep):
+    if priors is None:
+        return None
+    c = np.ascontiguousarray(np.broadcast_to(priors.get("c", 10.0), (L,)), dtype=np.float64)
+    s = np.ascontiguousarray(np.broadcast_to(priors.get("s", 100.0), (L,)), dtype=np.float64)
+    keep += [c, s]
+    p = fb_priors(priors.get("a", 1.0), priors.get("b", 1.0), priors.get("d", 1000.0), _p(c), _p(s))
+    keep.append(p)
+    return C.pointer(p)
+
+
+def fb_create(counts, X, h, priors=None, seed=0, options=None) -> C.c_void_p:
+    counts = np.ascontiguousarray(counts, dtype=np.int32)
+    X = np.ascontiguousarray(X, dtype=np.float64)
+    h = np.ascontiguousarray(h, dtype=np.float64)
+    G, N = counts.shape
+    L = X.shape[1]
+    keep = []
+    pp = _priors_struct(priors, L, keep)
+    opt = options if options is not None else fb_default_options()
+    ctx = C.c_void_p()
+    rc = load().fb_create(C.byref(ctx), _p(counts, C.c_int32), G, N, _p(X), L, _p(h), pp,
+                          C.c_uint64(seed), C.byref(opt))
+    _check(rc, None)
+    return ctx
+
+
+def fb_create_batch(datasets, options=None) -> C.c_void_p:
+    """datasets: list of dicts with counts, X, h, optional priors, seed."""
+    keep = []
+    arr = (fb_dataset * len(datasets))()
+    for i, d in enumerate(datasets):
+        y = np.ascontiguousarray(d["counts"], dtype=np.int32)
+        X = np.ascontiguousarray(d["X"], dtype=np.float64)
+        h = np.ascontiguousarray(d["h"], dtype=np.float64)
+        keep += [y, X, h]
+        pp = _priors_struct(d.get("priors"), X.shape[1], keep)
+        arr[i] = fb_dataset(_p(y, C.c_int32), y.shape[0], y.shape[1], _p(X), X.shape[1], _p(h),
+                            pp, C.c_uint64(d.get("seed", 0)))
+    opt = options if options is not None else fb_default_options()
+    ctx = C.c_void_p()
+    _check(load().fb_create_batch(C.byref(ctx), arr, len(datasets), C.byref(opt)), None)
+    return ctx
+
+
+def fb_destroy(ctx):
+    load().fb_destroy(ctx)
+
+
+def fb_sweep(ctx, n: int):
+    return _check(load().fb_sweep(ctx, int(n)), ctx)
+
+
+def fb_sync(ctx):
+    return _check(load().fb_sync(ctx), ctx)
+
+
+def fb_num_segments(ctx) -> int:
+    return int(load().fb_num_segments(ctx))
+
+
+def fb_segment_dims(ctx, seg: int):
+    G, N, L, d, c = C.c_int64(), C.c_int32(), C.c_int32(), C.c_int32(), C.c_int32()
+    _check(load().fb_segment_dims(ctx, seg, C.byref(G), C.byref(N), C.byref(L), C.byref(d),
+                                  C.byref(c)), ctx)
+    return dict(G=G.value, N=N.value, L=L.value, dataset=d.value, chain=c.value)
+
+
+STATE_KEYS = ("eps", "gam", "beta", "hyp", "w_eps", "waux_eps", "w_gam", "waux_gam", "w_beta",
+              "waux_beta", "w_hyp", "waux_hyp")
+
+
+def _state_shapes(G, N, L):
+    return dict(eps=(G, N), gam=(G,), beta=(G, L), hyp=(2 + 2 * L,), w_eps=(G, N),
+                waux_eps=(G, N), w_gam=(G,), waux_gam=(G,), w_beta=(G, L), waux_beta=(G, L),
+                w_hyp=(2 + L,), waux_hyp=(2 + L,))
+
+
+def fb_get_state(ctx, seg: int = 0) -> dict:
+    d = fb_segment_dims(ctx, seg)
+    shapes = _state_shapes(d["G"], d["N"], d["L"])
+    out = {k: np.empty(shapes[k]) for k in STATE_KEYS}
+    st = fb_state(*[_p(out[k]) for k in STATE_KEYS], 0)
+    _check(load().fb_get_state(ctx, seg, C.byref(st)), ctx, (FB_ENUMERIC,))
+    out["m"] = int(st.m)
+    return out
+
+
+def fb_set_state(ctx, state: dict, seg: int = 0):
+    arrs = {k: (None if state.get(k) is None else np.ascontiguousarray(state[k], dtype=np.float64))
+            for k in STATE_KEYS}
+    st = fb_state(*[_p(arrs[k]) for k in STATE_KEYS], int(state["m"]))
+    _check(load().fb_set_state(ctx, seg, C.byref(st)), ctx)
+
+
+def fb_summaries(ctx, seg: int = 0) -> dict:
+    d = fb_segment_dims(ctx, seg)
+    G, N, L = d["G"], d["N"], d["L"]
+    out = dict(mean_eps=np.empty((G, N)), msq_eps=np.empty((G, N)), mean_gam=np.empty(G),
+               msq_gam=np.empty(G), mean_beta=np.empty((G, L)), msq_beta=np.empty((G, L)),
+               mean_hyp=np.empty(2 + 2 * L), msq_hyp=np.empty(2 + 2 * L))
+    keys = ("mean_eps", "msq_eps", "mean_gam", "msq_gam", "mean_beta", "msq_beta", "mean_hyp",
+            "msq_hyp")
+    s = fb_summary(*[_p(out[k]) for k in keys], 0)
+    _check(load().fb_summaries(ctx, seg, C.byref(s)), ctx, (FB_ENUMERIC,))
+    out["count"] = int(s.count)
+    return out
+
+
+def fb_trace_genes(ctx, seg: int = 0) -> np.ndarray:
+    T = C.c_int32()
+    _check(load().fb_trace_genes(ctx, seg, None, C.byref(T)), ctx)
+    genes = np.empty(T.value, dtype=np.int64)
+    _check(load().fb_trace_genes(ctx, seg, _p(genes, C.c_int64), C.byref(T)), ctx)
+    return genes
+
+
+def fb_trace(ctx, seg: int = 0):
+    """Recorded trace points of one segment as float32 [points, 2 + 2L + T (L + 1)]."""
+    d = fb_segment_dims(ctx, seg)
+    T = len(fb_trace_genes(ctx, seg))
+    L = d["L"]
+    n, dropped = C.c_int64(), C.c_int64()
+    _check(load().fb_trace(ctx, seg, None, 0, C.byref(n), C.byref(dropped)), ctx, (FB_ENUMERIC,))
+    buf = np.empty((n.value, 2 + 2 * L + T * (L + 1)), dtype=np.float32)
+    _check(load().fb_trace(ctx, seg, _p(buf, C.c_float), n.value, C.byref(n), C.byref(dropped)), ctx,
+           (FB_ENUMERIC,))
+    return buf[: n.value], int(dropped.value)
+
+
+def fb_trace_reset(ctx):
+    _check(load().fb_trace_reset(ctx), ctx)
+
+
+def fb_debug_counts(ctx, seg: int = 0) -> dict:
+    d = fb_segment_dims(ctx, seg)
+    G, N, L = d["G"], d["N"], d["L"]
+    out = dict(eps=np.empty((G, N, 4), np.int32), gam=np.empty((G, 4), np.int32),
+               beta=np.empty((G, L, 4), np.int32), hyp=np.empty((2 + L, 4), np.int32))
+    _check(load().fb_debug_counts(ctx, seg, *[_p(out[k], C.c_int32) for k in ("eps", "gam", "beta", "hyp")]),
+           ctx, (FB_ENUMERIC,))
+    return out
+
+
+def fb_reductions(ctx, seg: int = 0) -> np.ndarray:
+    L = fb_segment_dims(ctx, seg)["L"]
+    out = np.empty(2 + 2 * L)
+    _check(load().fb_reductions(ctx, seg, _p(out)), ctx, (FB_ENUMERIC,))
+    return out
+
+
+def fb_philox(ctr, key) -> np.ndarray:
+    ctr = np.ascontiguousarray(ctr, dtype=np.uint32).reshape(-1, 4)
+    key = np.ascontiguousarray(key, dtype=np.uint32).reshape(-1, 2)
+    out = np.empty_like(ctr)
+    _check(load().fb_philox(_p(ctr, C.c_uint32), _p(key, C.c_uint32), _p(out, C.c_uint32), ctr.shape[0]))
+    return out
+
+
+def fb_last_sweep_time(ctx):
+    ms, n = C.c_double(), C.c_int64()
+    _check(load().fb_last_sweep_time(ctx, C.byref(ms), C.byref(n)), ctx)
+    return ms.value, n.value
+
+
+def fb_profile(ctx, every: int, max_samples: int):
+    _check(load().fb_profile(ctx, int(every), int(max_samples)), ctx)
+
+
+def fb_kernel_times(ctx):
+    """(mean gene-kernel ms, mean hyper-kernel ms, samples) of the sampled sweeps."""
+    g, h, n = C.c_double(), C.c_double(), C.c_int64()
+    _check(load().fb_kernel_times(ctx, C.byref(g), C.byref(h), C.byref(n)), ctx)
+    return g.value, h.value, n.value
+
+
+class Sampler:
+    """One libfbmc context.  Datasets are (counts, X, h) arrays; see fb_create."""
+
+    def __init__(self, counts=None, X=None, h=None, *, priors=None, seed=0, datasets=None, **options):
+        self.options = fb_default_options(**options)
+        if datasets is not None:
+            self.ctx = fb_create_batch(datasets, self.options)
+        else:
+            self.ctx = fb_create(counts, X, h, priors=priors, seed=seed, options=self.options)
+
+    def close(self):
+        if getattr(self, "ctx", None):
+            fb_destroy(self.ctx)
+            self.ctx = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    def __enter__(self):
+        return self
+
+    def __exit__(self, *a):
+        self.close()
+
+    @property
+    def num_segments(self):
+        return fb_num_segments(self.ctx)
+
+    def dims(self, seg=0):
+        return fb_segment_dims(self.ctx, seg)
+
+    def sweep(self, n=1):
+        return fb_sweep(self.ctx, n)
+
+    def sync(self):
+        return fb_sync(self.ctx)
+
+    def get_state(self, seg=0):
+        return fb_get_state(self.ctx, seg)
+
+    def set_state(self, state, seg=0):
+        return fb_set_state(self.ctx, state, seg)
+
+    def summaries(self, seg=0):
+        return fb_summaries(self.ctx, seg)
+
+    def trace(self, seg=0):
+        return fb_trace(self.ctx, seg)
+
+    def trace_genes(self, seg=0):
+        return fb_trace_genes(self.ctx, seg)
+
+    def trace_reset(self):
+        return fb_trace_reset(self.ctx)
+
+    def debug_counts(self, seg=0):
+        return fb_debug_counts(self.ctx, seg)
+
+    def reductions(self, seg=0):
+        return fb_reductions(self.ctx, seg)
+
+    def last_sweep_time(self):
+        return fb_last_sweep_time(self.ctx)

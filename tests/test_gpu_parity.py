@@ -1,0 +1,237 @@
+"""Parity of the HIP sampler with the FP64 CPU oracle (GPU only).
+
+* Philox words: bit-exact.
+* FP64 mode: 100 free-running sweeps from a shared state, every draw within a
+  relative 1e-5 (absolute floor 1e-10) and every per-draw integer record
+  (K_L, step-outs, shrink candidates) identical; tuning and moments included.
+* FP32 mode (log densities in float): the GPU is re-synchronised to the
+  oracle's state before each sweep; draws agree within 1e-5 relative (plus
+  1e-5 of the draw's slice width) except in genes where a slice decision
+  flipped, which must be rare and must sit on a near-tie of the oracle.
+"""
+import numpy as np
+import pytest
+
+from paper_1606_06659_amd import datagen
+from tests.gpu_common import STATE_KEYS, require_gpu, say
+
+pytestmark = pytest.mark.gpu
+
+
+def test_philox_words_bit_exact(oracle_lib):
+    F = require_gpu()
+    rng = np.random.default_rng(7)
+    n = 4096
+    ctr = rng.integers(0, 2 ** 32, size=(n, 4), dtype=np.uint64).astype(np.uint32)
+    key = rng.integers(0, 2 ** 32, size=(n, 2), dtype=np.uint64).astype(np.uint32)
+    ctr[:4] = [[0, 0, 0, 0], [5, (1 << 24) | 3, 7, 1], [49999, (5 << 24) | 4, 20000, 0],
+               [0xFFFFFFFF] * 4]
+    dev = F.fb_philox(ctr, key)
+    ref = np.array([oracle_lib.philox(c, k) for c, k in zip(ctr, key)])
+    assert np.array_equal(dev, ref)
+
+
+def _make_pair(oracle_lib, ds, *, seed, burnin, tune_start, precision, K=15, cap=200, w0=1.0,
+               chains=1, **ora_kw):
+    F = require_gpu()
+    opts = F.fb_default_options(burnin=burnin, tune_start=tune_start, precision=precision,
+                                debug_counts=1, jitter=0, chains=chains, max_steps=K,
+                                shrink_cap=cap, w0=w0)
+    g = F.fb_create(ds.y, ds.X, ds.h, seed=seed, options=opts, priors=ora_kw.pop("priors", None))
+    o = oracle_lib.Oracle(ds.y, ds.X, ds.h, seed=seed, burnin=burnin, tune_start=tune_start, K=K,
+                          shrink_cap=cap, w0=w0, **ora_kw)
+    return F, g, o
+
+
+def _compare_fp64(F, g, o, label, rtol=1e-5, atol=1e-10):
+    so, sg = o.get_state(), F.fb_get_state(g)
+    for k in ("eps", "gam", "beta", "hyp", "w_eps", "w_gam", "w_beta", "w_hyp", "waux_eps",
+              "waux_gam", "waux_beta", "waux_hyp"):
+        err = np.abs(sg[k] - so[k])
+        tol = rtol * np.abs(so[k]) + atol
+        bad = np.argwhere(~(err <= tol))
+        assert bad.size == 0, (label, k, bad[:5], sg[k].ravel()[:3], so[k].ravel()[:3])
+    co, cg = o.counts(), F.fb_debug_counts(g)
+    for k in ("eps", "gam", "beta", "hyp"):
+        assert np.array_equal(co[k], cg[k]), (label, k, np.argwhere(co[k] != cg[k])[:5])
+    assert sg["m"] == so["m"]
+
+
+def test_fp64_parity_100_sweeps(oracle_lib):
+    ds = datagen.small_two_group(G=1000, seed=0)
+    F, g, o = _make_pair(oracle_lib, ds, seed=11, burnin=40, tune_start=5, precision=F_FP64())
+    F.fb_set_state(g, o.get_state())
+    for it in range(100):
+        assert o.sweep(1) == 0
+        F.fb_sweep(g, 1)
+        _compare_fp64(F, g, o, f"sweep {it + 1}")
+    mo, mg = o.moments(), F.fb_summaries(g)
+    assert mg["count"] == mo["count"] == 60
+    for k in ("mean_eps", "msq_eps", "mean_gam", "msq_gam", "mean_beta", "msq_beta", "mean_hyp",
+              "msq_hyp"):
+        np.testing.assert_allclose(mg[k], mo[k], rtol=1e-9, atol=1e-12, err_msg=k)
+    np.testing.assert_allclose(F.fb_reductions(g), o.reductions(), rtol=1e-9)
+    F.fb_destroy(g)
+
+
+def F_FP64():
+    return 0
+
+
+def _edge_datasets():
+    out = []
+    two = datagen.design_two_groups(2)
+    out.append(("G1", datagen.simulate(1, two, [3.0, 0.0], [1.5, 0.5], seed=1), {}))
+    out.append(("G65_ragged", datagen.simulate(65, two, [3.0, 0.0], [1.5, 0.5], seed=2), {}))
+    out.append(("N3_L1", datagen.simulate(130, np.ones((3, 1)), [2.0], [1.0], seed=3), {}))
+    out.append(("L_eq_N", datagen.simulate(200, np.eye(3), [2.0, 1.0, 0.0], [1.0, 1.0, 1.0], seed=4), {}))
+    out.append(("N1_L1", datagen.simulate(100, np.ones((1, 1)), [1.0], [1.0], seed=5), {}))
+    z = datagen.simulate(70, two, [3.0, 0.0], [1.5, 0.5], seed=6)
+    z.y[:] = 0
+    out.append(("all_zero", z, {}))
+    out.append(("huge_counts", datagen.simulate(100, two, [19.0, 0.0], [0.5, 0.3], seed=7), {}))
+    out.append(("paper_N16", datagen.paper_design_16(G=300, seed=8), {}))
+    out.append(("K0", datagen.simulate(100, two, [3.0, 0.0], [1.5, 0.5], seed=9), dict(K=0)))
+    out.append(("K3_w0small", datagen.simulate(100, two, [3.0, 0.0], [1.5, 0.5], seed=10),
+                dict(K=3, w0=0.05)))
+    out.append(("priors", datagen.simulate(150, two, [3.0, 0.0], [1.5, 0.5], seed=12),
+                dict(priors=dict(a=2.0, b=0.5, d=50.0, c=[3.0, 1.0], s=[5.0, 2.0]))))
+    return out
+
+
+@pytest.mark.parametrize("name,ds,kw", _edge_datasets(), ids=[e[0] for e in _edge_datasets()])
+def test_fp64_parity_edge_cases(oracle_lib, name, ds, kw):
+    say("edge case", name, ds.y.shape)
+    kw = dict(kw)
+    ora_kw = {}
+    if "priors" in kw:
+        p = kw.pop("priors")
+        ora_kw = dict(a=p["a"], b=p["b"], d=p["d"], c=np.array(p["c"]), s=np.array(p["s"]))
+        kw["priors"] = p
+    F, g, o = _make_pair(oracle_lib, ds, seed=3, burnin=10, tune_start=2, precision=0, **kw, **ora_kw)
+    F.fb_set_state(g, o.get_state())
+    for it in range(20):
+        o.sweep(1)
+        F.fb_sweep(g, 1)
+        _compare_fp64(F, g, o, f"{name} sweep {it + 1}")
+    F.fb_destroy(g)
+
+
+def test_shrink_cap_is_reported_and_matches(oracle_lib):
+    ds = datagen.small_two_group(G=200, seed=1)
+    F, g, o = _make_pair(oracle_lib, ds, seed=5, burnin=0, tune_start=0, precision=0, cap=2, w0=30.0)
+    F.fb_set_state(g, o.get_state())
+    rc = o.sweep(1)
+    assert rc == -4 and o.errors() > 0
+    F.fb_sweep(g, 1)
+    with pytest.raises(F.FbError) as e:
+        F.fb_sync(g)
+    assert e.value.code == F.FB_ENUMERIC
+    with pytest.raises(F.FbError):
+        F.fb_sweep(g, 1)               # the flag is sticky
+    _compare_fp64(F, g, o, "shrink cap")   # capped draws keep x0 on both sides
+    F.fb_destroy(g)
+
+
+def _fp32_resync(oracle_lib, ds, *, seed, n_sweeps, warm, threads=1, label=""):
+    F = require_gpu()
+    opts = F.fb_default_options(burnin=warm // 2, tune_start=2, precision=1, debug_counts=1, jitter=0)
+    g = F.fb_create(ds.y, ds.X, ds.h, seed=seed, options=opts)
+    o = oracle_lib.Oracle(ds.y, ds.X, ds.h, seed=seed, burnin=warm // 2, tune_start=2, threads=threads)
+    o.sweep(warm)
+    G, N, L = ds.G, ds.N, ds.L
+    n_genes_flip = 0
+    n_genes = 0
+    worst_margin = 0.0
+    for it in range(n_sweeps):
+        so = o.get_state()
+        F.fb_set_state(g, so)
+        F.fb_sweep(g, 1)
+        o.sweep(1)
+        sn, sg = o.get_state(), F.fb_get_state(g)
+        co, cg = o.counts(), F.fb_debug_counts(g)
+        flip_gene = (np.any(co["eps"] != cg["eps"], axis=(1, 2)) | np.any(co["gam"] != cg["gam"], axis=1)
+                     | np.any(co["beta"] != cg["beta"], axis=(1, 2)))
+        # tolerance: 1e-5 relative plus 1e-5 of the slice width the draw used
+        def mism(k, wk):
+            a, b = sg[k], sn[k]
+            w = so[wk]
+            return ~(np.abs(a - b) <= 1e-5 * np.abs(b) + 1e-5 * w)
+        bad_gene = (np.any(mism("eps", "w_eps"), axis=1) | mism("gam", "w_gam")
+                    | np.any(mism("beta", "w_beta"), axis=1))
+        # every out-of-tolerance gene carries a flipped decision...
+        assert not np.any(bad_gene & ~flip_gene), (label, it, np.argwhere(bad_gene & ~flip_gene)[:5])
+        # ...and every flip sits on a near-tie of the oracle
+        if np.any(flip_gene):
+            m_eps = np.where(np.any(co["eps"] != cg["eps"], axis=2), co["mrg_eps"], np.inf).min(axis=1)
+            m_gam = np.where(np.any(co["gam"] != cg["gam"], axis=1), co["mrg_gam"], np.inf)
+            m_beta = np.where(np.any(co["beta"] != cg["beta"], axis=2), co["mrg_beta"], np.inf).min(axis=1)
+            first = np.minimum(np.minimum(m_eps, m_gam), m_beta)[flip_gene]
+            worst_margin = max(worst_margin, float(first.max()))
+        n_genes_flip += int(flip_gene.sum())
+        n_genes += G
+        # The reductions the GPU's hyperparameter step used equal the sums of
+        # its own new state (FP64 sums of the FP32 values, any order).
+        gam64, beta64 = sg["gam"], sg["beta"]
+        th = sg["hyp"][2:2 + L]
+        want = [np.log(gam64).sum(), (1.0 / gam64).sum()]
+        for l in range(L):
+            want += [beta64[:, l].sum(), ((beta64[:, l] - th[l]) ** 2).sum()]
+        np.testing.assert_allclose(F.fb_reductions(g), want, rtol=1e-9, atol=1e-9)
+        # Hyperparameters are drawn in FP64 on both sides; a flipped gene moves
+        # the sums they depend on, so compare them only in sweeps without flips.
+        if not np.any(flip_gene) and not np.any(co["hyp"] != cg["hyp"]):
+            np.testing.assert_allclose(sg["hyp"], sn["hyp"], rtol=1e-4, atol=1e-7)
+    F.fb_destroy(g)
+    say(label, "flipped genes", n_genes_flip, "of", n_genes, "worst margin", worst_margin)
+    return n_genes_flip / n_genes, worst_margin
+
+
+def test_fp32_parity_resync_paper_design(oracle_lib):
+    ds = datagen.paper_design_16(G=2000, seed=0)
+    frac, worst = _fp32_resync(oracle_lib, ds, seed=21, n_sweeps=100, warm=60, label="fp32 G=2000")
+    assert frac < 2e-3
+    assert worst < 1e-2
+
+
+def test_fp32_parity_resync_two_group(oracle_lib):
+    ds = datagen.small_two_group(G=1000, seed=0)
+    frac, worst = _fp32_resync(oracle_lib, ds, seed=22, n_sweeps=50, warm=40, label="fp32 G=1000 N=4")
+    assert frac < 2e-3
+    assert worst < 1e-2
+
+
+def test_fp32_parity_full_size_paper_design(oracle_lib):
+    """Full G = 50,000, N = 16, L = 5 workload in the benchmark's launch
+    configuration, re-synchronised from the oracle for three sweeps."""
+    ds = datagen.paper_design_16(G=50_000, seed=0)
+    frac, worst = _fp32_resync(oracle_lib, ds, seed=1, n_sweeps=3, warm=8, threads=16,
+                               label="fp32 G=50000")
+    assert frac < 2e-3
+    assert worst < 1e-2
+
+
+def test_determinism_and_resume():
+    F = require_gpu()
+    ds = datagen.paper_design_16(G=3000, seed=2)
+    outs = []
+    for _ in range(2):
+        g = F.fb_create(ds.y, ds.X, ds.h, seed=4,
+                        options=F.fb_default_options(burnin=20, tune_start=2, precision=1))
+        F.fb_sweep(g, 40)
+        outs.append(F.fb_get_state(g))
+        F.fb_destroy(g)
+    for k in STATE_KEYS:
+        assert np.array_equal(outs[0][k], outs[1][k]), k
+    # 20 sweeps, save, 20 more in a fresh context == 40 sweeps
+    g = F.fb_create(ds.y, ds.X, ds.h, seed=4, options=F.fb_default_options(burnin=20, tune_start=2, precision=1))
+    F.fb_sweep(g, 20)
+    mid = F.fb_get_state(g)
+    F.fb_destroy(g)
+    g = F.fb_create(ds.y, ds.X, ds.h, seed=4, options=F.fb_default_options(burnin=20, tune_start=2, precision=1))
+    F.fb_set_state(g, mid)
+    F.fb_sweep(g, 20)
+    end = F.fb_get_state(g)
+    F.fb_destroy(g)
+    for k in STATE_KEYS:
+        assert np.array_equal(end[k], outs[0][k]), k
