@@ -68,6 +68,8 @@ def main():
     ap.add_argument("--genes", type=int, default=50_000)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-ess", action="store_true")
+    ap.add_argument("--copy-mib", type=int, default=0,
+                    help="first run a plain device copy of this many MiB (counter calibration)")
     args = ap.parse_args()
     if args.gpus != 1:
         print(f"bench.py runs on one GPU only (asked for {args.gpus}); the sampler is a "
@@ -82,8 +84,18 @@ def main():
     stream = torch.cuda.current_stream()
     ds = datagen.paper_design_16(G=args.genes, seed=0)
     N, L, G = ds.N, ds.L, ds.G
-    post = max(TOTAL_ITERS - BURNIN, args.warmup + args.steps)
     do_ess = not args.no_ess
+    post = max(TOTAL_ITERS - BURNIN, args.warmup + args.steps) if do_ess else args.warmup + args.steps
+    if args.copy_mib > 0:
+        # a copy of known size: FETCH_SIZE and WRITE_SIZE of this kernel give the
+        # counters' bytes-per-reported-KiB scale on this device
+        n = args.copy_mib * (1 << 20) // 4
+        src = torch.ones(n, dtype=torch.float32, device="cuda")
+        dst = torch.empty_like(src)
+        for _ in range(3):
+            dst.copy_(src)
+        torch.cuda.synchronize()
+        del src, dst
     opts = fbmc.fb_default_options(
         burnin=BURNIN, tune_start=BURNIN // 10, precision=fbmc.FB_FP32, jitter=0,
         thin=1 if do_ess else 0, trace_genes=TRACE_GENES if do_ess else 0,

@@ -219,6 +219,79 @@ int fb_last_sweep_time(fb_ctx *c, double *ms, int64_t *sweeps);
 int fb_profile(fb_ctx *c, int32_t every, int32_t max_samples);
 int fb_kernel_times(fb_ctx *c, double *gene_ms, double *hyper_ms, int64_t *samples);
 
+/* ------------------------------------------------------------------------
+ * Learned beta proposal (independence Metropolis-Hastings for the block beta_g)
+ *
+ * A network maps 32 features of gene g -- for each distinct row r of X,
+ * log((Y_r + 1/2) / A_r) and log(Y_r + 1/2) with Y_r the row's count sum and
+ * A_r = sum over the row's samples of exp(h_n + eps_gn); then theta_l and
+ * log sigma_l^2; zero-padded -- to a Gaussian proposal N(mu, diag(exp(ls))^2)
+ * for beta_g.  The features never involve beta_g, so one step with exact
+ * acceptance probability leaves the beta_g full conditional invariant.
+ * Network: x = (phi - fmean) * fscale; h1 = gelu(x W1 + b1); h2 = gelu(h1 W2 + b2);
+ * o = h2 W3 + b3; mu_l = omean_l + oscale_l o_l; ls_l = log(oscale_l) + o_{L+l}
+ * (gelu in the erf form).  Products run on the matrix cores with BF16
+ * operands and FP32 accumulation; parameters are kept in FP32.
+ * ---------------------------------------------------------------------- */
+enum fb_beta_update { FB_BETA_SLICE = 0, FB_BETA_LEARNED = 1 };
+
+/* Host arrays of the network's parameters (FP32, row-major, input index first). */
+typedef struct {
+    float *fmean, *fscale;   /* [32] input standardisation */
+    float *W1, *b1;          /* [32][128], [128] */
+    float *W2, *b2;          /* [128][128], [128] */
+    float *W3, *b3;          /* [128][32], [32]; outputs >= 2L are unused */
+    float *omean, *oscale;   /* [8]; the first L are used */
+} fb_mlp;
+
+typedef struct {
+    int32_t epochs;           /* passes over pairs_per_epoch sampled pairs */
+    int32_t pairs_per_epoch;  /* pairs drawn (with replacement) per epoch */
+    int32_t minibatch;        /* Adam step size in pairs, a multiple of 32 */
+    double lr;                /* Adam learning rate */
+    uint64_t seed;            /* initial weights and minibatch sampling */
+} fb_train_opts;
+
+/* epochs 200, 10240 pairs per epoch, minibatch 1024, lr 1e-3, seed 1. */
+void fb_default_train_opts(fb_train_opts *o);
+
+/* Run `sweeps` sweeps with slice draws for beta and, on every sweep whose index
+ * is a multiple of `every`, store (features, new beta_g) of every gene of every
+ * segment as training pairs (earlier pairs are discarded). */
+int fb_proposal_collect(fb_ctx *c, int64_t sweeps, int32_t every);
+/* Train the network on the stored pairs with the project's own device kernels:
+ * standardisation from the pairs' means and sds, seeded initial weights, Adam
+ * on the mean Gaussian negative log likelihood of beta given the features.
+ * epoch_loss (may be NULL) receives the mean training loss of each epoch. */
+int fb_proposal_train(fb_ctx *c, const fb_train_opts *o, double *epoch_loss);
+/* Run `sweeps` sweeps in which every gene of every segment takes the IMH
+ * step, then set the fallback mask: genes whose acceptance rate was below
+ * min_accept keep the slice steps from now on.  Adaptive: call it during
+ * burn-in only. */
+int fb_proposal_calibrate(fb_ctx *c, int64_t sweeps, double min_accept);
+/* FB_BETA_SLICE, or FB_BETA_LEARNED (needs a trained or loaded network). */
+int fb_set_beta_update(fb_ctx *c, int32_t mode);
+/* Copy the network's parameters out, or load new ones (both host arrays). */
+int fb_proposal_get(fb_ctx *c, fb_mlp *out);
+int fb_proposal_set(fb_ctx *c, const fb_mlp *in);
+/* Per-gene fallback mask of a segment (1 = slice), read or written. */
+int fb_fallback(fb_ctx *c, int32_t seg, int32_t *get, const int32_t *set);
+/* Last sweep's beta step per gene: 1 IMH accepted, 0 rejected, -1 slice. */
+int fb_imh_last(fb_ctx *c, int32_t seg, int32_t *last);
+/* Features of every gene of segment seg computed on the device from its
+ * current state ([G][32]). */
+int fb_features(fb_ctx *c, int32_t seg, float *phi);
+
+/* Device kernels of the network on host data (tests): one matrix-core product
+ * of A [32][16] and B [16][32] into C [32][32]; the network's outputs for raw
+ * features phi [B][32] (mu, ls: [B][L]); and the mean loss and its gradients
+ * for targets [B][L] (B a multiple of 32; gradients of fmean, fscale, omean,
+ * oscale are zero). */
+int fb_mfma_probe(const float *A, const float *B, float *C);
+int fb_mlp_forward(const fb_mlp *w, int32_t L, const float *phi, int64_t B, float *mu, float *ls);
+int fb_mlp_loss_grad(const fb_mlp *w, int32_t L, const float *phi, const float *target, int64_t B,
+                     float *loss, fb_mlp *grad);
+
 const char *fb_last_error(const fb_ctx *c);
 const char *fb_strerror(int code);
 

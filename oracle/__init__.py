@@ -35,7 +35,7 @@ def build(force: bool = True, mutant: int = 0) -> str:
         os.makedirs(os.path.dirname(so), exist_ok=True)
         cmd = ["gcc", "-O2", "-std=gnu11", "-fPIC", "-shared", "-fopenmp",
                "-fno-fast-math", "-ffp-contract=off", f"-DOR_MUTANT={int(mutant)}",
-               os.path.join(_HERE, "oracle.c"), "-o", so + ".tmp", "-lm"]
+               os.path.join(_HERE, "oracle.c"), os.path.join(_HERE, "mlp.c"), "-o", so + ".tmp", "-lm"]
         subprocess.run(cmd, check=True)
         os.replace(so + ".tmp", so)
     return so
@@ -241,3 +241,95 @@ def variant(mutant: int):
         philox=functools.partial(philox, _lib=L),
         KIND_EPS=KIND_EPS, KIND_GAMMA=KIND_GAMMA, KIND_NU=KIND_NU, KIND_TAU=KIND_TAU,
         KIND_BETA=KIND_BETA, KIND_THETA=KIND_THETA, KIND_SIG2=KIND_SIG2, UPDATE_ALL=UPDATE_ALL)
+
+
+# ---------------------------------------------------------------------------
+# Learned proposal (mlp.c)
+# ---------------------------------------------------------------------------
+MLP_KEYS = ("fmean", "fscale", "W1", "b1", "W2", "b2", "W3", "b3", "omean", "oscale")
+
+
+class _Mlp(C.Structure):
+    _fields_ = [("F", C.c_int32), ("H", C.c_int32), ("O", C.c_int32)] + \
+               [(k, C.POINTER(C.c_double)) for k in MLP_KEYS]
+
+
+def _mlp_struct(m: dict, keep: list) -> _Mlp:
+    arrs = {k: np.ascontiguousarray(m[k], dtype=np.float64) for k in MLP_KEYS}
+    keep.append(arrs)
+    return _Mlp(int(m["F"]), int(m["H"]), int(m["O"]), *[_p(arrs[k]) for k in MLP_KEYS])
+
+
+def _mlp_lib(L):
+    if getattr(L, "_mlp_ready", False):
+        return L
+    dp = C.POINTER(C.c_double)
+    L.or_mlp_forward.argtypes = [C.POINTER(_Mlp), dp, C.c_int64, dp, dp]
+    L.or_mlp_loss_grad.argtypes = [C.POINTER(_Mlp), dp, dp, C.c_int64, dp, dp, dp, dp, dp, dp, dp]
+    L.or_set_proposal.argtypes = [C.c_void_p, C.POINTER(_Mlp), C.POINTER(C.c_int32)]
+    L.or_features.argtypes = [C.c_void_p, C.c_int32, dp]
+    L.or_get_imh.argtypes = [C.c_void_p, C.POINTER(C.c_int32), dp]
+    L.or_num_rows.argtypes = [C.c_void_p]
+    L._mlp_ready = True
+    return L
+
+
+def mlp_forward(m: dict, phi, _lib=None):
+    L = _mlp_lib(_lib or lib())
+    keep = []
+    st = _mlp_struct(m, keep)
+    phi = np.ascontiguousarray(phi, dtype=np.float64).reshape(-1, int(m["F"]))
+    B, Lc = phi.shape[0], int(m["O"]) // 2
+    mu, ls = np.empty((B, Lc)), np.empty((B, Lc))
+    if L.or_mlp_forward(C.byref(st), _p(phi), B, _p(mu), _p(ls)) != 0:
+        raise ValueError("or_mlp_forward failed")
+    return mu, ls
+
+
+def mlp_loss_grad(m: dict, phi, target, grads=True, _lib=None):
+    L = _mlp_lib(_lib or lib())
+    keep = []
+    st = _mlp_struct(m, keep)
+    F, H, O = int(m["F"]), int(m["H"]), int(m["O"])
+    phi = np.ascontiguousarray(phi, dtype=np.float64).reshape(-1, F)
+    tgt = np.ascontiguousarray(target, dtype=np.float64).reshape(-1, O // 2)
+    g = dict(W1=np.empty((F, H)), b1=np.empty(H), W2=np.empty((H, H)), b2=np.empty(H),
+             W3=np.empty((H, O)), b3=np.empty(O)) if grads else {}
+    loss = C.c_double()
+    ptrs = [_p(g[k]) if grads else None for k in ("W1", "b1", "W2", "b2", "W3", "b3")]
+    if L.or_mlp_loss_grad(C.byref(st), _p(phi), _p(tgt), phi.shape[0], C.byref(loss), *ptrs) != 0:
+        raise ValueError("or_mlp_loss_grad failed")
+    return float(loss.value), g
+
+
+def _oracle_set_proposal(self, m: dict, fallback_mask=None):
+    L = _mlp_lib(self._L)
+    if m is None:
+        L.or_set_proposal(self._h, None, None)
+        return
+    keep = []
+    st = _mlp_struct(m, keep)
+    mask = None if fallback_mask is None else np.ascontiguousarray(fallback_mask, dtype=np.int32)
+    if L.or_set_proposal(self._h, C.byref(st), _p(mask, C.c_int32)) != 0:
+        raise ValueError("or_set_proposal failed")
+
+
+def _oracle_imh(self):
+    L = _mlp_lib(self._L)
+    acc = np.empty(self.G, np.int32)
+    la = np.empty(self.G)
+    L.or_get_imh(self._h, _p(acc, C.c_int32), _p(la))
+    return acc, la
+
+
+def _oracle_features(self, F=32):
+    L = _mlp_lib(self._L)
+    out = np.empty((self.G, F))
+    if L.or_features(self._h, F, _p(out)) != 0:
+        raise ValueError("or_features failed")
+    return out
+
+
+Oracle.set_proposal = _oracle_set_proposal
+Oracle.imh = _oracle_imh
+Oracle.features = _oracle_features

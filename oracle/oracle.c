@@ -215,6 +215,16 @@ struct or_ctx {
     int64_t errors;
     double red[2 + 2 * 64];
     int nthreads;
+    /* distinct rows of X in order of first appearance (features of the proposal) */
+    int R;
+    int *row_of;           /* [N] */
+    /* learned beta proposal: owned copy of the model, fallback mask, records */
+    int prop_on;
+    or_mlp prop;
+    double *prop_buf;
+    int32_t *prop_mask;    /* [G]: 1 = slice fallback */
+    int32_t *imh_acc;      /* [G]: last sweep, 1 = accepted, 0 = rejected, -1 = slice */
+    double *imh_la;        /* [G]: log acceptance ratio of the last IMH step */
 };
 
 static int64_t n_params(const or_ctx *c)
@@ -271,7 +281,23 @@ int or_create(or_ctx **out, const or_config *cfg)
     c->cnt = (int32_t *)xcalloc((size_t)(4 * n_slice(c)), sizeof(int32_t));
     c->mrg = (double *)xcalloc((size_t)n_slice(c), sizeof(double));
     c->nthreads = 1;
-    if (!c->y || !c->eps || !c->mean || !c->msq || !c->cnt || !c->mrg) { or_destroy(c); return -2; }
+    c->row_of = (int *)xcalloc((size_t)N, sizeof(int));
+    c->prop_mask = (int32_t *)xcalloc((size_t)G, sizeof(int32_t));
+    c->imh_acc = (int32_t *)xcalloc((size_t)G, sizeof(int32_t));
+    c->imh_la = (double *)xcalloc((size_t)G, sizeof(double));
+    if (!c->y || !c->eps || !c->mean || !c->msq || !c->cnt || !c->mrg || !c->row_of || !c->prop_mask ||
+        !c->imh_acc || !c->imh_la) { or_destroy(c); return -2; }
+    /* rows of X that are equal entry by entry share a row index */
+    c->R = 0;
+    for (int n = 0; n < N; ++n) {
+        int found = -1;
+        for (int q = 0; q < n && found < 0; ++q) {
+            int same = 1;
+            for (int l = 0; l < L; ++l) if (c->X[q * L + l] != c->X[n * L + l]) { same = 0; break; }
+            if (same) found = c->row_of[q];
+        }
+        c->row_of[n] = found >= 0 ? found : c->R++;
+    }
     for (int64_t i = 0; i < G * N; ++i) c->w_eps[i] = cfg->w0;
     for (int64_t i = 0; i < G; ++i) c->w_gam[i] = cfg->w0;
     for (int64_t i = 0; i < G * L; ++i) c->w_beta[i] = cfg->w0;
@@ -290,6 +316,7 @@ void or_destroy(or_ctx *c)
     free(c->w_eps); free(c->wa_eps); free(c->w_gam); free(c->wa_gam);
     free(c->w_beta); free(c->wa_beta); free(c->w_sig2); free(c->wa_sig2);
     free(c->mean); free(c->msq); free(c->cnt); free(c->mrg);
+    free(c->row_of); free(c->prop_buf); free(c->prop_mask); free(c->imh_acc); free(c->imh_la);
     free(c);
 }
 
@@ -390,6 +417,130 @@ static double logf_sig2(double x, const void *p)
 }
 
 /* ------------------------------------------------------------------ */
+/* Learned proposal: features and the independence-MH step             */
+/* ------------------------------------------------------------------ */
+/* Features of gene g (definition in mlp.c): per distinct row r of X,
+ * log((Y_r + 1/2) / A_r) and log(Y_r + 1/2), then theta and log sigma^2. */
+static void gene_features(const or_ctx *c, int64_t g, double *phi, int F)
+{
+    const int N = c->cfg.N, L = c->cfg.L, R = c->R;
+    double Y[64], A[64];
+    for (int r = 0; r < R; ++r) { Y[r] = 0.0; A[r] = 0.0; }
+    for (int n = 0; n < N; ++n) {
+        Y[c->row_of[n]] += (double)c->y[g * N + n];
+        A[c->row_of[n]] += exp(c->h[n] + c->eps[g * N + n]);
+    }
+    for (int i = 0; i < F; ++i) phi[i] = 0.0;
+    for (int r = 0; r < R; ++r) {
+        phi[r] = log((Y[r] + 0.5) / A[r]);
+        phi[R + r] = log(Y[r] + 0.5);
+    }
+    for (int l = 0; l < L; ++l) {
+        phi[2 * R + l] = c->theta[l];
+        phi[2 * R + L + l] = log(c->sig2[l]);
+    }
+}
+
+/* log of the beta_g full conditional at b, up to a constant:
+ * sum_n [y_gn X_n b - exp(h_n + eps_gn + X_n b)] - sum_l (b_l - theta_l)^2 / (2 sigma_l^2) */
+static double log_post_beta(const or_ctx *c, int64_t g, const double *b)
+{
+    const int N = c->cfg.N, L = c->cfg.L;
+    double s = 0.0;
+    for (int n = 0; n < N; ++n) {
+        double xb = 0.0;
+        for (int l = 0; l < L; ++l) xb += c->X[n * L + l] * b[l];
+        s += (double)c->y[g * N + n] * xb - exp(c->h[n] + c->eps[g * N + n] + xb);
+    }
+    for (int l = 0; l < L; ++l) {
+        const double d = b[l] - c->theta[l];
+        s -= d * d / (2.0 * c->sig2[l]);
+    }
+    return s;
+}
+
+/* One independence Metropolis-Hastings step for beta_g.  Random words come
+ * from counter (g, 8 << 24, m, chain << 16 | j): word 0 is the acceptance
+ * uniform, words (1 + 2p, 2 + 2p) give the Box-Muller pair p of normals
+ * (z_2p = rho cos(2 pi u_b), z_2p+1 = rho sin(2 pi u_b), rho = sqrt(-2 log u_a)). */
+static void imh_step(or_ctx *c, int64_t g, uint32_t mm)
+{
+    const int L = c->cfg.L, F = c->prop.F;
+    double phi[OR_MLP_MAXW], mu[64], ls[64], z[64], bs[64];
+    gene_features(c, g, phi, F);
+    or_mlp_forward(&c->prop, phi, 1, mu, ls);
+    rstream rs;
+    rs_init(&rs, c->cfg.seed, (uint32_t)g, OR_KIND_IMH, 0, mm, (uint32_t)c->cfg.chain);
+    const double uacc = u01(rs_word(&rs, 0));
+    for (int p = 0; 2 * p < L; ++p) {
+        const double ua = u01(rs_word(&rs, (uint32_t)(1 + 2 * p)));
+        const double ub = u01(rs_word(&rs, (uint32_t)(2 + 2 * p)));
+        const double rho = sqrt(-2.0 * log(ua));
+        z[2 * p] = rho * cos(2.0 * M_PI * ub);
+        if (2 * p + 1 < L) z[2 * p + 1] = rho * sin(2.0 * M_PI * ub);
+    }
+    for (int l = 0; l < L; ++l) bs[l] = mu[l] + exp(ls[l]) * z[l];
+    const double *b = c->beta + g * L;
+    double lq_new = 0.0, lq_old = 0.0;
+    for (int l = 0; l < L; ++l) {
+        const double e2 = exp(-2.0 * ls[l]);
+        lq_new -= ls[l] + 0.5 * (bs[l] - mu[l]) * (bs[l] - mu[l]) * e2;
+        lq_old -= ls[l] + 0.5 * (b[l] - mu[l]) * (b[l] - mu[l]) * e2;
+    }
+    const double la = (log_post_beta(c, g, bs) - log_post_beta(c, g, b)) - (OR_MUTANT == 9 ? 0.0 : lq_new - lq_old);
+    c->imh_la[g] = la;
+    if (log(uacc) < la) {
+        for (int l = 0; l < L; ++l) c->beta[g * L + l] = bs[l];
+        c->imh_acc[g] = 1;
+    } else {
+        c->imh_acc[g] = 0;
+    }
+}
+
+int or_set_proposal(or_ctx *c, const or_mlp *m, const int32_t *fallback_mask)
+{
+    if (!c) return -1;
+    if (!m) { c->prop_on = 0; return 0; }
+    const int L = c->cfg.L;
+    if (m->O != 2 * L || m->F < 2 * c->R + 2 * L || m->F > OR_MLP_MAXW || m->H > OR_MLP_MAXW || m->H < 1)
+        return -1;
+    const size_t F = (size_t)m->F, H = (size_t)m->H, O = (size_t)m->O;
+    const size_t total = 2 * F + F * H + H + H * H + H + H * O + O + 2 * (size_t)L;
+    double *buf = (double *)malloc(sizeof(double) * total);
+    if (!buf) return -2;
+    double *p = buf;
+    or_mlp cp = *m;
+#define OR_TAKE(field, n) do { memcpy(p, m->field, sizeof(double) * (n)); cp.field = p; p += (n); } while (0)
+    OR_TAKE(fmean, F); OR_TAKE(fscale, F);
+    OR_TAKE(W1, F * H); OR_TAKE(b1, H); OR_TAKE(W2, H * H); OR_TAKE(b2, H);
+    OR_TAKE(W3, H * O); OR_TAKE(b3, O); OR_TAKE(omean, (size_t)L); OR_TAKE(oscale, (size_t)L);
+#undef OR_TAKE
+    free(c->prop_buf);
+    c->prop_buf = buf;
+    c->prop = cp;
+    for (int64_t g = 0; g < c->cfg.G; ++g) c->prop_mask[g] = fallback_mask ? fallback_mask[g] : 0;
+    c->prop_on = 1;
+    return 0;
+}
+
+int or_features(const or_ctx *c, int32_t F, double *phi)
+{
+    if (!c || !phi || F < 2 * c->R + 2 * c->cfg.L) return -1;
+    for (int64_t g = 0; g < c->cfg.G; ++g) gene_features(c, g, phi + g * F, F);
+    return 0;
+}
+
+int or_get_imh(const or_ctx *c, int32_t *acc, double *log_alpha)
+{
+    if (!c) return -1;
+    if (acc) memcpy(acc, c->imh_acc, sizeof(int32_t) * (size_t)c->cfg.G);
+    if (log_alpha) memcpy(log_alpha, c->imh_la, sizeof(double) * (size_t)c->cfg.G);
+    return 0;
+}
+
+int or_num_rows(const or_ctx *c) { return c ? c->R : -1; }
+
+/* ------------------------------------------------------------------ */
 /* One sweep (Algorithm 1)                                             */
 /* ------------------------------------------------------------------ */
 static void record(or_ctx *c, int64_t idx, const draw_info *di)
@@ -479,11 +630,19 @@ static int64_t sweep_once(or_ctx *c)
         record(c, off_beta + G * L + 1, &di);
         errs += di.bad;
     }
-    /* Step 5: for l = 1..L, in parallel over g, beta_gl */
+    /* Step 5: beta_g, in parallel over g (l = 1..L in order within a gene; the
+     * genes are conditionally independent, so gene-major order is the same
+     * chain).  Genes with the learned proposal on take one independence
+     * Metropolis-Hastings step for the whole block instead. */
     if (mask & (1u << OR_KIND_BETA)) {
-        for (int l = 0; l < L; ++l) {
 #pragma omp parallel for schedule(static) reduction(+:errs) num_threads(c->nthreads)
-            for (int64_t g = 0; g < G; ++g) {
+        for (int64_t g = 0; g < G; ++g) {
+            if (c->prop_on && !c->prop_mask[g]) {
+                imh_step(c, g, mm);
+                continue;
+            }
+            c->imh_acc[g] = -1;
+            for (int l = 0; l < L; ++l) {
                 double bwork[64];
                 for (int i = 0; i < L; ++i) bwork[i] = c->beta[g * L + i];
                 double Yl = 0.0;

@@ -116,6 +116,37 @@ int  or_slice_test(int32_t target, const double *params, const double *x0, doubl
                    int64_t n, double w, int32_t K, uint64_t seed, uint32_t m,
                    int32_t *counts);
 
+/* ---- learned beta proposal (mlp.c) ---- */
+#define OR_MLP_MAXW 256
+typedef struct {
+    int32_t F, H, O;              /* inputs, hidden width, outputs (= 2L) */
+    const double *fmean, *fscale; /* [F] input standardisation */
+    const double *W1, *b1;        /* [F][H], [H] */
+    const double *W2, *b2;        /* [H][H], [H] */
+    const double *W3, *b3;        /* [H][O], [O] */
+    const double *omean, *oscale; /* [L] output affine map */
+} or_mlp;
+
+/* mu, ls: [B][L] proposal means and log-scales for feature rows phi [B][F]. */
+int or_mlp_forward(const or_mlp *m, const double *phi, int64_t B, double *mu, double *ls);
+/* Mean Gaussian NLL of targets [B][L] and its gradients (any may be NULL). */
+int or_mlp_loss_grad(const or_mlp *m, const double *phi, const double *target, int64_t B,
+                     double *loss, double *gW1, double *gb1, double *gW2, double *gb2,
+                     double *gW3, double *gb3);
+
+/* Use the learned proposal for step 5: genes with fallback_mask[g] = 0 take
+ * one independence Metropolis-Hastings step for beta_g (mlp.c describes the
+ * features and the network); the others keep the slice steps.  The model is
+ * copied.  m = NULL switches the proposal off. */
+int or_set_proposal(or_ctx *c, const or_mlp *m, const int32_t *fallback_mask);
+/* Features of every gene of the current state, [G][F]. */
+int or_features(const or_ctx *c, int32_t F, double *phi);
+/* Last sweep's IMH records per gene: acc (1 accepted, 0 rejected, -1 slice)
+ * and the log acceptance ratio. */
+int or_get_imh(const or_ctx *c, int32_t *acc, double *log_alpha);
+/* Number of distinct rows of X. */
+int or_num_rows(const or_ctx *c);
+
 #ifdef __cplusplus
 }
 #endif

@@ -10,7 +10,7 @@ CSRC = os.path.join(PKG, "csrc")
 INCLUDE = os.path.join(ROOT, "include")
 LIB = os.path.join(PKG, "libfbmc.so")
 
-SOURCES = ["fbmc_kernels.hip", "fbmc_host.cpp"]
+SOURCES = ["fbmc_kernels.hip", "fbmc_mlp.hip", "fbmc_host.cpp"]
 
 HIPCC_FLAGS = [
     "-O3", "-std=c++17", "--offload-arch=gfx950", "-fPIC",

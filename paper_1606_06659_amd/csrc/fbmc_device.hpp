@@ -55,7 +55,17 @@ template <> __device__ inline float uwin<float>(uint32_t r) { return ((float)(r 
 __device__ inline double dlog(double x) { return ::log(x); }
 __device__ inline float dlog(float x) { return ::logf(x); }
 __device__ inline double dexpm1(double x) { return ::expm1(x); }
-__device__ inline float dexpm1(float x) { return ::expm1f(x); }
+// float expm1: for |x| <= ln(2)/2 the degree-7 Taylor polynomial of e^x - 1
+// (truncation below 1.4e-8 relative, under one float ulp); elsewhere e^x - 1,
+// whose magnitude is then at least 0.29 so the subtraction loses no accuracy.
+// Both are computed and one is selected, so a wavefront never branches here.
+__device__ inline float dexpm1(float x)
+{
+    const float p = x * (1.0f + x * (0.5f + x * (1.0f / 6.0f + x * (1.0f / 24.0f +
+                    x * (1.0f / 120.0f + x * (1.0f / 720.0f + x * (1.0f / 5040.0f)))))));
+    const float e = __expf(x) - 1.0f;
+    return __builtin_fabsf(x) <= 0.34657359f ? p : e;
+}
 __device__ inline double dexp(double x) { return ::exp(x); }
 __device__ inline float dexp(float x) { return ::expf(x); }
 __device__ inline double dlog1p(double x) { return ::log1p(x); }
@@ -77,6 +87,12 @@ struct DrawRec {
 //   f.base(x0) : the reference level (0 when f returns log f(x) - log f(x0))
 //   f(x)       : the value compared with base + log u
 // A point x is in the slice when f(x) > f.base + log u, u ~ U(0, 1).
+//
+// Each trip evaluates one point.  The trip is written without branches: the
+// point of every phase is formed and the one of the lane's phase selected, and
+// the interval, counters and phase are updated with selects, so lanes in
+// different phases share one instruction stream.  Only the rare fetch of a
+// further Philox block (shrink candidate 3, 7, ...) branches.
 template <typename T, typename F>
 __device__ inline T slice_draw(F &f, T x0, T w, uint32_t k0, uint32_t k1, uint4 ctr, int K,
                                int cap, DrawRec &rec)
@@ -94,34 +110,39 @@ __device__ inline T slice_draw(F &f, T x0, T w, uint32_t k0, uint32_t k1, uint4 
     T x1 = x0;
     bool bad = false;
     for (;;) {
-        T x;
-        if (phase == 0) {
-            x = L;
-        } else if (phase == 1) {
-            x = R;
-        } else {
-            // shrink candidate t + 1 reads word q = t + 2 of the draw's stream
-            const uint32_t q = (uint32_t)t + 2u;
-            if ((q >> 2) != blk) {
-                blk = q >> 2;
-                r = philox4x32_10(make_uint4(ctr.x, ctr.y, ctr.z, (ctr.w & 0xFFFF0000u) | blk), k0, k1);
-            }
-            const uint32_t s = q & 3u;
-            const uint32_t word = s == 0 ? r.x : (s == 1 ? r.y : (s == 2 ? r.z : r.w));
-            x = L + u01<T>(word) * (R - L);
+        // shrink candidate t + 1 reads word q = t + 2 of the draw's stream
+        const uint32_t q = (uint32_t)t + 2u;
+        if (phase == 2 && (q >> 2) != blk) {
+            blk = q >> 2;
+            r = philox4x32_10(make_uint4(ctr.x, ctr.y, ctr.z, (ctr.w & 0xFFFF0000u) | blk), k0, k1);
         }
+        const uint32_t s = q & 3u;
+        const uint32_t word = s == 0 ? r.x : (s == 1 ? r.y : (s == 2 ? r.z : r.w));
+        const T xs = L + u01<T>(word) * (R - L);
+        const bool p0 = phase == 0, p1 = phase == 1, p2 = phase == 2;
+        const T x = p0 ? L : (p1 ? R : xs);
         const bool in = f(x) > thr;
-        if (phase == 0) {
-            if (in) { L = L - w; ++nl; }
-            if (!in || nl == KL) phase = KR > 0 ? 1 : 2;
-        } else if (phase == 1) {
-            if (in) { R = R + w; ++nr; }
-            if (!in || nr == KR) phase = 2;
-        } else {
-            ++t;
-            if (in) { x1 = x; break; }
-            if (x > x0) R = x; else L = x;
-            if (t >= cap) { bad = true; break; }
+        // step out (phases 0 and 1)
+        const bool mvl = p0 && in, mvr = p1 && in;
+        L = mvl ? L - w : L;
+        R = mvr ? R + w : R;
+        nl += mvl ? 1 : 0;
+        nr += mvr ? 1 : 0;
+        const int after_left = KR > 0 ? 1 : 2;
+        const int ph_left = (!in || nl == KL) ? after_left : 0;
+        const int ph_right = (!in || nr == KR) ? 2 : 1;
+        // shrink (phase 2)
+        t += p2 ? 1 : 0;
+        const bool acc = p2 && in;
+        const bool rej = p2 && !in;
+        R = (rej && x > x0) ? x : R;
+        L = (rej && !(x > x0)) ? x : L;
+        x1 = acc ? x : x1;
+        const bool capped = rej && t >= cap;
+        phase = p0 ? ph_left : (p1 ? ph_right : 2);
+        if (acc || capped) {
+            bad = capped;
+            break;
         }
     }
     rec.kl = KL;
@@ -130,6 +151,94 @@ __device__ inline T slice_draw(F &f, T x0, T w, uint32_t k0, uint32_t k1, uint4 
     rec.nc = t;
     rec.bad = bad;
     return x1;
+}
+
+// The same draw by a whole wavefront for one scalar (hyperparameters): the
+// step-out points L - k w (lanes 0..15) and R + k w (lanes 32..47) are
+// evaluated at once, then the chain of shrink candidates that assumes every
+// earlier candidate was rejected (it is known in advance: each interval update
+// depends only on the candidate and x0) is evaluated at once, 32 candidates per
+// round; the first point in the slice is the sequential algorithm's result.
+// Points are formed by the same repeated additions as the sequential code, so
+// the result, counters and records match it exactly.  All 64 lanes must call.
+template <typename F>
+__device__ inline double slice_draw_wave(F &f, double x0, double w, uint32_t k0, uint32_t k1, uint4 ctr,
+                                         int K, int cap, DrawRec &rec, double *words /* LDS [64] */)
+{
+    const int lane = (int)(threadIdx.x & 63);
+    const uint4 r0 = philox4x32_10(ctr, k0, k1);
+    const double thr = f.base(x0) + dlog(u01<double>(r0.x));
+    const double v = w * uwin<double>(r0.y);
+    const double L0 = x0 - v;
+    const double R0 = L0 + w;
+    const int KL = (int)(r0.y & (uint32_t)K);
+    const int KR = K - KL;
+    // step out in parallel
+    const int j = lane & 31;
+    const bool left = lane < 32;
+    double pt = left ? L0 : R0;
+    for (int i = 0; i < j && i < 15; ++i) pt = left ? pt - w : pt + w;
+    const bool need = left ? (j < KL) : (j < KR);
+    const bool in = need && (f(pt) > thr);
+    const uint64_t fail_l = __ballot(left && need && !in);
+    const uint64_t fail_r = __ballot(!left && need && !in) >> 32;
+    const int nl = fail_l ? __builtin_ctzll(fail_l) : KL;
+    const int nr = fail_r ? __builtin_ctzll(fail_r) : KR;
+    double L = L0, R = R0;
+    for (int i = 0; i < nl; ++i) L = L - w;
+    for (int i = 0; i < nr; ++i) R = R + w;
+    // shrink: words of the stream, block b from lane b
+    double x1 = x0;
+    int nc = cap;
+    bool found = false;
+    for (int base = 0; base < cap && !found; base += 32) {
+        // words q = base + 2 .. base + 33 cover candidates base + 1 .. base + 32
+        const uint32_t b0 = (uint32_t)(base + 2) >> 2;
+        if (lane < 10) {
+            const uint32_t b = b0 + (uint32_t)lane;
+            const uint4 rb = b == 0 ? r0
+                             : philox4x32_10(make_uint4(ctr.x, ctr.y, ctr.z, (ctr.w & 0xFFFF0000u) | b), k0, k1);
+            words[4 * lane + 0] = u01<double>(rb.x);
+            words[4 * lane + 1] = u01<double>(rb.y);
+            words[4 * lane + 2] = u01<double>(rb.z);
+            words[4 * lane + 3] = u01<double>(rb.w);
+        }
+        __builtin_amdgcn_wave_barrier();
+        __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "wavefront");
+        // lane c (< 32) evaluates candidate base + c + 1: run the rejection chain to it
+        double xc = 0.0, Lc = L, Rc = R;
+        const int c = lane & 31;
+        for (int i = 0; i <= c; ++i) {
+            const int q = base + i + 2;
+            const double u = words[q - 4 * (int)b0];
+            xc = Lc + u * (Rc - Lc);
+            if (i < c) {
+                if (xc > x0) Rc = xc; else Lc = xc;
+            }
+        }
+        const bool cand = lane < 32 && base + c < cap;
+        const bool acc = cand && (f(xc) > thr);
+        const uint64_t hit = __ballot(acc);
+        // advance the shared interval past this round's 32 rejections
+        if (hit) {
+            const int first = __builtin_ctzll(hit);
+            x1 = __shfl(xc, first, 64);
+            nc = base + first + 1;
+            found = true;
+        } else {
+            L = __shfl(Lc, 31, 64);
+            R = __shfl(Rc, 31, 64);
+            const double xl = __shfl(xc, 31, 64);
+            if (xl > x0) R = xl; else L = xl;
+        }
+        __builtin_amdgcn_wave_barrier();
+    }
+    rec.kl = KL;
+    rec.nl = nl;
+    rec.nr = nr;
+    rec.nc = found ? nc : cap;
+    rec.bad = !found;
+    return found ? x1 : x0;
 }
 
 // Algorithm 2 step 7: tuning of w during burn-in (m <= M_B).

@@ -16,6 +16,7 @@
 #include <vector>
 
 #include "fbmc_device.hpp"
+#include "fbmc_mlp.hpp"
 #include "fbmc_types.hpp"
 
 namespace fbmc {
@@ -23,6 +24,18 @@ hipError_t launch_gene(int precision, const SegInfo *segs, const int2 *tiles, in
                        const SweepArgs &a, int *err, hipStream_t st);
 hipError_t launch_hyper(const SegInfo *segs, int nseg, const SweepArgs &a, int *err, hipStream_t st);
 hipError_t launch_philox(const uint4 *ctr, const uint2 *key, uint4 *out, int64_t n, hipStream_t st);
+hipError_t launch_split(int precision, const SegInfo *segs, const int2 *tiles, int ntiles, const SweepArgs &a,
+                        int *err, hipStream_t st);
+hipError_t launch_beta(int precision, const SegInfo *segs, const int2 *tiles, int ntiles, const SweepArgs &a,
+                       int *err, hipStream_t st);
+hipError_t launch_feat_mlp(int precision, const SegInfo *segs, const int2 *tiles, int ntiles, const MlpDev *net,
+                           hipStream_t st);
+hipError_t launch_mlp_infer_raw(const float *phi, int64_t B, int L, const MlpDev *net, float *mu, float *ls,
+                                hipStream_t st);
+hipError_t launch_features(int precision, const SegInfo *seg, int64_t G, float *out, hipStream_t st);
+hipError_t launch_gather_pairs(const float *pairs, int64_t P, int L, const float *master, float *X, float *Tg,
+                               int B, uint32_t epoch, uint32_t step, uint32_t k0, uint32_t k1, hipStream_t st);
+hipError_t launch_col_moments(const float *M, int64_t rows, int cols, double *out, hipStream_t st);
 }  // namespace fbmc
 
 using namespace fbmc;
@@ -87,6 +100,14 @@ struct fb_ctx {
     int32_t prof_every = 0, prof_cap = 0, prof_n = 0;
     int64_t prof_count = 0;
     std::vector<hipEvent_t> prof_ev;   // 4 per sample
+    // learned beta proposal
+    int beta_mode = FB_BETA_SLICE;
+    bool split_ready = false;
+    float *d_master = nullptr;        // kMlpParams FP32
+    MlpDev *d_net = nullptr;          // packed inference copy
+    bool net_ready = false;
+    float *d_pairs = nullptr;
+    int64_t pair_cap = 0, pair_n = 0, totalG = 0;
 };
 
 namespace {
@@ -537,6 +558,229 @@ bool valid_seg(const fb_ctx *c, int32_t seg) { return c && seg >= 0 && seg < (in
 
 }  // namespace
 
+namespace {
+
+struct SweepMode {
+    bool split = false;      // eps/gamma kernel, [network], beta kernel
+    bool learned = false;    // IMH where the fallback mask is 0
+    bool count_imh = false;  // add accepted IMH steps to the counters
+    int32_t collect_every = 0;
+    int64_t collect_slot = 0;
+};
+
+int run_sweeps(fb_ctx *c, int64_t n, SweepMode &md)
+{
+    const fb_options &o = c->opt;
+    HIPCHK(c, hipEventRecord(c->ev0, c->st));
+    for (int64_t i = 0; i < n; ++i) {
+        SweepArgs a{};
+        a.m = c->m + 1;
+        a.burnin = o.burnin;
+        a.tune_start = o.tune_start;
+        a.K = o.max_steps;
+        a.cap = o.shrink_cap;
+        a.mask = o.update_mask;
+        a.dbg = o.debug_counts;
+        a.trace_point = -1;
+        a.learned = md.learned ? 1 : 0;
+        a.count_imh = md.count_imh ? 1 : 0;
+        a.pair_base = -1;
+        if (md.collect_every > 0 && a.m % md.collect_every == 0 &&
+            (md.collect_slot + 1) * c->totalG <= c->pair_cap) {
+            a.pair_base = md.collect_slot * c->totalG;
+            ++md.collect_slot;
+            c->pair_n = md.collect_slot * c->totalG;
+        }
+        if (o.thin > 0 && o.trace_capacity > 0 && a.m % o.thin == 0 && (!o.trace_after_burnin || a.m > o.burnin)) {
+            if (c->trace_n < o.trace_capacity) a.trace_point = (int32_t)c->trace_n++;
+            else ++c->trace_dropped;
+        }
+        const bool prof = c->prof_every > 0 && c->prof_n < c->prof_cap && (c->prof_count++ % c->prof_every) == 0;
+        hipEvent_t *pe = prof ? &c->prof_ev[4 * (size_t)c->prof_n++] : nullptr;
+        if (pe) HIPCHK(c, hipEventRecord(pe[0], c->st));
+        if (md.split) {
+            HIPCHK(c, launch_split(c->prec, c->d_segs, c->d_tiles, c->ntiles, a, c->d_err, c->st));
+            if (md.learned) HIPCHK(c, launch_feat_mlp(c->prec, c->d_segs, c->d_tiles, c->ntiles, c->d_net, c->st));
+            HIPCHK(c, launch_beta(c->prec, c->d_segs, c->d_tiles, c->ntiles, a, c->d_err, c->st));
+        } else {
+            HIPCHK(c, launch_gene(c->prec, c->d_segs, c->d_tiles, c->ntiles, a, c->d_err, c->st));
+        }
+        if (pe) HIPCHK(c, hipEventRecord(pe[1], c->st));
+        if (pe) HIPCHK(c, hipEventRecord(pe[2], c->st));
+        HIPCHK(c, launch_hyper(c->d_segs, (int)c->seg.size(), a, c->d_err, c->st));
+        if (pe) HIPCHK(c, hipEventRecord(pe[3], c->st));
+        c->m = a.m;
+    }
+    HIPCHK(c, hipEventRecord(c->ev1, c->st));
+    c->last_n = n;
+    return FB_OK;
+}
+
+int upload_segs(fb_ctx *c)
+{
+    std::vector<SegInfo> infos;
+    for (auto &S : c->seg) infos.push_back(S.info);
+    HIPCHK(c, hipStreamSynchronize(c->st));
+    HIPCHK(c, hipMemcpy(c->d_segs, infos.data(), infos.size() * sizeof(SegInfo), hipMemcpyHostToDevice));
+    return FB_OK;
+}
+
+// Buffers of the split sweep: per segment the row sums A_r, the constant count
+// sums Y_r, the network's outputs, the fallback mask and the IMH records.
+int ensure_split(fb_ctx *c)
+{
+    if (c->split_ready) return FB_OK;
+    int rc;
+    c->totalG = 0;
+    for (auto &S : c->seg) {
+        const DatasetH &D = c->ds[S.dataset];
+        const int R = D.des.R, L = D.L;
+        const size_t Gp = (size_t)S.Gp;
+        SegInfo &I = S.info;
+        if ((rc = dalloc(c, &I.Ar, (size_t)R * Gp * c->esz))) return rc;
+        if ((rc = dalloc(c, &I.YR, (size_t)R * Gp * c->esz))) return rc;
+        std::vector<double> yr((size_t)D.G * R, 0.0);
+        for (int64_t g = 0; g < D.G; ++g)
+            for (int n = 0; n < D.N; ++n) yr[(size_t)g * R + D.des.row_of[n]] += (double)D.y[g * D.N + n];
+        if ((rc = upload_array(c, I.YR, yr.data(), D.G, R, S.Gp, 0.0))) return rc;
+        if ((rc = dalloc(c, (void **)&I.mlp_out, 2 * (size_t)L * Gp * sizeof(float)))) return rc;
+        if ((rc = dalloc(c, (void **)&I.fallback, Gp * sizeof(int32_t)))) return rc;
+        if ((rc = dalloc(c, (void **)&I.imh_count, Gp * sizeof(int32_t)))) return rc;
+        if ((rc = dalloc(c, (void **)&I.imh_last, Gp * sizeof(int32_t)))) return rc;
+        c->totalG += S.G;
+    }
+    if ((rc = upload_segs(c))) return rc;
+    c->split_ready = true;
+    return FB_OK;
+}
+
+int ensure_net(fb_ctx *c)
+{
+    int rc;
+    if (!c->d_master && (rc = dalloc(c, (void **)&c->d_master, kMlpParams * sizeof(float)))) return rc;
+    if (!c->d_net && (rc = dalloc(c, (void **)&c->d_net, sizeof(MlpDev)))) return rc;
+    return FB_OK;
+}
+
+int pack_net(fb_ctx *c, const float *d_master, MlpDev *d_net, hipStream_t st)
+{
+    const int total = (kMlpH / 16) * (kMlpH / 32) * 64 * 8;
+    hipLaunchKernelGGL(pack_mlp, dim3((total + 255) / 256), dim3(256), 0, st, d_master, d_net);
+    HIPCHK(c, hipGetLastError());
+    return FB_OK;
+}
+
+// Host fb_mlp <-> contiguous master block.
+bool mlp_to_block(const fb_mlp *w, std::vector<float> &blk)
+{
+    if (!w || !w->fmean || !w->fscale || !w->W1 || !w->b1 || !w->W2 || !w->b2 || !w->W3 || !w->b3 ||
+        !w->omean || !w->oscale)
+        return false;
+    blk.assign(kMlpParams, 0.0f);
+    std::copy(w->fmean, w->fmean + kMlpF, blk.begin() + kOffFmean);
+    std::copy(w->fscale, w->fscale + kMlpF, blk.begin() + kOffFscale);
+    std::copy(w->W1, w->W1 + kMlpF * kMlpH, blk.begin() + kOffW1);
+    std::copy(w->b1, w->b1 + kMlpH, blk.begin() + kOffB1);
+    std::copy(w->W2, w->W2 + kMlpH * kMlpH, blk.begin() + kOffW2);
+    std::copy(w->b2, w->b2 + kMlpH, blk.begin() + kOffB2);
+    std::copy(w->W3, w->W3 + kMlpH * kMlpO, blk.begin() + kOffW3);
+    std::copy(w->b3, w->b3 + kMlpO, blk.begin() + kOffB3);
+    std::copy(w->omean, w->omean + 8, blk.begin() + kOffOmean);
+    std::copy(w->oscale, w->oscale + 8, blk.begin() + kOffOscale);
+    return true;
+}
+
+void block_to_mlp(const std::vector<float> &blk, fb_mlp *w)
+{
+    auto put = [&](float *dst, int off, int n) { if (dst) std::copy(blk.begin() + off, blk.begin() + off + n, dst); };
+    put(w->fmean, kOffFmean, kMlpF);
+    put(w->fscale, kOffFscale, kMlpF);
+    put(w->W1, kOffW1, kMlpF * kMlpH);
+    put(w->b1, kOffB1, kMlpH);
+    put(w->W2, kOffW2, kMlpH * kMlpH);
+    put(w->b2, kOffB2, kMlpH);
+    put(w->W3, kOffW3, kMlpH * kMlpO);
+    put(w->b3, kOffB3, kMlpO);
+    put(w->omean, kOffOmean, 8);
+    put(w->oscale, kOffOscale, 8);
+}
+
+// Scratch of one forward/backward pass on B rows.
+struct TrainBufs {
+    float *X = nullptr, *Tg = nullptr, *Z1 = nullptr, *H1 = nullptr, *Z2 = nullptr, *H2 = nullptr;
+    float *O = nullptr, *dO = nullptr, *dH = nullptr, *dZ2 = nullptr, *dZ1 = nullptr, *loss = nullptr;
+    float *grad = nullptr;
+    int B = 0;
+};
+
+int alloc_train(fb_ctx *c, TrainBufs &t, int B, int L)
+{
+    int rc;
+    const size_t b = (size_t)B;
+    float **bufs[] = {&t.Z1, &t.H1, &t.Z2, &t.H2, &t.dH, &t.dZ2, &t.dZ1};
+    for (float **p : bufs) if ((rc = dalloc(c, (void **)p, b * kMlpH * sizeof(float)))) return rc;
+    if ((rc = dalloc(c, (void **)&t.X, b * kMlpF * sizeof(float)))) return rc;
+    if ((rc = dalloc(c, (void **)&t.Tg, b * (size_t)std::max(L, 1) * sizeof(float)))) return rc;
+    if ((rc = dalloc(c, (void **)&t.O, b * kMlpO * sizeof(float)))) return rc;
+    if ((rc = dalloc(c, (void **)&t.dO, b * kMlpO * sizeof(float)))) return rc;
+    if ((rc = dalloc(c, (void **)&t.loss, b * sizeof(float)))) return rc;
+    if ((rc = dalloc(c, (void **)&t.grad, kMlpParams * sizeof(float)))) return rc;
+    t.B = B;
+    return FB_OK;
+}
+
+hipError_t gemm(const float *A, int lda, int tA, const float *B, int ldb, int tB, float *C, int ldc, int M, int N,
+                int K, hipStream_t st)
+{
+    const int tiles = (M / 32) * (N / 32);
+    hipLaunchKernelGGL(gemm_bf16, dim3(tiles), dim3(64), 0, st, A, lda, tA, B, ldb, tB, C, ldc, M, N, K, 0);
+    return hipGetLastError();
+}
+
+// Loss and gradients of the mean Gaussian NLL over the B standardised rows in
+// t.X with targets t.Tg; the gradient block has the master layout.
+int forward_backward(fb_ctx *c, const float *master, TrainBufs &t, int L, hipStream_t st)
+{
+    const int B = t.B;
+    const float *W1 = master + kOffW1, *W2 = master + kOffW2, *W3 = master + kOffW3;
+    auto ew = [&](int64_t n) { return dim3((unsigned)((n + 255) / 256)); };
+    HIPCHK(c, gemm(t.X, kMlpF, 0, W1, kMlpH, 0, t.Z1, kMlpH, B, kMlpH, kMlpF, st));
+    hipLaunchKernelGGL(bias_gelu, ew((int64_t)B * kMlpH), dim3(256), 0, st, t.Z1, master + kOffB1, t.H1, B, kMlpH, 1);
+    HIPCHK(c, gemm(t.H1, kMlpH, 0, W2, kMlpH, 0, t.Z2, kMlpH, B, kMlpH, kMlpH, st));
+    hipLaunchKernelGGL(bias_gelu, ew((int64_t)B * kMlpH), dim3(256), 0, st, t.Z2, master + kOffB2, t.H2, B, kMlpH, 1);
+    HIPCHK(c, gemm(t.H2, kMlpH, 0, W3, kMlpO, 0, t.O, kMlpO, B, kMlpO, kMlpH, st));
+    hipLaunchKernelGGL(bias_gelu, ew((int64_t)B * kMlpO), dim3(256), 0, st, t.O, master + kOffB3, (float *)nullptr, B,
+                       kMlpO, 0);
+    hipLaunchKernelGGL(nll_grad, ew(B), dim3(256), 0, st, t.O, kMlpO, t.Tg, L, master + kOffOmean,
+                       master + kOffOscale, t.dO, t.loss, B);
+    HIPCHK(c, hipMemsetAsync(t.grad, 0, kMlpParams * sizeof(float), st));
+    float *g = t.grad;
+    // layer 3
+    HIPCHK(c, gemm(t.H2, kMlpH, 1, t.dO, kMlpO, 0, g + kOffW3, kMlpO, kMlpH, kMlpO, B, st));
+    hipLaunchKernelGGL(col_sum, dim3(1), dim3(kMlpO), 0, st, t.dO, B, kMlpO, g + kOffB3);
+    HIPCHK(c, gemm(t.dO, kMlpO, 0, W3, kMlpO, 1, t.dH, kMlpH, B, kMlpH, kMlpO, st));
+    hipLaunchKernelGGL(gelu_backward, ew((int64_t)B * kMlpH), dim3(256), 0, st, t.Z2, t.dH, t.dZ2, (int64_t)B * kMlpH);
+    // layer 2
+    HIPCHK(c, gemm(t.H1, kMlpH, 1, t.dZ2, kMlpH, 0, g + kOffW2, kMlpH, kMlpH, kMlpH, B, st));
+    hipLaunchKernelGGL(col_sum, dim3(1), dim3(kMlpH), 0, st, t.dZ2, B, kMlpH, g + kOffB2);
+    HIPCHK(c, gemm(t.dZ2, kMlpH, 0, W2, kMlpH, 1, t.dH, kMlpH, B, kMlpH, kMlpH, st));
+    hipLaunchKernelGGL(gelu_backward, ew((int64_t)B * kMlpH), dim3(256), 0, st, t.Z1, t.dH, t.dZ1, (int64_t)B * kMlpH);
+    // layer 1
+    HIPCHK(c, gemm(t.X, kMlpF, 1, t.dZ1, kMlpH, 0, g + kOffW1, kMlpH, kMlpF, kMlpH, B, st));
+    hipLaunchKernelGGL(col_sum, dim3(1), dim3(kMlpH), 0, st, t.dZ1, B, kMlpH, g + kOffB1);
+    HIPCHK(c, hipGetLastError());
+    return FB_OK;
+}
+
+double std_normal_key(uint64_t seed, uint32_t i, uint32_t j)
+{
+    const uint4 r = philox4x32_10(make_uint4(i, j, 0xA11Cu, 0), (uint32_t)seed, (uint32_t)(seed >> 32));
+    const double u0 = ((double)r.x + 0.5) * 0x1p-32, u1 = ((double)r.y + 0.5) * 0x1p-32;
+    return std::sqrt(-2.0 * std::log(u0)) * std::cos(6.283185307179586 * u1);
+}
+
+}  // namespace
+
 // ===========================================================================
 // C ABI
 // ===========================================================================
@@ -613,35 +857,10 @@ int fb_sweep(fb_ctx *c, int64_t n)
     if (!c) return fail(nullptr, FB_EINVAL, "NULL context");
     if (n < 0) return fail(c, FB_EINVAL, "n must be >= 0");
     if (c->sticky) return c->sticky;
-    const fb_options &o = c->opt;
-    HIPCHK(c, hipEventRecord(c->ev0, c->st));
-    for (int64_t i = 0; i < n; ++i) {
-        SweepArgs a{};
-        a.m = c->m + 1;
-        a.burnin = o.burnin;
-        a.tune_start = o.tune_start;
-        a.K = o.max_steps;
-        a.cap = o.shrink_cap;
-        a.mask = o.update_mask;
-        a.dbg = o.debug_counts;
-        a.trace_point = -1;
-        if (o.thin > 0 && o.trace_capacity > 0 && a.m % o.thin == 0 && (!o.trace_after_burnin || a.m > o.burnin)) {
-            if (c->trace_n < o.trace_capacity) a.trace_point = (int32_t)c->trace_n++;
-            else ++c->trace_dropped;
-        }
-        const bool prof = c->prof_every > 0 && c->prof_n < c->prof_cap && (c->prof_count++ % c->prof_every) == 0;
-        hipEvent_t *pe = prof ? &c->prof_ev[4 * (size_t)c->prof_n++] : nullptr;
-        if (pe) HIPCHK(c, hipEventRecord(pe[0], c->st));
-        HIPCHK(c, launch_gene(c->prec, c->d_segs, c->d_tiles, c->ntiles, a, c->d_err, c->st));
-        if (pe) HIPCHK(c, hipEventRecord(pe[1], c->st));
-        if (pe) HIPCHK(c, hipEventRecord(pe[2], c->st));
-        HIPCHK(c, launch_hyper(c->d_segs, (int)c->seg.size(), a, c->d_err, c->st));
-        if (pe) HIPCHK(c, hipEventRecord(pe[3], c->st));
-        c->m = a.m;
-    }
-    HIPCHK(c, hipEventRecord(c->ev1, c->st));
-    c->last_n = n;
-    return FB_OK;
+    SweepMode md;
+    md.learned = c->beta_mode == FB_BETA_LEARNED;
+    md.split = md.learned;
+    return run_sweeps(c, n, md);
 }
 
 int fb_sync(fb_ctx *c)
@@ -944,6 +1163,335 @@ int fb_kernel_times(fb_ctx *c, double *gene_ms, double *hyper_ms, int64_t *sampl
     if (samples) *samples = c->prof_n;
     c->prof_n = 0;
     c->prof_count = 0;
+    return FB_OK;
+}
+
+void fb_default_train_opts(fb_train_opts *o)
+{
+    if (!o) return;
+    o->epochs = 200;
+    o->pairs_per_epoch = 10240;
+    o->minibatch = 1024;
+    o->lr = 1e-3;
+    o->seed = 1;
+}
+
+static int same_design(fb_ctx *c)
+{
+    for (auto &S : c->seg) {
+        const DatasetH &D = c->ds[S.dataset], &D0 = c->ds[c->seg[0].dataset];
+        if (D.L != D0.L || D.des.R != D0.des.R) return fail(c, FB_EINVAL, "the proposal needs one design for every segment");
+        if (2 * D.des.R + 2 * D.L > kMlpF) return fail(c, FB_EINVAL, "too many features for the proposal network");
+    }
+    return FB_OK;
+}
+
+int fb_proposal_collect(fb_ctx *c, int64_t sweeps, int32_t every)
+{
+    if (!c) return fail(nullptr, FB_EINVAL, "NULL context");
+    if (sweeps < 0 || every < 1) return fail(c, FB_EINVAL, "need sweeps >= 0 and every >= 1");
+    if (c->sticky) return c->sticky;
+    int rc;
+    if ((rc = same_design(c)) || (rc = ensure_split(c))) return rc;
+    const int64_t slots = std::max<int64_t>(1, sweeps / every + 1);
+    const int64_t need = slots * c->totalG;
+    if (need > c->pair_cap) {
+        if ((rc = dalloc(c, (void **)&c->d_pairs, (size_t)need * kPairStride * sizeof(float)))) return rc;
+        c->pair_cap = need;
+    }
+    int64_t off = 0;
+    for (auto &S : c->seg) {
+        S.info.pairs = c->d_pairs + off * kPairStride;
+        off += S.G;
+    }
+    if ((rc = upload_segs(c))) return rc;
+    c->pair_n = 0;
+    SweepMode md;
+    md.split = true;
+    md.learned = false;
+    md.collect_every = every;
+    return run_sweeps(c, sweeps, md);
+}
+
+int fb_proposal_train(fb_ctx *c, const fb_train_opts *opts, double *epoch_loss)
+{
+    if (!c) return fail(nullptr, FB_EINVAL, "NULL context");
+    fb_train_opts o;
+    fb_default_train_opts(&o);
+    if (opts) o = *opts;
+    if (o.epochs < 1 || o.minibatch < 32 || o.minibatch % 32 || o.pairs_per_epoch < o.minibatch || !(o.lr > 0))
+        return fail(c, FB_EINVAL, "bad training options");
+    if (c->pair_n < 2) return fail(c, FB_ESTATE, "no training pairs: call fb_proposal_collect first");
+    int rc;
+    if ((rc = ensure_net(c))) return rc;
+    const int L = c->seg[0].L;
+    const int64_t P = c->pair_n;
+    HIPCHK(c, hipStreamSynchronize(c->st));
+    // standardisation from the pairs
+    double *d_mom = nullptr;
+    if ((rc = dalloc(c, (void **)&d_mom, 2 * kPairStride * sizeof(double)))) return rc;
+    HIPCHK(c, launch_col_moments(c->d_pairs, P, kPairStride, d_mom, c->st));
+    std::vector<double> mom(2 * kPairStride);
+    HIPCHK(c, hipMemcpyAsync(mom.data(), d_mom, mom.size() * sizeof(double), hipMemcpyDeviceToHost, c->st));
+    HIPCHK(c, hipStreamSynchronize(c->st));
+    std::vector<float> blk(kMlpParams, 0.0f);
+    for (int k = 0; k < kMlpF; ++k) {
+        const double mu = mom[2 * k] / (double)P;
+        const double var = std::max(0.0, mom[2 * k + 1] / (double)P - mu * mu);
+        blk[kOffFmean + k] = (float)mu;
+        blk[kOffFscale + k] = var > 1e-12 ? (float)(1.0 / std::sqrt(var)) : 0.0f;
+    }
+    for (int l = 0; l < 8; ++l) {
+        if (l < L) {
+            const double mu = mom[2 * (32 + l)] / (double)P;
+            const double var = std::max(0.0, mom[2 * (32 + l) + 1] / (double)P - mu * mu);
+            blk[kOffOmean + l] = (float)mu;
+            blk[kOffOscale + l] = (float)std::max(std::sqrt(var), 1e-3);
+        } else {
+            blk[kOffOscale + l] = 1.0f;
+        }
+    }
+    // seeded initial weights: N(0, 1 / fan_in); the output layer starts small
+    for (int i = 0; i < kMlpF * kMlpH; ++i)
+        blk[kOffW1 + i] = (float)(std_normal_key(o.seed, 1, i) / std::sqrt((double)kMlpF));
+    for (int i = 0; i < kMlpH * kMlpH; ++i)
+        blk[kOffW2 + i] = (float)(std_normal_key(o.seed, 2, i) / std::sqrt((double)kMlpH));
+    for (int i = 0; i < kMlpH * kMlpO; ++i) {
+        const int col = i % kMlpO;
+        blk[kOffW3 + i] = col < 2 * L ? (float)(0.1 * std_normal_key(o.seed, 3, i) / std::sqrt((double)kMlpH)) : 0.0f;
+    }
+    HIPCHK(c, hipMemcpy(c->d_master, blk.data(), kMlpParams * sizeof(float), hipMemcpyHostToDevice));
+    float *d_m = nullptr, *d_v = nullptr;
+    if ((rc = dalloc(c, (void **)&d_m, kMlpParams * sizeof(float)))) return rc;
+    if ((rc = dalloc(c, (void **)&d_v, kMlpParams * sizeof(float)))) return rc;
+    TrainBufs t;
+    if ((rc = alloc_train(c, t, o.minibatch, L))) return rc;
+    const int steps = o.pairs_per_epoch / o.minibatch;
+    const float b1 = 0.9f, b2 = 0.999f, eps = 1e-8f;
+    int64_t it = 0;
+    std::vector<float> lossv(o.minibatch);
+    const int64_t nopt = kOffOmean - kOffW1;   // W1 .. b3 are trained
+    for (int e = 0; e < o.epochs; ++e) {
+        double esum = 0.0;
+        for (int sidx = 0; sidx < steps; ++sidx) {
+            HIPCHK(c, launch_gather_pairs(c->d_pairs, P, L, c->d_master, t.X, t.Tg, o.minibatch, (uint32_t)e,
+                                          (uint32_t)sidx, (uint32_t)o.seed, (uint32_t)(o.seed >> 32), c->st));
+            if ((rc = forward_backward(c, c->d_master, t, L, c->st))) return rc;
+            ++it;
+            const float c1 = 1.0f - std::pow(b1, (float)it), c2 = 1.0f - std::pow(b2, (float)it);
+            hipLaunchKernelGGL(adam_step, dim3((unsigned)((nopt + 255) / 256)), dim3(256), 0, c->st,
+                               c->d_master + kOffW1, t.grad + kOffW1, d_m + kOffW1, d_v + kOffW1, nopt, (float)o.lr,
+                               b1, b2, eps, c1, c2);
+            HIPCHK(c, hipGetLastError());
+            if (epoch_loss) {
+                HIPCHK(c, hipMemcpyAsync(lossv.data(), t.loss, lossv.size() * sizeof(float), hipMemcpyDeviceToHost, c->st));
+                HIPCHK(c, hipStreamSynchronize(c->st));
+                for (float v : lossv) esum += v;
+            }
+        }
+        if (epoch_loss) epoch_loss[e] = esum / ((double)steps * o.minibatch);
+    }
+    if ((rc = pack_net(c, c->d_master, c->d_net, c->st))) return rc;
+    HIPCHK(c, hipStreamSynchronize(c->st));
+    c->net_ready = true;
+    return FB_OK;
+}
+
+int fb_proposal_calibrate(fb_ctx *c, int64_t sweeps, double min_accept)
+{
+    if (!c) return fail(nullptr, FB_EINVAL, "NULL context");
+    if (sweeps < 1) return fail(c, FB_EINVAL, "need sweeps >= 1");
+    if (!c->net_ready) return fail(c, FB_ESTATE, "no network: train or load one first");
+    if (c->sticky) return c->sticky;
+    int rc;
+    if ((rc = ensure_split(c))) return rc;
+    for (auto &S : c->seg) {
+        HIPCHK(c, hipMemsetAsync(S.info.fallback, 0, (size_t)S.Gp * sizeof(int32_t), c->st));
+        HIPCHK(c, hipMemsetAsync(S.info.imh_count, 0, (size_t)S.Gp * sizeof(int32_t), c->st));
+    }
+    SweepMode md;
+    md.split = true;
+    md.learned = true;
+    md.count_imh = true;
+    if ((rc = run_sweeps(c, sweeps, md))) return rc;
+    HIPCHK(c, hipStreamSynchronize(c->st));
+    for (auto &S : c->seg) {
+        std::vector<int32_t> cnt((size_t)S.Gp), mask((size_t)S.Gp, 0);
+        HIPCHK(c, hipMemcpy(cnt.data(), S.info.imh_count, cnt.size() * sizeof(int32_t), hipMemcpyDeviceToHost));
+        for (int64_t g = 0; g < S.G; ++g) mask[g] = ((double)cnt[g] / (double)sweeps) < min_accept ? 1 : 0;
+        HIPCHK(c, hipMemcpy(S.info.fallback, mask.data(), mask.size() * sizeof(int32_t), hipMemcpyHostToDevice));
+    }
+    return FB_OK;
+}
+
+int fb_set_beta_update(fb_ctx *c, int32_t mode)
+{
+    if (!c) return fail(nullptr, FB_EINVAL, "NULL context");
+    if (mode != FB_BETA_SLICE && mode != FB_BETA_LEARNED) return fail(c, FB_EINVAL, "unknown beta update");
+    if (mode == FB_BETA_LEARNED) {
+        if (!c->net_ready) return fail(c, FB_ESTATE, "no network: train or load one first");
+        int rc;
+        if ((rc = same_design(c)) || (rc = ensure_split(c))) return rc;
+    }
+    c->beta_mode = mode;
+    return FB_OK;
+}
+
+int fb_proposal_get(fb_ctx *c, fb_mlp *out)
+{
+    if (!c || !out) return fail(c, FB_EINVAL, "NULL argument");
+    if (!c->net_ready) return fail(c, FB_ESTATE, "no network");
+    std::vector<float> blk(kMlpParams);
+    HIPCHK(c, hipStreamSynchronize(c->st));
+    HIPCHK(c, hipMemcpy(blk.data(), c->d_master, kMlpParams * sizeof(float), hipMemcpyDeviceToHost));
+    block_to_mlp(blk, out);
+    return FB_OK;
+}
+
+int fb_proposal_set(fb_ctx *c, const fb_mlp *in)
+{
+    if (!c) return fail(nullptr, FB_EINVAL, "NULL context");
+    std::vector<float> blk;
+    if (!mlp_to_block(in, blk)) return fail(c, FB_EINVAL, "every parameter array is required");
+    for (float v : blk) if (!std::isfinite(v)) return fail(c, FB_EINVAL, "parameters must be finite");
+    for (int l = 0; l < 8; ++l) if (!(blk[kOffOscale + l] > 0)) return fail(c, FB_EINVAL, "oscale must be > 0");
+    int rc;
+    if ((rc = same_design(c)) || (rc = ensure_net(c)) || (rc = ensure_split(c))) return rc;
+    HIPCHK(c, hipStreamSynchronize(c->st));
+    HIPCHK(c, hipMemcpy(c->d_master, blk.data(), kMlpParams * sizeof(float), hipMemcpyHostToDevice));
+    if ((rc = pack_net(c, c->d_master, c->d_net, c->st))) return rc;
+    HIPCHK(c, hipStreamSynchronize(c->st));
+    c->net_ready = true;
+    return FB_OK;
+}
+
+int fb_fallback(fb_ctx *c, int32_t seg, int32_t *get, const int32_t *set)
+{
+    if (!valid_seg(c, seg)) return fail(c, FB_EINVAL, "bad segment");
+    int rc;
+    if ((rc = ensure_split(c))) return rc;
+    SegmentH &S = c->seg[seg];
+    HIPCHK(c, hipStreamSynchronize(c->st));
+    if (set) {
+        std::vector<int32_t> m((size_t)S.Gp, 0);
+        for (int64_t g = 0; g < S.G; ++g) m[g] = set[g] ? 1 : 0;
+        HIPCHK(c, hipMemcpy(S.info.fallback, m.data(), m.size() * sizeof(int32_t), hipMemcpyHostToDevice));
+    }
+    if (get) HIPCHK(c, hipMemcpy(get, S.info.fallback, (size_t)S.G * sizeof(int32_t), hipMemcpyDeviceToHost));
+    return FB_OK;
+}
+
+int fb_imh_last(fb_ctx *c, int32_t seg, int32_t *last)
+{
+    if (!valid_seg(c, seg) || !last) return fail(c, FB_EINVAL, "bad segment or NULL output");
+    if (!c->split_ready) return fail(c, FB_ESTATE, "no split sweep has run");
+    int rc = fb_sync(c);
+    if (rc && rc != FB_ENUMERIC) return rc;
+    HIPCHK(c, hipMemcpy(last, c->seg[seg].info.imh_last, (size_t)c->seg[seg].G * sizeof(int32_t),
+                        hipMemcpyDeviceToHost));
+    return c->sticky;
+}
+
+int fb_features(fb_ctx *c, int32_t seg, float *phi)
+{
+    if (!valid_seg(c, seg) || !phi) return fail(c, FB_EINVAL, "bad segment or NULL output");
+    SegmentH &S = c->seg[seg];
+    float *d = nullptr;
+    HIPCHK(c, hipStreamSynchronize(c->st));
+    if (hipMalloc((void **)&d, (size_t)S.G * 32 * sizeof(float)) != hipSuccess) return fail(c, FB_ENOMEM, "hipMalloc");
+    hipError_t e = launch_features(c->prec, c->d_segs + seg, S.G, d, c->st);
+    if (e == hipSuccess) e = hipStreamSynchronize(c->st);
+    if (e == hipSuccess) e = hipMemcpy(phi, d, (size_t)S.G * 32 * sizeof(float), hipMemcpyDeviceToHost);
+    (void)hipFree(d);
+    if (e != hipSuccess) return fail(c, FB_EDEVICE, std::string("fb_features: ") + hipGetErrorString(e));
+    return FB_OK;
+}
+
+// ---- test entry points on host data, each with its own temporary context ----
+int fb_mfma_probe(const float *A, const float *B, float *C)
+{
+    if (!A || !B || !C) return fail(nullptr, FB_EINVAL, "NULL argument");
+    float *d = nullptr;
+    if (hipMalloc((void **)&d, (512 + 512 + 1024) * sizeof(float)) != hipSuccess) return fail(nullptr, FB_ENOMEM, "hipMalloc");
+    hipError_t e = hipMemcpy(d, A, 512 * sizeof(float), hipMemcpyHostToDevice);
+    if (e == hipSuccess) e = hipMemcpy(d + 512, B, 512 * sizeof(float), hipMemcpyHostToDevice);
+    if (e == hipSuccess) {
+        hipLaunchKernelGGL(mfma_probe, dim3(1), dim3(64), 0, nullptr, d, d + 512, d + 1024);
+        e = hipGetLastError();
+    }
+    if (e == hipSuccess) e = hipMemcpy(C, d + 1024, 1024 * sizeof(float), hipMemcpyDeviceToHost);
+    (void)hipFree(d);
+    if (e != hipSuccess) return fail(nullptr, FB_EDEVICE, std::string("fb_mfma_probe: ") + hipGetErrorString(e));
+    return FB_OK;
+}
+
+int fb_mlp_forward(const fb_mlp *w, int32_t L, const float *phi, int64_t B, float *mu, float *ls)
+{
+    std::vector<float> blk;
+    if (!mlp_to_block(w, blk) || L < 1 || L > kMaxL || B < 0 || (B > 0 && (!phi || !mu || !ls)))
+        return fail(nullptr, FB_EINVAL, "bad arguments");
+    if (B == 0) return FB_OK;
+    fb_ctx tmp;
+    int rc;
+    float *d_master = nullptr, *d_phi = nullptr, *d_out = nullptr;
+    MlpDev *d_net = nullptr;
+    if ((rc = dalloc(&tmp, (void **)&d_master, kMlpParams * sizeof(float))) ||
+        (rc = dalloc(&tmp, (void **)&d_net, sizeof(MlpDev))) ||
+        (rc = dalloc(&tmp, (void **)&d_phi, (size_t)B * 32 * sizeof(float))) ||
+        (rc = dalloc(&tmp, (void **)&d_out, (size_t)B * 2 * L * sizeof(float)))) {
+        g_thread_err = tmp.err;
+        for (void *p : tmp.allocs) (void)hipFree(p);
+        return rc;
+    }
+    hipError_t e = hipMemcpy(d_master, blk.data(), kMlpParams * sizeof(float), hipMemcpyHostToDevice);
+    if (e == hipSuccess) e = hipMemcpy(d_phi, phi, (size_t)B * 32 * sizeof(float), hipMemcpyHostToDevice);
+    if (e == hipSuccess && pack_net(&tmp, d_master, d_net, nullptr) != FB_OK) e = hipErrorUnknown;
+    if (e == hipSuccess) e = launch_mlp_infer_raw(d_phi, B, L, d_net, d_out, d_out + (size_t)B * L, nullptr);
+    if (e == hipSuccess) e = hipMemcpy(mu, d_out, (size_t)B * L * sizeof(float), hipMemcpyDeviceToHost);
+    if (e == hipSuccess) e = hipMemcpy(ls, d_out + (size_t)B * L, (size_t)B * L * sizeof(float), hipMemcpyDeviceToHost);
+    for (void *p : tmp.allocs) (void)hipFree(p);
+    if (e != hipSuccess) return fail(nullptr, FB_EDEVICE, std::string("fb_mlp_forward: ") + hipGetErrorString(e));
+    return FB_OK;
+}
+
+int fb_mlp_loss_grad(const fb_mlp *w, int32_t L, const float *phi, const float *target, int64_t B, float *loss,
+                     fb_mlp *grad)
+{
+    std::vector<float> blk;
+    if (!mlp_to_block(w, blk) || L < 1 || L > kMaxL || B < 32 || B % 32 || !phi || !target)
+        return fail(nullptr, FB_EINVAL, "bad arguments (B must be a positive multiple of 32)");
+    fb_ctx tmp;
+    int rc;
+    float *d_master = nullptr, *d_pairs = nullptr;
+    TrainBufs t;
+    if ((rc = dalloc(&tmp, (void **)&d_master, kMlpParams * sizeof(float))) ||
+        (rc = dalloc(&tmp, (void **)&d_pairs, (size_t)B * kPairStride * sizeof(float))) ||
+        (rc = alloc_train(&tmp, t, (int)B, L))) {
+        g_thread_err = tmp.err;
+        for (void *p : tmp.allocs) (void)hipFree(p);
+        return rc;
+    }
+    // rows in order: standardise on the host side of the copy (plain arithmetic)
+    std::vector<float> X((size_t)B * kMlpF);
+    for (int64_t b = 0; b < B; ++b)
+        for (int k = 0; k < kMlpF; ++k)
+            X[b * kMlpF + k] = (phi[b * 32 + k] - blk[kOffFmean + k]) * blk[kOffFscale + k];
+    hipError_t e = hipMemcpy(d_master, blk.data(), kMlpParams * sizeof(float), hipMemcpyHostToDevice);
+    if (e == hipSuccess) e = hipMemcpy(t.X, X.data(), X.size() * sizeof(float), hipMemcpyHostToDevice);
+    if (e == hipSuccess) e = hipMemcpy(t.Tg, target, (size_t)B * L * sizeof(float), hipMemcpyHostToDevice);
+    if (e == hipSuccess && forward_backward(&tmp, d_master, t, L, nullptr) != FB_OK) e = hipErrorUnknown;
+    if (e == hipSuccess) e = hipDeviceSynchronize();
+    std::vector<float> lv((size_t)B), gb(kMlpParams);
+    if (e == hipSuccess) e = hipMemcpy(lv.data(), t.loss, lv.size() * sizeof(float), hipMemcpyDeviceToHost);
+    if (e == hipSuccess) e = hipMemcpy(gb.data(), t.grad, gb.size() * sizeof(float), hipMemcpyDeviceToHost);
+    for (void *p : tmp.allocs) (void)hipFree(p);
+    if (e != hipSuccess) return fail(nullptr, FB_EDEVICE, std::string("fb_mlp_loss_grad: ") + hipGetErrorString(e) + " " + tmp.err);
+    if (loss) {
+        double sum = 0.0;
+        for (float v : lv) sum += v;
+        *loss = (float)(sum / (double)B);
+    }
+    if (grad) block_to_mlp(gb, grad);
     return FB_OK;
 }
 

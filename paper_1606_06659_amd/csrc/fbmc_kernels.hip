@@ -26,6 +26,7 @@
 //          over the samples whose X_nl equals the k-th distinct non-zero value v_k
 //          of column l (exact regrouping of the sum over n).
 #include "fbmc_device.hpp"
+#include "fbmc_mlp.hpp"
 #include "fbmc_types.hpp"
 
 namespace fbmc {
@@ -120,9 +121,231 @@ __device__ inline void raise_flag(int *err, int bit)
 }
 
 // ---------------------------------------------------------------------------
+// Beta-step building blocks (one lane per gene)
+// ---------------------------------------------------------------------------
+// C_r = A_r exp(X_r beta_g): the sum over the samples of distinct row r of
+// exp(h_n + eps_gn + X_n beta_g).
+template <typename T>
+__device__ inline void row_sums_at_beta(const SegInfo &S, const T (&A)[kMaxRows], const T (&beta)[kMaxL],
+                                        T (&C)[kMaxRows])
+{
+    const int L = S.L, R = S.R;
+#pragma unroll
+    for (int r = 0; r < kMaxRows; ++r) {
+        T xr = (T)0;
+#pragma unroll
+        for (int l = 0; l < kMaxL; ++l)
+            if (l < L) xr += (T)S.Xrow[r * kMaxL + l] * beta[l];
+        C[r] = (r < R) ? A[r] * dexp(xr) : (T)0;
+    }
+}
+
+// Features of the learned proposal (any function of y_g, eps_g, h, theta,
+// sigma^2, never of beta_g): per distinct row r, log((Y_r + 1/2) / A_r) and
+// log(Y_r + 1/2); then theta_l and log sigma_l^2; zero up to 32.
+template <typename T>
+__device__ inline void gene_features(const SegInfo &S, const T (&A)[kMaxRows], const T (&YR)[kMaxRows],
+                                     const double (&th)[kMaxL], const double (&s2)[kMaxL], float (&phi)[32])
+{
+    const int L = S.L, R = S.R;
+#pragma unroll
+    for (int k = 0; k < 32; ++k) phi[k] = 0.0f;
+#pragma unroll
+    for (int r = 0; r < kMaxRows; ++r) {
+        if (r < R) {
+            const float y = (float)YR[r] + 0.5f;
+            const float lr = ::logf(y / (float)A[r]);
+            const float ly = ::logf(y);
+#pragma unroll
+            for (int k = 0; k < 32; ++k) {
+                if (k == r) phi[k] = lr;
+                if (k == R + r) phi[k] = ly;
+            }
+        }
+    }
+#pragma unroll
+    for (int l = 0; l < kMaxL; ++l) {
+        if (l < L) {
+            const float t = (float)th[l], ls2 = (float)::log(s2[l]);
+#pragma unroll
+            for (int k = 0; k < 32; ++k) {
+                if (k == 2 * R + l) phi[k] = t;
+                if (k == 2 * R + L + l) phi[k] = ls2;
+            }
+        }
+    }
+}
+
+// Algorithm 1 step 5 by slice draws: beta_g1..beta_gL in order, each moving
+// the row sums C_r to the new coefficient.
+template <typename T>
+__device__ inline void beta_slice_draws(const SegInfo &S, const SweepArgs &a, int64_t g, int64_t Gp,
+                                        T (&beta)[kMaxL], T (&wb)[kMaxL], T (&wab)[kMaxL],
+                                        const double (&th)[kMaxL], const double (&s2)[kMaxL],
+                                        T (&C)[kMaxRows], const T (&YR)[kMaxRows], bool tuning, int &bad)
+{
+    const int L = S.L, R = S.R;
+    const uint32_t mm = (uint32_t)a.m;
+    T *__restrict__ betap = (T *)S.beta;
+    for (int l = 0; l < L; ++l) {
+        const int64_t idx = (int64_t)l * Gp + g;
+        T b0 = (T)0, w = (T)1, wa = (T)0;
+        double thl = 0.0, s2l = 1.0;
+#pragma unroll
+        for (int j = 0; j < kMaxL; ++j)
+            if (j == l) { b0 = beta[j]; w = wb[j]; wa = wab[j]; thl = th[j]; s2l = s2[j]; }
+        BetaF<T> f;
+        f.Y = (T)0;
+#pragma unroll
+        for (int r = 0; r < kMaxRows; ++r)
+            if (r < R) f.Y += (T)S.Xrow[r * kMaxL + l] * YR[r];
+        f.nv = S.nv[l];
+#pragma unroll
+        for (int k = 0; k < kMaxVals; ++k) {
+            f.Gk[k] = (T)0;
+            f.vk[k] = (T)S.vals[l * kMaxVals + k];
+            f.em1[k] = (T)0;
+        }
+#pragma unroll
+        for (int r = 0; r < kMaxRows; ++r) {
+            const int k = S.xidx[r * kMaxL + l];
+#pragma unroll
+            for (int kk = 0; kk < kMaxVals; ++kk)
+                if (r < R && k == kk) f.Gk[kk] += C[r];
+        }
+        f.x0 = b0;
+        f.dth = (T)((double)b0 - thl);
+        f.inv_s2 = (T)(1.0 / s2l);
+        DrawRec rec;
+        const T b1 = slice_draw<T>(f, b0, w, S.key0, S.key1,
+                                   draw_counter((uint32_t)g, 5, (uint32_t)l, mm, (uint32_t)S.chain, 0), a.K,
+                                   a.cap, rec);
+        if (tuning) {
+            tune_width<T>(w, wa, b0, b1, a.m, a.burnin, a.tune_start);
+            ((T *)S.w_beta)[idx] = w;
+            ((T *)S.wa_beta)[idx] = wa;
+        }
+        betap[idx] = b1;
+        bad |= rec.bad;
+        if (a.dbg) S.dbg_beta[idx] = make_int4(rec.kl, rec.nl, rec.nr, rec.nc);
+        // C_r *= exp(X_rl (b1 - b0)), from expm1 at the accepted point
+        T fac[kMaxVals];
+#pragma unroll
+        for (int k = 0; k < kMaxVals; ++k) fac[k] = rec.bad ? (T)1 : (T)1 + f.em1[k];
+#pragma unroll
+        for (int r = 0; r < kMaxRows; ++r) {
+            const int k = S.xidx[r * kMaxL + l];
+#pragma unroll
+            for (int kk = 0; kk < kMaxVals; ++kk)
+                if (r < R && k == kk) C[r] *= fac[kk];
+        }
+#pragma unroll
+        for (int j = 0; j < kMaxL; ++j)
+            if (j == l) beta[j] = b1;
+    }
+}
+
+// Algorithm 1 step 5 by one independence Metropolis-Hastings step for the
+// block beta_g with the proposal N(mu, diag(exp(ls))^2) the network produced.
+// Random words: counter (g, 8 << 24, m, chain << 16 | j); word 0 is the
+// acceptance uniform, words (1 + 2p, 2 + 2p) the Box-Muller pair p.
+// log alpha = [log pi(beta*) - log pi(beta)] + [log q(beta) - log q(beta*)],
+// with the conditional's difference formed from the row sums:
+//   sum_r [Y_r X_r d - C_r expm1(X_r d)] - sum_l d_l (beta_l - theta_l + d_l / 2) / sigma_l^2.
+// Returns 1 if accepted.
+template <typename T>
+__device__ inline int beta_imh_draw(const SegInfo &S, const SweepArgs &a, int64_t g, int64_t Gp,
+                                    T (&beta)[kMaxL], const double (&th)[kMaxL], const double (&s2)[kMaxL],
+                                    const T (&C)[kMaxRows], const T (&YR)[kMaxRows])
+{
+    const int L = S.L, R = S.R;
+    const uint32_t mm = (uint32_t)a.m;
+    const uint4 ctr = draw_counter((uint32_t)g, 8, 0, mm, (uint32_t)S.chain, 0);
+    uint4 b0 = philox4x32_10(ctr, S.key0, S.key1);
+    uint4 b1 = philox4x32_10(make_uint4(ctr.x, ctr.y, ctr.z, ctr.w | 1u), S.key0, S.key1);
+    uint4 b2 = philox4x32_10(make_uint4(ctr.x, ctr.y, ctr.z, ctr.w | 2u), S.key0, S.key1);
+    const uint32_t wv[12] = {b0.x, b0.y, b0.z, b0.w, b1.x, b1.y, b1.z, b1.w, b2.x, b2.y, b2.z, b2.w};
+    T z[kMaxL];
+#pragma unroll
+    for (int p = 0; p < kMaxL / 2; ++p) {
+        const T ua = u01<T>(wv[1 + 2 * p]), ub = u01<T>(wv[2 + 2 * p]);
+        const T rho = (T)::sqrt(-2.0 * (double)dlog(ua));
+        const double ang = 6.283185307179586 * (double)ub;
+        z[2 * p] = rho * (T)::cos(ang);
+        z[2 * p + 1] = rho * (T)::sin(ang);
+    }
+    T d[kMaxL], bs[kMaxL];
+    T dq = (T)0, dpi = (T)0;
+#pragma unroll
+    for (int l = 0; l < kMaxL; ++l) {
+        d[l] = (T)0;
+        bs[l] = beta[l];
+        if (l < L) {
+            const T mu = (T)S.mlp_out[(int64_t)l * Gp + g];
+            const T ls = (T)S.mlp_out[(int64_t)(L + l) * Gp + g];
+            bs[l] = mu + dexp(ls) * z[l];
+            d[l] = bs[l] - beta[l];
+            const T r0 = (beta[l] - mu) * dexp(-ls);
+            dq += (T)0.5 * (z[l] * z[l] - r0 * r0);
+            dpi -= d[l] * ((T)((double)beta[l] - th[l]) + (T)0.5 * d[l]) * (T)(1.0 / s2[l]);
+        }
+    }
+#pragma unroll
+    for (int r = 0; r < kMaxRows; ++r) {
+        if (r < R) {
+            T xd = (T)0;
+#pragma unroll
+            for (int l = 0; l < kMaxL; ++l)
+                if (l < L) xd += (T)S.Xrow[r * kMaxL + l] * d[l];
+            dpi += YR[r] * xd - C[r] * dexpm1(xd);
+        }
+    }
+    const T la = dpi + dq;
+    const bool acc = dlog(u01<T>(wv[0])) < la;
+    if (acc) {
+#pragma unroll
+        for (int l = 0; l < kMaxL; ++l)
+            if (l < L) {
+                beta[l] = bs[l];
+                ((T *)S.beta)[(int64_t)l * Gp + g] = bs[l];
+            }
+    }
+    return acc ? 1 : 0;
+}
+
+// After the beta step: moments, trace, and the tile partials of
+// (beta_l - theta_l) and its square (all lanes of the wavefront call).
+template <typename T>
+__device__ inline void beta_finish(const SegInfo &S, const SweepArgs &a, int64_t g, int64_t Gp, bool active,
+                                   const T (&beta)[kMaxL], double2 (&mob)[kMaxL], const double (&th)[kMaxL],
+                                   int tile, int lane, int tslot, float *trow, bool sampling, double kmom)
+{
+    const int L = S.L;
+    for (int l = 0; l < L; ++l) {
+        T b1 = (T)0;
+        double2 mo = make_double2(0.0, 0.0);
+        double thl = 0.0;
+#pragma unroll
+        for (int j = 0; j < kMaxL; ++j)
+            if (j == l) { b1 = beta[j]; mo = mob[j]; thl = th[j]; }
+        if (active && sampling) {
+            welford(mo, (double)b1, kmom);
+            S.mom_beta[(int64_t)l * Gp + g] = mo;
+        }
+        if (tslot >= 0) trow[(int64_t)tslot * (L + 1) + 1 + l] = (float)b1;
+        const double dv = active ? (double)b1 - thl : 0.0;
+        const double s0 = wave_sum(dv), s1 = wave_sum(dv * dv);
+        if (lane == 0) {
+            S.partials[(int64_t)tile * kMaxParts + 2 + 2 * l] = s0;
+            S.partials[(int64_t)tile * kMaxParts + 3 + 2 * l] = s1;
+        }
+    }
+}
+
+// ---------------------------------------------------------------------------
 // Gene kernel
 // ---------------------------------------------------------------------------
-template <typename T>
+template <typename T, bool kSplit>
 __global__ __launch_bounds__(256) void gene_sweep(const SegInfo *__restrict__ segs,
                                                   const int2 *__restrict__ tiles, int ntiles,
                                                   SweepArgs a, int *err)
@@ -135,34 +358,62 @@ __global__ __launch_bounds__(256) void gene_sweep(const SegInfo *__restrict__ se
     const int sidx = __builtin_amdgcn_readfirstlane(tt.x);
     const int tile = __builtin_amdgcn_readfirstlane(tt.y);
     const SegInfo &S = segs[sidx];
-    const HyperState &H = *S.hyp;
     const int64_t Gp = S.Gp;
     const int64_t g = (int64_t)tile * kTile + lane;
     const bool active = g < S.G;
     const int N = S.N, L = S.L, R = S.R;
     const uint32_t mm = (uint32_t)a.m;
     const uint32_t chain = (uint32_t)S.chain;
+    const uint32_t k0 = S.key0, k1 = S.key1;
     const bool tuning = a.m <= a.burnin;
     const bool sampling = a.m > a.burnin;
     const double kmom = (double)(a.m - a.burnin);
     const bool dbg = a.dbg != 0;
     const bool tracing = a.trace_point >= 0;
+    const bool upd_eps = (a.mask >> 1) & 1u;
+    const bool upd_gam = (a.mask >> 2) & 1u;
+    const bool upd_beta = (a.mask >> 5) & 1u;
+
+    const int32_t *__restrict__ yp = S.y;
+    T *__restrict__ eps = (T *)S.eps;
+    T *__restrict__ w_eps = (T *)S.w_eps;
+    T *__restrict__ wa_eps = (T *)S.wa_eps;
+    double2 *__restrict__ mom_eps = S.mom_eps;
+    T *__restrict__ gamp = (T *)S.gam;
+    T *__restrict__ betap = (T *)S.beta;
+    T *__restrict__ w_beta = (T *)S.w_beta;
+    T *__restrict__ wa_beta = (T *)S.wa_beta;
+    double2 *__restrict__ mom_beta = S.mom_beta;
+
+    // Hyperparameters of the previous sweep (read once).
+    const HyperState &H = *S.hyp;
+    const double nu = H.nu, tau = H.tau;
+    double th[kMaxL], s2[kMaxL];
+#pragma unroll
+    for (int l = 0; l < kMaxL; ++l) {
+        th[l] = l < L ? H.theta[l] : 0.0;
+        s2[l] = l < L ? H.sig2[l] : 1.0;
+    }
+
+    // Everything the gamma and beta steps read is requested now, so its latency
+    // hides behind the eps draws.
+    T beta[kMaxL], wb[kMaxL], wab[kMaxL];
+    double2 mob[kMaxL];
+#pragma unroll
+    for (int l = 0; l < kMaxL; ++l) {
+        const bool on = l < L && active;
+        const int64_t idx = (int64_t)l * Gp + g;
+        beta[l] = on ? betap[idx] : (T)0;
+        wb[l] = (on && upd_beta) ? w_beta[idx] : (T)1;
+        wab[l] = (on && upd_beta && tuning) ? wa_beta[idx] : (T)0;
+        mob[l] = (on && sampling) ? mom_beta[idx] : make_double2(0.0, 0.0);
+    }
+    T gam = active ? gamp[g] : (T)1;
+    T wg = (active && upd_gam) ? ((T *)S.w_gam)[g] : (T)1;
+    T wag = (active && upd_gam && tuning) ? ((T *)S.wa_gam)[g] : (T)0;
+    double2 mog = (active && sampling) ? S.mom_gam[g] : make_double2(0.0, 0.0);
     const int tslot = (tracing && active) ? S.trace_slot[g] : -1;
     float *trow = tracing ? S.trace + (int64_t)a.trace_point * S.trace_stride + 2 + 2 * L : nullptr;
-
-    T *eps = (T *)S.eps;
-    T *w_eps = (T *)S.w_eps;
-    T *wa_eps = (T *)S.wa_eps;
-    T *gamp = (T *)S.gam;
-    T *betap = (T *)S.beta;
-    T *w_beta = (T *)S.w_beta;
-    T *wa_beta = (T *)S.wa_beta;
-
-    // current beta_g and gamma_g
-    T beta[kMaxL];
-#pragma unroll
-    for (int l = 0; l < kMaxL; ++l) beta[l] = (l < L && active) ? betap[(int64_t)l * Gp + g] : (T)0;
-    T gam = active ? gamp[g] : (T)1;
 
     T A[kMaxRows], YR[kMaxRows];
 #pragma unroll
@@ -171,13 +422,28 @@ __global__ __launch_bounds__(256) void gene_sweep(const SegInfo *__restrict__ se
     int bad = 0;
 
     // ---- Algorithm 1 step 1: eps_gn, n = 1..N ----
-    const bool upd_eps = (a.mask >> 1) & 1u;
+    // Software pipeline: sample n + 1 is loaded while sample n is drawn.
     const T inv_gam = (T)1 / gam;
     if (active) {
+        int y_nx = 0;
+        T e_nx = (T)0, w_nx = (T)1, wa_nx = (T)0;
+        double2 mo_nx = make_double2(0.0, 0.0);
+        auto fetch = [&](int n) {
+            const int64_t idx = (int64_t)n * Gp + g;
+            y_nx = yp[idx];
+            e_nx = eps[idx];
+            if (upd_eps) w_nx = w_eps[idx];
+            if (upd_eps && tuning) wa_nx = wa_eps[idx];
+            if (sampling) mo_nx = mom_eps[idx];
+        };
+        fetch(0);
         for (int n = 0; n < N; ++n) {
             const int64_t idx = (int64_t)n * Gp + g;
-            const int yv = S.y[idx];
-            const T e0 = eps[idx];
+            const int yv = y_nx;
+            const T e0 = e_nx;
+            T w = w_nx, wa = wa_nx;
+            double2 mo = mo_nx;
+            if (n + 1 < N) fetch(n + 1);
             T xb = (T)0;
 #pragma unroll
             for (int l = 0; l < kMaxL; ++l)
@@ -185,14 +451,12 @@ __global__ __launch_bounds__(256) void gene_sweep(const SegInfo *__restrict__ se
             const T hn = (T)S.h[n];
             T e1 = e0;
             if (upd_eps) {
-                T w = w_eps[idx];
                 EpsF<T> f{(T)yv, dexp(hn + e0 + xb), e0, inv_gam};
                 DrawRec rec;
-                e1 = slice_draw<T>(f, e0, w, S.key0, S.key1, draw_counter((uint32_t)g, 1, (uint32_t)n, mm, chain, 0),
+                e1 = slice_draw<T>(f, e0, w, k0, k1, draw_counter((uint32_t)g, 1, (uint32_t)n, mm, chain, 0),
                                    a.K, a.cap, rec);
                 eps[idx] = e1;
                 if (tuning) {
-                    T wa = wa_eps[idx];
                     tune_width<T>(w, wa, e0, e1, a.m, a.burnin, a.tune_start);
                     w_eps[idx] = w;
                     wa_eps[idx] = wa;
@@ -201,9 +465,8 @@ __global__ __launch_bounds__(256) void gene_sweep(const SegInfo *__restrict__ se
                 if (dbg) S.dbg_eps[idx] = make_int4(rec.kl, rec.nl, rec.nr, rec.nc);
             }
             if (sampling) {
-                double2 mo = S.mom_eps[idx];
                 welford(mo, (double)e1, kmom);
-                S.mom_eps[idx] = mo;
+                mom_eps[idx] = mo;
             }
             S2 += e1 * e1;
             const T ehe = dexp(hn + e1);
@@ -217,19 +480,17 @@ __global__ __launch_bounds__(256) void gene_sweep(const SegInfo *__restrict__ se
     // ---- step 2: gamma_g ----
     double lg = 0.0, ig = 0.0;
     if (active) {
-        if ((a.mask >> 2) & 1u) {
-            const double alpha1 = 0.5 * H.nu + 0.5 * N + 1.0;
-            const double scale = 0.5 * H.nu * H.tau + 0.5 * (double)S2;
+        if (upd_gam) {
+            const double alpha1 = 0.5 * nu + 0.5 * N + 1.0;
+            const double scale = 0.5 * nu * tau + 0.5 * (double)S2;
             GamF<T> f{(T)alpha1, (T)scale, gam};
-            T w = ((T *)S.w_gam)[g];
             DrawRec rec;
-            const T g1 = slice_draw<T>(f, gam, w, S.key0, S.key1, draw_counter((uint32_t)g, 2, 0, mm, chain, 0),
+            const T g1 = slice_draw<T>(f, gam, wg, k0, k1, draw_counter((uint32_t)g, 2, 0, mm, chain, 0),
                                        a.K, a.cap, rec);
             if (tuning) {
-                T wa = ((T *)S.wa_gam)[g];
-                tune_width<T>(w, wa, gam, g1, a.m, a.burnin, a.tune_start);
-                ((T *)S.w_gam)[g] = w;
-                ((T *)S.wa_gam)[g] = wa;
+                tune_width<T>(wg, wag, gam, g1, a.m, a.burnin, a.tune_start);
+                ((T *)S.w_gam)[g] = wg;
+                ((T *)S.wa_gam)[g] = wag;
             }
             gam = g1;
             gamp[g] = g1;
@@ -237,9 +498,8 @@ __global__ __launch_bounds__(256) void gene_sweep(const SegInfo *__restrict__ se
             if (dbg) S.dbg_gam[g] = make_int4(rec.kl, rec.nl, rec.nr, rec.nc);
         }
         if (sampling) {
-            double2 mo = S.mom_gam[g];
-            welford(mo, (double)gam, kmom);
-            S.mom_gam[g] = mo;
+            welford(mog, (double)gam, kmom);
+            S.mom_gam[g] = mog;
         }
         lg = ::log((double)gam);
         ig = 1.0 / (double)gam;
@@ -253,91 +513,366 @@ __global__ __launch_bounds__(256) void gene_sweep(const SegInfo *__restrict__ se
         }
     }
 
-    // ---- step 5: beta_gl, l = 1..L in order ----
-    // C_r = sum over the samples of distinct row r of exp(h_n + eps_gn + X_r beta_g)
-    T C[kMaxRows];
-#pragma unroll
-    for (int r = 0; r < kMaxRows; ++r) {
-        T xr = (T)0;
-#pragma unroll
-        for (int l = 0; l < kMaxL; ++l)
-            if (l < L) xr += (T)S.Xrow[r * kMaxL + l] * beta[l];
-        C[r] = (r < R) ? A[r] * dexp(xr) : (T)0;
-    }
-    const bool upd_beta = (a.mask >> 5) & 1u;
-    for (int l = 0; l < L; ++l) {
-        const int64_t idx = (int64_t)l * Gp + g;
-        T b0 = (T)0;
-#pragma unroll
-        for (int j = 0; j < kMaxL; ++j)
-            if (j == l) b0 = beta[j];
-        T b1 = b0;
-        if (active && upd_beta) {
-            BetaF<T> f;
-            f.Y = (T)0;
+    if constexpr (kSplit) {
+        // split sweep: leave the row sums for the beta kernel
+        if (active) {
+            T *__restrict__ Arp = (T *)S.Ar;
 #pragma unroll
             for (int r = 0; r < kMaxRows; ++r)
-                if (r < R) f.Y += (T)S.Xrow[r * kMaxL + l] * YR[r];
-            f.nv = S.nv[l];
-#pragma unroll
-            for (int k = 0; k < kMaxVals; ++k) {
-                f.Gk[k] = (T)0;
-                f.vk[k] = (T)S.vals[l * kMaxVals + k];
-                f.em1[k] = (T)0;
-            }
-#pragma unroll
-            for (int r = 0; r < kMaxRows; ++r) {
-                const int k = S.xidx[r * kMaxL + l];
-#pragma unroll
-                for (int kk = 0; kk < kMaxVals; ++kk)
-                    if (r < R && k == kk) f.Gk[kk] += C[r];
-            }
-            const double th = H.theta[l], s2 = H.sig2[l];
-            f.x0 = b0;
-            f.dth = (T)((double)b0 - th);
-            f.inv_s2 = (T)(1.0 / s2);
-            T w = w_beta[idx];
-            DrawRec rec;
-            b1 = slice_draw<T>(f, b0, w, S.key0, S.key1, draw_counter((uint32_t)g, 5, (uint32_t)l, mm, chain, 0),
-                               a.K, a.cap, rec);
-            if (tuning) {
-                T wa = wa_beta[idx];
-                tune_width<T>(w, wa, b0, b1, a.m, a.burnin, a.tune_start);
-                w_beta[idx] = w;
-                wa_beta[idx] = wa;
-            }
-            betap[idx] = b1;
-            bad |= rec.bad;
-            if (dbg) S.dbg_beta[idx] = make_int4(rec.kl, rec.nl, rec.nr, rec.nc);
-            // move the row sums to the new beta_gl: C_r *= exp(X_rl (b1 - b0))
-            T fac[kMaxVals];
-#pragma unroll
-            for (int k = 0; k < kMaxVals; ++k) fac[k] = rec.bad ? (T)1 : (T)1 + f.em1[k];
-#pragma unroll
-            for (int r = 0; r < kMaxRows; ++r) {
-                const int k = S.xidx[r * kMaxL + l];
-#pragma unroll
-                for (int kk = 0; kk < kMaxVals; ++kk)
-                    if (r < R && k == kk) C[r] *= fac[kk];
-            }
-#pragma unroll
-            for (int j = 0; j < kMaxL; ++j)
-                if (j == l) beta[j] = b1;
+                if (r < R) Arp[(int64_t)r * Gp + g] = A[r];
         }
-        if (active && sampling) {
-            double2 mo = S.mom_beta[idx];
-            welford(mo, (double)b1, kmom);
-            S.mom_beta[idx] = mo;
-        }
-        if (tslot >= 0) trow[(int64_t)tslot * (L + 1) + 1 + l] = (float)b1;
-        const double dv = active ? (double)b1 - H.theta[l] : 0.0;
-        const double s0 = wave_sum(dv), s1 = wave_sum(dv * dv);
-        if (lane == 0) {
-            S.partials[(int64_t)tile * kMaxParts + 2 + 2 * l] = s0;
-            S.partials[(int64_t)tile * kMaxParts + 3 + 2 * l] = s1;
+        if (bad) raise_flag(err, 2);
+        return;
+    }
+
+    // ---- step 5: beta_gl, l = 1..L in order ----
+    T C[kMaxRows];
+    row_sums_at_beta<T>(S, A, beta, C);
+    if (active && upd_beta)
+        beta_slice_draws<T>(S, a, g, Gp, beta, wb, wab, th, s2, C, YR, tuning, bad);
+    beta_finish<T>(S, a, g, Gp, active, beta, mob, th, tile, lane, tslot, trow, sampling, kmom);
+    if (bad) raise_flag(err, 2);
+}
+
+// ---------------------------------------------------------------------------
+// Beta kernel of the split sweep: independence MH with the learned proposal
+// where the fallback mask is 0, slice draws elsewhere
+// ---------------------------------------------------------------------------
+template <typename T>
+__global__ __launch_bounds__(256) void beta_sweep(const SegInfo *__restrict__ segs,
+                                                  const int2 *__restrict__ tiles, int ntiles,
+                                                  SweepArgs a, int *err)
+{
+    const int wave = __builtin_amdgcn_readfirstlane((int)(threadIdx.x >> 6));
+    const int lane = (int)(threadIdx.x & 63);
+    const int tix = (int)blockIdx.x * 4 + wave;
+    if (tix >= ntiles) return;
+    const int2 tt = tiles[tix];
+    const int sidx = __builtin_amdgcn_readfirstlane(tt.x);
+    const int tile = __builtin_amdgcn_readfirstlane(tt.y);
+    const SegInfo &S = segs[sidx];
+    const int64_t Gp = S.Gp;
+    const int64_t g = (int64_t)tile * kTile + lane;
+    const bool active = g < S.G;
+    const int L = S.L, R = S.R;
+    const bool tuning = a.m <= a.burnin;
+    const bool sampling = a.m > a.burnin;
+    const double kmom = (double)(a.m - a.burnin);
+    const bool tracing = a.trace_point >= 0;
+    const bool upd_beta = (a.mask >> 5) & 1u;
+    const HyperState &H = *S.hyp;
+    double th[kMaxL], s2[kMaxL];
+#pragma unroll
+    for (int l = 0; l < kMaxL; ++l) {
+        th[l] = l < L ? H.theta[l] : 0.0;
+        s2[l] = l < L ? H.sig2[l] : 1.0;
+    }
+    T beta[kMaxL], wb[kMaxL], wab[kMaxL];
+    double2 mob[kMaxL];
+#pragma unroll
+    for (int l = 0; l < kMaxL; ++l) {
+        const bool on = l < L && active;
+        const int64_t idx = (int64_t)l * Gp + g;
+        beta[l] = on ? ((T *)S.beta)[idx] : (T)0;
+        wb[l] = (on && upd_beta) ? ((T *)S.w_beta)[idx] : (T)1;
+        wab[l] = (on && upd_beta && tuning) ? ((T *)S.wa_beta)[idx] : (T)0;
+        mob[l] = (on && sampling) ? S.mom_beta[idx] : make_double2(0.0, 0.0);
+    }
+    T A[kMaxRows], YR[kMaxRows];
+#pragma unroll
+    for (int r = 0; r < kMaxRows; ++r) {
+        const bool on = r < R && active;
+        A[r] = on ? ((const T *)S.Ar)[(int64_t)r * Gp + g] : (T)0;
+        YR[r] = on ? ((const T *)S.YR)[(int64_t)r * Gp + g] : (T)0;
+    }
+    const int tslot = (tracing && active) ? S.trace_slot[g] : -1;
+    float *trow = tracing ? S.trace + (int64_t)a.trace_point * S.trace_stride + 2 + 2 * L : nullptr;
+    // training pairs: the features the beta step saw, then the new beta
+    float *pair = (a.pair_base >= 0 && active) ? S.pairs + (a.pair_base + g) * kPairStride : nullptr;
+    if (pair) {
+        float phi[32];
+        gene_features<T>(S, A, YR, th, s2, phi);
+#pragma unroll
+        for (int k = 0; k < 32; ++k) pair[k] = phi[k];
+    }
+    T C[kMaxRows];
+    row_sums_at_beta<T>(S, A, beta, C);
+    int bad = 0;
+    if (active && upd_beta) {
+        const bool use_imh = a.learned && S.fallback[g] == 0;
+        if (use_imh) {
+            const int acc = beta_imh_draw<T>(S, a, g, Gp, beta, th, s2, C, YR);
+            S.imh_last[g] = acc;
+            if (a.count_imh) S.imh_count[g] += acc;
+        } else {
+            beta_slice_draws<T>(S, a, g, Gp, beta, wb, wab, th, s2, C, YR, tuning, bad);
+            S.imh_last[g] = -1;
         }
     }
+    if (pair) {
+#pragma unroll
+        for (int l = 0; l < kMaxL; ++l)
+            if (l < L) pair[32 + l] = (float)beta[l];
+    }
+    beta_finish<T>(S, a, g, Gp, active, beta, mob, th, tile, lane, tslot, trow, sampling, kmom);
     if (bad) raise_flag(err, 2);
+}
+
+// ---------------------------------------------------------------------------
+// Proposal network inference: one wavefront per 64-gene tile.  Features are
+// standardised, rounded to BF16 and stored row per gene in LDS; each layer is
+// 2 x (N / 32) output tiles of v_mfma_f32_32x32x16_bf16 whose A fragments are
+// read from the previous layer's LDS rows and whose B fragments are the packed
+// weights; bias and GELU are applied to the accumulators and the result is
+// written back to LDS as BF16 rows for the next layer.
+// ---------------------------------------------------------------------------
+constexpr int kXs = kMlpF + 8;     // LDS row strides (elements), padded against bank conflicts
+constexpr int kHs = kMlpH + 8;
+constexpr int kOs = kMlpO + 1;
+
+template <int K, int N, bool kGelu>
+__device__ inline void mlp_layer(const __bf16 *__restrict__ in, int in_stride, const __bf16 *__restrict__ Wp,
+                                 const float *__restrict__ bias, __bf16 *out_bf, float *out_f, int out_stride)
+{
+    const int lane = (int)(threadIdx.x & 63);
+    const int i = lane & 31, h = lane >> 5;
+    constexpr int nct = N / 32, nks = K / 16;
+#pragma unroll
+    for (int rt = 0; rt < 2; ++rt) {
+#pragma unroll
+        for (int ct = 0; ct < nct; ++ct) {
+            floatx16 acc = {};
+#pragma unroll
+            for (int ks = 0; ks < nks; ++ks) {
+                const bf16x8 av = *reinterpret_cast<const bf16x8 *>(in + (rt * 32 + i) * in_stride + ks * 16 + 8 * h);
+                const bf16x8 bv = *reinterpret_cast<const bf16x8 *>(Wp + ((ks * nct + ct) * 64 + lane) * 8);
+                acc = __builtin_amdgcn_mfma_f32_32x32x16_bf16(av, bv, acc, 0, 0, 0);
+            }
+            const float bb = bias[ct * 32 + i];
+#pragma unroll
+            for (int r = 0; r < 16; ++r) {
+                const int row = rt * 32 + 8 * (r >> 2) + 4 * h + (r & 3);
+                float v = acc[r] + bb;
+                if constexpr (kGelu) {
+                    v = 0.5f * v * (1.0f + erff(v * 0.70710678118654752f));
+                    out_bf[row * out_stride + ct * 32 + i] = (__bf16)v;
+                } else {
+                    out_f[row * out_stride + ct * 32 + i] = v;
+                }
+            }
+        }
+    }
+}
+
+// The network on the 64 feature rows a wavefront holds (phi of lane = row);
+// writes mu and ls of the lane's row.  All 64 lanes call.
+__device__ inline void mlp_rows(const float (&phi)[32], bool active, const MlpDev *__restrict__ net, int L,
+                                float (&mu)[kMaxL], float (&ls)[kMaxL])
+{
+    __shared__ __attribute__((aligned(16))) __bf16 xs[64 * kXs];
+    __shared__ __attribute__((aligned(16))) __bf16 h1[64 * kHs];
+    __shared__ __attribute__((aligned(16))) __bf16 h2[64 * kHs];
+    __shared__ float os[64 * kOs];
+    const int lane = (int)(threadIdx.x & 63);
+#pragma unroll
+    for (int k = 0; k < kMlpF; ++k) {
+        const float x = active ? (phi[k] - net->fmean[k]) * net->fscale[k] : 0.0f;
+        xs[lane * kXs + k] = (__bf16)x;
+    }
+    __syncthreads();
+    mlp_layer<kMlpF, kMlpH, true>(xs, kXs, net->W1p, net->b1, h1, nullptr, kHs);
+    __syncthreads();
+    mlp_layer<kMlpH, kMlpH, true>(h1, kHs, net->W2p, net->b2, h2, nullptr, kHs);
+    __syncthreads();
+    mlp_layer<kMlpH, kMlpO, false>(h2, kHs, net->W3p, net->b3, nullptr, os, kOs);
+    __syncthreads();
+#pragma unroll
+    for (int l = 0; l < kMaxL; ++l) {
+        mu[l] = 0.0f;
+        ls[l] = 0.0f;
+        if (l < L) {
+            mu[l] = net->omean[l] + net->oscale[l] * os[lane * kOs + l];
+            ls[l] = ::logf(net->oscale[l]) + os[lane * kOs + L + l];
+        }
+    }
+}
+
+template <typename T>
+__global__ __launch_bounds__(64) void feat_mlp(const SegInfo *__restrict__ segs, const int2 *__restrict__ tiles,
+                                               int ntiles, const MlpDev *__restrict__ net)
+{
+    const int lane = (int)threadIdx.x;
+    const int tix = (int)blockIdx.x;
+    if (tix >= ntiles) return;
+    const int2 tt = tiles[tix];
+    const int sidx = __builtin_amdgcn_readfirstlane(tt.x);
+    const int tile = __builtin_amdgcn_readfirstlane(tt.y);
+    const SegInfo &S = segs[sidx];
+    const int64_t Gp = S.Gp;
+    const int64_t g = (int64_t)tile * kTile + lane;
+    const bool active = g < S.G;
+    const int L = S.L, R = S.R;
+    const HyperState &H = *S.hyp;
+    double th[kMaxL], s2[kMaxL];
+#pragma unroll
+    for (int l = 0; l < kMaxL; ++l) {
+        th[l] = l < L ? H.theta[l] : 0.0;
+        s2[l] = l < L ? H.sig2[l] : 1.0;
+    }
+    T A[kMaxRows], YR[kMaxRows];
+#pragma unroll
+    for (int r = 0; r < kMaxRows; ++r) {
+        const bool on = r < R && active;
+        A[r] = on ? ((const T *)S.Ar)[(int64_t)r * Gp + g] : (T)1;
+        YR[r] = on ? ((const T *)S.YR)[(int64_t)r * Gp + g] : (T)0;
+    }
+    float phi[32], mu[kMaxL], ls[kMaxL];
+    gene_features<T>(S, A, YR, th, s2, phi);
+    mlp_rows(phi, active, net, L, mu, ls);
+    if (active) {
+        for (int l = 0; l < L; ++l) {
+            float m = 0.0f, v = 0.0f;
+#pragma unroll
+            for (int j = 0; j < kMaxL; ++j)
+                if (j == l) { m = mu[j]; v = ls[j]; }
+            S.mlp_out[(int64_t)l * Gp + g] = m;
+            S.mlp_out[(int64_t)(L + l) * Gp + g] = v;
+        }
+    }
+}
+
+// The network on raw feature rows phi [B][32] (tests): mu, ls [B][L].
+__global__ __launch_bounds__(64) void mlp_infer_raw(const float *__restrict__ phi, int64_t B, int L,
+                                                    const MlpDev *__restrict__ net, float *mu_out, float *ls_out)
+{
+    const int lane = (int)threadIdx.x;
+    const int64_t b = (int64_t)blockIdx.x * 64 + lane;
+    const bool active = b < B;
+    float phi_r[32], mu[kMaxL], ls[kMaxL];
+#pragma unroll
+    for (int k = 0; k < 32; ++k) phi_r[k] = active ? phi[b * 32 + k] : 0.0f;
+    mlp_rows(phi_r, active, net, L, mu, ls);
+    if (active)
+        for (int l = 0; l < L; ++l) {
+            float m = 0.0f, v = 0.0f;
+#pragma unroll
+            for (int j = 0; j < kMaxL; ++j)
+                if (j == l) { m = mu[j]; v = ls[j]; }
+            mu_out[b * L + l] = m;
+            ls_out[b * L + l] = v;
+        }
+}
+
+// Features of every gene from the current state (tests): A_r and Y_r summed
+// from eps and y, theta and sigma^2 from the hyperparameter state.
+template <typename T>
+__global__ void features_kernel(const SegInfo *__restrict__ seg, float *__restrict__ out)
+{
+    const SegInfo &S = *seg;
+    const int64_t g = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (g >= S.G) return;
+    const int N = S.N, L = S.L, R = S.R;
+    T A[kMaxRows], YR[kMaxRows];
+#pragma unroll
+    for (int r = 0; r < kMaxRows; ++r) { A[r] = (T)0; YR[r] = (T)0; }
+    for (int n = 0; n < N; ++n) {
+        const int64_t idx = (int64_t)n * S.Gp + g;
+        const T e = dexp((T)S.h[n] + ((const T *)S.eps)[idx]);
+        const T y = (T)S.y[idx];
+        const int rr = S.row_of[n];
+#pragma unroll
+        for (int r = 0; r < kMaxRows; ++r)
+            if (r == rr) { A[r] += e; YR[r] += y; }
+    }
+    double th[kMaxL], s2[kMaxL];
+#pragma unroll
+    for (int l = 0; l < kMaxL; ++l) {
+        th[l] = l < L ? S.hyp->theta[l] : 0.0;
+        s2[l] = l < L ? S.hyp->sig2[l] : 1.0;
+    }
+    float phi[32];
+    gene_features<T>(S, A, YR, th, s2, phi);
+    for (int k = 0; k < 32; ++k) out[g * 32 + k] = phi[k];
+    (void)R;
+}
+
+// Minibatch gather: row i takes pair (Philox word of (i, step, epoch)) mod P,
+// standardises its features and copies its targets.
+__global__ void gather_pairs(const float *__restrict__ pairs, int64_t P, int L, const float *__restrict__ master,
+                             float *X, float *Tg, int B, uint32_t epoch, uint32_t step, uint32_t k0, uint32_t k1)
+{
+    const int i = (int)(blockIdx.x * blockDim.x + threadIdx.x);
+    if (i >= B) return;
+    const uint4 r = philox4x32_10(make_uint4((uint32_t)i, step, epoch, 0xB0u), k0, k1);
+    const int64_t p = (int64_t)(((uint64_t)r.x << 32 | r.y) % (uint64_t)P);
+    const float *row = pairs + p * kPairStride;
+    for (int k = 0; k < kMlpF; ++k) X[(int64_t)i * kMlpF + k] = (row[k] - master[kOffFmean + k]) * master[kOffFscale + k];
+    for (int l = 0; l < L; ++l) Tg[(int64_t)i * L + l] = row[32 + l];
+}
+
+// Column sums and sums of squares (FP64) of a row-major [rows][cols] float array.
+__global__ void col_moments(const float *__restrict__ M, int64_t rows, int cols, double *out)
+{
+    const int c = (int)blockIdx.x;
+    double s = 0.0, q = 0.0;
+    for (int64_t r = threadIdx.x; r < rows; r += blockDim.x) {
+        const double v = M[r * cols + c];
+        s += v;
+        q += v * v;
+    }
+    __shared__ double sh[2][256];
+    sh[0][threadIdx.x] = s;
+    sh[1][threadIdx.x] = q;
+    __syncthreads();
+    for (int st = 128; st > 0; st >>= 1) {
+        if ((int)threadIdx.x < st) {
+            sh[0][threadIdx.x] += sh[0][threadIdx.x + st];
+            sh[1][threadIdx.x] += sh[1][threadIdx.x + st];
+        }
+        __syncthreads();
+    }
+    if (threadIdx.x == 0) { out[2 * c] = sh[0][0]; out[2 * c + 1] = sh[1][0]; }
+}
+
+hipError_t launch_mlp_infer_raw(const float *phi, int64_t B, int L, const MlpDev *net, float *mu, float *ls,
+                                hipStream_t st)
+{
+    if (B <= 0) return hipSuccess;
+    hipLaunchKernelGGL(mlp_infer_raw, dim3((unsigned)((B + 63) / 64)), dim3(64), 0, st, phi, B, L, net, mu, ls);
+    return hipGetLastError();
+}
+
+hipError_t launch_features(int precision, const SegInfo *seg, int64_t G, float *out, hipStream_t st)
+{
+    const unsigned blocks = (unsigned)((G + 255) / 256);
+    if (precision == 0) hipLaunchKernelGGL((features_kernel<double>), dim3(blocks), dim3(256), 0, st, seg, out);
+    else hipLaunchKernelGGL((features_kernel<float>), dim3(blocks), dim3(256), 0, st, seg, out);
+    return hipGetLastError();
+}
+
+hipError_t launch_gather_pairs(const float *pairs, int64_t P, int L, const float *master, float *X, float *Tg,
+                               int B, uint32_t epoch, uint32_t step, uint32_t k0, uint32_t k1, hipStream_t st)
+{
+    hipLaunchKernelGGL(gather_pairs, dim3((B + 255) / 256), dim3(256), 0, st, pairs, P, L, master, X, Tg, B,
+                       epoch, step, k0, k1);
+    return hipGetLastError();
+}
+
+hipError_t launch_col_moments(const float *M, int64_t rows, int cols, double *out, hipStream_t st)
+{
+    hipLaunchKernelGGL(col_moments, dim3(cols), dim3(256), 0, st, M, rows, cols, out);
+    return hipGetLastError();
+}
+
+hipError_t launch_feat_mlp(int precision, const SegInfo *segs, const int2 *tiles, int ntiles, const MlpDev *net,
+                           hipStream_t st)
+{
+    if (ntiles == 0) return hipSuccess;
+    if (precision == 0)
+        hipLaunchKernelGGL((feat_mlp<double>), dim3(ntiles), dim3(64), 0, st, segs, tiles, ntiles, net);
+    else
+        hipLaunchKernelGGL((feat_mlp<float>), dim3(ntiles), dim3(64), 0, st, segs, tiles, ntiles, net);
+    return hipGetLastError();
 }
 
 // ---------------------------------------------------------------------------
@@ -347,12 +882,19 @@ __global__ __launch_bounds__(256) void hyper_sweep(const SegInfo *__restrict__ s
                                                    int *err)
 {
     const SegInfo &S = segs[blockIdx.x];
-    HyperState &H = *S.hyp;
     const int L = S.L;
     const int nparts = 2 + 2 * L;
     const int tid = (int)threadIdx.x;
     const int lane = tid & 63, wave = tid >> 6;
     __shared__ double part[4][kMaxParts];
+    // The whole hyperparameter state is staged in LDS: the draws below are a
+    // short serial chain, and LDS keeps each dependent access at LDS latency.
+    __shared__ HyperState H;
+    constexpr int kWords = (int)(sizeof(HyperState) / sizeof(double));
+    static_assert(sizeof(HyperState) % sizeof(double) == 0, "HyperState must be whole doubles");
+    double *hs = reinterpret_cast<double *>(&H);
+    const double *hg = reinterpret_cast<const double *>(S.hyp);
+    for (int i = tid; i < kWords; i += 256) hs[i] = hg[i];
 
     // Fixed-order reduction: thread t sums tiles t, t + 256, ... in order, then a
     // butterfly inside each wavefront, then the four wavefronts in order.
@@ -370,91 +912,109 @@ __global__ __launch_bounds__(256) void hyper_sweep(const SegInfo *__restrict__ s
         if (lane == 0) part[wave][j] = v;
     }
     __syncthreads();
-    if (tid != 0) return;
 
-    double red[kMaxParts];
-    for (int j = 0; j < nparts; ++j) red[j] = ((part[0][j] + part[1][j]) + part[2][j]) + part[3][j];
+    // The draws: wavefront 0, every lane computing the same values; the slice
+    // draws evaluate their points across the lanes (slice_draw_wave).
+    __shared__ double words[64];
+    if (wave == 0) {
+        double red[kMaxParts];
+        for (int j = 0; j < nparts; ++j) red[j] = ((part[0][j] + part[1][j]) + part[2][j]) + part[3][j];
+        const double G = (double)S.G;
+        const double pa = S.a, pb = S.b, pd = S.d;
+        const uint32_t k0 = S.key0, k1 = S.key1;
+        const uint32_t mm = (uint32_t)a.m;
+        const uint32_t chain = (uint32_t)S.chain;
+        const bool sampling = a.m > a.burnin;
+        const double kmom = (double)(a.m - a.burnin);
+        const bool w0 = lane == 0;
+        int bad = 0;
+        DrawRec rec;
+        double nu = H.nu, tau = H.tau;
 
-    const double G = (double)S.G;
-    const uint32_t mm = (uint32_t)a.m;
-    const uint32_t chain = (uint32_t)S.chain;
-    const bool tuning = a.m <= a.burnin;
-    const bool sampling = a.m > a.burnin;
-    const double kmom = (double)(a.m - a.burnin);
-    int bad = 0;
-    DrawRec rec;
-
-    // step 3: nu
-    if ((a.mask >> 3) & 1u) {
-        NuF f{G, H.tau, red[0], red[1], S.d};
-        const double x0 = H.nu;
-        const double x1 = slice_draw<double>(f, x0, H.w_nu, S.key0, S.key1, draw_counter(0, 3, 0, mm, chain, 0),
-                                             a.K, a.cap, rec);
-        tune_width<double>(H.w_nu, H.wa_nu, x0, x1, a.m, a.burnin, a.tune_start);
-        H.nu = x1;
-        bad |= rec.bad;
-        if (a.dbg) H.dbg[0] = make_int4(rec.kl, rec.nl, rec.nr, rec.nc);
-    }
-    // step 4: tau
-    if ((a.mask >> 4) & 1u) {
-        TauF f{S.a + 0.5 * G * H.nu - 1.0, S.b + 0.5 * H.nu * red[1]};
-        const double x0 = H.tau;
-        const double x1 = slice_draw<double>(f, x0, H.w_tau, S.key0, S.key1, draw_counter(0, 4, 0, mm, chain, 0),
-                                             a.K, a.cap, rec);
-        tune_width<double>(H.w_tau, H.wa_tau, x0, x1, a.m, a.burnin, a.tune_start);
-        H.tau = x1;
-        bad |= rec.bad;
-        if (a.dbg) H.dbg[1] = make_int4(rec.kl, rec.nl, rec.nr, rec.nc);
-    }
-    // steps 6 and 7: theta_l then sigma_l^2.  The partials are sums of
-    // (beta - s) and (beta - s)^2 with the shift s = theta_l before this step.
-    for (int l = 0; l < L; ++l) {
-        const double s = H.theta[l];
-        const double d1 = red[2 + 2 * l], d2 = red[3 + 2 * l];
-        const double sb = d1 + G * s;
-        if ((a.mask >> 6) & 1u) {
-            const double prec = G / H.sig2[l] + 1.0 / (S.c[l] * S.c[l]);
-            const double mean = (sb / H.sig2[l]) / prec;
-            const uint4 r = philox4x32_10(draw_counter(0, 6, (uint32_t)l, mm, chain, 0), S.key0, S.key1);
-            const double zn = ::sqrt(-2.0 * ::log(u01<double>(r.x))) *
-                              ::cos(6.283185307179586 * u01<double>(r.y));
-            H.theta[l] = mean + zn / ::sqrt(prec);
-        }
-        const double dt = H.theta[l] - s;
-        const double Ssq = d2 - 2.0 * dt * d1 + G * dt * dt;
-        red[2 + 2 * l] = sb;
-        red[3 + 2 * l] = Ssq;
-        if ((a.mask >> 7) & 1u) {
-            Sig2F f{0.5 * (G + 1.0), Ssq, S.s[l] * S.s[l]};
-            const double x0 = H.sig2[l];
-            const double x1 = slice_draw<double>(f, x0, H.w_sig2[l], S.key0, S.key1,
-                                                 draw_counter(0, 7, (uint32_t)l, mm, chain, 0), a.K, a.cap, rec);
-            tune_width<double>(H.w_sig2[l], H.wa_sig2[l], x0, x1, a.m, a.burnin, a.tune_start);
-            H.sig2[l] = x1;
+        // step 3: nu
+        if ((a.mask >> 3) & 1u) {
+            NuF f{G, tau, red[0], red[1], pd};
+            double w = H.w_nu, wa = H.wa_nu;
+            const double x1 = slice_draw_wave(f, nu, w, k0, k1, draw_counter(0, 3, 0, mm, chain, 0), a.K,
+                                              a.cap, rec, words);
+            tune_width<double>(w, wa, nu, x1, a.m, a.burnin, a.tune_start);
+            nu = x1;
+            if (w0) { H.nu = x1; H.w_nu = w; H.wa_nu = wa; }
             bad |= rec.bad;
-            if (a.dbg) H.dbg[2 + l] = make_int4(rec.kl, rec.nl, rec.nr, rec.nc);
+            if (a.dbg && w0) H.dbg[0] = make_int4(rec.kl, rec.nl, rec.nr, rec.nc);
         }
-    }
-    for (int j = 0; j < nparts; ++j) H.red[j] = red[j];
-    if (sampling) {
-        welford(H.mom[0], H.nu, kmom);
-        welford(H.mom[1], H.tau, kmom);
+        // step 4: tau
+        if ((a.mask >> 4) & 1u) {
+            TauF f{pa + 0.5 * G * nu - 1.0, pb + 0.5 * nu * red[1]};
+            double w = H.w_tau, wa = H.wa_tau;
+            const double x1 = slice_draw_wave(f, tau, w, k0, k1, draw_counter(0, 4, 0, mm, chain, 0), a.K,
+                                              a.cap, rec, words);
+            tune_width<double>(w, wa, tau, x1, a.m, a.burnin, a.tune_start);
+            tau = x1;
+            if (w0) { H.tau = x1; H.w_tau = w; H.wa_tau = wa; }
+            bad |= rec.bad;
+            if (a.dbg && w0) H.dbg[1] = make_int4(rec.kl, rec.nl, rec.nr, rec.nc);
+        }
+        // steps 6 and 7: theta_l then sigma_l^2.  The partials are sums of
+        // (beta - s) and (beta - s)^2 with the shift s = theta_l before this step.
         for (int l = 0; l < L; ++l) {
-            welford(H.mom[2 + l], H.theta[l], kmom);
-            welford(H.mom[2 + L + l], H.sig2[l], kmom);
+            const double s = H.theta[l];
+            const double d1 = red[2 + 2 * l], d2 = red[3 + 2 * l];
+            const double sb = d1 + G * s;
+            const double sig2 = H.sig2[l];
+            double th = s;
+            if ((a.mask >> 6) & 1u) {
+                const double cl = S.c[l];
+                const double prec = G / sig2 + 1.0 / (cl * cl);
+                const double mean = (sb / sig2) / prec;
+                const uint4 r = philox4x32_10(draw_counter(0, 6, (uint32_t)l, mm, chain, 0), k0, k1);
+                const double zn = ::sqrt(-2.0 * ::log(u01<double>(r.x))) *
+                                  ::cos(6.283185307179586 * u01<double>(r.y));
+                th = mean + zn / ::sqrt(prec);
+            }
+            const double dt = th - s;
+            const double Ssq = d2 - 2.0 * dt * d1 + G * dt * dt;
+            red[2 + 2 * l] = sb;
+            red[3 + 2 * l] = Ssq;
+            double s2new = sig2;
+            double w = H.w_sig2[l], wa = H.wa_sig2[l];
+            if ((a.mask >> 7) & 1u) {
+                const double sl = S.s[l];
+                Sig2F f{0.5 * (G + 1.0), Ssq, sl * sl};
+                s2new = slice_draw_wave(f, sig2, w, k0, k1, draw_counter(0, 7, (uint32_t)l, mm, chain, 0), a.K,
+                                        a.cap, rec, words);
+                tune_width<double>(w, wa, sig2, s2new, a.m, a.burnin, a.tune_start);
+                bad |= rec.bad;
+                if (a.dbg && w0) H.dbg[2 + l] = make_int4(rec.kl, rec.nl, rec.nr, rec.nc);
+            }
+            if (w0) { H.theta[l] = th; H.sig2[l] = s2new; H.w_sig2[l] = w; H.wa_sig2[l] = wa; }
+            if (sampling && w0) {
+                welford(H.mom[2 + l], th, kmom);
+                welford(H.mom[2 + L + l], s2new, kmom);
+            }
+            if (a.trace_point >= 0 && w0) {
+                float *row = S.trace + (int64_t)a.trace_point * S.trace_stride;
+                row[2 + l] = (float)th;
+                row[2 + L + l] = (float)s2new;
+            }
+        }
+        if (w0) {
+            for (int j = 0; j < nparts; ++j) H.red[j] = red[j];
+            if (sampling) {
+                welford(H.mom[0], nu, kmom);
+                welford(H.mom[1], tau, kmom);
+            }
+            if (a.trace_point >= 0) {
+                float *row = S.trace + (int64_t)a.trace_point * S.trace_stride;
+                row[0] = (float)nu;
+                row[1] = (float)tau;
+            }
+            if (bad) raise_flag(err, 2);
         }
     }
-    if (a.trace_point >= 0) {
-        float *row = S.trace + (int64_t)a.trace_point * S.trace_stride;
-        row[0] = (float)H.nu;
-        row[1] = (float)H.tau;
-        for (int l = 0; l < L; ++l) {
-            row[2 + l] = (float)H.theta[l];
-            row[2 + L + l] = (float)H.sig2[l];
-        }
-    }
-    if (bad) raise_flag(err, 2);
-    (void)tuning;
+    __syncthreads();
+    double *hw = reinterpret_cast<double *>(S.hyp);
+    for (int i = tid; i < kWords; i += 256) hw[i] = hs[i];
 }
 
 __global__ void philox_kernel(const uint4 *ctr, const uint2 *key, uint4 *out, int64_t n)
@@ -472,9 +1032,33 @@ hipError_t launch_gene(int precision, const SegInfo *segs, const int2 *tiles, in
     const int blocks = (ntiles + 3) / 4;
     if (blocks == 0) return hipSuccess;
     if (precision == 0)
-        hipLaunchKernelGGL(gene_sweep<double>, dim3(blocks), dim3(256), 0, st, segs, tiles, ntiles, a, err);
+        hipLaunchKernelGGL((gene_sweep<double, false>), dim3(blocks), dim3(256), 0, st, segs, tiles, ntiles, a, err);
     else
-        hipLaunchKernelGGL(gene_sweep<float>, dim3(blocks), dim3(256), 0, st, segs, tiles, ntiles, a, err);
+        hipLaunchKernelGGL((gene_sweep<float, false>), dim3(blocks), dim3(256), 0, st, segs, tiles, ntiles, a, err);
+    return hipGetLastError();
+}
+
+hipError_t launch_split(int precision, const SegInfo *segs, const int2 *tiles, int ntiles,
+                        const SweepArgs &a, int *err, hipStream_t st)
+{
+    const int blocks = (ntiles + 3) / 4;
+    if (blocks == 0) return hipSuccess;
+    if (precision == 0)
+        hipLaunchKernelGGL((gene_sweep<double, true>), dim3(blocks), dim3(256), 0, st, segs, tiles, ntiles, a, err);
+    else
+        hipLaunchKernelGGL((gene_sweep<float, true>), dim3(blocks), dim3(256), 0, st, segs, tiles, ntiles, a, err);
+    return hipGetLastError();
+}
+
+hipError_t launch_beta(int precision, const SegInfo *segs, const int2 *tiles, int ntiles,
+                       const SweepArgs &a, int *err, hipStream_t st)
+{
+    const int blocks = (ntiles + 3) / 4;
+    if (blocks == 0) return hipSuccess;
+    if (precision == 0)
+        hipLaunchKernelGGL((beta_sweep<double>), dim3(blocks), dim3(256), 0, st, segs, tiles, ntiles, a, err);
+    else
+        hipLaunchKernelGGL((beta_sweep<float>), dim3(blocks), dim3(256), 0, st, segs, tiles, ntiles, a, err);
     return hipGetLastError();
 }
 

@@ -1,0 +1,172 @@
+// fbmc_mlp.hip -- the learned beta proposal's network on gfx950 matrix cores.
+//
+// The network maps a gene's 32 features to (mu_l, log s_l), l = 1..L, with two
+// 128-wide GELU layers (F = 32 -> H = 128 -> H = 128 -> O = 16 padded outputs).
+// Products use v_mfma_f32_32x32x16_bf16: BF16 operands, FP32 accumulation.
+// Weights and activations live in FP32; a fragment is rounded to BF16 as it is
+// loaded into the matrix core.
+//
+// 32x32x16 operand layout (wavefront of 64 lanes, lane = 32 h + i):
+//   A (32 x 16): lane holds A[i][8 h + j], j = 0..7
+//   B (16 x 32): lane holds B[8 h + j][i], j = 0..7
+//   C (32 x 32): lane holds C[8 (r / 4) + 4 h + (r % 4)][i], r = 0..15
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+#include "fbmc_mlp.hpp"
+
+namespace fbmc {
+
+__device__ inline bf16x8 to_bf16x8(const float *v)
+{
+    bf16x8 r;
+#pragma unroll
+    for (int j = 0; j < 8; ++j) r[j] = (__bf16)v[j];
+    return r;
+}
+
+// One MFMA on explicit operands: used to check the lane layout on the device.
+__global__ void mfma_probe(const float *A, const float *B, float *C)
+{
+    const int lane = (int)threadIdx.x;
+    const int i = lane & 31, h = lane >> 5;
+    float a[8], b[8];
+#pragma unroll
+    for (int j = 0; j < 8; ++j) {
+        a[j] = A[i * 16 + 8 * h + j];      // A is 32 x 16 row-major
+        b[j] = B[(8 * h + j) * 32 + i];    // B is 16 x 32 row-major
+    }
+    floatx16 acc = {};
+    acc = __builtin_amdgcn_mfma_f32_32x32x16_bf16(to_bf16x8(a), to_bf16x8(b), acc, 0, 0, 0);
+#pragma unroll
+    for (int r = 0; r < 16; ++r) C[(8 * (r >> 2) + 4 * h + (r & 3)) * 32 + i] = acc[r];
+}
+
+// C[M][N] = (accumulate ? C : 0) + op(A) op(B), op(A) is M x K, op(B) is K x N.
+// A is [M][lda] (or [K][lda] read transposed when tA), B is [K][ldb] (or [N][ldb]
+// when tB).  M, N multiples of 32 and K a multiple of 16; one wavefront per
+// 32 x 32 tile of C.
+__global__ __launch_bounds__(64) void gemm_bf16(const float *__restrict__ A, int lda, int tA,
+                                                const float *__restrict__ B, int ldb, int tB,
+                                                float *__restrict__ C, int ldc, int M, int N, int K,
+                                                int accumulate)
+{
+    const int tilesN = N / 32;
+    const int m0 = (int)(blockIdx.x / tilesN) * 32, n0 = (int)(blockIdx.x % tilesN) * 32;
+    if (m0 >= M) return;
+    const int lane = (int)threadIdx.x;
+    const int i = lane & 31, h = lane >> 5;
+    floatx16 acc = {};
+    for (int k0 = 0; k0 < K; k0 += 16) {
+        float a[8], b[8];
+#pragma unroll
+        for (int j = 0; j < 8; ++j) {
+            const int k = k0 + 8 * h + j;
+            a[j] = tA ? A[(int64_t)k * lda + m0 + i] : A[(int64_t)(m0 + i) * lda + k];
+            b[j] = tB ? B[(int64_t)(n0 + i) * ldb + k] : B[(int64_t)k * ldb + n0 + i];
+        }
+        acc = __builtin_amdgcn_mfma_f32_32x32x16_bf16(to_bf16x8(a), to_bf16x8(b), acc, 0, 0, 0);
+    }
+#pragma unroll
+    for (int r = 0; r < 16; ++r) {
+        const int row = m0 + 8 * (r >> 2) + 4 * h + (r & 3);
+        float *dst = C + (int64_t)row * ldc + n0 + i;
+        *dst = accumulate ? *dst + acc[r] : acc[r];
+    }
+}
+
+__device__ inline float gelu_f(float z) { return 0.5f * z * (1.0f + erff(z * 0.70710678118654752f)); }
+__device__ inline float gelu_df(float z)
+{
+    return 0.5f * (1.0f + erff(z * 0.70710678118654752f)) + z * __expf(-0.5f * z * z) * 0.3989422804014327f;
+}
+
+// Z[b][j] += bias[j]; H = gelu(Z) (H may alias nothing).
+__global__ void bias_gelu(float *Z, const float *bias, float *H, int rows, int cols, int apply_gelu)
+{
+    const int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (t >= (int64_t)rows * cols) return;
+    const int j = (int)(t % cols);
+    const float z = Z[t] + bias[j];
+    Z[t] = z;
+    if (apply_gelu) H[t] = gelu_f(z);
+}
+
+// dZ = dH * gelu'(Z)
+__global__ void gelu_backward(const float *Z, const float *dH, float *dZ, int64_t n)
+{
+    const int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (t < n) dZ[t] = dH[t] * gelu_df(Z[t]);
+}
+
+// Gaussian NLL of targets T [B][L] under (mu, ls) from the outputs O [B][Op]:
+// mu_l = omean_l + oscale_l O[b][l], ls_l = log oscale_l + O[b][L + l].
+// Writes dO (zero beyond 2L) and per-sample losses.
+__global__ void nll_grad(const float *O, int Op, const float *T, int L, const float *omean,
+                         const float *oscale, float *dO, float *loss, int B)
+{
+    const int b = (int)(blockIdx.x * blockDim.x + threadIdx.x);
+    if (b >= B) return;
+    const float invB = 1.0f / (float)B;
+    float tot = 0.0f;
+    for (int j = 0; j < Op; ++j) dO[(int64_t)b * Op + j] = 0.0f;
+    for (int l = 0; l < L; ++l) {
+        const float mu = omean[l] + oscale[l] * O[(int64_t)b * Op + l];
+        const float lsv = __logf(oscale[l]) + O[(int64_t)b * Op + L + l];
+        const float r = T[(int64_t)b * L + l] - mu;
+        const float e2 = __expf(-2.0f * lsv);
+        tot += lsv + 0.5f * r * r * e2;
+        dO[(int64_t)b * Op + l] = -r * e2 * oscale[l] * invB;
+        dO[(int64_t)b * Op + L + l] = (1.0f - r * r * e2) * invB;
+    }
+    loss[b] = tot;
+}
+
+// out[j] = sum_b M[b][j] over rows in a fixed order (one thread per column).
+__global__ void col_sum(const float *Mx, int rows, int cols, float *out)
+{
+    const int j = (int)(blockIdx.x * blockDim.x + threadIdx.x);
+    if (j >= cols) return;
+    float s = 0.0f;
+    for (int b = 0; b < rows; ++b) s += Mx[(int64_t)b * cols + j];
+    out[j] = s;
+}
+
+// FP32 master parameters -> the inference copy (BF16 fragments in MFMA B order:
+// lane 32 h + i of fragment (ks, ct) holds W[16 ks + 8 h + j][32 ct + i]).
+__global__ void pack_mlp(const float *master, MlpDev *out)
+{
+    const int t = (int)(blockIdx.x * blockDim.x + threadIdx.x);
+    auto pack = [&](const float *W, int K, int N, __bf16 *dst, int idx) {
+        const int nct = N / 32;
+        const int total = (K / 16) * nct * 64 * 8;
+        if (idx >= total) return;
+        const int j = idx & 7, lane = (idx >> 3) & 63, frag = idx >> 9;
+        const int ks = frag / nct, ct = frag % nct;
+        const int k = 16 * ks + 8 * (lane >> 5) + j, n = 32 * ct + (lane & 31);
+        dst[idx] = (__bf16)W[k * N + n];
+    };
+    pack(master + kOffW1, kMlpF, kMlpH, out->W1p, t);
+    pack(master + kOffW2, kMlpH, kMlpH, out->W2p, t);
+    pack(master + kOffW3, kMlpH, kMlpO, out->W3p, t);
+    if (t < kMlpF) { out->fmean[t] = master[kOffFmean + t]; out->fscale[t] = master[kOffFscale + t]; }
+    if (t < kMlpH) { out->b1[t] = master[kOffB1 + t]; out->b2[t] = master[kOffB2 + t]; }
+    if (t < kMlpO) out->b3[t] = master[kOffB3 + t];
+    if (t < 8) { out->omean[t] = master[kOffOmean + t]; out->oscale[t] = master[kOffOscale + t]; }
+}
+
+// Adam on FP32 master weights; p, g, m, v of length n.
+__global__ void adam_step(float *p, const float *g, float *m, float *v, int64_t n, float lr, float b1,
+                          float b2, float eps, float c1, float c2)
+{
+    const int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (t >= n) return;
+    const float gt = g[t];
+    const float mt = b1 * m[t] + (1.0f - b1) * gt;
+    const float vt = b2 * v[t] + (1.0f - b2) * gt * gt;
+    m[t] = mt;
+    v[t] = vt;
+    p[t] -= lr * (mt / c1) / (__builtin_sqrtf(vt / c2) + eps);
+}
+
+}  // namespace fbmc

@@ -1,0 +1,51 @@
+// fbmc_mlp.hpp -- shapes and kernels of the learned beta proposal's network.
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+namespace fbmc {
+
+typedef __bf16 bf16x8 __attribute__((ext_vector_type(8)));
+typedef float floatx16 __attribute__((ext_vector_type(16)));
+
+constexpr int kMlpF = 32;    // features (zero-padded)
+constexpr int kMlpH = 128;   // hidden width
+constexpr int kMlpO = 32;    // outputs, 2L padded to one 32-wide tile
+
+// FP32 master parameters, one contiguous block (offsets in floats).
+constexpr int kOffFmean = 0;
+constexpr int kOffFscale = kOffFmean + kMlpF;
+constexpr int kOffW1 = kOffFscale + kMlpF;                 // [F][H]
+constexpr int kOffB1 = kOffW1 + kMlpF * kMlpH;
+constexpr int kOffW2 = kOffB1 + kMlpH;                     // [H][H]
+constexpr int kOffB2 = kOffW2 + kMlpH * kMlpH;
+constexpr int kOffW3 = kOffB2 + kMlpH;                     // [H][O]
+constexpr int kOffB3 = kOffW3 + kMlpH * kMlpO;
+constexpr int kOffOmean = kOffB3 + kMlpO;                  // [8]
+constexpr int kOffOscale = kOffOmean + 8;
+constexpr int kMlpParams = kOffOscale + 8;
+
+// Inference copy: weights as BF16 MFMA B fragments, [kstep][coltile][lane][8].
+struct MlpDev {
+    float fmean[kMlpF], fscale[kMlpF];
+    float b1[kMlpH], b2[kMlpH], b3[kMlpO];
+    float omean[8], oscale[8];
+    __bf16 W1p[(kMlpF / 16) * (kMlpH / 32) * 64 * 8];
+    __bf16 W2p[(kMlpH / 16) * (kMlpH / 32) * 64 * 8];
+    __bf16 W3p[(kMlpH / 16) * (kMlpO / 32) * 64 * 8];
+};
+
+__global__ void mfma_probe(const float *A, const float *B, float *C);
+__global__ void gemm_bf16(const float *A, int lda, int tA, const float *B, int ldb, int tB, float *C,
+                          int ldc, int M, int N, int K, int accumulate);
+__global__ void bias_gelu(float *Z, const float *bias, float *H, int rows, int cols, int apply_gelu);
+__global__ void gelu_backward(const float *Z, const float *dH, float *dZ, int64_t n);
+__global__ void nll_grad(const float *O, int Op, const float *T, int L, const float *omean,
+                         const float *oscale, float *dO, float *loss, int B);
+__global__ void col_sum(const float *Mx, int rows, int cols, float *out);
+__global__ void pack_mlp(const float *master, MlpDev *out);
+__global__ void adam_step(float *p, const float *g, float *m, float *v, int64_t n, float lr, float b1,
+                          float b2, float eps, float c1, float c2);
+
+}  // namespace fbmc

@@ -52,7 +52,17 @@ struct SegInfo {
     float *trace;                 // [capacity][trace_stride]
     int4 *dbg_eps, *dbg_gam, *dbg_beta;  // per-draw records [N][Gp], [Gp], [L][Gp]
     struct HyperState *hyp;
+    // split sweep (eps/gamma, then beta) used by the learned proposal
+    void *Ar;                     // [R][Gp] sum over row r of exp(h_n + eps_gn), this sweep
+    void *YR;                     // [R][Gp] sum over row r of y_gn (constant)
+    float *mlp_out;               // [2L][Gp] proposal mean mu_l then log-scale ls_l
+    int32_t *fallback;            // [Gp] 1 = slice step for beta_g
+    int32_t *imh_count;           // [Gp] accepted IMH steps while counting
+    int32_t *imh_last;            // [Gp] last sweep: 1 accepted, 0 rejected, -1 slice
+    float *pairs;                 // training pairs [capacity][kPairStride]: features, beta
 };
+
+constexpr int kPairStride = 32 + kMaxL;   // 32 raw features then L targets
 
 // FP64 hyperparameter state of one segment.
 struct HyperState {
@@ -75,7 +85,9 @@ struct SweepArgs {
     uint32_t mask;        // update mask
     int32_t trace_point;  // trace row to write this sweep, or -1
     int32_t dbg;          // write per-draw records
-    int32_t pad;
+    int32_t learned;      // beta by independence MH where the fallback mask is 0
+    int32_t count_imh;    // add accepted IMH steps to imh_count
+    int64_t pair_base;    // collect (features, beta) pairs at row pair_base + g, or -1
 };
 
 }  // namespace fbmc

@@ -68,7 +68,10 @@ EXPORTS = [
     "fb_num_segments", "fb_segment_dims", "fb_get_state", "fb_set_state", "fb_summaries",
     "fb_trace_genes", "fb_trace", "fb_trace_reset", "fb_debug_counts", "fb_reductions",
     "fb_philox", "fb_last_sweep_time", "fb_profile", "fb_kernel_times", "fb_last_error",
-    "fb_strerror",
+    "fb_strerror", "fb_default_train_opts", "fb_proposal_collect", "fb_proposal_train",
+    "fb_proposal_calibrate", "fb_set_beta_update", "fb_proposal_get", "fb_proposal_set",
+    "fb_fallback", "fb_imh_last", "fb_features", "fb_mfma_probe", "fb_mlp_forward",
+    "fb_mlp_loss_grad",
 ]
 
 _lib = None
@@ -114,6 +117,7 @@ def load() -> C.CDLL:
     L.fb_last_error.restype = C.c_char_p
     L.fb_strerror.argtypes = [i32]
     L.fb_strerror.restype = C.c_char_p
+    _load_proposal_api(L)
     _lib = L
     return L
 
@@ -383,3 +387,158 @@ class Sampler:
 
     def last_sweep_time(self):
         return fb_last_sweep_time(self.ctx)
+
+
+# ---------------------------------------------------------------------------
+# Learned beta proposal
+# ---------------------------------------------------------------------------
+FB_BETA_SLICE, FB_BETA_LEARNED = 0, 1
+MLP_F, MLP_H, MLP_O = 32, 128, 32
+
+_FP = C.POINTER(C.c_float)
+
+
+class fb_mlp(C.Structure):
+    _fields_ = [(k, _FP) for k in ("fmean", "fscale", "W1", "b1", "W2", "b2", "W3", "b3",
+                                   "omean", "oscale")]
+
+
+class fb_train_opts(C.Structure):
+    _fields_ = [("epochs", C.c_int32), ("pairs_per_epoch", C.c_int32), ("minibatch", C.c_int32),
+                ("lr", C.c_double), ("seed", C.c_uint64)]
+
+
+MLP_SHAPES = dict(fmean=(MLP_F,), fscale=(MLP_F,), W1=(MLP_F, MLP_H), b1=(MLP_H,), W2=(MLP_H, MLP_H),
+                  b2=(MLP_H,), W3=(MLP_H, MLP_O), b3=(MLP_O,), omean=(8,), oscale=(8,))
+
+
+def mlp_zeros() -> dict:
+    d = {k: np.zeros(v, np.float32) for k, v in MLP_SHAPES.items()}
+    d["oscale"][:] = 1.0
+    d["fscale"][:] = 1.0
+    return d
+
+
+def _mlp_struct(params: dict, keep: list) -> fb_mlp:
+    arrs = {k: np.ascontiguousarray(params[k], dtype=np.float32).reshape(MLP_SHAPES[k]) for k in MLP_SHAPES}
+    keep.append(arrs)
+    return fb_mlp(*[_p(arrs[k], C.c_float) for k in MLP_SHAPES])
+
+
+def _load_proposal_api(L):
+    vp, i32, i64 = C.c_void_p, C.c_int32, C.c_int64
+    L.fb_default_train_opts.argtypes = [C.POINTER(fb_train_opts)]
+    L.fb_default_train_opts.restype = None
+    L.fb_proposal_collect.argtypes = [vp, i64, i32]
+    L.fb_proposal_train.argtypes = [vp, C.POINTER(fb_train_opts), _DP]
+    L.fb_proposal_calibrate.argtypes = [vp, i64, C.c_double]
+    L.fb_set_beta_update.argtypes = [vp, i32]
+    L.fb_proposal_get.argtypes = [vp, C.POINTER(fb_mlp)]
+    L.fb_proposal_set.argtypes = [vp, C.POINTER(fb_mlp)]
+    ip = C.POINTER(C.c_int32)
+    L.fb_fallback.argtypes = [vp, i32, ip, ip]
+    L.fb_imh_last.argtypes = [vp, i32, ip]
+    L.fb_features.argtypes = [vp, i32, _FP]
+    L.fb_mfma_probe.argtypes = [_FP, _FP, _FP]
+    L.fb_mlp_forward.argtypes = [C.POINTER(fb_mlp), i32, _FP, i64, _FP, _FP]
+    L.fb_mlp_loss_grad.argtypes = [C.POINTER(fb_mlp), i32, _FP, _FP, i64, _FP, C.POINTER(fb_mlp)]
+
+
+def fb_default_train_opts(**kw) -> fb_train_opts:
+    o = fb_train_opts()
+    load().fb_default_train_opts(C.byref(o))
+    for k, v in kw.items():
+        if not hasattr(o, k):
+            raise TypeError(f"unknown training option {k}")
+        setattr(o, k, v)
+    return o
+
+
+def fb_proposal_collect(ctx, sweeps: int, every: int = 1):
+    _check(load().fb_proposal_collect(ctx, int(sweeps), int(every)), ctx)
+
+
+def fb_proposal_train(ctx, opts=None) -> np.ndarray:
+    o = opts if opts is not None else fb_default_train_opts()
+    losses = np.zeros(o.epochs)
+    _check(load().fb_proposal_train(ctx, C.byref(o), _p(losses)), ctx)
+    return losses
+
+
+def fb_proposal_calibrate(ctx, sweeps: int, min_accept: float = 0.2):
+    _check(load().fb_proposal_calibrate(ctx, int(sweeps), float(min_accept)), ctx)
+
+
+def fb_set_beta_update(ctx, mode: int):
+    _check(load().fb_set_beta_update(ctx, int(mode)), ctx)
+
+
+def fb_proposal_get(ctx) -> dict:
+    out = {k: np.zeros(v, np.float32) for k, v in MLP_SHAPES.items()}
+    st = fb_mlp(*[_p(out[k], C.c_float) for k in MLP_SHAPES])
+    _check(load().fb_proposal_get(ctx, C.byref(st)), ctx)
+    return out
+
+
+def fb_proposal_set(ctx, params: dict):
+    keep = []
+    st = _mlp_struct(params, keep)
+    _check(load().fb_proposal_set(ctx, C.byref(st)), ctx)
+
+
+def fb_fallback(ctx, seg: int = 0, set_mask=None) -> np.ndarray:
+    G = fb_segment_dims(ctx, seg)["G"]
+    get = np.zeros(G, np.int32)
+    setp = None
+    if set_mask is not None:
+        sm = np.ascontiguousarray(set_mask, dtype=np.int32)
+        setp = _p(sm, C.c_int32)
+    _check(load().fb_fallback(ctx, seg, _p(get, C.c_int32), setp), ctx)
+    return get
+
+
+def fb_imh_last(ctx, seg: int = 0) -> np.ndarray:
+    G = fb_segment_dims(ctx, seg)["G"]
+    out = np.zeros(G, np.int32)
+    _check(load().fb_imh_last(ctx, seg, _p(out, C.c_int32)), ctx, (FB_ENUMERIC,))
+    return out
+
+
+def fb_features(ctx, seg: int = 0) -> np.ndarray:
+    G = fb_segment_dims(ctx, seg)["G"]
+    out = np.zeros((G, 32), np.float32)
+    _check(load().fb_features(ctx, seg, _p(out, C.c_float)), ctx)
+    return out
+
+
+def fb_mfma_probe(A, B) -> np.ndarray:
+    A = np.ascontiguousarray(A, dtype=np.float32).reshape(32, 16)
+    B = np.ascontiguousarray(B, dtype=np.float32).reshape(16, 32)
+    Cm = np.zeros((32, 32), np.float32)
+    _check(load().fb_mfma_probe(_p(A, C.c_float), _p(B, C.c_float), _p(Cm, C.c_float)))
+    return Cm
+
+
+def fb_mlp_forward(params: dict, L: int, phi):
+    keep = []
+    st = _mlp_struct(params, keep)
+    phi = np.ascontiguousarray(phi, dtype=np.float32).reshape(-1, 32)
+    B = phi.shape[0]
+    mu = np.zeros((B, L), np.float32)
+    ls = np.zeros((B, L), np.float32)
+    _check(load().fb_mlp_forward(C.byref(st), L, _p(phi, C.c_float), B, _p(mu, C.c_float), _p(ls, C.c_float)))
+    return mu, ls
+
+
+def fb_mlp_loss_grad(params: dict, L: int, phi, target):
+    keep = []
+    st = _mlp_struct(params, keep)
+    phi = np.ascontiguousarray(phi, dtype=np.float32).reshape(-1, 32)
+    tgt = np.ascontiguousarray(target, dtype=np.float32).reshape(-1, L)
+    B = phi.shape[0]
+    loss = C.c_float()
+    grads = {k: np.zeros(v, np.float32) for k, v in MLP_SHAPES.items()}
+    gst = fb_mlp(*[_p(grads[k], C.c_float) for k in MLP_SHAPES])
+    _check(load().fb_mlp_loss_grad(C.byref(st), L, _p(phi, C.c_float), _p(tgt, C.c_float), B, C.byref(loss),
+                                   C.byref(gst)))
+    return float(loss.value), grads

@@ -2,6 +2,7 @@
 (a compile-time switch, built only here, on the CPU) makes its pin fail."""
 import pytest
 
+from tests import test_oracle_mlp as M
 from tests import test_oracle_pins as P
 
 MUTANTS = [
@@ -19,6 +20,8 @@ MUTANTS = [
      lambda o: P.test_theta_conditional(o)),
     (8, "tau rate b + nu sum 1/gamma instead of b + (nu/2) sum 1/gamma",
      lambda o: P.test_tau_conditional(o)),
+    (9, "independence MH acceptance without the proposal-density ratio",
+     lambda o: M.test_imh_step_is_stationary(o, "cell_means", *M.PROPOSALS[0])),
 ]
 
 
