@@ -11,8 +11,11 @@ genes traced every sweep.  Inside the post-burn-in phase, after `--warmup`
 sweeps, exactly `--steps` sweeps are timed (device synchronised on both sides);
 `value` is sweeps per second over that window.  min-ESS/s of beta is the
 minimum effective sample size over the traced (gene, coefficient) pairs divided
-by the wall time of all post-burn-in sweeps.  The gene kernel's average launch
-duration comes from HIP events on the sampler's stream over the timed window.
+by the wall time of all post-burn-in sweeps.  A sweep is two launches: the
+eps kernel (one lane per gene and sample; it also carries the previous sweep's
+hyperparameter step) and the gamma/beta kernel.  Their average launch durations
+come from HIP events on the sampler's stream over the timed window; the
+launch shape is picked by the library's autotuner after burn-in.
 """
 from __future__ import annotations
 
@@ -33,12 +36,15 @@ TOTAL_ITERS = 20000
 TRACE_GENES = 1000
 
 
-def algorithmic_bytes_per_gene(N: int, L: int, state_bytes: int) -> int:
-    """Post-burn-in bytes one gene moves in one sweep: per eps draw y (4 B), eps
-    read + write, the read-only slice width, and the FP64 (mean, mean square)
-    read + write; the same for gamma and each beta without the count."""
+def algorithmic_bytes(N: int, L: int, state_bytes: int):
+    """Post-burn-in bytes one gene moves in one sweep, split by kernel: per eps
+    draw y (4 B), eps read + write, the read-only slice width, and the FP64
+    (mean, mean square) read + write; the same for gamma and each beta without
+    the count.  Returns (eps kernel, gamma/beta kernel, whole sweep)."""
     per_draw = 3 * state_bytes + 32
-    return N * (4 + per_draw) + (1 + L) * per_draw
+    e = N * (4 + per_draw)
+    gb = (1 + L) * per_draw
+    return e, gb, e + gb
 
 
 def cpu_baseline(ds, seconds: float = 15.0):
@@ -68,6 +74,7 @@ def main():
     ap.add_argument("--genes", type=int, default=50_000)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-ess", action="store_true")
+    ap.add_argument("--no-autotune", action="store_true")
     ap.add_argument("--copy-mib", type=int, default=0,
                     help="first run a plain device copy of this many MiB (counter calibration)")
     args = ap.parse_args()
@@ -106,6 +113,10 @@ def main():
     # burn-in (tunes the slice widths), untimed
     smp.sweep(BURNIN)
     smp.sync()
+    if args.no_autotune:
+        shape = fbmc.fb_get_launch(smp.ctx) + (None,)
+    else:
+        shape = fbmc.fb_autotune(smp.ctx, 50)
 
     torch.cuda.synchronize()
     t_post0 = time.perf_counter()
@@ -119,7 +130,7 @@ def main():
     smp.sync()
     torch.cuda.synchronize()
     t1 = time.perf_counter()
-    gene_ms, hyper_ms, nsamp = fbmc.fb_kernel_times(smp.ctx)
+    eps_ms, gb_ms, hyp_ms, nsamp = fbmc.fb_kernel_times(smp.ctx)
     fbmc.fb_profile(smp.ctx, 0, 0)
     rest = post - args.warmup - args.steps
     if rest > 0:
@@ -130,9 +141,18 @@ def main():
 
     ms_per_step = (t1 - t0) * 1e3 / args.steps
     sweeps_per_s = args.steps / (t1 - t0)
-    bpg = algorithmic_bytes_per_gene(N, L, 4)
-    bytes_per_launch = bpg * G
-    achieved = bytes_per_launch / (gene_ms * 1e-3) / 1e9 if gene_ms > 0 else None
+    b_eps, b_gb, b_sweep = algorithmic_bytes(N, L, 4)
+    gbs = lambda nbytes, ms: nbytes / (ms * 1e-3) / 1e9 if ms > 0 else None
+    kernels = {
+        "eps_sweep": {"ms": eps_ms, "bytes_per_gene": b_eps, "bytes_per_launch": b_eps * G,
+                      "achieved_GBs": gbs(b_eps * G, eps_ms)},
+        "gb_sweep": {"ms": gb_ms, "bytes_per_gene": b_gb, "bytes_per_launch": b_gb * G,
+                     "achieved_GBs": gbs(b_gb * G, gb_ms)},
+        "hyper_sweep": {"ms": hyp_ms, "fused_into_eps_sweep": bool(shape[1])},
+        "samples": nsamp,
+    }
+    dom = "eps_sweep" if eps_ms >= gb_ms else "gb_sweep"
+    achieved = kernels[dom]["achieved_GBs"]
 
     ess_info = None
     if do_ess:
@@ -163,15 +183,20 @@ def main():
         "data": "synthetic (model simulation, seed 0)",
         "config": {"workload": f"paper design G={G} N={N} L={L}, 1 chain, plain slice sweep",
                    "genes": G, "samples": N, "coefficients": L, "chains": 1,
-                   "burnin": BURNIN, "iterations": BURNIN + post},
+                   "burnin": BURNIN, "iterations": BURNIN + post,
+                   "launch": {"samples_per_wave": shape[0], "fused_hyper": shape[1],
+                              "autotuned_ms_per_sweep": shape[2]}},
         "min_ess_per_s": None if ess_info is None else ess_info["min_ess_per_s"],
         "ess": ess_info,
         "learned_proposal": None,
-        "kernel_ms": {"gene_sweep": gene_ms, "hyper_sweep": hyper_ms, "samples": nsamp},
-        "roofline": {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
+        "kernels": kernels,
+        "roofline": {"bound": "hbm", "kernel": dom, "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
                      "frac": None if achieved is None else achieved / HBM_PEAK_GBS,
                      "traffic": None,
-                     "bytes_per_launch": bytes_per_launch, "bytes_per_gene": bpg},
+                     "bytes_per_launch": kernels[dom]["bytes_per_launch"],
+                     "bytes_per_gene": kernels[dom]["bytes_per_gene"]},
+        "sweep_hbm": {"bytes_per_sweep": b_sweep * G, "achieved_GBs": b_sweep * G * sweeps_per_s / 1e9,
+                      "frac": b_sweep * G * sweeps_per_s / 1e9 / HBM_PEAK_GBS},
     }
     if not args.no_cpu_baseline:
         line["cpu_baseline"] = cpu_baseline(ds)

@@ -206,18 +206,44 @@ int fb_reductions(fb_ctx *c, int32_t seg, double *out);
 /* Philox4x32-10 words computed on the device: ctr [n][4], key [n][2], out [n][4]. */
 int fb_philox(const uint32_t *ctr, const uint32_t *key, uint32_t *out, int64_t n);
 
-/* Time of the last fb_sweep batch measured with HIP events around the gene and
- * hyperparameter kernels (milliseconds), and the number of sweeps in it. */
+/* Time of the last fb_sweep batch measured with HIP events around all its
+ * launches (milliseconds), and the number of sweeps in it. */
 int fb_last_sweep_time(fb_ctx *c, double *ms, int64_t *sweeps);
 
-/* Sampled kernel timing with HIP events on the context's stream: from now on,
- * the gene and hyperparameter launches of every `every`-th sweep are bracketed
- * by events, for at most max_samples sweeps (every = 0 turns it off).
- * fb_kernel_times waits for the stream, returns the mean duration of the
- * sampled gene-kernel launches and hyperparameter-kernel launches (ms) and the
- * number of samples, and starts a new sample set. */
+/* Sampled kernel timing with HIP events on the context's stream.  A sweep is
+ * two or three launches: the eps kernel (Algorithm 1 step 1), the gamma/beta
+ * kernel (steps 2 and 5) and the hyperparameter step (steps 3, 4, 6, 7), which
+ * either rides in the next sweep's eps kernel (fused, the eps time includes
+ * it) or is a kernel of its own (see fb_set_launch).  From now on the launches
+ * of every `every`-th sweep are bracketed by events, for at most max_samples
+ * sweeps (every = 0 turns it off).  fb_kernel_times waits for the stream,
+ * returns the mean duration (ms) of the sampled eps, gamma/beta and separate
+ * hyperparameter launches (0 when fused) and the number of samples, and starts
+ * a new sample set. */
 int fb_profile(fb_ctx *c, int32_t every, int32_t max_samples);
-int fb_kernel_times(fb_ctx *c, double *gene_ms, double *hyper_ms, int64_t *samples);
+int fb_kernel_times(fb_ctx *c, double *eps_ms, double *gb_ms, double *hyper_ms, int64_t *samples);
+
+/* Launch shape of a sweep; no choice changes any draw (the draws are functions
+ * of their counters only).
+ *   samples_per_wave  eps draws per lane, in sample order (1 .. max N): a
+ *                     wavefront covers 64 genes x this many samples
+ *   fuse_hyper        1: the hyperparameter step of sweep m runs in the first
+ *                     workgroups of sweep m + 1's eps kernel (no eps conditional
+ *                     involves a hyperparameter); 0: a kernel of its own
+ * Defaults: 1 and 1.  FB_EINVAL outside these ranges. */
+int fb_set_launch(fb_ctx *c, int32_t samples_per_wave, int32_t fuse_hyper);
+int fb_get_launch(const fb_ctx *c, int32_t *samples_per_wave, int32_t *fuse_hyper);
+
+/* Autotuner: times trial_sweeps sweeps (after 2 warm-up sweeps) for every
+ * samples_per_wave in {1, 2, 4, 8} (up to max N) with and without fusion,
+ * starting each trial from a device snapshot of the state, then restores the
+ * snapshot and keeps the fastest shape.  The chain continues exactly as if no
+ * trial had run (traces and training pairs are not written by the trials; the
+ * time reported by fb_last_sweep_time is the last trial's).  Outputs (may be
+ * NULL): the chosen shape and its time per sweep (ms).  Needs device memory
+ * for one copy of the state. */
+int fb_autotune(fb_ctx *c, int32_t trial_sweeps, int32_t *samples_per_wave, int32_t *fuse_hyper,
+                double *ms_per_sweep);
 
 /* ------------------------------------------------------------------------
  * Learned beta proposal (independence Metropolis-Hastings for the block beta_g)

@@ -153,33 +153,39 @@ __device__ inline T slice_draw(F &f, T x0, T w, uint32_t k0, uint32_t k1, uint4 
     return x1;
 }
 
-// The same draw by a whole wavefront for one scalar (hyperparameters): the
-// step-out points L - k w (lanes 0..15) and R + k w (lanes 32..47) are
-// evaluated at once, then the chain of shrink candidates that assumes every
-// earlier candidate was rejected (it is known in advance: each interval update
-// depends only on the candidate and x0) is evaluated at once, 32 candidates per
-// round; the first point in the slice is the sequential algorithm's result.
-// Points are formed by the same repeated additions as the sequential code, so
-// the result, counters and records match it exactly.  All 64 lanes must call.
+// The same draw by a whole wavefront for one scalar (hyperparameters).  One
+// round of evaluations covers the reference point x0 (lane 63) and the
+// step-out points L - k w (lanes 0..15) and R + k w (lanes 32..47); the first
+// failure on each side ends its step-out as in the sequential algorithm.  The
+// shrink candidates then come 16 per round: the chain of intervals that
+// assumes every earlier candidate was rejected is known in advance (each update
+// depends only on the candidate and x0), every lane runs it, lane c evaluates
+// candidate c, and the first point in the slice is the sequential result.
+// Points are formed by the same operations as the sequential code, so the
+// result and the counters match it.  All 64 lanes must call; `words` is 20
+// doubles of LDS private to the wavefront.
 template <typename F>
 __device__ inline double slice_draw_wave(F &f, double x0, double w, uint32_t k0, uint32_t k1, uint4 ctr,
-                                         int K, int cap, DrawRec &rec, double *words /* LDS [64] */)
+                                         int K, int cap, DrawRec &rec, double *words)
 {
+    constexpr int kRound = 16;
     const int lane = (int)(threadIdx.x & 63);
     const uint4 r0 = philox4x32_10(ctr, k0, k1);
-    const double thr = f.base(x0) + dlog(u01<double>(r0.x));
+    const double lu = dlog(u01<double>(r0.x));
     const double v = w * uwin<double>(r0.y);
     const double L0 = x0 - v;
     const double R0 = L0 + w;
     const int KL = (int)(r0.y & (uint32_t)K);
     const int KR = K - KL;
-    // step out in parallel
     const int j = lane & 31;
     const bool left = lane < 32;
     double pt = left ? L0 : R0;
     for (int i = 0; i < j && i < 15; ++i) pt = left ? pt - w : pt + w;
+    if (lane == 63) pt = x0;
+    const double fv = f(pt);
+    const double thr = __shfl(fv, 63, 64) + lu;
     const bool need = left ? (j < KL) : (j < KR);
-    const bool in = need && (f(pt) > thr);
+    const bool in = need && (fv > thr);
     const uint64_t fail_l = __ballot(left && need && !in);
     const uint64_t fail_r = __ballot(!left && need && !in) >> 32;
     const int nl = fail_l ? __builtin_ctzll(fail_l) : KL;
@@ -187,14 +193,14 @@ __device__ inline double slice_draw_wave(F &f, double x0, double w, uint32_t k0,
     double L = L0, R = R0;
     for (int i = 0; i < nl; ++i) L = L - w;
     for (int i = 0; i < nr; ++i) R = R + w;
-    // shrink: words of the stream, block b from lane b
     double x1 = x0;
     int nc = cap;
     bool found = false;
-    for (int base = 0; base < cap && !found; base += 32) {
-        // words q = base + 2 .. base + 33 cover candidates base + 1 .. base + 32
+    const int c = lane & (kRound - 1);
+    for (int base = 0; base < cap && !found; base += kRound) {
+        // candidates base + 1 .. base + 16 read words q = base + 2 .. base + 17
         const uint32_t b0 = (uint32_t)(base + 2) >> 2;
-        if (lane < 10) {
+        if (lane < 5) {
             const uint32_t b = b0 + (uint32_t)lane;
             const uint4 rb = b == 0 ? r0
                              : philox4x32_10(make_uint4(ctr.x, ctr.y, ctr.z, (ctr.w & 0xFFFF0000u) | b), k0, k1);
@@ -203,35 +209,33 @@ __device__ inline double slice_draw_wave(F &f, double x0, double w, uint32_t k0,
             words[4 * lane + 2] = u01<double>(rb.z);
             words[4 * lane + 3] = u01<double>(rb.w);
         }
+        __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
         __builtin_amdgcn_wave_barrier();
-        __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "wavefront");
-        // lane c (< 32) evaluates candidate base + c + 1: run the rejection chain to it
-        double xc = 0.0, Lc = L, Rc = R;
-        const int c = lane & 31;
-        for (int i = 0; i <= c; ++i) {
-            const int q = base + i + 2;
-            const double u = words[q - 4 * (int)b0];
-            xc = Lc + u * (Rc - Lc);
-            if (i < c) {
-                if (xc > x0) Rc = xc; else Lc = xc;
-            }
+        __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+        const int off = base + 2 - 4 * (int)b0;
+        double Lc = L, Rc = R, xc = 0.0;
+#pragma unroll
+        for (int i = 0; i < kRound; ++i) {
+            const double x = Lc + words[off + i] * (Rc - Lc);
+            xc = i == c ? x : xc;
+            const bool gt = x > x0;
+            Rc = gt ? x : Rc;
+            Lc = gt ? Lc : x;
         }
-        const bool cand = lane < 32 && base + c < cap;
-        const bool acc = cand && (f(xc) > thr);
-        const uint64_t hit = __ballot(acc);
-        // advance the shared interval past this round's 32 rejections
+        const bool acc = base + c < cap && f(xc) > thr;
+        const uint64_t hit = __ballot(lane < kRound && acc);
         if (hit) {
             const int first = __builtin_ctzll(hit);
             x1 = __shfl(xc, first, 64);
             nc = base + first + 1;
             found = true;
         } else {
-            L = __shfl(Lc, 31, 64);
-            R = __shfl(Rc, 31, 64);
-            const double xl = __shfl(xc, 31, 64);
-            if (xl > x0) R = xl; else L = xl;
+            L = Lc;
+            R = Rc;
         }
+        __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
         __builtin_amdgcn_wave_barrier();
+        __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
     }
     rec.kl = KL;
     rec.nl = nl;
@@ -255,11 +259,12 @@ __device__ inline void tune_width(T &w, T &waux, T x0, T x1, int64_t m, int64_t 
     }
 }
 
-// Welford's running mean and mean of squares (Section 3.1), k = m - M_B.
-__device__ inline void welford(double2 &mm, double x, double k)
+// Welford's running mean and mean of squares (Section 3.1) with weight
+// inv_k = 1 / k, k = m - M_B (a product instead of two FP64 divisions).
+__device__ inline void welford(double2 &mm, double x, double inv_k)
 {
-    mm.x += (x - mm.x) / k;
-    mm.y += (x * x - mm.y) / k;
+    mm.x += (x - mm.x) * inv_k;
+    mm.y += (x * x - mm.y) * inv_k;
 }
 
 }  // namespace fbmc

@@ -20,16 +20,12 @@
 #include "fbmc_types.hpp"
 
 namespace fbmc {
-hipError_t launch_gene(int precision, const SegInfo *segs, const int2 *tiles, int ntiles,
-                       const SweepArgs &a, int *err, hipStream_t st);
+hipError_t launch_eps(int precision, const SegInfo *segs, const int4 *items, int nitems, const SweepArgs &a,
+                      int nhyp, const SweepArgs &ha, int *err, hipStream_t st);
+hipError_t launch_gb(int precision, bool learned, const SegInfo *segs, const int2 *tiles, int ntiles,
+                     const SweepArgs &a, const MlpDev *net, int *err, hipStream_t st);
 hipError_t launch_hyper(const SegInfo *segs, int nseg, const SweepArgs &a, int *err, hipStream_t st);
 hipError_t launch_philox(const uint4 *ctr, const uint2 *key, uint4 *out, int64_t n, hipStream_t st);
-hipError_t launch_split(int precision, const SegInfo *segs, const int2 *tiles, int ntiles, const SweepArgs &a,
-                        int *err, hipStream_t st);
-hipError_t launch_beta(int precision, const SegInfo *segs, const int2 *tiles, int ntiles, const SweepArgs &a,
-                       int *err, hipStream_t st);
-hipError_t launch_feat_mlp(int precision, const SegInfo *segs, const int2 *tiles, int ntiles, const MlpDev *net,
-                           hipStream_t st);
 hipError_t launch_mlp_infer_raw(const float *phi, int64_t B, int L, const MlpDev *net, float *mu, float *ls,
                                 hipStream_t st);
 hipError_t launch_features(int precision, const SegInfo *seg, int64_t G, float *out, hipStream_t st);
@@ -84,6 +80,12 @@ struct fb_ctx {
     SegInfo *d_segs = nullptr;
     int2 *d_tiles = nullptr;
     int ntiles = 0;
+    // eps work items (segment, tile, n0, n1): samples per wavefront `spw`
+    int4 *d_items = nullptr;
+    int nitems = 0, item_cap = 0, spw = 0;
+    // the hyperparameter step rides in the next sweep's eps kernel (true) or
+    // is a kernel of its own after the gamma/beta kernel (false)
+    bool fuse = true;
     hipStream_t st = nullptr;
     bool own_stream = false;
     int *d_err = nullptr;
@@ -99,10 +101,11 @@ struct fb_ctx {
     // every `prof_every`-th sweep
     int32_t prof_every = 0, prof_cap = 0, prof_n = 0;
     int64_t prof_count = 0;
-    std::vector<hipEvent_t> prof_ev;   // 4 per sample
+    std::vector<hipEvent_t> prof_ev;   // 6 per sample: eps, gamma/beta, hyperparameter kernel
+    std::vector<char> prof_hyp;        // sample has a separate hyperparameter kernel
     // learned beta proposal
     int beta_mode = FB_BETA_SLICE;
-    bool split_ready = false;
+    bool learned_ready = false;
     float *d_master = nullptr;        // kMlpParams FP32
     MlpDev *d_net = nullptr;          // packed inference copy
     bool net_ready = false;
@@ -412,6 +415,8 @@ int write_state(fb_ctx *c, SegmentH &S, const HostState &hs)
     return FB_OK;
 }
 
+int build_items(fb_ctx *c, int spw);
+
 int build_context(fb_ctx *c, const fb_dataset *dsv, int nds)
 {
     int rc;
@@ -498,6 +503,15 @@ int build_context(fb_ctx *c, const fb_dataset *dsv, int nds)
             if ((rc = dalloc(c, (void **)&I.mom_gam, Gp * sizeof(double2)))) return rc;
             if ((rc = dalloc(c, (void **)&I.mom_beta, L * Gp * sizeof(double2)))) return rc;
             if ((rc = dalloc(c, (void **)&I.partials, (size_t)S.ntiles * kMaxParts * sizeof(double)))) return rc;
+            // Y_r = sum over the samples of distinct row r of y_gn (constant)
+            if ((rc = dalloc(c, &I.YR, (size_t)D.des.R * Gp * e))) return rc;
+            {
+                const int R = D.des.R;
+                std::vector<double> yr((size_t)D.G * R, 0.0);
+                for (int64_t g = 0; g < D.G; ++g)
+                    for (int n = 0; n < D.N; ++n) yr[(size_t)g * R + D.des.row_of[n]] += (double)D.y[g * D.N + n];
+                if ((rc = upload_array(c, I.YR, yr.data(), D.G, R, D.Gp, 0.0))) return rc;
+            }
             if ((rc = dalloc(c, (void **)&S.d_hyp, sizeof(HyperState)))) return rc;
             I.hyp = S.d_hyp;
             if (c->opt.debug_counts) {
@@ -551,7 +565,7 @@ int build_context(fb_ctx *c, const fb_dataset *dsv, int nds)
     }
     HIPCHK(c, hipEventCreate(&c->ev0));
     HIPCHK(c, hipEventCreate(&c->ev1));
-    return FB_OK;
+    return build_items(c, 1);
 }
 
 bool valid_seg(const fb_ctx *c, int32_t seg) { return c && seg >= 0 && seg < (int32_t)c->seg.size(); }
@@ -561,22 +575,55 @@ bool valid_seg(const fb_ctx *c, int32_t seg) { return c && seg >= 0 && seg < (in
 namespace {
 
 struct SweepMode {
-    bool split = false;      // eps/gamma kernel, [network], beta kernel
-    bool learned = false;    // IMH where the fallback mask is 0
-    bool count_imh = false;  // add accepted IMH steps to the counters
+    bool learned_kernel = false;  // beta wavefront with features (IMH, pairs, counts)
+    bool learned = false;         // IMH where the fallback mask is 0
+    bool count_imh = false;       // add accepted IMH steps to the counters
+    bool no_trace = false;        // trial sweeps of the autotuner: no trace rows
     int32_t collect_every = 0;
     int64_t collect_slot = 0;
 };
 
+// Work items of the eps kernel: every (segment, tile) split into sample ranges
+// of `spw` samples, tile-major so the wavefronts of one tile share a workgroup.
+int build_items(fb_ctx *c, int spw)
+{
+    std::vector<int4> items;
+    for (size_t k = 0; k < c->seg.size(); ++k) {
+        const SegmentH &S = c->seg[k];
+        for (int64_t t = 0; t < S.ntiles; ++t)
+            for (int n0 = 0; n0 < S.N; n0 += spw)
+                items.push_back(make_int4((int)k, (int)t, n0, std::min(S.N, n0 + spw)));
+    }
+    if ((int)items.size() > c->item_cap) {
+        int rc;
+        if ((rc = dalloc(c, (void **)&c->d_items, items.size() * sizeof(int4)))) return rc;
+        c->item_cap = (int)items.size();
+    }
+    HIPCHK(c, hipStreamSynchronize(c->st));
+    HIPCHK(c, hipMemcpy(c->d_items, items.data(), items.size() * sizeof(int4), hipMemcpyHostToDevice));
+    c->nitems = (int)items.size();
+    c->spw = spw;
+    return FB_OK;
+}
+
+// One sweep m is two launches: the eps kernel of sweep m, which also runs the
+// hyperparameter step of sweep m - 1 in its first workgroups, then the
+// gamma/beta kernel of sweep m.  The hyperparameter step of the last sweep of
+// the call runs on its own at the end, so the state is whole between calls.
+// Unfused (c->fuse false), every sweep ends with its own hyperparameter kernel.
 int run_sweeps(fb_ctx *c, int64_t n, SweepMode &md)
 {
     const fb_options &o = c->opt;
+    const int nseg = (int)c->seg.size();
     HIPCHK(c, hipEventRecord(c->ev0, c->st));
+    SweepArgs prev{};
+    bool pending = false;
     for (int64_t i = 0; i < n; ++i) {
         SweepArgs a{};
         a.m = c->m + 1;
         a.burnin = o.burnin;
         a.tune_start = o.tune_start;
+        a.inv_k = a.m > o.burnin ? 1.0 / (double)(a.m - o.burnin) : 0.0;
         a.K = o.max_steps;
         a.cap = o.shrink_cap;
         a.mask = o.update_mask;
@@ -591,26 +638,33 @@ int run_sweeps(fb_ctx *c, int64_t n, SweepMode &md)
             ++md.collect_slot;
             c->pair_n = md.collect_slot * c->totalG;
         }
-        if (o.thin > 0 && o.trace_capacity > 0 && a.m % o.thin == 0 && (!o.trace_after_burnin || a.m > o.burnin)) {
+        if (!md.no_trace && o.thin > 0 && o.trace_capacity > 0 && a.m % o.thin == 0 &&
+            (!o.trace_after_burnin || a.m > o.burnin)) {
             if (c->trace_n < o.trace_capacity) a.trace_point = (int32_t)c->trace_n++;
             else ++c->trace_dropped;
         }
         const bool prof = c->prof_every > 0 && c->prof_n < c->prof_cap && (c->prof_count++ % c->prof_every) == 0;
-        hipEvent_t *pe = prof ? &c->prof_ev[4 * (size_t)c->prof_n++] : nullptr;
+        hipEvent_t *pe = prof ? &c->prof_ev[6 * (size_t)c->prof_n] : nullptr;
+        if (prof) c->prof_hyp[c->prof_n++] = c->fuse ? 0 : 1;
         if (pe) HIPCHK(c, hipEventRecord(pe[0], c->st));
-        if (md.split) {
-            HIPCHK(c, launch_split(c->prec, c->d_segs, c->d_tiles, c->ntiles, a, c->d_err, c->st));
-            if (md.learned) HIPCHK(c, launch_feat_mlp(c->prec, c->d_segs, c->d_tiles, c->ntiles, c->d_net, c->st));
-            HIPCHK(c, launch_beta(c->prec, c->d_segs, c->d_tiles, c->ntiles, a, c->d_err, c->st));
-        } else {
-            HIPCHK(c, launch_gene(c->prec, c->d_segs, c->d_tiles, c->ntiles, a, c->d_err, c->st));
-        }
+        HIPCHK(c, launch_eps(c->prec, c->d_segs, c->d_items, c->nitems, a, pending ? nseg : 0, prev, c->d_err,
+                             c->st));
         if (pe) HIPCHK(c, hipEventRecord(pe[1], c->st));
         if (pe) HIPCHK(c, hipEventRecord(pe[2], c->st));
-        HIPCHK(c, launch_hyper(c->d_segs, (int)c->seg.size(), a, c->d_err, c->st));
+        HIPCHK(c, launch_gb(c->prec, md.learned_kernel, c->d_segs, c->d_tiles, c->ntiles, a, c->d_net, c->d_err,
+                            c->st));
         if (pe) HIPCHK(c, hipEventRecord(pe[3], c->st));
+        if (c->fuse) {
+            prev = a;
+            pending = true;
+        } else {
+            if (pe) HIPCHK(c, hipEventRecord(pe[4], c->st));
+            HIPCHK(c, launch_hyper(c->d_segs, nseg, a, c->d_err, c->st));
+            if (pe) HIPCHK(c, hipEventRecord(pe[5], c->st));
+        }
         c->m = a.m;
     }
+    if (pending) HIPCHK(c, launch_hyper(c->d_segs, nseg, prev, c->d_err, c->st));
     HIPCHK(c, hipEventRecord(c->ev1, c->st));
     c->last_n = n;
     return FB_OK;
@@ -625,32 +679,23 @@ int upload_segs(fb_ctx *c)
     return FB_OK;
 }
 
-// Buffers of the split sweep: per segment the row sums A_r, the constant count
-// sums Y_r, the network's outputs, the fallback mask and the IMH records.
-int ensure_split(fb_ctx *c)
+// Buffers of the learned beta step: per segment the fallback mask and the IMH
+// records.
+int ensure_learned(fb_ctx *c)
 {
-    if (c->split_ready) return FB_OK;
+    if (c->learned_ready) return FB_OK;
     int rc;
     c->totalG = 0;
     for (auto &S : c->seg) {
-        const DatasetH &D = c->ds[S.dataset];
-        const int R = D.des.R, L = D.L;
         const size_t Gp = (size_t)S.Gp;
         SegInfo &I = S.info;
-        if ((rc = dalloc(c, &I.Ar, (size_t)R * Gp * c->esz))) return rc;
-        if ((rc = dalloc(c, &I.YR, (size_t)R * Gp * c->esz))) return rc;
-        std::vector<double> yr((size_t)D.G * R, 0.0);
-        for (int64_t g = 0; g < D.G; ++g)
-            for (int n = 0; n < D.N; ++n) yr[(size_t)g * R + D.des.row_of[n]] += (double)D.y[g * D.N + n];
-        if ((rc = upload_array(c, I.YR, yr.data(), D.G, R, S.Gp, 0.0))) return rc;
-        if ((rc = dalloc(c, (void **)&I.mlp_out, 2 * (size_t)L * Gp * sizeof(float)))) return rc;
         if ((rc = dalloc(c, (void **)&I.fallback, Gp * sizeof(int32_t)))) return rc;
         if ((rc = dalloc(c, (void **)&I.imh_count, Gp * sizeof(int32_t)))) return rc;
         if ((rc = dalloc(c, (void **)&I.imh_last, Gp * sizeof(int32_t)))) return rc;
         c->totalG += S.G;
     }
     if ((rc = upload_segs(c))) return rc;
-    c->split_ready = true;
+    c->learned_ready = true;
     return FB_OK;
 }
 
@@ -859,7 +904,7 @@ int fb_sweep(fb_ctx *c, int64_t n)
     if (c->sticky) return c->sticky;
     SweepMode md;
     md.learned = c->beta_mode == FB_BETA_LEARNED;
-    md.split = md.learned;
+    md.learned_kernel = md.learned;
     return run_sweeps(c, n, md);
 }
 
@@ -1133,12 +1178,13 @@ int fb_profile(fb_ctx *c, int32_t every, int32_t max_samples)
     if (!c) return fail(nullptr, FB_EINVAL, "NULL context");
     if (every < 0 || max_samples < 0) return fail(c, FB_EINVAL, "every and max_samples must be >= 0");
     HIPCHK(c, hipStreamSynchronize(c->st));
-    const size_t need = 4 * (size_t)max_samples;
+    const size_t need = 6 * (size_t)max_samples;
     while (c->prof_ev.size() < need) {
         hipEvent_t e;
         HIPCHK(c, hipEventCreate(&e));
         c->prof_ev.push_back(e);
     }
+    c->prof_hyp.assign((size_t)max_samples, 0);
     c->prof_every = every;
     c->prof_cap = max_samples;
     c->prof_n = 0;
@@ -1146,23 +1192,149 @@ int fb_profile(fb_ctx *c, int32_t every, int32_t max_samples)
     return FB_OK;
 }
 
-int fb_kernel_times(fb_ctx *c, double *gene_ms, double *hyper_ms, int64_t *samples)
+int fb_kernel_times(fb_ctx *c, double *eps_ms, double *gb_ms, double *hyper_ms, int64_t *samples)
 {
     if (!c) return fail(nullptr, FB_EINVAL, "NULL context");
     HIPCHK(c, hipStreamSynchronize(c->st));
-    double tg = 0, th = 0;
+    double te = 0, tg = 0, th = 0;
+    int64_t nh = 0;
     for (int32_t i = 0; i < c->prof_n; ++i) {
-        float a = 0, b = 0;
-        HIPCHK(c, hipEventElapsedTime(&a, c->prof_ev[4 * i], c->prof_ev[4 * i + 1]));
-        HIPCHK(c, hipEventElapsedTime(&b, c->prof_ev[4 * i + 2], c->prof_ev[4 * i + 3]));
-        tg += a;
-        th += b;
+        float a = 0, b = 0, h = 0;
+        HIPCHK(c, hipEventElapsedTime(&a, c->prof_ev[6 * i], c->prof_ev[6 * i + 1]));
+        HIPCHK(c, hipEventElapsedTime(&b, c->prof_ev[6 * i + 2], c->prof_ev[6 * i + 3]));
+        if (c->prof_hyp[i]) {
+            HIPCHK(c, hipEventElapsedTime(&h, c->prof_ev[6 * i + 4], c->prof_ev[6 * i + 5]));
+            th += h;
+            ++nh;
+        }
+        te += a;
+        tg += b;
     }
-    if (gene_ms) *gene_ms = c->prof_n ? tg / c->prof_n : 0.0;
-    if (hyper_ms) *hyper_ms = c->prof_n ? th / c->prof_n : 0.0;
+    if (eps_ms) *eps_ms = c->prof_n ? te / c->prof_n : 0.0;
+    if (gb_ms) *gb_ms = c->prof_n ? tg / c->prof_n : 0.0;
+    if (hyper_ms) *hyper_ms = nh ? th / nh : 0.0;
     if (samples) *samples = c->prof_n;
     c->prof_n = 0;
     c->prof_count = 0;
+    return FB_OK;
+}
+
+int fb_set_launch(fb_ctx *c, int32_t samples_per_wave, int32_t fuse_hyper)
+{
+    if (!c) return fail(nullptr, FB_EINVAL, "NULL context");
+    int maxN = 1;
+    for (auto &S : c->seg) maxN = std::max(maxN, S.N);
+    if (samples_per_wave < 1 || samples_per_wave > maxN)
+        return fail(c, FB_EINVAL, "samples_per_wave must be in [1, max N]");
+    if (fuse_hyper != 0 && fuse_hyper != 1) return fail(c, FB_EINVAL, "fuse_hyper must be 0 or 1");
+    int rc;
+    if (samples_per_wave != c->spw && (rc = build_items(c, samples_per_wave))) return rc;
+    c->fuse = fuse_hyper != 0;
+    return FB_OK;
+}
+
+int fb_get_launch(const fb_ctx *c, int32_t *samples_per_wave, int32_t *fuse_hyper)
+{
+    if (!c) return fail(nullptr, FB_EINVAL, "NULL context");
+    if (samples_per_wave) *samples_per_wave = c->spw;
+    if (fuse_hyper) *fuse_hyper = c->fuse ? 1 : 0;
+    return FB_OK;
+}
+
+namespace {
+
+// Every device buffer a sweep writes, except traces and training pairs.
+void sweep_buffers(fb_ctx *c, std::vector<std::pair<void *, size_t>> &out)
+{
+    out.clear();
+    for (auto &S : c->seg) {
+        const SegInfo &I = S.info;
+        const size_t Gp = (size_t)S.Gp, N = (size_t)S.N, L = (size_t)S.L, e = c->esz;
+        for (void *p : {I.eps, I.w_eps, I.wa_eps}) out.push_back({p, N * Gp * e});
+        for (void *p : {I.gam, I.w_gam, I.wa_gam}) out.push_back({p, Gp * e});
+        for (void *p : {I.beta, I.w_beta, I.wa_beta}) out.push_back({p, L * Gp * e});
+        out.push_back({(void *)I.mom_eps, N * Gp * sizeof(double2)});
+        out.push_back({(void *)I.mom_gam, Gp * sizeof(double2)});
+        out.push_back({(void *)I.mom_beta, L * Gp * sizeof(double2)});
+        out.push_back({(void *)I.partials, (size_t)S.ntiles * kMaxParts * sizeof(double)});
+        out.push_back({(void *)S.d_hyp, sizeof(HyperState)});
+        if (I.dbg_eps) {
+            out.push_back({(void *)I.dbg_eps, N * Gp * sizeof(int4)});
+            out.push_back({(void *)I.dbg_gam, Gp * sizeof(int4)});
+            out.push_back({(void *)I.dbg_beta, L * Gp * sizeof(int4)});
+        }
+        if (I.imh_last) {
+            out.push_back({(void *)I.imh_count, Gp * sizeof(int32_t)});
+            out.push_back({(void *)I.imh_last, Gp * sizeof(int32_t)});
+        }
+    }
+    out.push_back({(void *)c->d_err, sizeof(int)});
+}
+
+}  // namespace
+
+int fb_autotune(fb_ctx *c, int32_t trial_sweeps, int32_t *samples_per_wave, int32_t *fuse_hyper, double *ms_per_sweep)
+{
+    if (!c) return fail(nullptr, FB_EINVAL, "NULL context");
+    if (trial_sweeps < 1) return fail(c, FB_EINVAL, "trial_sweeps must be >= 1");
+    if (c->sticky) return c->sticky;
+    HIPCHK(c, hipStreamSynchronize(c->st));
+    std::vector<std::pair<void *, size_t>> bufs;
+    sweep_buffers(c, bufs);
+    size_t total = 0;
+    for (auto &b : bufs) total += (b.second + 255) / 256 * 256;
+    char *snap = nullptr;
+    if (hipMalloc((void **)&snap, total) != hipSuccess) return fail(c, FB_ENOMEM, "hipMalloc (autotune snapshot)");
+    auto copy_all = [&](bool save) -> hipError_t {
+        size_t off = 0;
+        for (auto &b : bufs) {
+            hipError_t e = save ? hipMemcpyAsync(snap + off, b.first, b.second, hipMemcpyDeviceToDevice, c->st)
+                                : hipMemcpyAsync(b.first, snap + off, b.second, hipMemcpyDeviceToDevice, c->st);
+            if (e != hipSuccess) return e;
+            off += (b.second + 255) / 256 * 256;
+        }
+        return hipStreamSynchronize(c->st);
+    };
+    int maxN = 1;
+    for (auto &S : c->seg) maxN = std::max(maxN, S.N);
+    const int64_t m0 = c->m;
+    const int spw0 = c->spw;
+    const bool fuse0 = c->fuse;
+    int best_spw = spw0, rc = FB_OK;
+    bool best_fuse = fuse0;
+    double best = 1e300;
+    hipError_t e = copy_all(true);
+    for (int spw = 1; e == hipSuccess && rc == FB_OK && spw <= std::min(maxN, 8); spw *= 2) {
+        for (int fz = 0; fz < 2 && e == hipSuccess && rc == FB_OK; ++fz) {
+            if ((rc = build_items(c, spw))) break;
+            c->fuse = fz != 0;
+            SweepMode md;
+            md.learned = c->beta_mode == FB_BETA_LEARNED;
+            md.learned_kernel = md.learned;
+            md.no_trace = true;
+            if ((rc = run_sweeps(c, 2, md))) break;               // warm-up
+            if ((e = hipStreamSynchronize(c->st)) != hipSuccess) break;
+            if ((rc = run_sweeps(c, trial_sweeps, md))) break;
+            if ((e = hipEventSynchronize(c->ev1)) != hipSuccess) break;
+            float ms = 0;
+            if ((e = hipEventElapsedTime(&ms, c->ev0, c->ev1)) != hipSuccess) break;
+            const double per = ms / trial_sweeps;
+            if (per < best) { best = per; best_spw = spw; best_fuse = fz != 0; }
+            c->m = m0;
+            e = copy_all(false);
+        }
+    }
+    c->m = m0;
+    if (e == hipSuccess) e = copy_all(false);
+    (void)hipFree(snap);
+    if (e != hipSuccess) return fail(c, FB_EDEVICE, std::string("autotune: ") + hipGetErrorString(e));
+    if (rc) return rc;
+    c->fuse = best_fuse;
+    if ((rc = build_items(c, best_spw))) return rc;
+    if (samples_per_wave) *samples_per_wave = best_spw;
+    if (fuse_hyper) *fuse_hyper = best_fuse ? 1 : 0;
+    if (ms_per_sweep) *ms_per_sweep = best;
+    (void)spw0;
     return FB_OK;
 }
 
@@ -1192,7 +1364,7 @@ int fb_proposal_collect(fb_ctx *c, int64_t sweeps, int32_t every)
     if (sweeps < 0 || every < 1) return fail(c, FB_EINVAL, "need sweeps >= 0 and every >= 1");
     if (c->sticky) return c->sticky;
     int rc;
-    if ((rc = same_design(c)) || (rc = ensure_split(c))) return rc;
+    if ((rc = same_design(c)) || (rc = ensure_learned(c))) return rc;
     const int64_t slots = std::max<int64_t>(1, sweeps / every + 1);
     const int64_t need = slots * c->totalG;
     if (need > c->pair_cap) {
@@ -1207,7 +1379,7 @@ int fb_proposal_collect(fb_ctx *c, int64_t sweeps, int32_t every)
     if ((rc = upload_segs(c))) return rc;
     c->pair_n = 0;
     SweepMode md;
-    md.split = true;
+    md.learned_kernel = true;
     md.learned = false;
     md.collect_every = every;
     return run_sweeps(c, sweeps, md);
@@ -1304,13 +1476,13 @@ int fb_proposal_calibrate(fb_ctx *c, int64_t sweeps, double min_accept)
     if (!c->net_ready) return fail(c, FB_ESTATE, "no network: train or load one first");
     if (c->sticky) return c->sticky;
     int rc;
-    if ((rc = ensure_split(c))) return rc;
+    if ((rc = ensure_learned(c))) return rc;
     for (auto &S : c->seg) {
         HIPCHK(c, hipMemsetAsync(S.info.fallback, 0, (size_t)S.Gp * sizeof(int32_t), c->st));
         HIPCHK(c, hipMemsetAsync(S.info.imh_count, 0, (size_t)S.Gp * sizeof(int32_t), c->st));
     }
     SweepMode md;
-    md.split = true;
+    md.learned_kernel = true;
     md.learned = true;
     md.count_imh = true;
     if ((rc = run_sweeps(c, sweeps, md))) return rc;
@@ -1331,7 +1503,7 @@ int fb_set_beta_update(fb_ctx *c, int32_t mode)
     if (mode == FB_BETA_LEARNED) {
         if (!c->net_ready) return fail(c, FB_ESTATE, "no network: train or load one first");
         int rc;
-        if ((rc = same_design(c)) || (rc = ensure_split(c))) return rc;
+        if ((rc = same_design(c)) || (rc = ensure_learned(c))) return rc;
     }
     c->beta_mode = mode;
     return FB_OK;
@@ -1356,7 +1528,7 @@ int fb_proposal_set(fb_ctx *c, const fb_mlp *in)
     for (float v : blk) if (!std::isfinite(v)) return fail(c, FB_EINVAL, "parameters must be finite");
     for (int l = 0; l < 8; ++l) if (!(blk[kOffOscale + l] > 0)) return fail(c, FB_EINVAL, "oscale must be > 0");
     int rc;
-    if ((rc = same_design(c)) || (rc = ensure_net(c)) || (rc = ensure_split(c))) return rc;
+    if ((rc = same_design(c)) || (rc = ensure_net(c)) || (rc = ensure_learned(c))) return rc;
     HIPCHK(c, hipStreamSynchronize(c->st));
     HIPCHK(c, hipMemcpy(c->d_master, blk.data(), kMlpParams * sizeof(float), hipMemcpyHostToDevice));
     if ((rc = pack_net(c, c->d_master, c->d_net, c->st))) return rc;
@@ -1369,7 +1541,7 @@ int fb_fallback(fb_ctx *c, int32_t seg, int32_t *get, const int32_t *set)
 {
     if (!valid_seg(c, seg)) return fail(c, FB_EINVAL, "bad segment");
     int rc;
-    if ((rc = ensure_split(c))) return rc;
+    if ((rc = ensure_learned(c))) return rc;
     SegmentH &S = c->seg[seg];
     HIPCHK(c, hipStreamSynchronize(c->st));
     if (set) {
@@ -1384,7 +1556,7 @@ int fb_fallback(fb_ctx *c, int32_t seg, int32_t *get, const int32_t *set)
 int fb_imh_last(fb_ctx *c, int32_t seg, int32_t *last)
 {
     if (!valid_seg(c, seg) || !last) return fail(c, FB_EINVAL, "bad segment or NULL output");
-    if (!c->split_ready) return fail(c, FB_ESTATE, "no split sweep has run");
+    if (!c->learned_ready) return fail(c, FB_ESTATE, "no learned-proposal sweep has run");
     int rc = fb_sync(c);
     if (rc && rc != FB_ENUMERIC) return rc;
     HIPCHK(c, hipMemcpy(last, c->seg[seg].info.imh_last, (size_t)c->seg[seg].G * sizeof(int32_t),

@@ -115,6 +115,15 @@ __device__ inline double wave_sum(double v)
     return v;
 }
 
+// Orders the LDS accesses of one wavefront: the writes of every lane before
+// the reads that follow.
+__device__ inline void wave_lds_sync()
+{
+    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+    __builtin_amdgcn_wave_barrier();
+    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+}
+
 __device__ inline void raise_flag(int *err, int bit)
 {
     __hip_atomic_fetch_or(err, bit, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
@@ -256,7 +265,8 @@ __device__ inline void beta_slice_draws(const SegInfo &S, const SweepArgs &a, in
 template <typename T>
 __device__ inline int beta_imh_draw(const SegInfo &S, const SweepArgs &a, int64_t g, int64_t Gp,
                                     T (&beta)[kMaxL], const double (&th)[kMaxL], const double (&s2)[kMaxL],
-                                    const T (&C)[kMaxRows], const T (&YR)[kMaxRows])
+                                    const T (&C)[kMaxRows], const T (&YR)[kMaxRows], const float (&mu_n)[kMaxL],
+                                    const float (&ls_n)[kMaxL])
 {
     const int L = S.L, R = S.R;
     const uint32_t mm = (uint32_t)a.m;
@@ -281,8 +291,8 @@ __device__ inline int beta_imh_draw(const SegInfo &S, const SweepArgs &a, int64_
         d[l] = (T)0;
         bs[l] = beta[l];
         if (l < L) {
-            const T mu = (T)S.mlp_out[(int64_t)l * Gp + g];
-            const T ls = (T)S.mlp_out[(int64_t)(L + l) * Gp + g];
+            const T mu = (T)mu_n[l];
+            const T ls = (T)ls_n[l];
             bs[l] = mu + dexp(ls) * z[l];
             d[l] = bs[l] - beta[l];
             const T r0 = (beta[l] - mu) * dexp(-ls);
@@ -318,7 +328,7 @@ __device__ inline int beta_imh_draw(const SegInfo &S, const SweepArgs &a, int64_
 template <typename T>
 __device__ inline void beta_finish(const SegInfo &S, const SweepArgs &a, int64_t g, int64_t Gp, bool active,
                                    const T (&beta)[kMaxL], double2 (&mob)[kMaxL], const double (&th)[kMaxL],
-                                   int tile, int lane, int tslot, float *trow, bool sampling, double kmom)
+                                   int tile, int lane, int tslot, float *trow, bool sampling)
 {
     const int L = S.L;
     for (int l = 0; l < L; ++l) {
@@ -329,7 +339,7 @@ __device__ inline void beta_finish(const SegInfo &S, const SweepArgs &a, int64_t
         for (int j = 0; j < kMaxL; ++j)
             if (j == l) { b1 = beta[j]; mo = mob[j]; thl = th[j]; }
         if (active && sampling) {
-            welford(mo, (double)b1, kmom);
+            welford(mo, (double)b1, a.inv_k);
             S.mom_beta[(int64_t)l * Gp + g] = mo;
         }
         if (tslot >= 0) trow[(int64_t)tslot * (L + 1) + 1 + l] = (float)b1;
@@ -343,150 +353,111 @@ __device__ inline void beta_finish(const SegInfo &S, const SweepArgs &a, int64_t
 }
 
 // ---------------------------------------------------------------------------
-// Gene kernel
+// Step 1: eps draws, one lane per (gene, sample)
 // ---------------------------------------------------------------------------
-template <typename T, bool kSplit>
-__global__ __launch_bounds__(256) void gene_sweep(const SegInfo *__restrict__ segs,
-                                                  const int2 *__restrict__ tiles, int ntiles,
-                                                  SweepArgs a, int *err)
+// A work item is (segment, tile, n0, n1): one wavefront draws eps_gn for the
+// 64 genes of the tile and the samples n0 <= n < n1, one sample after the
+// other.  The eps conditional involves only y_gn, h_n, X_n beta_g and gamma_g,
+// so every (gene, sample) draw is independent of the others in the sweep.
+template <typename T>
+__device__ inline void eps_wave(const SegInfo &S, int tile, int n0, int n1, const SweepArgs &a, int *err)
 {
-    const int wave = __builtin_amdgcn_readfirstlane((int)(threadIdx.x >> 6));
     const int lane = (int)(threadIdx.x & 63);
-    const int tix = (int)blockIdx.x * 4 + wave;
-    if (tix >= ntiles) return;
-    const int2 tt = tiles[tix];
-    const int sidx = __builtin_amdgcn_readfirstlane(tt.x);
-    const int tile = __builtin_amdgcn_readfirstlane(tt.y);
-    const SegInfo &S = segs[sidx];
     const int64_t Gp = S.Gp;
     const int64_t g = (int64_t)tile * kTile + lane;
-    const bool active = g < S.G;
-    const int N = S.N, L = S.L, R = S.R;
-    const uint32_t mm = (uint32_t)a.m;
-    const uint32_t chain = (uint32_t)S.chain;
+    if (g >= S.G) return;                 // no cross-lane operations follow
+    const int L = S.L;
+    const uint32_t mm = (uint32_t)a.m, chain = (uint32_t)S.chain;
     const uint32_t k0 = S.key0, k1 = S.key1;
-    const bool tuning = a.m <= a.burnin;
-    const bool sampling = a.m > a.burnin;
-    const double kmom = (double)(a.m - a.burnin);
-    const bool dbg = a.dbg != 0;
-    const bool tracing = a.trace_point >= 0;
-    const bool upd_eps = (a.mask >> 1) & 1u;
-    const bool upd_gam = (a.mask >> 2) & 1u;
-    const bool upd_beta = (a.mask >> 5) & 1u;
-
+    const bool tuning = a.m <= a.burnin, sampling = a.m > a.burnin;
+    const bool upd = (a.mask >> 1) & 1u;
     const int32_t *__restrict__ yp = S.y;
     T *__restrict__ eps = (T *)S.eps;
     T *__restrict__ w_eps = (T *)S.w_eps;
     T *__restrict__ wa_eps = (T *)S.wa_eps;
-    double2 *__restrict__ mom_eps = S.mom_eps;
-    T *__restrict__ gamp = (T *)S.gam;
-    T *__restrict__ betap = (T *)S.beta;
-    T *__restrict__ w_beta = (T *)S.w_beta;
-    T *__restrict__ wa_beta = (T *)S.wa_beta;
-    double2 *__restrict__ mom_beta = S.mom_beta;
-
-    // Hyperparameters of the previous sweep (read once).
-    const HyperState &H = *S.hyp;
-    const double nu = H.nu, tau = H.tau;
-    double th[kMaxL], s2[kMaxL];
+    double2 *__restrict__ mom = S.mom_eps;
+    const T *__restrict__ betap = (const T *)S.beta;
+    T beta[kMaxL];
 #pragma unroll
-    for (int l = 0; l < kMaxL; ++l) {
-        th[l] = l < L ? H.theta[l] : 0.0;
-        s2[l] = l < L ? H.sig2[l] : 1.0;
-    }
-
-    // Everything the gamma and beta steps read is requested now, so its latency
-    // hides behind the eps draws.
-    T beta[kMaxL], wb[kMaxL], wab[kMaxL];
-    double2 mob[kMaxL];
-#pragma unroll
-    for (int l = 0; l < kMaxL; ++l) {
-        const bool on = l < L && active;
-        const int64_t idx = (int64_t)l * Gp + g;
-        beta[l] = on ? betap[idx] : (T)0;
-        wb[l] = (on && upd_beta) ? w_beta[idx] : (T)1;
-        wab[l] = (on && upd_beta && tuning) ? wa_beta[idx] : (T)0;
-        mob[l] = (on && sampling) ? mom_beta[idx] : make_double2(0.0, 0.0);
-    }
-    T gam = active ? gamp[g] : (T)1;
-    T wg = (active && upd_gam) ? ((T *)S.w_gam)[g] : (T)1;
-    T wag = (active && upd_gam && tuning) ? ((T *)S.wa_gam)[g] : (T)0;
-    double2 mog = (active && sampling) ? S.mom_gam[g] : make_double2(0.0, 0.0);
-    const int tslot = (tracing && active) ? S.trace_slot[g] : -1;
-    float *trow = tracing ? S.trace + (int64_t)a.trace_point * S.trace_stride + 2 + 2 * L : nullptr;
-
-    T A[kMaxRows], YR[kMaxRows];
-#pragma unroll
-    for (int r = 0; r < kMaxRows; ++r) { A[r] = (T)0; YR[r] = (T)0; }
-    T S2 = (T)0;
+    for (int l = 0; l < kMaxL; ++l) beta[l] = l < L ? betap[(int64_t)l * Gp + g] : (T)0;
+    const T inv_gam = (T)1 / ((const T *)S.gam)[g];
     int bad = 0;
-
-    // ---- Algorithm 1 step 1: eps_gn, n = 1..N ----
-    // Software pipeline: sample n + 1 is loaded while sample n is drawn.
-    const T inv_gam = (T)1 / gam;
-    if (active) {
-        int y_nx = 0;
-        T e_nx = (T)0, w_nx = (T)1, wa_nx = (T)0;
-        double2 mo_nx = make_double2(0.0, 0.0);
-        auto fetch = [&](int n) {
-            const int64_t idx = (int64_t)n * Gp + g;
-            y_nx = yp[idx];
-            e_nx = eps[idx];
-            if (upd_eps) w_nx = w_eps[idx];
-            if (upd_eps && tuning) wa_nx = wa_eps[idx];
-            if (sampling) mo_nx = mom_eps[idx];
-        };
-        fetch(0);
-        for (int n = 0; n < N; ++n) {
-            const int64_t idx = (int64_t)n * Gp + g;
-            const int yv = y_nx;
-            const T e0 = e_nx;
-            T w = w_nx, wa = wa_nx;
-            double2 mo = mo_nx;
-            if (n + 1 < N) fetch(n + 1);
-            T xb = (T)0;
+    for (int n = n0; n < n1; ++n) {
+        const int64_t idx = (int64_t)n * Gp + g;
+        const int yv = yp[idx];
+        const T e0 = eps[idx];
+        T w = upd ? w_eps[idx] : (T)1;
+        T wa = (upd && tuning) ? wa_eps[idx] : (T)0;
+        double2 mo = sampling ? mom[idx] : make_double2(0.0, 0.0);
+        T xb = (T)0;
 #pragma unroll
-            for (int l = 0; l < kMaxL; ++l)
-                if (l < L) xb += (T)S.X[n * kMaxL + l] * beta[l];
-            const T hn = (T)S.h[n];
-            T e1 = e0;
-            if (upd_eps) {
-                EpsF<T> f{(T)yv, dexp(hn + e0 + xb), e0, inv_gam};
-                DrawRec rec;
-                e1 = slice_draw<T>(f, e0, w, k0, k1, draw_counter((uint32_t)g, 1, (uint32_t)n, mm, chain, 0),
-                                   a.K, a.cap, rec);
-                eps[idx] = e1;
-                if (tuning) {
-                    tune_width<T>(w, wa, e0, e1, a.m, a.burnin, a.tune_start);
-                    w_eps[idx] = w;
-                    wa_eps[idx] = wa;
-                }
-                bad |= rec.bad;
-                if (dbg) S.dbg_eps[idx] = make_int4(rec.kl, rec.nl, rec.nr, rec.nc);
+        for (int l = 0; l < kMaxL; ++l)
+            if (l < L) xb += (T)S.X[n * kMaxL + l] * beta[l];
+        T e1 = e0;
+        if (upd) {
+            EpsF<T> f{(T)yv, dexp((T)S.h[n] + e0 + xb), e0, inv_gam};
+            DrawRec rec;
+            e1 = slice_draw<T>(f, e0, w, k0, k1, draw_counter((uint32_t)g, 1, (uint32_t)n, mm, chain, 0), a.K,
+                               a.cap, rec);
+            eps[idx] = e1;
+            if (tuning) {
+                tune_width<T>(w, wa, e0, e1, a.m, a.burnin, a.tune_start);
+                w_eps[idx] = w;
+                wa_eps[idx] = wa;
             }
-            if (sampling) {
-                welford(mo, (double)e1, kmom);
-                mom_eps[idx] = mo;
-            }
-            S2 += e1 * e1;
-            const T ehe = dexp(hn + e1);
-            const int rr = S.row_of[n];
-#pragma unroll
-            for (int r = 0; r < kMaxRows; ++r)
-                if (r == rr) { A[r] += ehe; YR[r] += (T)yv; }
+            bad |= rec.bad;
+            if (a.dbg) S.dbg_eps[idx] = make_int4(rec.kl, rec.nl, rec.nr, rec.nc);
+        }
+        if (sampling) {
+            welford(mo, (double)e1, a.inv_k);
+            mom[idx] = mo;
         }
     }
+    if (bad) raise_flag(err, 2);
+}
 
-    // ---- step 2: gamma_g ----
+// ---------------------------------------------------------------------------
+// Steps 2 and 5 after the eps draws: gamma_g and beta_g on two wavefronts
+// ---------------------------------------------------------------------------
+// Given eps_g, gamma_g depends on nu and tau only and beta_g on theta and
+// sigma^2 only, so the two draws of a gene are independent and run on
+// separate wavefronts of the tile's workgroup.
+
+// Step 2 (wavefront 0): S_g = sum_n eps_gn^2, one gamma draw, moments, trace
+// and the tile partials of log gamma and 1 / gamma.
+template <typename T>
+__device__ inline void gamma_wave(const SegInfo &S, int tile, const SweepArgs &a, int *err)
+{
+    const int lane = (int)(threadIdx.x & 63);
+    const int64_t Gp = S.Gp;
+    const int64_t g = (int64_t)tile * kTile + lane;
+    const bool active = g < S.G;
+    const int N = S.N, L = S.L;
+    const bool tuning = a.m <= a.burnin, sampling = a.m > a.burnin;
+    const T *__restrict__ eps = (const T *)S.eps;
+    T *__restrict__ gamp = (T *)S.gam;
     double lg = 0.0, ig = 0.0;
+    int bad = 0;
     if (active) {
-        if (upd_gam) {
+        T S2 = (T)0;
+#pragma unroll 8
+        for (int n = 0; n < N; ++n) {
+            const T e = eps[(int64_t)n * Gp + g];
+            S2 += e * e;
+        }
+        T gam = gamp[g];
+        if ((a.mask >> 2) & 1u) {
+            const HyperState &H = *S.hyp;
+            const double nu = H.nu, tau = H.tau;
+            T wg = ((T *)S.w_gam)[g];
+            T wag = tuning ? ((T *)S.wa_gam)[g] : (T)0;
             const double alpha1 = 0.5 * nu + 0.5 * N + 1.0;
             const double scale = 0.5 * nu * tau + 0.5 * (double)S2;
             GamF<T> f{(T)alpha1, (T)scale, gam};
             DrawRec rec;
-            const T g1 = slice_draw<T>(f, gam, wg, k0, k1, draw_counter((uint32_t)g, 2, 0, mm, chain, 0),
-                                       a.K, a.cap, rec);
+            const T g1 = slice_draw<T>(f, gam, wg, S.key0, S.key1,
+                                       draw_counter((uint32_t)g, 2, 0, (uint32_t)a.m, (uint32_t)S.chain, 0), a.K,
+                                       a.cap, rec);
             if (tuning) {
                 tune_width<T>(wg, wag, gam, g1, a.m, a.burnin, a.tune_start);
                 ((T *)S.w_gam)[g] = wg;
@@ -495,70 +466,48 @@ __global__ __launch_bounds__(256) void gene_sweep(const SegInfo *__restrict__ se
             gam = g1;
             gamp[g] = g1;
             bad |= rec.bad;
-            if (dbg) S.dbg_gam[g] = make_int4(rec.kl, rec.nl, rec.nr, rec.nc);
+            if (a.dbg) S.dbg_gam[g] = make_int4(rec.kl, rec.nl, rec.nr, rec.nc);
         }
         if (sampling) {
-            welford(mog, (double)gam, kmom);
+            double2 mog = S.mom_gam[g];
+            welford(mog, (double)gam, a.inv_k);
             S.mom_gam[g] = mog;
         }
         lg = ::log((double)gam);
         ig = 1.0 / (double)gam;
-        if (tslot >= 0) trow[(int64_t)tslot * (L + 1)] = (float)gam;
-    }
-    {
-        const double s0 = wave_sum(lg), s1 = wave_sum(ig);
-        if (lane == 0) {
-            S.partials[(int64_t)tile * kMaxParts + 0] = s0;
-            S.partials[(int64_t)tile * kMaxParts + 1] = s1;
+        if (a.trace_point >= 0) {
+            const int tslot = S.trace_slot[g];
+            if (tslot >= 0)
+                S.trace[(int64_t)a.trace_point * S.trace_stride + 2 + 2 * L + (int64_t)tslot * (L + 1)] = (float)gam;
         }
     }
-
-    if constexpr (kSplit) {
-        // split sweep: leave the row sums for the beta kernel
-        if (active) {
-            T *__restrict__ Arp = (T *)S.Ar;
-#pragma unroll
-            for (int r = 0; r < kMaxRows; ++r)
-                if (r < R) Arp[(int64_t)r * Gp + g] = A[r];
-        }
-        if (bad) raise_flag(err, 2);
-        return;
+    const double s0 = wave_sum(lg), s1 = wave_sum(ig);
+    if (lane == 0) {
+        S.partials[(int64_t)tile * kMaxParts + 0] = s0;
+        S.partials[(int64_t)tile * kMaxParts + 1] = s1;
     }
-
-    // ---- step 5: beta_gl, l = 1..L in order ----
-    T C[kMaxRows];
-    row_sums_at_beta<T>(S, A, beta, C);
-    if (active && upd_beta)
-        beta_slice_draws<T>(S, a, g, Gp, beta, wb, wab, th, s2, C, YR, tuning, bad);
-    beta_finish<T>(S, a, g, Gp, active, beta, mob, th, tile, lane, tslot, trow, sampling, kmom);
     if (bad) raise_flag(err, 2);
 }
 
-// ---------------------------------------------------------------------------
-// Beta kernel of the split sweep: independence MH with the learned proposal
-// where the fallback mask is 0, slice draws elsewhere
-// ---------------------------------------------------------------------------
-template <typename T>
-__global__ __launch_bounds__(256) void beta_sweep(const SegInfo *__restrict__ segs,
-                                                  const int2 *__restrict__ tiles, int ntiles,
-                                                  SweepArgs a, int *err)
+// The network on the 64 feature rows of a wavefront (defined below).
+__device__ inline void mlp_rows(const float (&phi)[32], bool active, const MlpDev *__restrict__ net, int L,
+                                float (&mu)[kMaxL], float (&ls)[kMaxL]);
+
+// Step 5 (wavefront 1): the row sums A_r = sum over the samples of row r of
+// exp(h_n + eps_gn), then beta_g1..beta_gL by slice draws, or, with the
+// learned proposal, one independence MH step for the block where the gene's
+// fallback flag is 0; moments, trace, training pairs and the tile partials
+// of (beta_l - theta_l) and its square.
+template <typename T, bool kLearned>
+__device__ inline void beta_wave(const SegInfo &S, int tile, const SweepArgs &a, const MlpDev *__restrict__ net,
+                                 int *err)
 {
-    const int wave = __builtin_amdgcn_readfirstlane((int)(threadIdx.x >> 6));
     const int lane = (int)(threadIdx.x & 63);
-    const int tix = (int)blockIdx.x * 4 + wave;
-    if (tix >= ntiles) return;
-    const int2 tt = tiles[tix];
-    const int sidx = __builtin_amdgcn_readfirstlane(tt.x);
-    const int tile = __builtin_amdgcn_readfirstlane(tt.y);
-    const SegInfo &S = segs[sidx];
     const int64_t Gp = S.Gp;
     const int64_t g = (int64_t)tile * kTile + lane;
     const bool active = g < S.G;
-    const int L = S.L, R = S.R;
-    const bool tuning = a.m <= a.burnin;
-    const bool sampling = a.m > a.burnin;
-    const double kmom = (double)(a.m - a.burnin);
-    const bool tracing = a.trace_point >= 0;
+    const int N = S.N, L = S.L, R = S.R;
+    const bool tuning = a.m <= a.burnin, sampling = a.m > a.burnin;
     const bool upd_beta = (a.mask >> 5) & 1u;
     const HyperState &H = *S.hyp;
     double th[kMaxL], s2[kMaxL];
@@ -573,49 +522,79 @@ __global__ __launch_bounds__(256) void beta_sweep(const SegInfo *__restrict__ se
     for (int l = 0; l < kMaxL; ++l) {
         const bool on = l < L && active;
         const int64_t idx = (int64_t)l * Gp + g;
-        beta[l] = on ? ((T *)S.beta)[idx] : (T)0;
-        wb[l] = (on && upd_beta) ? ((T *)S.w_beta)[idx] : (T)1;
-        wab[l] = (on && upd_beta && tuning) ? ((T *)S.wa_beta)[idx] : (T)0;
+        beta[l] = on ? ((const T *)S.beta)[idx] : (T)0;
+        wb[l] = (on && upd_beta) ? ((const T *)S.w_beta)[idx] : (T)1;
+        wab[l] = (on && upd_beta && tuning) ? ((const T *)S.wa_beta)[idx] : (T)0;
         mob[l] = (on && sampling) ? S.mom_beta[idx] : make_double2(0.0, 0.0);
     }
     T A[kMaxRows], YR[kMaxRows];
 #pragma unroll
     for (int r = 0; r < kMaxRows; ++r) {
-        const bool on = r < R && active;
-        A[r] = on ? ((const T *)S.Ar)[(int64_t)r * Gp + g] : (T)0;
-        YR[r] = on ? ((const T *)S.YR)[(int64_t)r * Gp + g] : (T)0;
+        A[r] = (T)0;
+        YR[r] = (r < R && active) ? ((const T *)S.YR)[(int64_t)r * Gp + g] : (T)0;
     }
-    const int tslot = (tracing && active) ? S.trace_slot[g] : -1;
-    float *trow = tracing ? S.trace + (int64_t)a.trace_point * S.trace_stride + 2 + 2 * L : nullptr;
-    // training pairs: the features the beta step saw, then the new beta
-    float *pair = (a.pair_base >= 0 && active) ? S.pairs + (a.pair_base + g) * kPairStride : nullptr;
-    if (pair) {
-        float phi[32];
-        gene_features<T>(S, A, YR, th, s2, phi);
+    if (active) {
+        const T *__restrict__ eps = (const T *)S.eps;
+#pragma unroll 8
+        for (int n = 0; n < N; ++n) {
+            const T ehe = dexp((T)S.h[n] + eps[(int64_t)n * Gp + g]);
+            const int rr = S.row_of[n];
 #pragma unroll
-        for (int k = 0; k < 32; ++k) pair[k] = phi[k];
+            for (int r = 0; r < kMaxRows; ++r)
+                if (r == rr) A[r] += ehe;
+        }
     }
+    const int tslot = (a.trace_point >= 0 && active) ? S.trace_slot[g] : -1;
+    float *trow = a.trace_point >= 0 ? S.trace + (int64_t)a.trace_point * S.trace_stride + 2 + 2 * L : nullptr;
     T C[kMaxRows];
     row_sums_at_beta<T>(S, A, beta, C);
     int bad = 0;
-    if (active && upd_beta) {
-        const bool use_imh = a.learned && S.fallback[g] == 0;
-        if (use_imh) {
-            const int acc = beta_imh_draw<T>(S, a, g, Gp, beta, th, s2, C, YR);
-            S.imh_last[g] = acc;
-            if (a.count_imh) S.imh_count[g] += acc;
-        } else {
-            beta_slice_draws<T>(S, a, g, Gp, beta, wb, wab, th, s2, C, YR, tuning, bad);
-            S.imh_last[g] = -1;
-        }
-    }
-    if (pair) {
+    if constexpr (kLearned) {
+        float phi[32], mu[kMaxL], ls[kMaxL];
+        gene_features<T>(S, A, YR, th, s2, phi);
+        // training pairs: the features the beta step saw, then the new beta
+        float *pair = (a.pair_base >= 0 && active) ? S.pairs + (a.pair_base + g) * kPairStride : nullptr;
+        if (pair) {
 #pragma unroll
-        for (int l = 0; l < kMaxL; ++l)
-            if (l < L) pair[32 + l] = (float)beta[l];
+            for (int k = 0; k < 32; ++k) pair[k] = phi[k];
+        }
+        if (a.learned) mlp_rows(phi, active, net, L, mu, ls);
+        if (active && upd_beta) {
+            if (a.learned && S.fallback[g] == 0) {
+                const int acc = beta_imh_draw<T>(S, a, g, Gp, beta, th, s2, C, YR, mu, ls);
+                S.imh_last[g] = acc;
+                if (a.count_imh) S.imh_count[g] += acc;
+            } else {
+                beta_slice_draws<T>(S, a, g, Gp, beta, wb, wab, th, s2, C, YR, tuning, bad);
+                S.imh_last[g] = -1;
+            }
+        }
+        if (pair) {
+#pragma unroll
+            for (int l = 0; l < kMaxL; ++l)
+                if (l < L) pair[32 + l] = (float)beta[l];
+        }
+    } else {
+        if (active && upd_beta) beta_slice_draws<T>(S, a, g, Gp, beta, wb, wab, th, s2, C, YR, tuning, bad);
     }
-    beta_finish<T>(S, a, g, Gp, active, beta, mob, th, tile, lane, tslot, trow, sampling, kmom);
+    beta_finish<T>(S, a, g, Gp, active, beta, mob, th, tile, lane, tslot, trow, sampling);
     if (bad) raise_flag(err, 2);
+}
+
+
+template <typename T, bool kLearned>
+__global__ __launch_bounds__(128) void gb_sweep(const SegInfo *__restrict__ segs, const int2 *__restrict__ tiles,
+                                                int ntiles, SweepArgs a, const MlpDev *__restrict__ net, int *err)
+{
+    const int wave = __builtin_amdgcn_readfirstlane((int)(threadIdx.x >> 6));
+    const int tix = (int)blockIdx.x;
+    if (tix >= ntiles) return;
+    const int2 tt = tiles[tix];
+    const int sidx = __builtin_amdgcn_readfirstlane(tt.x);
+    const int tile = __builtin_amdgcn_readfirstlane(tt.y);
+    const SegInfo &S = segs[sidx];
+    if (wave == 0) gamma_wave<T>(S, tile, a, err);
+    else beta_wave<T, kLearned>(S, tile, a, net, err);
 }
 
 // ---------------------------------------------------------------------------
@@ -665,7 +644,8 @@ __device__ inline void mlp_layer(const __bf16 *__restrict__ in, int in_stride, c
 }
 
 // The network on the 64 feature rows a wavefront holds (phi of lane = row);
-// writes mu and ls of the lane's row.  All 64 lanes call.
+// writes mu and ls of the lane's row.  All 64 lanes of one wavefront call; the
+// LDS buffers belong to the workgroup and only one of its wavefronts uses them.
 __device__ inline void mlp_rows(const float (&phi)[32], bool active, const MlpDev *__restrict__ net, int L,
                                 float (&mu)[kMaxL], float (&ls)[kMaxL])
 {
@@ -679,13 +659,13 @@ __device__ inline void mlp_rows(const float (&phi)[32], bool active, const MlpDe
         const float x = active ? (phi[k] - net->fmean[k]) * net->fscale[k] : 0.0f;
         xs[lane * kXs + k] = (__bf16)x;
     }
-    __syncthreads();
+    wave_lds_sync();
     mlp_layer<kMlpF, kMlpH, true>(xs, kXs, net->W1p, net->b1, h1, nullptr, kHs);
-    __syncthreads();
+    wave_lds_sync();
     mlp_layer<kMlpH, kMlpH, true>(h1, kHs, net->W2p, net->b2, h2, nullptr, kHs);
-    __syncthreads();
+    wave_lds_sync();
     mlp_layer<kMlpH, kMlpO, false>(h2, kHs, net->W3p, net->b3, nullptr, os, kOs);
-    __syncthreads();
+    wave_lds_sync();
 #pragma unroll
     for (int l = 0; l < kMaxL; ++l) {
         mu[l] = 0.0f;
@@ -697,49 +677,6 @@ __device__ inline void mlp_rows(const float (&phi)[32], bool active, const MlpDe
     }
 }
 
-template <typename T>
-__global__ __launch_bounds__(64) void feat_mlp(const SegInfo *__restrict__ segs, const int2 *__restrict__ tiles,
-                                               int ntiles, const MlpDev *__restrict__ net)
-{
-    const int lane = (int)threadIdx.x;
-    const int tix = (int)blockIdx.x;
-    if (tix >= ntiles) return;
-    const int2 tt = tiles[tix];
-    const int sidx = __builtin_amdgcn_readfirstlane(tt.x);
-    const int tile = __builtin_amdgcn_readfirstlane(tt.y);
-    const SegInfo &S = segs[sidx];
-    const int64_t Gp = S.Gp;
-    const int64_t g = (int64_t)tile * kTile + lane;
-    const bool active = g < S.G;
-    const int L = S.L, R = S.R;
-    const HyperState &H = *S.hyp;
-    double th[kMaxL], s2[kMaxL];
-#pragma unroll
-    for (int l = 0; l < kMaxL; ++l) {
-        th[l] = l < L ? H.theta[l] : 0.0;
-        s2[l] = l < L ? H.sig2[l] : 1.0;
-    }
-    T A[kMaxRows], YR[kMaxRows];
-#pragma unroll
-    for (int r = 0; r < kMaxRows; ++r) {
-        const bool on = r < R && active;
-        A[r] = on ? ((const T *)S.Ar)[(int64_t)r * Gp + g] : (T)1;
-        YR[r] = on ? ((const T *)S.YR)[(int64_t)r * Gp + g] : (T)0;
-    }
-    float phi[32], mu[kMaxL], ls[kMaxL];
-    gene_features<T>(S, A, YR, th, s2, phi);
-    mlp_rows(phi, active, net, L, mu, ls);
-    if (active) {
-        for (int l = 0; l < L; ++l) {
-            float m = 0.0f, v = 0.0f;
-#pragma unroll
-            for (int j = 0; j < kMaxL; ++j)
-                if (j == l) { m = mu[j]; v = ls[j]; }
-            S.mlp_out[(int64_t)l * Gp + g] = m;
-            S.mlp_out[(int64_t)(L + l) * Gp + g] = v;
-        }
-    }
-}
 
 // The network on raw feature rows phi [B][32] (tests): mu, ls [B][L].
 __global__ __launch_bounds__(64) void mlp_infer_raw(const float *__restrict__ phi, int64_t B, int L,
@@ -864,79 +801,69 @@ hipError_t launch_col_moments(const float *M, int64_t rows, int cols, double *ou
     return hipGetLastError();
 }
 
-hipError_t launch_feat_mlp(int precision, const SegInfo *segs, const int2 *tiles, int ntiles, const MlpDev *net,
-                           hipStream_t st)
-{
-    if (ntiles == 0) return hipSuccess;
-    if (precision == 0)
-        hipLaunchKernelGGL((feat_mlp<double>), dim3(ntiles), dim3(64), 0, st, segs, tiles, ntiles, net);
-    else
-        hipLaunchKernelGGL((feat_mlp<float>), dim3(ntiles), dim3(64), 0, st, segs, tiles, ntiles, net);
-    return hipGetLastError();
-}
+// ---------------------------------------------------------------------------
+// Hyperparameter step: one 256-thread workgroup per segment
+// ---------------------------------------------------------------------------
+// Fixed-order FP64 reduction of the tile partials, then the draws on separate
+// wavefronts: (nu, then tau) on wavefront 0, (theta_l, then sigma_l^2) on
+// wavefront 1 + (l mod 3).  The pairs are conditionally independent of one
+// another (nu and tau involve only gamma; theta_l and sigma_l^2 only column l
+// of beta), so with counter-based random numbers their order does not matter.
+constexpr int kHyperThreads = 256;
+constexpr int kHyperWaves = kHyperThreads / 64;
 
-// ---------------------------------------------------------------------------
-// Hyperparameter kernel: one 256-thread workgroup per segment
-// ---------------------------------------------------------------------------
-__global__ __launch_bounds__(256) void hyper_sweep(const SegInfo *__restrict__ segs, SweepArgs a,
-                                                   int *err)
+__device__ inline void hyper_block(const SegInfo &S, const SweepArgs &a, int *err)
 {
-    const SegInfo &S = segs[blockIdx.x];
     const int L = S.L;
     const int nparts = 2 + 2 * L;
     const int tid = (int)threadIdx.x;
     const int lane = tid & 63, wave = tid >> 6;
-    __shared__ double part[4][kMaxParts];
-    // The whole hyperparameter state is staged in LDS: the draws below are a
-    // short serial chain, and LDS keeps each dependent access at LDS latency.
+    __shared__ double part[kHyperWaves][kMaxParts];
+    __shared__ double red[kMaxParts];
+    __shared__ double words[kHyperWaves][20];
+    // The hyperparameter state is staged in LDS: the draws are short serial
+    // chains, and LDS keeps each dependent access at LDS latency.
     __shared__ HyperState H;
     constexpr int kWords = (int)(sizeof(HyperState) / sizeof(double));
     static_assert(sizeof(HyperState) % sizeof(double) == 0, "HyperState must be whole doubles");
     double *hs = reinterpret_cast<double *>(&H);
     const double *hg = reinterpret_cast<const double *>(S.hyp);
-    for (int i = tid; i < kWords; i += 256) hs[i] = hg[i];
+    for (int i = tid; i < kWords; i += kHyperThreads) hs[i] = hg[i];
 
-    // Fixed-order reduction: thread t sums tiles t, t + 256, ... in order, then a
-    // butterfly inside each wavefront, then the four wavefronts in order.
-    double acc[kMaxParts];
-#pragma unroll
-    for (int j = 0; j < kMaxParts; ++j) acc[j] = 0.0;
-    for (int64_t t = tid; t < S.ntiles; t += 256) {
-#pragma unroll
-        for (int j = 0; j < kMaxParts; ++j)
-            if (j < nparts) acc[j] += S.partials[t * kMaxParts + j];
+    // thread t sums tiles t, t + 256, ... in order; a butterfly inside each
+    // wavefront; the wavefronts in order
+    for (int j = 0; j < nparts; ++j) {
+        double acc = 0.0;
+        for (int64_t t = tid; t < S.ntiles; t += kHyperThreads) acc += S.partials[t * kMaxParts + j];
+        acc = wave_sum(acc);
+        if (lane == 0) part[wave][j] = acc;
     }
-#pragma unroll
-    for (int j = 0; j < kMaxParts; ++j) {
-        const double v = wave_sum(acc[j]);
-        if (lane == 0) part[wave][j] = v;
+    __syncthreads();
+    if (tid < nparts) {
+        double s = 0.0;
+        for (int w = 0; w < kHyperWaves; ++w) s += part[w][tid];
+        red[tid] = s;
     }
     __syncthreads();
 
-    // The draws: wavefront 0, every lane computing the same values; the slice
-    // draws evaluate their points across the lanes (slice_draw_wave).
-    __shared__ double words[64];
+    const double G = (double)S.G;
+    const uint32_t k0 = S.key0, k1 = S.key1;
+    const uint32_t mm = (uint32_t)a.m;
+    const uint32_t chain = (uint32_t)S.chain;
+    const bool sampling = a.m > a.burnin;
+    const bool w0 = lane == 0;
+    float *trow = a.trace_point >= 0 ? S.trace + (int64_t)a.trace_point * S.trace_stride : nullptr;
+    double *wd = &words[wave][0];
+    int bad = 0;
+    DrawRec rec;
     if (wave == 0) {
-        double red[kMaxParts];
-        for (int j = 0; j < nparts; ++j) red[j] = ((part[0][j] + part[1][j]) + part[2][j]) + part[3][j];
-        const double G = (double)S.G;
-        const double pa = S.a, pb = S.b, pd = S.d;
-        const uint32_t k0 = S.key0, k1 = S.key1;
-        const uint32_t mm = (uint32_t)a.m;
-        const uint32_t chain = (uint32_t)S.chain;
-        const bool sampling = a.m > a.burnin;
-        const double kmom = (double)(a.m - a.burnin);
-        const bool w0 = lane == 0;
-        int bad = 0;
-        DrawRec rec;
         double nu = H.nu, tau = H.tau;
-
         // step 3: nu
         if ((a.mask >> 3) & 1u) {
-            NuF f{G, tau, red[0], red[1], pd};
+            NuF f{G, tau, red[0], red[1], S.d};
             double w = H.w_nu, wa = H.wa_nu;
-            const double x1 = slice_draw_wave(f, nu, w, k0, k1, draw_counter(0, 3, 0, mm, chain, 0), a.K,
-                                              a.cap, rec, words);
+            const double x1 = slice_draw_wave(f, nu, w, k0, k1, draw_counter(0, 3, 0, mm, chain, 0), a.K, a.cap,
+                                              rec, wd);
             tune_width<double>(w, wa, nu, x1, a.m, a.burnin, a.tune_start);
             nu = x1;
             if (w0) { H.nu = x1; H.w_nu = w; H.wa_nu = wa; }
@@ -945,19 +872,29 @@ __global__ __launch_bounds__(256) void hyper_sweep(const SegInfo *__restrict__ s
         }
         // step 4: tau
         if ((a.mask >> 4) & 1u) {
-            TauF f{pa + 0.5 * G * nu - 1.0, pb + 0.5 * nu * red[1]};
+            TauF f{S.a + 0.5 * G * nu - 1.0, S.b + 0.5 * nu * red[1]};
             double w = H.w_tau, wa = H.wa_tau;
-            const double x1 = slice_draw_wave(f, tau, w, k0, k1, draw_counter(0, 4, 0, mm, chain, 0), a.K,
-                                              a.cap, rec, words);
+            const double x1 = slice_draw_wave(f, tau, w, k0, k1, draw_counter(0, 4, 0, mm, chain, 0), a.K, a.cap,
+                                              rec, wd);
             tune_width<double>(w, wa, tau, x1, a.m, a.burnin, a.tune_start);
             tau = x1;
             if (w0) { H.tau = x1; H.w_tau = w; H.wa_tau = wa; }
             bad |= rec.bad;
             if (a.dbg && w0) H.dbg[1] = make_int4(rec.kl, rec.nl, rec.nr, rec.nc);
         }
+        if (w0) {
+            H.red[0] = red[0];
+            H.red[1] = red[1];
+            if (sampling) {
+                welford(H.mom[0], nu, a.inv_k);
+                welford(H.mom[1], tau, a.inv_k);
+            }
+            if (trow) { trow[0] = (float)nu; trow[1] = (float)tau; }
+        }
+    } else {
         // steps 6 and 7: theta_l then sigma_l^2.  The partials are sums of
         // (beta - s) and (beta - s)^2 with the shift s = theta_l before this step.
-        for (int l = 0; l < L; ++l) {
+        for (int l = wave - 1; l < L; l += kHyperWaves - 1) {
             const double s = H.theta[l];
             const double d1 = red[2 + 2 * l], d2 = red[3 + 2 * l];
             const double sb = d1 + G * s;
@@ -968,53 +905,71 @@ __global__ __launch_bounds__(256) void hyper_sweep(const SegInfo *__restrict__ s
                 const double prec = G / sig2 + 1.0 / (cl * cl);
                 const double mean = (sb / sig2) / prec;
                 const uint4 r = philox4x32_10(draw_counter(0, 6, (uint32_t)l, mm, chain, 0), k0, k1);
-                const double zn = ::sqrt(-2.0 * ::log(u01<double>(r.x))) *
-                                  ::cos(6.283185307179586 * u01<double>(r.y));
+                const double zn = ::sqrt(-2.0 * ::log(u01<double>(r.x))) * ::cos(6.283185307179586 * u01<double>(r.y));
                 th = mean + zn / ::sqrt(prec);
             }
             const double dt = th - s;
             const double Ssq = d2 - 2.0 * dt * d1 + G * dt * dt;
-            red[2 + 2 * l] = sb;
-            red[3 + 2 * l] = Ssq;
             double s2new = sig2;
             double w = H.w_sig2[l], wa = H.wa_sig2[l];
             if ((a.mask >> 7) & 1u) {
                 const double sl = S.s[l];
                 Sig2F f{0.5 * (G + 1.0), Ssq, sl * sl};
                 s2new = slice_draw_wave(f, sig2, w, k0, k1, draw_counter(0, 7, (uint32_t)l, mm, chain, 0), a.K,
-                                        a.cap, rec, words);
+                                        a.cap, rec, wd);
                 tune_width<double>(w, wa, sig2, s2new, a.m, a.burnin, a.tune_start);
                 bad |= rec.bad;
                 if (a.dbg && w0) H.dbg[2 + l] = make_int4(rec.kl, rec.nl, rec.nr, rec.nc);
             }
-            if (w0) { H.theta[l] = th; H.sig2[l] = s2new; H.w_sig2[l] = w; H.wa_sig2[l] = wa; }
-            if (sampling && w0) {
-                welford(H.mom[2 + l], th, kmom);
-                welford(H.mom[2 + L + l], s2new, kmom);
+            if (w0) {
+                H.theta[l] = th;
+                H.sig2[l] = s2new;
+                H.w_sig2[l] = w;
+                H.wa_sig2[l] = wa;
+                H.red[2 + 2 * l] = sb;
+                H.red[3 + 2 * l] = Ssq;
+                if (sampling) {
+                    welford(H.mom[2 + l], th, a.inv_k);
+                    welford(H.mom[2 + L + l], s2new, a.inv_k);
+                }
+                if (trow) { trow[2 + l] = (float)th; trow[2 + L + l] = (float)s2new; }
             }
-            if (a.trace_point >= 0 && w0) {
-                float *row = S.trace + (int64_t)a.trace_point * S.trace_stride;
-                row[2 + l] = (float)th;
-                row[2 + L + l] = (float)s2new;
-            }
-        }
-        if (w0) {
-            for (int j = 0; j < nparts; ++j) H.red[j] = red[j];
-            if (sampling) {
-                welford(H.mom[0], nu, kmom);
-                welford(H.mom[1], tau, kmom);
-            }
-            if (a.trace_point >= 0) {
-                float *row = S.trace + (int64_t)a.trace_point * S.trace_stride;
-                row[0] = (float)nu;
-                row[1] = (float)tau;
-            }
-            if (bad) raise_flag(err, 2);
         }
     }
+    if (bad && w0) raise_flag(err, 2);
     __syncthreads();
     double *hw = reinterpret_cast<double *>(S.hyp);
-    for (int i = tid; i < kWords; i += 256) hw[i] = hs[i];
+    for (int i = tid; i < kWords; i += kHyperThreads) hw[i] = hs[i];
+}
+
+__global__ __launch_bounds__(kHyperThreads) void hyper_sweep(const SegInfo *__restrict__ segs, SweepArgs a, int *err)
+{
+    hyper_block(segs[blockIdx.x], a, err);
+}
+
+// Step 1 of sweep a.m over the work items; when nhyp > 0 the first nhyp
+// workgroups run the hyperparameter step of the previous sweep ha.m (one per
+// segment) alongside, since no eps conditional involves a hyperparameter.
+// The register budget is set for the eps wavefronts (7 per SIMD); the FP64
+// hyperparameter code, which runs on one workgroup per segment, spills.
+template <typename T>
+__global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(7, 8))) void eps_sweep(
+    const SegInfo *__restrict__ segs, const int4 *__restrict__ items, int nitems, SweepArgs a, int nhyp,
+    SweepArgs ha, int *err)
+{
+    if ((int)blockIdx.x < nhyp) {
+        hyper_block(segs[blockIdx.x], ha, err);
+        return;
+    }
+    const int wave = __builtin_amdgcn_readfirstlane((int)(threadIdx.x >> 6));
+    const int it = ((int)blockIdx.x - nhyp) * 4 + wave;
+    if (it >= nitems) return;
+    const int4 w = items[it];
+    const int sidx = __builtin_amdgcn_readfirstlane(w.x);
+    const int tile = __builtin_amdgcn_readfirstlane(w.y);
+    const int n0 = __builtin_amdgcn_readfirstlane(w.z);
+    const int n1 = __builtin_amdgcn_readfirstlane(w.w);
+    eps_wave<T>(segs[sidx], tile, n0, n1, a, err);
 }
 
 __global__ void philox_kernel(const uint4 *ctr, const uint2 *key, uint4 *out, int64_t n)
@@ -1026,45 +981,36 @@ __global__ void philox_kernel(const uint4 *ctr, const uint2 *key, uint4 *out, in
 // ---------------------------------------------------------------------------
 // Launchers
 // ---------------------------------------------------------------------------
-hipError_t launch_gene(int precision, const SegInfo *segs, const int2 *tiles, int ntiles,
-                       const SweepArgs &a, int *err, hipStream_t st)
+hipError_t launch_eps(int precision, const SegInfo *segs, const int4 *items, int nitems, const SweepArgs &a,
+                      int nhyp, const SweepArgs &ha, int *err, hipStream_t st)
 {
-    const int blocks = (ntiles + 3) / 4;
+    const int blocks = nhyp + (nitems + 3) / 4;
     if (blocks == 0) return hipSuccess;
     if (precision == 0)
-        hipLaunchKernelGGL((gene_sweep<double, false>), dim3(blocks), dim3(256), 0, st, segs, tiles, ntiles, a, err);
+        hipLaunchKernelGGL((eps_sweep<double>), dim3(blocks), dim3(256), 0, st, segs, items, nitems, a, nhyp, ha, err);
     else
-        hipLaunchKernelGGL((gene_sweep<float, false>), dim3(blocks), dim3(256), 0, st, segs, tiles, ntiles, a, err);
+        hipLaunchKernelGGL((eps_sweep<float>), dim3(blocks), dim3(256), 0, st, segs, items, nitems, a, nhyp, ha, err);
     return hipGetLastError();
 }
 
-hipError_t launch_split(int precision, const SegInfo *segs, const int2 *tiles, int ntiles,
-                        const SweepArgs &a, int *err, hipStream_t st)
+hipError_t launch_gb(int precision, bool learned, const SegInfo *segs, const int2 *tiles, int ntiles,
+                     const SweepArgs &a, const MlpDev *net, int *err, hipStream_t st)
 {
-    const int blocks = (ntiles + 3) / 4;
-    if (blocks == 0) return hipSuccess;
-    if (precision == 0)
-        hipLaunchKernelGGL((gene_sweep<double, true>), dim3(blocks), dim3(256), 0, st, segs, tiles, ntiles, a, err);
-    else
-        hipLaunchKernelGGL((gene_sweep<float, true>), dim3(blocks), dim3(256), 0, st, segs, tiles, ntiles, a, err);
-    return hipGetLastError();
-}
-
-hipError_t launch_beta(int precision, const SegInfo *segs, const int2 *tiles, int ntiles,
-                       const SweepArgs &a, int *err, hipStream_t st)
-{
-    const int blocks = (ntiles + 3) / 4;
-    if (blocks == 0) return hipSuccess;
-    if (precision == 0)
-        hipLaunchKernelGGL((beta_sweep<double>), dim3(blocks), dim3(256), 0, st, segs, tiles, ntiles, a, err);
-    else
-        hipLaunchKernelGGL((beta_sweep<float>), dim3(blocks), dim3(256), 0, st, segs, tiles, ntiles, a, err);
+    if (ntiles == 0) return hipSuccess;
+    const dim3 grid(ntiles), block(128);
+    if (precision == 0) {
+        if (learned) hipLaunchKernelGGL((gb_sweep<double, true>), grid, block, 0, st, segs, tiles, ntiles, a, net, err);
+        else hipLaunchKernelGGL((gb_sweep<double, false>), grid, block, 0, st, segs, tiles, ntiles, a, net, err);
+    } else {
+        if (learned) hipLaunchKernelGGL((gb_sweep<float, true>), grid, block, 0, st, segs, tiles, ntiles, a, net, err);
+        else hipLaunchKernelGGL((gb_sweep<float, false>), grid, block, 0, st, segs, tiles, ntiles, a, net, err);
+    }
     return hipGetLastError();
 }
 
 hipError_t launch_hyper(const SegInfo *segs, int nseg, const SweepArgs &a, int *err, hipStream_t st)
 {
-    hipLaunchKernelGGL(hyper_sweep, dim3(nseg), dim3(256), 0, st, segs, a, err);
+    hipLaunchKernelGGL(hyper_sweep, dim3(nseg), dim3(kHyperThreads), 0, st, segs, a, err);
     return hipGetLastError();
 }
 

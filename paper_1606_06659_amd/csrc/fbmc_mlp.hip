@@ -1,7 +1,7 @@
 // fbmc_mlp.hip -- the learned beta proposal's network on gfx950 matrix cores.
 //
 // The network maps a gene's 32 features to (mu_l, log s_l), l = 1..L, with two
-// 128-wide GELU layers (F = 32 -> H = 128 -> H = 128 -> O = 16 padded outputs).
+// 128-wide GELU layers (F = 32 -> H = 128 -> H = 128 -> O = 32 padded outputs).
 // Products use v_mfma_f32_32x32x16_bf16: BF16 operands, FP32 accumulation.
 // Weights and activations live in FP32; a fragment is rounded to BF16 as it is
 // loaded into the matrix core.

@@ -80,6 +80,7 @@ struct SweepArgs {
     int64_t m;            // sweep index (1-based)
     int64_t burnin;       // M_B
     int64_t tune_start;   // M_C
+    double inv_k;         // 1 / (m - M_B) once m > M_B: weight of the running moments
     int32_t K;            // step-out budget
     int32_t cap;          // shrink cap
     uint32_t mask;        // update mask

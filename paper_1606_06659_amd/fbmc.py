@@ -67,7 +67,8 @@ EXPORTS = [
     "fb_default_options", "fb_create", "fb_create_batch", "fb_destroy", "fb_sweep", "fb_sync",
     "fb_num_segments", "fb_segment_dims", "fb_get_state", "fb_set_state", "fb_summaries",
     "fb_trace_genes", "fb_trace", "fb_trace_reset", "fb_debug_counts", "fb_reductions",
-    "fb_philox", "fb_last_sweep_time", "fb_profile", "fb_kernel_times", "fb_last_error",
+    "fb_philox", "fb_last_sweep_time", "fb_profile", "fb_kernel_times", "fb_set_launch",
+    "fb_get_launch", "fb_autotune", "fb_last_error",
     "fb_strerror", "fb_default_train_opts", "fb_proposal_collect", "fb_proposal_train",
     "fb_proposal_calibrate", "fb_set_beta_update", "fb_proposal_get", "fb_proposal_set",
     "fb_fallback", "fb_imh_last", "fb_features", "fb_mfma_probe", "fb_mlp_forward",
@@ -112,7 +113,10 @@ def load() -> C.CDLL:
     L.fb_philox.argtypes = [up, up, up, i64]
     L.fb_last_sweep_time.argtypes = [vp, _DP, C.POINTER(i64)]
     L.fb_profile.argtypes = [vp, i32, i32]
-    L.fb_kernel_times.argtypes = [vp, _DP, _DP, C.POINTER(i64)]
+    L.fb_kernel_times.argtypes = [vp, _DP, _DP, _DP, C.POINTER(i64)]
+    L.fb_set_launch.argtypes = [vp, i32, i32]
+    L.fb_get_launch.argtypes = [vp, C.POINTER(i32), C.POINTER(i32)]
+    L.fb_autotune.argtypes = [vp, i32, C.POINTER(i32), C.POINTER(i32), _DP]
     L.fb_last_error.argtypes = [vp]
     L.fb_last_error.restype = C.c_char_p
     L.fb_strerror.argtypes = [i32]
@@ -315,10 +319,30 @@ def fb_profile(ctx, every: int, max_samples: int):
 
 
 def fb_kernel_times(ctx):
-    """(mean gene-kernel ms, mean hyper-kernel ms, samples) of the sampled sweeps."""
-    g, h, n = C.c_double(), C.c_double(), C.c_int64()
-    _check(load().fb_kernel_times(ctx, C.byref(g), C.byref(h), C.byref(n)), ctx)
-    return g.value, h.value, n.value
+    """(mean eps-kernel ms, mean gamma/beta-kernel ms, mean separate
+    hyperparameter-kernel ms or 0 when fused, samples) of the sampled sweeps."""
+    e, g, h, n = C.c_double(), C.c_double(), C.c_double(), C.c_int64()
+    _check(load().fb_kernel_times(ctx, C.byref(e), C.byref(g), C.byref(h), C.byref(n)), ctx)
+    return e.value, g.value, h.value, n.value
+
+
+def fb_set_launch(ctx, samples_per_wave: int, fuse_hyper: int):
+    _check(load().fb_set_launch(ctx, int(samples_per_wave), int(fuse_hyper)), ctx)
+
+
+def fb_get_launch(ctx):
+    """(samples per eps wavefront, fused hyperparameter step 0/1)."""
+    a, b = C.c_int32(), C.c_int32()
+    _check(load().fb_get_launch(ctx, C.byref(a), C.byref(b)), ctx)
+    return a.value, b.value
+
+
+def fb_autotune(ctx, trial_sweeps: int = 20):
+    """Time every launch shape on snapshots of the state and keep the fastest:
+    (samples per wavefront, fused 0/1, ms per sweep)."""
+    a, b, t = C.c_int32(), C.c_int32(), C.c_double()
+    _check(load().fb_autotune(ctx, int(trial_sweeps), C.byref(a), C.byref(b), C.byref(t)), ctx)
+    return a.value, b.value, t.value
 
 
 class Sampler:

@@ -235,3 +235,99 @@ def test_determinism_and_resume():
     F.fb_destroy(g)
     for k in STATE_KEYS:
         assert np.array_equal(end[k], outs[0][k]), k
+
+
+SHAPES = [(1, 1), (1, 0), (3, 1), (16, 0), (16, 1)]
+
+
+@pytest.mark.parametrize("precision", [0, 1])
+def test_launch_shapes_give_identical_chains(precision):
+    """Every draw is a function of its counter only: the samples per eps
+    wavefront and fusing the hyperparameter step into the next eps launch
+    change no bit of the state, the moments or the trace."""
+    F = require_gpu()
+    ds = datagen.paper_design_16(G=1500, seed=5)
+    outs = []
+    for spw, fuse in SHAPES:
+        say("shape", spw, fuse, "precision", precision)
+        opts = F.fb_default_options(burnin=15, tune_start=3, precision=precision, jitter=0, thin=1,
+                                    trace_genes=10, trace_capacity=40, debug_counts=1)
+        g = F.fb_create(ds.y, ds.X, ds.h, seed=6, options=opts)
+        F.fb_set_launch(g, spw, fuse)
+        assert F.fb_get_launch(g) == (spw, fuse)
+        F.fb_sweep(g, 7)
+        F.fb_sweep(g, 1)
+        F.fb_sweep(g, 22)
+        st = F.fb_get_state(g)
+        summ = F.fb_summaries(g)
+        tr, _ = F.fb_trace(g)
+        cnt = F.fb_debug_counts(g)
+        outs.append((st, summ, tr, cnt))
+        F.fb_destroy(g)
+    ref = outs[0]
+    for (spw, fuse), (st, summ, tr, cnt) in zip(SHAPES[1:], outs[1:]):
+        for k in STATE_KEYS:
+            assert np.array_equal(st[k], ref[0][k]), (spw, fuse, k)
+        for k in summ:
+            assert np.array_equal(np.asarray(summ[k]), np.asarray(ref[1][k])), (spw, fuse, k)
+        assert np.array_equal(tr, ref[2]), (spw, fuse)
+        for k in cnt:
+            assert np.array_equal(cnt[k], ref[3][k]), (spw, fuse, k)
+
+
+def test_autotune_leaves_the_chain_unchanged():
+    F = require_gpu()
+    ds = datagen.paper_design_16(G=2000, seed=7)
+    opts = F.fb_default_options(burnin=10, tune_start=2, precision=1, jitter=0, thin=1,
+                                trace_genes=5, trace_capacity=100)
+    a = F.fb_create(ds.y, ds.X, ds.h, seed=8, options=opts)
+    F.fb_sweep(a, 30)
+    sa, ta = F.fb_get_state(a), F.fb_trace(a)[0]
+    F.fb_destroy(a)
+    b = F.fb_create(ds.y, ds.X, ds.h, seed=8, options=opts)
+    F.fb_sweep(b, 12)
+    spw, fuse, ms = F.fb_autotune(b, 3)
+    say("autotune chose", spw, fuse, ms)
+    assert F.fb_get_launch(b) == (spw, fuse) and ms > 0
+    F.fb_sweep(b, 18)
+    sb, tb = F.fb_get_state(b), F.fb_trace(b)[0]
+    F.fb_destroy(b)
+    for k in STATE_KEYS:
+        assert np.array_equal(sa[k], sb[k]), k
+    assert np.array_equal(ta, tb)
+
+
+@pytest.mark.parametrize("precision", [0, 1])
+def test_batched_segments_match_single_runs(precision):
+    """Datasets of uneven G, N and L, each with two chains, in one context: every
+    (dataset, chain) segment is bit-identical to the same dataset run alone
+    (its draws use the dataset's seed and the chain index only; its
+    reductions cover its own tiles only)."""
+    F = require_gpu()
+    meta = [(300, 4), (1000, 16), (77, 8), (2500, 4), (64, 16)]
+    dss = [datagen.batched_dataset(k + 1, G, N) for k, (G, N) in enumerate(meta)]
+    opts = dict(burnin=10, tune_start=2, precision=precision, jitter=1, chains=2, thin=1,
+                trace_genes=8, trace_capacity=30, debug_counts=1)
+    b = F.fb_create_batch([dict(counts=d.y, X=d.X, h=d.h, seed=100 + k) for k, d in enumerate(dss)],
+                          F.fb_default_options(**opts))
+    assert F.fb_num_segments(b) == 2 * len(dss)
+    F.fb_set_launch(b, 2, 1)
+    F.fb_sweep(b, 25)
+    for k, d in enumerate(dss):
+        s = F.fb_create(d.y, d.X, d.h, seed=100 + k, options=F.fb_default_options(**opts))
+        F.fb_sweep(s, 25)
+        for ch in range(2):
+            seg = 2 * k + ch
+            dims = F.fb_segment_dims(b, seg)
+            assert (dims["dataset"], dims["chain"], dims["G"], dims["N"]) == (k, ch, d.G, d.N)
+            sb, ss = F.fb_get_state(b, seg), F.fb_get_state(s, ch)
+            for key in STATE_KEYS:
+                assert np.array_equal(sb[key], ss[key]), (k, ch, key)
+            mb, ms = F.fb_summaries(b, seg), F.fb_summaries(s, ch)
+            for key in ("mean_beta", "msq_gam", "mean_hyp"):
+                assert np.array_equal(mb[key], ms[key]), (k, ch, key)
+            assert np.array_equal(F.fb_trace(b, seg)[0], F.fb_trace(s, ch)[0]), (k, ch)
+        # the two chains of a dataset differ
+        assert not np.array_equal(F.fb_get_state(b, 2 * k)["beta"], F.fb_get_state(b, 2 * k + 1)["beta"])
+        F.fb_destroy(s)
+    F.fb_destroy(b)
