@@ -66,6 +66,94 @@ def cpu_baseline(ds, seconds: float = 15.0):
                        f"(FP64, OpenMP over genes, {dt:.1f} s)")
 
 
+def run_chain(fbmc, diagnostics, ds, args, burnin, post, do_ess, stream, learned):
+    """One chain of the workload: `burnin` sweeps, then `post` post-burn-in
+    sweeps of which `steps` (after `warmup`) are timed.  With learned=True the
+    last 1,000 burn-in sweeps adapt the learned beta proposal: 400 plain sweeps
+    store training pairs (every 4th sweep, 100 x G pairs), the network is
+    trained on the GPU, 200 sweeps with the IMH step everywhere calibrate the
+    fallback mask (acceptance < 0.2 keeps the slice steps), and the remaining
+    burn-in and every post-burn-in sweep use the learned step."""
+    N, L = ds.N, ds.L
+    opts = fbmc.fb_default_options(
+        burnin=burnin, tune_start=burnin // 10, precision=fbmc.FB_FP32, jitter=0,
+        thin=1 if do_ess else 0, trace_genes=TRACE_GENES if do_ess else 0,
+        trace_after_burnin=1, trace_capacity=post if do_ess else 0,
+        stream=stream.cuda_stream)
+    smp = fbmc.Sampler(ds.y, ds.X, ds.h, seed=1, **{k: getattr(opts, k) for k, *_ in opts._fields_})
+    proposal = None
+    if learned:
+        adapt = min(1000, burnin)
+        smp.sweep(burnin - adapt)
+        fbmc.fb_proposal_collect(smp.ctx, adapt * 2 // 5, every=4)
+        smp.sync()
+        t0 = time.perf_counter()
+        losses = fbmc.fb_proposal_train(smp.ctx, fbmc.fb_default_train_opts(epochs=300))
+        smp.sync()
+        train_s = time.perf_counter() - t0
+        fbmc.fb_proposal_calibrate(smp.ctx, adapt // 5, 0.2)
+        fbmc.fb_set_beta_update(smp.ctx, fbmc.FB_BETA_LEARNED)
+        smp.sweep(adapt - adapt * 2 // 5 - adapt // 5)
+        smp.sync()
+        fb = fbmc.fb_fallback(smp.ctx)
+        proposal = {"training_pairs": int(adapt * 2 // 5 // 4) * ds.G, "epochs": 300,
+                    "train_seconds": train_s, "loss_first": float(losses[0]), "loss_last": float(losses[-1]),
+                    "fallback_fraction": float(fb.mean())}
+    else:
+        smp.sweep(burnin)
+        smp.sync()
+    if args.launch == "auto":
+        spw, fuse, ms, tried = fbmc.fb_autotune(smp.ctx, 50)
+        shape = {"samples_per_wave": spw, "fused_hyper": fuse, "autotuned_ms_per_sweep": ms,
+                 "tried_ms_per_sweep": {f"{k[0]},{k[1]}": v for k, v in tried.items()}}
+    else:
+        spw, fuse = (int(v) for v in args.launch.split(","))
+        fbmc.fb_set_launch(smp.ctx, spw, fuse)
+        shape = {"samples_per_wave": spw, "fused_hyper": fuse}
+
+    import torch
+    torch.cuda.synchronize()
+    t_post0 = time.perf_counter()
+    smp.sweep(args.warmup)
+    # timed window: exactly `steps` sweeps, events around every 10th sweep's launches
+    fbmc.fb_profile(smp.ctx, 10, args.steps // 10 + 1)
+    smp.sync()
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    smp.sweep(args.steps)
+    smp.sync()
+    torch.cuda.synchronize()
+    t1 = time.perf_counter()
+    kt = fbmc.fb_kernel_times(smp.ctx)
+    fbmc.fb_profile(smp.ctx, 0, 0)
+    if learned:
+        last = fbmc.fb_imh_last(smp.ctx)
+        imh = last >= 0
+        proposal["accept_rate_last_sweep"] = float(np.mean(last[imh] == 1)) if imh.any() else None
+    rest = post - args.warmup - args.steps
+    if rest > 0:
+        smp.sweep(rest)
+    smp.sync()
+    torch.cuda.synchronize()
+    t_post1 = time.perf_counter()
+    ess_info = None
+    if do_ess:
+        tr, dropped = smp.trace()
+        T = len(smp.trace_genes())
+        genes = tr[:, 2 + 2 * L:].reshape(tr.shape[0], T, L + 1)[:, :, 1:]   # beta [M, T, L]
+        series = genes.reshape(tr.shape[0], -1).T.astype(np.float64)          # [T*L, M]
+        ess = diagnostics.ess_batch(series)
+        post_time = t_post1 - t_post0
+        ess_info = dict(min_ess=float(np.nanmin(ess)), median_ess=float(np.nanmedian(ess)),
+                        post_burnin_sweeps=int(tr.shape[0]), post_burnin_seconds=post_time,
+                        min_ess_per_s=float(np.nanmin(ess)) / post_time,
+                        median_ess_per_s=float(np.nanmedian(ess)) / post_time,
+                        traced=f"{T} genes x {L} coefficients", dropped=dropped)
+    smp.close()
+    return dict(sweeps_per_s=args.steps / (t1 - t0), ms_per_sweep=(t1 - t0) * 1e3 / args.steps,
+                kernel_ms=kt, launch=shape, ess=ess_info, proposal=proposal)
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -74,7 +162,11 @@ def main():
     ap.add_argument("--genes", type=int, default=50_000)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-ess", action="store_true")
-    ap.add_argument("--no-autotune", action="store_true")
+    ap.add_argument("--no-learned", action="store_true", help="skip the learned-proposal chain")
+    ap.add_argument("--launch", default="auto",
+                    help="'auto' (autotuner) or 'SPW,FUSE': samples per eps wavefront, fused hyper step 0/1")
+    ap.add_argument("--burnin", type=int, default=BURNIN,
+                    help="burn-in sweeps (profiling runs shorten it; the bench line uses the default)")
     ap.add_argument("--copy-mib", type=int, default=0,
                     help="first run a plain device copy of this many MiB (counter calibration)")
     args = ap.parse_args()
@@ -92,7 +184,8 @@ def main():
     ds = datagen.paper_design_16(G=args.genes, seed=0)
     N, L, G = ds.N, ds.L, ds.G
     do_ess = not args.no_ess
-    post = max(TOTAL_ITERS - BURNIN, args.warmup + args.steps) if do_ess else args.warmup + args.steps
+    burnin = args.burnin
+    post = max(TOTAL_ITERS - burnin, args.warmup + args.steps) if do_ess else args.warmup + args.steps
     if args.copy_mib > 0:
         # a copy of known size: FETCH_SIZE and WRITE_SIZE of this kernel give the
         # counters' bytes-per-reported-KiB scale on this device
@@ -103,44 +196,13 @@ def main():
             dst.copy_(src)
         torch.cuda.synchronize()
         del src, dst
-    opts = fbmc.fb_default_options(
-        burnin=BURNIN, tune_start=BURNIN // 10, precision=fbmc.FB_FP32, jitter=0,
-        thin=1 if do_ess else 0, trace_genes=TRACE_GENES if do_ess else 0,
-        trace_after_burnin=1, trace_capacity=post if do_ess else 0,
-        stream=stream.cuda_stream)
-    smp = fbmc.Sampler(ds.y, ds.X, ds.h, seed=1, **{k: getattr(opts, k) for k, *_ in opts._fields_})
-
-    # burn-in (tunes the slice widths), untimed
-    smp.sweep(BURNIN)
-    smp.sync()
-    if args.no_autotune:
-        shape = fbmc.fb_get_launch(smp.ctx) + (None,)
-    else:
-        shape = fbmc.fb_autotune(smp.ctx, 50)
-
-    torch.cuda.synchronize()
-    t_post0 = time.perf_counter()
-    smp.sweep(args.warmup)
-    # timed window: exactly `steps` sweeps, events around every 10th gene launch
-    fbmc.fb_profile(smp.ctx, 10, args.steps // 10 + 1)
-    smp.sync()
-    torch.cuda.synchronize()
-    t0 = time.perf_counter()
-    smp.sweep(args.steps)
-    smp.sync()
-    torch.cuda.synchronize()
-    t1 = time.perf_counter()
-    eps_ms, gb_ms, hyp_ms, nsamp = fbmc.fb_kernel_times(smp.ctx)
-    fbmc.fb_profile(smp.ctx, 0, 0)
-    rest = post - args.warmup - args.steps
-    if rest > 0:
-        smp.sweep(rest)
-    smp.sync()
-    torch.cuda.synchronize()
-    t_post1 = time.perf_counter()
-
-    ms_per_step = (t1 - t0) * 1e3 / args.steps
-    sweeps_per_s = args.steps / (t1 - t0)
+    plain = run_chain(fbmc, diagnostics, ds, args, burnin, post, do_ess, stream, learned=False)
+    learned = None if args.no_learned else run_chain(fbmc, diagnostics, ds, args, burnin, post, do_ess,
+                                                      stream, learned=True)
+    sweeps_per_s = plain["sweeps_per_s"]
+    ms_per_step = plain["ms_per_sweep"]
+    shape = plain["launch"]
+    eps_ms, gb_ms, hyp_ms, nsamp = plain["kernel_ms"]
     b_eps, b_gb, b_sweep = algorithmic_bytes(N, L, 4)
     gbs = lambda nbytes, ms: nbytes / (ms * 1e-3) / 1e9 if ms > 0 else None
     kernels = {
@@ -148,25 +210,22 @@ def main():
                       "achieved_GBs": gbs(b_eps * G, eps_ms)},
         "gb_sweep": {"ms": gb_ms, "bytes_per_gene": b_gb, "bytes_per_launch": b_gb * G,
                      "achieved_GBs": gbs(b_gb * G, gb_ms)},
-        "hyper_sweep": {"ms": hyp_ms, "fused_into_eps_sweep": bool(shape[1])},
+        "hyper_sweep": {"ms": hyp_ms, "fused_into_eps_sweep": bool(shape["fused_hyper"])},
         "samples": nsamp,
     }
     dom = "eps_sweep" if eps_ms >= gb_ms else "gb_sweep"
     achieved = kernels[dom]["achieved_GBs"]
-
-    ess_info = None
-    if do_ess:
-        tr, dropped = smp.trace()
-        T = len(smp.trace_genes())
-        genes = tr[:, 2 + 2 * L:].reshape(tr.shape[0], T, L + 1)[:, :, 1:]   # beta [M, T, L]
-        series = genes.reshape(tr.shape[0], -1).T.astype(np.float64)          # [T*L, M]
-        ess = diagnostics.ess_batch(series)
-        post_time = t_post1 - t_post0
-        ess_info = dict(min_ess=float(np.nanmin(ess)), median_ess=float(np.nanmedian(ess)),
-                        post_burnin_sweeps=int(tr.shape[0]), post_burnin_seconds=post_time,
-                        min_ess_per_s=float(np.nanmin(ess)) / post_time,
-                        traced=f"{T} genes x {L} coefficients", dropped=dropped)
-    smp.close()
+    ess_info = plain["ess"]
+    if learned is not None:
+        learned_info = {k: learned[k] for k in ("sweeps_per_s", "ms_per_sweep", "ess", "launch", "proposal",
+                                                "kernel_ms")}
+        learned_info["min_ess_per_s"] = None if learned["ess"] is None else learned["ess"]["min_ess_per_s"]
+        if learned["ess"] is not None and ess_info is not None:
+            learned_info["min_ess_per_s_ratio_vs_plain"] = (learned["ess"]["min_ess_per_s"] /
+                                                            ess_info["min_ess_per_s"])
+        learned_info["sweeps_per_s_ratio_vs_plain"] = learned["sweeps_per_s"] / sweeps_per_s
+    else:
+        learned_info = None
 
     line = {
         "metric": "Gibbs sweeps/s + min-ESS/s of beta at G=50k,N=16; learned vs plain proposal",
@@ -183,12 +242,11 @@ def main():
         "data": "synthetic (model simulation, seed 0)",
         "config": {"workload": f"paper design G={G} N={N} L={L}, 1 chain, plain slice sweep",
                    "genes": G, "samples": N, "coefficients": L, "chains": 1,
-                   "burnin": BURNIN, "iterations": BURNIN + post,
-                   "launch": {"samples_per_wave": shape[0], "fused_hyper": shape[1],
-                              "autotuned_ms_per_sweep": shape[2]}},
+                   "burnin": burnin, "iterations": burnin + post,
+                   "launch": shape},
         "min_ess_per_s": None if ess_info is None else ess_info["min_ess_per_s"],
         "ess": ess_info,
-        "learned_proposal": None,
+        "learned_proposal": learned_info,
         "kernels": kernels,
         "roofline": {"bound": "hbm", "kernel": dom, "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
                      "frac": None if achieved is None else achieved / HBM_PEAK_GBS,

@@ -230,20 +230,21 @@ int fb_kernel_times(fb_ctx *c, double *eps_ms, double *gb_ms, double *hyper_ms, 
  *   fuse_hyper        1: the hyperparameter step of sweep m runs in the first
  *                     workgroups of sweep m + 1's eps kernel (no eps conditional
  *                     involves a hyperparameter); 0: a kernel of its own
- * Defaults: 1 and 1.  FB_EINVAL outside these ranges. */
+ * Defaults: 1 and 1.  FB_EINVAL outside these values. */
 int fb_set_launch(fb_ctx *c, int32_t samples_per_wave, int32_t fuse_hyper);
 int fb_get_launch(const fb_ctx *c, int32_t *samples_per_wave, int32_t *fuse_hyper);
 
 /* Autotuner: times trial_sweeps sweeps (after 2 warm-up sweeps) for every
- * samples_per_wave in {1, 2, 4, 8} (up to max N) with and without fusion,
+ * samples_per_wave in {1, 2, 4, 8} (up to max N), with and without fusion,
  * starting each trial from a device snapshot of the state, then restores the
- * snapshot and keeps the fastest shape.  The chain continues exactly as if no
- * trial had run (traces and training pairs are not written by the trials; the
- * time reported by fb_last_sweep_time is the last trial's).  Outputs (may be
- * NULL): the chosen shape and its time per sweep (ms).  Needs device memory
- * for one copy of the state. */
+ * snapshot and keeps the fastest shape.  The chain continues exactly as if no trial had run (traces
+ * and training pairs are not written by the trials; the time reported by
+ * fb_last_sweep_time is the last trial's).  Outputs (each may be NULL): the
+ * chosen shape, its time per sweep (ms), and table[8], the time per sweep of shape
+ * k = 2 log2(samples_per_wave) + fuse_hyper, -1 if not tried.  Needs device
+ * memory for one copy of the state. */
 int fb_autotune(fb_ctx *c, int32_t trial_sweeps, int32_t *samples_per_wave, int32_t *fuse_hyper,
-                double *ms_per_sweep);
+                double *ms_per_sweep, double *table);
 
 /* ------------------------------------------------------------------------
  * Learned beta proposal (independence Metropolis-Hastings for the block beta_g)
@@ -251,11 +252,15 @@ int fb_autotune(fb_ctx *c, int32_t trial_sweeps, int32_t *samples_per_wave, int3
  * A network maps 32 features of gene g -- for each distinct row r of X,
  * log((Y_r + 1/2) / A_r) and log(Y_r + 1/2) with Y_r the row's count sum and
  * A_r = sum over the row's samples of exp(h_n + eps_gn); then theta_l and
- * log sigma_l^2; zero-padded -- to a Gaussian proposal N(mu, diag(exp(ls))^2)
- * for beta_g.  The features never involve beta_g, so one step with exact
- * acceptance probability leaves the beta_g full conditional invariant.
+ * log sigma_l^2; zero-padded -- to a Gaussian proposal N(mu, Lc Lc^T) for
+ * beta_g with a lower-triangular factor Lc (the beta_g conditional is
+ * correlated across l).  The features never involve beta_g, so one step with
+ * exact acceptance probability leaves the beta_g full conditional invariant.
  * Network: x = (phi - fmean) * fscale; h1 = gelu(x W1 + b1); h2 = gelu(h1 W2 + b2);
- * o = h2 W3 + b3; mu_l = omean_l + oscale_l o_l; ls_l = log(oscale_l) + o_{L+l}
+ * o = h2 W3 + b3 (O = 2L + L(L-1)/2 outputs used);
+ *   mu_l = omean_l + oscale_l o_l,
+ *   Lc_ll = exp(ls_l), ls_l = log(oscale_l) + o_{L+l},
+ *   Lc_lj = oscale_l o_{2L + l(l-1)/2 + j} for j < l
  * (gelu in the erf form).  Products run on the matrix cores with BF16
  * operands and FP32 accumulation; parameters are kept in FP32.
  * ---------------------------------------------------------------------- */
@@ -266,7 +271,7 @@ typedef struct {
     float *fmean, *fscale;   /* [32] input standardisation */
     float *W1, *b1;          /* [32][128], [128] */
     float *W2, *b2;          /* [128][128], [128] */
-    float *W3, *b3;          /* [128][32], [32]; outputs >= 2L are unused */
+    float *W3, *b3;          /* [128][64], [64]; outputs >= 2L + L(L-1)/2 are unused */
     float *omean, *oscale;   /* [8]; the first L are used */
 } fb_mlp;
 
@@ -310,11 +315,14 @@ int fb_features(fb_ctx *c, int32_t seg, float *phi);
 
 /* Device kernels of the network on host data (tests): one matrix-core product
  * of A [32][16] and B [16][32] into C [32][32]; the network's outputs for raw
- * features phi [B][32] (mu, ls: [B][L]); and the mean loss and its gradients
+ * features phi [B][32] (mu, ls: [B][L]; off: [B][L(L-1)/2], the factor's
+ * strict lower triangle in units of oscale, row-major; off may be NULL); and
+ * the mean loss sum_l ls_l + |u|^2 / 2 (Lc u = target - mu) and its gradients
  * for targets [B][L] (B a multiple of 32; gradients of fmean, fscale, omean,
  * oscale are zero). */
 int fb_mfma_probe(const float *A, const float *B, float *C);
-int fb_mlp_forward(const fb_mlp *w, int32_t L, const float *phi, int64_t B, float *mu, float *ls);
+int fb_mlp_forward(const fb_mlp *w, int32_t L, const float *phi, int64_t B, float *mu, float *ls,
+                   float *off);
 int fb_mlp_loss_grad(const fb_mlp *w, int32_t L, const float *phi, const float *target, int64_t B,
                      float *loss, fb_mlp *grad);
 

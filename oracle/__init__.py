@@ -31,7 +31,9 @@ def build(force: bool = True, mutant: int = 0) -> str:
 
     mutant > 0 builds a deliberately wrong variant (tests of the pins only)."""
     so = _so_path(mutant)
-    if force or not os.path.exists(so):
+    srcs = [os.path.join(_HERE, f) for f in ("oracle.c", "mlp.c", "oracle.h")]
+    stale = not os.path.exists(so) or any(os.path.getmtime(f) > os.path.getmtime(so) for f in srcs)
+    if force or stale:
         os.makedirs(os.path.dirname(so), exist_ok=True)
         cmd = ["gcc", "-O2", "-std=gnu11", "-fPIC", "-shared", "-fopenmp",
                "-fno-fast-math", "-ffp-contract=off", f"-DOR_MUTANT={int(mutant)}",
@@ -264,7 +266,7 @@ def _mlp_lib(L):
     if getattr(L, "_mlp_ready", False):
         return L
     dp = C.POINTER(C.c_double)
-    L.or_mlp_forward.argtypes = [C.POINTER(_Mlp), dp, C.c_int64, dp, dp]
+    L.or_mlp_forward.argtypes = [C.POINTER(_Mlp), dp, C.c_int64, dp, dp, dp]
     L.or_mlp_loss_grad.argtypes = [C.POINTER(_Mlp), dp, dp, C.c_int64, dp, dp, dp, dp, dp, dp, dp]
     L.or_set_proposal.argtypes = [C.c_void_p, C.POINTER(_Mlp), C.POINTER(C.c_int32)]
     L.or_features.argtypes = [C.c_void_p, C.c_int32, dp]
@@ -274,16 +276,29 @@ def _mlp_lib(L):
     return L
 
 
+def mlp_coefs(O: int) -> int:
+    """L of a network with O = 2L + L(L-1)/2 outputs."""
+    for L in range(1, 17):
+        if 2 * L + L * (L - 1) // 2 == O:
+            return L
+    raise ValueError(f"no L has {O} outputs")
+
+
+def mlp_outputs(L: int) -> int:
+    return 2 * L + L * (L - 1) // 2
+
+
 def mlp_forward(m: dict, phi, _lib=None):
+    """(mu [B, L], ls [B, L], off [B, L(L-1)/2]) of feature rows phi [B, F]."""
     L = _mlp_lib(_lib or lib())
     keep = []
     st = _mlp_struct(m, keep)
     phi = np.ascontiguousarray(phi, dtype=np.float64).reshape(-1, int(m["F"]))
-    B, Lc = phi.shape[0], int(m["O"]) // 2
-    mu, ls = np.empty((B, Lc)), np.empty((B, Lc))
-    if L.or_mlp_forward(C.byref(st), _p(phi), B, _p(mu), _p(ls)) != 0:
+    B, Lc = phi.shape[0], mlp_coefs(int(m["O"]))
+    mu, ls, off = np.empty((B, Lc)), np.empty((B, Lc)), np.empty((B, Lc * (Lc - 1) // 2))
+    if L.or_mlp_forward(C.byref(st), _p(phi), B, _p(mu), _p(ls), _p(off)) != 0:
         raise ValueError("or_mlp_forward failed")
-    return mu, ls
+    return mu, ls, off
 
 
 def mlp_loss_grad(m: dict, phi, target, grads=True, _lib=None):
@@ -292,7 +307,7 @@ def mlp_loss_grad(m: dict, phi, target, grads=True, _lib=None):
     st = _mlp_struct(m, keep)
     F, H, O = int(m["F"]), int(m["H"]), int(m["O"])
     phi = np.ascontiguousarray(phi, dtype=np.float64).reshape(-1, F)
-    tgt = np.ascontiguousarray(target, dtype=np.float64).reshape(-1, O // 2)
+    tgt = np.ascontiguousarray(target, dtype=np.float64).reshape(-1, mlp_coefs(O))
     g = dict(W1=np.empty((F, H)), b1=np.empty(H), W2=np.empty((H, H)), b2=np.empty(H),
              W3=np.empty((H, O)), b3=np.empty(O)) if grads else {}
     loss = C.c_double()

@@ -4,16 +4,20 @@
  *
  * The proposal is an independence Metropolis-Hastings step for beta_g (the
  * block of L coefficients of one gene) whose proposal density is a Gaussian
- * with mean mu and log-scale ls given by a small MLP of per-gene features:
+ * N(mu, Lc Lc^T) with mean and lower-triangular factor given by a small MLP
+ * of per-gene features:
  *
  *   input   x = (phi - fmean) * fscale                           [F]
  *   z1 = x W1 + b1,  h1 = gelu(z1)                                [H]
  *   z2 = h1 W2 + b2, h2 = gelu(z2)                                [H]
- *   o  = h2 W3 + b3                                               [2L]
- *   mu_l = omean_l + oscale_l o_l,  ls_l = log(oscale_l) + o_{L+l}
+ *   o  = h2 W3 + b3                                  [O = 2L + L(L-1)/2]
+ *   mu_l  = omean_l + oscale_l o_l
+ *   Lc_ll = exp(ls_l),  ls_l = log(oscale_l) + o_{L+l}
+ *   Lc_lj = oscale_l o_{2L + l(l-1)/2 + j}   (j < l; zero above the diagonal)
  *
- * with gelu(z) = z Phi(z) (the erf form).  Weights are row-major with the
- * input index first: z1_j = b1_j + sum_i x_i W1[i][j].
+ * so Lc = diag(oscale) Ls, with Ls the factor in units of oscale.  gelu(z) =
+ * z Phi(z) (the erf form).  Weights are row-major with the input index first:
+ * z1_j = b1_j + sum_i x_i W1[i][j].
  *
  * Features of gene g (any function of y_g, eps_g, h, theta, sigma^2 -- never
  * of beta_g, so the proposal does not depend on the current value and the
@@ -26,7 +30,9 @@
  * zero beyond 2R + 2L.
  *
  * Training loss (Gaussian negative log likelihood of a target beta), averaged
- * over the batch: sum_l [ls_l + (t_l - mu_l)^2 exp(-2 ls_l) / 2].
+ * over the batch: sum_l ls_l + |u|^2 / 2 with Lc u = t - mu (forward
+ * substitution).  With zero off-diagonal outputs this is
+ * sum_l [ls_l + (t_l - mu_l)^2 exp(-2 ls_l) / 2].
  */
 #include <math.h>
 #include <stdint.h>
@@ -66,10 +72,18 @@ static void fwd(const or_mlp *m, const double *phi, double *x, double *z1, doubl
     }
 }
 
-int or_mlp_forward(const or_mlp *m, const double *phi, int64_t B, double *mu, double *ls)
+int or_mlp_coefs(int O)
+{
+    for (int L = 1; L <= 16; ++L)
+        if (2 * L + L * (L - 1) / 2 == O) return L;
+    return -1;
+}
+
+int or_mlp_forward(const or_mlp *m, const double *phi, int64_t B, double *mu, double *ls, double *off)
 {
     if (!m || !phi || B < 0 || m->F > OR_MLP_MAXW || m->H > OR_MLP_MAXW || m->O > OR_MLP_MAXW) return -1;
-    const int L = m->O / 2;
+    const int L = or_mlp_coefs(m->O), K = L * (L - 1) / 2;
+    if (L < 1) return -1;
     double x[OR_MLP_MAXW], z1[OR_MLP_MAXW], h1[OR_MLP_MAXW], z2[OR_MLP_MAXW], h2[OR_MLP_MAXW], o[OR_MLP_MAXW];
     for (int64_t b = 0; b < B; ++b) {
         fwd(m, phi + b * m->F, x, z1, h1, z2, h2, o);
@@ -77,8 +91,27 @@ int or_mlp_forward(const or_mlp *m, const double *phi, int64_t B, double *mu, do
             if (mu) mu[b * L + l] = m->omean[l] + m->oscale[l] * o[l];
             if (ls) ls[b * L + l] = log(m->oscale[l]) + o[L + l];
         }
+        if (off)
+            for (int k = 0; k < K; ++k) off[b * K + k] = o[2 * L + k];
     }
     return 0;
+}
+
+/* u with Lc u = d: Lc_ll = oscale_l exp(o_{L+l}), Lc_lj = oscale_l o_{2L+l(l-1)/2+j}. */
+void or_mlp_solve(const or_mlp *m, int L, const double *o, const double *d, double *u)
+{
+    for (int l = 0; l < L; ++l) {
+        double s = d[l] / m->oscale[l];
+        for (int j = 0; j < l; ++j) s -= o[2 * L + l * (l - 1) / 2 + j] * u[j];
+        u[l] = s / exp(o[L + l]);
+    }
+}
+
+/* The raw outputs o of one feature row. */
+void or_mlp_outputs(const or_mlp *m, const double *phi, double *o)
+{
+    double x[OR_MLP_MAXW], z1[OR_MLP_MAXW], h1[OR_MLP_MAXW], z2[OR_MLP_MAXW], h2[OR_MLP_MAXW];
+    fwd(m, phi, x, z1, h1, z2, h2, o);
 }
 
 int or_mlp_loss_grad(const or_mlp *m, const double *phi, const double *target, int64_t B,
@@ -86,8 +119,8 @@ int or_mlp_loss_grad(const or_mlp *m, const double *phi, const double *target, i
                      double *gW3, double *gb3)
 {
     if (!m || !phi || !target || B < 1) return -1;
-    const int F = m->F, H = m->H, O = m->O, L = O / 2;
-    if (F > OR_MLP_MAXW || H > OR_MLP_MAXW || O > OR_MLP_MAXW) return -1;
+    const int F = m->F, H = m->H, O = m->O, L = or_mlp_coefs(O);
+    if (F > OR_MLP_MAXW || H > OR_MLP_MAXW || O > OR_MLP_MAXW || L < 1) return -1;
     if (gW1) memset(gW1, 0, sizeof(double) * (size_t)F * H);
     if (gb1) memset(gb1, 0, sizeof(double) * (size_t)H);
     if (gW2) memset(gW2, 0, sizeof(double) * (size_t)H * H);
@@ -96,18 +129,26 @@ int or_mlp_loss_grad(const or_mlp *m, const double *phi, const double *target, i
     if (gb3) memset(gb3, 0, sizeof(double) * (size_t)O);
     double x[OR_MLP_MAXW], z1[OR_MLP_MAXW], h1[OR_MLP_MAXW], z2[OR_MLP_MAXW], h2[OR_MLP_MAXW], o[OR_MLP_MAXW];
     double dO[OR_MLP_MAXW], dZ2[OR_MLP_MAXW], dZ1[OR_MLP_MAXW];
+    double d[OR_MLP_MAXW], u[OR_MLP_MAXW], v[OR_MLP_MAXW];
     double total = 0.0;
     const double invB = 1.0 / (double)B;
     for (int64_t b = 0; b < B; ++b) {
         fwd(m, phi + b * F, x, z1, h1, z2, h2, o);
+        for (int l = 0; l < L; ++l) d[l] = target[b * L + l] - (m->omean[l] + m->oscale[l] * o[l]);
+        or_mlp_solve(m, L, o, d, u);
+        /* v = Ls^{-T} u (back substitution on the factor in units of oscale) */
+        for (int l = L - 1; l >= 0; --l) {
+            double s = u[l];
+            for (int i = l + 1; i < L; ++i) s -= o[2 * L + i * (i - 1) / 2 + l] * v[i];
+            v[l] = s / exp(o[L + l]);
+        }
+        for (int l = 0; l < L; ++l) total += log(m->oscale[l]) + o[L + l] + 0.5 * u[l] * u[l];
+        /* d/d o: mean -v_l; log-diagonal 1 - v_l u_l Ls_ll; off-diagonal (l, j) -v_l u_j */
+        for (int j = 0; j < O; ++j) dO[j] = 0.0;
         for (int l = 0; l < L; ++l) {
-            const double mu = m->omean[l] + m->oscale[l] * o[l];
-            const double lsv = log(m->oscale[l]) + o[L + l];
-            const double r = target[b * L + l] - mu;
-            const double e2 = exp(-2.0 * lsv);
-            total += lsv + 0.5 * r * r * e2;
-            dO[l] = -r * e2 * m->oscale[l] * invB;         /* dloss/do_l through mu */
-            dO[L + l] = (1.0 - r * r * e2) * invB;         /* dloss/do_{L+l} through ls */
+            dO[l] = -v[l] * invB;
+            dO[L + l] = (1.0 - v[l] * u[l] * exp(o[L + l])) * invB;
+            for (int j = 0; j < l; ++j) dO[2 * L + l * (l - 1) / 2 + j] = -v[l] * u[j] * invB;
         }
         for (int j = 0; j < O; ++j) {
             if (gb3) gb3[j] += dO[j];

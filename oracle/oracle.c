@@ -459,16 +459,20 @@ static double log_post_beta(const or_ctx *c, int64_t g, const double *b)
     return s;
 }
 
-/* One independence Metropolis-Hastings step for beta_g.  Random words come
- * from counter (g, 8 << 24, m, chain << 16 | j): word 0 is the acceptance
- * uniform, words (1 + 2p, 2 + 2p) give the Box-Muller pair p of normals
- * (z_2p = rho cos(2 pi u_b), z_2p+1 = rho sin(2 pi u_b), rho = sqrt(-2 log u_a)). */
+/* One independence Metropolis-Hastings step for beta_g with the proposal
+ * N(mu, Lc Lc^T) of the network (mlp.c): beta* = mu + Lc z, z ~ N(0, I).
+ * Random words come from counter (g, 8 << 24, m, chain << 16 | j): word 0 is
+ * the acceptance uniform, words (1 + 2p, 2 + 2p) give the Box-Muller pair p of
+ * normals (z_2p = rho cos(2 pi u_b), z_2p+1 = rho sin(2 pi u_b),
+ * rho = sqrt(-2 log u_a)).  log q(x) = -sum_l ls_l - |u|^2 / 2, Lc u = x - mu. */
 static void imh_step(or_ctx *c, int64_t g, uint32_t mm)
 {
     const int L = c->cfg.L, F = c->prop.F;
-    double phi[OR_MLP_MAXW], mu[64], ls[64], z[64], bs[64];
+    const or_mlp *pm = &c->prop;
+    double phi[OR_MLP_MAXW], o[OR_MLP_MAXW], mu[64], z[64], bs[64], d[64], u[64];
     gene_features(c, g, phi, F);
-    or_mlp_forward(&c->prop, phi, 1, mu, ls);
+    or_mlp_outputs(pm, phi, o);
+    for (int l = 0; l < L; ++l) mu[l] = pm->omean[l] + pm->oscale[l] * o[l];
     rstream rs;
     rs_init(&rs, c->cfg.seed, (uint32_t)g, OR_KIND_IMH, 0, mm, (uint32_t)c->cfg.chain);
     const double uacc = u01(rs_word(&rs, 0));
@@ -479,14 +483,19 @@ static void imh_step(or_ctx *c, int64_t g, uint32_t mm)
         z[2 * p] = rho * cos(2.0 * M_PI * ub);
         if (2 * p + 1 < L) z[2 * p + 1] = rho * sin(2.0 * M_PI * ub);
     }
-    for (int l = 0; l < L; ++l) bs[l] = mu[l] + exp(ls[l]) * z[l];
+    for (int l = 0; l < L; ++l) {
+        double s = exp(o[L + l]) * z[l];
+        for (int j = 0; j < l; ++j) s += o[2 * L + l * (l - 1) / 2 + j] * z[j];
+        bs[l] = mu[l] + pm->oscale[l] * s;
+    }
     const double *b = c->beta + g * L;
     double lq_new = 0.0, lq_old = 0.0;
-    for (int l = 0; l < L; ++l) {
-        const double e2 = exp(-2.0 * ls[l]);
-        lq_new -= ls[l] + 0.5 * (bs[l] - mu[l]) * (bs[l] - mu[l]) * e2;
-        lq_old -= ls[l] + 0.5 * (b[l] - mu[l]) * (b[l] - mu[l]) * e2;
-    }
+    for (int l = 0; l < L; ++l) d[l] = bs[l] - mu[l];
+    or_mlp_solve(pm, L, o, d, u);
+    for (int l = 0; l < L; ++l) lq_new -= log(pm->oscale[l]) + o[L + l] + 0.5 * u[l] * u[l];
+    for (int l = 0; l < L; ++l) d[l] = b[l] - mu[l];
+    or_mlp_solve(pm, L, o, d, u);
+    for (int l = 0; l < L; ++l) lq_old -= log(pm->oscale[l]) + o[L + l] + 0.5 * u[l] * u[l];
     const double la = (log_post_beta(c, g, bs) - log_post_beta(c, g, b)) - (OR_MUTANT == 9 ? 0.0 : lq_new - lq_old);
     c->imh_la[g] = la;
     if (log(uacc) < la) {
@@ -502,7 +511,7 @@ int or_set_proposal(or_ctx *c, const or_mlp *m, const int32_t *fallback_mask)
     if (!c) return -1;
     if (!m) { c->prop_on = 0; return 0; }
     const int L = c->cfg.L;
-    if (m->O != 2 * L || m->F < 2 * c->R + 2 * L || m->F > OR_MLP_MAXW || m->H > OR_MLP_MAXW || m->H < 1)
+    if (m->O != 2 * L + L * (L - 1) / 2 || m->F < 2 * c->R + 2 * L || m->F > OR_MLP_MAXW || m->H > OR_MLP_MAXW || m->H < 1)
         return -1;
     const size_t F = (size_t)m->F, H = (size_t)m->H, O = (size_t)m->O;
     const size_t total = 2 * F + F * H + H + H * H + H + H * O + O + 2 * (size_t)L;

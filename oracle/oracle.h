@@ -127,8 +127,15 @@ typedef struct {
     const double *omean, *oscale; /* [L] output affine map */
 } or_mlp;
 
-/* mu, ls: [B][L] proposal means and log-scales for feature rows phi [B][F]. */
-int or_mlp_forward(const or_mlp *m, const double *phi, int64_t B, double *mu, double *ls);
+/* Number of coefficients L of a network with O = 2L + L(L-1)/2 outputs, or -1. */
+int or_mlp_coefs(int O);
+/* For feature rows phi [B][F]: mu, ls [B][L] (proposal means and log of the
+ * factor's diagonal) and off [B][L(L-1)/2] (the strict lower triangle of the
+ * factor in units of oscale, row-major); any output may be NULL. */
+int or_mlp_forward(const or_mlp *m, const double *phi, int64_t B, double *mu, double *ls, double *off);
+/* Raw outputs o [O] of one feature row; u with Lc u = d for outputs o. */
+void or_mlp_outputs(const or_mlp *m, const double *phi, double *o);
+void or_mlp_solve(const or_mlp *m, int L, const double *o, const double *d, double *u);
 /* Mean Gaussian NLL of targets [B][L] and its gradients (any may be NULL). */
 int or_mlp_loss_grad(const or_mlp *m, const double *phi, const double *target, int64_t B,
                      double *loss, double *gW1, double *gb1, double *gW2, double *gb2,

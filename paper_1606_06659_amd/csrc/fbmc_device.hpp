@@ -91,8 +91,8 @@ struct DrawRec {
 // Each trip evaluates one point.  The trip is written without branches: the
 // point of every phase is formed and the one of the lane's phase selected, and
 // the interval, counters and phase are updated with selects, so lanes in
-// different phases share one instruction stream.  Only the rare fetch of a
-// further Philox block (shrink candidate 3, 7, ...) branches.
+// different phases share one instruction stream.  Only the rare shrink
+// candidates 3, 4, ... (words of further Philox blocks) branch.
 template <typename T, typename F>
 __device__ inline T slice_draw(F &f, T x0, T w, uint32_t k0, uint32_t k1, uint4 ctr, int K,
                                int cap, DrawRec &rec)
@@ -109,16 +109,23 @@ __device__ inline T slice_draw(F &f, T x0, T w, uint32_t k0, uint32_t k1, uint4 
     uint32_t blk = 0;
     T x1 = x0;
     bool bad = false;
+    // shrink candidate t + 1 reads word t + 2 of the draw's stream: candidates
+    // 1 and 2 words 2 and 3 of block 0, later ones words of further blocks
+    const T u1 = u01<T>(r.z), u2 = u01<T>(r.w);
     for (;;) {
-        // shrink candidate t + 1 reads word q = t + 2 of the draw's stream
-        const uint32_t q = (uint32_t)t + 2u;
-        if (phase == 2 && (q >> 2) != blk) {
-            blk = q >> 2;
-            r = philox4x32_10(make_uint4(ctr.x, ctr.y, ctr.z, (ctr.w & 0xFFFF0000u) | blk), k0, k1);
+        T u = t == 0 ? u1 : u2;
+        if (phase == 2 && t >= 2) {
+            const uint32_t q = (uint32_t)t + 2u;
+            if ((q >> 2) != blk) {
+                blk = q >> 2;
+                r = philox4x32_10(make_uint4(ctr.x, ctr.y, ctr.z, (ctr.w & 0xFFFF0000u) | blk), k0, k1);
+            }
+            // word q & 3 of the block, chosen by selects on its two bits
+            const uint32_t wlo = (q & 1u) ? r.y : r.x;
+            const uint32_t whi = (q & 1u) ? r.w : r.z;
+            u = u01<T>((q & 2u) ? whi : wlo);
         }
-        const uint32_t s = q & 3u;
-        const uint32_t word = s == 0 ? r.x : (s == 1 ? r.y : (s == 2 ? r.z : r.w));
-        const T xs = L + u01<T>(word) * (R - L);
+        const T xs = L + u * (R - L);
         const bool p0 = phase == 0, p1 = phase == 1, p2 = phase == 2;
         const T x = p0 ? L : (p1 ? R : xs);
         const bool in = f(x) > thr;

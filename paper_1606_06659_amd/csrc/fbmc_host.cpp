@@ -27,7 +27,7 @@ hipError_t launch_gb(int precision, bool learned, const SegInfo *segs, const int
 hipError_t launch_hyper(const SegInfo *segs, int nseg, const SweepArgs &a, int *err, hipStream_t st);
 hipError_t launch_philox(const uint4 *ctr, const uint2 *key, uint4 *out, int64_t n, hipStream_t st);
 hipError_t launch_mlp_infer_raw(const float *phi, int64_t B, int L, const MlpDev *net, float *mu, float *ls,
-                                hipStream_t st);
+                                float *off, hipStream_t st);
 hipError_t launch_features(int precision, const SegInfo *seg, int64_t G, float *out, hipStream_t st);
 hipError_t launch_gather_pairs(const float *pairs, int64_t P, int L, const float *master, float *X, float *Tg,
                                int B, uint32_t epoch, uint32_t step, uint32_t k0, uint32_t k1, hipStream_t st);
@@ -1273,7 +1273,8 @@ void sweep_buffers(fb_ctx *c, std::vector<std::pair<void *, size_t>> &out)
 
 }  // namespace
 
-int fb_autotune(fb_ctx *c, int32_t trial_sweeps, int32_t *samples_per_wave, int32_t *fuse_hyper, double *ms_per_sweep)
+int fb_autotune(fb_ctx *c, int32_t trial_sweeps, int32_t *samples_per_wave, int32_t *fuse_hyper,
+                double *ms_per_sweep, double *table)
 {
     if (!c) return fail(nullptr, FB_EINVAL, "NULL context");
     if (trial_sweeps < 1) return fail(c, FB_EINVAL, "trial_sweeps must be >= 1");
@@ -1304,8 +1305,12 @@ int fb_autotune(fb_ctx *c, int32_t trial_sweeps, int32_t *samples_per_wave, int3
     bool best_fuse = fuse0;
     double best = 1e300;
     hipError_t e = copy_all(true);
-    for (int spw = 1; e == hipSuccess && rc == FB_OK && spw <= std::min(maxN, 8); spw *= 2) {
-        for (int fz = 0; fz < 2 && e == hipSuccess && rc == FB_OK; ++fz) {
+    if (table)
+        for (int i = 0; i < 8; ++i) table[i] = -1.0;
+    for (int k = 0; e == hipSuccess && rc == FB_OK && k < 8; ++k) {
+        const int spw = 1 << (k >> 1), fz = k & 1;
+        if (spw > std::min(maxN, 8)) continue;
+        {
             if ((rc = build_items(c, spw))) break;
             c->fuse = fz != 0;
             SweepMode md;
@@ -1319,6 +1324,7 @@ int fb_autotune(fb_ctx *c, int32_t trial_sweeps, int32_t *samples_per_wave, int3
             float ms = 0;
             if ((e = hipEventElapsedTime(&ms, c->ev0, c->ev1)) != hipSuccess) break;
             const double per = ms / trial_sweeps;
+            if (table) table[k] = per;
             if (per < best) { best = per; best_spw = spw; best_fuse = fz != 0; }
             c->m = m0;
             e = copy_all(false);
@@ -1430,7 +1436,8 @@ int fb_proposal_train(fb_ctx *c, const fb_train_opts *opts, double *epoch_loss)
         blk[kOffW2 + i] = (float)(std_normal_key(o.seed, 2, i) / std::sqrt((double)kMlpH));
     for (int i = 0; i < kMlpH * kMlpO; ++i) {
         const int col = i % kMlpO;
-        blk[kOffW3 + i] = col < 2 * L ? (float)(0.1 * std_normal_key(o.seed, 3, i) / std::sqrt((double)kMlpH)) : 0.0f;
+        blk[kOffW3 + i] =
+            col < mlp_outputs(L) ? (float)(0.1 * std_normal_key(o.seed, 3, i) / std::sqrt((double)kMlpH)) : 0.0f;
     }
     HIPCHK(c, hipMemcpy(c->d_master, blk.data(), kMlpParams * sizeof(float), hipMemcpyHostToDevice));
     float *d_m = nullptr, *d_v = nullptr;
@@ -1597,7 +1604,7 @@ int fb_mfma_probe(const float *A, const float *B, float *C)
     return FB_OK;
 }
 
-int fb_mlp_forward(const fb_mlp *w, int32_t L, const float *phi, int64_t B, float *mu, float *ls)
+int fb_mlp_forward(const fb_mlp *w, int32_t L, const float *phi, int64_t B, float *mu, float *ls, float *off)
 {
     std::vector<float> blk;
     if (!mlp_to_block(w, blk) || L < 1 || L > kMaxL || B < 0 || (B > 0 && (!phi || !mu || !ls)))
@@ -1610,7 +1617,7 @@ int fb_mlp_forward(const fb_mlp *w, int32_t L, const float *phi, int64_t B, floa
     if ((rc = dalloc(&tmp, (void **)&d_master, kMlpParams * sizeof(float))) ||
         (rc = dalloc(&tmp, (void **)&d_net, sizeof(MlpDev))) ||
         (rc = dalloc(&tmp, (void **)&d_phi, (size_t)B * 32 * sizeof(float))) ||
-        (rc = dalloc(&tmp, (void **)&d_out, (size_t)B * 2 * L * sizeof(float)))) {
+        (rc = dalloc(&tmp, (void **)&d_out, (size_t)B * mlp_outputs(L) * sizeof(float)))) {
         g_thread_err = tmp.err;
         for (void *p : tmp.allocs) (void)hipFree(p);
         return rc;
@@ -1618,9 +1625,13 @@ int fb_mlp_forward(const fb_mlp *w, int32_t L, const float *phi, int64_t B, floa
     hipError_t e = hipMemcpy(d_master, blk.data(), kMlpParams * sizeof(float), hipMemcpyHostToDevice);
     if (e == hipSuccess) e = hipMemcpy(d_phi, phi, (size_t)B * 32 * sizeof(float), hipMemcpyHostToDevice);
     if (e == hipSuccess && pack_net(&tmp, d_master, d_net, nullptr) != FB_OK) e = hipErrorUnknown;
-    if (e == hipSuccess) e = launch_mlp_infer_raw(d_phi, B, L, d_net, d_out, d_out + (size_t)B * L, nullptr);
+    const size_t K = (size_t)L * (L - 1) / 2;
+    float *d_off = d_out + 2 * (size_t)B * L;
+    if (e == hipSuccess) e = launch_mlp_infer_raw(d_phi, B, L, d_net, d_out, d_out + (size_t)B * L, d_off, nullptr);
     if (e == hipSuccess) e = hipMemcpy(mu, d_out, (size_t)B * L * sizeof(float), hipMemcpyDeviceToHost);
     if (e == hipSuccess) e = hipMemcpy(ls, d_out + (size_t)B * L, (size_t)B * L * sizeof(float), hipMemcpyDeviceToHost);
+    if (e == hipSuccess && off && K > 0)
+        e = hipMemcpy(off, d_off, (size_t)B * K * sizeof(float), hipMemcpyDeviceToHost);
     for (void *p : tmp.allocs) (void)hipFree(p);
     if (e != hipSuccess) return fail(nullptr, FB_EDEVICE, std::string("fb_mlp_forward: ") + hipGetErrorString(e));
     return FB_OK;

@@ -186,9 +186,9 @@ __device__ inline void gene_features(const SegInfo &S, const T (&A)[kMaxRows], c
 }
 
 // Algorithm 1 step 5 by slice draws: beta_g1..beta_gL in order, each moving
-// the row sums C_r to the new coefficient.
+// the row sums C_r to the new coefficient; only `lead` lanes store.
 template <typename T>
-__device__ inline void beta_slice_draws(const SegInfo &S, const SweepArgs &a, int64_t g, int64_t Gp,
+__device__ inline void beta_slice_draws(const SegInfo &S, const SweepArgs &a, int64_t g, int64_t Gp, bool lead,
                                         T (&beta)[kMaxL], T (&wb)[kMaxL], T (&wab)[kMaxL],
                                         const double (&th)[kMaxL], const double (&s2)[kMaxL],
                                         T (&C)[kMaxRows], const T (&YR)[kMaxRows], bool tuning, int &bad)
@@ -226,17 +226,18 @@ __device__ inline void beta_slice_draws(const SegInfo &S, const SweepArgs &a, in
         f.dth = (T)((double)b0 - thl);
         f.inv_s2 = (T)(1.0 / s2l);
         DrawRec rec;
-        const T b1 = slice_draw<T>(f, b0, w, S.key0, S.key1,
-                                   draw_counter((uint32_t)g, 5, (uint32_t)l, mm, (uint32_t)S.chain, 0), a.K,
-                                   a.cap, rec);
+        const uint4 ctr = draw_counter((uint32_t)g, 5, (uint32_t)l, mm, (uint32_t)S.chain, 0);
+        const T b1 = slice_draw<T>(f, b0, w, S.key0, S.key1, ctr, a.K, a.cap, rec);
         if (tuning) {
             tune_width<T>(w, wa, b0, b1, a.m, a.burnin, a.tune_start);
-            ((T *)S.w_beta)[idx] = w;
-            ((T *)S.wa_beta)[idx] = wa;
+            if (lead) {
+                ((T *)S.w_beta)[idx] = w;
+                ((T *)S.wa_beta)[idx] = wa;
+            }
         }
-        betap[idx] = b1;
+        if (lead) betap[idx] = b1;
         bad |= rec.bad;
-        if (a.dbg) S.dbg_beta[idx] = make_int4(rec.kl, rec.nl, rec.nr, rec.nc);
+        if (a.dbg && lead) S.dbg_beta[idx] = make_int4(rec.kl, rec.nl, rec.nr, rec.nc);
         // C_r *= exp(X_rl (b1 - b0)), from expm1 at the accepted point
         T fac[kMaxVals];
 #pragma unroll
@@ -255,18 +256,21 @@ __device__ inline void beta_slice_draws(const SegInfo &S, const SweepArgs &a, in
 }
 
 // Algorithm 1 step 5 by one independence Metropolis-Hastings step for the
-// block beta_g with the proposal N(mu, diag(exp(ls))^2) the network produced.
+// block beta_g with the proposal N(mu, Lc Lc^T) of the network's outputs o
+// (mu_l = omean_l + oscale_l o_l, Lc = diag(oscale) Ls, Ls_ll = exp(o_{L+l}),
+// Ls_lj = o_{2L + l(l-1)/2 + j}): beta* = mu + Lc z.
 // Random words: counter (g, 8 << 24, m, chain << 16 | j); word 0 is the
 // acceptance uniform, words (1 + 2p, 2 + 2p) the Box-Muller pair p.
 // log alpha = [log pi(beta*) - log pi(beta)] + [log q(beta) - log q(beta*)],
-// with the conditional's difference formed from the row sums:
+// log q(x) = -sum_l ls_l - |u|^2 / 2 with Lc u = x - mu (forward substitution);
+// the conditional's difference is formed from the row sums:
 //   sum_r [Y_r X_r d - C_r expm1(X_r d)] - sum_l d_l (beta_l - theta_l + d_l / 2) / sigma_l^2.
 // Returns 1 if accepted.
 template <typename T>
 __device__ inline int beta_imh_draw(const SegInfo &S, const SweepArgs &a, int64_t g, int64_t Gp,
                                     T (&beta)[kMaxL], const double (&th)[kMaxL], const double (&s2)[kMaxL],
-                                    const T (&C)[kMaxRows], const T (&YR)[kMaxRows], const float (&mu_n)[kMaxL],
-                                    const float (&ls_n)[kMaxL])
+                                    const T (&C)[kMaxRows], const T (&YR)[kMaxRows], const MlpDev *__restrict__ net,
+                                    const float *__restrict__ o)
 {
     const int L = S.L, R = S.R;
     const uint32_t mm = (uint32_t)a.m;
@@ -284,19 +288,40 @@ __device__ inline int beta_imh_draw(const SegInfo &S, const SweepArgs &a, int64_
         z[2 * p] = rho * (T)::cos(ang);
         z[2 * p + 1] = rho * (T)::sin(ang);
     }
-    T d[kMaxL], bs[kMaxL];
+    // proposal and the forward substitutions for log q at beta* and at beta
+    T mu[kMaxL], dg[kMaxL], bs[kMaxL], un[kMaxL], uo[kMaxL];
+#pragma unroll
+    for (int l = 0; l < kMaxL; ++l) {
+        mu[l] = (T)0; dg[l] = (T)1; bs[l] = beta[l]; un[l] = (T)0; uo[l] = (T)0;
+        if (l < L) {
+            const T osl = (T)net->oscale[l];
+            mu[l] = (T)net->omean[l] + osl * (T)o[l];
+            dg[l] = dexp((T)o[L + l]);
+            T sz = dg[l] * z[l];
+#pragma unroll
+            for (int j = 0; j < kMaxL; ++j)
+                if (j < l) sz += (T)o[2 * L + l * (l - 1) / 2 + j] * z[j];
+            bs[l] = mu[l] + osl * sz;
+            T sn = (bs[l] - mu[l]) / osl, so = (beta[l] - mu[l]) / osl;
+#pragma unroll
+            for (int j = 0; j < kMaxL; ++j)
+                if (j < l) {
+                    const T ol = (T)o[2 * L + l * (l - 1) / 2 + j];
+                    sn -= ol * un[j];
+                    so -= ol * uo[j];
+                }
+            un[l] = sn / dg[l];
+            uo[l] = so / dg[l];
+        }
+    }
+    T d[kMaxL];
     T dq = (T)0, dpi = (T)0;
 #pragma unroll
     for (int l = 0; l < kMaxL; ++l) {
         d[l] = (T)0;
-        bs[l] = beta[l];
         if (l < L) {
-            const T mu = (T)mu_n[l];
-            const T ls = (T)ls_n[l];
-            bs[l] = mu + dexp(ls) * z[l];
             d[l] = bs[l] - beta[l];
-            const T r0 = (beta[l] - mu) * dexp(-ls);
-            dq += (T)0.5 * (z[l] * z[l] - r0 * r0);
+            dq += (T)0.5 * (un[l] * un[l] - uo[l] * uo[l]);
             dpi -= d[l] * ((T)((double)beta[l] - th[l]) + (T)0.5 * d[l]) * (T)(1.0 / s2[l]);
         }
     }
@@ -346,8 +371,8 @@ __device__ inline void beta_finish(const SegInfo &S, const SweepArgs &a, int64_t
         const double dv = active ? (double)b1 - thl : 0.0;
         const double s0 = wave_sum(dv), s1 = wave_sum(dv * dv);
         if (lane == 0) {
-            S.partials[(int64_t)tile * kMaxParts + 2 + 2 * l] = s0;
-            S.partials[(int64_t)tile * kMaxParts + 3 + 2 * l] = s1;
+            S.partials[(int64_t)(2 + 2 * l) * S.ntiles + tile] = s0;
+            S.partials[(int64_t)(3 + 2 * l) * S.ntiles + tile] = s1;
         }
     }
 }
@@ -382,13 +407,27 @@ __device__ inline void eps_wave(const SegInfo &S, int tile, int n0, int n1, cons
     for (int l = 0; l < kMaxL; ++l) beta[l] = l < L ? betap[(int64_t)l * Gp + g] : (T)0;
     const T inv_gam = (T)1 / ((const T *)S.gam)[g];
     int bad = 0;
+    // software pipeline: the next sample's inputs are requested before the
+    // current draw, so their latency hides behind its slice loop
+    int y_nx = 0;
+    T e_nx = (T)0, w_nx = (T)1, wa_nx = (T)0;
+    double2 mo_nx = make_double2(0.0, 0.0);
+    auto fetch = [&](int n) {
+        const int64_t idx = (int64_t)n * Gp + g;
+        y_nx = yp[idx];
+        e_nx = eps[idx];
+        if (upd) w_nx = w_eps[idx];
+        if (upd && tuning) wa_nx = wa_eps[idx];
+        if (sampling) mo_nx = mom[idx];
+    };
+    if (n0 < n1) fetch(n0);
     for (int n = n0; n < n1; ++n) {
         const int64_t idx = (int64_t)n * Gp + g;
-        const int yv = yp[idx];
-        const T e0 = eps[idx];
-        T w = upd ? w_eps[idx] : (T)1;
-        T wa = (upd && tuning) ? wa_eps[idx] : (T)0;
-        double2 mo = sampling ? mom[idx] : make_double2(0.0, 0.0);
+        const int yv = y_nx;
+        const T e0 = e_nx;
+        T w = w_nx, wa = wa_nx;
+        double2 mo = mo_nx;
+        if (n + 1 < n1) fetch(n + 1);
         T xb = (T)0;
 #pragma unroll
         for (int l = 0; l < kMaxL; ++l)
@@ -483,15 +522,14 @@ __device__ inline void gamma_wave(const SegInfo &S, int tile, const SweepArgs &a
     }
     const double s0 = wave_sum(lg), s1 = wave_sum(ig);
     if (lane == 0) {
-        S.partials[(int64_t)tile * kMaxParts + 0] = s0;
-        S.partials[(int64_t)tile * kMaxParts + 1] = s1;
+        S.partials[tile] = s0;
+        S.partials[S.ntiles + tile] = s1;
     }
     if (bad) raise_flag(err, 2);
 }
 
 // The network on the 64 feature rows of a wavefront (defined below).
-__device__ inline void mlp_rows(const float (&phi)[32], bool active, const MlpDev *__restrict__ net, int L,
-                                float (&mu)[kMaxL], float (&ls)[kMaxL]);
+__device__ inline const float *mlp_rows(const float (&phi)[32], bool active, const MlpDev *__restrict__ net);
 
 // Step 5 (wavefront 1): the row sums A_r = sum over the samples of row r of
 // exp(h_n + eps_gn), then beta_g1..beta_gL by slice draws, or, with the
@@ -550,7 +588,7 @@ __device__ inline void beta_wave(const SegInfo &S, int tile, const SweepArgs &a,
     row_sums_at_beta<T>(S, A, beta, C);
     int bad = 0;
     if constexpr (kLearned) {
-        float phi[32], mu[kMaxL], ls[kMaxL];
+        float phi[32];
         gene_features<T>(S, A, YR, th, s2, phi);
         // training pairs: the features the beta step saw, then the new beta
         float *pair = (a.pair_base >= 0 && active) ? S.pairs + (a.pair_base + g) * kPairStride : nullptr;
@@ -558,14 +596,14 @@ __device__ inline void beta_wave(const SegInfo &S, int tile, const SweepArgs &a,
 #pragma unroll
             for (int k = 0; k < 32; ++k) pair[k] = phi[k];
         }
-        if (a.learned) mlp_rows(phi, active, net, L, mu, ls);
+        const float *o = a.learned ? mlp_rows(phi, active, net) : nullptr;
         if (active && upd_beta) {
             if (a.learned && S.fallback[g] == 0) {
-                const int acc = beta_imh_draw<T>(S, a, g, Gp, beta, th, s2, C, YR, mu, ls);
+                const int acc = beta_imh_draw<T>(S, a, g, Gp, beta, th, s2, C, YR, net, o);
                 S.imh_last[g] = acc;
                 if (a.count_imh) S.imh_count[g] += acc;
             } else {
-                beta_slice_draws<T>(S, a, g, Gp, beta, wb, wab, th, s2, C, YR, tuning, bad);
+                beta_slice_draws<T>(S, a, g, Gp, true, beta, wb, wab, th, s2, C, YR, tuning, bad);
                 S.imh_last[g] = -1;
             }
         }
@@ -575,7 +613,7 @@ __device__ inline void beta_wave(const SegInfo &S, int tile, const SweepArgs &a,
                 if (l < L) pair[32 + l] = (float)beta[l];
         }
     } else {
-        if (active && upd_beta) beta_slice_draws<T>(S, a, g, Gp, beta, wb, wab, th, s2, C, YR, tuning, bad);
+        if (active && upd_beta) beta_slice_draws<T>(S, a, g, Gp, true, beta, wb, wab, th, s2, C, YR, tuning, bad);
     }
     beta_finish<T>(S, a, g, Gp, active, beta, mob, th, tile, lane, tslot, trow, sampling);
     if (bad) raise_flag(err, 2);
@@ -644,10 +682,10 @@ __device__ inline void mlp_layer(const __bf16 *__restrict__ in, int in_stride, c
 }
 
 // The network on the 64 feature rows a wavefront holds (phi of lane = row);
-// writes mu and ls of the lane's row.  All 64 lanes of one wavefront call; the
-// LDS buffers belong to the workgroup and only one of its wavefronts uses them.
-__device__ inline void mlp_rows(const float (&phi)[32], bool active, const MlpDev *__restrict__ net, int L,
-                                float (&mu)[kMaxL], float (&ls)[kMaxL])
+// returns the lane's row of raw outputs o (in LDS, valid until the next call).
+// All 64 lanes of one wavefront call; the LDS buffers belong to the workgroup
+// and only one of its wavefronts uses them.
+__device__ inline const float *mlp_rows(const float (&phi)[32], bool active, const MlpDev *__restrict__ net)
 {
     __shared__ __attribute__((aligned(16))) __bf16 xs[64 * kXs];
     __shared__ __attribute__((aligned(16))) __bf16 h1[64 * kHs];
@@ -666,38 +704,31 @@ __device__ inline void mlp_rows(const float (&phi)[32], bool active, const MlpDe
     wave_lds_sync();
     mlp_layer<kMlpH, kMlpO, false>(h2, kHs, net->W3p, net->b3, nullptr, os, kOs);
     wave_lds_sync();
-#pragma unroll
-    for (int l = 0; l < kMaxL; ++l) {
-        mu[l] = 0.0f;
-        ls[l] = 0.0f;
-        if (l < L) {
-            mu[l] = net->omean[l] + net->oscale[l] * os[lane * kOs + l];
-            ls[l] = ::logf(net->oscale[l]) + os[lane * kOs + L + l];
-        }
-    }
+    return os + lane * kOs;
 }
 
 
-// The network on raw feature rows phi [B][32] (tests): mu, ls [B][L].
+// The network on raw feature rows phi [B][32] (tests): mu, ls [B][L] and the
+// factor's strict lower triangle off [B][L(L-1)/2] (units of oscale).
 __global__ __launch_bounds__(64) void mlp_infer_raw(const float *__restrict__ phi, int64_t B, int L,
-                                                    const MlpDev *__restrict__ net, float *mu_out, float *ls_out)
+                                                    const MlpDev *__restrict__ net, float *mu_out, float *ls_out,
+                                                    float *off_out)
 {
     const int lane = (int)threadIdx.x;
     const int64_t b = (int64_t)blockIdx.x * 64 + lane;
     const bool active = b < B;
-    float phi_r[32], mu[kMaxL], ls[kMaxL];
+    float phi_r[32];
 #pragma unroll
     for (int k = 0; k < 32; ++k) phi_r[k] = active ? phi[b * 32 + k] : 0.0f;
-    mlp_rows(phi_r, active, net, L, mu, ls);
-    if (active)
+    const float *o = mlp_rows(phi_r, active, net);
+    if (active) {
         for (int l = 0; l < L; ++l) {
-            float m = 0.0f, v = 0.0f;
-#pragma unroll
-            for (int j = 0; j < kMaxL; ++j)
-                if (j == l) { m = mu[j]; v = ls[j]; }
-            mu_out[b * L + l] = m;
-            ls_out[b * L + l] = v;
+            mu_out[b * L + l] = net->omean[l] + net->oscale[l] * o[l];
+            ls_out[b * L + l] = ::logf(net->oscale[l]) + o[L + l];
         }
+        const int K = L * (L - 1) / 2;
+        for (int k = 0; k < K; ++k) off_out[b * K + k] = o[2 * L + k];
+    }
 }
 
 // Features of every gene from the current state (tests): A_r and Y_r summed
@@ -772,10 +803,11 @@ __global__ void col_moments(const float *__restrict__ M, int64_t rows, int cols,
 }
 
 hipError_t launch_mlp_infer_raw(const float *phi, int64_t B, int L, const MlpDev *net, float *mu, float *ls,
-                                hipStream_t st)
+                                float *off, hipStream_t st)
 {
     if (B <= 0) return hipSuccess;
-    hipLaunchKernelGGL(mlp_infer_raw, dim3((unsigned)((B + 63) / 64)), dim3(64), 0, st, phi, B, L, net, mu, ls);
+    hipLaunchKernelGGL(mlp_infer_raw, dim3((unsigned)((B + 63) / 64)), dim3(64), 0, st, phi, B, L, net, mu, ls,
+                       off);
     return hipGetLastError();
 }
 
@@ -831,12 +863,26 @@ __device__ inline void hyper_block(const SegInfo &S, const SweepArgs &a, int *er
     for (int i = tid; i < kWords; i += kHyperThreads) hs[i] = hg[i];
 
     // thread t sums tiles t, t + 256, ... in order; a butterfly inside each
-    // wavefront; the wavefronts in order
-    for (int j = 0; j < nparts; ++j) {
-        double acc = 0.0;
-        for (int64_t t = tid; t < S.ntiles; t += kHyperThreads) acc += S.partials[t * kMaxParts + j];
-        acc = wave_sum(acc);
-        if (lane == 0) part[wave][j] = acc;
+    // wavefront; the wavefronts in order.  The partials are part-major, so a
+    // pass reads consecutive tiles; four parts per pass keep few loads in
+    // flight (this code also runs inside the eps kernel, whose register budget
+    // is set for the eps wavefronts) and few round trips.
+    const int64_t nt = S.ntiles;
+    for (int j0 = 0; j0 < nparts; j0 += 4) {
+        double acc[4] = {0.0, 0.0, 0.0, 0.0};
+#pragma unroll 2
+        for (int64_t t = tid; t < nt; t += kHyperThreads) {
+            double v[4];
+#pragma unroll
+            for (int q = 0; q < 4; ++q) v[q] = j0 + q < nparts ? S.partials[(int64_t)(j0 + q) * nt + t] : 0.0;
+#pragma unroll
+            for (int q = 0; q < 4; ++q) acc[q] += v[q];
+        }
+#pragma unroll
+        for (int q = 0; q < 4; ++q) {
+            const double r = wave_sum(acc[q]);
+            if (lane == 0 && j0 + q < nparts) part[wave][j0 + q] = r;
+        }
     }
     __syncthreads();
     if (tid < nparts) {

@@ -1,7 +1,9 @@
 // fbmc_mlp.hip -- the learned beta proposal's network on gfx950 matrix cores.
 //
-// The network maps a gene's 32 features to (mu_l, log s_l), l = 1..L, with two
-// 128-wide GELU layers (F = 32 -> H = 128 -> H = 128 -> O = 32 padded outputs).
+// The network maps a gene's 32 features to a Gaussian proposal for its L
+// coefficients -- the mean, the log-diagonal of a lower-triangular factor and
+// its strict lower triangle -- with two 128-wide GELU layers
+// (F = 32 -> H = 128 -> H = 128 -> O = 64 padded outputs, 2L + L(L-1)/2 used).
 // Products use v_mfma_f32_32x32x16_bf16: BF16 operands, FP32 accumulation.
 // Weights and activations live in FP32; a fragment is rounded to BF16 as it is
 // loaded into the matrix core.
@@ -99,25 +101,41 @@ __global__ void gelu_backward(const float *Z, const float *dH, float *dZ, int64_
     if (t < n) dZ[t] = dH[t] * gelu_df(Z[t]);
 }
 
-// Gaussian NLL of targets T [B][L] under (mu, ls) from the outputs O [B][Op]:
-// mu_l = omean_l + oscale_l O[b][l], ls_l = log oscale_l + O[b][L + l].
-// Writes dO (zero beyond 2L) and per-sample losses.
+// Gaussian NLL of targets T [B][L] under N(mu, Lc Lc^T) from the outputs
+// O [B][Op]: mu_l = omean_l + oscale_l O_l, Lc = diag(oscale) Ls with
+// Ls_ll = exp(O_{L+l}) and Ls_lj = O_{2L + l(l-1)/2 + j} (j < l).  Per row:
+// loss = sum_l (log oscale_l + O_{L+l}) + |u|^2 / 2 with Ls u = (T - mu) / oscale
+// (forward substitution), v = Ls^{-T} u (back substitution); the gradient of
+// the batch mean is -v_l for the mean outputs, 1 - v_l u_l Ls_ll for the
+// log-diagonal and -v_l u_j for the off-diagonal (l, j).  Writes dO (zero
+// beyond the used outputs) and per-row losses.
 __global__ void nll_grad(const float *O, int Op, const float *T, int L, const float *omean,
                          const float *oscale, float *dO, float *loss, int B)
 {
     const int b = (int)(blockIdx.x * blockDim.x + threadIdx.x);
     if (b >= B) return;
     const float invB = 1.0f / (float)B;
+    const float *o = O + (int64_t)b * Op;
+    float *g = dO + (int64_t)b * Op;
+    for (int j = 0; j < Op; ++j) g[j] = 0.0f;
+    float u[8], v[8], dg[8];
     float tot = 0.0f;
-    for (int j = 0; j < Op; ++j) dO[(int64_t)b * Op + j] = 0.0f;
     for (int l = 0; l < L; ++l) {
-        const float mu = omean[l] + oscale[l] * O[(int64_t)b * Op + l];
-        const float lsv = __logf(oscale[l]) + O[(int64_t)b * Op + L + l];
-        const float r = T[(int64_t)b * L + l] - mu;
-        const float e2 = __expf(-2.0f * lsv);
-        tot += lsv + 0.5f * r * r * e2;
-        dO[(int64_t)b * Op + l] = -r * e2 * oscale[l] * invB;
-        dO[(int64_t)b * Op + L + l] = (1.0f - r * r * e2) * invB;
+        dg[l] = __expf(o[L + l]);
+        float s = (T[(int64_t)b * L + l] - (omean[l] + oscale[l] * o[l])) / oscale[l];
+        for (int j = 0; j < l; ++j) s -= o[2 * L + l * (l - 1) / 2 + j] * u[j];
+        u[l] = s / dg[l];
+        tot += __logf(oscale[l]) + o[L + l] + 0.5f * u[l] * u[l];
+    }
+    for (int l = L - 1; l >= 0; --l) {
+        float s = u[l];
+        for (int i = l + 1; i < L; ++i) s -= o[2 * L + i * (i - 1) / 2 + l] * v[i];
+        v[l] = s / dg[l];
+    }
+    for (int l = 0; l < L; ++l) {
+        g[l] = -v[l] * invB;
+        g[L + l] = (1.0f - v[l] * u[l] * dg[l]) * invB;
+        for (int j = 0; j < l; ++j) g[2 * L + l * (l - 1) / 2 + j] = -v[l] * u[j] * invB;
     }
     loss[b] = tot;
 }

@@ -11,7 +11,11 @@ typedef float floatx16 __attribute__((ext_vector_type(16)));
 
 constexpr int kMlpF = 32;    // features (zero-padded)
 constexpr int kMlpH = 128;   // hidden width
-constexpr int kMlpO = 32;    // outputs, 2L padded to one 32-wide tile
+constexpr int kMlpO = 64;    // outputs: 2L + L(L-1)/2 <= 44 used, padded to two 32-wide tiles
+
+// Outputs of the network for L coefficients: mean, log-diagonal of the factor,
+// its strict lower triangle (row-major).
+__host__ __device__ constexpr int mlp_outputs(int L) { return 2 * L + L * (L - 1) / 2; }
 
 // FP32 master parameters, one contiguous block (offsets in floats).
 constexpr int kOffFmean = 0;

@@ -47,7 +47,7 @@ struct SegInfo {
     double2 *mom_eps;             // [N][Gp]  (mean, mean of squares)
     double2 *mom_gam;             // [Gp]
     double2 *mom_beta;            // [L][Gp]
-    double *partials;             // [ntiles][kMaxParts]
+    double *partials;             // [kMaxParts][ntiles] (part-major)
     int32_t *trace_slot;          // [Gp] slot of traced genes, -1 otherwise
     float *trace;                 // [capacity][trace_stride]
     int4 *dbg_eps, *dbg_gam, *dbg_beta;  // per-draw records [N][Gp], [Gp], [L][Gp]

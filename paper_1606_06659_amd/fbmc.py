@@ -116,7 +116,7 @@ def load() -> C.CDLL:
     L.fb_kernel_times.argtypes = [vp, _DP, _DP, _DP, C.POINTER(i64)]
     L.fb_set_launch.argtypes = [vp, i32, i32]
     L.fb_get_launch.argtypes = [vp, C.POINTER(i32), C.POINTER(i32)]
-    L.fb_autotune.argtypes = [vp, i32, C.POINTER(i32), C.POINTER(i32), _DP]
+    L.fb_autotune.argtypes = [vp, i32, C.POINTER(i32), C.POINTER(i32), _DP, _DP]
     L.fb_last_error.argtypes = [vp]
     L.fb_last_error.restype = C.c_char_p
     L.fb_strerror.argtypes = [i32]
@@ -338,11 +338,14 @@ def fb_get_launch(ctx):
 
 
 def fb_autotune(ctx, trial_sweeps: int = 20):
-    """Time every launch shape on snapshots of the state and keep the fastest:
-    (samples per wavefront, fused 0/1, ms per sweep)."""
+    """Time every launch shape on snapshots of the state and keep the fastest.
+    Returns (samples per wavefront, fused 0/1, ms per sweep, {(spw, fuse): ms
+    per sweep} of every shape tried)."""
     a, b, t = C.c_int32(), C.c_int32(), C.c_double()
-    _check(load().fb_autotune(ctx, int(trial_sweeps), C.byref(a), C.byref(b), C.byref(t)), ctx)
-    return a.value, b.value, t.value
+    table = np.zeros(8)
+    _check(load().fb_autotune(ctx, int(trial_sweeps), C.byref(a), C.byref(b), C.byref(t), _p(table)), ctx)
+    tried = {(1 << (k >> 1), k & 1): float(table[k]) for k in range(8) if table[k] >= 0}
+    return a.value, b.value, t.value, tried
 
 
 class Sampler:
@@ -417,7 +420,7 @@ class Sampler:
 # Learned beta proposal
 # ---------------------------------------------------------------------------
 FB_BETA_SLICE, FB_BETA_LEARNED = 0, 1
-MLP_F, MLP_H, MLP_O = 32, 128, 32
+MLP_F, MLP_H, MLP_O = 32, 128, 64
 
 _FP = C.POINTER(C.c_float)
 
@@ -464,7 +467,7 @@ def _load_proposal_api(L):
     L.fb_imh_last.argtypes = [vp, i32, ip]
     L.fb_features.argtypes = [vp, i32, _FP]
     L.fb_mfma_probe.argtypes = [_FP, _FP, _FP]
-    L.fb_mlp_forward.argtypes = [C.POINTER(fb_mlp), i32, _FP, i64, _FP, _FP]
+    L.fb_mlp_forward.argtypes = [C.POINTER(fb_mlp), i32, _FP, i64, _FP, _FP, _FP]
     L.fb_mlp_loss_grad.argtypes = [C.POINTER(fb_mlp), i32, _FP, _FP, i64, _FP, C.POINTER(fb_mlp)]
 
 
@@ -543,15 +546,24 @@ def fb_mfma_probe(A, B) -> np.ndarray:
     return Cm
 
 
+def mlp_outputs(L: int) -> int:
+    """Used outputs of the network for L coefficients: mean, log-diagonal and
+    strict lower triangle of the proposal's factor."""
+    return 2 * L + L * (L - 1) // 2
+
+
 def fb_mlp_forward(params: dict, L: int, phi):
+    """(mu [B, L], ls [B, L], off [B, L(L-1)/2]) of raw feature rows phi [B, 32]."""
     keep = []
     st = _mlp_struct(params, keep)
     phi = np.ascontiguousarray(phi, dtype=np.float32).reshape(-1, 32)
     B = phi.shape[0]
     mu = np.zeros((B, L), np.float32)
     ls = np.zeros((B, L), np.float32)
-    _check(load().fb_mlp_forward(C.byref(st), L, _p(phi, C.c_float), B, _p(mu, C.c_float), _p(ls, C.c_float)))
-    return mu, ls
+    off = np.zeros((B, L * (L - 1) // 2), np.float32)
+    _check(load().fb_mlp_forward(C.byref(st), L, _p(phi, C.c_float), B, _p(mu, C.c_float), _p(ls, C.c_float),
+                                 _p(off, C.c_float)))
+    return mu, ls, off
 
 
 def fb_mlp_loss_grad(params: dict, L: int, phi, target):

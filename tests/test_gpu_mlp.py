@@ -2,12 +2,14 @@
 
 * The 32x32x16 BF16 matrix-core product matches numpy exactly on inputs whose
   products and sums are exact in FP32 (checks the lane layout).
-* The network's outputs and the training gradients match the FP64 oracle on
-  the same BF16-rounded weights and inputs (BF16 activations on the GPU:
-  per-tensor relative error <= 3e-2, cosine > 0.999).
+* The network's outputs (proposal mean, log-diagonal and lower triangle of
+  its factor) and the training gradients match the FP64 oracle on the same
+  BF16-rounded weights and inputs (BF16 activations on the GPU: per-tensor
+  relative error <= 3e-2, cosine > 0.999).
 * The features of every gene match the oracle's.
-* A full sweep with the IMH beta step matches the oracle draw for draw in FP64
-  when the network's outputs are exact (a network with zero weights).
+* A full sweep with the IMH beta step (correlated proposal factor) matches the
+  oracle draw for draw in FP64 when the network's outputs are exact (a network
+  with zero weights and biases on a 1/64 grid).
 * Training on pairs collected from the plain sampler lowers the loss.
 """
 import numpy as np
@@ -38,8 +40,9 @@ def to_gpu_params(m, L):
     p["b1"][:] = m["b1"]
     p["W2"][:] = m["W2"]
     p["b2"][:] = m["b2"]
-    p["W3"][:, :2 * L] = m["W3"]
-    p["b3"][:2 * L] = m["b3"]
+    O = fbmc.mlp_outputs(L)
+    p["W3"][:, :O] = m["W3"]
+    p["b3"][:O] = m["b3"]
     p["omean"][:L] = m["omean"]
     p["oscale"][:L] = m["oscale"]
     return p
@@ -79,13 +82,13 @@ def test_mlp_forward_matches_oracle(oracle_lib):
     L = 5
     m = random_model(rng, L)
     phi = rng.normal(0, 1.5, (300, 32))
-    mu_g, ls_g = F.fb_mlp_forward(to_gpu_params(m, L), L, phi)
+    mu_g, ls_g, off_g = F.fb_mlp_forward(to_gpu_params(m, L), L, phi)
     mr = rounded_oracle_model(m)
     x = bf16((phi.astype(np.float32) - mr["fmean"].astype(np.float32)) * mr["fscale"].astype(np.float32))
     # feed the oracle the rounded standardised inputs through an identity standardisation
     mo = dict(mr, fmean=np.zeros(32), fscale=np.ones(32))
-    mu_o, ls_o = oracle_lib.mlp_forward(mo, x)
-    for g, o in ((mu_g, mu_o), (ls_g, ls_o)):
+    mu_o, ls_o, off_o = oracle_lib.mlp_forward(mo, x)
+    for g, o in ((mu_g, mu_o), (ls_g, ls_o), (off_g, off_o)):
         assert _rel(g, o) < 3e-2, _rel(g, o)
         assert _cos(g - g.mean(0), o - o.mean(0)) > 0.999
 
@@ -105,12 +108,14 @@ def test_mlp_gradients_match_oracle(oracle_lib):
     loss_o, grads_o = oracle_lib.mlp_loss_grad(mo, x, tgt.astype(np.float32))
     assert abs(loss_g - loss_o) < 2e-2 * max(1.0, abs(loss_o)), (loss_g, loss_o)
     for k in ("W1", "b1", "W2", "b2", "W3", "b3"):
-        g = grads_g[k][:, :2 * L] if k == "W3" else (grads_g[k][:2 * L] if k == "b3" else grads_g[k])
+        O = F.mlp_outputs(L)
+        g = grads_g[k][:, :O] if k == "W3" else (grads_g[k][:O] if k == "b3" else grads_g[k])
         o = grads_o[k]
         say(k, "rel", _rel(g, o), "cos", _cos(g, o))
         assert _rel(g, o) < 3e-2, (k, _rel(g, o))
         assert _cos(g, o) > 0.999, (k, _cos(g, o))
-    assert np.all(grads_g["W3"][:, 2 * L:] == 0) and np.all(grads_g["b3"][2 * L:] == 0)
+    O = F.mlp_outputs(L)
+    assert np.all(grads_g["W3"][:, O:] == 0) and np.all(grads_g["b3"][O:] == 0)
 
 
 @pytest.mark.parametrize("precision", [0, 1])
@@ -138,7 +143,9 @@ def test_imh_sweep_parity_fp64(oracle_lib):
     mu = np.round(ds.beta.mean(0) * 64) / 64
     log_s = np.full(L, np.log(0.25))
     log_s = np.round(log_s * 64) / 64
-    m = constant_model(L, mu, log_s)
+    # a correlated factor: lower triangle on the same 1/64 grid (exact in FP32)
+    off = np.round(np.random.default_rng(12).uniform(-0.3, 0.3, L * (L - 1) // 2) * 64) / 64
+    m = constant_model(L, mu, log_s, off=off)
     o = oracle_lib.Oracle(ds.y, ds.X, ds.h, seed=9, burnin=10, tune_start=2)
     o.sweep(15)
     opts = F.fb_default_options(precision=0, jitter=0, debug_counts=1, burnin=10, tune_start=2)

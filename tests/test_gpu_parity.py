@@ -286,9 +286,9 @@ def test_autotune_leaves_the_chain_unchanged():
     F.fb_destroy(a)
     b = F.fb_create(ds.y, ds.X, ds.h, seed=8, options=opts)
     F.fb_sweep(b, 12)
-    spw, fuse, ms = F.fb_autotune(b, 3)
-    say("autotune chose", spw, fuse, ms)
-    assert F.fb_get_launch(b) == (spw, fuse) and ms > 0
+    spw, fuse, ms, tried = F.fb_autotune(b, 3)
+    say("autotune chose", spw, fuse, ms, tried)
+    assert F.fb_get_launch(b) == (spw, fuse) and ms > 0 and len(tried) == 8
     F.fb_sweep(b, 18)
     sb, tb = F.fb_get_state(b), F.fb_trace(b)[0]
     F.fb_destroy(b)

@@ -1,11 +1,13 @@
 """Pins of the oracle's learned-proposal code (CPU only).
 
-* Gradients of the Gaussian NLL through the MLP against central finite
-  differences in FP64.
+* Gradients of the Gaussian NLL (full lower-triangular factor) through the
+  MLP against central finite differences in FP64; the loss against the
+  multivariate normal log density written with numpy's solver.
 * The independence-MH beta step leaves the exact beta conditional invariant:
   exact draws (scipy quadrature of prior x likelihood) go through one IMH step
-  with deliberately mis-centred, too-wide, too-narrow and feature-dependent
-  proposals, and their probability-integral transforms stay uniform.
+  with deliberately mis-centred, too-wide, too-narrow, correlated and
+  feature-dependent proposals, and their probability-integral transforms stay
+  uniform.
 """
 import numpy as np
 import pytest
@@ -15,21 +17,42 @@ from paper_1606_06659_amd import datagen
 from tests.quadrature import grid_cdf, inverse_cdf, pit
 
 
+def n_out(L):
+    """Outputs of the network: mean, log-diagonal, strict lower triangle."""
+    return 2 * L + L * (L - 1) // 2
+
+
 def random_model(rng, L, F=32, H=128, scale=0.2):
-    return dict(F=F, H=H, O=2 * L,
+    O = n_out(L)
+    return dict(F=F, H=H, O=O,
                 fmean=rng.normal(0, 0.5, F), fscale=np.exp(rng.normal(0, 0.2, F)),
                 W1=rng.normal(0, scale, (F, H)), b1=rng.normal(0, 0.1, H),
                 W2=rng.normal(0, scale / 2, (H, H)), b2=rng.normal(0, 0.1, H),
-                W3=rng.normal(0, scale / 2, (H, 2 * L)), b3=rng.normal(0, 0.1, 2 * L),
+                W3=rng.normal(0, scale / 2, (H, O)), b3=rng.normal(0, 0.1, O),
                 omean=rng.normal(0, 1, L), oscale=np.exp(rng.normal(0, 0.3, L)))
 
 
-def constant_model(L, mu, log_s, F=32, H=128):
-    """A network whose output ignores its input: proposal N(mu, exp(log_s)^2)."""
-    return dict(F=F, H=H, O=2 * L, fmean=np.zeros(F), fscale=np.ones(F),
+def constant_model(L, mu, log_s, F=32, H=128, off=None):
+    """A network whose output ignores its input: proposal N(mu, Lc Lc^T) with
+    Lc_ll = exp(log_s_l) and Lc_lj = off[l (l - 1) / 2 + j] (j < l)."""
+    K = L * (L - 1) // 2
+    off = np.zeros(K) if off is None else np.asarray(off, float)
+    return dict(F=F, H=H, O=n_out(L), fmean=np.zeros(F), fscale=np.ones(F),
                 W1=np.zeros((F, H)), b1=np.zeros(H), W2=np.zeros((H, H)), b2=np.zeros(H),
-                W3=np.zeros((H, 2 * L)), b3=np.concatenate([np.zeros(L), np.asarray(log_s, float)]),
+                W3=np.zeros((H, n_out(L))), b3=np.concatenate([np.zeros(L), np.asarray(log_s, float), off]),
                 omean=np.asarray(mu, float), oscale=np.ones(L))
+
+
+def factor(ls, off, oscale):
+    """Lc of one row: diagonal exp(ls), strict lower triangle oscale_l off."""
+    L = len(ls)
+    Lc = np.diag(np.exp(ls))
+    k = 0
+    for l in range(L):
+        for j in range(l):
+            Lc[l, j] = oscale[l] * off[k]
+            k += 1
+    return Lc
 
 
 def test_mlp_gradients_match_finite_differences(oracle_lib):
@@ -54,9 +77,15 @@ def test_mlp_gradients_match_finite_differences(oracle_lib):
             fd = (lp - lm) / (2 * h)
             g = grads[name].reshape(-1)[i]
             assert abs(fd - g) <= 1e-6 * max(1.0, abs(g)), (name, i, fd, g)
-    # the loss itself: mean over rows of sum_l [ls + (t - mu)^2 e^{-2 ls} / 2]
-    mu, ls = oracle_lib.mlp_forward(m, phi)
-    want = np.mean(np.sum(ls + 0.5 * (tgt - mu) ** 2 * np.exp(-2 * ls), axis=1))
+    # the loss itself: the mean over rows of -log N(t; mu, Lc Lc^T) without
+    # its constant, from numpy's triangular solve and determinant
+    mu, ls, off = oracle_lib.mlp_forward(m, phi)
+    want = 0.0
+    for b in range(B):
+        Lc = factor(ls[b], off[b], m["oscale"])
+        u = np.linalg.solve(Lc, tgt[b] - mu[b])
+        want += np.log(np.abs(np.linalg.det(Lc))) + 0.5 * u @ u
+    want /= B
     assert abs(loss - want) < 1e-12 * max(1, abs(want))
 
 
@@ -123,7 +152,10 @@ PROPOSALS = [
     ("off_centre", lambda L, ds: constant_model(L, ds.theta + 0.4, np.full(L, np.log(0.3)))),
     ("too_wide", lambda L, ds: constant_model(L, ds.theta, np.full(L, np.log(2.0)))),
     ("too_narrow", lambda L, ds: constant_model(L, ds.theta, np.full(L, np.log(0.08)))),
-    ("random_net", lambda L, ds: random_model(np.random.default_rng(7), L)),
+    ("correlated", lambda L, ds: constant_model(L, ds.theta + 0.1, np.full(L, np.log(0.2)),
+                                                off=np.full(L * (L - 1) // 2, 0.25))),
+    ("random_net", lambda L, ds: dict(random_model(np.random.default_rng(7), L), omean=ds.theta,
+                                      oscale=np.full(L, 0.5))),
 ]
 
 
