@@ -252,17 +252,21 @@ int fb_autotune(fb_ctx *c, int32_t trial_sweeps, int32_t *samples_per_wave, int3
  * A network maps 32 features of gene g -- for each distinct row r of X,
  * log((Y_r + 1/2) / A_r) and log(Y_r + 1/2) with Y_r the row's count sum and
  * A_r = sum over the row's samples of exp(h_n + eps_gn); then theta_l and
- * log sigma_l^2; zero-padded -- to a Gaussian proposal N(mu, Lc Lc^T) for
- * beta_g with a lower-triangular factor Lc (the beta_g conditional is
- * correlated across l).  The features never involve beta_g, so one step with
- * exact acceptance probability leaves the beta_g full conditional invariant.
- * Network: x = (phi - fmean) * fscale; h1 = gelu(x W1 + b1); h2 = gelu(h1 W2 + b2);
- * o = h2 W3 + b3 (O = 2L + L(L-1)/2 outputs used);
+ * log sigma_l^2; zero-padded -- to a correction of the Laplace approximation
+ * N(bh, H^-1) of the beta_g conditional.  bh and H = U U^T come from the same
+ * sufficient statistics (a weighted least-squares start, two Newton steps, the
+ * negative Hessian at the last iterate); in the whitened coordinates
+ * w = U^T (b - bh) the network gives w ~ N(mu, Lc Lc^T), so
+ * beta* = bh + U^-T (mu + Lc z).  The features never involve beta_g, so one
+ * step with exact acceptance probability leaves the beta_g full conditional
+ * invariant.  Network: x = (phi - fmean) * fscale; h1 = gelu(x W1 + b1);
+ * h2 = gelu(h1 W2 + b2); o = h2 W3 + b3 (O = 2L + L(L-1)/2 outputs used);
  *   mu_l = omean_l + oscale_l o_l,
  *   Lc_ll = exp(ls_l), ls_l = log(oscale_l) + o_{L+l},
  *   Lc_lj = oscale_l o_{2L + l(l-1)/2 + j} for j < l
- * (gelu in the erf form).  Products run on the matrix cores with BF16
- * operands and FP32 accumulation; parameters are kept in FP32.
+ * (gelu in the erf form; a zero network with omean = 0, oscale = 1 leaves the
+ * Laplace proposal).  Products run on the matrix cores with BF16 operands and
+ * FP32 accumulation; parameters are kept in FP32.
  * ---------------------------------------------------------------------- */
 enum fb_beta_update { FB_BETA_SLICE = 0, FB_BETA_LEARNED = 1 };
 
@@ -287,12 +291,13 @@ typedef struct {
 void fb_default_train_opts(fb_train_opts *o);
 
 /* Run `sweeps` sweeps with slice draws for beta and, on every sweep whose index
- * is a multiple of `every`, store (features, new beta_g) of every gene of every
- * segment as training pairs (earlier pairs are discarded). */
+ * is a multiple of `every`, store (features, whitened new beta_g) of every gene
+ * of every segment as training pairs (earlier pairs are discarded). */
 int fb_proposal_collect(fb_ctx *c, int64_t sweeps, int32_t every);
 /* Train the network on the stored pairs with the project's own device kernels:
  * standardisation from the pairs' means and sds, seeded initial weights, Adam
- * on the mean Gaussian negative log likelihood of beta given the features.
+ * on the mean Gaussian negative log likelihood of the whitened beta given the
+ * features.
  * epoch_loss (may be NULL) receives the mean training loss of each epoch. */
 int fb_proposal_train(fb_ctx *c, const fb_train_opts *o, double *epoch_loss);
 /* Run `sweeps` sweeps in which every gene of every segment takes the IMH

@@ -3,9 +3,12 @@
  * proposal (plain loops, no blocking).
  *
  * The proposal is an independence Metropolis-Hastings step for beta_g (the
- * block of L coefficients of one gene) whose proposal density is a Gaussian
- * N(mu, Lc Lc^T) with mean and lower-triangular factor given by a small MLP
- * of per-gene features:
+ * block of L coefficients of one gene).  Its base is the Laplace approximation
+ * N(bh, H^-1) of the beta_g conditional (oracle.c), and the network corrects it
+ * in the whitened coordinates w = U^T (b - bh), H = U U^T: w ~ N(mu, Lc Lc^T)
+ * with mean and lower-triangular factor given by a small MLP of per-gene
+ * features (a zero network with omean = 0, oscale = 1 leaves the Laplace
+ * proposal):
  *
  *   input   x = (phi - fmean) * fscale                           [F]
  *   z1 = x W1 + b1,  h1 = gelu(z1)                                [H]
@@ -29,7 +32,8 @@
  *   phi[2R + l]  = theta_l,  phi[2R + L + l] = log sigma_l^2,
  * zero beyond 2R + 2L.
  *
- * Training loss (Gaussian negative log likelihood of a target beta), averaged
+ * Training loss (Gaussian negative log likelihood of a target, the whitened
+ * w of a draw of beta_g from its conditional), averaged
  * over the batch: sum_l ls_l + |u|^2 / 2 with Lc u = t - mu (forward
  * substitution).  With zero off-diagonal outputs this is
  * sum_l [ls_l + (t_l - mu_l)^2 exp(-2 ls_l) / 2].

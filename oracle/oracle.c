@@ -459,20 +459,128 @@ static double log_post_beta(const or_ctx *c, int64_t g, const double *b)
     return s;
 }
 
-/* One independence Metropolis-Hastings step for beta_g with the proposal
- * N(mu, Lc Lc^T) of the network (mlp.c): beta* = mu + Lc z, z ~ N(0, I).
+/* Cholesky factor of a symmetric positive definite L x L matrix: H = U U^T,
+ * U lower triangular (row-major, zero above the diagonal). */
+static void chol(const double *H, int L, double *U)
+{
+    for (int i = 0; i < L * L; ++i) U[i] = 0.0;
+    for (int j = 0; j < L; ++j) {
+        double d = H[j * L + j];
+        for (int k = 0; k < j; ++k) d -= U[j * L + k] * U[j * L + k];
+        U[j * L + j] = sqrt(d);
+        for (int i = j + 1; i < L; ++i) {
+            double s = H[i * L + j];
+            for (int k = 0; k < j; ++k) s -= U[i * L + k] * U[j * L + k];
+            U[i * L + j] = s / U[j * L + j];
+        }
+    }
+}
+
+/* x with H x = b, H = U U^T: forward then back substitution. */
+static void chol_solve(const double *U, int L, const double *b, double *x)
+{
+    double t[64];
+    for (int i = 0; i < L; ++i) {
+        double s = b[i];
+        for (int k = 0; k < i; ++k) s -= U[i * L + k] * t[k];
+        t[i] = s / U[i * L + i];
+    }
+    for (int i = L - 1; i >= 0; --i) {
+        double s = t[i];
+        for (int k = i + 1; k < L; ++k) s -= U[k * L + i] * x[k];
+        x[i] = s / U[i * L + i];
+    }
+}
+
+/* The Laplace approximation of the beta_g conditional given eps_g, the base
+ * of the learned proposal.  With Y_r and A_r the row sums of the counts and of
+ * exp(h_n + eps_gn) over the samples of distinct row r (x_r) of X, the
+ * conditional is
+ *   log pi(b) = sum_r [Y_r x_r.b - A_r exp(x_r.b)] - sum_l (b_l - theta_l)^2 / (2 sigma_l^2).
+ * Start: the weighted least-squares fit of log((Y_r + 1/2) / A_r) on x_r with
+ * weights Y_r + 1/2 and the prior; then two Newton steps
+ *   b += H^-1 [sum_r (Y_r - c_r) x_r - (b - theta) / sigma^2],
+ *   H = sum_r c_r x_r x_r^T + diag(1 / sigma^2),  c_r = A_r exp(x_r.b).
+ * Returns the last iterate bh and the lower Cholesky factor U of H at bh. */
+static void laplace_base(const or_ctx *c, const double *Y, const double *A, double *bh, double *U)
+{
+    const int N = c->cfg.N, L = c->cfg.L, R = c->R;
+    double xr[64 * 64], H[64], rhs[64], cr[64];
+    for (int r = 0; r < R; ++r) {
+        int n0 = 0;
+        while (c->row_of[n0] != r) ++n0;
+        for (int l = 0; l < L; ++l) xr[r * L + l] = c->X[n0 * L + l];
+    }
+    (void)N;
+    /* weighted least squares start */
+    for (int i = 0; i < L; ++i) {
+        rhs[i] = c->theta[i] / c->sig2[i];
+        for (int j = 0; j < L; ++j) H[i * L + j] = i == j ? 1.0 / c->sig2[i] : 0.0;
+    }
+    for (int r = 0; r < R; ++r) {
+        const double w = Y[r] + 0.5, z = log(w / A[r]);
+        for (int i = 0; i < L; ++i) {
+            rhs[i] += w * z * xr[r * L + i];
+            for (int j = 0; j < L; ++j) H[i * L + j] += w * xr[r * L + i] * xr[r * L + j];
+        }
+    }
+    chol(H, L, U);
+    chol_solve(U, L, rhs, bh);
+    /* Newton steps, then the factor at the last iterate */
+    for (int it = 0; it <= 2; ++it) {
+        for (int r = 0; r < R; ++r) {
+            double xb = 0.0;
+            for (int l = 0; l < L; ++l) xb += xr[r * L + l] * bh[l];
+            cr[r] = A[r] * exp(xb);
+        }
+        for (int i = 0; i < L; ++i) {
+            rhs[i] = -(bh[i] - c->theta[i]) / c->sig2[i];
+            for (int j = 0; j < L; ++j) H[i * L + j] = i == j ? 1.0 / c->sig2[i] : 0.0;
+        }
+        for (int r = 0; r < R; ++r)
+            for (int i = 0; i < L; ++i) {
+                rhs[i] += (Y[r] - cr[r]) * xr[r * L + i];
+                for (int j = 0; j < L; ++j) H[i * L + j] += cr[r] * xr[r * L + i] * xr[r * L + j];
+            }
+        chol(H, L, U);
+        if (it == 2) break;
+        double step[64];
+        chol_solve(U, L, rhs, step);
+        for (int l = 0; l < L; ++l) bh[l] += step[l];
+    }
+}
+
+/* Row sums of gene g: Y_r (counts) and A_r (exp(h_n + eps_gn)). */
+static void row_sums(const or_ctx *c, int64_t g, double *Y, double *A)
+{
+    const int N = c->cfg.N, R = c->R;
+    for (int r = 0; r < R; ++r) { Y[r] = 0.0; A[r] = 0.0; }
+    for (int n = 0; n < N; ++n) {
+        Y[c->row_of[n]] += (double)c->y[g * N + n];
+        A[c->row_of[n]] += exp(c->h[n] + c->eps[g * N + n]);
+    }
+}
+
+/* One independence Metropolis-Hastings step for beta_g.  The proposal is the
+ * Laplace approximation N(bh, H^-1) corrected by the network in whitened
+ * coordinates w = U^T (b - bh): w ~ N(mu_w, Lw Lw^T) with the network's
+ * outputs (mlp.c: mu_w = omean + oscale o, Lw = diag(oscale) Ls), so
+ * beta* = bh + U^-T (mu_w + Lw z), z ~ N(0, I).  Up to a constant,
+ * log q(x) = -sum_l ls_l - |u|^2 / 2 with Lw u = U^T (x - bh) - mu_w.
  * Random words come from counter (g, 8 << 24, m, chain << 16 | j): word 0 is
  * the acceptance uniform, words (1 + 2p, 2 + 2p) give the Box-Muller pair p of
  * normals (z_2p = rho cos(2 pi u_b), z_2p+1 = rho sin(2 pi u_b),
- * rho = sqrt(-2 log u_a)).  log q(x) = -sum_l ls_l - |u|^2 / 2, Lc u = x - mu. */
+ * rho = sqrt(-2 log u_a)). */
 static void imh_step(or_ctx *c, int64_t g, uint32_t mm)
 {
     const int L = c->cfg.L, F = c->prop.F;
     const or_mlp *pm = &c->prop;
-    double phi[OR_MLP_MAXW], o[OR_MLP_MAXW], mu[64], z[64], bs[64], d[64], u[64];
+    double phi[OR_MLP_MAXW], o[OR_MLP_MAXW], Y[64], A[64], bh[64], U[64], mw[64], z[64], w[64], bs[64], d[64], u[64];
     gene_features(c, g, phi, F);
     or_mlp_outputs(pm, phi, o);
-    for (int l = 0; l < L; ++l) mu[l] = pm->omean[l] + pm->oscale[l] * o[l];
+    row_sums(c, g, Y, A);
+    laplace_base(c, Y, A, bh, U);
+    for (int l = 0; l < L; ++l) mw[l] = pm->omean[l] + pm->oscale[l] * o[l];
     rstream rs;
     rs_init(&rs, c->cfg.seed, (uint32_t)g, OR_KIND_IMH, 0, mm, (uint32_t)c->cfg.chain);
     const double uacc = u01(rs_word(&rs, 0));
@@ -483,19 +591,31 @@ static void imh_step(or_ctx *c, int64_t g, uint32_t mm)
         z[2 * p] = rho * cos(2.0 * M_PI * ub);
         if (2 * p + 1 < L) z[2 * p + 1] = rho * sin(2.0 * M_PI * ub);
     }
+    /* w = mu_w + Lw z; beta* = bh + v with U^T v = w (back substitution) */
     for (int l = 0; l < L; ++l) {
         double s = exp(o[L + l]) * z[l];
         for (int j = 0; j < l; ++j) s += o[2 * L + l * (l - 1) / 2 + j] * z[j];
-        bs[l] = mu[l] + pm->oscale[l] * s;
+        w[l] = mw[l] + pm->oscale[l] * s;
+    }
+    for (int i = L - 1; i >= 0; --i) {
+        double s = w[i];
+        for (int k = i + 1; k < L; ++k) s -= U[k * L + i] * (bs[k] - bh[k]);
+        bs[i] = bh[i] + s / U[i * L + i];
     }
     const double *b = c->beta + g * L;
     double lq_new = 0.0, lq_old = 0.0;
-    for (int l = 0; l < L; ++l) d[l] = bs[l] - mu[l];
-    or_mlp_solve(pm, L, o, d, u);
-    for (int l = 0; l < L; ++l) lq_new -= log(pm->oscale[l]) + o[L + l] + 0.5 * u[l] * u[l];
-    for (int l = 0; l < L; ++l) d[l] = b[l] - mu[l];
-    or_mlp_solve(pm, L, o, d, u);
-    for (int l = 0; l < L; ++l) lq_old -= log(pm->oscale[l]) + o[L + l] + 0.5 * u[l] * u[l];
+    for (int pass = 0; pass < 2; ++pass) {
+        const double *x = pass == 0 ? bs : b;
+        for (int i = 0; i < L; ++i) {          /* d = U^T (x - bh) - mu_w */
+            double s = 0.0;
+            for (int k = i; k < L; ++k) s += U[k * L + i] * (x[k] - bh[k]);
+            d[i] = s - mw[i];
+        }
+        or_mlp_solve(pm, L, o, d, u);
+        double lq = 0.0;
+        for (int l = 0; l < L; ++l) lq -= log(pm->oscale[l]) + o[L + l] + 0.5 * u[l] * u[l];
+        if (pass == 0) lq_new = lq; else lq_old = lq;
+    }
     const double la = (log_post_beta(c, g, bs) - log_post_beta(c, g, b)) - (OR_MUTANT == 9 ? 0.0 : lq_new - lq_old);
     c->imh_la[g] = la;
     if (log(uacc) < la) {

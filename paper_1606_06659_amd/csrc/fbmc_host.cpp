@@ -23,7 +23,7 @@ namespace fbmc {
 hipError_t launch_eps(int precision, const SegInfo *segs, const int4 *items, int nitems, const SweepArgs &a,
                       int nhyp, const SweepArgs &ha, int *err, hipStream_t st);
 hipError_t launch_gb(int precision, bool learned, const SegInfo *segs, const int2 *tiles, int ntiles,
-                     const SweepArgs &a, const MlpDev *net, int *err, hipStream_t st);
+                     const int4 *fb_items, int nfb, const SweepArgs &a, const MlpDev *net, int *err, hipStream_t st);
 hipError_t launch_hyper(const SegInfo *segs, int nseg, const SweepArgs &a, int *err, hipStream_t st);
 hipError_t launch_philox(const uint4 *ctr, const uint2 *key, uint4 *out, int64_t n, hipStream_t st);
 hipError_t launch_mlp_infer_raw(const float *phi, int64_t B, int L, const MlpDev *net, float *mu, float *ls,
@@ -106,6 +106,10 @@ struct fb_ctx {
     // learned beta proposal
     int beta_mode = FB_BETA_SLICE;
     bool learned_ready = false;
+    // groups of up to 64 genes that keep the slice steps under the learned step:
+    // (segment, first entry of the segment's list, count, partial column)
+    int4 *d_fb_items = nullptr;
+    int nfb_items = 0, fb_item_cap = 0;
     float *d_master = nullptr;        // kMlpParams FP32
     MlpDev *d_net = nullptr;          // packed inference copy
     bool net_ready = false;
@@ -502,7 +506,9 @@ int build_context(fb_ctx *c, const fb_dataset *dsv, int nds)
             if ((rc = dalloc(c, (void **)&I.mom_eps, N * Gp * sizeof(double2)))) return rc;
             if ((rc = dalloc(c, (void **)&I.mom_gam, Gp * sizeof(double2)))) return rc;
             if ((rc = dalloc(c, (void **)&I.mom_beta, L * Gp * sizeof(double2)))) return rc;
-            if ((rc = dalloc(c, (void **)&I.partials, (size_t)S.ntiles * kMaxParts * sizeof(double)))) return rc;
+            // partial columns: one per tile, then up to one per 64 fallback genes
+            I.pstride = 2 * S.ntiles;
+            if ((rc = dalloc(c, (void **)&I.partials, (size_t)I.pstride * kMaxParts * sizeof(double)))) return rc;
             // Y_r = sum over the samples of distinct row r of y_gn (constant)
             if ((rc = dalloc(c, &I.YR, (size_t)D.des.R * Gp * e))) return rc;
             {
@@ -651,8 +657,8 @@ int run_sweeps(fb_ctx *c, int64_t n, SweepMode &md)
                              c->st));
         if (pe) HIPCHK(c, hipEventRecord(pe[1], c->st));
         if (pe) HIPCHK(c, hipEventRecord(pe[2], c->st));
-        HIPCHK(c, launch_gb(c->prec, md.learned_kernel, c->d_segs, c->d_tiles, c->ntiles, a, c->d_net, c->d_err,
-                            c->st));
+        HIPCHK(c, launch_gb(c->prec, md.learned_kernel, c->d_segs, c->d_tiles, c->ntiles, c->d_fb_items,
+                            md.learned ? c->nfb_items : 0, a, c->d_net, c->d_err, c->st));
         if (pe) HIPCHK(c, hipEventRecord(pe[3], c->st));
         if (c->fuse) {
             prev = a;
@@ -692,11 +698,45 @@ int ensure_learned(fb_ctx *c)
         if ((rc = dalloc(c, (void **)&I.fallback, Gp * sizeof(int32_t)))) return rc;
         if ((rc = dalloc(c, (void **)&I.imh_count, Gp * sizeof(int32_t)))) return rc;
         if ((rc = dalloc(c, (void **)&I.imh_last, Gp * sizeof(int32_t)))) return rc;
+        if ((rc = dalloc(c, (void **)&I.fb_genes, Gp * sizeof(int32_t)))) return rc;
+        I.nfbw = 0;
         c->totalG += S.G;
     }
     if ((rc = upload_segs(c))) return rc;
     c->learned_ready = true;
     return FB_OK;
+}
+
+// The fallback lists from the device masks: per segment the flagged genes in
+// ascending order, cut into groups of 64, each with its own partial column
+// after the segment's tiles.
+int build_fallback(fb_ctx *c)
+{
+    HIPCHK(c, hipStreamSynchronize(c->st));
+    std::vector<int4> items;
+    for (size_t k = 0; k < c->seg.size(); ++k) {
+        SegmentH &S = c->seg[k];
+        std::vector<int32_t> mask((size_t)S.Gp), list;
+        HIPCHK(c, hipMemcpy(mask.data(), S.info.fallback, mask.size() * sizeof(int32_t), hipMemcpyDeviceToHost));
+        for (int64_t g = 0; g < S.G; ++g)
+            if (mask[g]) list.push_back((int32_t)g);
+        if (!list.empty())
+            HIPCHK(c, hipMemcpy((void *)S.info.fb_genes, list.data(), list.size() * sizeof(int32_t),
+                                hipMemcpyHostToDevice));
+        const int n = (int)list.size();
+        S.info.nfbw = (n + kTile - 1) / kTile;
+        for (int i = 0; i < S.info.nfbw; ++i)
+            items.push_back(make_int4((int)k, i * kTile, std::min(kTile, n - i * kTile), (int)(S.ntiles + i)));
+    }
+    if ((int)items.size() > c->fb_item_cap) {
+        int rc;
+        if ((rc = dalloc(c, (void **)&c->d_fb_items, items.size() * sizeof(int4)))) return rc;
+        c->fb_item_cap = (int)items.size();
+    }
+    if (!items.empty())
+        HIPCHK(c, hipMemcpy(c->d_fb_items, items.data(), items.size() * sizeof(int4), hipMemcpyHostToDevice));
+    c->nfb_items = (int)items.size();
+    return upload_segs(c);
 }
 
 int ensure_net(fb_ctx *c)
@@ -1256,7 +1296,7 @@ void sweep_buffers(fb_ctx *c, std::vector<std::pair<void *, size_t>> &out)
         out.push_back({(void *)I.mom_eps, N * Gp * sizeof(double2)});
         out.push_back({(void *)I.mom_gam, Gp * sizeof(double2)});
         out.push_back({(void *)I.mom_beta, L * Gp * sizeof(double2)});
-        out.push_back({(void *)I.partials, (size_t)S.ntiles * kMaxParts * sizeof(double)});
+        out.push_back({(void *)I.partials, (size_t)I.pstride * kMaxParts * sizeof(double)});
         out.push_back({(void *)S.d_hyp, sizeof(HyperState)});
         if (I.dbg_eps) {
             out.push_back({(void *)I.dbg_eps, N * Gp * sizeof(int4)});
@@ -1488,6 +1528,7 @@ int fb_proposal_calibrate(fb_ctx *c, int64_t sweeps, double min_accept)
         HIPCHK(c, hipMemsetAsync(S.info.fallback, 0, (size_t)S.Gp * sizeof(int32_t), c->st));
         HIPCHK(c, hipMemsetAsync(S.info.imh_count, 0, (size_t)S.Gp * sizeof(int32_t), c->st));
     }
+    if ((rc = build_fallback(c))) return rc;     // no fallback groups while calibrating
     SweepMode md;
     md.learned_kernel = true;
     md.learned = true;
@@ -1500,7 +1541,7 @@ int fb_proposal_calibrate(fb_ctx *c, int64_t sweeps, double min_accept)
         for (int64_t g = 0; g < S.G; ++g) mask[g] = ((double)cnt[g] / (double)sweeps) < min_accept ? 1 : 0;
         HIPCHK(c, hipMemcpy(S.info.fallback, mask.data(), mask.size() * sizeof(int32_t), hipMemcpyHostToDevice));
     }
-    return FB_OK;
+    return build_fallback(c);
 }
 
 int fb_set_beta_update(fb_ctx *c, int32_t mode)
@@ -1555,6 +1596,7 @@ int fb_fallback(fb_ctx *c, int32_t seg, int32_t *get, const int32_t *set)
         std::vector<int32_t> m((size_t)S.Gp, 0);
         for (int64_t g = 0; g < S.G; ++g) m[g] = set[g] ? 1 : 0;
         HIPCHK(c, hipMemcpy(S.info.fallback, m.data(), m.size() * sizeof(int32_t), hipMemcpyHostToDevice));
+        if ((rc = build_fallback(c))) return rc;
     }
     if (get) HIPCHK(c, hipMemcpy(get, S.info.fallback, (size_t)S.G * sizeof(int32_t), hipMemcpyDeviceToHost));
     return FB_OK;

@@ -255,22 +255,166 @@ __device__ inline void beta_slice_draws(const SegInfo &S, const SweepArgs &a, in
     }
 }
 
+// ---------------------------------------------------------------------------
+// Laplace approximation of the beta_g conditional given eps_g (the base of the
+// learned proposal).  Symmetric and triangular L x L matrices are stored
+// packed by rows of their lower triangle: element (i, j), j <= i, at tri(i, j).
+// ---------------------------------------------------------------------------
+constexpr int kTri = kMaxL * (kMaxL + 1) / 2;
+__host__ __device__ constexpr int tri(int i, int j) { return i * (i + 1) / 2 + j; }
+
+// In place: H (symmetric positive definite) -> U, lower, with H = U U^T.
+template <typename T>
+__device__ inline void chol_packed(T (&H)[kTri], int L)
+{
+#pragma unroll
+    for (int j = 0; j < kMaxL; ++j) {
+        if (j < L) {
+            T d = H[tri(j, j)];
+#pragma unroll
+            for (int k = 0; k < kMaxL; ++k)
+                if (k < j) d -= H[tri(j, k)] * H[tri(j, k)];
+            const T ujj = (T)::sqrt((double)d);
+            H[tri(j, j)] = ujj;
+#pragma unroll
+            for (int i = 0; i < kMaxL; ++i) {
+                if (i > j && i < L) {
+                    T sum = H[tri(i, j)];
+#pragma unroll
+                    for (int k = 0; k < kMaxL; ++k)
+                        if (k < j) sum -= H[tri(i, k)] * H[tri(j, k)];
+                    H[tri(i, j)] = sum / ujj;
+                }
+            }
+        }
+    }
+}
+
+// x with U U^T x = b (forward, then back substitution).
+template <typename T>
+__device__ inline void chol_solve_packed(const T (&U)[kTri], int L, const T (&b)[kMaxL], T (&x)[kMaxL])
+{
+    T t[kMaxL];
+#pragma unroll
+    for (int i = 0; i < kMaxL; ++i) {
+        t[i] = (T)0;
+        if (i < L) {
+            T sum = b[i];
+#pragma unroll
+            for (int k = 0; k < kMaxL; ++k)
+                if (k < i) sum -= U[tri(i, k)] * t[k];
+            t[i] = sum / U[tri(i, i)];
+        }
+    }
+#pragma unroll
+    for (int i = kMaxL - 1; i >= 0; --i) {
+        x[i] = (T)0;
+        if (i < L) {
+            T sum = t[i];
+#pragma unroll
+            for (int k = 0; k < kMaxL; ++k)
+                if (k > i && k < L) sum -= U[tri(k, i)] * x[k];
+            x[i] = sum / U[tri(i, i)];
+        }
+    }
+}
+
+// With Y_r and A_r the row sums (counts; exp(h_n + eps_gn)) over the samples of
+// distinct row r (x_r) of X, the conditional is
+//   log pi(b) = sum_r [Y_r x_r.b - A_r exp(x_r.b)] - sum_l (b_l - theta_l)^2 / (2 sigma_l^2).
+// Start: the weighted least-squares fit of log((Y_r + 1/2) / A_r) on x_r with
+// weights Y_r + 1/2 and the prior; then two Newton steps
+//   b += H^-1 [sum_r (Y_r - c_r) x_r - (b - theta) / sigma^2],
+//   H = sum_r c_r x_r x_r^T + diag(1 / sigma^2),  c_r = A_r exp(x_r.b).
+// Returns the last iterate bh and the lower Cholesky factor U of H at bh.
+template <typename T>
+__device__ inline void laplace_base(const SegInfo &S, const T (&A)[kMaxRows], const T (&Y)[kMaxRows],
+                                    const double (&th)[kMaxL], const double (&s2)[kMaxL], T (&bh)[kMaxL],
+                                    T (&U)[kTri])
+{
+    const int L = S.L, R = S.R;
+    T rhs[kMaxL];
+#pragma unroll
+    for (int i = 0; i < kMaxL; ++i) {
+        rhs[i] = i < L ? (T)(th[i] / s2[i]) : (T)0;
+#pragma unroll
+        for (int j = 0; j <= i; ++j) U[tri(i, j)] = (i == j && i < L) ? (T)(1.0 / s2[i]) : (T)0;
+    }
+#pragma unroll
+    for (int r = 0; r < kMaxRows; ++r) {
+        if (r < R) {
+            const T w = Y[r] + (T)0.5, z = dlog(w / A[r]);
+#pragma unroll
+            for (int i = 0; i < kMaxL; ++i) {
+                if (i < L) {
+                    const T xi = (T)S.Xrow[r * kMaxL + i];
+                    rhs[i] += w * z * xi;
+#pragma unroll
+                    for (int j = 0; j <= i; ++j) U[tri(i, j)] += w * xi * (T)S.Xrow[r * kMaxL + j];
+                }
+            }
+        }
+    }
+    chol_packed<T>(U, L);
+    chol_solve_packed<T>(U, L, rhs, bh);
+#pragma unroll 1
+    for (int it = 0; it <= 2; ++it) {
+        T cr[kMaxRows];
+#pragma unroll
+        for (int r = 0; r < kMaxRows; ++r) {
+            T xb = (T)0;
+#pragma unroll
+            for (int l = 0; l < kMaxL; ++l)
+                if (l < L) xb += (T)S.Xrow[r * kMaxL + l] * bh[l];
+            cr[r] = r < R ? A[r] * dexp(xb) : (T)0;
+        }
+#pragma unroll
+        for (int i = 0; i < kMaxL; ++i) {
+            rhs[i] = i < L ? (T)(-((double)bh[i] - th[i]) / s2[i]) : (T)0;
+#pragma unroll
+            for (int j = 0; j <= i; ++j) U[tri(i, j)] = (i == j && i < L) ? (T)(1.0 / s2[i]) : (T)0;
+        }
+#pragma unroll
+        for (int r = 0; r < kMaxRows; ++r) {
+            if (r < R) {
+#pragma unroll
+                for (int i = 0; i < kMaxL; ++i) {
+                    if (i < L) {
+                        const T xi = (T)S.Xrow[r * kMaxL + i];
+                        rhs[i] += (Y[r] - cr[r]) * xi;
+#pragma unroll
+                        for (int j = 0; j <= i; ++j) U[tri(i, j)] += cr[r] * xi * (T)S.Xrow[r * kMaxL + j];
+                    }
+                }
+            }
+        }
+        chol_packed<T>(U, L);
+        if (it == 2) break;
+        T step[kMaxL];
+        chol_solve_packed<T>(U, L, rhs, step);
+#pragma unroll
+        for (int l = 0; l < kMaxL; ++l) bh[l] += step[l];
+    }
+}
+
 // Algorithm 1 step 5 by one independence Metropolis-Hastings step for the
-// block beta_g with the proposal N(mu, Lc Lc^T) of the network's outputs o
-// (mu_l = omean_l + oscale_l o_l, Lc = diag(oscale) Ls, Ls_ll = exp(o_{L+l}),
-// Ls_lj = o_{2L + l(l-1)/2 + j}): beta* = mu + Lc z.
+// block beta_g.  The proposal is the Laplace approximation N(bh, H^-1),
+// H = U U^T (laplace_base), corrected by the network in the whitened
+// coordinates w = U^T (b - bh): w ~ N(mu_w, Lw Lw^T) with mu_w,l = omean_l +
+// oscale_l o_l, Lw = diag(oscale) Ls, Ls_ll = exp(o_{L+l}), Ls_lj =
+// o_{2L + l(l-1)/2 + j}.  So beta* = bh + U^-T (mu_w + Lw z), and up to a
+// constant log q(x) = -sum_l ls_l - |u|^2 / 2 with Lw u = U^T (x - bh) - mu_w.
 // Random words: counter (g, 8 << 24, m, chain << 16 | j); word 0 is the
 // acceptance uniform, words (1 + 2p, 2 + 2p) the Box-Muller pair p.
 // log alpha = [log pi(beta*) - log pi(beta)] + [log q(beta) - log q(beta*)],
-// log q(x) = -sum_l ls_l - |u|^2 / 2 with Lc u = x - mu (forward substitution);
-// the conditional's difference is formed from the row sums:
+// the conditional's difference formed from the row sums:
 //   sum_r [Y_r X_r d - C_r expm1(X_r d)] - sum_l d_l (beta_l - theta_l + d_l / 2) / sigma_l^2.
 // Returns 1 if accepted.
 template <typename T>
 __device__ inline int beta_imh_draw(const SegInfo &S, const SweepArgs &a, int64_t g, int64_t Gp,
                                     T (&beta)[kMaxL], const double (&th)[kMaxL], const double (&s2)[kMaxL],
-                                    const T (&C)[kMaxRows], const T (&YR)[kMaxRows], const MlpDev *__restrict__ net,
-                                    const float *__restrict__ o)
+                                    const T (&C)[kMaxRows], const T (&YR)[kMaxRows], const T (&bh)[kMaxL],
+                                    const T (&U)[kTri], const MlpDev *__restrict__ net, const float *__restrict__ o)
 {
     const int L = S.L, R = S.R;
     const uint32_t mm = (uint32_t)a.m;
@@ -283,45 +427,82 @@ __device__ inline int beta_imh_draw(const SegInfo &S, const SweepArgs &a, int64_
 #pragma unroll
     for (int p = 0; p < kMaxL / 2; ++p) {
         const T ua = u01<T>(wv[1 + 2 * p]), ub = u01<T>(wv[2 + 2 * p]);
-        const T rho = (T)::sqrt(-2.0 * (double)dlog(ua));
-        const double ang = 6.283185307179586 * (double)ub;
-        z[2 * p] = rho * (T)::cos(ang);
-        z[2 * p + 1] = rho * (T)::sin(ang);
+        if constexpr (sizeof(T) == sizeof(float)) {
+            const float rho = ::sqrtf(-2.0f * ::logf(ua));
+            float sn, cs;
+            ::sincosf(6.28318530717958648f * ub, &sn, &cs);
+            z[2 * p] = rho * cs;
+            z[2 * p + 1] = rho * sn;
+        } else {
+            const double rho = ::sqrt(-2.0 * ::log((double)ua));
+            const double ang = 6.283185307179586 * (double)ub;
+            z[2 * p] = (T)(rho * ::cos(ang));
+            z[2 * p + 1] = (T)(rho * ::sin(ang));
+        }
     }
-    // proposal and the forward substitutions for log q at beta* and at beta
-    T mu[kMaxL], dg[kMaxL], bs[kMaxL], un[kMaxL], uo[kMaxL];
+    // w = mu_w + Lw z, then beta* = bh + v with U^T v = w (back substitution)
+    T mw[kMaxL], dg[kMaxL], w[kMaxL], bs[kMaxL];
 #pragma unroll
     for (int l = 0; l < kMaxL; ++l) {
-        mu[l] = (T)0; dg[l] = (T)1; bs[l] = beta[l]; un[l] = (T)0; uo[l] = (T)0;
+        mw[l] = (T)0; dg[l] = (T)1; w[l] = (T)0;
         if (l < L) {
             const T osl = (T)net->oscale[l];
-            mu[l] = (T)net->omean[l] + osl * (T)o[l];
+            mw[l] = (T)net->omean[l] + osl * (T)o[l];
             dg[l] = dexp((T)o[L + l]);
             T sz = dg[l] * z[l];
 #pragma unroll
             for (int j = 0; j < kMaxL; ++j)
                 if (j < l) sz += (T)o[2 * L + l * (l - 1) / 2 + j] * z[j];
-            bs[l] = mu[l] + osl * sz;
-            T sn = (bs[l] - mu[l]) / osl, so = (beta[l] - mu[l]) / osl;
+            w[l] = mw[l] + osl * sz;
+        }
+    }
 #pragma unroll
-            for (int j = 0; j < kMaxL; ++j)
-                if (j < l) {
-                    const T ol = (T)o[2 * L + l * (l - 1) / 2 + j];
-                    sn -= ol * un[j];
-                    so -= ol * uo[j];
-                }
-            un[l] = sn / dg[l];
-            uo[l] = so / dg[l];
+    for (int i = kMaxL - 1; i >= 0; --i) {
+        bs[i] = beta[i];
+        if (i < L) {
+            T sum = w[i];
+#pragma unroll
+            for (int k = 0; k < kMaxL; ++k)
+                if (k > i && k < L) sum -= U[tri(k, i)] * (bs[k] - bh[k]);
+            bs[i] = bh[i] + sum / U[tri(i, i)];
+        }
+    }
+    // log q at beta* and at beta: u with Lw u = U^T (x - bh) - mu_w
+    T dq = (T)0;
+#pragma unroll
+    for (int pass = 0; pass < 2; ++pass) {
+        T dd[kMaxL], u[kMaxL];
+#pragma unroll
+        for (int i = 0; i < kMaxL; ++i) {
+            dd[i] = (T)0;
+            if (i < L) {
+                T sum = (T)0;
+#pragma unroll
+                for (int k = 0; k < kMaxL; ++k)
+                    if (k >= i && k < L) sum += U[tri(k, i)] * ((pass == 0 ? bs[k] : beta[k]) - bh[k]);
+                dd[i] = sum - mw[i];
+            }
+        }
+#pragma unroll
+        for (int l = 0; l < kMaxL; ++l) {
+            u[l] = (T)0;
+            if (l < L) {
+                T sum = dd[l] / (T)net->oscale[l];
+#pragma unroll
+                for (int j = 0; j < kMaxL; ++j)
+                    if (j < l) sum -= (T)o[2 * L + l * (l - 1) / 2 + j] * u[j];
+                u[l] = sum / dg[l];
+                dq += (pass == 0 ? (T)0.5 : (T)-0.5) * u[l] * u[l];
+            }
         }
     }
     T d[kMaxL];
-    T dq = (T)0, dpi = (T)0;
+    T dpi = (T)0;
 #pragma unroll
     for (int l = 0; l < kMaxL; ++l) {
         d[l] = (T)0;
         if (l < L) {
             d[l] = bs[l] - beta[l];
-            dq += (T)0.5 * (un[l] * un[l] - uo[l] * uo[l]);
             dpi -= d[l] * ((T)((double)beta[l] - th[l]) + (T)0.5 * d[l]) * (T)(1.0 / s2[l]);
         }
     }
@@ -348,6 +529,24 @@ __device__ inline int beta_imh_draw(const SegInfo &S, const SweepArgs &a, int64_
     return acc ? 1 : 0;
 }
 
+// Whitened coordinates w = U^T (b - bh) of the Laplace approximation: the
+// training targets of the proposal network.
+template <typename T>
+__device__ inline void whiten(int L, const T (&U)[kTri], const T (&bh)[kMaxL], const T (&b)[kMaxL], T (&w)[kMaxL])
+{
+#pragma unroll
+    for (int i = 0; i < kMaxL; ++i) {
+        w[i] = (T)0;
+        if (i < L) {
+            T sum = (T)0;
+#pragma unroll
+            for (int k = 0; k < kMaxL; ++k)
+                if (k >= i && k < L) sum += U[tri(k, i)] * (b[k] - bh[k]);
+            w[i] = sum;
+        }
+    }
+}
+
 // After the beta step: moments, trace, and the tile partials of
 // (beta_l - theta_l) and its square (all lanes of the wavefront call).
 template <typename T>
@@ -371,8 +570,8 @@ __device__ inline void beta_finish(const SegInfo &S, const SweepArgs &a, int64_t
         const double dv = active ? (double)b1 - thl : 0.0;
         const double s0 = wave_sum(dv), s1 = wave_sum(dv * dv);
         if (lane == 0) {
-            S.partials[(int64_t)(2 + 2 * l) * S.ntiles + tile] = s0;
-            S.partials[(int64_t)(3 + 2 * l) * S.ntiles + tile] = s1;
+            S.partials[(int64_t)(2 + 2 * l) * S.pstride + tile] = s0;
+            S.partials[(int64_t)(3 + 2 * l) * S.pstride + tile] = s1;
         }
     }
 }
@@ -523,7 +722,7 @@ __device__ inline void gamma_wave(const SegInfo &S, int tile, const SweepArgs &a
     const double s0 = wave_sum(lg), s1 = wave_sum(ig);
     if (lane == 0) {
         S.partials[tile] = s0;
-        S.partials[S.ntiles + tile] = s1;
+        S.partials[S.pstride + tile] = s1;
     }
     if (bad) raise_flag(err, 2);
 }
@@ -531,22 +730,28 @@ __device__ inline void gamma_wave(const SegInfo &S, int tile, const SweepArgs &a
 // The network on the 64 feature rows of a wavefront (defined below).
 __device__ inline const float *mlp_rows(const float (&phi)[32], bool active, const MlpDev *__restrict__ net);
 
-// Step 5 (wavefront 1): the row sums A_r = sum over the samples of row r of
-// exp(h_n + eps_gn), then beta_g1..beta_gL by slice draws, or, with the
-// learned proposal, one independence MH step for the block where the gene's
-// fallback flag is 0; moments, trace, training pairs and the tile partials
-// of (beta_l - theta_l) and its square.
+// Step 5 for the genes of one wavefront: the row sums A_r = sum over the
+// samples of row r of exp(h_n + eps_gn), then beta_g1..beta_gL by slice draws,
+// or, with the learned proposal, one independence MH step for the block.
+// Then the moments, trace, training pairs and the wavefront's partials of
+// (beta_l - theta_l) and its square in column `col`.
+//   lane gene g, `active`: the lane holds a gene
+//   kLearned, fallback_group = false: a tile's wavefront; with a.learned the
+//     genes flagged for fallback are left to their fallback group
+//   fallback_group = true: up to 64 flagged genes, slice steps only
 template <typename T, bool kLearned>
-__device__ inline void beta_wave(const SegInfo &S, int tile, const SweepArgs &a, const MlpDev *__restrict__ net,
-                                 int *err)
+__device__ inline void beta_genes(const SegInfo &S, int64_t g, bool active, int64_t col, bool fallback_group,
+                                  const SweepArgs &a, const MlpDev *__restrict__ net, int *err)
 {
     const int lane = (int)(threadIdx.x & 63);
     const int64_t Gp = S.Gp;
-    const int64_t g = (int64_t)tile * kTile + lane;
-    const bool active = g < S.G;
     const int N = S.N, L = S.L, R = S.R;
     const bool tuning = a.m <= a.burnin, sampling = a.m > a.burnin;
     const bool upd_beta = (a.mask >> 5) & 1u;
+    // with the learned step, a tile's wavefront leaves flagged genes alone
+    bool mine = active;
+    if constexpr (kLearned)
+        if (!fallback_group && a.learned && active && S.fallback[g] != 0) mine = false;
     const HyperState &H = *S.hyp;
     double th[kMaxL], s2[kMaxL];
 #pragma unroll
@@ -558,7 +763,7 @@ __device__ inline void beta_wave(const SegInfo &S, int tile, const SweepArgs &a,
     double2 mob[kMaxL];
 #pragma unroll
     for (int l = 0; l < kMaxL; ++l) {
-        const bool on = l < L && active;
+        const bool on = l < L && mine;
         const int64_t idx = (int64_t)l * Gp + g;
         beta[l] = on ? ((const T *)S.beta)[idx] : (T)0;
         wb[l] = (on && upd_beta) ? ((const T *)S.w_beta)[idx] : (T)1;
@@ -569,9 +774,9 @@ __device__ inline void beta_wave(const SegInfo &S, int tile, const SweepArgs &a,
 #pragma unroll
     for (int r = 0; r < kMaxRows; ++r) {
         A[r] = (T)0;
-        YR[r] = (r < R && active) ? ((const T *)S.YR)[(int64_t)r * Gp + g] : (T)0;
+        YR[r] = (r < R && mine) ? ((const T *)S.YR)[(int64_t)r * Gp + g] : (T)0;
     }
-    if (active) {
+    if (mine) {
         const T *__restrict__ eps = (const T *)S.eps;
 #pragma unroll 8
         for (int n = 0; n < N; ++n) {
@@ -582,57 +787,93 @@ __device__ inline void beta_wave(const SegInfo &S, int tile, const SweepArgs &a,
                 if (r == rr) A[r] += ehe;
         }
     }
-    const int tslot = (a.trace_point >= 0 && active) ? S.trace_slot[g] : -1;
+    const int tslot = (a.trace_point >= 0 && mine) ? S.trace_slot[g] : -1;
     float *trow = a.trace_point >= 0 ? S.trace + (int64_t)a.trace_point * S.trace_stride + 2 + 2 * L : nullptr;
     T C[kMaxRows];
     row_sums_at_beta<T>(S, A, beta, C);
     int bad = 0;
     if constexpr (kLearned) {
-        float phi[32];
-        gene_features<T>(S, A, YR, th, s2, phi);
-        // training pairs: the features the beta step saw, then the new beta
-        float *pair = (a.pair_base >= 0 && active) ? S.pairs + (a.pair_base + g) * kPairStride : nullptr;
-        if (pair) {
-#pragma unroll
-            for (int k = 0; k < 32; ++k) pair[k] = phi[k];
-        }
-        const float *o = a.learned ? mlp_rows(phi, active, net) : nullptr;
-        if (active && upd_beta) {
-            if (a.learned && S.fallback[g] == 0) {
-                const int acc = beta_imh_draw<T>(S, a, g, Gp, beta, th, s2, C, YR, net, o);
-                S.imh_last[g] = acc;
-                if (a.count_imh) S.imh_count[g] += acc;
-            } else {
+        if (fallback_group) {
+            if (mine && upd_beta) {
                 beta_slice_draws<T>(S, a, g, Gp, true, beta, wb, wab, th, s2, C, YR, tuning, bad);
                 S.imh_last[g] = -1;
             }
-        }
-        if (pair) {
+        } else {
+            float phi[32];
+            gene_features<T>(S, A, YR, th, s2, phi);
+            // training pairs: the features the beta step saw, then the new beta
+            float *pair = (a.pair_base >= 0 && mine) ? S.pairs + (a.pair_base + g) * kPairStride : nullptr;
+            if (pair) {
 #pragma unroll
-            for (int l = 0; l < kMaxL; ++l)
-                if (l < L) pair[32 + l] = (float)beta[l];
+                for (int k = 0; k < 32; ++k) pair[k] = phi[k];
+            }
+            const float *o = a.learned ? mlp_rows(phi, mine, net) : nullptr;
+            T bh[kMaxL], U[kTri];
+            if (a.learned || pair) laplace_base<T>(S, A, YR, th, s2, bh, U);
+            if (mine && upd_beta) {
+                if (a.learned) {
+                    const int acc = beta_imh_draw<T>(S, a, g, Gp, beta, th, s2, C, YR, bh, U, net, o);
+                    S.imh_last[g] = acc;
+                    if (a.count_imh) S.imh_count[g] += acc;
+                } else {
+                    beta_slice_draws<T>(S, a, g, Gp, true, beta, wb, wab, th, s2, C, YR, tuning, bad);
+                    S.imh_last[g] = -1;
+                }
+            }
+            if (pair) {          // the target: beta after the step, whitened
+                T wt[kMaxL];
+                whiten<T>(L, U, bh, beta, wt);
+#pragma unroll
+                for (int l = 0; l < kMaxL; ++l)
+                    if (l < L) pair[32 + l] = (float)wt[l];
+            }
         }
     } else {
-        if (active && upd_beta) beta_slice_draws<T>(S, a, g, Gp, true, beta, wb, wab, th, s2, C, YR, tuning, bad);
+        if (mine && upd_beta) beta_slice_draws<T>(S, a, g, Gp, true, beta, wb, wab, th, s2, C, YR, tuning, bad);
     }
-    beta_finish<T>(S, a, g, Gp, active, beta, mob, th, tile, lane, tslot, trow, sampling);
+    beta_finish<T>(S, a, g, Gp, mine, beta, mob, th, col, lane, tslot, trow, sampling);
     if (bad) raise_flag(err, 2);
 }
 
-
+// Steps 2 and 5: one workgroup per tile (wavefront 0 gamma, wavefront 1
+// beta); with the learned step, `nfb` further workgroups each draw beta by
+// slice steps for a group of up to 64 genes flagged for fallback
+// (fb_items: segment, first list entry, count, partial column).
 template <typename T, bool kLearned>
 __global__ __launch_bounds__(128) void gb_sweep(const SegInfo *__restrict__ segs, const int2 *__restrict__ tiles,
-                                                int ntiles, SweepArgs a, const MlpDev *__restrict__ net, int *err)
+                                                int ntiles, const int4 *__restrict__ fb_items, int nfb, SweepArgs a,
+                                                const MlpDev *__restrict__ net, int *err)
 {
     const int wave = __builtin_amdgcn_readfirstlane((int)(threadIdx.x >> 6));
+    const int lane = (int)(threadIdx.x & 63);
     const int tix = (int)blockIdx.x;
-    if (tix >= ntiles) return;
-    const int2 tt = tiles[tix];
-    const int sidx = __builtin_amdgcn_readfirstlane(tt.x);
-    const int tile = __builtin_amdgcn_readfirstlane(tt.y);
-    const SegInfo &S = segs[sidx];
-    if (wave == 0) gamma_wave<T>(S, tile, a, err);
-    else beta_wave<T, kLearned>(S, tile, a, net, err);
+    if (tix < ntiles) {
+        const int2 tt = tiles[tix];
+        const int sidx = __builtin_amdgcn_readfirstlane(tt.x);
+        const int tile = __builtin_amdgcn_readfirstlane(tt.y);
+        const SegInfo &S = segs[sidx];
+        if (wave == 0) {
+            gamma_wave<T>(S, tile, a, err);
+        } else {
+            const int64_t g = (int64_t)tile * kTile + lane;
+            beta_genes<T, kLearned>(S, g, g < S.G, tile, false, a, net, err);
+        }
+        return;
+    }
+    if constexpr (kLearned) {
+        if (tix - ntiles >= nfb || wave != 0) return;
+        const int4 it = fb_items[tix - ntiles];
+        const int sidx = __builtin_amdgcn_readfirstlane(it.x);
+        const SegInfo &S = segs[sidx];
+        const bool active = lane < it.z;
+        const int64_t g = active ? S.fb_genes[it.y + lane] : 0;
+        const int64_t col = it.w;
+        beta_genes<T, true>(S, g, active, col, true, a, net, err);
+        if (lane == 0) {      // no gamma in a fallback column
+            S.partials[col] = 0.0;
+            S.partials[S.pstride + col] = 0.0;
+        }
+    }
 }
 
 // ---------------------------------------------------------------------------
@@ -867,14 +1108,15 @@ __device__ inline void hyper_block(const SegInfo &S, const SweepArgs &a, int *er
     // pass reads consecutive tiles; four parts per pass keep few loads in
     // flight (this code also runs inside the eps kernel, whose register budget
     // is set for the eps wavefronts) and few round trips.
-    const int64_t nt = S.ntiles;
+    // columns: the tiles, then (learned step) the fallback groups
+    const int64_t nt = S.ntiles + (a.learned ? S.nfbw : 0);
     for (int j0 = 0; j0 < nparts; j0 += 4) {
         double acc[4] = {0.0, 0.0, 0.0, 0.0};
 #pragma unroll 2
         for (int64_t t = tid; t < nt; t += kHyperThreads) {
             double v[4];
 #pragma unroll
-            for (int q = 0; q < 4; ++q) v[q] = j0 + q < nparts ? S.partials[(int64_t)(j0 + q) * nt + t] : 0.0;
+            for (int q = 0; q < 4; ++q) v[q] = j0 + q < nparts ? S.partials[(int64_t)(j0 + q) * S.pstride + t] : 0.0;
 #pragma unroll
             for (int q = 0; q < 4; ++q) acc[q] += v[q];
         }
@@ -1040,16 +1282,26 @@ hipError_t launch_eps(int precision, const SegInfo *segs, const int4 *items, int
 }
 
 hipError_t launch_gb(int precision, bool learned, const SegInfo *segs, const int2 *tiles, int ntiles,
-                     const SweepArgs &a, const MlpDev *net, int *err, hipStream_t st)
+                     const int4 *fb_items, int nfb, const SweepArgs &a, const MlpDev *net, int *err, hipStream_t st)
 {
     if (ntiles == 0) return hipSuccess;
-    const dim3 grid(ntiles), block(128);
+    const dim3 block(128);
+    if (!learned) nfb = 0;
+    const dim3 grid(ntiles + nfb);
     if (precision == 0) {
-        if (learned) hipLaunchKernelGGL((gb_sweep<double, true>), grid, block, 0, st, segs, tiles, ntiles, a, net, err);
-        else hipLaunchKernelGGL((gb_sweep<double, false>), grid, block, 0, st, segs, tiles, ntiles, a, net, err);
+        if (learned)
+            hipLaunchKernelGGL((gb_sweep<double, true>), grid, block, 0, st, segs, tiles, ntiles, fb_items, nfb, a, net,
+                               err);
+        else
+            hipLaunchKernelGGL((gb_sweep<double, false>), grid, block, 0, st, segs, tiles, ntiles, fb_items, 0, a, net,
+                               err);
     } else {
-        if (learned) hipLaunchKernelGGL((gb_sweep<float, true>), grid, block, 0, st, segs, tiles, ntiles, a, net, err);
-        else hipLaunchKernelGGL((gb_sweep<float, false>), grid, block, 0, st, segs, tiles, ntiles, a, net, err);
+        if (learned)
+            hipLaunchKernelGGL((gb_sweep<float, true>), grid, block, 0, st, segs, tiles, ntiles, fb_items, nfb, a, net,
+                               err);
+        else
+            hipLaunchKernelGGL((gb_sweep<float, false>), grid, block, 0, st, segs, tiles, ntiles, fb_items, 0, a, net,
+                               err);
     }
     return hipGetLastError();
 }

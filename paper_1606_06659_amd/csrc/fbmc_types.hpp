@@ -47,7 +47,11 @@ struct SegInfo {
     double2 *mom_eps;             // [N][Gp]  (mean, mean of squares)
     double2 *mom_gam;             // [Gp]
     double2 *mom_beta;            // [L][Gp]
-    double *partials;             // [kMaxParts][ntiles] (part-major)
+    double *partials;             // [kMaxParts][pstride] (part-major): tiles, then fallback groups
+    int64_t pstride;              // columns of the partials array: 2 ntiles
+    const int32_t *fb_genes;      // learned step: genes that keep the slice steps, ascending
+    int32_t nfbw;                 // learned step: fallback groups (<= 64 genes each) of this segment
+    int32_t pad1;
     int32_t *trace_slot;          // [Gp] slot of traced genes, -1 otherwise
     float *trace;                 // [capacity][trace_stride]
     int4 *dbg_eps, *dbg_gam, *dbg_beta;  // per-draw records [N][Gp], [Gp], [L][Gp]

@@ -7,9 +7,10 @@
   BF16-rounded weights and inputs (BF16 activations on the GPU: per-tensor
   relative error <= 3e-2, cosine > 0.999).
 * The features of every gene match the oracle's.
-* A full sweep with the IMH beta step (correlated proposal factor) matches the
-  oracle draw for draw in FP64 when the network's outputs are exact (a network
-  with zero weights and biases on a 1/64 grid).
+* A full sweep with the IMH beta step (Laplace approximation corrected by a
+  shift, a scale and a correlated factor) matches the oracle draw for draw in
+  FP64 when the network's outputs are exact (a network with zero weights and
+  biases on a 1/64 grid).
 * Training on pairs collected from the plain sampler lowers the loss.
 """
 import numpy as np
@@ -93,11 +94,21 @@ def test_mlp_forward_matches_oracle(oracle_lib):
         assert _cos(g - g.mean(0), o - o.mean(0)) > 0.999
 
 
+def conditioned_model(rng, L):
+    """A random network whose factor stays well conditioned (small strict
+    lower triangle), so BF16 rounding is not amplified by the triangular solve."""
+    m = random_model(rng, L)
+    m["W3"][:, L:2 * L] *= 0.3
+    m["W3"][:, 2 * L:] *= 0.1
+    m["b3"][2 * L:] *= 0.1
+    return m
+
+
 def test_mlp_gradients_match_oracle(oracle_lib):
     F = require_gpu()
     rng = np.random.default_rng(2)
     L = 5
-    m = random_model(rng, L)
+    m = conditioned_model(rng, L)
     B = 256
     phi = rng.normal(0, 1.5, (B, 32))
     tgt = rng.normal(0, 1, (B, L))
@@ -140,10 +151,10 @@ def test_imh_sweep_parity_fp64(oracle_lib):
     F = require_gpu()
     ds = datagen.paper_design_16(G=500, seed=4)
     L = ds.L
-    mu = np.round(ds.beta.mean(0) * 64) / 64
-    log_s = np.full(L, np.log(0.25))
-    log_s = np.round(log_s * 64) / 64
-    # a correlated factor: lower triangle on the same 1/64 grid (exact in FP32)
+    # a correction of the Laplace proposal in its whitened coordinates: mean
+    # shift, scale and a correlated factor, on a 1/64 grid (exact in FP32)
+    mu = np.round(np.random.default_rng(11).uniform(-0.4, 0.4, L) * 64) / 64
+    log_s = np.round(np.full(L, np.log(0.9)) * 64) / 64
     off = np.round(np.random.default_rng(12).uniform(-0.3, 0.3, L * (L - 1) // 2) * 64) / 64
     m = constant_model(L, mu, log_s, off=off)
     o = oracle_lib.Oracle(ds.y, ds.X, ds.h, seed=9, burnin=10, tune_start=2)
@@ -173,6 +184,43 @@ def test_imh_sweep_parity_fp64(oracle_lib):
     F.fb_destroy(g)
 
 
+def test_imh_sweep_parity_with_fallback_genes_fp64(oracle_lib):
+    """As above with about 30% of the genes flagged for fallback: they take
+    the slice steps in their own groups, the others the IMH step, and the whole
+    sweep (moments and reductions included) matches the oracle."""
+    F = require_gpu()
+    ds = datagen.paper_design_16(G=700, seed=8)
+    L = ds.L
+    mu = np.round(np.random.default_rng(15).uniform(-0.4, 0.4, L) * 64) / 64
+    log_s = np.round(np.full(L, np.log(1.1)) * 64) / 64
+    off = np.round(np.random.default_rng(13).uniform(-0.3, 0.3, L * (L - 1) // 2) * 64) / 64
+    m = constant_model(L, mu, log_s, off=off)
+    mask = (np.random.default_rng(14).uniform(size=ds.G) < 0.3).astype(np.int32)
+    o = oracle_lib.Oracle(ds.y, ds.X, ds.h, seed=19, burnin=10, tune_start=2)
+    o.sweep(12)
+    opts = F.fb_default_options(precision=0, jitter=0, debug_counts=1, burnin=10, tune_start=2)
+    g = F.fb_create(ds.y, ds.X, ds.h, seed=19, options=opts)
+    F.fb_set_state(g, o.get_state())
+    F.fb_proposal_set(g, to_gpu_params(m, L))
+    F.fb_fallback(g, 0, mask)
+    F.fb_set_beta_update(g, F.FB_BETA_LEARNED)
+    o.set_proposal(m, mask)
+    for it in range(12):
+        o.sweep(1)
+        F.fb_sweep(g, 1)
+        so, sg = o.get_state(), F.fb_get_state(g)
+        acc_o, _ = o.imh()
+        acc_g = F.fb_imh_last(g)
+        assert np.array_equal(acc_o, acc_g), (it, np.flatnonzero(acc_o != acc_g)[:5])
+        assert np.all(acc_g[mask == 1] == -1)
+        for k in ("eps", "gam", "beta", "hyp", "w_beta", "waux_beta"):
+            np.testing.assert_allclose(sg[k], so[k], rtol=1e-9, atol=1e-12, err_msg=f"sweep {it} {k}")
+        np.testing.assert_allclose(F.fb_reductions(g), o.reductions(), rtol=1e-9, atol=1e-9)
+    sm, om = F.fb_summaries(g), o.moments()
+    np.testing.assert_allclose(sm["mean_beta"], om["mean_beta"], rtol=1e-9, atol=1e-12)
+    F.fb_destroy(g)
+
+
 def test_training_lowers_loss():
     F = require_gpu()
     ds = datagen.small_two_group(G=2000, seed=6)
@@ -183,7 +231,9 @@ def test_training_lowers_loss():
     losses = F.fb_proposal_train(g, F.fb_default_train_opts(epochs=40))
     say("training losses", losses[:3], losses[-3:])
     assert np.all(np.isfinite(losses))
-    assert losses[-1] < losses[0] - 0.5
+    # the targets are whitened by the Laplace approximation, so the untrained
+    # network (a small correction) already starts near L / 2 = 1
+    assert losses[-1] < losses[0]
     params = F.fb_proposal_get(g)
     assert np.all(np.isfinite(params["W1"]))
     F.fb_proposal_calibrate(g, 20, 0.2)
@@ -193,5 +243,6 @@ def test_training_lowers_loss():
     fb = F.fb_fallback(g)
     say("fallback genes", int(fb.sum()), "accept rate", float(np.mean(last[fb == 0] == 1)))
     assert np.all(last[fb == 1] == -1)
-    assert np.mean(last[fb == 0] == 1) > 0.3
+    assert np.mean(last[fb == 0] == 1) > 0.6
+    assert fb.mean() < 0.05
     F.fb_destroy(g)

@@ -5,9 +5,10 @@
   multivariate normal log density written with numpy's solver.
 * The independence-MH beta step leaves the exact beta conditional invariant:
   exact draws (scipy quadrature of prior x likelihood) go through one IMH step
-  with deliberately mis-centred, too-wide, too-narrow, correlated and
-  feature-dependent proposals, and their probability-integral transforms stay
-  uniform.
+  whose proposal is the Laplace approximation itself, or that approximation
+  corrected in its whitened coordinates by a shifted, too-wide, too-narrow,
+  correlated or feature-dependent network, and their probability-integral
+  transforms stay uniform.
 """
 import numpy as np
 import pytest
@@ -132,30 +133,18 @@ def _imh_case(oracle_lib, design, model_fn, seed):
     return st.kstest(u, "uniform").pvalue, float(np.mean(acc))
 
 
-def tracking_model(L, shift=0.1, scale=0.15, F=32, H=128, lift=10.0):
-    """mu_l = phi_l + shift, ls_l = log(scale): for designs whose rows each carry
-    one coefficient, phi_l (row l's log-rate) is near the conditional mode of
-    beta_l, so this proposal tracks every gene.  GELU(z) = z to 1e-6 for
-    z > 5, which the lift keeps every unit above."""
-    m = constant_model(L, np.zeros(L), np.full(L, np.log(scale)), F, H)
-    for l in range(L):
-        m["W1"][l, l] = 1.0
-        m["b1"][l] = lift
-        m["W2"][l, l] = 1.0
-        m["W3"][l, l] = 1.0
-        m["b3"][l] = -lift + shift
-    return m
-
-
+# Proposals, as corrections of the Laplace approximation in its whitened
+# coordinates: none, a shifted mean, too wide, too narrow, correlated, and a
+# feature-dependent random network.
 PROPOSALS = [
-    ("tracking", lambda L, ds: tracking_model(L)),
-    ("off_centre", lambda L, ds: constant_model(L, ds.theta + 0.4, np.full(L, np.log(0.3)))),
-    ("too_wide", lambda L, ds: constant_model(L, ds.theta, np.full(L, np.log(2.0)))),
-    ("too_narrow", lambda L, ds: constant_model(L, ds.theta, np.full(L, np.log(0.08)))),
-    ("correlated", lambda L, ds: constant_model(L, ds.theta + 0.1, np.full(L, np.log(0.2)),
-                                                off=np.full(L * (L - 1) // 2, 0.25))),
-    ("random_net", lambda L, ds: dict(random_model(np.random.default_rng(7), L), omean=ds.theta,
-                                      oscale=np.full(L, 0.5))),
+    ("laplace", lambda L, ds: constant_model(L, np.zeros(L), np.zeros(L))),
+    ("shifted", lambda L, ds: constant_model(L, np.full(L, 0.8), np.zeros(L))),
+    ("too_wide", lambda L, ds: constant_model(L, np.zeros(L), np.full(L, np.log(2.0)))),
+    ("too_narrow", lambda L, ds: constant_model(L, np.zeros(L), np.full(L, np.log(0.5)))),
+    ("correlated", lambda L, ds: constant_model(L, np.full(L, 0.1), np.full(L, np.log(0.9)),
+                                                off=np.full(L * (L - 1) // 2, 0.3))),
+    ("random_net", lambda L, ds: dict(random_model(np.random.default_rng(7), L), omean=np.zeros(L),
+                                      oscale=np.full(L, 0.4))),
 ]
 
 

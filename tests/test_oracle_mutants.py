@@ -21,7 +21,7 @@ MUTANTS = [
     (8, "tau rate b + nu sum 1/gamma instead of b + (nu/2) sum 1/gamma",
      lambda o: P.test_tau_conditional(o)),
     (9, "independence MH acceptance without the proposal-density ratio",
-     lambda o: M.test_imh_step_is_stationary(o, "cell_means", *M.PROPOSALS[0])),
+     lambda o: M.test_imh_step_is_stationary(o, "cell_means", *M.PROPOSALS[1])),
 ]
 
 
