@@ -626,6 +626,62 @@ static void imh_step(or_ctx *c, int64_t g, uint32_t mm)
     }
 }
 
+/* The shift step (an addition to Algorithm 1, enabled by bit OR_KIND_SHIFT of
+ * update_mask).  In the model of Section 4.1 the counts of gene g depend on
+ * eps_g and beta_g only through the sums zeta_gn = eps_gn + X_n beta_g, so the
+ * map beta_g -> beta_g + delta, eps_gn -> eps_gn - X_n delta leaves the
+ * likelihood unchanged and has unit Jacobian.  Given zeta_g, gamma_g, theta
+ * and sigma^2, delta has the Gaussian density proportional to
+ *   exp(-sum_n (eps_gn - X_n delta)^2 / (2 gamma_g)
+ *       - sum_l (beta_gl + delta_l - theta_l)^2 / (2 sigma_l^2)),
+ * i.e. precision P = X^T X / gamma_g + diag(1 / sigma^2) and mean P^-1 c with
+ * c = X^T eps_g / gamma_g - (beta_g - theta) / sigma^2.  The step draws delta
+ * exactly: delta = P^-1 c + U^-T z, P = U U^T, z ~ N(0, I) from Box-Muller
+ * pairs on words (2p, 2p + 1) of counter (g, 11 << 24, m, chain << 16 | j). */
+static void shift_step(or_ctx *c, int64_t g, uint32_t mm)
+{
+    const int N = c->cfg.N, L = c->cfg.L;
+    double P[64], U[64], cv[64], mean[64], z[64], v[64];
+    const double ig = 1.0 / c->gam[g];
+    for (int i = 0; i < L; ++i) {
+        double s = 0.0;
+        for (int n = 0; n < N; ++n) s += c->X[n * L + i] * c->eps[g * N + n];
+        cv[i] = s * ig - (OR_MUTANT == 11 ? 0.0 : (c->beta[g * L + i] - c->theta[i]) / c->sig2[i]);
+        for (int j = 0; j < L; ++j) {
+            double x = 0.0;
+            for (int n = 0; n < N; ++n) x += c->X[n * L + i] * c->X[n * L + j];
+            P[i * L + j] = x * ig + (i == j ? 1.0 / c->sig2[i] : 0.0);
+        }
+    }
+    chol(P, L, U);
+    chol_solve(U, L, cv, mean);
+    rstream rs;
+    rs_init(&rs, c->cfg.seed, (uint32_t)g, OR_KIND_SHIFT, 0, mm, (uint32_t)c->cfg.chain);
+    for (int p = 0; 2 * p < L; ++p) {
+        const double ua = u01(rs_word(&rs, (uint32_t)(2 * p)));
+        const double ub = u01(rs_word(&rs, (uint32_t)(2 * p + 1)));
+        const double rho = sqrt(-2.0 * log(ua));
+        z[2 * p] = rho * cos(2.0 * M_PI * ub);
+        if (2 * p + 1 < L) z[2 * p + 1] = rho * sin(2.0 * M_PI * ub);
+    }
+    /* v = U^-T z (back substitution) */
+    for (int i = L - 1; i >= 0; --i) {
+        double s = z[i];
+        for (int k = i + 1; k < L; ++k) s -= U[k * L + i] * v[k];
+        v[i] = s / U[i * L + i];
+    }
+    double d[64];
+    for (int l = 0; l < L; ++l) {
+        d[l] = mean[l] + v[l];
+        c->beta[g * L + l] += d[l];
+    }
+    for (int n = 0; n < N; ++n) {
+        double xd = 0.0;
+        for (int l = 0; l < L; ++l) xd += c->X[n * L + l] * d[l];
+        c->eps[g * N + n] -= (OR_MUTANT == 10 ? -xd : xd);
+    }
+}
+
 int or_set_proposal(or_ctx *c, const or_mlp *m, const int32_t *fallback_mask)
 {
     if (!c) return -1;
@@ -789,6 +845,11 @@ static int64_t sweep_once(or_ctx *c)
                 errs += di.bad;
             }
         }
+    }
+    /* The shift step (an addition; see shift_step), after step 5 */
+    if (mask & (1u << OR_KIND_SHIFT)) {
+#pragma omp parallel for schedule(static) num_threads(c->nthreads)
+        for (int64_t g = 0; g < G; ++g) shift_step(c, g, mm);
     }
     /* Steps 6 and 7: reductions, then theta_l (Normal) and sigma_l^2 (slice) */
     for (int l = 0; l < L; ++l) {

@@ -4,6 +4,7 @@ import pytest
 
 from tests import test_oracle_mlp as M
 from tests import test_oracle_pins as P
+from tests import test_oracle_shift as S
 
 MUTANTS = [
     # (switch, what is wrong, the pin that must fail)
@@ -22,6 +23,10 @@ MUTANTS = [
      lambda o: P.test_tau_conditional(o)),
     (9, "independence MH acceptance without the proposal-density ratio",
      lambda o: M.test_imh_step_is_stationary(o, "cell_means", *M.PROPOSALS[1])),
+    (10, "shift step moves eps by +X delta instead of -X delta",
+     lambda o: S.test_shift_keeps_the_likelihood_sums(o, "paper")),
+    (11, "shift step mean without the prior term (beta - theta) / sigma^2",
+     lambda o: S.test_shift_draws_the_conditional(o, "two_group")),
 ]
 
 
