@@ -36,15 +36,54 @@ TOTAL_ITERS = 20000
 TRACE_GENES = 1000
 
 
-def algorithmic_bytes(N: int, L: int, state_bytes: int):
+def algorithmic_bytes(N: int, L: int, state_bytes: int, shift: bool = False):
     """Post-burn-in bytes one gene moves in one sweep, split by kernel: per eps
     draw y (4 B), eps read + write, the read-only slice width, and the FP64
     (mean, mean square) read + write; the same for gamma and each beta without
-    the count.  Returns (eps kernel, gamma/beta kernel, whole sweep)."""
-    per_draw = 3 * state_bytes + 32
-    e = N * (4 + per_draw)
-    gb = (1 + L) * per_draw
-    return e, gb, e + gb
+    the count.  With the shift step on, the shift kernel reads gamma, reads
+    and writes eps and beta once more, and takes over the eps and beta moments.
+    Returns (eps kernel, gamma/beta kernel, shift kernel, whole sweep)."""
+    s = state_bytes
+    e = N * (4 + 3 * s) + (0 if shift else N * 32)
+    gb = (1 + L) * 3 * s + 32 + (0 if shift else L * 32)
+    sh = (s + 2 * N * s + 2 * L * s + (N + L) * 32) if shift else 0
+    return e, gb, sh, e + gb + sh
+
+
+PROFILE_SUMMARY = os.path.join(ROOT, "profiles", "sweep_kernels_paper_G50k_N16.md")
+KERNEL_SOURCES = ("fbmc_kernels.hip", "fbmc_device.hpp", "fbmc_types.hpp")
+
+
+def kernel_sources_digest() -> str:
+    """sha256 over the sweep kernels' source files, in a fixed order."""
+    import hashlib
+    h = hashlib.sha256()
+    for name in KERNEL_SOURCES:
+        with open(os.path.join(ROOT, "paper_1606_06659_amd", "csrc", name), "rb") as f:
+            h.update(f.read())
+    return h.hexdigest()
+
+
+def measured_traffic():
+    """HBM bytes per launch of each sweep kernel from the committed counter
+    summary (FETCH_SIZE and WRITE_SIZE, each scaled by what the counter reads
+    for device copies of known size).  The summary carries one line
+    `traffic-json: {...}` with the digest of the kernel sources it was taken
+    on; if the sources have changed since, the figures no longer describe
+    these kernels and None is returned."""
+    try:
+        with open(PROFILE_SUMMARY) as f:
+            for line in f:
+                if line.startswith("traffic-json:"):
+                    rec = json.loads(line.split(":", 1)[1])
+                    break
+            else:
+                return None
+    except OSError:
+        return None
+    if rec.get("sources_sha256") != kernel_sources_digest():
+        return None
+    return rec
 
 
 def cpu_baseline(ds, seconds: float = 15.0):
@@ -66,9 +105,11 @@ def cpu_baseline(ds, seconds: float = 15.0):
                        f"(FP64, OpenMP over genes, {dt:.1f} s)")
 
 
-def run_chain(fbmc, diagnostics, ds, args, burnin, post, do_ess, stream, learned):
+def run_chain(fbmc, diagnostics, ds, args, burnin, post, do_ess, stream, learned, shift=False):
     """One chain of the workload: `burnin` sweeps, then `post` post-burn-in
-    sweeps of which `steps` (after `warmup`) are timed.  With learned=True the
+    sweeps of which `steps` (after `warmup`) are timed.  shift=True adds the
+    shift step (beta_g + delta, eps_g - X delta, delta from its exact
+    conditional) to every sweep.  With learned=True the
     last 1,000 burn-in sweeps adapt the learned beta proposal: 400 plain sweeps
     store training pairs (every 4th sweep, 100 x G pairs), the network is
     trained on the GPU, 200 sweeps with the IMH step everywhere calibrate the
@@ -79,6 +120,7 @@ def run_chain(fbmc, diagnostics, ds, args, burnin, post, do_ess, stream, learned
         burnin=burnin, tune_start=burnin // 10, precision=fbmc.FB_FP32, jitter=0,
         thin=1 if do_ess else 0, trace_genes=TRACE_GENES if do_ess else 0,
         trace_after_burnin=1, trace_capacity=post if do_ess else 0,
+        update_mask=fbmc.FB_UPDATE_ALL | (fbmc.FB_SHIFT if shift else 0),
         stream=stream.cuda_stream)
     smp = fbmc.Sampler(ds.y, ds.X, ds.h, seed=1, **{k: getattr(opts, k) for k, *_ in opts._fields_})
     proposal = None
@@ -178,9 +220,9 @@ def run_heavy(fbmc, stream, steps=100, burnin=300):
     smp.sync()
     torch.cuda.synchronize()
     t1 = time.perf_counter()
-    eps_ms, gb_ms, hyp_ms, _ = fbmc.fb_kernel_times(smp.ctx)
+    eps_ms, gb_ms, hyp_ms, _, _ = fbmc.fb_kernel_times(smp.ctx)
     smp.close()
-    b_eps, b_gb, b_sweep = algorithmic_bytes(N, L, 4)
+    b_eps, b_gb, _, b_sweep = algorithmic_bytes(N, L, 4)
     per = (t1 - t0) / steps
     return {"workload": f"heavy G={G} N={N} L={L}, {C} chains in one context", "zero_fraction": float((ds.y == 0).mean()),
             "sweeps_per_s": 1.0 / per, "ms_per_sweep": per * 1e3,
@@ -200,7 +242,8 @@ def main():
     ap.add_argument("--genes", type=int, default=50_000)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-ess", action="store_true")
-    ap.add_argument("--no-learned", action="store_true", help="skip the learned-proposal chain")
+    ap.add_argument("--no-learned", action="store_true", help="skip the learned-proposal chains")
+    ap.add_argument("--no-shift", action="store_true", help="skip the chains with the shift step")
     ap.add_argument("--no-heavy", action="store_true",
                     help="skip the secondary heavy workload (4 chains x G=200k x N=48)")
     ap.add_argument("--launch", default="auto",
@@ -236,14 +279,17 @@ def main():
             dst.copy_(src)
         torch.cuda.synchronize()
         del src, dst
-    plain = run_chain(fbmc, diagnostics, ds, args, burnin, post, do_ess, stream, learned=False)
-    learned = None if args.no_learned else run_chain(fbmc, diagnostics, ds, args, burnin, post, do_ess,
-                                                      stream, learned=True)
+    run = lambda learned, shift: run_chain(fbmc, diagnostics, ds, args, burnin, post, do_ess, stream,
+                                           learned=learned, shift=shift)
+    plain = run(False, False)
+    learned = None if args.no_learned else run(True, False)
+    plain_shift = None if args.no_shift else run(False, True)
+    learned_shift = None if (args.no_shift or args.no_learned) else run(True, True)
     sweeps_per_s = plain["sweeps_per_s"]
     ms_per_step = plain["ms_per_sweep"]
     shape = plain["launch"]
-    eps_ms, gb_ms, hyp_ms, nsamp = plain["kernel_ms"]
-    b_eps, b_gb, b_sweep = algorithmic_bytes(N, L, 4)
+    eps_ms, gb_ms, hyp_ms, _, nsamp = plain["kernel_ms"]
+    b_eps, b_gb, _, b_sweep = algorithmic_bytes(N, L, 4)
     gbs = lambda nbytes, ms: nbytes / (ms * 1e-3) / 1e9 if ms > 0 else None
     kernels = {
         "eps_sweep": {"ms": eps_ms, "bytes_per_gene": b_eps, "bytes_per_launch": b_eps * G,
@@ -254,18 +300,27 @@ def main():
         "samples": nsamp,
     }
     dom = "eps_sweep" if eps_ms >= gb_ms else "gb_sweep"
+    traffic = measured_traffic()
     achieved = kernels[dom]["achieved_GBs"]
     ess_info = plain["ess"]
-    if learned is not None:
-        learned_info = {k: learned[k] for k in ("sweeps_per_s", "ms_per_sweep", "ess", "launch", "proposal",
-                                                "kernel_ms")}
-        learned_info["min_ess_per_s"] = None if learned["ess"] is None else learned["ess"]["min_ess_per_s"]
-        if learned["ess"] is not None and ess_info is not None:
-            learned_info["min_ess_per_s_ratio_vs_plain"] = (learned["ess"]["min_ess_per_s"] /
-                                                            ess_info["min_ess_per_s"])
-        learned_info["sweeps_per_s_ratio_vs_plain"] = learned["sweeps_per_s"] / sweeps_per_s
-    else:
-        learned_info = None
+
+    def form(r, ref):
+        """Summary of one chain and its ratios to the chain `ref`."""
+        if r is None:
+            return None
+        out = {k: r[k] for k in ("sweeps_per_s", "ms_per_sweep", "ess", "launch", "proposal")}
+        e, s_, h, sh, n = r["kernel_ms"]
+        out["kernel_ms"] = {"eps_sweep": e, "gb_sweep": s_, "hyper_sweep": h, "shift_sweep": sh, "samples": n}
+        out["min_ess_per_s"] = None if r["ess"] is None else r["ess"]["min_ess_per_s"]
+        if ref is not None and r["ess"] is not None and ref["ess"] is not None:
+            out["min_ess_per_s_ratio"] = r["ess"]["min_ess_per_s"] / ref["ess"]["min_ess_per_s"]
+        if ref is not None:
+            out["sweeps_per_s_ratio"] = r["sweeps_per_s"] / ref["sweeps_per_s"]
+        return out
+
+    learned_info = form(learned, plain)
+    forms = {"plain": form(plain, None), "learned": learned_info,
+             "plain+shift": form(plain_shift, plain), "learned+shift": form(learned_shift, plain_shift)}
 
     line = {
         "metric": "Gibbs sweeps/s + min-ESS/s of beta at G=50k,N=16; learned vs plain proposal",
@@ -287,10 +342,14 @@ def main():
         "min_ess_per_s": None if ess_info is None else ess_info["min_ess_per_s"],
         "ess": ess_info,
         "learned_proposal": learned_info,
+        "forms": {"note": "ratios: learned vs plain; plain+shift vs plain; learned+shift vs plain+shift",
+                  **forms},
         "kernels": kernels,
         "roofline": {"bound": "hbm", "kernel": dom, "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
                      "frac": None if achieved is None else achieved / HBM_PEAK_GBS,
-                     "traffic": None,
+                     "traffic": None if traffic is None else traffic["bytes_per_launch"].get(dom),
+                     "traffic_unit": "bytes per launch (scaled FETCH_SIZE + WRITE_SIZE)",
+                     "traffic_launch": None if traffic is None else traffic.get("launch"),
                      "bytes_per_launch": kernels[dom]["bytes_per_launch"],
                      "bytes_per_gene": kernels[dom]["bytes_per_gene"]},
         "sweep_hbm": {"bytes_per_sweep": b_sweep * G, "achieved_GBs": b_sweep * G * sweeps_per_s / 1e9,

@@ -66,8 +66,21 @@ enum fb_precision {
 
 enum fb_kind {     /* Philox counter kinds, also bit positions of update_mask */
     FB_KIND_EPS = 1, FB_KIND_GAMMA = 2, FB_KIND_NU = 3, FB_KIND_TAU = 4,
-    FB_KIND_BETA = 5, FB_KIND_THETA = 6, FB_KIND_SIG2 = 7, FB_KIND_IMH = 8
+    FB_KIND_BETA = 5, FB_KIND_THETA = 6, FB_KIND_SIG2 = 7, FB_KIND_IMH = 8,
+    FB_KIND_SHIFT = 11
 };
+/* The steps of Algorithm 1.  The shift step (bit 1 << FB_KIND_SHIFT) is an
+ * addition that is off unless asked for: after steps 2 and 5 it moves every
+ * gene along the directions that leave eps_gn + X_n beta_g -- and so the
+ * likelihood of the model of Section 4.1 -- unchanged,
+ *   beta_g -> beta_g + delta,  eps_gn -> eps_gn - X_n delta,
+ * with delta drawn exactly from its Gaussian conditional given those sums,
+ * gamma_g, theta and sigma^2 (precision X^T X / gamma_g + diag(1 / sigma^2),
+ * mean precision^-1 [X^T eps_g / gamma_g - (beta_g - theta) / sigma^2]).
+ * Philox counter (g, 11 << 24, m, chain << 16 | j); Box-Muller pairs on words
+ * (2p, 2p + 1).  It leaves the posterior invariant and removes the slow
+ * exchange between eps_g and beta_g that the one-at-a-time conditionals have
+ * when the counts pin their sum. */
 #define FB_UPDATE_ALL 0xFEu
 
 /* Prior constants of Section 4.1: tau ~ Gamma(a, rate b), nu ~ U(0, d),
@@ -211,17 +224,19 @@ int fb_philox(const uint32_t *ctr, const uint32_t *key, uint32_t *out, int64_t n
 int fb_last_sweep_time(fb_ctx *c, double *ms, int64_t *sweeps);
 
 /* Sampled kernel timing with HIP events on the context's stream.  A sweep is
- * two or three launches: the eps kernel (Algorithm 1 step 1), the gamma/beta
- * kernel (steps 2 and 5) and the hyperparameter step (steps 3, 4, 6, 7), which
- * either rides in the next sweep's eps kernel (fused, the eps time includes
- * it) or is a kernel of its own (see fb_set_launch).  From now on the launches
- * of every `every`-th sweep are bracketed by events, for at most max_samples
- * sweeps (every = 0 turns it off).  fb_kernel_times waits for the stream,
- * returns the mean duration (ms) of the sampled eps, gamma/beta and separate
- * hyperparameter launches (0 when fused) and the number of samples, and starts
- * a new sample set. */
+ * two to four launches: the eps kernel (Algorithm 1 step 1), the gamma/beta
+ * kernel (steps 2 and 5), the shift kernel when that step is on, and the
+ * hyperparameter step (steps 3, 4, 6, 7), which either rides in the next
+ * sweep's eps kernel (fused, the eps time includes it) or is a kernel of its
+ * own (see fb_set_launch).  From now on the launches of every `every`-th sweep
+ * are bracketed by events, for at most max_samples sweeps (every = 0 turns it
+ * off).  fb_kernel_times waits for the stream, returns the mean duration (ms)
+ * of the sampled eps, gamma/beta, separate hyperparameter (0 when fused) and
+ * shift (0 when off) launches and the number of samples, and starts a new
+ * sample set.  Null output pointers are skipped. */
 int fb_profile(fb_ctx *c, int32_t every, int32_t max_samples);
-int fb_kernel_times(fb_ctx *c, double *eps_ms, double *gb_ms, double *hyper_ms, int64_t *samples);
+int fb_kernel_times(fb_ctx *c, double *eps_ms, double *gb_ms, double *hyper_ms, double *shift_ms,
+                    int64_t *samples);
 
 /* Launch shape of a sweep; no choice changes any draw (the draws are functions
  * of their counters only).

@@ -25,6 +25,8 @@ hipError_t launch_eps(int precision, const SegInfo *segs, const int4 *items, int
 hipError_t launch_gb(int precision, bool learned, const SegInfo *segs, const int2 *tiles, int ntiles,
                      const int4 *fb_items, int nfb, const SweepArgs &a, const MlpDev *net, int *err, hipStream_t st);
 hipError_t launch_hyper(const SegInfo *segs, int nseg, const SweepArgs &a, int *err, hipStream_t st);
+hipError_t launch_shift(int precision, const SegInfo *segs, const int2 *tiles, int ntiles, const SweepArgs &a,
+                        hipStream_t st);
 hipError_t launch_philox(const uint4 *ctr, const uint2 *key, uint4 *out, int64_t n, hipStream_t st);
 hipError_t launch_mlp_infer_raw(const float *phi, int64_t B, int L, const MlpDev *net, float *mu, float *ls,
                                 float *off, hipStream_t st);
@@ -101,8 +103,9 @@ struct fb_ctx {
     // every `prof_every`-th sweep
     int32_t prof_every = 0, prof_cap = 0, prof_n = 0;
     int64_t prof_count = 0;
-    std::vector<hipEvent_t> prof_ev;   // 6 per sample: eps, gamma/beta, hyperparameter kernel
+    std::vector<hipEvent_t> prof_ev;   // 8 per sample: eps, gamma/beta, hyperparameter, shift kernel
     std::vector<char> prof_hyp;        // sample has a separate hyperparameter kernel
+    std::vector<char> prof_shift;      // sample has a shift kernel
     // learned beta proposal
     int beta_mode = FB_BETA_SLICE;
     bool learned_ready = false;
@@ -483,6 +486,12 @@ int build_context(fb_ctx *c, const fb_dataset *dsv, int nds)
                 I.eh[n] = std::exp(D.h[n]);
                 I.row_of[n] = D.des.row_of[n];
             }
+            for (int i = 0; i < D.L; ++i)
+                for (int j = 0; j < D.L; ++j) {
+                    double x = 0.0;
+                    for (int n = 0; n < D.N; ++n) x += D.X[n * D.L + i] * D.X[n * D.L + j];
+                    I.XtX[i * kMaxL + j] = x;
+                }
             for (int r = 0; r < D.des.R; ++r)
                 for (int l = 0; l < D.L; ++l) {
                     I.Xrow[r * kMaxL + l] = D.des.Xrow[r * D.L + l];
@@ -650,8 +659,12 @@ int run_sweeps(fb_ctx *c, int64_t n, SweepMode &md)
             else ++c->trace_dropped;
         }
         const bool prof = c->prof_every > 0 && c->prof_n < c->prof_cap && (c->prof_count++ % c->prof_every) == 0;
-        hipEvent_t *pe = prof ? &c->prof_ev[6 * (size_t)c->prof_n] : nullptr;
-        if (prof) c->prof_hyp[c->prof_n++] = c->fuse ? 0 : 1;
+        const bool shift = (a.mask >> kKindShift) & 1u;
+        hipEvent_t *pe = prof ? &c->prof_ev[8 * (size_t)c->prof_n] : nullptr;
+        if (prof) {
+            c->prof_hyp[c->prof_n] = c->fuse ? 0 : 1;
+            c->prof_shift[c->prof_n++] = shift ? 1 : 0;
+        }
         if (pe) HIPCHK(c, hipEventRecord(pe[0], c->st));
         HIPCHK(c, launch_eps(c->prec, c->d_segs, c->d_items, c->nitems, a, pending ? nseg : 0, prev, c->d_err,
                              c->st));
@@ -660,6 +673,11 @@ int run_sweeps(fb_ctx *c, int64_t n, SweepMode &md)
         HIPCHK(c, launch_gb(c->prec, md.learned_kernel, c->d_segs, c->d_tiles, c->ntiles, c->d_fb_items,
                             md.learned ? c->nfb_items : 0, a, c->d_net, c->d_err, c->st));
         if (pe) HIPCHK(c, hipEventRecord(pe[3], c->st));
+        if (shift) {
+            if (pe) HIPCHK(c, hipEventRecord(pe[6], c->st));
+            HIPCHK(c, launch_shift(c->prec, c->d_segs, c->d_tiles, c->ntiles, a, c->st));
+            if (pe) HIPCHK(c, hipEventRecord(pe[7], c->st));
+        }
         if (c->fuse) {
             prev = a;
             pending = true;
@@ -1218,13 +1236,14 @@ int fb_profile(fb_ctx *c, int32_t every, int32_t max_samples)
     if (!c) return fail(nullptr, FB_EINVAL, "NULL context");
     if (every < 0 || max_samples < 0) return fail(c, FB_EINVAL, "every and max_samples must be >= 0");
     HIPCHK(c, hipStreamSynchronize(c->st));
-    const size_t need = 6 * (size_t)max_samples;
+    const size_t need = 8 * (size_t)max_samples;
     while (c->prof_ev.size() < need) {
         hipEvent_t e;
         HIPCHK(c, hipEventCreate(&e));
         c->prof_ev.push_back(e);
     }
     c->prof_hyp.assign((size_t)max_samples, 0);
+    c->prof_shift.assign((size_t)max_samples, 0);
     c->prof_every = every;
     c->prof_cap = max_samples;
     c->prof_n = 0;
@@ -1232,20 +1251,27 @@ int fb_profile(fb_ctx *c, int32_t every, int32_t max_samples)
     return FB_OK;
 }
 
-int fb_kernel_times(fb_ctx *c, double *eps_ms, double *gb_ms, double *hyper_ms, int64_t *samples)
+int fb_kernel_times(fb_ctx *c, double *eps_ms, double *gb_ms, double *hyper_ms, double *shift_ms,
+                    int64_t *samples)
 {
     if (!c) return fail(nullptr, FB_EINVAL, "NULL context");
     HIPCHK(c, hipStreamSynchronize(c->st));
-    double te = 0, tg = 0, th = 0;
-    int64_t nh = 0;
+    double te = 0, tg = 0, th = 0, ts = 0;
+    int64_t nh = 0, ns = 0;
     for (int32_t i = 0; i < c->prof_n; ++i) {
-        float a = 0, b = 0, h = 0;
-        HIPCHK(c, hipEventElapsedTime(&a, c->prof_ev[6 * i], c->prof_ev[6 * i + 1]));
-        HIPCHK(c, hipEventElapsedTime(&b, c->prof_ev[6 * i + 2], c->prof_ev[6 * i + 3]));
+        const hipEvent_t *pe = &c->prof_ev[8 * (size_t)i];
+        float a = 0, b = 0, h = 0, sh = 0;
+        HIPCHK(c, hipEventElapsedTime(&a, pe[0], pe[1]));
+        HIPCHK(c, hipEventElapsedTime(&b, pe[2], pe[3]));
         if (c->prof_hyp[i]) {
-            HIPCHK(c, hipEventElapsedTime(&h, c->prof_ev[6 * i + 4], c->prof_ev[6 * i + 5]));
+            HIPCHK(c, hipEventElapsedTime(&h, pe[4], pe[5]));
             th += h;
             ++nh;
+        }
+        if (c->prof_shift[i]) {
+            HIPCHK(c, hipEventElapsedTime(&sh, pe[6], pe[7]));
+            ts += sh;
+            ++ns;
         }
         te += a;
         tg += b;
@@ -1253,6 +1279,7 @@ int fb_kernel_times(fb_ctx *c, double *eps_ms, double *gb_ms, double *hyper_ms, 
     if (eps_ms) *eps_ms = c->prof_n ? te / c->prof_n : 0.0;
     if (gb_ms) *gb_ms = c->prof_n ? tg / c->prof_n : 0.0;
     if (hyper_ms) *hyper_ms = nh ? th / nh : 0.0;
+    if (shift_ms) *shift_ms = ns ? ts / ns : 0.0;
     if (samples) *samples = c->prof_n;
     c->prof_n = 0;
     c->prof_count = 0;

@@ -593,7 +593,9 @@ __device__ inline void eps_wave(const SegInfo &S, int tile, int n0, int n1, cons
     const int L = S.L;
     const uint32_t mm = (uint32_t)a.m, chain = (uint32_t)S.chain;
     const uint32_t k0 = S.key0, k1 = S.key1;
-    const bool tuning = a.m <= a.burnin, sampling = a.m > a.burnin;
+    const bool tuning = a.m <= a.burnin;
+    // with the shift step on, eps moments are taken after it (shift_sweep)
+    const bool sampling = a.m > a.burnin && !((a.mask >> kKindShift) & 1u);
     const bool upd = (a.mask >> 1) & 1u;
     const int32_t *__restrict__ yp = S.y;
     T *__restrict__ eps = (T *)S.eps;
@@ -831,7 +833,10 @@ __device__ inline void beta_genes(const SegInfo &S, int64_t g, bool active, int6
     } else {
         if (mine && upd_beta) beta_slice_draws<T>(S, a, g, Gp, true, beta, wb, wab, th, s2, C, YR, tuning, bad);
     }
-    beta_finish<T>(S, a, g, Gp, mine, beta, mob, th, col, lane, tslot, trow, sampling);
+    // with the shift step on, the moments, trace and partials of beta are
+    // taken after it (shift_sweep)
+    if (!((a.mask >> kKindShift) & 1u))
+        beta_finish<T>(S, a, g, Gp, mine, beta, mob, th, col, lane, tslot, trow, sampling);
     if (bad) raise_flag(err, 2);
 }
 
@@ -874,6 +879,146 @@ __global__ __launch_bounds__(128) void gb_sweep(const SegInfo *__restrict__ segs
             S.partials[S.pstride + col] = 0.0;
         }
     }
+}
+
+// ---------------------------------------------------------------------------
+// The shift step (an addition to Algorithm 1; update_mask bit kKindShift),
+// after steps 2 and 5 and before the hyperparameter steps.  In the model of
+// Section 4.1 the counts of gene g depend on eps_g and beta_g only through
+// eps_gn + X_n beta_g, so beta_g -> beta_g + delta, eps_gn -> eps_gn - X_n delta
+// keeps the likelihood and has unit Jacobian; given those sums, gamma_g, theta
+// and sigma^2, delta is Gaussian with precision P = X^T X / gamma_g +
+// diag(1 / sigma^2) and mean P^-1 c, c = X^T eps_g / gamma_g - (beta_g - theta)
+// / sigma^2.  It is drawn exactly: delta = P^-1 c + U^-T z, P = U U^T, z from
+// Box-Muller pairs on words (2p, 2p + 1) of counter (g, 11 << 24, m,
+// chain << 16 | j).  The eps moments, and the beta moments, trace and tile
+// partials, are taken here, after the step.  One lane per gene, one wavefront
+// per tile, four tiles per workgroup.
+// ---------------------------------------------------------------------------
+template <typename T>
+__device__ inline void shift_genes(const SegInfo &S, int tile, const SweepArgs &a)
+{
+    const int lane = (int)(threadIdx.x & 63);
+    const int64_t Gp = S.Gp;
+    const int64_t g = (int64_t)tile * kTile + lane;
+    const bool active = g < S.G;
+    const int N = S.N, L = S.L;
+    const bool sampling = a.m > a.burnin;
+    const HyperState &H = *S.hyp;
+    double th[kMaxL], s2[kMaxL];
+#pragma unroll
+    for (int l = 0; l < kMaxL; ++l) {
+        th[l] = l < L ? H.theta[l] : 0.0;
+        s2[l] = l < L ? H.sig2[l] : 1.0;
+    }
+    T *__restrict__ eps = (T *)S.eps;
+    T *__restrict__ betap = (T *)S.beta;
+    T beta[kMaxL], d[kMaxL];
+    double2 mob[kMaxL];
+#pragma unroll
+    for (int l = 0; l < kMaxL; ++l) {
+        const bool on = l < L && active;
+        beta[l] = on ? betap[(int64_t)l * Gp + g] : (T)0;
+        mob[l] = (on && sampling) ? S.mom_beta[(int64_t)l * Gp + g] : make_double2(0.0, 0.0);
+        d[l] = (T)0;
+    }
+    if (active) {
+        const T ig = (T)1 / ((const T *)S.gam)[g];
+        T xe[kMaxL];
+#pragma unroll
+        for (int l = 0; l < kMaxL; ++l) xe[l] = (T)0;
+#pragma unroll 4
+        for (int n = 0; n < N; ++n) {
+            const T e = eps[(int64_t)n * Gp + g];
+#pragma unroll
+            for (int l = 0; l < kMaxL; ++l)
+                if (l < L) xe[l] += (T)S.X[n * kMaxL + l] * e;
+        }
+        T U[kTri], cv[kMaxL], mean[kMaxL];
+#pragma unroll
+        for (int i = 0; i < kMaxL; ++i) {
+            cv[i] = i < L ? xe[i] * ig - (T)(((double)beta[i] - th[i]) / s2[i]) : (T)0;
+#pragma unroll
+            for (int j = 0; j <= i; ++j)
+                U[tri(i, j)] = (i < L) ? (T)S.XtX[i * kMaxL + j] * ig + (i == j ? (T)(1.0 / s2[i]) : (T)0)
+                                       : (T)0;
+        }
+        chol_packed<T>(U, L);
+        chol_solve_packed<T>(U, L, cv, mean);
+        const uint4 ctr = draw_counter((uint32_t)g, kKindShift, 0, (uint32_t)a.m, (uint32_t)S.chain, 0);
+        const uint4 b0 = philox4x32_10(ctr, S.key0, S.key1);
+        const uint4 b1 = philox4x32_10(make_uint4(ctr.x, ctr.y, ctr.z, ctr.w | 1u), S.key0, S.key1);
+        const uint32_t wv[8] = {b0.x, b0.y, b0.z, b0.w, b1.x, b1.y, b1.z, b1.w};
+        T z[kMaxL];
+#pragma unroll
+        for (int p = 0; p < kMaxL / 2; ++p) {
+            const T ua = u01<T>(wv[2 * p]), ub = u01<T>(wv[2 * p + 1]);
+            if constexpr (sizeof(T) == sizeof(float)) {
+                const float rho = ::sqrtf(-2.0f * ::logf(ua));
+                float sn, cs;
+                ::sincosf(6.28318530717958648f * ub, &sn, &cs);
+                z[2 * p] = rho * cs;
+                z[2 * p + 1] = rho * sn;
+            } else {
+                const double rho = ::sqrt(-2.0 * ::log((double)ua));
+                const double ang = 6.283185307179586 * (double)ub;
+                z[2 * p] = (T)(rho * ::cos(ang));
+                z[2 * p + 1] = (T)(rho * ::sin(ang));
+            }
+        }
+        // v = U^-T z (back substitution), delta = mean + v
+        T v[kMaxL];
+#pragma unroll
+        for (int i = kMaxL - 1; i >= 0; --i) {
+            v[i] = (T)0;
+            if (i < L) {
+                T sum = z[i];
+#pragma unroll
+                for (int k = 0; k < kMaxL; ++k)
+                    if (k > i && k < L) sum -= U[tri(k, i)] * v[k];
+                v[i] = sum / U[tri(i, i)];
+            }
+        }
+#pragma unroll
+        for (int l = 0; l < kMaxL; ++l)
+            if (l < L) {
+                d[l] = mean[l] + v[l];
+                beta[l] += d[l];
+                betap[(int64_t)l * Gp + g] = beta[l];
+            }
+        double2 *__restrict__ mom = S.mom_eps;
+#pragma unroll 4
+        for (int n = 0; n < N; ++n) {
+            const int64_t idx = (int64_t)n * Gp + g;
+            T xd = (T)0;
+#pragma unroll
+            for (int l = 0; l < kMaxL; ++l)
+                if (l < L) xd += (T)S.X[n * kMaxL + l] * d[l];
+            const T e = eps[idx] - xd;
+            eps[idx] = e;
+            if (sampling) {
+                double2 mo = mom[idx];
+                welford(mo, (double)e, a.inv_k);
+                mom[idx] = mo;
+            }
+        }
+    }
+    const int tslot = (a.trace_point >= 0 && active) ? S.trace_slot[g] : -1;
+    float *trow = a.trace_point >= 0 ? S.trace + (int64_t)a.trace_point * S.trace_stride + 2 + 2 * L : nullptr;
+    beta_finish<T>(S, a, g, Gp, active, beta, mob, th, tile, lane, tslot, trow, sampling);
+}
+
+template <typename T>
+__global__ __launch_bounds__(256) void shift_sweep(const SegInfo *__restrict__ segs, const int2 *__restrict__ tiles,
+                                                   int ntiles, SweepArgs a)
+{
+    const int wave = __builtin_amdgcn_readfirstlane((int)(threadIdx.x >> 6));
+    const int tix = (int)blockIdx.x * 4 + wave;
+    if (tix >= ntiles) return;            // the whole wavefront leaves
+    const int2 tt = tiles[tix];
+    const int sidx = __builtin_amdgcn_readfirstlane(tt.x);
+    const int tile = __builtin_amdgcn_readfirstlane(tt.y);
+    shift_genes<T>(segs[sidx], tile, a);
 }
 
 // ---------------------------------------------------------------------------
@@ -1109,7 +1254,9 @@ __device__ inline void hyper_block(const SegInfo &S, const SweepArgs &a, int *er
     // flight (this code also runs inside the eps kernel, whose register budget
     // is set for the eps wavefronts) and few round trips.
     // columns: the tiles, then (learned step) the fallback groups
-    const int64_t nt = S.ntiles + (a.learned ? S.nfbw : 0);
+    // fallback groups hold beta partials of their own unless the shift step
+    // takes every gene's partials in its tile column
+    const int64_t nt = S.ntiles + ((a.learned && !((a.mask >> kKindShift) & 1u)) ? S.nfbw : 0);
     for (int j0 = 0; j0 < nparts; j0 += 4) {
         double acc[4] = {0.0, 0.0, 0.0, 0.0};
 #pragma unroll 2
@@ -1303,6 +1450,18 @@ hipError_t launch_gb(int precision, bool learned, const SegInfo *segs, const int
             hipLaunchKernelGGL((gb_sweep<float, false>), grid, block, 0, st, segs, tiles, ntiles, fb_items, 0, a, net,
                                err);
     }
+    return hipGetLastError();
+}
+
+hipError_t launch_shift(int precision, const SegInfo *segs, const int2 *tiles, int ntiles, const SweepArgs &a,
+                        hipStream_t st)
+{
+    if (ntiles <= 0) return hipSuccess;
+    const dim3 grid((unsigned)((ntiles + 3) / 4)), block(256);
+    if (precision == 1)
+        hipLaunchKernelGGL(shift_sweep<float>, grid, block, 0, st, segs, tiles, ntiles, a);
+    else
+        hipLaunchKernelGGL(shift_sweep<double>, grid, block, 0, st, segs, tiles, ntiles, a);
     return hipGetLastError();
 }
 

@@ -12,6 +12,7 @@ constexpr int kMaxRows = 8;    // distinct rows of X
 constexpr int kMaxVals = 4;    // distinct non-zero values per column
 constexpr int kTile = 64;      // genes per wavefront tile
 constexpr int kMaxParts = 2 + 2 * kMaxL;
+constexpr int kKindShift = 11;  // Philox kind and update_mask bit of the shift step
 
 // Per-segment (dataset x chain) description.  Lives in device memory and is
 // read with wavefront-uniform loads.  Arrays of state are gene-contiguous
@@ -36,6 +37,7 @@ struct SegInfo {
     int32_t xidx[kMaxRows * kMaxL];// [R][L]: index of X_rl among the column's non-zero values, -1 if 0
     int32_t nv[kMaxL];            // distinct non-zero values of column l
     double vals[kMaxL * kMaxVals];// [L][kMaxVals]
+    double XtX[kMaxL * kMaxL];    // [L][L] sum_n X_n^T X_n (shift step)
     // prior constants (Section 4.1)
     double a, b, d;
     double c[kMaxL], s[kMaxL];

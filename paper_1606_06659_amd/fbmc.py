@@ -19,6 +19,8 @@ FB_OK, FB_EINVAL, FB_ENOMEM, FB_EDEVICE, FB_ENUMERIC, FB_ESTATE = 0, -1, -2, -3,
 FB_FP64, FB_FP32 = 0, 1
 FB_KIND_EPS, FB_KIND_GAMMA, FB_KIND_NU, FB_KIND_TAU = 1, 2, 3, 4
 FB_KIND_BETA, FB_KIND_THETA, FB_KIND_SIG2, FB_KIND_IMH = 5, 6, 7, 8
+FB_KIND_SHIFT = 11
+FB_SHIFT = 1 << FB_KIND_SHIFT     # update_mask bit of the shift step (off by default)
 FB_UPDATE_ALL = 0xFE
 FB_MAX_N, FB_MAX_L, FB_MAX_ROWS, FB_MAX_COLVALS = 64, 8, 8, 4
 
@@ -113,7 +115,7 @@ def load() -> C.CDLL:
     L.fb_philox.argtypes = [up, up, up, i64]
     L.fb_last_sweep_time.argtypes = [vp, _DP, C.POINTER(i64)]
     L.fb_profile.argtypes = [vp, i32, i32]
-    L.fb_kernel_times.argtypes = [vp, _DP, _DP, _DP, C.POINTER(i64)]
+    L.fb_kernel_times.argtypes = [vp, _DP, _DP, _DP, _DP, C.POINTER(i64)]
     L.fb_set_launch.argtypes = [vp, i32, i32]
     L.fb_get_launch.argtypes = [vp, C.POINTER(i32), C.POINTER(i32)]
     L.fb_autotune.argtypes = [vp, i32, C.POINTER(i32), C.POINTER(i32), _DP, _DP]
@@ -320,10 +322,11 @@ def fb_profile(ctx, every: int, max_samples: int):
 
 def fb_kernel_times(ctx):
     """(mean eps-kernel ms, mean gamma/beta-kernel ms, mean separate
-    hyperparameter-kernel ms or 0 when fused, samples) of the sampled sweeps."""
-    e, g, h, n = C.c_double(), C.c_double(), C.c_double(), C.c_int64()
-    _check(load().fb_kernel_times(ctx, C.byref(e), C.byref(g), C.byref(h), C.byref(n)), ctx)
-    return e.value, g.value, h.value, n.value
+    hyperparameter-kernel ms or 0 when fused, mean shift-kernel ms or 0 when
+    the step is off, samples) of the sampled sweeps."""
+    e, g, h, s, n = C.c_double(), C.c_double(), C.c_double(), C.c_double(), C.c_int64()
+    _check(load().fb_kernel_times(ctx, C.byref(e), C.byref(g), C.byref(h), C.byref(s), C.byref(n)), ctx)
+    return e.value, g.value, h.value, s.value, n.value
 
 
 def fb_set_launch(ctx, samples_per_wave: int, fuse_hyper: int):

@@ -184,10 +184,12 @@ def test_imh_sweep_parity_fp64(oracle_lib):
     F.fb_destroy(g)
 
 
-def test_imh_sweep_parity_with_fallback_genes_fp64(oracle_lib):
+@pytest.mark.parametrize("shift", [0, 1])
+def test_imh_sweep_parity_with_fallback_genes_fp64(oracle_lib, shift):
     """As above with about 30% of the genes flagged for fallback: they take
     the slice steps in their own groups, the others the IMH step, and the whole
-    sweep (moments and reductions included) matches the oracle."""
+    sweep (moments and reductions included) matches the oracle; with the shift
+    step on, it follows both kinds of beta step."""
     F = require_gpu()
     ds = datagen.paper_design_16(G=700, seed=8)
     L = ds.L
@@ -196,9 +198,13 @@ def test_imh_sweep_parity_with_fallback_genes_fp64(oracle_lib):
     off = np.round(np.random.default_rng(13).uniform(-0.3, 0.3, L * (L - 1) // 2) * 64) / 64
     m = constant_model(L, mu, log_s, off=off)
     mask = (np.random.default_rng(14).uniform(size=ds.G) < 0.3).astype(np.int32)
-    o = oracle_lib.Oracle(ds.y, ds.X, ds.h, seed=19, burnin=10, tune_start=2)
-    o.sweep(12)
-    opts = F.fb_default_options(precision=0, jitter=0, debug_counts=1, burnin=10, tune_start=2)
+    # hand the state over before the end of burn-in, so that both sides
+    # accumulate the running moments over the same post-burn-in sweeps
+    mask = F.FB_UPDATE_ALL | (F.FB_SHIFT if shift else 0)
+    o = oracle_lib.Oracle(ds.y, ds.X, ds.h, seed=19, burnin=10, tune_start=2, update_mask=mask)
+    o.sweep(7)
+    opts = F.fb_default_options(precision=0, jitter=0, debug_counts=1, burnin=10, tune_start=2,
+                                update_mask=mask)
     g = F.fb_create(ds.y, ds.X, ds.h, seed=19, options=opts)
     F.fb_set_state(g, o.get_state())
     F.fb_proposal_set(g, to_gpu_params(m, L))

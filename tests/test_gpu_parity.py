@@ -240,8 +240,8 @@ def test_determinism_and_resume():
 SHAPES = [(1, 1), (1, 0), (3, 1), (16, 0), (16, 1)]
 
 
-@pytest.mark.parametrize("precision", [0, 1])
-def test_launch_shapes_give_identical_chains(precision):
+@pytest.mark.parametrize("precision,shift", [(0, 0), (1, 0), (1, 1)])
+def test_launch_shapes_give_identical_chains(precision, shift):
     """Every draw is a function of its counter only: the samples per eps
     wavefront and fusing the hyperparameter step into the next eps launch
     change no bit of the state, the moments or the trace."""
@@ -251,7 +251,8 @@ def test_launch_shapes_give_identical_chains(precision):
     for spw, fuse in SHAPES:
         say("shape", spw, fuse, "precision", precision)
         opts = F.fb_default_options(burnin=15, tune_start=3, precision=precision, jitter=0, thin=1,
-                                    trace_genes=10, trace_capacity=40, debug_counts=1)
+                                    trace_genes=10, trace_capacity=40, debug_counts=1,
+                                    update_mask=F.FB_UPDATE_ALL | (F.FB_SHIFT if shift else 0))
         g = F.fb_create(ds.y, ds.X, ds.h, seed=6, options=opts)
         F.fb_set_launch(g, spw, fuse)
         assert F.fb_get_launch(g) == (spw, fuse)
@@ -297,8 +298,8 @@ def test_autotune_leaves_the_chain_unchanged():
     assert np.array_equal(ta, tb)
 
 
-@pytest.mark.parametrize("precision", [0, 1])
-def test_batched_segments_match_single_runs(precision):
+@pytest.mark.parametrize("precision,shift", [(0, 0), (1, 0), (1, 1)])
+def test_batched_segments_match_single_runs(precision, shift):
     """Datasets of uneven G, N and L, each with two chains, in one context: every
     (dataset, chain) segment is bit-identical to the same dataset run alone
     (its draws use the dataset's seed and the chain index only; its
@@ -307,7 +308,8 @@ def test_batched_segments_match_single_runs(precision):
     meta = [(300, 4), (1000, 16), (77, 8), (2500, 4), (64, 16)]
     dss = [datagen.batched_dataset(k + 1, G, N) for k, (G, N) in enumerate(meta)]
     opts = dict(burnin=10, tune_start=2, precision=precision, jitter=1, chains=2, thin=1,
-                trace_genes=8, trace_capacity=30, debug_counts=1)
+                trace_genes=8, trace_capacity=30, debug_counts=1,
+                update_mask=F.FB_UPDATE_ALL | (F.FB_SHIFT if shift else 0))
     b = F.fb_create_batch([dict(counts=d.y, X=d.X, h=d.h, seed=100 + k) for k, d in enumerate(dss)],
                           F.fb_default_options(**opts))
     assert F.fb_num_segments(b) == 2 * len(dss)
