@@ -22,11 +22,13 @@
 namespace fbmc {
 hipError_t launch_eps(int precision, const SegInfo *segs, const int4 *items, int nitems, const SweepArgs &a,
                       int nhyp, const SweepArgs &ha, int *err, hipStream_t st);
-hipError_t launch_gb(int precision, bool learned, const SegInfo *segs, const int2 *tiles, int ntiles,
+hipError_t launch_gb(int precision, bool learned, int maxL, const SegInfo *segs, const int2 *tiles, int ntiles,
                      const int4 *fb_items, int nfb, const SweepArgs &a, const MlpDev *net, int *err, hipStream_t st);
 hipError_t launch_hyper(const SegInfo *segs, int nseg, const SweepArgs &a, int *err, hipStream_t st);
-hipError_t launch_shift(int precision, const SegInfo *segs, const int2 *tiles, int ntiles, const SweepArgs &a,
-                        hipStream_t st);
+hipError_t launch_shift(int precision, int maxL, const SegInfo *segs, const int2 *tiles, int ntiles,
+                        const SweepArgs &a, hipStream_t st);
+hipError_t launch_mlp_sweep(int precision, const SegInfo *segs, const int2 *tiles, int ntiles, const MlpDev *net,
+                            hipStream_t st);
 hipError_t launch_philox(const uint4 *ctr, const uint2 *key, uint4 *out, int64_t n, hipStream_t st);
 hipError_t launch_mlp_infer_raw(const float *phi, int64_t B, int L, const MlpDev *net, float *mu, float *ls,
                                 float *off, hipStream_t st);
@@ -82,6 +84,7 @@ struct fb_ctx {
     SegInfo *d_segs = nullptr;
     int2 *d_tiles = nullptr;
     int ntiles = 0;
+    int maxL = 0;                     // largest L over the segments (picks the compiled bound)
     // eps work items (segment, tile, n0, n1): samples per wavefront `spw`
     int4 *d_items = nullptr;
     int nitems = 0, item_cap = 0, spw = 0;
@@ -565,6 +568,8 @@ int build_context(fb_ctx *c, const fb_dataset *dsv, int nds)
         }
     }
     c->ntiles = (int)tiles.size();
+    c->maxL = 0;
+    for (const auto &S : c->seg) c->maxL = std::max(c->maxL, S.L);
     if ((rc = dalloc(c, (void **)&c->d_tiles, tiles.size() * sizeof(int2)))) return rc;
     HIPCHK(c, hipMemcpy(c->d_tiles, tiles.data(), tiles.size() * sizeof(int2), hipMemcpyHostToDevice));
     std::vector<SegInfo> infos;
@@ -670,12 +675,13 @@ int run_sweeps(fb_ctx *c, int64_t n, SweepMode &md)
                              c->st));
         if (pe) HIPCHK(c, hipEventRecord(pe[1], c->st));
         if (pe) HIPCHK(c, hipEventRecord(pe[2], c->st));
-        HIPCHK(c, launch_gb(c->prec, md.learned_kernel, c->d_segs, c->d_tiles, c->ntiles, c->d_fb_items,
+        if (md.learned) HIPCHK(c, launch_mlp_sweep(c->prec, c->d_segs, c->d_tiles, c->ntiles, c->d_net, c->st));
+        HIPCHK(c, launch_gb(c->prec, md.learned_kernel, c->maxL, c->d_segs, c->d_tiles, c->ntiles, c->d_fb_items,
                             md.learned ? c->nfb_items : 0, a, c->d_net, c->d_err, c->st));
         if (pe) HIPCHK(c, hipEventRecord(pe[3], c->st));
         if (shift) {
             if (pe) HIPCHK(c, hipEventRecord(pe[6], c->st));
-            HIPCHK(c, launch_shift(c->prec, c->d_segs, c->d_tiles, c->ntiles, a, c->st));
+            HIPCHK(c, launch_shift(c->prec, c->maxL, c->d_segs, c->d_tiles, c->ntiles, a, c->st));
             if (pe) HIPCHK(c, hipEventRecord(pe[7], c->st));
         }
         if (c->fuse) {
@@ -717,6 +723,7 @@ int ensure_learned(fb_ctx *c)
         if ((rc = dalloc(c, (void **)&I.imh_count, Gp * sizeof(int32_t)))) return rc;
         if ((rc = dalloc(c, (void **)&I.imh_last, Gp * sizeof(int32_t)))) return rc;
         if ((rc = dalloc(c, (void **)&I.fb_genes, Gp * sizeof(int32_t)))) return rc;
+        if ((rc = dalloc(c, (void **)&I.mlp_out, Gp * (size_t)mlp_outputs(S.L) * sizeof(float)))) return rc;
         I.nfbw = 0;
         c->totalG += S.G;
     }
@@ -767,7 +774,7 @@ int ensure_net(fb_ctx *c)
 
 int pack_net(fb_ctx *c, const float *d_master, MlpDev *d_net, hipStream_t st)
 {
-    const int total = (kMlpH / 16) * (kMlpH / 32) * 64 * 8;
+    const int total = std::max((kMlpH / 16) * (kMlpH / 32) * 64 * 8, kWtFrags * 64 * 8);
     hipLaunchKernelGGL(pack_mlp, dim3((total + 255) / 256), dim3(256), 0, st, d_master, d_net);
     HIPCHK(c, hipGetLastError());
     return FB_OK;
@@ -860,17 +867,17 @@ int forward_backward(fb_ctx *c, const float *master, TrainBufs &t, int L, hipStr
     float *g = t.grad;
     // layer 3
     HIPCHK(c, gemm(t.H2, kMlpH, 1, t.dO, kMlpO, 0, g + kOffW3, kMlpO, kMlpH, kMlpO, B, st));
-    hipLaunchKernelGGL(col_sum, dim3(1), dim3(kMlpO), 0, st, t.dO, B, kMlpO, g + kOffB3);
+    hipLaunchKernelGGL(col_sum, dim3(kMlpO), dim3(256), 0, st, t.dO, B, kMlpO, g + kOffB3);
     HIPCHK(c, gemm(t.dO, kMlpO, 0, W3, kMlpO, 1, t.dH, kMlpH, B, kMlpH, kMlpO, st));
     hipLaunchKernelGGL(gelu_backward, ew((int64_t)B * kMlpH), dim3(256), 0, st, t.Z2, t.dH, t.dZ2, (int64_t)B * kMlpH);
     // layer 2
     HIPCHK(c, gemm(t.H1, kMlpH, 1, t.dZ2, kMlpH, 0, g + kOffW2, kMlpH, kMlpH, kMlpH, B, st));
-    hipLaunchKernelGGL(col_sum, dim3(1), dim3(kMlpH), 0, st, t.dZ2, B, kMlpH, g + kOffB2);
+    hipLaunchKernelGGL(col_sum, dim3(kMlpH), dim3(256), 0, st, t.dZ2, B, kMlpH, g + kOffB2);
     HIPCHK(c, gemm(t.dZ2, kMlpH, 0, W2, kMlpH, 1, t.dH, kMlpH, B, kMlpH, kMlpH, st));
     hipLaunchKernelGGL(gelu_backward, ew((int64_t)B * kMlpH), dim3(256), 0, st, t.Z1, t.dH, t.dZ1, (int64_t)B * kMlpH);
     // layer 1
     HIPCHK(c, gemm(t.X, kMlpF, 1, t.dZ1, kMlpH, 0, g + kOffW1, kMlpH, kMlpF, kMlpH, B, st));
-    hipLaunchKernelGGL(col_sum, dim3(1), dim3(kMlpH), 0, st, t.dZ1, B, kMlpH, g + kOffB1);
+    hipLaunchKernelGGL(col_sum, dim3(kMlpH), dim3(256), 0, st, t.dZ1, B, kMlpH, g + kOffB1);
     HIPCHK(c, hipGetLastError());
     return FB_OK;
 }

@@ -124,6 +124,12 @@ __device__ inline void wave_lds_sync()
     __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
 }
 
+// L of a segment in code compiled for at most kML coefficients.  The launcher
+// picks kML < kMaxL only when every segment has L <= kML; the bound lets the
+// compiler drop the array elements and loop steps beyond kML.
+template <int kML>
+__device__ inline int seg_L(const SegInfo &S) { return kML >= kMaxL ? S.L : (S.L < kML ? S.L : kML); }
+
 __device__ inline void raise_flag(int *err, int bit)
 {
     __hip_atomic_fetch_or(err, bit, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
@@ -134,11 +140,11 @@ __device__ inline void raise_flag(int *err, int bit)
 // ---------------------------------------------------------------------------
 // C_r = A_r exp(X_r beta_g): the sum over the samples of distinct row r of
 // exp(h_n + eps_gn + X_n beta_g).
-template <typename T>
+template <typename T, int kML = kMaxL>
 __device__ inline void row_sums_at_beta(const SegInfo &S, const T (&A)[kMaxRows], const T (&beta)[kMaxL],
                                         T (&C)[kMaxRows])
 {
-    const int L = S.L, R = S.R;
+    const int L = seg_L<kML>(S), R = S.R;
 #pragma unroll
     for (int r = 0; r < kMaxRows; ++r) {
         T xr = (T)0;
@@ -152,11 +158,11 @@ __device__ inline void row_sums_at_beta(const SegInfo &S, const T (&A)[kMaxRows]
 // Features of the learned proposal (any function of y_g, eps_g, h, theta,
 // sigma^2, never of beta_g): per distinct row r, log((Y_r + 1/2) / A_r) and
 // log(Y_r + 1/2); then theta_l and log sigma_l^2; zero up to 32.
-template <typename T>
+template <typename T, int kML = kMaxL>
 __device__ inline void gene_features(const SegInfo &S, const T (&A)[kMaxRows], const T (&YR)[kMaxRows],
                                      const double (&th)[kMaxL], const double (&s2)[kMaxL], float (&phi)[32])
 {
-    const int L = S.L, R = S.R;
+    const int L = seg_L<kML>(S), R = S.R;
 #pragma unroll
     for (int k = 0; k < 32; ++k) phi[k] = 0.0f;
 #pragma unroll
@@ -187,13 +193,13 @@ __device__ inline void gene_features(const SegInfo &S, const T (&A)[kMaxRows], c
 
 // Algorithm 1 step 5 by slice draws: beta_g1..beta_gL in order, each moving
 // the row sums C_r to the new coefficient; only `lead` lanes store.
-template <typename T>
+template <typename T, int kML = kMaxL>
 __device__ inline void beta_slice_draws(const SegInfo &S, const SweepArgs &a, int64_t g, int64_t Gp, bool lead,
                                         T (&beta)[kMaxL], T (&wb)[kMaxL], T (&wab)[kMaxL],
                                         const double (&th)[kMaxL], const double (&s2)[kMaxL],
                                         T (&C)[kMaxRows], const T (&YR)[kMaxRows], bool tuning, int &bad)
 {
-    const int L = S.L, R = S.R;
+    const int L = seg_L<kML>(S), R = S.R;
     const uint32_t mm = (uint32_t)a.m;
     T *__restrict__ betap = (T *)S.beta;
     for (int l = 0; l < L; ++l) {
@@ -261,21 +267,29 @@ __device__ inline void beta_slice_draws(const SegInfo &S, const SweepArgs &a, in
 // packed by rows of their lower triangle: element (i, j), j <= i, at tri(i, j).
 // ---------------------------------------------------------------------------
 constexpr int kTri = kMaxL * (kMaxL + 1) / 2;
+constexpr int kMaxOff = kMaxL * (kMaxL - 1) / 2;   // strict lower triangle
 __host__ __device__ constexpr int tri(int i, int j) { return i * (i + 1) / 2 + j; }
 
-// In place: H (symmetric positive definite) -> U, lower, with H = U U^T.
+__device__ inline float dsqrt(float x) { return ::sqrtf(x); }
+__device__ inline double dsqrt(double x) { return ::sqrt(x); }
+
+// In place: H (symmetric positive definite) -> U, lower, with H = U U^T; dinv
+// receives 1 / U_jj, which the solves multiply by.
 template <typename T>
-__device__ inline void chol_packed(T (&H)[kTri], int L)
+__device__ inline void chol_packed(T (&H)[kTri], int L, T (&dinv)[kMaxL])
 {
 #pragma unroll
     for (int j = 0; j < kMaxL; ++j) {
+        dinv[j] = (T)1;
         if (j < L) {
             T d = H[tri(j, j)];
 #pragma unroll
             for (int k = 0; k < kMaxL; ++k)
                 if (k < j) d -= H[tri(j, k)] * H[tri(j, k)];
-            const T ujj = (T)::sqrt((double)d);
+            const T ujj = dsqrt(d);
+            const T inv = (T)1 / ujj;
             H[tri(j, j)] = ujj;
+            dinv[j] = inv;
 #pragma unroll
             for (int i = 0; i < kMaxL; ++i) {
                 if (i > j && i < L) {
@@ -283,7 +297,7 @@ __device__ inline void chol_packed(T (&H)[kTri], int L)
 #pragma unroll
                     for (int k = 0; k < kMaxL; ++k)
                         if (k < j) sum -= H[tri(i, k)] * H[tri(j, k)];
-                    H[tri(i, j)] = sum / ujj;
+                    H[tri(i, j)] = sum * inv;
                 }
             }
         }
@@ -292,7 +306,8 @@ __device__ inline void chol_packed(T (&H)[kTri], int L)
 
 // x with U U^T x = b (forward, then back substitution).
 template <typename T>
-__device__ inline void chol_solve_packed(const T (&U)[kTri], int L, const T (&b)[kMaxL], T (&x)[kMaxL])
+__device__ inline void chol_solve_packed(const T (&U)[kTri], const T (&dinv)[kMaxL], int L, const T (&b)[kMaxL],
+                                         T (&x)[kMaxL])
 {
     T t[kMaxL];
 #pragma unroll
@@ -303,7 +318,7 @@ __device__ inline void chol_solve_packed(const T (&U)[kTri], int L, const T (&b)
 #pragma unroll
             for (int k = 0; k < kMaxL; ++k)
                 if (k < i) sum -= U[tri(i, k)] * t[k];
-            t[i] = sum / U[tri(i, i)];
+            t[i] = sum * dinv[i];
         }
     }
 #pragma unroll
@@ -314,7 +329,7 @@ __device__ inline void chol_solve_packed(const T (&U)[kTri], int L, const T (&b)
 #pragma unroll
             for (int k = 0; k < kMaxL; ++k)
                 if (k > i && k < L) sum -= U[tri(k, i)] * x[k];
-            x[i] = sum / U[tri(i, i)];
+            x[i] = sum * dinv[i];
         }
     }
 }
@@ -326,19 +341,20 @@ __device__ inline void chol_solve_packed(const T (&U)[kTri], int L, const T (&b)
 // weights Y_r + 1/2 and the prior; then two Newton steps
 //   b += H^-1 [sum_r (Y_r - c_r) x_r - (b - theta) / sigma^2],
 //   H = sum_r c_r x_r x_r^T + diag(1 / sigma^2),  c_r = A_r exp(x_r.b).
-// Returns the last iterate bh and the lower Cholesky factor U of H at bh.
-template <typename T>
+// Returns the last iterate bh, the lower Cholesky factor U of H at bh and
+// 1 / diag(U).  thT, is2: theta and 1 / sigma^2 in the working precision.
+template <typename T, int kML = kMaxL>
 __device__ inline void laplace_base(const SegInfo &S, const T (&A)[kMaxRows], const T (&Y)[kMaxRows],
-                                    const double (&th)[kMaxL], const double (&s2)[kMaxL], T (&bh)[kMaxL],
-                                    T (&U)[kTri])
+                                    const T (&thT)[kMaxL], const T (&is2)[kMaxL], T (&bh)[kMaxL], T (&U)[kTri],
+                                    T (&dinv)[kMaxL])
 {
-    const int L = S.L, R = S.R;
+    const int L = seg_L<kML>(S), R = S.R;
     T rhs[kMaxL];
 #pragma unroll
     for (int i = 0; i < kMaxL; ++i) {
-        rhs[i] = i < L ? (T)(th[i] / s2[i]) : (T)0;
+        rhs[i] = i < L ? thT[i] * is2[i] : (T)0;
 #pragma unroll
-        for (int j = 0; j <= i; ++j) U[tri(i, j)] = (i == j && i < L) ? (T)(1.0 / s2[i]) : (T)0;
+        for (int j = 0; j <= i; ++j) U[tri(i, j)] = (i == j && i < L) ? is2[i] : (T)0;
     }
 #pragma unroll
     for (int r = 0; r < kMaxRows; ++r) {
@@ -355,8 +371,8 @@ __device__ inline void laplace_base(const SegInfo &S, const T (&A)[kMaxRows], co
             }
         }
     }
-    chol_packed<T>(U, L);
-    chol_solve_packed<T>(U, L, rhs, bh);
+    chol_packed<T>(U, L, dinv);
+    chol_solve_packed<T>(U, dinv, L, rhs, bh);
 #pragma unroll 1
     for (int it = 0; it <= 2; ++it) {
         T cr[kMaxRows];
@@ -370,9 +386,9 @@ __device__ inline void laplace_base(const SegInfo &S, const T (&A)[kMaxRows], co
         }
 #pragma unroll
         for (int i = 0; i < kMaxL; ++i) {
-            rhs[i] = i < L ? (T)(-((double)bh[i] - th[i]) / s2[i]) : (T)0;
+            rhs[i] = i < L ? (thT[i] - bh[i]) * is2[i] : (T)0;
 #pragma unroll
-            for (int j = 0; j <= i; ++j) U[tri(i, j)] = (i == j && i < L) ? (T)(1.0 / s2[i]) : (T)0;
+            for (int j = 0; j <= i; ++j) U[tri(i, j)] = (i == j && i < L) ? is2[i] : (T)0;
         }
 #pragma unroll
         for (int r = 0; r < kMaxRows; ++r) {
@@ -388,10 +404,10 @@ __device__ inline void laplace_base(const SegInfo &S, const T (&A)[kMaxRows], co
                 }
             }
         }
-        chol_packed<T>(U, L);
+        chol_packed<T>(U, L, dinv);
         if (it == 2) break;
         T step[kMaxL];
-        chol_solve_packed<T>(U, L, rhs, step);
+        chol_solve_packed<T>(U, dinv, L, rhs, step);
 #pragma unroll
         for (int l = 0; l < kMaxL; ++l) bh[l] += step[l];
     }
@@ -410,13 +426,15 @@ __device__ inline void laplace_base(const SegInfo &S, const T (&A)[kMaxRows], co
 // the conditional's difference formed from the row sums:
 //   sum_r [Y_r X_r d - C_r expm1(X_r d)] - sum_l d_l (beta_l - theta_l + d_l / 2) / sigma_l^2.
 // Returns 1 if accepted.
-template <typename T>
+template <typename T, int kML = kMaxL>
 __device__ inline int beta_imh_draw(const SegInfo &S, const SweepArgs &a, int64_t g, int64_t Gp,
-                                    T (&beta)[kMaxL], const double (&th)[kMaxL], const double (&s2)[kMaxL],
+                                    T (&beta)[kMaxL], const T (&thT)[kMaxL], const T (&is2)[kMaxL],
                                     const T (&C)[kMaxRows], const T (&YR)[kMaxRows], const T (&bh)[kMaxL],
-                                    const T (&U)[kTri], const MlpDev *__restrict__ net, const float *__restrict__ o)
+                                    const T (&U)[kTri], const T (&dinv)[kMaxL], const MlpDev *__restrict__ net,
+                                    const float (&om)[kMaxL],
+                                    const float (&ol)[kMaxL], const float (&oo)[kMaxOff])
 {
-    const int L = S.L, R = S.R;
+    const int L = seg_L<kML>(S), R = S.R;
     const uint32_t mm = (uint32_t)a.m;
     const uint4 ctr = draw_counter((uint32_t)g, 8, 0, mm, (uint32_t)S.chain, 0);
     uint4 b0 = philox4x32_10(ctr, S.key0, S.key1);
@@ -441,18 +459,20 @@ __device__ inline int beta_imh_draw(const SegInfo &S, const SweepArgs &a, int64_
         }
     }
     // w = mu_w + Lw z, then beta* = bh + v with U^T v = w (back substitution)
-    T mw[kMaxL], dg[kMaxL], w[kMaxL], bs[kMaxL];
+    T mw[kMaxL], dg[kMaxL], idg[kMaxL], ios[kMaxL], w[kMaxL], bs[kMaxL];
 #pragma unroll
     for (int l = 0; l < kMaxL; ++l) {
-        mw[l] = (T)0; dg[l] = (T)1; w[l] = (T)0;
+        mw[l] = (T)0; dg[l] = (T)1; idg[l] = (T)1; ios[l] = (T)1; w[l] = (T)0;
         if (l < L) {
             const T osl = (T)net->oscale[l];
-            mw[l] = (T)net->omean[l] + osl * (T)o[l];
-            dg[l] = dexp((T)o[L + l]);
+            mw[l] = (T)net->omean[l] + osl * (T)om[l];
+            dg[l] = dexp((T)ol[l]);
+            idg[l] = dexp(-(T)ol[l]);
+            ios[l] = (T)(1.0f / net->oscale[l]);
             T sz = dg[l] * z[l];
 #pragma unroll
             for (int j = 0; j < kMaxL; ++j)
-                if (j < l) sz += (T)o[2 * L + l * (l - 1) / 2 + j] * z[j];
+                if (j < l) sz += (T)oo[l * (l - 1) / 2 + j] * z[j];
             w[l] = mw[l] + osl * sz;
         }
     }
@@ -464,7 +484,7 @@ __device__ inline int beta_imh_draw(const SegInfo &S, const SweepArgs &a, int64_
 #pragma unroll
             for (int k = 0; k < kMaxL; ++k)
                 if (k > i && k < L) sum -= U[tri(k, i)] * (bs[k] - bh[k]);
-            bs[i] = bh[i] + sum / U[tri(i, i)];
+            bs[i] = bh[i] + sum * dinv[i];
         }
     }
     // log q at beta* and at beta: u with Lw u = U^T (x - bh) - mu_w
@@ -487,11 +507,11 @@ __device__ inline int beta_imh_draw(const SegInfo &S, const SweepArgs &a, int64_
         for (int l = 0; l < kMaxL; ++l) {
             u[l] = (T)0;
             if (l < L) {
-                T sum = dd[l] / (T)net->oscale[l];
+                T sum = dd[l] * ios[l];
 #pragma unroll
                 for (int j = 0; j < kMaxL; ++j)
-                    if (j < l) sum -= (T)o[2 * L + l * (l - 1) / 2 + j] * u[j];
-                u[l] = sum / dg[l];
+                    if (j < l) sum -= (T)oo[l * (l - 1) / 2 + j] * u[j];
+                u[l] = sum * idg[l];
                 dq += (pass == 0 ? (T)0.5 : (T)-0.5) * u[l] * u[l];
             }
         }
@@ -503,7 +523,7 @@ __device__ inline int beta_imh_draw(const SegInfo &S, const SweepArgs &a, int64_
         d[l] = (T)0;
         if (l < L) {
             d[l] = bs[l] - beta[l];
-            dpi -= d[l] * ((T)((double)beta[l] - th[l]) + (T)0.5 * d[l]) * (T)(1.0 / s2[l]);
+            dpi -= d[l] * ((beta[l] - thT[l]) + (T)0.5 * d[l]) * is2[l];
         }
     }
 #pragma unroll
@@ -549,12 +569,12 @@ __device__ inline void whiten(int L, const T (&U)[kTri], const T (&bh)[kMaxL], c
 
 // After the beta step: moments, trace, and the tile partials of
 // (beta_l - theta_l) and its square (all lanes of the wavefront call).
-template <typename T>
+template <typename T, int kML = kMaxL>
 __device__ inline void beta_finish(const SegInfo &S, const SweepArgs &a, int64_t g, int64_t Gp, bool active,
                                    const T (&beta)[kMaxL], double2 (&mob)[kMaxL], const double (&th)[kMaxL],
                                    int tile, int lane, int tslot, float *trow, bool sampling)
 {
-    const int L = S.L;
+    const int L = seg_L<kML>(S);
     for (int l = 0; l < L; ++l) {
         T b1 = (T)0;
         double2 mo = make_double2(0.0, 0.0);
@@ -665,14 +685,14 @@ __device__ inline void eps_wave(const SegInfo &S, int tile, int n0, int n1, cons
 
 // Step 2 (wavefront 0): S_g = sum_n eps_gn^2, one gamma draw, moments, trace
 // and the tile partials of log gamma and 1 / gamma.
-template <typename T>
+template <typename T, int kML = kMaxL>
 __device__ inline void gamma_wave(const SegInfo &S, int tile, const SweepArgs &a, int *err)
 {
     const int lane = (int)(threadIdx.x & 63);
     const int64_t Gp = S.Gp;
     const int64_t g = (int64_t)tile * kTile + lane;
     const bool active = g < S.G;
-    const int N = S.N, L = S.L;
+    const int N = S.N, L = seg_L<kML>(S);
     const bool tuning = a.m <= a.burnin, sampling = a.m > a.burnin;
     const T *__restrict__ eps = (const T *)S.eps;
     T *__restrict__ gamp = (T *)S.gam;
@@ -729,8 +749,6 @@ __device__ inline void gamma_wave(const SegInfo &S, int tile, const SweepArgs &a
     if (bad) raise_flag(err, 2);
 }
 
-// The network on the 64 feature rows of a wavefront (defined below).
-__device__ inline const float *mlp_rows(const float (&phi)[32], bool active, const MlpDev *__restrict__ net);
 
 // Step 5 for the genes of one wavefront: the row sums A_r = sum over the
 // samples of row r of exp(h_n + eps_gn), then beta_g1..beta_gL by slice draws,
@@ -741,13 +759,13 @@ __device__ inline const float *mlp_rows(const float (&phi)[32], bool active, con
 //   kLearned, fallback_group = false: a tile's wavefront; with a.learned the
 //     genes flagged for fallback are left to their fallback group
 //   fallback_group = true: up to 64 flagged genes, slice steps only
-template <typename T, bool kLearned>
+template <typename T, bool kLearned, int kML = kMaxL>
 __device__ inline void beta_genes(const SegInfo &S, int64_t g, bool active, int64_t col, bool fallback_group,
                                   const SweepArgs &a, const MlpDev *__restrict__ net, int *err)
 {
     const int lane = (int)(threadIdx.x & 63);
     const int64_t Gp = S.Gp;
-    const int N = S.N, L = S.L, R = S.R;
+    const int N = S.N, L = seg_L<kML>(S), R = S.R;
     const bool tuning = a.m <= a.burnin, sampling = a.m > a.burnin;
     const bool upd_beta = (a.mask >> 5) & 1u;
     // with the learned step, a tile's wavefront leaves flagged genes alone
@@ -792,33 +810,51 @@ __device__ inline void beta_genes(const SegInfo &S, int64_t g, bool active, int6
     const int tslot = (a.trace_point >= 0 && mine) ? S.trace_slot[g] : -1;
     float *trow = a.trace_point >= 0 ? S.trace + (int64_t)a.trace_point * S.trace_stride + 2 + 2 * L : nullptr;
     T C[kMaxRows];
-    row_sums_at_beta<T>(S, A, beta, C);
+    row_sums_at_beta<T, kML>(S, A, beta, C);
     int bad = 0;
     if constexpr (kLearned) {
         if (fallback_group) {
             if (mine && upd_beta) {
-                beta_slice_draws<T>(S, a, g, Gp, true, beta, wb, wab, th, s2, C, YR, tuning, bad);
+                beta_slice_draws<T, kML>(S, a, g, Gp, true, beta, wb, wab, th, s2, C, YR, tuning, bad);
                 S.imh_last[g] = -1;
             }
         } else {
-            float phi[32];
-            gene_features<T>(S, A, YR, th, s2, phi);
             // training pairs: the features the beta step saw, then the new beta
             float *pair = (a.pair_base >= 0 && mine) ? S.pairs + (a.pair_base + g) * kPairStride : nullptr;
             if (pair) {
+                float phi[32];
+                gene_features<T, kML>(S, A, YR, th, s2, phi);
 #pragma unroll
                 for (int k = 0; k < 32; ++k) pair[k] = phi[k];
             }
-            const float *o = a.learned ? mlp_rows(phi, mine, net) : nullptr;
-            T bh[kMaxL], U[kTri];
-            if (a.learned || pair) laplace_base<T>(S, A, YR, th, s2, bh, U);
+            // the network's outputs for this gene (mlp_sweep ran before this kernel)
+            float om[kMaxL], ol[kMaxL], oo[kMaxOff];
+            const bool use_net = a.learned && mine && upd_beta;
+            const int nof = L * (L - 1) / 2;
+#pragma unroll
+            for (int l = 0; l < kMaxL; ++l) {
+                om[l] = (use_net && l < L) ? S.mlp_out[(int64_t)l * Gp + g] : 0.0f;
+                ol[l] = (use_net && l < L) ? S.mlp_out[(int64_t)(L + l) * Gp + g] : 0.0f;
+            }
+#pragma unroll
+            for (int k = 0; k < kMaxOff; ++k)
+                oo[k] = (use_net && k < nof) ? S.mlp_out[(int64_t)(2 * L + k) * Gp + g] : 0.0f;
+            T thT[kMaxL], is2[kMaxL];
+#pragma unroll
+            for (int l = 0; l < kMaxL; ++l) {
+                thT[l] = (T)th[l];
+                is2[l] = (T)(1.0 / s2[l]);
+            }
+            T bh[kMaxL], U[kTri], dinv[kMaxL];
+            if (a.learned || pair) laplace_base<T, kML>(S, A, YR, thT, is2, bh, U, dinv);
             if (mine && upd_beta) {
                 if (a.learned) {
-                    const int acc = beta_imh_draw<T>(S, a, g, Gp, beta, th, s2, C, YR, bh, U, net, o);
+                    const int acc =
+                        beta_imh_draw<T, kML>(S, a, g, Gp, beta, thT, is2, C, YR, bh, U, dinv, net, om, ol, oo);
                     S.imh_last[g] = acc;
                     if (a.count_imh) S.imh_count[g] += acc;
                 } else {
-                    beta_slice_draws<T>(S, a, g, Gp, true, beta, wb, wab, th, s2, C, YR, tuning, bad);
+                    beta_slice_draws<T, kML>(S, a, g, Gp, true, beta, wb, wab, th, s2, C, YR, tuning, bad);
                     S.imh_last[g] = -1;
                 }
             }
@@ -831,12 +867,12 @@ __device__ inline void beta_genes(const SegInfo &S, int64_t g, bool active, int6
             }
         }
     } else {
-        if (mine && upd_beta) beta_slice_draws<T>(S, a, g, Gp, true, beta, wb, wab, th, s2, C, YR, tuning, bad);
+        if (mine && upd_beta) beta_slice_draws<T, kML>(S, a, g, Gp, true, beta, wb, wab, th, s2, C, YR, tuning, bad);
     }
     // with the shift step on, the moments, trace and partials of beta are
     // taken after it (shift_sweep)
     if (!((a.mask >> kKindShift) & 1u))
-        beta_finish<T>(S, a, g, Gp, mine, beta, mob, th, col, lane, tslot, trow, sampling);
+        beta_finish<T, kML>(S, a, g, Gp, mine, beta, mob, th, col, lane, tslot, trow, sampling);
     if (bad) raise_flag(err, 2);
 }
 
@@ -844,7 +880,7 @@ __device__ inline void beta_genes(const SegInfo &S, int64_t g, bool active, int6
 // beta); with the learned step, `nfb` further workgroups each draw beta by
 // slice steps for a group of up to 64 genes flagged for fallback
 // (fb_items: segment, first list entry, count, partial column).
-template <typename T, bool kLearned>
+template <typename T, bool kLearned, int kML>
 __global__ __launch_bounds__(128) void gb_sweep(const SegInfo *__restrict__ segs, const int2 *__restrict__ tiles,
                                                 int ntiles, const int4 *__restrict__ fb_items, int nfb, SweepArgs a,
                                                 const MlpDev *__restrict__ net, int *err)
@@ -858,10 +894,10 @@ __global__ __launch_bounds__(128) void gb_sweep(const SegInfo *__restrict__ segs
         const int tile = __builtin_amdgcn_readfirstlane(tt.y);
         const SegInfo &S = segs[sidx];
         if (wave == 0) {
-            gamma_wave<T>(S, tile, a, err);
+            gamma_wave<T, kML>(S, tile, a, err);
         } else {
             const int64_t g = (int64_t)tile * kTile + lane;
-            beta_genes<T, kLearned>(S, g, g < S.G, tile, false, a, net, err);
+            beta_genes<T, kLearned, kML>(S, g, g < S.G, tile, false, a, net, err);
         }
         return;
     }
@@ -873,7 +909,7 @@ __global__ __launch_bounds__(128) void gb_sweep(const SegInfo *__restrict__ segs
         const bool active = lane < it.z;
         const int64_t g = active ? S.fb_genes[it.y + lane] : 0;
         const int64_t col = it.w;
-        beta_genes<T, true>(S, g, active, col, true, a, net, err);
+        beta_genes<T, true, kML>(S, g, active, col, true, a, net, err);
         if (lane == 0) {      // no gamma in a fallback column
             S.partials[col] = 0.0;
             S.partials[S.pstride + col] = 0.0;
@@ -895,14 +931,16 @@ __global__ __launch_bounds__(128) void gb_sweep(const SegInfo *__restrict__ segs
 // partials, are taken here, after the step.  One lane per gene, one wavefront
 // per tile, four tiles per workgroup.
 // ---------------------------------------------------------------------------
-template <typename T>
+constexpr int kShiftChunk = 16;    // samples whose eps and moments a lane holds at once
+
+template <typename T, int kML>
 __device__ inline void shift_genes(const SegInfo &S, int tile, const SweepArgs &a)
 {
     const int lane = (int)(threadIdx.x & 63);
     const int64_t Gp = S.Gp;
     const int64_t g = (int64_t)tile * kTile + lane;
     const bool active = g < S.G;
-    const int N = S.N, L = S.L;
+    const int N = S.N, L = seg_L<kML>(S);
     const bool sampling = a.m > a.burnin;
     const HyperState &H = *S.hyp;
     double th[kMaxL], s2[kMaxL];
@@ -913,8 +951,12 @@ __device__ inline void shift_genes(const SegInfo &S, int tile, const SweepArgs &
     }
     T *__restrict__ eps = (T *)S.eps;
     T *__restrict__ betap = (T *)S.beta;
-    T beta[kMaxL], d[kMaxL];
-    double2 mob[kMaxL];
+    double2 *__restrict__ mom = S.mom_eps;
+    // every load of the first chunk is issued before any arithmetic: the
+    // kernel is one lane per gene, so its time is memory round trips
+    T beta[kMaxL], d[kMaxL], e[kShiftChunk];
+    double2 mob[kMaxL], mo[kShiftChunk];
+    const T gam = active ? ((const T *)S.gam)[g] : (T)1;
 #pragma unroll
     for (int l = 0; l < kMaxL; ++l) {
         const bool on = l < L && active;
@@ -922,29 +964,47 @@ __device__ inline void shift_genes(const SegInfo &S, int tile, const SweepArgs &
         mob[l] = (on && sampling) ? S.mom_beta[(int64_t)l * Gp + g] : make_double2(0.0, 0.0);
         d[l] = (T)0;
     }
+#pragma unroll
+    for (int k = 0; k < kShiftChunk; ++k) {
+        const bool on = active && k < N;
+        e[k] = on ? eps[(int64_t)k * Gp + g] : (T)0;
+        mo[k] = (on && sampling) ? mom[(int64_t)k * Gp + g] : make_double2(0.0, 0.0);
+    }
     if (active) {
-        const T ig = (T)1 / ((const T *)S.gam)[g];
+        const T ig = (T)1 / gam;
         T xe[kMaxL];
 #pragma unroll
         for (int l = 0; l < kMaxL; ++l) xe[l] = (T)0;
-#pragma unroll 4
-        for (int n = 0; n < N; ++n) {
-            const T e = eps[(int64_t)n * Gp + g];
 #pragma unroll
-            for (int l = 0; l < kMaxL; ++l)
-                if (l < L) xe[l] += (T)S.X[n * kMaxL + l] * e;
+        for (int k = 0; k < kShiftChunk; ++k)
+            if (k < N) {
+#pragma unroll
+                for (int l = 0; l < kMaxL; ++l)
+                    if (l < L) xe[l] += (T)S.X[k * kMaxL + l] * e[k];
+            }
+        for (int c0 = kShiftChunk; c0 < N; c0 += kShiftChunk) {     // N > 16: further chunks
+            T ec[kShiftChunk];
+#pragma unroll
+            for (int k = 0; k < kShiftChunk; ++k) ec[k] = c0 + k < N ? eps[(int64_t)(c0 + k) * Gp + g] : (T)0;
+#pragma unroll
+            for (int k = 0; k < kShiftChunk; ++k)
+                if (c0 + k < N) {
+#pragma unroll
+                    for (int l = 0; l < kMaxL; ++l)
+                        if (l < L) xe[l] += (T)S.X[(c0 + k) * kMaxL + l] * ec[k];
+                }
         }
-        T U[kTri], cv[kMaxL], mean[kMaxL];
+        T U[kTri], dinv[kMaxL], cv[kMaxL], mean[kMaxL];
 #pragma unroll
         for (int i = 0; i < kMaxL; ++i) {
-            cv[i] = i < L ? xe[i] * ig - (T)(((double)beta[i] - th[i]) / s2[i]) : (T)0;
+            const T is2 = (T)(1.0 / s2[i]);
+            cv[i] = i < L ? xe[i] * ig - (beta[i] - (T)th[i]) * is2 : (T)0;
 #pragma unroll
             for (int j = 0; j <= i; ++j)
-                U[tri(i, j)] = (i < L) ? (T)S.XtX[i * kMaxL + j] * ig + (i == j ? (T)(1.0 / s2[i]) : (T)0)
-                                       : (T)0;
+                U[tri(i, j)] = (i < L) ? (T)S.XtX[i * kMaxL + j] * ig + (i == j ? is2 : (T)0) : (T)0;
         }
-        chol_packed<T>(U, L);
-        chol_solve_packed<T>(U, L, cv, mean);
+        chol_packed<T>(U, L, dinv);
+        chol_solve_packed<T>(U, dinv, L, cv, mean);
         const uint4 ctr = draw_counter((uint32_t)g, kKindShift, 0, (uint32_t)a.m, (uint32_t)S.chain, 0);
         const uint4 b0 = philox4x32_10(ctr, S.key0, S.key1);
         const uint4 b1 = philox4x32_10(make_uint4(ctr.x, ctr.y, ctr.z, ctr.w | 1u), S.key0, S.key1);
@@ -976,7 +1036,7 @@ __device__ inline void shift_genes(const SegInfo &S, int tile, const SweepArgs &
 #pragma unroll
                 for (int k = 0; k < kMaxL; ++k)
                     if (k > i && k < L) sum -= U[tri(k, i)] * v[k];
-                v[i] = sum / U[tri(i, i)];
+                v[i] = sum * dinv[i];
             }
         }
 #pragma unroll
@@ -986,29 +1046,41 @@ __device__ inline void shift_genes(const SegInfo &S, int tile, const SweepArgs &
                 beta[l] += d[l];
                 betap[(int64_t)l * Gp + g] = beta[l];
             }
-        double2 *__restrict__ mom = S.mom_eps;
-#pragma unroll 4
-        for (int n = 0; n < N; ++n) {
-            const int64_t idx = (int64_t)n * Gp + g;
-            T xd = (T)0;
+        for (int c0 = 0; c0 < N; c0 += kShiftChunk) {
+            if (c0 > 0) {
 #pragma unroll
-            for (int l = 0; l < kMaxL; ++l)
-                if (l < L) xd += (T)S.X[n * kMaxL + l] * d[l];
-            const T e = eps[idx] - xd;
-            eps[idx] = e;
-            if (sampling) {
-                double2 mo = mom[idx];
-                welford(mo, (double)e, a.inv_k);
-                mom[idx] = mo;
+                for (int k = 0; k < kShiftChunk; ++k) {
+                    const bool on = c0 + k < N;
+                    e[k] = on ? eps[(int64_t)(c0 + k) * Gp + g] : (T)0;
+                    mo[k] = (on && sampling) ? mom[(int64_t)(c0 + k) * Gp + g] : make_double2(0.0, 0.0);
+                }
+            }
+#pragma unroll
+            for (int k = 0; k < kShiftChunk; ++k) {
+                const int n = c0 + k;
+                if (n < N) {
+                    const int64_t idx = (int64_t)n * Gp + g;
+                    T xd = (T)0;
+#pragma unroll
+                    for (int l = 0; l < kMaxL; ++l)
+                        if (l < L) xd += (T)S.X[n * kMaxL + l] * d[l];
+                    const T en = e[k] - xd;
+                    eps[idx] = en;
+                    if (sampling) {
+                        double2 m2 = mo[k];
+                        welford(m2, (double)en, a.inv_k);
+                        mom[idx] = m2;
+                    }
+                }
             }
         }
     }
     const int tslot = (a.trace_point >= 0 && active) ? S.trace_slot[g] : -1;
     float *trow = a.trace_point >= 0 ? S.trace + (int64_t)a.trace_point * S.trace_stride + 2 + 2 * L : nullptr;
-    beta_finish<T>(S, a, g, Gp, active, beta, mob, th, tile, lane, tslot, trow, sampling);
+    beta_finish<T, kML>(S, a, g, Gp, active, beta, mob, th, tile, lane, tslot, trow, sampling);
 }
 
-template <typename T>
+template <typename T, int kML>
 __global__ __launch_bounds__(256) void shift_sweep(const SegInfo *__restrict__ segs, const int2 *__restrict__ tiles,
                                                    int ntiles, SweepArgs a)
 {
@@ -1018,7 +1090,7 @@ __global__ __launch_bounds__(256) void shift_sweep(const SegInfo *__restrict__ s
     const int2 tt = tiles[tix];
     const int sidx = __builtin_amdgcn_readfirstlane(tt.x);
     const int tile = __builtin_amdgcn_readfirstlane(tt.y);
-    shift_genes<T>(segs[sidx], tile, a);
+    shift_genes<T, kML>(segs[sidx], tile, a);
 }
 
 // ---------------------------------------------------------------------------
@@ -1029,92 +1101,207 @@ __global__ __launch_bounds__(256) void shift_sweep(const SegInfo *__restrict__ s
 // weights; bias and GELU are applied to the accumulators and the result is
 // written back to LDS as BF16 rows for the next layer.
 // ---------------------------------------------------------------------------
-constexpr int kXs = kMlpF + 8;     // LDS row strides (elements), padded against bank conflicts
-constexpr int kHs = kMlpH + 8;
-constexpr int kOs = kMlpO + 1;
 
-template <int K, int N, bool kGelu>
-__device__ inline void mlp_layer(const __bf16 *__restrict__ in, int in_stride, const __bf16 *__restrict__ Wp,
-                                 const float *__restrict__ bias, __bf16 *out_bf, float *out_f, int out_stride)
+// GELU(v) = v Phi(v) for inference, branch-free: with x = |v| / sqrt(2),
+// q = erfc(x) from Abramowitz & Stegun 7.1.26 (q = t (a1 + t (a2 + ...)) e^(-x^2),
+// t = 1 / (1 + p x), |error| <= 1.5e-7), Phi(v) = 1 - q / 2 for v >= 0 and
+// q / 2 for v < 0 (no cancellation).  The activations are rounded to BF16
+// right after, whose relative step (2^-8) is far above that error.
+__device__ inline float gelu_f(float v)
+{
+    const float x = ::fabsf(v) * 0.70710678118654752f;
+    const float t = __builtin_amdgcn_rcpf(1.0f + 0.3275911f * x);
+    const float poly =
+        t * (0.254829592f + t * (-0.284496736f + t * (1.421413741f + t * (-1.453152027f + t * 1.061405429f))));
+    const float q = poly * __expf(-x * x);
+    return v >= 0.0f ? v * (1.0f - 0.5f * q) : v * (0.5f * q);
+}
+
+// Bias, GELU and BF16 rounding of one 32 x 32 output tile `ot`: register r of
+// lane 32 h + i holds unit 32 ot + 8 (r / 4) + 4 h + r % 4, which is element
+// r % 8 of the next layer's B fragment for k-step 2 ot + r / 8 (units in
+// wt_unit order).
+// The biases of one output tile, units 32 ot + 8 q + 4 h + t as float4 q; the
+// empty asm makes the address opaque so the loads stay beside their use
+// instead of being hoisted out of the tile loop into registers.
+__device__ inline void tile_bias(const float *__restrict__ bias, int ot, int h, float4 (&bb)[4])
+{
+    const float *bp = bias + 32 * ot + 4 * h;
+    asm volatile("" : "+v"(bp));
+#pragma unroll
+    for (int q = 0; q < 4; ++q) bb[q] = *reinterpret_cast<const float4 *>(bp + 8 * q);
+}
+
+__device__ inline void tile_to_next(const floatx16 &acc, const float *__restrict__ bias, int ot, int h,
+                                    bf16x8 (&nx)[8])
+{
+    float4 bb[4];
+    tile_bias(bias, ot, h, bb);
+#pragma unroll
+    for (int r = 0; r < 16; ++r) {
+        const float4 &b4 = bb[r >> 2];
+        const float bv = (r & 3) == 0 ? b4.x : (r & 3) == 1 ? b4.y : (r & 3) == 2 ? b4.z : b4.w;
+        nx[2 * ot + (r >> 3)][r & 7] = (__bf16)gelu_f(acc[r] + bv);
+    }
+}
+
+// The network on 32 feature rows per wavefront, in the transposed form
+// out^T = W^T in^T: v_mfma_f32_32x32x16_bf16 with A = packed weights (Wl, in
+// LDS) and B = activations, so that each layer's accumulators become the next
+// layer's B fragments in registers (tile_to_next).  Lanes i and 32 + i both
+// hold the features of row i (each computed them); lane 32 h + i takes
+// features 16 ks + 8 h .. + 7 of its row as the layer-1 B fragment of k-step
+// ks, so no operand passes through LDS.  store(u, i, v) receives output u < O
+// of row i (0..31) from lane 32 h + i for the units 8 q + 4 h + t it holds.
+template <typename Store>
+__device__ inline void mlp_block(const float (&phi)[kMlpF], bool active, const bf16x8 *__restrict__ Wl,
+                                 const MlpDev *__restrict__ net, int O, Store &&store)
 {
     const int lane = (int)(threadIdx.x & 63);
-    const int i = lane & 31, h = lane >> 5;
-    constexpr int nct = N / 32, nks = K / 16;
+    const int h = lane >> 5;
+    bf16x8 x1[2], h1[8], h2[8];
 #pragma unroll
-    for (int rt = 0; rt < 2; ++rt) {
+    for (int ks = 0; ks < 2; ++ks)
 #pragma unroll
-        for (int ct = 0; ct < nct; ++ct) {
+        for (int j = 0; j < 8; ++j) {
+            const int k0 = 16 * ks + j, k1 = 16 * ks + 8 + j;
+            const float x0 = (phi[k0] - net->fmean[k0]) * net->fscale[k0];
+            const float xh = (phi[k1] - net->fmean[k1]) * net->fscale[k1];
+            x1[ks][j] = (__bf16)(active ? (h ? xh : x0) : 0.0f);
+        }
+    const int nct3 = (O + 31) >> 5;
+#pragma unroll
+    for (int ot = 0; ot < 4; ++ot) {
+        floatx16 acc = {};
+#pragma unroll
+        for (int ks = 0; ks < 2; ++ks)
+            acc = __builtin_amdgcn_mfma_f32_32x32x16_bf16(Wl[(2 * ot + ks) * 64 + lane], x1[ks], acc, 0, 0, 0);
+        tile_to_next(acc, net->b1, ot, h, h1);
+    }
+#pragma unroll
+    for (int ot = 0; ot < 4; ++ot) {
+        // one output tile's weight fragments in flight at a time
+        __builtin_amdgcn_sched_barrier(0);
+        floatx16 acc = {};
+#pragma unroll
+        for (int ks = 0; ks < 8; ++ks)
+            acc = __builtin_amdgcn_mfma_f32_32x32x16_bf16(Wl[(8 + 8 * ot + ks) * 64 + lane], h1[ks], acc, 0, 0, 0);
+        tile_to_next(acc, net->b2, ot, h, h2);
+    }
+#pragma unroll
+    for (int ot = 0; ot < 2; ++ot) {
+        __builtin_amdgcn_sched_barrier(0);
+        if (ot < nct3) {
             floatx16 acc = {};
 #pragma unroll
-            for (int ks = 0; ks < nks; ++ks) {
-                const bf16x8 av = *reinterpret_cast<const bf16x8 *>(in + (rt * 32 + i) * in_stride + ks * 16 + 8 * h);
-                const bf16x8 bv = *reinterpret_cast<const bf16x8 *>(Wp + ((ks * nct + ct) * 64 + lane) * 8);
-                acc = __builtin_amdgcn_mfma_f32_32x32x16_bf16(av, bv, acc, 0, 0, 0);
-            }
-            const float bb = bias[ct * 32 + i];
+            for (int ks = 0; ks < 8; ++ks)
+                acc = __builtin_amdgcn_mfma_f32_32x32x16_bf16(Wl[(40 + 8 * ot + ks) * 64 + lane], h2[ks], acc, 0, 0,
+                                                              0);
+            float4 bb[4];
+            tile_bias(net->b3, ot, h, bb);
 #pragma unroll
             for (int r = 0; r < 16; ++r) {
-                const int row = rt * 32 + 8 * (r >> 2) + 4 * h + (r & 3);
-                float v = acc[r] + bb;
-                if constexpr (kGelu) {
-                    v = 0.5f * v * (1.0f + erff(v * 0.70710678118654752f));
-                    out_bf[row * out_stride + ct * 32 + i] = (__bf16)v;
-                } else {
-                    out_f[row * out_stride + ct * 32 + i] = v;
-                }
+                const int u = 32 * ot + 8 * (r >> 2) + 4 * h + (r & 3);
+                const float4 &b4 = bb[r >> 2];
+                const float bv = (r & 3) == 0 ? b4.x : (r & 3) == 1 ? b4.y : (r & 3) == 2 ? b4.z : b4.w;
+                if (u < O) store(u, lane & 31, acc[r] + bv);
             }
         }
     }
 }
 
-// The network on the 64 feature rows a wavefront holds (phi of lane = row);
-// returns the lane's row of raw outputs o (in LDS, valid until the next call).
-// All 64 lanes of one wavefront call; the LDS buffers belong to the workgroup
-// and only one of its wavefronts uses them.
-__device__ inline const float *mlp_rows(const float (&phi)[32], bool active, const MlpDev *__restrict__ net)
+// Copy of the packed weights into the workgroup's LDS (all threads call).
+__device__ inline void load_weights(bf16x8 *Wl, const MlpDev *__restrict__ net)
 {
-    __shared__ __attribute__((aligned(16))) __bf16 xs[64 * kXs];
-    __shared__ __attribute__((aligned(16))) __bf16 h1[64 * kHs];
-    __shared__ __attribute__((aligned(16))) __bf16 h2[64 * kHs];
-    __shared__ float os[64 * kOs];
-    const int lane = (int)(threadIdx.x & 63);
-#pragma unroll
-    for (int k = 0; k < kMlpF; ++k) {
-        const float x = active ? (phi[k] - net->fmean[k]) * net->fscale[k] : 0.0f;
-        xs[lane * kXs + k] = (__bf16)x;
-    }
-    wave_lds_sync();
-    mlp_layer<kMlpF, kMlpH, true>(xs, kXs, net->W1p, net->b1, h1, nullptr, kHs);
-    wave_lds_sync();
-    mlp_layer<kMlpH, kMlpH, true>(h1, kHs, net->W2p, net->b2, h2, nullptr, kHs);
-    wave_lds_sync();
-    mlp_layer<kMlpH, kMlpO, false>(h2, kHs, net->W3p, net->b3, nullptr, os, kOs);
-    wave_lds_sync();
-    return os + lane * kOs;
+    const bf16x8 *src = reinterpret_cast<const bf16x8 *>(net->Wt);
+    for (int t = (int)threadIdx.x; t < kWtFrags * 64; t += (int)blockDim.x) Wl[t] = src[t];
+    __syncthreads();
 }
 
+// The proposal network of every gene in the sweep, after the eps draws and
+// before the gamma/beta kernel: features from this sweep's eps (row sums A_r,
+// Y_r) and the current theta, sigma^2, then the network; output u of gene g
+// goes to mlp_out[u][g].  512 threads: eight wavefronts share the weights in
+// LDS, each taking 32-gene blocks (half tiles) in turn.
+template <typename T>
+__global__ __launch_bounds__(512) void mlp_sweep(const SegInfo *__restrict__ segs, const int2 *__restrict__ tiles,
+                                                 int ntiles, const MlpDev *__restrict__ net)
+{
+    __shared__ bf16x8 Wl[kWtFrags * 64];
+    load_weights(Wl, net);
+    const int wave = __builtin_amdgcn_readfirstlane((int)(threadIdx.x >> 6));
+    const int lane = (int)(threadIdx.x & 63);
+    for (int bi = (int)blockIdx.x * 8 + wave; bi < 2 * ntiles; bi += (int)gridDim.x * 8) {
+        const int2 tt = tiles[bi >> 1];
+        const int sidx = __builtin_amdgcn_readfirstlane(tt.x);
+        const int tile = __builtin_amdgcn_readfirstlane(tt.y);
+        const SegInfo &S = segs[sidx];
+        const int64_t Gp = S.Gp, g0 = (int64_t)tile * kTile + 32 * (bi & 1);
+        const int64_t g = g0 + (lane & 31);
+        const bool active = g < S.G;
+        const int N = S.N, L = S.L, R = S.R;
+        T A[kMaxRows], YR[kMaxRows];
+#pragma unroll
+        for (int r = 0; r < kMaxRows; ++r) {
+            A[r] = (T)0;
+            YR[r] = (r < R && active) ? ((const T *)S.YR)[(int64_t)r * Gp + g] : (T)0;
+        }
+        if (active) {
+            const T *__restrict__ eps = (const T *)S.eps;
+#pragma unroll 8
+            for (int n = 0; n < N; ++n) {
+                const T ehe = dexp((T)S.h[n] + eps[(int64_t)n * Gp + g]);
+                const int rr = S.row_of[n];
+#pragma unroll
+                for (int r = 0; r < kMaxRows; ++r)
+                    if (r == rr) A[r] += ehe;
+            }
+        }
+        double th[kMaxL], s2[kMaxL];
+#pragma unroll
+        for (int l = 0; l < kMaxL; ++l) {
+            th[l] = l < L ? S.hyp->theta[l] : 0.0;
+            s2[l] = l < L ? S.hyp->sig2[l] : 1.0;
+        }
+        float phi[kMlpF];
+        if (active) gene_features<T>(S, A, YR, th, s2, phi);
+        else {
+#pragma unroll
+            for (int k = 0; k < kMlpF; ++k) phi[k] = 0.0f;
+        }
+        float *__restrict__ out = S.mlp_out;
+        const int64_t G = S.G;
+        mlp_block(phi, active, Wl, net, mlp_outputs(L), [&](int u, int row, float v) {
+            if (g0 + row < G) out[(int64_t)u * Gp + g0 + row] = v;
+        });
+    }
+}
 
 // The network on raw feature rows phi [B][32] (tests): mu, ls [B][L] and the
-// factor's strict lower triangle off [B][L(L-1)/2] (units of oscale).
-__global__ __launch_bounds__(64) void mlp_infer_raw(const float *__restrict__ phi, int64_t B, int L,
-                                                    const MlpDev *__restrict__ net, float *mu_out, float *ls_out,
-                                                    float *off_out)
+// factor's strict lower triangle off [B][L(L-1)/2] (units of oscale), through
+// the same block routine as the sweep.
+__global__ __launch_bounds__(512) void mlp_infer_raw(const float *__restrict__ phi, int64_t B, int L,
+                                                     const MlpDev *__restrict__ net, float *mu_out, float *ls_out,
+                                                     float *off_out)
 {
-    const int lane = (int)threadIdx.x;
-    const int64_t b = (int64_t)blockIdx.x * 64 + lane;
+    __shared__ bf16x8 Wl[kWtFrags * 64];
+    load_weights(Wl, net);
+    const int wave = (int)(threadIdx.x >> 6), lane = (int)(threadIdx.x & 63);
+    const int64_t b0 = ((int64_t)blockIdx.x * 8 + wave) * 32;
+    if (b0 >= B) return;                  // whole wavefront; no workgroup barrier follows
+    const int64_t b = b0 + (lane & 31);
     const bool active = b < B;
-    float phi_r[32];
+    float phi_r[kMlpF];
 #pragma unroll
-    for (int k = 0; k < 32; ++k) phi_r[k] = active ? phi[b * 32 + k] : 0.0f;
-    const float *o = mlp_rows(phi_r, active, net);
-    if (active) {
-        for (int l = 0; l < L; ++l) {
-            mu_out[b * L + l] = net->omean[l] + net->oscale[l] * o[l];
-            ls_out[b * L + l] = ::logf(net->oscale[l]) + o[L + l];
-        }
-        const int K = L * (L - 1) / 2;
-        for (int k = 0; k < K; ++k) off_out[b * K + k] = o[2 * L + k];
-    }
+    for (int k = 0; k < kMlpF; ++k) phi_r[k] = active ? phi[b * kMlpF + k] : 0.0f;
+    const int K = L * (L - 1) / 2;
+    mlp_block(phi_r, active, Wl, net, mlp_outputs(L), [&](int u, int row, float v) {
+        const int64_t bb = b0 + row;
+        if (bb >= B) return;
+        if (u < L) mu_out[bb * L + u] = net->omean[u] + net->oscale[u] * v;
+        else if (u < 2 * L) ls_out[bb * L + u - L] = ::logf(net->oscale[u - L]) + v;
+        else off_out[bb * K + u - 2 * L] = v;
+    });
 }
 
 // Features of every gene from the current state (tests): A_r and Y_r summed
@@ -1192,8 +1379,21 @@ hipError_t launch_mlp_infer_raw(const float *phi, int64_t B, int L, const MlpDev
                                 float *off, hipStream_t st)
 {
     if (B <= 0) return hipSuccess;
-    hipLaunchKernelGGL(mlp_infer_raw, dim3((unsigned)((B + 63) / 64)), dim3(64), 0, st, phi, B, L, net, mu, ls,
+    hipLaunchKernelGGL(mlp_infer_raw, dim3((unsigned)((B + 255) / 256)), dim3(512), 0, st, phi, B, L, net, mu, ls,
                        off);
+    return hipGetLastError();
+}
+
+hipError_t launch_mlp_sweep(int precision, const SegInfo *segs, const int2 *tiles, int ntiles, const MlpDev *net,
+                            hipStream_t st)
+{
+    if (ntiles <= 0) return hipSuccess;
+    const int nwg = (2 * ntiles + 7) / 8;
+    const dim3 grid((unsigned)(nwg < 512 ? nwg : 512)), block(512);
+    if (precision == 1)
+        hipLaunchKernelGGL(mlp_sweep<float>, grid, block, 0, st, segs, tiles, ntiles, net);
+    else
+        hipLaunchKernelGGL(mlp_sweep<double>, grid, block, 0, st, segs, tiles, ntiles, net);
     return hipGetLastError();
 }
 
@@ -1428,40 +1628,54 @@ hipError_t launch_eps(int precision, const SegInfo *segs, const int4 *items, int
     return hipGetLastError();
 }
 
-hipError_t launch_gb(int precision, bool learned, const SegInfo *segs, const int2 *tiles, int ntiles,
+// kML: the smallest compiled bound (5 or kMaxL) on every segment's L.
+template <int kML>
+static void launch_gb_k(int precision, bool learned, const SegInfo *segs, const int2 *tiles, int ntiles,
+                        const int4 *fb_items, int nfb, const SweepArgs &a, const MlpDev *net, int *err,
+                        hipStream_t st)
+{
+    const dim3 block(128), grid(ntiles + nfb);
+    if (precision == 0) {
+        if (learned)
+            hipLaunchKernelGGL((gb_sweep<double, true, kML>), grid, block, 0, st, segs, tiles, ntiles, fb_items, nfb,
+                               a, net, err);
+        else
+            hipLaunchKernelGGL((gb_sweep<double, false, kML>), grid, block, 0, st, segs, tiles, ntiles, fb_items, 0,
+                               a, net, err);
+    } else {
+        if (learned)
+            hipLaunchKernelGGL((gb_sweep<float, true, kML>), grid, block, 0, st, segs, tiles, ntiles, fb_items, nfb,
+                               a, net, err);
+        else
+            hipLaunchKernelGGL((gb_sweep<float, false, kML>), grid, block, 0, st, segs, tiles, ntiles, fb_items, 0,
+                               a, net, err);
+    }
+}
+
+hipError_t launch_gb(int precision, bool learned, int maxL, const SegInfo *segs, const int2 *tiles, int ntiles,
                      const int4 *fb_items, int nfb, const SweepArgs &a, const MlpDev *net, int *err, hipStream_t st)
 {
     if (ntiles == 0) return hipSuccess;
-    const dim3 block(128);
     if (!learned) nfb = 0;
-    const dim3 grid(ntiles + nfb);
-    if (precision == 0) {
-        if (learned)
-            hipLaunchKernelGGL((gb_sweep<double, true>), grid, block, 0, st, segs, tiles, ntiles, fb_items, nfb, a, net,
-                               err);
-        else
-            hipLaunchKernelGGL((gb_sweep<double, false>), grid, block, 0, st, segs, tiles, ntiles, fb_items, 0, a, net,
-                               err);
-    } else {
-        if (learned)
-            hipLaunchKernelGGL((gb_sweep<float, true>), grid, block, 0, st, segs, tiles, ntiles, fb_items, nfb, a, net,
-                               err);
-        else
-            hipLaunchKernelGGL((gb_sweep<float, false>), grid, block, 0, st, segs, tiles, ntiles, fb_items, 0, a, net,
-                               err);
-    }
+    if (maxL <= 5)
+        launch_gb_k<5>(precision, learned, segs, tiles, ntiles, fb_items, nfb, a, net, err, st);
+    else
+        launch_gb_k<kMaxL>(precision, learned, segs, tiles, ntiles, fb_items, nfb, a, net, err, st);
     return hipGetLastError();
 }
 
-hipError_t launch_shift(int precision, const SegInfo *segs, const int2 *tiles, int ntiles, const SweepArgs &a,
-                        hipStream_t st)
+hipError_t launch_shift(int precision, int maxL, const SegInfo *segs, const int2 *tiles, int ntiles,
+                        const SweepArgs &a, hipStream_t st)
 {
     if (ntiles <= 0) return hipSuccess;
     const dim3 grid((unsigned)((ntiles + 3) / 4)), block(256);
-    if (precision == 1)
-        hipLaunchKernelGGL(shift_sweep<float>, grid, block, 0, st, segs, tiles, ntiles, a);
-    else
-        hipLaunchKernelGGL(shift_sweep<double>, grid, block, 0, st, segs, tiles, ntiles, a);
+    if (precision == 1) {
+        if (maxL <= 5) hipLaunchKernelGGL((shift_sweep<float, 5>), grid, block, 0, st, segs, tiles, ntiles, a);
+        else hipLaunchKernelGGL((shift_sweep<float, kMaxL>), grid, block, 0, st, segs, tiles, ntiles, a);
+    } else {
+        if (maxL <= 5) hipLaunchKernelGGL((shift_sweep<double, 5>), grid, block, 0, st, segs, tiles, ntiles, a);
+        else hipLaunchKernelGGL((shift_sweep<double, kMaxL>), grid, block, 0, st, segs, tiles, ntiles, a);
+    }
     return hipGetLastError();
 }
 

@@ -140,14 +140,23 @@ __global__ void nll_grad(const float *O, int Op, const float *T, int L, const fl
     loss[b] = tot;
 }
 
-// out[j] = sum_b M[b][j] over rows in a fixed order (one thread per column).
-__global__ void col_sum(const float *Mx, int rows, int cols, float *out)
+// out[j] = sum_b M[b][j]: one 256-thread workgroup per column; thread t sums
+// rows t, t + 256, ... in order, then a fixed-order tree in LDS (the result
+// does not depend on scheduling).
+__global__ __launch_bounds__(256) void col_sum(const float *Mx, int rows, int cols, float *out)
 {
-    const int j = (int)(blockIdx.x * blockDim.x + threadIdx.x);
-    if (j >= cols) return;
+    __shared__ float part[256];
+    const int j = (int)blockIdx.x, t = (int)threadIdx.x;
     float s = 0.0f;
-    for (int b = 0; b < rows; ++b) s += Mx[(int64_t)b * cols + j];
-    out[j] = s;
+    if (j < cols)
+        for (int b = t; b < rows; b += 256) s += Mx[(int64_t)b * cols + j];
+    part[t] = s;
+    __syncthreads();
+    for (int w = 128; w > 0; w >>= 1) {
+        if (t < w) part[t] += part[t + w];
+        __syncthreads();
+    }
+    if (t == 0 && j < cols) out[j] = part[0];
 }
 
 // FP32 master parameters -> the inference copy (BF16 fragments in MFMA B order:
@@ -167,6 +176,22 @@ __global__ void pack_mlp(const float *master, MlpDev *out)
     pack(master + kOffW1, kMlpF, kMlpH, out->W1p, t);
     pack(master + kOffW2, kMlpH, kMlpH, out->W2p, t);
     pack(master + kOffW3, kMlpH, kMlpO, out->W3p, t);
+    if (t < kWtFrags * 64 * 8) {
+        const int j = t & 7, lane = (t >> 3) & 63, frag = t >> 9;
+        const int h = lane >> 5, i = lane & 31;
+        float w;
+        if (frag < 8) {
+            const int ot = frag >> 1, ks = frag & 1;
+            w = master[kOffW1 + (16 * ks + 8 * h + j) * kMlpH + 32 * ot + i];
+        } else if (frag < 40) {
+            const int ot = (frag - 8) >> 3, ks = (frag - 8) & 7;
+            w = master[kOffW2 + wt_unit(ks, h, j) * kMlpH + 32 * ot + i];
+        } else {
+            const int ot = (frag - 40) >> 3, ks = (frag - 40) & 7;
+            w = master[kOffW3 + wt_unit(ks, h, j) * kMlpO + 32 * ot + i];
+        }
+        out->Wt[t] = (__bf16)w;
+    }
     if (t < kMlpF) { out->fmean[t] = master[kOffFmean + t]; out->fscale[t] = master[kOffFscale + t]; }
     if (t < kMlpH) { out->b1[t] = master[kOffB1 + t]; out->b2[t] = master[kOffB2 + t]; }
     if (t < kMlpO) out->b3[t] = master[kOffB3 + t];

@@ -30,7 +30,22 @@ constexpr int kOffOmean = kOffB3 + kMlpO;                  // [8]
 constexpr int kOffOscale = kOffOmean + 8;
 constexpr int kMlpParams = kOffOscale + 8;
 
-// Inference copy: weights as BF16 MFMA B fragments, [kstep][coltile][lane][8].
+// Inference copy of the weights.  W1p..W3p: BF16 MFMA B fragments
+// [kstep][coltile][lane][8] of the row-major layers (training-side checks).
+// Wt: the A fragments of the transposed layers out^T = W^T in^T that the sweep
+// runs (one wavefront per 64 genes; the output tile of one layer is, register
+// for register, the B fragments of the next), kWtFrags fragments of
+// [64 lanes][8]: layer 1 at (ot, ks) -> 2 ot + ks, layer 2 -> 8 + 8 ot + ks,
+// layer 3 -> 40 + 8 ot + ks.  Lane 32 h + i, element j of fragment (ot, ks)
+// holds W[k][32 ot + i] with k = 16 ks + 8 h + j in layer 1 (inputs in natural
+// order) and k = wt_unit(ks, h, j) in layers 2 and 3 (the order in which a
+// 32 x 32 accumulator tile holds its rows).
+constexpr int kWtFrags = 4 * 2 + 4 * 8 + 2 * 8;
+__host__ __device__ constexpr int wt_unit(int ks, int h, int j)
+{
+    return 32 * (ks >> 1) + 16 * (ks & 1) + 8 * (j >> 2) + 4 * h + (j & 3);
+}
+
 struct MlpDev {
     float fmean[kMlpF], fscale[kMlpF];
     float b1[kMlpH], b2[kMlpH], b3[kMlpO];
@@ -38,6 +53,7 @@ struct MlpDev {
     __bf16 W1p[(kMlpF / 16) * (kMlpH / 32) * 64 * 8];
     __bf16 W2p[(kMlpH / 16) * (kMlpH / 32) * 64 * 8];
     __bf16 W3p[(kMlpH / 16) * (kMlpO / 32) * 64 * 8];
+    __attribute__((aligned(16))) __bf16 Wt[kWtFrags * 64 * 8];
 };
 
 __global__ void mfma_probe(const float *A, const float *B, float *C);

@@ -61,7 +61,7 @@ struct SegInfo {
     // split sweep (eps/gamma, then beta) used by the learned proposal
     void *Ar;                     // [R][Gp] sum over row r of exp(h_n + eps_gn), this sweep
     void *YR;                     // [R][Gp] sum over row r of y_gn (constant)
-    float *mlp_out;               // [2L][Gp] proposal mean mu_l then log-scale ls_l
+    float *mlp_out;               // [2L + L(L-1)/2][Gp] the proposal network's outputs, this sweep
     int32_t *fallback;            // [Gp] 1 = slice step for beta_g
     int32_t *imh_count;           // [Gp] accepted IMH steps while counting
     int32_t *imh_last;            // [Gp] last sweep: 1 accepted, 0 rejected, -1 slice

@@ -32,14 +32,15 @@ def test_philox_words_bit_exact(oracle_lib):
 
 
 def _make_pair(oracle_lib, ds, *, seed, burnin, tune_start, precision, K=15, cap=200, w0=1.0,
-               chains=1, **ora_kw):
+               chains=1, update_mask=None, **ora_kw):
     F = require_gpu()
+    mask = F.FB_UPDATE_ALL if update_mask is None else update_mask
     opts = F.fb_default_options(burnin=burnin, tune_start=tune_start, precision=precision,
                                 debug_counts=1, jitter=0, chains=chains, max_steps=K,
-                                shrink_cap=cap, w0=w0)
+                                shrink_cap=cap, w0=w0, update_mask=mask)
     g = F.fb_create(ds.y, ds.X, ds.h, seed=seed, options=opts, priors=ora_kw.pop("priors", None))
     o = oracle_lib.Oracle(ds.y, ds.X, ds.h, seed=seed, burnin=burnin, tune_start=tune_start, K=K,
-                          shrink_cap=cap, w0=w0, **ora_kw)
+                          shrink_cap=cap, w0=w0, update_mask=mask, **ora_kw)
     return F, g, o
 
 
@@ -96,6 +97,13 @@ def _edge_datasets():
                 dict(K=3, w0=0.05)))
     out.append(("priors", datagen.simulate(150, two, [3.0, 0.0], [1.5, 0.5], seed=12),
                 dict(priors=dict(a=2.0, b=0.5, d=50.0, c=[3.0, 1.0], s=[5.0, 2.0]))))
+    # L = 7 > 5: the kernels compiled for up to 8 coefficients (8 distinct
+    # rows, the first 7 columns of a Sylvester-Hadamard matrix)
+    H2 = np.array([[1.0, 1.0], [1.0, -1.0]])
+    H8 = np.kron(np.kron(H2, H2), H2)[:, :7]
+    wide = datagen.simulate(90, H8, [3.0] + [0.0] * 6, [1.5] + [0.3] * 6, seed=13)
+    out.append(("L7_N8", wide, {}))
+    out.append(("L7_N8_shift", wide, dict(update_mask=0xFE | (1 << 11))))
     return out
 
 
