@@ -22,7 +22,7 @@
 namespace fbmc {
 hipError_t launch_eps(int precision, const SegInfo *segs, const int4 *items, int nitems, const SweepArgs &a,
                       int nhyp, const SweepArgs &ha, int *err, hipStream_t st);
-hipError_t launch_gb(int precision, bool learned, int maxL, const SegInfo *segs, const int2 *tiles, int ntiles,
+hipError_t launch_gb(int precision, int mode, int maxL, const SegInfo *segs, const int2 *tiles, int ntiles,
                      const int4 *fb_items, int nfb, const SweepArgs &a, const MlpDev *net, int *err, hipStream_t st);
 hipError_t launch_hyper(const SegInfo *segs, int nseg, const SweepArgs &a, int *err, hipStream_t st);
 hipError_t launch_shift(int precision, int maxL, const SegInfo *segs, const int2 *tiles, int ntiles,
@@ -676,7 +676,9 @@ int run_sweeps(fb_ctx *c, int64_t n, SweepMode &md)
         if (pe) HIPCHK(c, hipEventRecord(pe[1], c->st));
         if (pe) HIPCHK(c, hipEventRecord(pe[2], c->st));
         if (md.learned) HIPCHK(c, launch_mlp_sweep(c->prec, c->d_segs, c->d_tiles, c->ntiles, c->d_net, c->st));
-        HIPCHK(c, launch_gb(c->prec, md.learned_kernel, c->maxL, c->d_segs, c->d_tiles, c->ntiles, c->d_fb_items,
+        // the learned kernel in its MH-only form when no training pairs are taken
+        const int gb_mode = !md.learned_kernel ? 0 : (md.learned && a.pair_base < 0) ? 2 : 1;
+        HIPCHK(c, launch_gb(c->prec, gb_mode, c->maxL, c->d_segs, c->d_tiles, c->ntiles, c->d_fb_items,
                             md.learned ? c->nfb_items : 0, a, c->d_net, c->d_err, c->st));
         if (pe) HIPCHK(c, hipEventRecord(pe[3], c->st));
         if (shift) {

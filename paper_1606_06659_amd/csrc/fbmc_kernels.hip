@@ -181,7 +181,7 @@ __device__ inline void gene_features(const SegInfo &S, const T (&A)[kMaxRows], c
 #pragma unroll
     for (int l = 0; l < kMaxL; ++l) {
         if (l < L) {
-            const float t = (float)th[l], ls2 = (float)::log(s2[l]);
+            const float t = (float)th[l], ls2 = ::logf((float)s2[l]);
 #pragma unroll
             for (int k = 0; k < 32; ++k) {
                 if (k == 2 * R + l) phi[k] = t;
@@ -756,13 +756,17 @@ __device__ inline void gamma_wave(const SegInfo &S, int tile, const SweepArgs &a
 // Then the moments, trace, training pairs and the wavefront's partials of
 // (beta_l - theta_l) and its square in column `col`.
 //   lane gene g, `active`: the lane holds a gene
-//   kLearned, fallback_group = false: a tile's wavefront; with a.learned the
-//     genes flagged for fallback are left to their fallback group
+//   kMode 0: slice steps (Algorithm 1)
+//   kMode 1 (learned kernel, any sweep: training pairs, slice or MH steps) and
+//   kMode 2 (the MH step only, no training pairs: the code the learned sweeps
+//   run), fallback_group = false: a tile's wavefront; with a.learned the genes
+//   flagged for fallback are left to their fallback group
 //   fallback_group = true: up to 64 flagged genes, slice steps only
-template <typename T, bool kLearned, int kML = kMaxL>
+template <typename T, int kMode, int kML = kMaxL>
 __device__ inline void beta_genes(const SegInfo &S, int64_t g, bool active, int64_t col, bool fallback_group,
                                   const SweepArgs &a, const MlpDev *__restrict__ net, int *err)
 {
+    constexpr bool kLearned = kMode != 0;
     const int lane = (int)(threadIdx.x & 63);
     const int64_t Gp = S.Gp;
     const int N = S.N, L = seg_L<kML>(S), R = S.R;
@@ -820,7 +824,8 @@ __device__ inline void beta_genes(const SegInfo &S, int64_t g, bool active, int6
             }
         } else {
             // training pairs: the features the beta step saw, then the new beta
-            float *pair = (a.pair_base >= 0 && mine) ? S.pairs + (a.pair_base + g) * kPairStride : nullptr;
+            float *pair = (kMode == 1 && a.pair_base >= 0 && mine) ? S.pairs + (a.pair_base + g) * kPairStride
+                                                                   : nullptr;
             if (pair) {
                 float phi[32];
                 gene_features<T, kML>(S, A, YR, th, s2, phi);
@@ -848,7 +853,7 @@ __device__ inline void beta_genes(const SegInfo &S, int64_t g, bool active, int6
             T bh[kMaxL], U[kTri], dinv[kMaxL];
             if (a.learned || pair) laplace_base<T, kML>(S, A, YR, thT, is2, bh, U, dinv);
             if (mine && upd_beta) {
-                if (a.learned) {
+                if (kMode == 2 || a.learned) {
                     const int acc =
                         beta_imh_draw<T, kML>(S, a, g, Gp, beta, thT, is2, C, YR, bh, U, dinv, net, om, ol, oo);
                     S.imh_last[g] = acc;
@@ -880,7 +885,7 @@ __device__ inline void beta_genes(const SegInfo &S, int64_t g, bool active, int6
 // beta); with the learned step, `nfb` further workgroups each draw beta by
 // slice steps for a group of up to 64 genes flagged for fallback
 // (fb_items: segment, first list entry, count, partial column).
-template <typename T, bool kLearned, int kML>
+template <typename T, int kMode, int kML>
 __global__ __launch_bounds__(128) void gb_sweep(const SegInfo *__restrict__ segs, const int2 *__restrict__ tiles,
                                                 int ntiles, const int4 *__restrict__ fb_items, int nfb, SweepArgs a,
                                                 const MlpDev *__restrict__ net, int *err)
@@ -897,11 +902,11 @@ __global__ __launch_bounds__(128) void gb_sweep(const SegInfo *__restrict__ segs
             gamma_wave<T, kML>(S, tile, a, err);
         } else {
             const int64_t g = (int64_t)tile * kTile + lane;
-            beta_genes<T, kLearned, kML>(S, g, g < S.G, tile, false, a, net, err);
+            beta_genes<T, kMode, kML>(S, g, g < S.G, tile, false, a, net, err);
         }
         return;
     }
-    if constexpr (kLearned) {
+    if constexpr (kMode != 0) {
         if (tix - ntiles >= nfb || wave != 0) return;
         const int4 it = fb_items[tix - ntiles];
         const int sidx = __builtin_amdgcn_readfirstlane(it.x);
@@ -909,7 +914,7 @@ __global__ __launch_bounds__(128) void gb_sweep(const SegInfo *__restrict__ segs
         const bool active = lane < it.z;
         const int64_t g = active ? S.fb_genes[it.y + lane] : 0;
         const int64_t col = it.w;
-        beta_genes<T, true, kML>(S, g, active, col, true, a, net, err);
+        beta_genes<T, kMode, kML>(S, g, active, col, true, a, net, err);
         if (lane == 0) {      // no gamma in a fallback column
             S.partials[col] = 0.0;
             S.partials[S.pstride + col] = 0.0;
@@ -1121,54 +1126,78 @@ __device__ inline float gelu_f(float v)
 // lane 32 h + i holds unit 32 ot + 8 (r / 4) + 4 h + r % 4, which is element
 // r % 8 of the next layer's B fragment for k-step 2 ot + r / 8 (units in
 // wt_unit order).
-// The biases of one output tile, units 32 ot + 8 q + 4 h + t as float4 q; the
-// empty asm makes the address opaque so the loads stay beside their use
-// instead of being hoisted out of the tile loop into registers.
-__device__ inline void tile_bias(const float *__restrict__ bias, int ot, int h, float4 (&bb)[4])
+constexpr int kFrStride = kMlpF + 1;   // LDS feature-row stride (floats), odd against bank conflicts
+
+// The network's parameters as a workgroup keeps them in LDS: the packed
+// weights, then the feature standardisation and the biases (every per-lane
+// read in the layers is an LDS read).
+struct MlpLds {
+    bf16x8 W[kWtFrags * 64];
+    float fmean[kMlpF], fscale[kMlpF];
+    float b1[kMlpH], b2[kMlpH], b3[kMlpO];
+};
+
+// The biases of one output tile, units 32 ot + 8 q + 4 h + t as float4 q.
+__device__ inline void tile_bias(const float *bias, int ot, int h, float4 (&bb)[4])
 {
     const float *bp = bias + 32 * ot + 4 * h;
-    asm volatile("" : "+v"(bp));
 #pragma unroll
     for (int q = 0; q < 4; ++q) bb[q] = *reinterpret_cast<const float4 *>(bp + 8 * q);
 }
 
-__device__ inline void tile_to_next(const floatx16 &acc, const float *__restrict__ bias, int ot, int h,
-                                    bf16x8 (&nx)[8])
+// Eight floats rounded to one BF16 fragment, built as a whole (element-wise
+// insertion makes the compiler shuffle 64-bit registers around each element).
+__device__ inline bf16x8 pack_bf16x8(const float (&v)[8])
+{
+    return bf16x8{(__bf16)v[0], (__bf16)v[1], (__bf16)v[2], (__bf16)v[3],
+                  (__bf16)v[4], (__bf16)v[5], (__bf16)v[6], (__bf16)v[7]};
+}
+
+__device__ inline void tile_to_next(const floatx16 &acc, const float *bias, int ot, int h, bf16x8 (&nx)[8])
 {
     float4 bb[4];
     tile_bias(bias, ot, h, bb);
+    float gv[16];
 #pragma unroll
     for (int r = 0; r < 16; ++r) {
         const float4 &b4 = bb[r >> 2];
         const float bv = (r & 3) == 0 ? b4.x : (r & 3) == 1 ? b4.y : (r & 3) == 2 ? b4.z : b4.w;
-        nx[2 * ot + (r >> 3)][r & 7] = (__bf16)gelu_f(acc[r] + bv);
+        gv[r] = gelu_f(acc[r] + bv);
+    }
+#pragma unroll
+    for (int q = 0; q < 2; ++q) {
+        float v8[8];
+#pragma unroll
+        for (int j = 0; j < 8; ++j) v8[j] = gv[8 * q + j];
+        nx[2 * ot + q] = pack_bf16x8(v8);
     }
 }
 
 // The network on 32 feature rows per wavefront, in the transposed form
-// out^T = W^T in^T: v_mfma_f32_32x32x16_bf16 with A = packed weights (Wl, in
-// LDS) and B = activations, so that each layer's accumulators become the next
-// layer's B fragments in registers (tile_to_next).  Lanes i and 32 + i both
-// hold the features of row i (each computed them); lane 32 h + i takes
-// features 16 ks + 8 h .. + 7 of its row as the layer-1 B fragment of k-step
-// ks, so no operand passes through LDS.  store(u, i, v) receives output u < O
-// of row i (0..31) from lane 32 h + i for the units 8 q + 4 h + t it holds.
+// out^T = W^T in^T: v_mfma_f32_32x32x16_bf16 with A = packed weights (in LDS)
+// and B = activations, so that each layer's accumulators become the next
+// layer's B fragments in registers (tile_to_next).  `row` is the raw feature
+// row of row i = lane % 32 (in LDS); lane 32 h + i takes features
+// 16 ks + 8 h .. + 7 of it, standardised, as the layer-1 B fragment of k-step
+// ks.  store(u, i, v) receives output u < O of row i (0..31) from lane
+// 32 h + i for the units 8 q + 4 h + t it holds.
 template <typename Store>
-__device__ inline void mlp_block(const float (&phi)[kMlpF], bool active, const bf16x8 *__restrict__ Wl,
-                                 const MlpDev *__restrict__ net, int O, Store &&store)
+__device__ inline void mlp_block(const float *row, bool active, const MlpLds &P, int O, Store &&store)
 {
+    const bf16x8 *Wl = P.W;
     const int lane = (int)(threadIdx.x & 63);
     const int h = lane >> 5;
     bf16x8 x1[2], h1[8], h2[8];
 #pragma unroll
-    for (int ks = 0; ks < 2; ++ks)
+    for (int ks = 0; ks < 2; ++ks) {
+        float v8[8];
 #pragma unroll
         for (int j = 0; j < 8; ++j) {
-            const int k0 = 16 * ks + j, k1 = 16 * ks + 8 + j;
-            const float x0 = (phi[k0] - net->fmean[k0]) * net->fscale[k0];
-            const float xh = (phi[k1] - net->fmean[k1]) * net->fscale[k1];
-            x1[ks][j] = (__bf16)(active ? (h ? xh : x0) : 0.0f);
+            const int k = 16 * ks + 8 * h + j;
+            v8[j] = active ? (row[k] - P.fmean[k]) * P.fscale[k] : 0.0f;
         }
+        x1[ks] = pack_bf16x8(v8);
+    }
     const int nct3 = (O + 31) >> 5;
 #pragma unroll
     for (int ot = 0; ot < 4; ++ot) {
@@ -1176,7 +1205,7 @@ __device__ inline void mlp_block(const float (&phi)[kMlpF], bool active, const b
 #pragma unroll
         for (int ks = 0; ks < 2; ++ks)
             acc = __builtin_amdgcn_mfma_f32_32x32x16_bf16(Wl[(2 * ot + ks) * 64 + lane], x1[ks], acc, 0, 0, 0);
-        tile_to_next(acc, net->b1, ot, h, h1);
+        tile_to_next(acc, P.b1, ot, h, h1);
     }
 #pragma unroll
     for (int ot = 0; ot < 4; ++ot) {
@@ -1186,7 +1215,7 @@ __device__ inline void mlp_block(const float (&phi)[kMlpF], bool active, const b
 #pragma unroll
         for (int ks = 0; ks < 8; ++ks)
             acc = __builtin_amdgcn_mfma_f32_32x32x16_bf16(Wl[(8 + 8 * ot + ks) * 64 + lane], h1[ks], acc, 0, 0, 0);
-        tile_to_next(acc, net->b2, ot, h, h2);
+        tile_to_next(acc, P.b2, ot, h, h2);
     }
 #pragma unroll
     for (int ot = 0; ot < 2; ++ot) {
@@ -1198,7 +1227,7 @@ __device__ inline void mlp_block(const float (&phi)[kMlpF], bool active, const b
                 acc = __builtin_amdgcn_mfma_f32_32x32x16_bf16(Wl[(40 + 8 * ot + ks) * 64 + lane], h2[ks], acc, 0, 0,
                                                               0);
             float4 bb[4];
-            tile_bias(net->b3, ot, h, bb);
+            tile_bias(P.b3, ot, h, bb);
 #pragma unroll
             for (int r = 0; r < 16; ++r) {
                 const int u = 32 * ot + 8 * (r >> 2) + 4 * h + (r & 3);
@@ -1210,11 +1239,20 @@ __device__ inline void mlp_block(const float (&phi)[kMlpF], bool active, const b
     }
 }
 
-// Copy of the packed weights into the workgroup's LDS (all threads call).
-__device__ inline void load_weights(bf16x8 *Wl, const MlpDev *__restrict__ net)
+// Copy of the network's parameters into the workgroup's LDS (all threads call).
+__device__ inline void load_weights(MlpLds &P, const MlpDev *__restrict__ net)
 {
     const bf16x8 *src = reinterpret_cast<const bf16x8 *>(net->Wt);
-    for (int t = (int)threadIdx.x; t < kWtFrags * 64; t += (int)blockDim.x) Wl[t] = src[t];
+    for (int t = (int)threadIdx.x; t < kWtFrags * 64; t += (int)blockDim.x) P.W[t] = src[t];
+    for (int t = (int)threadIdx.x; t < kMlpF; t += (int)blockDim.x) {
+        P.fmean[t] = net->fmean[t];
+        P.fscale[t] = net->fscale[t];
+    }
+    for (int t = (int)threadIdx.x; t < kMlpH; t += (int)blockDim.x) {
+        P.b1[t] = net->b1[t];
+        P.b2[t] = net->b2[t];
+    }
+    for (int t = (int)threadIdx.x; t < kMlpO; t += (int)blockDim.x) P.b3[t] = net->b3[t];
     __syncthreads();
 }
 
@@ -1227,10 +1265,14 @@ template <typename T>
 __global__ __launch_bounds__(512) void mlp_sweep(const SegInfo *__restrict__ segs, const int2 *__restrict__ tiles,
                                                  int ntiles, const MlpDev *__restrict__ net)
 {
-    __shared__ bf16x8 Wl[kWtFrags * 64];
-    load_weights(Wl, net);
+    __shared__ MlpLds P;
+    // raw feature rows of each wavefront's 32 genes: written by lanes 0..31 at
+    // positions that depend on the segment's R and L, read back in order
+    __shared__ float fr[8][32 * kFrStride];
+    load_weights(P, net);
     const int wave = __builtin_amdgcn_readfirstlane((int)(threadIdx.x >> 6));
     const int lane = (int)(threadIdx.x & 63);
+    float *row = &fr[wave][(lane & 31) * kFrStride];
     for (int bi = (int)blockIdx.x * 8 + wave; bi < 2 * ntiles; bi += (int)gridDim.x * 8) {
         const int2 tt = tiles[bi >> 1];
         const int sidx = __builtin_amdgcn_readfirstlane(tt.x);
@@ -1257,22 +1299,31 @@ __global__ __launch_bounds__(512) void mlp_sweep(const SegInfo *__restrict__ seg
                     if (r == rr) A[r] += ehe;
             }
         }
-        double th[kMaxL], s2[kMaxL];
+        // the features of gene_features: log((Y_r + 1/2) / A_r), log(Y_r + 1/2),
+        // theta_l, log sigma_l^2, zero to 32
+        wave_lds_sync();                  // earlier readers of the rows are done
+        if (lane < 32) {
 #pragma unroll
-        for (int l = 0; l < kMaxL; ++l) {
-            th[l] = l < L ? S.hyp->theta[l] : 0.0;
-            s2[l] = l < L ? S.hyp->sig2[l] : 1.0;
-        }
-        float phi[kMlpF];
-        if (active) gene_features<T>(S, A, YR, th, s2, phi);
-        else {
+            for (int k = 0; k < kMlpF; ++k) row[k] = 0.0f;
 #pragma unroll
-            for (int k = 0; k < kMlpF; ++k) phi[k] = 0.0f;
+            for (int r = 0; r < kMaxRows; ++r)
+                if (r < R) {
+                    const float y = (float)YR[r] + 0.5f;
+                    row[r] = ::logf(y / (float)A[r]);
+                    row[R + r] = ::logf(y);
+                }
+#pragma unroll
+            for (int l = 0; l < kMaxL; ++l)
+                if (l < L) {
+                    row[2 * R + l] = (float)S.hyp->theta[l];
+                    row[2 * R + L + l] = ::logf((float)S.hyp->sig2[l]);
+                }
         }
+        wave_lds_sync();
         float *__restrict__ out = S.mlp_out;
         const int64_t G = S.G;
-        mlp_block(phi, active, Wl, net, mlp_outputs(L), [&](int u, int row, float v) {
-            if (g0 + row < G) out[(int64_t)u * Gp + g0 + row] = v;
+        mlp_block(row, active, P, mlp_outputs(L), [&](int u, int rw, float v) {
+            if (g0 + rw < G) out[(int64_t)u * Gp + g0 + rw] = v;
         });
     }
 }
@@ -1284,18 +1335,22 @@ __global__ __launch_bounds__(512) void mlp_infer_raw(const float *__restrict__ p
                                                      const MlpDev *__restrict__ net, float *mu_out, float *ls_out,
                                                      float *off_out)
 {
-    __shared__ bf16x8 Wl[kWtFrags * 64];
-    load_weights(Wl, net);
+    __shared__ MlpLds P;
+    __shared__ float fr[8][32 * kFrStride];
+    load_weights(P, net);
     const int wave = (int)(threadIdx.x >> 6), lane = (int)(threadIdx.x & 63);
     const int64_t b0 = ((int64_t)blockIdx.x * 8 + wave) * 32;
     if (b0 >= B) return;                  // whole wavefront; no workgroup barrier follows
     const int64_t b = b0 + (lane & 31);
     const bool active = b < B;
-    float phi_r[kMlpF];
+    float *rowp = &fr[wave][(lane & 31) * kFrStride];
+    if (lane < 32) {
 #pragma unroll
-    for (int k = 0; k < kMlpF; ++k) phi_r[k] = active ? phi[b * kMlpF + k] : 0.0f;
+        for (int k = 0; k < kMlpF; ++k) rowp[k] = active ? phi[b * kMlpF + k] : 0.0f;
+    }
+    wave_lds_sync();
     const int K = L * (L - 1) / 2;
-    mlp_block(phi_r, active, Wl, net, mlp_outputs(L), [&](int u, int row, float v) {
+    mlp_block(rowp, active, P, mlp_outputs(L), [&](int u, int row, float v) {
         const int64_t bb = b0 + row;
         if (bb >= B) return;
         if (u < L) mu_out[bb * L + u] = net->omean[u] + net->oscale[u] * v;
@@ -1628,39 +1683,37 @@ hipError_t launch_eps(int precision, const SegInfo *segs, const int4 *items, int
     return hipGetLastError();
 }
 
+// mode: 0 slice steps, 1 learned kernel (any sweep), 2 learned MH step only;
 // kML: the smallest compiled bound (5 or kMaxL) on every segment's L.
-template <int kML>
-static void launch_gb_k(int precision, bool learned, const SegInfo *segs, const int2 *tiles, int ntiles,
+template <int kMode, int kML>
+static void launch_gb_k(int precision, const SegInfo *segs, const int2 *tiles, int ntiles, const int4 *fb_items,
+                        int nfb, const SweepArgs &a, const MlpDev *net, int *err, hipStream_t st)
+{
+    const dim3 block(128), grid(ntiles + nfb);
+    if (precision == 0)
+        hipLaunchKernelGGL((gb_sweep<double, kMode, kML>), grid, block, 0, st, segs, tiles, ntiles, fb_items, nfb, a,
+                           net, err);
+    else
+        hipLaunchKernelGGL((gb_sweep<float, kMode, kML>), grid, block, 0, st, segs, tiles, ntiles, fb_items, nfb, a,
+                           net, err);
+}
+
+template <int kMode>
+static void launch_gb_m(int precision, int maxL, const SegInfo *segs, const int2 *tiles, int ntiles,
                         const int4 *fb_items, int nfb, const SweepArgs &a, const MlpDev *net, int *err,
                         hipStream_t st)
 {
-    const dim3 block(128), grid(ntiles + nfb);
-    if (precision == 0) {
-        if (learned)
-            hipLaunchKernelGGL((gb_sweep<double, true, kML>), grid, block, 0, st, segs, tiles, ntiles, fb_items, nfb,
-                               a, net, err);
-        else
-            hipLaunchKernelGGL((gb_sweep<double, false, kML>), grid, block, 0, st, segs, tiles, ntiles, fb_items, 0,
-                               a, net, err);
-    } else {
-        if (learned)
-            hipLaunchKernelGGL((gb_sweep<float, true, kML>), grid, block, 0, st, segs, tiles, ntiles, fb_items, nfb,
-                               a, net, err);
-        else
-            hipLaunchKernelGGL((gb_sweep<float, false, kML>), grid, block, 0, st, segs, tiles, ntiles, fb_items, 0,
-                               a, net, err);
-    }
+    if (maxL <= 5) launch_gb_k<kMode, 5>(precision, segs, tiles, ntiles, fb_items, nfb, a, net, err, st);
+    else launch_gb_k<kMode, kMaxL>(precision, segs, tiles, ntiles, fb_items, nfb, a, net, err, st);
 }
 
-hipError_t launch_gb(int precision, bool learned, int maxL, const SegInfo *segs, const int2 *tiles, int ntiles,
+hipError_t launch_gb(int precision, int mode, int maxL, const SegInfo *segs, const int2 *tiles, int ntiles,
                      const int4 *fb_items, int nfb, const SweepArgs &a, const MlpDev *net, int *err, hipStream_t st)
 {
     if (ntiles == 0) return hipSuccess;
-    if (!learned) nfb = 0;
-    if (maxL <= 5)
-        launch_gb_k<5>(precision, learned, segs, tiles, ntiles, fb_items, nfb, a, net, err, st);
-    else
-        launch_gb_k<kMaxL>(precision, learned, segs, tiles, ntiles, fb_items, nfb, a, net, err, st);
+    if (mode == 0) launch_gb_m<0>(precision, maxL, segs, tiles, ntiles, fb_items, 0, a, net, err, st);
+    else if (mode == 1) launch_gb_m<1>(precision, maxL, segs, tiles, ntiles, fb_items, nfb, a, net, err, st);
+    else launch_gb_m<2>(precision, maxL, segs, tiles, ntiles, fb_items, nfb, a, net, err, st);
     return hipGetLastError();
 }
 
