@@ -246,6 +246,8 @@ def main():
     ap.add_argument("--no-shift", action="store_true", help="skip the chains with the shift step")
     ap.add_argument("--no-heavy", action="store_true",
                     help="skip the secondary heavy workload (4 chains x G=200k x N=48)")
+    ap.add_argument("--heavy-only", action="store_true",
+                    help="run only the heavy workload and print its record (profiling runs)")
     ap.add_argument("--launch", default="auto",
                     help="'auto' (autotuner) or 'SPW,FUSE': samples per eps wavefront, fused hyper step 0/1")
     ap.add_argument("--burnin", type=int, default=BURNIN,
@@ -279,6 +281,10 @@ def main():
             dst.copy_(src)
         torch.cuda.synchronize()
         del src, dst
+    if args.heavy_only:
+        print(json.dumps({"heavy_workload": run_heavy(fbmc, stream, steps=args.steps, burnin=args.burnin)}),
+              flush=True)
+        return
     run = lambda learned, shift: run_chain(fbmc, diagnostics, ds, args, burnin, post, do_ess, stream,
                                            learned=learned, shift=shift)
     plain = run(False, False)
