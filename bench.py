@@ -234,6 +234,33 @@ def run_heavy(fbmc, stream, steps=100, burnin=300):
             "sweep_hbm_frac": b_sweep * G * C / per / 1e9 / HBM_PEAK_GBS}
 
 
+def run_small(fbmc, stream, steps=2000, graph_sweeps=50):
+    """Secondary measurement: the small two-group workload (G = 1,000, N = 4,
+    L = 2, FP64, one chain), where a sweep is a few microseconds of GPU work
+    and launch overhead matters: sweeps/s with direct launches and with graph
+    replay in chunks of `graph_sweeps` sweeps (the same chain, bit for bit)."""
+    import torch
+    from paper_1606_06659_amd import datagen
+    ds = datagen.small_two_group(G=1000, seed=0)
+    out = {"workload": "two-group G=1000 N=4 L=2, FP64, 1 chain", "steps": steps, "graph_sweeps": graph_sweeps}
+    for name, k in (("direct", 0), ("graph", graph_sweeps)):
+        opts = fbmc.fb_default_options(burnin=500, tune_start=50, precision=fbmc.FB_FP64, jitter=0,
+                                       stream=stream.cuda_stream)
+        smp = fbmc.Sampler(ds.y, ds.X, ds.h, seed=1, **{f: getattr(opts, f) for f, *_ in opts._fields_})
+        fbmc.fb_set_graph(smp.ctx, k)
+        smp.sweep(600)
+        smp.sync()
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        smp.sweep(steps)
+        smp.sync()
+        torch.cuda.synchronize()
+        out[f"{name}_sweeps_per_s"] = steps / (time.perf_counter() - t0)
+        smp.close()
+    out["graph_speedup"] = out["graph_sweeps_per_s"] / out["direct_sweeps_per_s"]
+    return out
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -363,6 +390,7 @@ def main():
     }
     if not args.no_heavy:
         line["heavy_workload"] = run_heavy(fbmc, stream)
+        line["small_workload"] = run_small(fbmc, stream)
     if not args.no_cpu_baseline:
         line["cpu_baseline"] = cpu_baseline(ds)
     print(json.dumps(line), flush=True)

@@ -238,6 +238,22 @@ int fb_profile(fb_ctx *c, int32_t every, int32_t max_samples);
 int fb_kernel_times(fb_ctx *c, double *eps_ms, double *gb_ms, double *hyper_ms, double *shift_ms,
                     int64_t *samples);
 
+/* Graph replay of the sweep (HIP graphs).  With sweeps > 0, fb_sweep(n) runs
+ * n / sweeps chunks (integer division) of `sweeps` sweeps each as one replay of
+ * a captured HIP graph of the chunk's launches, and the remaining sweeps with
+ * direct launches.  Before each replay the chunk's per-sweep arguments (sweep
+ * index, trace rows, training-pair rows, ...) are copied from pinned host
+ * memory to a device array that the captured kernels read, so one capture
+ * serves every chunk; the chunk is captured again only when the launch shape,
+ * the buffers or the set of kernels changes (e.g. fb_set_launch, the learned
+ * step).  The draws are those of direct launches, bit for bit.  While
+ * fb_profile samples, sweeps launch directly.  sweeps = 0 turns replay off.
+ * Limits: 0 <= sweeps <= 4096.  The graph records no memset nodes.
+ * Errors: FB_EINVAL, FB_ENOMEM, FB_EDEVICE.  fb_get_graph returns the current
+ * setting (0 when off or for NULL). */
+int fb_set_graph(fb_ctx *c, int32_t sweeps);
+int32_t fb_get_graph(const fb_ctx *c);
+
 /* Launch shape of a sweep; no choice changes any draw (the draws are functions
  * of their counters only).
  *   samples_per_wave  eps draws per lane, in sample order (1 .. max N): a

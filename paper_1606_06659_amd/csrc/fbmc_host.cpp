@@ -121,6 +121,16 @@ struct fb_ctx {
     bool net_ready = false;
     float *d_pairs = nullptr;
     int64_t pair_cap = 0, pair_n = 0, totalG = 0;
+    // graph replay (fb_set_graph): chunks of graph_k sweeps read their
+    // arguments from d_args, filled from one of two pinned host buffers
+    int64_t graph_k = 0, graph_cap = 0;
+    hipGraph_t graph = nullptr;
+    hipGraphExec_t gexec = nullptr;
+    std::vector<int64_t> gsig;
+    SweepArgs *d_args = nullptr;
+    SweepArgs *h_args[2] = {nullptr, nullptr};
+    hipEvent_t gcopied[2] = {nullptr, nullptr};
+    int gslot = 0;
 };
 
 namespace {
@@ -626,45 +636,69 @@ int build_items(fb_ctx *c, int spw)
     return FB_OK;
 }
 
-// One sweep m is two launches: the eps kernel of sweep m, which also runs the
-// hyperparameter step of sweep m - 1 in its first workgroups, then the
-// gamma/beta kernel of sweep m.  The hyperparameter step of the last sweep of
-// the call runs on its own at the end, so the state is whole between calls.
-// Unfused (c->fuse false), every sweep ends with its own hyperparameter kernel.
-int run_sweeps(fb_ctx *c, int64_t n, SweepMode &md)
+// The arguments of the next sweep; advances the host-side counters (sweep
+// index, trace rows, training-pair slots).
+static SweepArgs next_args(fb_ctx *c, SweepMode &md, int64_t m)
 {
     const fb_options &o = c->opt;
+    SweepArgs a{};
+    a.m = m;
+    a.burnin = o.burnin;
+    a.tune_start = o.tune_start;
+    a.inv_k = a.m > o.burnin ? 1.0 / (double)(a.m - o.burnin) : 0.0;
+    a.K = o.max_steps;
+    a.cap = o.shrink_cap;
+    a.mask = o.update_mask;
+    a.dbg = o.debug_counts;
+    a.trace_point = -1;
+    a.learned = md.learned ? 1 : 0;
+    a.count_imh = md.count_imh ? 1 : 0;
+    a.pair_base = -1;
+    a.dev = nullptr;
+    a.idx = 0;
+    if (md.collect_every > 0 && a.m % md.collect_every == 0 && (md.collect_slot + 1) * c->totalG <= c->pair_cap) {
+        a.pair_base = md.collect_slot * c->totalG;
+        ++md.collect_slot;
+        c->pair_n = md.collect_slot * c->totalG;
+    }
+    if (!md.no_trace && o.thin > 0 && o.trace_capacity > 0 && a.m % o.thin == 0 &&
+        (!o.trace_after_burnin || a.m > o.burnin)) {
+        if (c->trace_n < o.trace_capacity) a.trace_point = (int32_t)c->trace_n++;
+        else ++c->trace_dropped;
+    }
+    return a;
+}
+
+// The gamma/beta kernel's form: the learned kernel in its MH-only form when
+// no training pairs are taken.
+static int gb_mode_of(const SweepMode &md, const SweepArgs &a)
+{
+    return !md.learned_kernel ? 0 : (md.learned && a.pair_base < 0) ? 2 : 1;
+}
+
+// Enqueue the sweeps args[0..n).  One sweep m is two launches: the eps kernel
+// of sweep m, which also runs the hyperparameter step of sweep m - 1 in its
+// first workgroups, then the gamma/beta kernel of sweep m (with the learned
+// proposal the network kernel before it, with the shift step the shift kernel
+// after it).  The hyperparameter step of the last sweep runs on its own at the
+// end, so the state is whole between calls.  Unfused (c->fuse false), every
+// sweep ends with its own hyperparameter kernel.  With dev set, every kernel
+// takes sweep i's arguments from dev[i] (graph capture); profiling events are
+// recorded only without it.
+static int launch_sweeps(fb_ctx *c, const SweepArgs *args, int64_t n, const SweepMode &md, const SweepArgs *dev)
+{
     const int nseg = (int)c->seg.size();
-    HIPCHK(c, hipEventRecord(c->ev0, c->st));
     SweepArgs prev{};
     bool pending = false;
     for (int64_t i = 0; i < n; ++i) {
-        SweepArgs a{};
-        a.m = c->m + 1;
-        a.burnin = o.burnin;
-        a.tune_start = o.tune_start;
-        a.inv_k = a.m > o.burnin ? 1.0 / (double)(a.m - o.burnin) : 0.0;
-        a.K = o.max_steps;
-        a.cap = o.shrink_cap;
-        a.mask = o.update_mask;
-        a.dbg = o.debug_counts;
-        a.trace_point = -1;
-        a.learned = md.learned ? 1 : 0;
-        a.count_imh = md.count_imh ? 1 : 0;
-        a.pair_base = -1;
-        if (md.collect_every > 0 && a.m % md.collect_every == 0 &&
-            (md.collect_slot + 1) * c->totalG <= c->pair_cap) {
-            a.pair_base = md.collect_slot * c->totalG;
-            ++md.collect_slot;
-            c->pair_n = md.collect_slot * c->totalG;
+        SweepArgs a = args[i];
+        if (dev) {
+            a.dev = dev;
+            a.idx = i;
         }
-        if (!md.no_trace && o.thin > 0 && o.trace_capacity > 0 && a.m % o.thin == 0 &&
-            (!o.trace_after_burnin || a.m > o.burnin)) {
-            if (c->trace_n < o.trace_capacity) a.trace_point = (int32_t)c->trace_n++;
-            else ++c->trace_dropped;
-        }
-        const bool prof = c->prof_every > 0 && c->prof_n < c->prof_cap && (c->prof_count++ % c->prof_every) == 0;
-        const bool shift = (a.mask >> kKindShift) & 1u;
+        const bool prof = !dev && c->prof_every > 0 && c->prof_n < c->prof_cap &&
+                          (c->prof_count++ % c->prof_every) == 0;
+        const bool shift = (args[i].mask >> kKindShift) & 1u;
         hipEvent_t *pe = prof ? &c->prof_ev[8 * (size_t)c->prof_n] : nullptr;
         if (prof) {
             c->prof_hyp[c->prof_n] = c->fuse ? 0 : 1;
@@ -676,10 +710,8 @@ int run_sweeps(fb_ctx *c, int64_t n, SweepMode &md)
         if (pe) HIPCHK(c, hipEventRecord(pe[1], c->st));
         if (pe) HIPCHK(c, hipEventRecord(pe[2], c->st));
         if (md.learned) HIPCHK(c, launch_mlp_sweep(c->prec, c->d_segs, c->d_tiles, c->ntiles, c->d_net, c->st));
-        // the learned kernel in its MH-only form when no training pairs are taken
-        const int gb_mode = !md.learned_kernel ? 0 : (md.learned && a.pair_base < 0) ? 2 : 1;
-        HIPCHK(c, launch_gb(c->prec, gb_mode, c->maxL, c->d_segs, c->d_tiles, c->ntiles, c->d_fb_items,
-                            md.learned ? c->nfb_items : 0, a, c->d_net, c->d_err, c->st));
+        HIPCHK(c, launch_gb(c->prec, gb_mode_of(md, args[i]), c->maxL, c->d_segs, c->d_tiles, c->ntiles,
+                            c->d_fb_items, md.learned ? c->nfb_items : 0, a, c->d_net, c->d_err, c->st));
         if (pe) HIPCHK(c, hipEventRecord(pe[3], c->st));
         if (shift) {
             if (pe) HIPCHK(c, hipEventRecord(pe[6], c->st));
@@ -694,9 +726,90 @@ int run_sweeps(fb_ctx *c, int64_t n, SweepMode &md)
             HIPCHK(c, launch_hyper(c->d_segs, nseg, a, c->d_err, c->st));
             if (pe) HIPCHK(c, hipEventRecord(pe[5], c->st));
         }
-        c->m = a.m;
     }
     if (pending) HIPCHK(c, launch_hyper(c->d_segs, nseg, prev, c->d_err, c->st));
+    return FB_OK;
+}
+
+// What a captured chunk's launches depend on besides the arguments in device
+// memory: launch shape, buffers, sizes and each sweep's set of kernels.
+static std::vector<int64_t> graph_signature(const fb_ctx *c, const SweepMode &md, const SweepArgs *args, int64_t n)
+{
+    std::vector<int64_t> sig = {n, c->prec, c->maxL, c->fuse ? 1 : 0, (int64_t)(uintptr_t)c->d_segs,
+                                (int64_t)(uintptr_t)c->d_items, c->nitems, (int64_t)(uintptr_t)c->d_tiles,
+                                c->ntiles, (int64_t)(uintptr_t)c->d_fb_items, md.learned ? c->nfb_items : 0,
+                                (int64_t)(uintptr_t)c->d_net, (int64_t)(uintptr_t)c->d_err,
+                                (int64_t)(uintptr_t)c->st, md.learned ? 1 : 0};
+    for (int64_t i = 0; i < n; ++i) {
+        sig.push_back(gb_mode_of(md, args[i]));
+        sig.push_back((args[i].mask >> kKindShift) & 1u);
+    }
+    return sig;
+}
+
+void drop_graph(fb_ctx *c)
+{
+    if (c->gexec) (void)hipGraphExecDestroy(c->gexec);
+    if (c->graph) (void)hipGraphDestroy(c->graph);
+    c->gexec = nullptr;
+    c->graph = nullptr;
+    c->gsig.clear();
+}
+
+// One chunk of graph_k sweeps: arguments to pinned memory, then to the device
+// array the captured kernels read, then a replay of the chunk's graph
+// (captured again only when its signature changes).
+static int graph_chunk(fb_ctx *c, SweepMode &md)
+{
+    const int64_t K = c->graph_k;
+    const int slot = c->gslot;
+    c->gslot ^= 1;
+    HIPCHK(c, hipEventSynchronize(c->gcopied[slot]));     // the slot's previous copy is done
+    SweepArgs *h = c->h_args[slot];
+    for (int64_t i = 0; i < K; ++i) h[i] = next_args(c, md, c->m + 1 + i);
+    std::vector<int64_t> sig = graph_signature(c, md, h, K);
+    if (!c->gexec || sig != c->gsig) {
+        drop_graph(c);
+        HIPCHK(c, hipStreamBeginCapture(c->st, hipStreamCaptureModeThreadLocal));
+        int rc = launch_sweeps(c, h, K, md, c->d_args);
+        hipGraph_t g = nullptr;
+        const hipError_t e = hipStreamEndCapture(c->st, &g);
+        if (rc) {
+            if (g) (void)hipGraphDestroy(g);
+            return rc;
+        }
+        HIPCHK(c, e);
+        c->graph = g;
+        HIPCHK(c, hipGraphInstantiate(&c->gexec, c->graph, nullptr, nullptr, 0));
+        c->gsig = sig;
+    }
+    HIPCHK(c, hipMemcpyAsync(c->d_args, h, K * sizeof(SweepArgs), hipMemcpyHostToDevice, c->st));
+    HIPCHK(c, hipEventRecord(c->gcopied[slot], c->st));
+    HIPCHK(c, hipGraphLaunch(c->gexec, c->st));
+    c->m += K;
+    return FB_OK;
+}
+
+int run_sweeps(fb_ctx *c, int64_t n, SweepMode &md)
+{
+    HIPCHK(c, hipEventRecord(c->ev0, c->st));
+    int64_t done = 0;
+    // graph replay in chunks of graph_k sweeps; sampled profiling and a
+    // remainder shorter than a chunk launch directly
+    if (c->graph_k > 0 && c->prof_every == 0) {
+        int rc;
+        while (n - done >= c->graph_k) {
+            if ((rc = graph_chunk(c, md))) return rc;
+            done += c->graph_k;
+        }
+    }
+    if (done < n) {
+        std::vector<SweepArgs> args((size_t)(n - done));
+        for (int64_t i = 0; i < n - done; ++i) args[(size_t)i] = next_args(c, md, c->m + 1 + i);
+        int rc = launch_sweeps(c, args.data(), n - done, md, nullptr);
+        if (rc) return rc;
+        c->m += n - done;
+    }
     HIPCHK(c, hipEventRecord(c->ev1, c->st));
     c->last_n = n;
     return FB_OK;
@@ -956,6 +1069,11 @@ void fb_destroy(fb_ctx *c)
 {
     if (!c) return;
     if (c->st) (void)hipStreamSynchronize(c->st);
+    drop_graph(c);
+    for (int i = 0; i < 2; ++i) {
+        if (c->h_args[i]) (void)hipHostFree(c->h_args[i]);
+        if (c->gcopied[i]) (void)hipEventDestroy(c->gcopied[i]);
+    }
     for (hipEvent_t e : c->prof_ev) (void)hipEventDestroy(e);
     for (void *p : c->allocs) (void)hipFree(p);
     if (c->ev0) (void)hipEventDestroy(c->ev0);
@@ -974,6 +1092,29 @@ int fb_sweep(fb_ctx *c, int64_t n)
     md.learned_kernel = md.learned;
     return run_sweeps(c, n, md);
 }
+
+int fb_set_graph(fb_ctx *c, int32_t sweeps)
+{
+    if (!c) return fail(nullptr, FB_EINVAL, "NULL context");
+    if (sweeps < 0 || sweeps > 4096) return fail(c, FB_EINVAL, "sweeps per graph must be in 0..4096");
+    HIPCHK(c, hipStreamSynchronize(c->st));
+    drop_graph(c);
+    if (sweeps > c->graph_cap) {
+        int rc;
+        if ((rc = dalloc(c, (void **)&c->d_args, (size_t)sweeps * sizeof(SweepArgs)))) return rc;
+        for (int i = 0; i < 2; ++i) {
+            if (c->h_args[i]) HIPCHK(c, hipHostFree(c->h_args[i]));
+            c->h_args[i] = nullptr;
+            HIPCHK(c, hipHostMalloc((void **)&c->h_args[i], (size_t)sweeps * sizeof(SweepArgs), hipHostMallocDefault));
+            if (!c->gcopied[i]) HIPCHK(c, hipEventCreateWithFlags(&c->gcopied[i], hipEventDisableTiming));
+        }
+        c->graph_cap = sweeps;
+    }
+    c->graph_k = sweeps;
+    return FB_OK;
+}
+
+int32_t fb_get_graph(const fb_ctx *c) { return c ? (int32_t)c->graph_k : 0; }
 
 int fb_sync(fb_ctx *c)
 {

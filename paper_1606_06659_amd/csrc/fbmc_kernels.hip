@@ -887,9 +887,10 @@ __device__ inline void beta_genes(const SegInfo &S, int64_t g, bool active, int6
 // (fb_items: segment, first list entry, count, partial column).
 template <typename T, int kMode, int kML>
 __global__ __launch_bounds__(128) void gb_sweep(const SegInfo *__restrict__ segs, const int2 *__restrict__ tiles,
-                                                int ntiles, const int4 *__restrict__ fb_items, int nfb, SweepArgs a,
+                                                int ntiles, const int4 *__restrict__ fb_items, int nfb, SweepArgs a0,
                                                 const MlpDev *__restrict__ net, int *err)
 {
+    const SweepArgs a = resolve_args(a0);
     const int wave = __builtin_amdgcn_readfirstlane((int)(threadIdx.x >> 6));
     const int lane = (int)(threadIdx.x & 63);
     const int tix = (int)blockIdx.x;
@@ -1087,8 +1088,9 @@ __device__ inline void shift_genes(const SegInfo &S, int tile, const SweepArgs &
 
 template <typename T, int kML>
 __global__ __launch_bounds__(256) void shift_sweep(const SegInfo *__restrict__ segs, const int2 *__restrict__ tiles,
-                                                   int ntiles, SweepArgs a)
+                                                   int ntiles, SweepArgs a0)
 {
+    const SweepArgs a = resolve_args(a0);
     const int wave = __builtin_amdgcn_readfirstlane((int)(threadIdx.x >> 6));
     const int tix = (int)blockIdx.x * 4 + wave;
     if (tix >= ntiles) return;            // the whole wavefront leaves
@@ -1632,9 +1634,9 @@ __device__ inline void hyper_block(const SegInfo &S, const SweepArgs &a, int *er
     for (int i = tid; i < kWords; i += kHyperThreads) hw[i] = hs[i];
 }
 
-__global__ __launch_bounds__(kHyperThreads) void hyper_sweep(const SegInfo *__restrict__ segs, SweepArgs a, int *err)
+__global__ __launch_bounds__(kHyperThreads) void hyper_sweep(const SegInfo *__restrict__ segs, SweepArgs a0, int *err)
 {
-    hyper_block(segs[blockIdx.x], a, err);
+    hyper_block(segs[blockIdx.x], resolve_args(a0), err);
 }
 
 // Step 1 of sweep a.m over the work items; when nhyp > 0 the first nhyp
@@ -1644,13 +1646,14 @@ __global__ __launch_bounds__(kHyperThreads) void hyper_sweep(const SegInfo *__re
 // hyperparameter code, which runs on one workgroup per segment, spills.
 template <typename T>
 __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(7, 8))) void eps_sweep(
-    const SegInfo *__restrict__ segs, const int4 *__restrict__ items, int nitems, SweepArgs a, int nhyp,
+    const SegInfo *__restrict__ segs, const int4 *__restrict__ items, int nitems, SweepArgs a0, int nhyp,
     SweepArgs ha, int *err)
 {
     if ((int)blockIdx.x < nhyp) {
-        hyper_block(segs[blockIdx.x], ha, err);
+        hyper_block(segs[blockIdx.x], resolve_args(ha), err);
         return;
     }
+    const SweepArgs a = resolve_args(a0);
     const int wave = __builtin_amdgcn_readfirstlane((int)(threadIdx.x >> 6));
     const int it = ((int)blockIdx.x - nhyp) * 4 + wave;
     if (it >= nitems) return;

@@ -95,6 +95,23 @@ struct SweepArgs {
     int32_t learned;      // beta by independence MH where the fallback mask is 0
     int32_t count_imh;    // add accepted IMH steps to imh_count
     int64_t pair_base;    // collect (features, beta) pairs at row pair_base + g, or -1
+    // graph replay: when dev is set, the kernel takes its arguments from
+    // dev[idx] (written before each replay) and ignores the fields above
+    const SweepArgs *dev;
+    int64_t idx;
 };
+
+// The arguments a kernel runs with: its own copy, or the one in device memory.
+// Written as a copy and a branch on purpose: the conditional-operator form
+// (a.dev ? a.dev[a.idx] : a), which selects between the kernel-argument copy
+// and the device-memory copy by address, gave wrong independence-MH
+// decisions in the FP64 learned gamma/beta kernel with this toolchain (the
+// FP64 parity tests against the oracle catch it); this form matches.
+__device__ inline SweepArgs resolve_args(const SweepArgs &a)
+{
+    SweepArgs r = a;
+    if (a.dev != nullptr) r = a.dev[a.idx];
+    return r;
+}
 
 }  // namespace fbmc

@@ -69,7 +69,8 @@ EXPORTS = [
     "fb_default_options", "fb_create", "fb_create_batch", "fb_destroy", "fb_sweep", "fb_sync",
     "fb_num_segments", "fb_segment_dims", "fb_get_state", "fb_set_state", "fb_summaries",
     "fb_trace_genes", "fb_trace", "fb_trace_reset", "fb_debug_counts", "fb_reductions",
-    "fb_philox", "fb_last_sweep_time", "fb_profile", "fb_kernel_times", "fb_set_launch",
+    "fb_philox", "fb_last_sweep_time", "fb_profile", "fb_kernel_times", "fb_set_graph", "fb_get_graph",
+    "fb_set_launch",
     "fb_get_launch", "fb_autotune", "fb_last_error",
     "fb_strerror", "fb_default_train_opts", "fb_proposal_collect", "fb_proposal_train",
     "fb_proposal_calibrate", "fb_set_beta_update", "fb_proposal_get", "fb_proposal_set",
@@ -116,6 +117,9 @@ def load() -> C.CDLL:
     L.fb_last_sweep_time.argtypes = [vp, _DP, C.POINTER(i64)]
     L.fb_profile.argtypes = [vp, i32, i32]
     L.fb_kernel_times.argtypes = [vp, _DP, _DP, _DP, _DP, C.POINTER(i64)]
+    L.fb_set_graph.argtypes = [vp, C.c_int32]
+    L.fb_get_graph.argtypes = [vp]
+    L.fb_get_graph.restype = C.c_int32
     L.fb_set_launch.argtypes = [vp, i32, i32]
     L.fb_get_launch.argtypes = [vp, C.POINTER(i32), C.POINTER(i32)]
     L.fb_autotune.argtypes = [vp, i32, C.POINTER(i32), C.POINTER(i32), _DP, _DP]
@@ -327,6 +331,15 @@ def fb_kernel_times(ctx):
     e, g, h, s, n = C.c_double(), C.c_double(), C.c_double(), C.c_double(), C.c_int64()
     _check(load().fb_kernel_times(ctx, C.byref(e), C.byref(g), C.byref(h), C.byref(s), C.byref(n)), ctx)
     return e.value, g.value, h.value, s.value, n.value
+
+
+def fb_set_graph(ctx, sweeps: int):
+    """Replay chunks of `sweeps` sweeps as one captured HIP graph (0: off)."""
+    _check(load().fb_set_graph(ctx, int(sweeps)), ctx)
+
+
+def fb_get_graph(ctx) -> int:
+    return int(load().fb_get_graph(ctx))
 
 
 def fb_set_launch(ctx, samples_per_wave: int, fuse_hyper: int):
