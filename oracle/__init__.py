@@ -348,3 +348,34 @@ def _oracle_features(self, F=32):
 Oracle.set_proposal = _oracle_set_proposal
 Oracle.imh = _oracle_imh
 Oracle.features = _oracle_features
+
+
+def _oracle_set_contrasts(self, events):
+    """Contrast events (Section 3.2): `events` is a list of events, each a list
+    of (v, b) rows meaning sum_l v_l beta_gl > b; an event holds when all of
+    its rows do.  Counting starts with the next sweep after burn-in."""
+    L = self._L
+    dp = C.POINTER(C.c_double)
+    L.or_set_contrasts.argtypes = [C.c_void_p, C.c_int32, C.c_int32, C.POINTER(C.c_int32), dp, dp]
+    rows = [(e, np.asarray(v, dtype=np.float64), float(b)) for e, ev in enumerate(events) for v, b in ev]
+    ev = np.array([r[0] for r in rows], np.int32)
+    V = np.ascontiguousarray(np.array([r[1] for r in rows]).reshape(len(rows), self.L), dtype=np.float64)
+    B = np.array([r[2] for r in rows], np.float64)
+    if L.or_set_contrasts(self._h, len(events), len(rows), _p(ev, C.c_int32), _p(V), _p(B)) != 0:
+        raise ValueError("or_set_contrasts failed")
+    self._n_events = len(events)
+
+
+def _oracle_event_counts(self):
+    """(counts [G, events] int64, sweeps counted)."""
+    L = self._L
+    L.or_event_counts.argtypes = [C.c_void_p, C.POINTER(C.c_int64), C.POINTER(C.c_int64)]
+    E = getattr(self, "_n_events", 0)
+    out = np.zeros((self.G, E), np.int64)
+    n = C.c_int64()
+    L.or_event_counts(self._h, _p(out, C.c_int64) if E else None, C.byref(n))
+    return out, int(n.value)
+
+
+Oracle.set_contrasts = _oracle_set_contrasts
+Oracle.event_counts = _oracle_event_counts

@@ -225,6 +225,15 @@ struct or_ctx {
     int32_t *prop_mask;    /* [G]: 1 = slice fallback */
     int32_t *imh_acc;      /* [G]: last sweep, 1 = accepted, 0 = rejected, -1 = slice */
     double *imh_la;        /* [G]: log acceptance ratio of the last IMH step */
+    /* posterior probabilities of contrast events (Section 3.2): event e is the
+     * conjunction of the rows r with crow_event[r] == e, row r the inequality
+     * sum_l cv[r][l] beta_gl > cb[r]; ev_count[g][e] counts the sweeps
+     * m > max(M_B, ev_from) whose end-of-sweep beta_g satisfies event e */
+    int n_ev, n_crow;
+    int32_t *crow_event;
+    double *cv, *cb;
+    int64_t *ev_count;
+    int64_t ev_from;
 };
 
 static int64_t n_params(const or_ctx *c)
@@ -317,6 +326,7 @@ void or_destroy(or_ctx *c)
     free(c->w_beta); free(c->wa_beta); free(c->w_sig2); free(c->wa_sig2);
     free(c->mean); free(c->msq); free(c->cnt); free(c->mrg);
     free(c->row_of); free(c->prop_buf); free(c->prop_mask); free(c->imh_acc); free(c->imh_la);
+    free(c->crow_event); free(c->cv); free(c->cb); free(c->ev_count);
     free(c);
 }
 
@@ -899,8 +909,65 @@ static int64_t sweep_once(or_ctx *c)
         for (int l = 0; l < L; ++l) welford(&mu[o + 2 + L + l], &sq[o + 2 + L + l], c->sig2[l], k);
         c->count = k;
     }
+    /* indicators of the contrast events at the end of the sweep (Section 3.2) */
+    if (c->n_ev > 0 && m > cf->burnin && m > c->ev_from) {
+        for (int64_t g = 0; g < G; ++g) {
+            for (int e = 0; e < c->n_ev; ++e) {
+                int all = 1;
+                for (int r = 0; r < c->n_crow; ++r) {
+                    if (c->crow_event[r] != e) continue;
+                    double sum = 0.0;
+                    for (int l = 0; l < L; ++l) sum += c->cv[r * L + l] * c->beta[g * L + l];
+                    if (OR_MUTANT == 12) { if (sum > c->cb[r]) all = 2; else if (all == 1) all = 0; }
+                    else if (!(sum > c->cb[r])) all = 0;
+                }
+                c->ev_count[g * c->n_ev + e] += all ? 1 : 0;
+            }
+        }
+    }
     c->m = m;
     return errs;
+}
+
+int or_set_contrasts(or_ctx *c, int32_t n_events, int32_t n_rows, const int32_t *row_event, const double *v,
+                     const double *b)
+{
+    if (!c || n_events < 0 || n_rows < n_events || (n_rows > 0 && (!row_event || !v || !b))) return -1;
+    for (int r = 0; r < n_rows; ++r)
+        if (row_event[r] < 0 || row_event[r] >= n_events) return -1;
+    for (int e = 0; e < n_events; ++e) {
+        int seen = 0;
+        for (int r = 0; r < n_rows; ++r) seen |= row_event[r] == e;
+        if (!seen) return -1;
+    }
+    const int L = c->cfg.L;
+    const int64_t G = c->cfg.G;
+    free(c->crow_event); free(c->cv); free(c->cb); free(c->ev_count);
+    c->crow_event = (int32_t *)xcalloc((size_t)n_rows, sizeof(int32_t));
+    c->cv = (double *)xcalloc((size_t)n_rows * L, sizeof(double));
+    c->cb = (double *)xcalloc((size_t)n_rows, sizeof(double));
+    c->ev_count = (int64_t *)xcalloc((size_t)(G * (n_events ? n_events : 1)), sizeof(int64_t));
+    if (!c->crow_event || !c->cv || !c->cb || !c->ev_count) return -2;
+    if (n_rows) {
+        memcpy(c->crow_event, row_event, sizeof(int32_t) * (size_t)n_rows);
+        memcpy(c->cv, v, sizeof(double) * (size_t)n_rows * L);
+        memcpy(c->cb, b, sizeof(double) * (size_t)n_rows);
+    }
+    c->n_ev = n_events;
+    c->n_crow = n_rows;
+    c->ev_from = c->m;
+    return 0;
+}
+
+int or_event_counts(const or_ctx *c, int64_t *counts, int64_t *n_sweeps)
+{
+    if (!c) return -1;
+    if (counts && c->n_ev) memcpy(counts, c->ev_count, sizeof(int64_t) * (size_t)(c->cfg.G * c->n_ev));
+    if (n_sweeps) {
+        const int64_t from = c->cfg.burnin > c->ev_from ? c->cfg.burnin : c->ev_from;
+        *n_sweeps = c->m > from ? c->m - from : 0;
+    }
+    return 0;
 }
 
 int or_sweep(or_ctx *c, int64_t n)

@@ -155,6 +155,15 @@ int or_get_imh(const or_ctx *c, int32_t *acc, double *log_alpha);
 /* Number of distinct rows of X. */
 int or_num_rows(const or_ctx *c);
 
+/* Posterior probabilities of contrast events (Section 3.2): event e holds
+ * when every row r with row_event[r] == e has sum_l v[r][l] beta_gl > b[r]
+ * (v is [n_rows][L]).  Counting starts with the sweeps after this call and
+ * after burn-in; or_event_counts returns counts [G][n_events] and the number
+ * of sweeps counted. */
+int or_set_contrasts(or_ctx *c, int32_t n_events, int32_t n_rows, const int32_t *row_event, const double *v,
+                     const double *b);
+int or_event_counts(const or_ctx *c, int64_t *counts, int64_t *n_sweeps);
+
 #ifdef __cplusplus
 }
 #endif

@@ -5,6 +5,7 @@ import pytest
 from tests import test_oracle_mlp as M
 from tests import test_oracle_pins as P
 from tests import test_oracle_shift as S
+from tests import test_oracle_events as E
 
 MUTANTS = [
     # (switch, what is wrong, the pin that must fail)
@@ -27,6 +28,8 @@ MUTANTS = [
      lambda o: S.test_shift_keeps_the_likelihood_sums(o, "paper")),
     (11, "shift step mean without the prior term (beta - theta) / sigma^2",
      lambda o: S.test_shift_draws_the_conditional(o, "two_group")),
+    (12, "contrast event as 'any row' instead of 'all rows'",
+     lambda o: E.test_event_counts_match_a_recount(o)),
 ]
 
 
