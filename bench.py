@@ -261,6 +261,42 @@ def run_small(fbmc, stream, steps=2000, graph_sweeps=50):
     return out
 
 
+def run_batched(fbmc, stream, steps=100, burnin=200, graph_sweeps=25):
+    """Secondary measurement: the batched workload, 64 datasets (G log-uniform
+    on [2,000, 60,000], N from {4, 8, 16} with L = 2, 3, 5; about 1.09M genes)
+    with one chain each, advancing together in one context, FP32.  After a
+    short burn-in the autotuner picks the launch shape; `steps` sweeps are then
+    timed with direct launches and with graph replay."""
+    import torch
+    from paper_1606_06659_amd import datagen
+    meta = datagen.batched_meta(64, seed=0)
+    dss = [datagen.batched_dataset(k + 1, G, N) for k, (G, N) in enumerate(meta)]
+    genes = sum(d.G for d in dss)
+    opts = fbmc.fb_default_options(burnin=burnin, tune_start=burnin // 10, precision=fbmc.FB_FP32, jitter=0,
+                                   stream=stream.cuda_stream)
+    ctx = fbmc.fb_create_batch([dict(counts=d.y, X=d.X, h=d.h, seed=k + 1) for k, d in enumerate(dss)], opts)
+    fbmc.fb_sweep(ctx, burnin + 10)
+    fbmc.fb_sync(ctx)
+    spw, fuse, _, _ = fbmc.fb_autotune(ctx, 10)
+    out = {"workload": f"batched: 64 datasets, {genes} genes in total, N in {{4, 8, 16}}, 1 chain each",
+           "genes": genes, "steps": steps, "launch": {"samples_per_wave": spw, "fused_hyper": fuse},
+           "graph_sweeps": graph_sweeps}
+    for name, k in (("direct", 0), ("graph", graph_sweeps)):
+        fbmc.fb_set_graph(ctx, k)
+        fbmc.fb_sweep(ctx, graph_sweeps)
+        fbmc.fb_sync(ctx)
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        fbmc.fb_sweep(ctx, steps)
+        fbmc.fb_sync(ctx)
+        torch.cuda.synchronize()
+        dt = time.perf_counter() - t0
+        out[f"{name}_sweeps_per_s"] = steps / dt
+        out[f"{name}_gene_sweeps_per_s"] = steps * genes / dt
+    fbmc.fb_destroy(ctx)
+    return out
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -391,6 +427,7 @@ def main():
     if not args.no_heavy:
         line["heavy_workload"] = run_heavy(fbmc, stream)
         line["small_workload"] = run_small(fbmc, stream)
+        line["batched_workload"] = run_batched(fbmc, stream)
     if not args.no_cpu_baseline:
         line["cpu_baseline"] = cpu_baseline(ds)
     print(json.dumps(line), flush=True)

@@ -238,6 +238,21 @@ int fb_profile(fb_ctx *c, int32_t every, int32_t max_samples);
 int fb_kernel_times(fb_ctx *c, double *eps_ms, double *gb_ms, double *hyper_ms, double *shift_ms,
                     int64_t *samples);
 
+/* Posterior probabilities of contrast events (Section 3.2).  Event e
+ * (0 <= e < n_events <= 8) holds for gene g at a sweep when every row r with
+ * row_event[r] == e satisfies sum_l v[r][l] beta_gl > b[r] (v is [n_rows][L],
+ * n_events <= n_rows <= 16, every event has a row; L is the context's, so all
+ * of its datasets must share it).  From the next sweep on, every post-burn-in
+ * sweep adds 1 to count[g][e] when event e holds on that sweep's final beta_g
+ * (after the shift step when it is on); the estimate of the probability is
+ * count / n_sweeps.  A new call replaces the events and restarts the counts.
+ * fb_event_counts fills counts [G][n_events] of segment `seg` (caller-
+ * allocated, NULL skips) and n_sweeps, the sweeps counted.  The library copies
+ * the arguments.  Errors: FB_EINVAL, FB_ENOMEM, FB_EDEVICE. */
+int fb_set_contrasts(fb_ctx *c, int32_t n_events, int32_t n_rows, const int32_t *row_event, const double *v,
+                     const double *b);
+int fb_event_counts(fb_ctx *c, int32_t seg, int32_t *counts, int64_t *n_sweeps);
+
 /* Graph replay of the sweep (HIP graphs).  With sweeps > 0, fb_sweep(n) runs
  * n / sweeps chunks (integer division) of `sweeps` sweeps each as one replay of
  * a captured HIP graph of the chunk's launches, and the remaining sweeps with

@@ -1350,6 +1350,66 @@ int fb_reductions(fb_ctx *c, int32_t seg, double *out)
     return c->sticky;
 }
 
+int fb_set_contrasts(fb_ctx *c, int32_t n_events, int32_t n_rows, const int32_t *row_event, const double *v,
+                     const double *b)
+{
+    if (!c) return fail(nullptr, FB_EINVAL, "NULL context");
+    if (n_events < 0 || n_events > kMaxEv || n_rows < n_events || n_rows > kMaxCtr ||
+        (n_rows > 0 && (!row_event || !v || !b)))
+        return fail(c, FB_EINVAL, "need 0 <= events <= 8, events <= rows <= 16 and the row arrays");
+    const int L = c->seg.front().L;
+    for (const auto &S : c->seg)
+        if (S.L != L) return fail(c, FB_EINVAL, "contrasts need every dataset of the context to have the same L");
+    for (int r = 0; r < n_rows; ++r) {
+        if (row_event[r] < 0 || row_event[r] >= n_events) return fail(c, FB_EINVAL, "row_event out of range");
+        for (int l = 0; l < L; ++l)
+            if (!std::isfinite(v[r * L + l])) return fail(c, FB_EINVAL, "non-finite contrast");
+        if (!std::isfinite(b[r])) return fail(c, FB_EINVAL, "non-finite bound");
+    }
+    for (int e = 0; e < n_events; ++e) {
+        bool seen = false;
+        for (int r = 0; r < n_rows; ++r) seen = seen || row_event[r] == e;
+        if (!seen) return fail(c, FB_EINVAL, "every event needs at least one row");
+    }
+    HIPCHK(c, hipStreamSynchronize(c->st));
+    for (auto &S : c->seg) {
+        SegInfo &I = S.info;
+        const size_t bytes = (size_t)kMaxEv * (size_t)S.Gp * sizeof(int32_t);
+        int rc;
+        if (!I.ev_count && (rc = dalloc(c, (void **)&I.ev_count, bytes))) return rc;
+        HIPCHK(c, hipMemset(I.ev_count, 0, bytes));
+        I.n_ev = n_events;
+        I.n_crow = n_rows;
+        I.ev_from = c->m;
+        for (int r = 0; r < kMaxCtr; ++r) {
+            I.crow_event[r] = r < n_rows ? row_event[r] : 0;
+            I.cb[r] = r < n_rows ? b[r] : 0.0;
+            for (int l = 0; l < kMaxL; ++l) I.cv[r * kMaxL + l] = (r < n_rows && l < L) ? v[r * L + l] : 0.0;
+        }
+    }
+    return upload_segs(c);
+}
+
+int fb_event_counts(fb_ctx *c, int32_t seg, int32_t *counts, int64_t *n_sweeps)
+{
+    if (!valid_seg(c, seg)) return fail(c, FB_EINVAL, "bad segment");
+    int rc = fb_sync(c);
+    if (rc && rc != FB_ENUMERIC) return rc;
+    const SegmentH &S = c->seg[seg];
+    const SegInfo &I = S.info;
+    if (n_sweeps) {
+        const int64_t from = I.n_ev > 0 ? std::max<int64_t>(c->opt.burnin, I.ev_from) : c->m;
+        *n_sweeps = c->m > from ? c->m - from : 0;
+    }
+    if (counts && I.n_ev > 0) {
+        std::vector<int32_t> buf((size_t)I.n_ev * (size_t)S.Gp);
+        HIPCHK(c, hipMemcpy(buf.data(), I.ev_count, buf.size() * sizeof(int32_t), hipMemcpyDeviceToHost));
+        for (int64_t g = 0; g < S.G; ++g)
+            for (int e = 0; e < I.n_ev; ++e) counts[g * I.n_ev + e] = buf[(size_t)e * (size_t)S.Gp + (size_t)g];
+    }
+    return c->sticky;
+}
+
 int fb_philox(const uint32_t *ctr, const uint32_t *key, uint32_t *out, int64_t n)
 {
     if (n < 0 || (n > 0 && (!ctr || !key || !out))) return fail(nullptr, FB_EINVAL, "bad arguments");

@@ -115,6 +115,22 @@ __device__ inline double wave_sum(double v)
     return v;
 }
 
+// N wavefront sums at once, each with the same butterfly as wave_sum (so the
+// same bits): per step all N exchanges are issued before any add waits for
+// them, instead of N dependent chains one after another.
+template <int N>
+__device__ inline void wave_sum_n(double (&v)[N])
+{
+#pragma unroll
+    for (int off = 32; off >= 1; off >>= 1) {
+        double t[N];
+#pragma unroll
+        for (int k = 0; k < N; ++k) t[k] = __shfl_xor(v[k], off, 64);
+#pragma unroll
+        for (int k = 0; k < N; ++k) v[k] += t[k];
+    }
+}
+
 // Orders the LDS accesses of one wavefront: the writes of every lane before
 // the reads that follow.
 __device__ inline void wave_lds_sync()
@@ -575,24 +591,47 @@ __device__ inline void beta_finish(const SegInfo &S, const SweepArgs &a, int64_t
                                    int tile, int lane, int tslot, float *trow, bool sampling)
 {
     const int L = seg_L<kML>(S);
-    for (int l = 0; l < L; ++l) {
-        T b1 = (T)0;
-        double2 mo = make_double2(0.0, 0.0);
-        double thl = 0.0;
+    constexpr int kB = kML < kMaxL ? kML : kMaxL;
+    double sv[2 * kB];
 #pragma unroll
-        for (int j = 0; j < kMaxL; ++j)
-            if (j == l) { b1 = beta[j]; mo = mob[j]; thl = th[j]; }
-        if (active && sampling) {
-            welford(mo, (double)b1, a.inv_k);
-            S.mom_beta[(int64_t)l * Gp + g] = mo;
+    for (int l = 0; l < kB; ++l) {
+        sv[2 * l] = 0.0;
+        sv[2 * l + 1] = 0.0;
+        if (l < L) {
+            const T b1 = beta[l];
+            if (active && sampling) {
+                double2 mo = mob[l];
+                welford(mo, (double)b1, a.inv_k);
+                S.mom_beta[(int64_t)l * Gp + g] = mo;
+            }
+            if (tslot >= 0) trow[(int64_t)tslot * (L + 1) + 1 + l] = (float)b1;
+            const double dv = active ? (double)b1 - th[l] : 0.0;
+            sv[2 * l] = dv;
+            sv[2 * l + 1] = dv * dv;
         }
-        if (tslot >= 0) trow[(int64_t)tslot * (L + 1) + 1 + l] = (float)b1;
-        const double dv = active ? (double)b1 - thl : 0.0;
-        const double s0 = wave_sum(dv), s1 = wave_sum(dv * dv);
-        if (lane == 0) {
-            S.partials[(int64_t)(2 + 2 * l) * S.pstride + tile] = s0;
-            S.partials[(int64_t)(3 + 2 * l) * S.pstride + tile] = s1;
+    }
+    // contrast events (Section 3.2) on the end-of-sweep beta: bit e of `fail`
+    // is set when a row of event e does not hold
+    if (S.n_ev > 0 && active && sampling && a.m > S.ev_from) {
+        uint32_t fail = 0;
+        for (int r = 0; r < S.n_crow; ++r) {
+            double sum = 0.0;
+#pragma unroll
+            for (int l = 0; l < kB; ++l)
+                if (l < L) sum += S.cv[r * kMaxL + l] * (double)beta[l];
+            if (!(sum > S.cb[r])) fail |= 1u << S.crow_event[r];
         }
+        for (int e = 0; e < S.n_ev; ++e)
+            if (!((fail >> e) & 1u)) S.ev_count[(int64_t)e * Gp + g] += 1;
+    }
+    wave_sum_n(sv);
+    if (lane == 0) {
+#pragma unroll
+        for (int l = 0; l < kB; ++l)
+            if (l < L) {
+                S.partials[(int64_t)(2 + 2 * l) * S.pstride + tile] = sv[2 * l];
+                S.partials[(int64_t)(3 + 2 * l) * S.pstride + tile] = sv[2 * l + 1];
+            }
     }
 }
 
@@ -741,10 +780,11 @@ __device__ inline void gamma_wave(const SegInfo &S, int tile, const SweepArgs &a
                 S.trace[(int64_t)a.trace_point * S.trace_stride + 2 + 2 * L + (int64_t)tslot * (L + 1)] = (float)gam;
         }
     }
-    const double s0 = wave_sum(lg), s1 = wave_sum(ig);
+    double sv[2] = {lg, ig};
+    wave_sum_n(sv);
     if (lane == 0) {
-        S.partials[tile] = s0;
-        S.partials[S.pstride + tile] = s1;
+        S.partials[tile] = sv[0];
+        S.partials[S.pstride + tile] = sv[1];
     }
     if (bad) raise_flag(err, 2);
 }

@@ -13,6 +13,8 @@ constexpr int kMaxVals = 4;    // distinct non-zero values per column
 constexpr int kTile = 64;      // genes per wavefront tile
 constexpr int kMaxParts = 2 + 2 * kMaxL;
 constexpr int kKindShift = 11;  // Philox kind and update_mask bit of the shift step
+constexpr int kMaxEv = 8;       // contrast events per context
+constexpr int kMaxCtr = 16;     // contrast rows (inequalities) over all events
 
 // Per-segment (dataset x chain) description.  Lives in device memory and is
 // read with wavefront-uniform loads.  Arrays of state are gene-contiguous
@@ -41,6 +43,15 @@ struct SegInfo {
     // prior constants (Section 4.1)
     double a, b, d;
     double c[kMaxL], s[kMaxL];
+    // contrast events (Section 3.2): event e holds when every row r with
+    // crow_event[r] == e has sum_l cv[r][l] beta_gl > cb[r]; ev_count[e][g]
+    // counts the sweeps m > max(M_B, ev_from) where it held for gene g
+    int32_t n_ev, n_crow;
+    int64_t ev_from;
+    int32_t crow_event[kMaxCtr];
+    double cv[kMaxCtr * kMaxL];   // [n_crow][kMaxL]
+    double cb[kMaxCtr];
+    int32_t *ev_count;            // [kMaxEv][Gp]
     // device pointers
     const int32_t *y;             // [N][Gp]
     void *eps, *w_eps, *wa_eps;   // [N][Gp] (float or double)

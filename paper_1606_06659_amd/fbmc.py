@@ -70,6 +70,7 @@ EXPORTS = [
     "fb_num_segments", "fb_segment_dims", "fb_get_state", "fb_set_state", "fb_summaries",
     "fb_trace_genes", "fb_trace", "fb_trace_reset", "fb_debug_counts", "fb_reductions",
     "fb_philox", "fb_last_sweep_time", "fb_profile", "fb_kernel_times", "fb_set_graph", "fb_get_graph",
+    "fb_set_contrasts", "fb_event_counts",
     "fb_set_launch",
     "fb_get_launch", "fb_autotune", "fb_last_error",
     "fb_strerror", "fb_default_train_opts", "fb_proposal_collect", "fb_proposal_train",
@@ -118,6 +119,8 @@ def load() -> C.CDLL:
     L.fb_profile.argtypes = [vp, i32, i32]
     L.fb_kernel_times.argtypes = [vp, _DP, _DP, _DP, _DP, C.POINTER(i64)]
     L.fb_set_graph.argtypes = [vp, C.c_int32]
+    L.fb_set_contrasts.argtypes = [vp, i32, i32, C.POINTER(C.c_int32), _DP, _DP]
+    L.fb_event_counts.argtypes = [vp, i32, C.POINTER(C.c_int32), C.POINTER(i64)]
     L.fb_get_graph.argtypes = [vp]
     L.fb_get_graph.restype = C.c_int32
     L.fb_set_launch.argtypes = [vp, i32, i32]
@@ -331,6 +334,32 @@ def fb_kernel_times(ctx):
     e, g, h, s, n = C.c_double(), C.c_double(), C.c_double(), C.c_double(), C.c_int64()
     _check(load().fb_kernel_times(ctx, C.byref(e), C.byref(g), C.byref(h), C.byref(s), C.byref(n)), ctx)
     return e.value, g.value, h.value, s.value, n.value
+
+
+def fb_set_contrasts(ctx, events, L: int):
+    """Contrast events (Section 3.2): a list of events, each a list of (v, b)
+    rows meaning sum_l v_l beta_gl > b; an event holds when all its rows do."""
+    rows = [(e, np.asarray(v, dtype=np.float64).reshape(L), float(b)) for e, ev in enumerate(events) for v, b in ev]
+    ev = np.array([r[0] for r in rows], np.int32)
+    V = np.ascontiguousarray(np.array([r[1] for r in rows]).reshape(len(rows), L), dtype=np.float64)
+    B = np.array([r[2] for r in rows], np.float64)
+    _check(load().fb_set_contrasts(ctx, len(events), len(rows), _p(ev, C.c_int32), _p(V), _p(B)), ctx)
+
+
+def fb_event_counts(ctx, n_events: int, seg: int = 0):
+    """(counts [G, n_events] int32, sweeps counted) of one segment."""
+    G = fb_segment_dims(ctx, seg)["G"]
+    out = np.zeros((G, n_events), np.int32)
+    n = C.c_int64()
+    _check(load().fb_event_counts(ctx, seg, _p(out, C.c_int32) if n_events else None, C.byref(n)), ctx,
+           (FB_ENUMERIC,))
+    return out, int(n.value)
+
+
+def fb_event_probs(ctx, n_events: int, seg: int = 0):
+    """Posterior probabilities [G, n_events]: counts / sweeps counted."""
+    c, n = fb_event_counts(ctx, n_events, seg)
+    return c / max(n, 1), n
 
 
 def fb_set_graph(ctx, sweeps: int):
