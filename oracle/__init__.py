@@ -17,6 +17,7 @@ _HERE = os.path.dirname(os.path.abspath(__file__))
 _SO = os.path.join(_HERE, "liboracle.so")
 
 KIND_EPS, KIND_GAMMA, KIND_NU, KIND_TAU, KIND_BETA, KIND_THETA, KIND_SIG2 = 1, 2, 3, 4, 5, 6, 7
+KIND_SHIFT, KIND_EXACT = 11, 12
 UPDATE_ALL = 0xFE
 
 
@@ -242,7 +243,8 @@ def variant(mutant: int):
         slice_test=functools.partial(slice_test, _lib=L),
         philox=functools.partial(philox, _lib=L),
         KIND_EPS=KIND_EPS, KIND_GAMMA=KIND_GAMMA, KIND_NU=KIND_NU, KIND_TAU=KIND_TAU,
-        KIND_BETA=KIND_BETA, KIND_THETA=KIND_THETA, KIND_SIG2=KIND_SIG2, UPDATE_ALL=UPDATE_ALL)
+        KIND_BETA=KIND_BETA, KIND_THETA=KIND_THETA, KIND_SIG2=KIND_SIG2, KIND_SHIFT=KIND_SHIFT,
+        KIND_EXACT=KIND_EXACT, UPDATE_ALL=UPDATE_ALL)
 
 
 # ---------------------------------------------------------------------------

@@ -194,6 +194,79 @@ static double slice_draw(logf_fn f, const void *arg, double x0, double *w, doubl
 }
 
 /* ------------------------------------------------------------------ */
+/* Exact conjugate draws (bit OR_KIND_EXACT of update_mask)            */
+/* ------------------------------------------------------------------ */
+/* Section 4.2 slice-samples the gamma and inverse-gamma conditionals only
+ * because the paper's GPU library had no gamma generator, and names a
+ * gamma sampler as the alternative.  This option draws them directly:
+ *   gamma_g    = B / X,  X ~ Gamma(alpha),  alpha = nu/2 + N/2, B = nu tau/2 + S_g/2
+ *   tau        = X / R,  X ~ Gamma(alpha),  alpha = a + G nu/2, R = b + (nu/2) sum 1/gamma
+ *   sigma_l^2  = B / X,  X ~ Gamma(alpha),  alpha = (G-1)/2,    B = S_l/2,
+ *                kept only when below s_l^2 (the truncation of its prior).
+ * Gamma(alpha, 1) variates come from the method of Marsaglia and Tsang (ACM
+ * TOMS 26(3), 2000): for alpha >= 1 put d = alpha - 1/3, c = 1/sqrt(9 d); a
+ * standard normal x gives v = (1 + c x)^3, and d v is a variate when v > 0
+ * and log u < x^2/2 + d - d v + d log v for a uniform u.  For alpha < 1 the
+ * variate for alpha + 1 times U^(1/alpha) is one for alpha.
+ * Random numbers: Philox counter (g, 12 << 24 | sub, m, chain << 16 | t) for
+ * attempt t = 0, 1, ...: words 0 and 1 give x by Box-Muller, word 2 gives u,
+ * word 3 the U of alpha < 1; sub = 0 for gamma_g, 1 for tau, 2 + l for
+ * sigma_l^2.  An attempt fails when its candidate is rejected or falls outside
+ * the support.  After OR_EXACT_TRIES failed attempts, or when alpha <= 0, the
+ * parameter takes the slice draw of Algorithm 2 instead; whether that happens
+ * does not depend on the parameter's current value, so the update remains a
+ * mixture of two kernels that both leave the conditional invariant. */
+#define OR_EXACT_TRIES 64
+
+typedef struct {
+    double alpha;    /* shape of the gamma variate X */
+    double q;        /* B of an inverse gamma (value q / X) or R of a gamma (value X / q) */
+    int inverse;     /* 1: value q / X, 0: value X / q */
+    double upper;    /* values must lie below this bound (INFINITY: none) */
+} exact_arg;
+
+/* Returns the number of attempts used (1..OR_EXACT_TRIES) with *out set, or
+ * 0 when no attempt succeeded.  di->margin gets the smallest gap of any
+ * decision taken (the acceptance test in log space, the truncation on the
+ * log scale). */
+static int exact_draw(const exact_arg *e, uint64_t seed, uint32_t g, uint32_t sub, uint32_t m, uint32_t chain,
+                      double *out, draw_info *di)
+{
+    di->margin = INFINITY;
+    di->bad = 0;
+    if (!(e->alpha > 0.0)) return 0;
+    const int boost = e->alpha < 1.0;
+    const double ab = boost ? e->alpha + 1.0 : e->alpha;
+    const double d = (OR_MUTANT == 13 ? ab - 0.5 : ab - 1.0 / 3.0);
+    const double c = 1.0 / sqrt(9.0 * d);
+    const uint32_t key[2] = { (uint32_t)seed, (uint32_t)(seed >> 32) };
+    for (int t = 0; t < OR_EXACT_TRIES; ++t) {
+        const uint32_t ctr[4] = { g, ((uint32_t)OR_KIND_EXACT << 24) | sub, m, (chain << 16) | (uint32_t)t };
+        uint32_t r[4];
+        or_philox4x32_10(ctr, key, r);
+        const double x = sqrt(-2.0 * log(u01(r[0]))) * cos(2.0 * M_PI * u01(r[1]));
+        const double s = 1.0 + c * x;
+        if (!(s > 0.0)) continue;
+        const double v = s * s * s;
+        const double lu = log(u01(r[2]));
+        const double rhs = 0.5 * x * x + d - d * v + d * log(v);
+        note_margin(di, lu, rhs);
+        if (!(lu < rhs)) continue;
+        double X = d * v;
+        if (boost) X *= exp(log(u01(r[3])) / (OR_MUTANT == 14 ? ab : e->alpha));
+        const double val = e->inverse ? e->q / X : X / e->q;
+        if (!(val > 0.0) || !isfinite(val)) continue;
+        if (isfinite(e->upper)) {
+            note_margin(di, log(val), log(e->upper));
+            if (!(val < e->upper)) continue;
+        }
+        *out = val;
+        return t + 1;
+    }
+    return 0;
+}
+
+/* ------------------------------------------------------------------ */
 /* Context                                                             */
 /* ------------------------------------------------------------------ */
 struct or_ctx {
@@ -791,6 +864,18 @@ static int64_t sweep_once(or_ctx *c)
                           0.5 * c->nu * c->tau + 0.5 * S };
             rstream rs;
             draw_info di;
+            if (mask & (1u << OR_KIND_EXACT)) {
+                exact_arg e = { 0.5 * c->nu + 0.5 * N, (OR_MUTANT == 15 ? c->nu * c->tau : 0.5 * c->nu * c->tau) + 0.5 * S,
+                                1, INFINITY };
+                double v;
+                int t = exact_draw(&e, cf->seed, (uint32_t)g, 0, mm, (uint32_t)cf->chain, &v, &di);
+                if (t > 0) {
+                    c->gam[g] = v;
+                    di.kl = -1; di.nl = 0; di.nr = 0; di.nc = t;
+                    record(c, off_gam + g, &di);
+                    continue;
+                }
+            }
             rs_init(&rs, cf->seed, (uint32_t)g, OR_KIND_GAMMA, 0, mm, (uint32_t)cf->chain);
             c->gam[g] = slice_draw(logf_gam, &a, c->gam[g], &c->w_gam[g], &c->wa_gam[g], m,
                                    cf->burnin, cf->tune_start, cf->K, cf->shrink_cap, &rs, &di);
@@ -819,9 +904,21 @@ static int64_t sweep_once(or_ctx *c)
                       cf->b + (OR_MUTANT == 8 ? 1.0 : 0.5) * c->nu * sum_inv };
         rstream rs;
         draw_info di;
-        rs_init(&rs, cf->seed, 0, OR_KIND_TAU, 0, mm, (uint32_t)cf->chain);
-        c->tau = slice_draw(logf_tau, &a, c->tau, &c->w_tau, &c->wa_tau, m, cf->burnin,
-                            cf->tune_start, cf->K, cf->shrink_cap, &rs, &di);
+        int t = 0;
+        if (mask & (1u << OR_KIND_EXACT)) {
+            exact_arg e = { a.shape_m1 + 1.0, a.rate, 0, INFINITY };
+            double v;
+            t = exact_draw(&e, cf->seed, 0, 1, mm, (uint32_t)cf->chain, &v, &di);
+            if (t > 0) {
+                c->tau = v;
+                di.kl = -1; di.nl = 0; di.nr = 0; di.nc = t;
+            }
+        }
+        if (t == 0) {
+            rs_init(&rs, cf->seed, 0, OR_KIND_TAU, 0, mm, (uint32_t)cf->chain);
+            c->tau = slice_draw(logf_tau, &a, c->tau, &c->w_tau, &c->wa_tau, m, cf->burnin,
+                                cf->tune_start, cf->K, cf->shrink_cap, &rs, &di);
+        }
         record(c, off_beta + G * L + 1, &di);
         errs += di.bad;
     }
@@ -887,9 +984,22 @@ static int64_t sweep_once(or_ctx *c)
             sig_arg a = { 0.5 * ((double)G + (OR_MUTANT == 3 ? 2.0 : 1.0)), S, c->s[l] * c->s[l] };
             rstream rs;
             draw_info di;
-            rs_init(&rs, cf->seed, 0, OR_KIND_SIG2, (uint32_t)l, mm, (uint32_t)cf->chain);
-            c->sig2[l] = slice_draw(logf_sig2, &a, c->sig2[l], &c->w_sig2[l], &c->wa_sig2[l], m,
-                                    cf->burnin, cf->tune_start, cf->K, cf->shrink_cap, &rs, &di);
+            int t = 0;
+            if (mask & (1u << OR_KIND_EXACT)) {
+                exact_arg e = { 0.5 * ((double)G - 1.0), 0.5 * S, 1,
+                                OR_MUTANT == 16 ? INFINITY : c->s[l] * c->s[l] };
+                double v;
+                t = exact_draw(&e, cf->seed, 0, 2u + (uint32_t)l, mm, (uint32_t)cf->chain, &v, &di);
+                if (t > 0) {
+                    c->sig2[l] = v;
+                    di.kl = -1; di.nl = 0; di.nr = 0; di.nc = t;
+                }
+            }
+            if (t == 0) {
+                rs_init(&rs, cf->seed, 0, OR_KIND_SIG2, (uint32_t)l, mm, (uint32_t)cf->chain);
+                c->sig2[l] = slice_draw(logf_sig2, &a, c->sig2[l], &c->w_sig2[l], &c->wa_sig2[l], m,
+                                        cf->burnin, cf->tune_start, cf->K, cf->shrink_cap, &rs, &di);
+            }
             record(c, off_beta + G * L + 2 + l, &di);
             errs += di.bad;
         }

@@ -36,11 +36,14 @@ extern "C" {
 enum {
     OR_KIND_EPS = 1, OR_KIND_GAMMA = 2, OR_KIND_NU = 3, OR_KIND_TAU = 4,
     OR_KIND_BETA = 5, OR_KIND_THETA = 6, OR_KIND_SIG2 = 7, OR_KIND_IMH = 8,
-    OR_KIND_INIT = 9, OR_KIND_TEST = 10, OR_KIND_SHIFT = 11
+    OR_KIND_INIT = 9, OR_KIND_TEST = 10, OR_KIND_SHIFT = 11, OR_KIND_EXACT = 12
 };
 
 /* bit (1 << kind) of update_mask enables that Gibbs step; the shift step
- * (kind 11) is an addition to Algorithm 1 and is not in OR_UPDATE_ALL */
+ * (kind 11) is an addition to Algorithm 1 and is not in OR_UPDATE_ALL.  Bit
+ * OR_KIND_EXACT (also not in OR_UPDATE_ALL) replaces the slice draws of
+ * gamma_g, tau and sigma_l^2 by direct draws from their conjugate full
+ * conditionals (Section 4.2 names this alternative); see oracle.c. */
 #define OR_UPDATE_ALL 0xFEu
 
 typedef struct {

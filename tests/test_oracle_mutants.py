@@ -6,6 +6,7 @@ from tests import test_oracle_mlp as M
 from tests import test_oracle_pins as P
 from tests import test_oracle_shift as S
 from tests import test_oracle_events as E
+from tests import test_oracle_exact as X
 
 MUTANTS = [
     # (switch, what is wrong, the pin that must fail)
@@ -30,6 +31,14 @@ MUTANTS = [
      lambda o: S.test_shift_draws_the_conditional(o, "two_group")),
     (12, "contrast event as 'any row' instead of 'all rows'",
      lambda o: E.test_event_counts_match_a_recount(o)),
+    (13, "Marsaglia-Tsang constant d = alpha - 1/2 instead of alpha - 1/3",
+     lambda o: X.test_exact_gamma_conditional(o)),
+    (14, "shape-below-one exponent 1/(alpha + 1) instead of 1/alpha",
+     lambda o: X.test_exact_gamma_shape_below_one(o)),
+    (15, "exact gamma_g draw with scale nu tau + S/2 instead of nu tau/2 + S/2",
+     lambda o: X.test_exact_gamma_conditional(o)),
+    (16, "exact sigma^2 draw ignores the truncation at s_l^2",
+     lambda o: X.test_exact_sigma2_falls_back_to_slice(o)),
 ]
 
 

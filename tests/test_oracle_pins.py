@@ -171,9 +171,9 @@ def test_eps_conditional(oracle_lib):
     _ks_uniform(np.concatenate(us), "eps")
 
 
-def test_gamma_conditional(oracle_lib):
+def test_gamma_conditional(oracle_lib, extra_mask=0):
     ds = _small(6000)
-    o = oracle_lib.Oracle(ds.y, ds.X, ds.h, seed=22, update_mask=1 << oracle_lib.KIND_GAMMA)
+    o = oracle_lib.Oracle(ds.y, ds.X, ds.h, seed=22, update_mask=(1 << oracle_lib.KIND_GAMMA) | extra_mask)
     s = o.get_state()
     nu, tau = 3.7, 0.08
     s["eps"] = ds.eps.copy()
@@ -235,10 +235,10 @@ def test_nu_conditional(oracle_lib):
     _ks_uniform(u, "nu")
 
 
-def test_tau_conditional(oracle_lib):
+def test_tau_conditional(oracle_lib, extra_mask=0):
     ds = _small(400)
     a, b = 2.0, 3.0
-    o = oracle_lib.Oracle(ds.y, ds.X, ds.h, seed=24, a=a, b=b, update_mask=1 << oracle_lib.KIND_TAU)
+    o = oracle_lib.Oracle(ds.y, ds.X, ds.h, seed=24, a=a, b=b, update_mask=(1 << oracle_lib.KIND_TAU) | extra_mask)
     s = o.get_state()
     nu = 4.2
     s["gam"] = ds.gamma.copy()
@@ -279,12 +279,12 @@ def test_theta_conditional(oracle_lib):
 
 
 @pytest.mark.parametrize("upper,G", [(100.0, 6), (100.0, 300), (0.58, 300)])
-def test_sigma2_conditional(oracle_lib, upper, G):
+def test_sigma2_conditional(oracle_lib, upper, G, extra_mask=0):
     # small G makes the Jacobian of the uniform prior on sigma visible
     ds = _small(G)
     L = ds.L
     s_l = np.full(L, upper)
-    o = oracle_lib.Oracle(ds.y, ds.X, ds.h, seed=26, s=s_l, update_mask=1 << oracle_lib.KIND_SIG2)
+    o = oracle_lib.Oracle(ds.y, ds.X, ds.h, seed=26, s=s_l, update_mask=(1 << oracle_lib.KIND_SIG2) | extra_mask)
     s = o.get_state()
     s["beta"] = ds.beta.copy()
     theta = ds.beta.mean(0) + np.array([0.1, -0.05])
