@@ -67,7 +67,7 @@ enum fb_precision {
 enum fb_kind {     /* Philox counter kinds, also bit positions of update_mask */
     FB_KIND_EPS = 1, FB_KIND_GAMMA = 2, FB_KIND_NU = 3, FB_KIND_TAU = 4,
     FB_KIND_BETA = 5, FB_KIND_THETA = 6, FB_KIND_SIG2 = 7, FB_KIND_IMH = 8,
-    FB_KIND_SHIFT = 11
+    FB_KIND_SHIFT = 11, FB_KIND_EXACT = 12
 };
 /* The steps of Algorithm 1.  The shift step (bit 1 << FB_KIND_SHIFT) is an
  * addition that is off unless asked for: after steps 2 and 5 it moves every
@@ -80,7 +80,22 @@ enum fb_kind {     /* Philox counter kinds, also bit positions of update_mask */
  * Philox counter (g, 11 << 24, m, chain << 16 | j); Box-Muller pairs on words
  * (2p, 2p + 1).  It leaves the posterior invariant and removes the slow
  * exchange between eps_g and beta_g that the one-at-a-time conditionals have
- * when the counts pin their sum. */
+ * when the counts pin their sum.
+ *
+ * Exact conjugate draws (bit 1 << FB_KIND_EXACT, off unless asked for):
+ * Section 4.2 slice-samples the gamma and inverse-gamma full conditionals and
+ * names a gamma sampler as the alternative.  With this bit, gamma_g ~
+ * IG(nu/2 + N/2, nu tau/2 + S_g/2), tau ~ Gamma(a + G nu/2, rate b + (nu/2)
+ * sum 1/gamma) and sigma_l^2 ~ IG((G-1)/2, S_l/2) truncated to (0, s_l^2)
+ * are drawn directly (each only when its own bit is set) from Gamma variates
+ * by the method of Marsaglia and Tsang (ACM TOMS 26(3), 2000), in FP64 in
+ * both precision modes.  Attempt k of a draw reads Philox block (g, 12 << 24
+ * | sub, m, chain << 16 | k), sub = 0 for gamma_g, 1 for tau, 2 + l for
+ * sigma_l^2: words 0 and 1 give the normal (Box-Muller), word 2 the
+ * acceptance uniform, word 3 the U^(1/alpha) factor used when the shape is
+ * below 1.  After 64 failed attempts (or a shape <= 0, e.g. sigma^2 with
+ * G = 1) the parameter takes its slice step.  fb_debug_counts records an
+ * exact draw as (K_L, left, right, candidates) = (-1, 0, 0, attempts). */
 #define FB_UPDATE_ALL 0xFEu
 
 /* Prior constants of Section 4.1: tau ~ Gamma(a, rate b), nu ~ U(0, d),

@@ -29,6 +29,8 @@
 #include "fbmc_mlp.hpp"
 #include "fbmc_types.hpp"
 
+static_assert(fbmc::kKindExact == (int)fbmc::kKindExactDraw, "one kind for the exact draws");
+
 namespace fbmc {
 
 // ---------------------------------------------------------------------------
@@ -752,20 +754,34 @@ __device__ inline void gamma_wave(const SegInfo &S, int tile, const SweepArgs &a
             T wag = tuning ? ((T *)S.wa_gam)[g] : (T)0;
             const double alpha1 = 0.5 * nu + 0.5 * N + 1.0;
             const double scale = 0.5 * nu * tau + 0.5 * (double)S2;
-            GamF<T> f{(T)alpha1, (T)scale, gam};
-            DrawRec rec;
-            const T g1 = slice_draw<T>(f, gam, wg, S.key0, S.key1,
-                                       draw_counter((uint32_t)g, 2, 0, (uint32_t)a.m, (uint32_t)S.chain, 0), a.K,
-                                       a.cap, rec);
-            if (tuning) {
-                tune_width<T>(wg, wag, gam, g1, a.m, a.burnin, a.tune_start);
-                ((T *)S.w_gam)[g] = wg;
-                ((T *)S.wa_gam)[g] = wag;
+            int tries = 0;
+            if ((a.mask >> kKindExact) & 1u) {
+                // exact draw: gamma_g = (nu tau/2 + S_g/2) / X, X ~ Gamma(nu/2 + N/2)
+                double v = 0.0;
+                tries = exact_gamma_draw(0.5 * nu + 0.5 * N, scale, true, __builtin_inf(), S.key0, S.key1,
+                                         (uint32_t)g, 0, (uint32_t)a.m, (uint32_t)S.chain, v);
+                if (tries > 0) {
+                    gam = (T)v;
+                    gamp[g] = gam;
+                    if (a.dbg) S.dbg_gam[g] = make_int4(-1, 0, 0, tries);
+                }
             }
-            gam = g1;
-            gamp[g] = g1;
-            bad |= rec.bad;
-            if (a.dbg) S.dbg_gam[g] = make_int4(rec.kl, rec.nl, rec.nr, rec.nc);
+            if (tries == 0) {
+                GamF<T> f{(T)alpha1, (T)scale, gam};
+                DrawRec rec;
+                const T g1 = slice_draw<T>(f, gam, wg, S.key0, S.key1,
+                                           draw_counter((uint32_t)g, 2, 0, (uint32_t)a.m, (uint32_t)S.chain, 0),
+                                           a.K, a.cap, rec);
+                if (tuning) {
+                    tune_width<T>(wg, wag, gam, g1, a.m, a.burnin, a.tune_start);
+                    ((T *)S.w_gam)[g] = wg;
+                    ((T *)S.wa_gam)[g] = wag;
+                }
+                gam = g1;
+                gamp[g] = g1;
+                bad |= rec.bad;
+                if (a.dbg) S.dbg_gam[g] = make_int4(rec.kl, rec.nl, rec.nr, rec.nc);
+            }
         }
         if (sampling) {
             double2 mog = S.mom_gam[g];
@@ -1583,6 +1599,7 @@ __device__ inline void hyper_block(const SegInfo &S, const SweepArgs &a, int *er
     const uint32_t mm = (uint32_t)a.m;
     const uint32_t chain = (uint32_t)S.chain;
     const bool sampling = a.m > a.burnin;
+    const bool exact = (a.mask >> kKindExact) & 1u;
     const bool w0 = lane == 0;
     float *trow = a.trace_point >= 0 ? S.trace + (int64_t)a.trace_point * S.trace_stride : nullptr;
     double *wd = &words[wave][0];
@@ -1605,14 +1622,28 @@ __device__ inline void hyper_block(const SegInfo &S, const SweepArgs &a, int *er
         // step 4: tau
         if ((a.mask >> 4) & 1u) {
             TauF f{S.a + 0.5 * G * nu - 1.0, S.b + 0.5 * nu * red[1]};
-            double w = H.w_tau, wa = H.wa_tau;
-            const double x1 = slice_draw_wave(f, tau, w, k0, k1, draw_counter(0, 4, 0, mm, chain, 0), a.K, a.cap,
-                                              rec, wd);
-            tune_width<double>(w, wa, tau, x1, a.m, a.burnin, a.tune_start);
-            tau = x1;
-            if (w0) { H.tau = x1; H.w_tau = w; H.wa_tau = wa; }
-            bad |= rec.bad;
-            if (a.dbg && w0) H.dbg[1] = make_int4(rec.kl, rec.nl, rec.nr, rec.nc);
+            int tries = 0;
+            if (exact) {
+                // exact draw, the same on every lane: tau = X / rate, X ~ Gamma(a + G nu / 2)
+                double v = 0.0;
+                tries = exact_gamma_draw(f.shape_m1 + 1.0, f.rate, false, __builtin_inf(), k0, k1, 0, 1, mm, chain,
+                                         v);
+                if (tries > 0) {
+                    tau = v;
+                    if (w0) H.tau = v;
+                    if (a.dbg && w0) H.dbg[1] = make_int4(-1, 0, 0, tries);
+                }
+            }
+            if (tries == 0) {
+                double w = H.w_tau, wa = H.wa_tau;
+                const double x1 = slice_draw_wave(f, tau, w, k0, k1, draw_counter(0, 4, 0, mm, chain, 0), a.K,
+                                                  a.cap, rec, wd);
+                tune_width<double>(w, wa, tau, x1, a.m, a.burnin, a.tune_start);
+                tau = x1;
+                if (w0) { H.tau = x1; H.w_tau = w; H.wa_tau = wa; }
+                bad |= rec.bad;
+                if (a.dbg && w0) H.dbg[1] = make_int4(rec.kl, rec.nl, rec.nr, rec.nc);
+            }
         }
         if (w0) {
             H.red[0] = red[0];
@@ -1646,12 +1677,21 @@ __device__ inline void hyper_block(const SegInfo &S, const SweepArgs &a, int *er
             double w = H.w_sig2[l], wa = H.wa_sig2[l];
             if ((a.mask >> 7) & 1u) {
                 const double sl = S.s[l];
-                Sig2F f{0.5 * (G + 1.0), Ssq, sl * sl};
-                s2new = slice_draw_wave(f, sig2, w, k0, k1, draw_counter(0, 7, (uint32_t)l, mm, chain, 0), a.K,
-                                        a.cap, rec, wd);
-                tune_width<double>(w, wa, sig2, s2new, a.m, a.burnin, a.tune_start);
-                bad |= rec.bad;
-                if (a.dbg && w0) H.dbg[2 + l] = make_int4(rec.kl, rec.nl, rec.nr, rec.nc);
+                int tries = 0;
+                if (exact) {
+                    // exact draw: sigma^2 = (S/2) / X, X ~ Gamma((G - 1)/2), kept below s_l^2
+                    tries = exact_gamma_draw(0.5 * (G - 1.0), 0.5 * Ssq, true, sl * sl, k0, k1, 0, 2u + (uint32_t)l,
+                                             mm, chain, s2new);
+                    if (tries > 0 && a.dbg && w0) H.dbg[2 + l] = make_int4(-1, 0, 0, tries);
+                }
+                if (tries == 0) {
+                    Sig2F f{0.5 * (G + 1.0), Ssq, sl * sl};
+                    s2new = slice_draw_wave(f, sig2, w, k0, k1, draw_counter(0, 7, (uint32_t)l, mm, chain, 0),
+                                            a.K, a.cap, rec, wd);
+                    tune_width<double>(w, wa, sig2, s2new, a.m, a.burnin, a.tune_start);
+                    bad |= rec.bad;
+                    if (a.dbg && w0) H.dbg[2 + l] = make_int4(rec.kl, rec.nl, rec.nr, rec.nc);
+                }
             }
             if (w0) {
                 H.theta[l] = th;

@@ -13,6 +13,7 @@ constexpr int kMaxVals = 4;    // distinct non-zero values per column
 constexpr int kTile = 64;      // genes per wavefront tile
 constexpr int kMaxParts = 2 + 2 * kMaxL;
 constexpr int kKindShift = 11;  // Philox kind and update_mask bit of the shift step
+constexpr int kKindExact = 12;  // update_mask bit of the exact conjugate draws (gamma, tau, sigma^2)
 constexpr int kMaxEv = 8;       // contrast events per context
 constexpr int kMaxCtr = 16;     // contrast rows (inequalities) over all events
 

@@ -21,6 +21,8 @@ FB_KIND_EPS, FB_KIND_GAMMA, FB_KIND_NU, FB_KIND_TAU = 1, 2, 3, 4
 FB_KIND_BETA, FB_KIND_THETA, FB_KIND_SIG2, FB_KIND_IMH = 5, 6, 7, 8
 FB_KIND_SHIFT = 11
 FB_SHIFT = 1 << FB_KIND_SHIFT     # update_mask bit of the shift step (off by default)
+FB_KIND_EXACT = 12
+FB_EXACT = 1 << FB_KIND_EXACT     # update_mask bit of the exact conjugate draws (off by default)
 FB_UPDATE_ALL = 0xFE
 FB_MAX_N, FB_MAX_L, FB_MAX_ROWS, FB_MAX_COLVALS = 64, 8, 8, 4
 

@@ -141,11 +141,14 @@ def test_shrink_cap_is_reported_and_matches(oracle_lib):
     F.fb_destroy(g)
 
 
-def _fp32_resync(oracle_lib, ds, *, seed, n_sweeps, warm, threads=1, label=""):
+def _fp32_resync(oracle_lib, ds, *, seed, n_sweeps, warm, threads=1, label="", update_mask=None):
     F = require_gpu()
-    opts = F.fb_default_options(burnin=warm // 2, tune_start=2, precision=1, debug_counts=1, jitter=0)
+    mask = F.FB_UPDATE_ALL if update_mask is None else update_mask
+    opts = F.fb_default_options(burnin=warm // 2, tune_start=2, precision=1, debug_counts=1, jitter=0,
+                                update_mask=mask)
     g = F.fb_create(ds.y, ds.X, ds.h, seed=seed, options=opts)
-    o = oracle_lib.Oracle(ds.y, ds.X, ds.h, seed=seed, burnin=warm // 2, tune_start=2, threads=threads)
+    o = oracle_lib.Oracle(ds.y, ds.X, ds.h, seed=seed, burnin=warm // 2, tune_start=2, threads=threads,
+                          update_mask=mask)
     o.sweep(warm)
     G, N, L = ds.G, ds.N, ds.L
     n_genes_flip = 0
