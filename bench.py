@@ -105,11 +105,12 @@ def cpu_baseline(ds, seconds: float = 15.0):
                        f"(FP64, OpenMP over genes, {dt:.1f} s)")
 
 
-def run_chain(fbmc, diagnostics, ds, args, burnin, post, do_ess, stream, learned, shift=False):
+def run_chain(fbmc, diagnostics, ds, args, burnin, post, do_ess, stream, learned, shift=False, exact=False):
     """One chain of the workload: `burnin` sweeps, then `post` post-burn-in
     sweeps of which `steps` (after `warmup`) are timed.  shift=True adds the
     shift step (beta_g + delta, eps_g - X delta, delta from its exact
-    conditional) to every sweep.  With learned=True the
+    conditional) to every sweep; exact=True draws gamma_g, tau and sigma^2
+    directly from their conjugate conditionals.  With learned=True the
     last 1,000 burn-in sweeps adapt the learned beta proposal: 400 plain sweeps
     store training pairs (every 4th sweep, 100 x G pairs), the network is
     trained on the GPU, 200 sweeps with the IMH step everywhere calibrate the
@@ -120,7 +121,7 @@ def run_chain(fbmc, diagnostics, ds, args, burnin, post, do_ess, stream, learned
         burnin=burnin, tune_start=burnin // 10, precision=fbmc.FB_FP32, jitter=0,
         thin=1 if do_ess else 0, trace_genes=TRACE_GENES if do_ess else 0,
         trace_after_burnin=1, trace_capacity=post if do_ess else 0,
-        update_mask=fbmc.FB_UPDATE_ALL | (fbmc.FB_SHIFT if shift else 0),
+        update_mask=fbmc.FB_UPDATE_ALL | (fbmc.FB_SHIFT if shift else 0) | (fbmc.FB_EXACT if exact else 0),
         stream=stream.cuda_stream)
     smp = fbmc.Sampler(ds.y, ds.X, ds.h, seed=1, **{k: getattr(opts, k) for k, *_ in opts._fields_})
     proposal = None
@@ -185,12 +186,15 @@ def run_chain(fbmc, diagnostics, ds, args, burnin, post, do_ess, stream, learned
         genes = tr[:, 2 + 2 * L:].reshape(tr.shape[0], T, L + 1)[:, :, 1:]   # beta [M, T, L]
         series = genes.reshape(tr.shape[0], -1).T.astype(np.float64)          # [T*L, M]
         ess = diagnostics.ess_batch(series)
+        hyp_ess = diagnostics.ess_batch(tr[:, :2 + 2 * L].T.astype(np.float64))
+        hyp_names = ["nu", "tau"] + [f"theta{l + 1}" for l in range(L)] + [f"sigma2_{l + 1}" for l in range(L)]
         post_time = t_post1 - t_post0
         ess_info = dict(min_ess=float(np.nanmin(ess)), median_ess=float(np.nanmedian(ess)),
                         post_burnin_sweeps=int(tr.shape[0]), post_burnin_seconds=post_time,
                         min_ess_per_s=float(np.nanmin(ess)) / post_time,
                         median_ess_per_s=float(np.nanmedian(ess)) / post_time,
-                        traced=f"{T} genes x {L} coefficients", dropped=dropped)
+                        traced=f"{T} genes x {L} coefficients", dropped=dropped,
+                        hyper_ess={k: float(v) for k, v in zip(hyp_names, hyp_ess)})
     smp.close()
     return dict(sweeps_per_s=args.steps / (t1 - t0), ms_per_sweep=(t1 - t0) * 1e3 / args.steps,
                 kernel_ms=kt, launch=shape, ess=ess_info, proposal=proposal)
@@ -307,6 +311,8 @@ def main():
     ap.add_argument("--no-ess", action="store_true")
     ap.add_argument("--no-learned", action="store_true", help="skip the learned-proposal chains")
     ap.add_argument("--no-shift", action="store_true", help="skip the chains with the shift step")
+    ap.add_argument("--no-exact", action="store_true",
+                    help="skip the chains with exact conjugate draws of gamma, tau and sigma^2")
     ap.add_argument("--no-heavy", action="store_true",
                     help="skip the secondary heavy workload (4 chains x G=200k x N=48)")
     ap.add_argument("--heavy-only", action="store_true",
@@ -348,12 +354,14 @@ def main():
         print(json.dumps({"heavy_workload": run_heavy(fbmc, stream, steps=args.steps, burnin=args.burnin)}),
               flush=True)
         return
-    run = lambda learned, shift: run_chain(fbmc, diagnostics, ds, args, burnin, post, do_ess, stream,
-                                           learned=learned, shift=shift)
+    run = lambda learned, shift, exact=False: run_chain(fbmc, diagnostics, ds, args, burnin, post, do_ess,
+                                                        stream, learned=learned, shift=shift, exact=exact)
     plain = run(False, False)
     learned = None if args.no_learned else run(True, False)
     plain_shift = None if args.no_shift else run(False, True)
     learned_shift = None if (args.no_shift or args.no_learned) else run(True, True)
+    plain_exact = None if args.no_exact else run(False, False, True)
+    plain_shift_exact = None if (args.no_exact or args.no_shift) else run(False, True, True)
     sweeps_per_s = plain["sweeps_per_s"]
     ms_per_step = plain["ms_per_sweep"]
     shape = plain["launch"]
@@ -389,7 +397,8 @@ def main():
 
     learned_info = form(learned, plain)
     forms = {"plain": form(plain, None), "learned": learned_info,
-             "plain+shift": form(plain_shift, plain), "learned+shift": form(learned_shift, plain_shift)}
+             "plain+shift": form(plain_shift, plain), "learned+shift": form(learned_shift, plain_shift),
+             "plain+exact": form(plain_exact, plain), "plain+shift+exact": form(plain_shift_exact, plain_shift)}
 
     line = {
         "metric": "Gibbs sweeps/s + min-ESS/s of beta at G=50k,N=16; learned vs plain proposal",
@@ -411,7 +420,8 @@ def main():
         "min_ess_per_s": None if ess_info is None else ess_info["min_ess_per_s"],
         "ess": ess_info,
         "learned_proposal": learned_info,
-        "forms": {"note": "ratios: learned vs plain; plain+shift vs plain; learned+shift vs plain+shift",
+        "forms": {"note": "ratios: learned vs plain; plain+shift vs plain; learned+shift vs plain+shift; "
+                          "plain+exact vs plain; plain+shift+exact vs plain+shift",
                   **forms},
         "kernels": kernels,
         "roofline": {"bound": "hbm", "kernel": dom, "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
