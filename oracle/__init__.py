@@ -87,6 +87,9 @@ def lib(path: str | None = None):
         L.or_philox4x32_10.restype = None
         L.or_slice_test.argtypes = [C.c_int32, dp, dp, dp, C.c_int64, C.c_double, C.c_int32,
                                     C.c_uint64, C.c_uint32, ip]
+        L.or_set_top_priors.argtypes = [C.c_void_p, C.c_double, dp]
+        L.or_top_draw.argtypes = [C.c_int32, C.c_int32, dp, dp, dp, dp, C.c_double, C.c_double, dp,
+                                  C.c_uint64, C.c_int32, C.c_int64, C.c_uint32, dp, dp, ip]
         _libs[path] = L
     return _libs[path]
 
@@ -133,6 +136,7 @@ class Oracle:
         self.G, self.N = self.y.shape
         self.L = self.X.shape[1]
         L = self.L
+        self.a = float(a)
         self.c = np.ascontiguousarray(np.full(L, 10.0) if c is None else c, dtype=np.float64)
         self.s = np.ascontiguousarray(np.full(L, 100.0) if s is None else s, dtype=np.float64)
         cfg = _Cfg(self.G, self.N, L, _p(self.y, C.c_int32), _p(self.X), _p(self.h),
@@ -168,6 +172,12 @@ class Oracle:
 
     def set_update_mask(self, mask: int):
         self._L.or_set_update_mask(self._h, mask)
+
+    def set_top_priors(self, b: float, theta_mean):
+        """Rate b of tau's Gamma prior and prior means of theta (three-level form)."""
+        tm = np.ascontiguousarray(theta_mean, dtype=np.float64)
+        if self._L.or_set_top_priors(self._h, float(b), _p(tm)) != 0:
+            raise ValueError("or_set_top_priors failed")
 
     def sweep(self, n: int = 1) -> int:
         return self._L.or_sweep(self._h, int(n))
@@ -233,6 +243,80 @@ class Oracle:
         return out
 
 
+class ThreeLevel:
+    """Three-level form of Section 2.3: K group oracles (each a copy of the model
+    of Section 4.1 with its own hyperparameters phi_k, its own seed and data)
+    tied by psi = (b, psi_1..psi_L): tau_k ~ Gamma(a_k, rate b), theta_kl ~
+    N(psi_l, c_kl^2), b ~ Gamma(a_b, rate b_b), psi_l ~ N(0, c0_l^2).
+
+    The sampler alternates (mu, psi) | phi and phi | mu, psi.  Given phi the
+    genes mu and psi are independent, so sweep m first draws psi(m) from the
+    groups' phi(m - 1) (or_top_draw), then runs every group's sweep with its
+    priors set from psi(m).  Moments of (b, psi) after burn-in as for every
+    other parameter."""
+
+    def __init__(self, groups, *, a_b=1.0, b_b=1.0, c0=None, seed=1, chain=0, burnin=0, b=None, psi=None,
+                 top_mask=3, _lib=None):
+        self._L = _lib or lib()
+        self.groups = list(groups)
+        self.K = len(self.groups)
+        L = self.groups[0].L
+        if any(g.L != L for g in self.groups):
+            raise ValueError("every group needs the same coefficients")
+        self.L = L
+        self.a_b, self.b_b = float(a_b), float(b_b)
+        self.c0 = np.ascontiguousarray(np.full(L, 10.0) if c0 is None else c0, dtype=np.float64)
+        self.seed, self.chain, self.burnin, self.top_mask = int(seed), int(chain), int(burnin), int(top_mask)
+        self.a = np.ascontiguousarray([g.a for g in self.groups], dtype=np.float64)
+        self.c = np.ascontiguousarray(np.stack([g.c for g in self.groups]), dtype=np.float64)
+        self.b = float(1.0 if b is None else b)
+        self.psi = np.ascontiguousarray(np.zeros(L) if psi is None else psi, dtype=np.float64)
+        self.m = self.groups[0].get_state()["m"]
+        self.mean = np.zeros(1 + L)
+        self.msq = np.zeros(1 + L)
+        self.count = 0
+        self.tries = 0
+        for g in self.groups:
+            g.set_top_priors(self.b, self.psi)
+
+    def set_top(self, b, psi, m=None):
+        self.b = float(b)
+        self.psi = np.ascontiguousarray(psi, dtype=np.float64)
+        if m is not None:
+            self.m = int(m)
+        for g in self.groups:
+            g.set_top_priors(self.b, self.psi)
+
+    def sweep(self, n: int = 1) -> int:
+        errs = 0
+        L = self.L
+        for _ in range(int(n)):
+            m = self.m + 1
+            hyp = np.stack([g.get_state()["hyp"] for g in self.groups])
+            theta = np.ascontiguousarray(hyp[:, 2:2 + L])
+            tau = np.ascontiguousarray(hyp[:, 1])
+            b = C.c_double(self.b)
+            psi = self.psi.copy()
+            tries = C.c_int32()
+            rc = self._L.or_top_draw(self.K, L, _p(theta), _p(tau), _p(self.a), _p(self.c), self.a_b, self.b_b,
+                                     _p(self.c0), self.seed, self.chain, m, self.top_mask, C.byref(b), _p(psi),
+                                     C.byref(tries))
+            if rc != 0:
+                raise ValueError("or_top_draw failed")
+            self.b, self.psi, self.tries = b.value, psi, int(tries.value)
+            for g in self.groups:
+                g.set_top_priors(self.b, self.psi)
+                errs += g.sweep(1)
+            self.m = m
+            if m > self.burnin:
+                k = m - self.burnin
+                x = np.concatenate([[self.b], self.psi])
+                self.mean += (x - self.mean) / k
+                self.msq += (x * x - self.msq) / k
+                self.count = k
+        return errs
+
+
 def variant(mutant: int):
     """A namespace like this module whose calls go to mutant library `mutant`."""
     import functools
@@ -244,7 +328,7 @@ def variant(mutant: int):
         philox=functools.partial(philox, _lib=L),
         KIND_EPS=KIND_EPS, KIND_GAMMA=KIND_GAMMA, KIND_NU=KIND_NU, KIND_TAU=KIND_TAU,
         KIND_BETA=KIND_BETA, KIND_THETA=KIND_THETA, KIND_SIG2=KIND_SIG2, KIND_SHIFT=KIND_SHIFT,
-        KIND_EXACT=KIND_EXACT, UPDATE_ALL=UPDATE_ALL)
+        KIND_EXACT=KIND_EXACT, UPDATE_ALL=UPDATE_ALL, ThreeLevel=functools.partial(ThreeLevel, _lib=L))
 
 
 # ---------------------------------------------------------------------------

@@ -229,8 +229,8 @@ typedef struct {
  * 0 when no attempt succeeded.  di->margin gets the smallest gap of any
  * decision taken (the acceptance test in log space, the truncation on the
  * log scale). */
-static int exact_draw(const exact_arg *e, uint64_t seed, uint32_t g, uint32_t sub, uint32_t m, uint32_t chain,
-                      double *out, draw_info *di)
+static int exact_draw(const exact_arg *e, uint64_t seed, uint32_t kind, uint32_t g, uint32_t sub, uint32_t m,
+                      uint32_t chain, double *out, draw_info *di)
 {
     di->margin = INFINITY;
     di->bad = 0;
@@ -241,7 +241,7 @@ static int exact_draw(const exact_arg *e, uint64_t seed, uint32_t g, uint32_t su
     const double c = 1.0 / sqrt(9.0 * d);
     const uint32_t key[2] = { (uint32_t)seed, (uint32_t)(seed >> 32) };
     for (int t = 0; t < OR_EXACT_TRIES; ++t) {
-        const uint32_t ctr[4] = { g, ((uint32_t)OR_KIND_EXACT << 24) | sub, m, (chain << 16) | (uint32_t)t };
+        const uint32_t ctr[4] = { g, (kind << 24) | sub, m, (chain << 16) | (uint32_t)t };
         uint32_t r[4];
         or_philox4x32_10(ctr, key, r);
         const double x = sqrt(-2.0 * log(u01(r[0]))) * cos(2.0 * M_PI * u01(r[1]));
@@ -307,6 +307,8 @@ struct or_ctx {
     double *cv, *cb;
     int64_t *ev_count;
     int64_t ev_from;
+    /* prior mean of theta_l (0 unless a three-level driver sets it) */
+    double theta_mean[64];
 };
 
 static int64_t n_params(const or_ctx *c)
@@ -411,6 +413,68 @@ int or_set_counts(or_ctx *c, const int32_t *y)
 }
 
 int or_set_update_mask(or_ctx *c, uint32_t mask) { if (!c) return -1; c->cfg.update_mask = mask; return 0; }
+
+int or_set_top_priors(or_ctx *c, double b, const double *theta_mean)
+{
+    if (!c || !(b > 0.0) || !theta_mean) return -1;
+    c->cfg.b = b;
+    for (int l = 0; l < c->cfg.L; ++l) c->theta_mean[l] = theta_mean[l];
+    return 0;
+}
+
+/* ------------------------------------------------------------------ */
+/* Three-level form (Section 2.3): the top-level draws                 */
+/* ------------------------------------------------------------------ */
+/* Groups k = 1..K are copies of the model of Section 4.1 with their own
+ * hyperparameters phi_k = (nu_k, tau_k, theta_k, sigma_k^2), tied through
+ * psi = (b, psi_1..psi_L):  tau_k ~ Gamma(a_k, rate b), theta_kl ~ N(psi_l,
+ * c_kl^2), with b ~ Gamma(a_b, rate b_b) and psi_l ~ N(0, c0_l^2).  Given phi
+ * the top level is independent of the genes, and its full conditionals are
+ * conjugate (a reduction over the groups each):
+ *   b     ~ Gamma(a_b + sum_k a_k, rate b_b + sum_k tau_k)
+ *   psi_l ~ N(v_l sum_k theta_kl / c_kl^2, v_l),  v_l = 1 / (1/c0_l^2 + sum_k 1/c_kl^2)
+ * Random numbers: Philox counter (0, 13 << 24 | sub, m, chain << 16 | j);
+ * psi_l: sub = l, block 0, Box-Muller on words 0 and 1; b: sub = 128, the
+ * gamma variate of exact_draw (attempt j in block j); if every attempt fails
+ * b keeps its value (a state-independent identity step).  mask bit 0 draws
+ * b, bit 1 the psi_l.  Sums run over k in order. */
+int or_top_draw(int32_t K, int32_t L, const double *theta, const double *tau, const double *a, const double *c,
+                double a_b, double b_b, const double *c0, uint64_t seed, int32_t chain, int64_t m, uint32_t mask,
+                double *b, double *psi, int32_t *tries)
+{
+    if (K < 1 || L < 1 || L > 64 || !theta || !tau || !a || !c || !c0 || !b || !psi) return -1;
+    const uint32_t mm = (uint32_t)m;
+    if (tries) *tries = 0;
+    if (mask & 1u) {
+        double sa = 0.0, st = 0.0;
+        for (int k = 0; k < K; ++k) { sa += a[k]; st += tau[k]; }
+        exact_arg e = { a_b + sa, OR_MUTANT == 18 ? st : b_b + st, 0, INFINITY };
+        draw_info di;
+        double v;
+        int t = exact_draw(&e, seed, OR_KIND_TOP, 0, 128u, mm, (uint32_t)chain, &v, &di);
+        if (t > 0) *b = v;
+        if (tries) *tries = t;
+    }
+    if (mask & 2u) {
+        const uint32_t key[2] = { (uint32_t)seed, (uint32_t)(seed >> 32) };
+        for (int l = 0; l < L; ++l) {
+            double prec = OR_MUTANT == 17 ? 0.0 : 1.0 / (c0[l] * c0[l]);
+            double sw = 0.0;
+            for (int k = 0; k < K; ++k) {
+                const double ckl = c[k * L + l];
+                prec += 1.0 / (ckl * ckl);
+                sw += theta[k * L + l] / (ckl * ckl);
+            }
+            const double mean = sw / prec;
+            const uint32_t ctr[4] = { 0, ((uint32_t)OR_KIND_TOP << 24) | (uint32_t)l, mm, (uint32_t)chain << 16 };
+            uint32_t r[4];
+            or_philox4x32_10(ctr, key, r);
+            const double zn = sqrt(-2.0 * log(u01(r[0]))) * cos(2.0 * M_PI * u01(r[1]));
+            psi[l] = mean + zn / sqrt(prec);
+        }
+    }
+    return 0;
+}
 
 int or_set_threads(or_ctx *c, int32_t nthreads)
 {
@@ -868,7 +932,7 @@ static int64_t sweep_once(or_ctx *c)
                 exact_arg e = { 0.5 * c->nu + 0.5 * N, (OR_MUTANT == 15 ? c->nu * c->tau : 0.5 * c->nu * c->tau) + 0.5 * S,
                                 1, INFINITY };
                 double v;
-                int t = exact_draw(&e, cf->seed, (uint32_t)g, 0, mm, (uint32_t)cf->chain, &v, &di);
+                int t = exact_draw(&e, cf->seed, OR_KIND_EXACT, (uint32_t)g, 0, mm, (uint32_t)cf->chain, &v, &di);
                 if (t > 0) {
                     c->gam[g] = v;
                     di.kl = -1; di.nl = 0; di.nr = 0; di.nc = t;
@@ -908,7 +972,7 @@ static int64_t sweep_once(or_ctx *c)
         if (mask & (1u << OR_KIND_EXACT)) {
             exact_arg e = { a.shape_m1 + 1.0, a.rate, 0, INFINITY };
             double v;
-            t = exact_draw(&e, cf->seed, 0, 1, mm, (uint32_t)cf->chain, &v, &di);
+            t = exact_draw(&e, cf->seed, OR_KIND_EXACT, 0, 1, mm, (uint32_t)cf->chain, &v, &di);
             if (t > 0) {
                 c->tau = v;
                 di.kl = -1; di.nl = 0; di.nr = 0; di.nc = t;
@@ -965,7 +1029,9 @@ static int64_t sweep_once(or_ctx *c)
         c->red[2 + 2 * l] = sb;
         if (mask & (1u << OR_KIND_THETA)) {
             double prec = (double)G / c->sig2[l] + 1.0 / (c->c[l] * c->c[l]);
-            double mean = (sb / c->sig2[l]) / prec;
+            /* prior N(theta_mean_l, c_l^2): theta_mean = 0 in the model of Section 4.1,
+             * psi_l of the top level in the three-level form (Section 2.3) */
+            double mean = (sb / c->sig2[l] + (OR_MUTANT == 19 ? 0.0 : c->theta_mean[l] / (c->c[l] * c->c[l]))) / prec;
             uint32_t ctr[4] = { 0, ((uint32_t)OR_KIND_THETA << 24) | (uint32_t)l, mm,
                                 (uint32_t)cf->chain << 16 };
             uint32_t key[2] = { (uint32_t)cf->seed, (uint32_t)(cf->seed >> 32) };
@@ -989,7 +1055,7 @@ static int64_t sweep_once(or_ctx *c)
                 exact_arg e = { 0.5 * ((double)G - 1.0), 0.5 * S, 1,
                                 OR_MUTANT == 16 ? INFINITY : c->s[l] * c->s[l] };
                 double v;
-                t = exact_draw(&e, cf->seed, 0, 2u + (uint32_t)l, mm, (uint32_t)cf->chain, &v, &di);
+                t = exact_draw(&e, cf->seed, OR_KIND_EXACT, 0, 2u + (uint32_t)l, mm, (uint32_t)cf->chain, &v, &di);
                 if (t > 0) {
                     c->sig2[l] = v;
                     di.kl = -1; di.nl = 0; di.nr = 0; di.nc = t;

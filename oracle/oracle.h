@@ -36,7 +36,7 @@ extern "C" {
 enum {
     OR_KIND_EPS = 1, OR_KIND_GAMMA = 2, OR_KIND_NU = 3, OR_KIND_TAU = 4,
     OR_KIND_BETA = 5, OR_KIND_THETA = 6, OR_KIND_SIG2 = 7, OR_KIND_IMH = 8,
-    OR_KIND_INIT = 9, OR_KIND_TEST = 10, OR_KIND_SHIFT = 11, OR_KIND_EXACT = 12
+    OR_KIND_INIT = 9, OR_KIND_TEST = 10, OR_KIND_SHIFT = 11, OR_KIND_EXACT = 12, OR_KIND_TOP = 13
 };
 
 /* bit (1 << kind) of update_mask enables that Gibbs step; the shift step
@@ -166,6 +166,16 @@ int or_num_rows(const or_ctx *c);
 int or_set_contrasts(or_ctx *c, int32_t n_events, int32_t n_rows, const int32_t *row_event, const double *v,
                      const double *b);
 int or_event_counts(const or_ctx *c, int64_t *counts, int64_t *n_sweeps);
+
+/* Three-level form (Section 2.3), see oracle.c: or_set_top_priors sets the
+ * rate b of tau's Gamma prior and the prior means of theta (both fixed by the
+ * top level psi); or_top_draw draws b and psi (arrays theta [K][L], tau [K],
+ * a [K], c [K][L], c0 [L]); b and psi are in/out; tries gets the attempts of
+ * the b draw (0: none succeeded, b kept). */
+int or_set_top_priors(or_ctx *c, double b, const double *theta_mean);
+int or_top_draw(int32_t K, int32_t L, const double *theta, const double *tau, const double *a, const double *c,
+                double a_b, double b_b, const double *c0, uint64_t seed, int32_t chain, int64_t m, uint32_t mask,
+                double *b, double *psi, int32_t *tries);
 
 #ifdef __cplusplus
 }

@@ -7,6 +7,7 @@ from tests import test_oracle_pins as P
 from tests import test_oracle_shift as S
 from tests import test_oracle_events as E
 from tests import test_oracle_exact as X
+from tests import test_oracle_three_level as T
 
 MUTANTS = [
     # (switch, what is wrong, the pin that must fail)
@@ -39,6 +40,12 @@ MUTANTS = [
      lambda o: X.test_exact_gamma_conditional(o)),
     (16, "exact sigma^2 draw ignores the truncation at s_l^2",
      lambda o: X.test_exact_sigma2_falls_back_to_slice(o)),
+    (17, "top-level psi precision without the prior term 1/c0^2",
+     lambda o: T.test_top_psi_conditional(o)),
+    (18, "top-level b rate sum tau_k without the prior rate b_b",
+     lambda o: T.test_top_b_conditional(o)),
+    (19, "group theta mean without the top-level prior mean psi_l",
+     lambda o: T.test_group_theta_uses_psi(o)),
 ]
 
 
