@@ -268,6 +268,44 @@ int fb_set_contrasts(fb_ctx *c, int32_t n_events, int32_t n_rows, const int32_t 
                      const double *b);
 int fb_event_counts(fb_ctx *c, int32_t seg, int32_t *counts, int64_t *n_sweeps);
 
+/* Three-level form (Section 2.3).  The datasets of a batched context become
+ * the groups k of a three-level hierarchy: each keeps its own hyperparameters
+ * phi_k = (nu_k, tau_k, theta_k, sigma_k^2), whose priors are tied by a top
+ * level psi = (b, psi_1..psi_L) per chain:
+ *   tau_k ~ Gamma(a_k, rate b),   theta_kl ~ N(psi_l, c_kl^2),
+ *   b ~ Gamma(a_b, rate b_b),     psi_l ~ N(0, c0_l^2)
+ * (a_k, c_kl from each dataset's fb_priors; b of fb_priors and the prior mean
+ * 0 of theta are replaced by the top level).  Each sweep draws psi(m) from the
+ * groups' phi(m - 1) -- given phi the top level is independent of the genes,
+ * the paper's (mu, psi) | phi step -- then the genes and phi_k(m) given psi(m)
+ * as before.  Both top-level conditionals are conjugate and drawn exactly from
+ * reductions over the groups:
+ *   b     ~ Gamma(a_b + sum_k a_k, rate b_b + sum_k tau_k)
+ *   psi_l ~ N(v sum_k theta_kl / c_kl^2, v),  1/v = 1/c0_l^2 + sum_k 1/c_kl^2
+ * Philox counter (0, 13 << 24 | sub, m, chain << 16 | j), key = `seed`: psi_l
+ * sub = l, Box-Muller on words 0 and 1 of block 0; b sub = 128, a Gamma
+ * variate as in the exact conjugate draws (attempt j in block j; b keeps its
+ * value if all 64 attempts fail).  `mask` bit 0 draws b, bit 1 the psi_l
+ * (3: both; others hold them fixed).  Sums run over the datasets in order.
+ *
+ * fb_set_top_level(c, p) turns the top level on (p != NULL) or off (NULL); on,
+ * it starts at b = the first dataset's prior rate and psi = 0 for every chain
+ * and needs every dataset to have the same L.  It must be called before burn-in
+ * ends (the running moments of b and psi start at M_B).  fb_get_top copies the
+ * chain's b, psi [L], the running means and means of squares [1 + L] (b, then
+ * psi) and the attempts of the last b draw (any pointer may be NULL);
+ * fb_set_top replaces b and psi.  Errors: FB_EINVAL (bad arguments, no top
+ * level, different L, after burn-in), FB_ENOMEM, FB_EDEVICE. */
+typedef struct {
+    double a_b, b_b;       /* b ~ Gamma(a_b, rate b_b) */
+    const double *c0;      /* [L]: psi_l ~ N(0, c0[l]^2) */
+    uint64_t seed;         /* Philox key of the top-level draws */
+    uint32_t mask;         /* bit 0: draw b, bit 1: draw psi */
+} fb_top_priors;
+int fb_set_top_level(fb_ctx *c, const fb_top_priors *p);
+int fb_get_top(fb_ctx *c, int32_t chain, double *b, double *psi, double *mean, double *msq, int32_t *tries);
+int fb_set_top(fb_ctx *c, int32_t chain, double b, const double *psi);
+
 /* Graph replay of the sweep (HIP graphs).  With sweeps > 0, fb_sweep(n) runs
  * n / sweeps chunks (integer division) of `sweeps` sweeps each as one replay of
  * a captured HIP graph of the chunk's launches, and the remaining sweeps with

@@ -273,18 +273,17 @@ __device__ inline void tune_width(T &w, T &waux, T x0, T x1, int64_t m, int64_t 
 // d (1 + c x)^3 is a Gamma(alpha') variate when t = 1 + c x > 0 and
 // log u < x^2/2 + d (1 - t^3 + log t^3).  For alpha < 1 the sampler runs with
 // alpha' = alpha + 1 and the variate is scaled by U^(1/alpha).
-// Attempt k reads the Philox block (g, kKindExact << 24 | sub, m, chain << 16 | k):
+// Attempt k reads the Philox block (g, kind << 24 | sub, m, chain << 16 | k):
 // x from words 0 and 1 by Box-Muller, u from word 2, U from word 3.  The
 // candidate becomes q / X (inverse = true) or X / q and must lie in
 // (0, upper).  Returns the attempt count (1..kExactTries) with `out` set, or
 // 0 when alpha <= 0 or every attempt failed (the caller then slice-samples).
 // FP64 throughout, in either precision mode.
 constexpr int kExactTries = 64;
-constexpr uint32_t kKindExactDraw = 12;
 
-__device__ inline int exact_gamma_draw(double alpha, double q, bool inverse, double upper, uint32_t k0,
-                                       uint32_t k1, uint32_t g, uint32_t sub, uint32_t m, uint32_t chain,
-                                       double &out)
+__device__ inline int exact_gamma_draw(uint32_t kind, double alpha, double q, bool inverse, double upper,
+                                       uint32_t k0, uint32_t k1, uint32_t g, uint32_t sub, uint32_t m,
+                                       uint32_t chain, double &out)
 {
     if (!(alpha > 0.0)) return 0;
     const bool boost = alpha < 1.0;
@@ -292,7 +291,7 @@ __device__ inline int exact_gamma_draw(double alpha, double q, bool inverse, dou
     const double d = ap - 1.0 / 3.0;
     const double c = 1.0 / ::sqrt(9.0 * d);
     for (int k = 0; k < kExactTries; ++k) {
-        const uint4 r = philox4x32_10(draw_counter(g, kKindExactDraw, sub, m, chain, (uint32_t)k), k0, k1);
+        const uint4 r = philox4x32_10(draw_counter(g, kind, sub, m, chain, (uint32_t)k), k0, k1);
         const double x = ::sqrt(-2.0 * ::log(u01<double>(r.x))) * ::cos(6.283185307179586 * u01<double>(r.y));
         const double t = 1.0 + c * x;
         if (!(t > 0.0)) continue;

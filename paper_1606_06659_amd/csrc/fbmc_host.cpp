@@ -25,6 +25,8 @@ hipError_t launch_eps(int precision, const SegInfo *segs, const int4 *items, int
 hipError_t launch_gb(int precision, int mode, int maxL, const SegInfo *segs, const int2 *tiles, int ntiles,
                      const int4 *fb_items, int nfb, const SweepArgs &a, const MlpDev *net, int *err, hipStream_t st);
 hipError_t launch_hyper(const SegInfo *segs, int nseg, const SweepArgs &a, int *err, hipStream_t st);
+hipError_t launch_top(const SegInfo *segs, int nseg, int chains, TopState *top, const TopPriors &P,
+                      const SweepArgs &a, hipStream_t st);
 hipError_t launch_shift(int precision, int maxL, const SegInfo *segs, const int2 *tiles, int ntiles,
                         const SweepArgs &a, hipStream_t st);
 hipError_t launch_mlp_sweep(int precision, const SegInfo *segs, const int2 *tiles, int ntiles, const MlpDev *net,
@@ -131,6 +133,10 @@ struct fb_ctx {
     SweepArgs *h_args[2] = {nullptr, nullptr};
     hipEvent_t gcopied[2] = {nullptr, nullptr};
     int gslot = 0;
+    // three-level form (fb_set_top_level): one TopState per chain
+    bool top_on = false;
+    TopState *d_top = nullptr;
+    TopPriors top_pri{};
 };
 
 namespace {
@@ -718,6 +724,8 @@ static int launch_sweeps(fb_ctx *c, const SweepArgs *args, int64_t n, const Swee
             HIPCHK(c, launch_shift(c->prec, c->maxL, c->d_segs, c->d_tiles, c->ntiles, a, c->st));
             if (pe) HIPCHK(c, hipEventRecord(pe[7], c->st));
         }
+        // top level psi(m) from the groups' phi(m - 1), before the hyperparameter step of m
+        if (c->top_on) HIPCHK(c, launch_top(c->d_segs, nseg, c->opt.chains, c->d_top, c->top_pri, a, c->st));
         if (c->fuse) {
             prev = a;
             pending = true;
@@ -739,7 +747,8 @@ static std::vector<int64_t> graph_signature(const fb_ctx *c, const SweepMode &md
                                 (int64_t)(uintptr_t)c->d_items, c->nitems, (int64_t)(uintptr_t)c->d_tiles,
                                 c->ntiles, (int64_t)(uintptr_t)c->d_fb_items, md.learned ? c->nfb_items : 0,
                                 (int64_t)(uintptr_t)c->d_net, (int64_t)(uintptr_t)c->d_err,
-                                (int64_t)(uintptr_t)c->st, md.learned ? 1 : 0};
+                                (int64_t)(uintptr_t)c->st, md.learned ? 1 : 0, c->top_on ? 1 : 0,
+                                (int64_t)(uintptr_t)c->d_top};
     for (int64_t i = 0; i < n; ++i) {
         sig.push_back(gb_mode_of(md, args[i]));
         sig.push_back((args[i].mask >> kKindShift) & 1u);
@@ -1388,6 +1397,89 @@ int fb_set_contrasts(fb_ctx *c, int32_t n_events, int32_t n_rows, const int32_t 
         }
     }
     return upload_segs(c);
+}
+
+int fb_set_top_level(fb_ctx *c, const fb_top_priors *p)
+{
+    if (!c) return fail(nullptr, FB_EINVAL, "NULL context");
+    if (c->m > c->opt.burnin) return fail(c, FB_EINVAL, "the top level is set before burn-in ends");
+    drop_graph(c);
+    if (!p) {
+        c->top_on = false;
+        for (auto &S : c->seg) S.info.top = nullptr;
+        return upload_segs(c);
+    }
+    const int L = c->seg.front().L;
+    for (const auto &S : c->seg)
+        if (S.L != L) return fail(c, FB_EINVAL, "a top level needs every dataset of the context to have the same L");
+    if (!(p->a_b > 0.0) || !(p->b_b > 0.0) || !p->c0 || (p->mask & ~3u))
+        return fail(c, FB_EINVAL, "need a_b > 0, b_b > 0, c0[L] and mask bits 0..1");
+    for (int l = 0; l < L; ++l)
+        if (!(p->c0[l] > 0.0) || !std::isfinite(p->c0[l])) return fail(c, FB_EINVAL, "need 0 < c0[l] < inf");
+    const int C = c->opt.chains;
+    int rc;
+    if (!c->d_top && (rc = dalloc(c, (void **)&c->d_top, (size_t)C * sizeof(TopState)))) return rc;
+    TopPriors P{};
+    P.a_b = p->a_b;
+    P.b_b = p->b_b;
+    for (int l = 0; l < L; ++l) P.c0[l] = p->c0[l];
+    P.key0 = (uint32_t)p->seed;
+    P.key1 = (uint32_t)(p->seed >> 32);
+    P.L = L;
+    P.mask = p->mask;
+    // start: b = the first dataset's prior rate, psi = 0 (the two-level priors)
+    std::vector<TopState> init((size_t)C);
+    for (auto &T : init) {
+        T = TopState{};
+        T.b = c->seg.front().info.b;
+    }
+    HIPCHK(c, hipStreamSynchronize(c->st));
+    HIPCHK(c, hipMemcpy(c->d_top, init.data(), init.size() * sizeof(TopState), hipMemcpyHostToDevice));
+    c->top_pri = P;
+    c->top_on = true;
+    for (auto &S : c->seg) S.info.top = c->d_top + S.chain;
+    return upload_segs(c);
+}
+
+int fb_get_top(fb_ctx *c, int32_t chain, double *b, double *psi, double *mean, double *msq, int32_t *tries)
+{
+    if (!c) return fail(nullptr, FB_EINVAL, "NULL context");
+    if (!c->top_on) return fail(c, FB_EINVAL, "no top level (fb_set_top_level)");
+    if (chain < 0 || chain >= c->opt.chains) return fail(c, FB_EINVAL, "bad chain");
+    int rc = fb_sync(c);
+    if (rc && rc != FB_ENUMERIC) return rc;
+    TopState T;
+    HIPCHK(c, hipMemcpy(&T, c->d_top + chain, sizeof(TopState), hipMemcpyDeviceToHost));
+    const int L = c->top_pri.L;
+    if (b) *b = T.b;
+    if (tries) *tries = T.tries;
+    for (int l = 0; l < L; ++l) {
+        if (psi) psi[l] = T.psi[l];
+    }
+    for (int i = 0; i < 1 + L; ++i) {
+        if (mean) mean[i] = T.mom[i].x;
+        if (msq) msq[i] = T.mom[i].y;
+    }
+    return c->sticky;
+}
+
+int fb_set_top(fb_ctx *c, int32_t chain, double b, const double *psi)
+{
+    if (!c) return fail(nullptr, FB_EINVAL, "NULL context");
+    if (!c->top_on) return fail(c, FB_EINVAL, "no top level (fb_set_top_level)");
+    if (chain < 0 || chain >= c->opt.chains || !psi) return fail(c, FB_EINVAL, "bad chain or psi");
+    if (!(b > 0.0) || !std::isfinite(b)) return fail(c, FB_EINVAL, "need 0 < b < inf");
+    const int L = c->top_pri.L;
+    for (int l = 0; l < L; ++l)
+        if (!std::isfinite(psi[l])) return fail(c, FB_EINVAL, "non-finite psi");
+    int rc = fb_sync(c);
+    if (rc && rc != FB_ENUMERIC) return rc;
+    TopState T;
+    HIPCHK(c, hipMemcpy(&T, c->d_top + chain, sizeof(TopState), hipMemcpyDeviceToHost));
+    T.b = b;
+    for (int l = 0; l < L; ++l) T.psi[l] = psi[l];
+    HIPCHK(c, hipMemcpy(c->d_top + chain, &T, sizeof(TopState), hipMemcpyHostToDevice));
+    return c->sticky;
 }
 
 int fb_event_counts(fb_ctx *c, int32_t seg, int32_t *counts, int64_t *n_sweeps)

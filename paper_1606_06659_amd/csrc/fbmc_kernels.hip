@@ -29,7 +29,6 @@
 #include "fbmc_mlp.hpp"
 #include "fbmc_types.hpp"
 
-static_assert(fbmc::kKindExact == (int)fbmc::kKindExactDraw, "one kind for the exact draws");
 
 namespace fbmc {
 
@@ -758,7 +757,7 @@ __device__ inline void gamma_wave(const SegInfo &S, int tile, const SweepArgs &a
             if ((a.mask >> kKindExact) & 1u) {
                 // exact draw: gamma_g = (nu tau/2 + S_g/2) / X, X ~ Gamma(nu/2 + N/2)
                 double v = 0.0;
-                tries = exact_gamma_draw(0.5 * nu + 0.5 * N, scale, true, __builtin_inf(), S.key0, S.key1,
+                tries = exact_gamma_draw(kKindExact, 0.5 * nu + 0.5 * N, scale, true, __builtin_inf(), S.key0, S.key1,
                                          (uint32_t)g, 0, (uint32_t)a.m, (uint32_t)S.chain, v);
                 if (tries > 0) {
                     gam = (T)v;
@@ -1621,12 +1620,14 @@ __device__ inline void hyper_block(const SegInfo &S, const SweepArgs &a, int *er
         }
         // step 4: tau
         if ((a.mask >> 4) & 1u) {
-            TauF f{S.a + 0.5 * G * nu - 1.0, S.b + 0.5 * nu * red[1]};
+            // rate of tau's Gamma prior: b, or the top level's b in the three-level form
+            const double rate_b = S.top != nullptr ? S.top->b : S.b;
+            TauF f{S.a + 0.5 * G * nu - 1.0, rate_b + 0.5 * nu * red[1]};
             int tries = 0;
             if (exact) {
                 // exact draw, the same on every lane: tau = X / rate, X ~ Gamma(a + G nu / 2)
                 double v = 0.0;
-                tries = exact_gamma_draw(f.shape_m1 + 1.0, f.rate, false, __builtin_inf(), k0, k1, 0, 1, mm, chain,
+                tries = exact_gamma_draw(kKindExact, f.shape_m1 + 1.0, f.rate, false, __builtin_inf(), k0, k1, 0, 1, mm, chain,
                                          v);
                 if (tries > 0) {
                     tau = v;
@@ -1666,7 +1667,9 @@ __device__ inline void hyper_block(const SegInfo &S, const SweepArgs &a, int *er
             if ((a.mask >> 6) & 1u) {
                 const double cl = S.c[l];
                 const double prec = G / sig2 + 1.0 / (cl * cl);
-                const double mean = (sb / sig2) / prec;
+                // prior N(0, c_l^2), or N(psi_l, c_l^2) under a top level
+                const double mean = S.top != nullptr ? (sb / sig2 + S.top->psi[l] / (cl * cl)) / prec
+                                                     : (sb / sig2) / prec;
                 const uint4 r = philox4x32_10(draw_counter(0, 6, (uint32_t)l, mm, chain, 0), k0, k1);
                 const double zn = ::sqrt(-2.0 * ::log(u01<double>(r.x))) * ::cos(6.283185307179586 * u01<double>(r.y));
                 th = mean + zn / ::sqrt(prec);
@@ -1680,7 +1683,7 @@ __device__ inline void hyper_block(const SegInfo &S, const SweepArgs &a, int *er
                 int tries = 0;
                 if (exact) {
                     // exact draw: sigma^2 = (S/2) / X, X ~ Gamma((G - 1)/2), kept below s_l^2
-                    tries = exact_gamma_draw(0.5 * (G - 1.0), 0.5 * Ssq, true, sl * sl, k0, k1, 0, 2u + (uint32_t)l,
+                    tries = exact_gamma_draw(kKindExact, 0.5 * (G - 1.0), 0.5 * Ssq, true, sl * sl, k0, k1, 0, 2u + (uint32_t)l,
                                              mm, chain, s2new);
                     if (tries > 0 && a.dbg && w0) H.dbg[2 + l] = make_int4(-1, 0, 0, tries);
                 }
@@ -1712,6 +1715,68 @@ __device__ inline void hyper_block(const SegInfo &S, const SweepArgs &a, int *er
     __syncthreads();
     double *hw = reinterpret_cast<double *>(S.hyp);
     for (int i = tid; i < kWords; i += kHyperThreads) hw[i] = hs[i];
+}
+
+// ---------------------------------------------------------------------------
+// Top level of the three-level form (Section 2.3): one workgroup per chain
+// ---------------------------------------------------------------------------
+// Given the groups' hyperparameters phi the top level is independent of the
+// genes, so psi(m) is drawn from phi(m - 1) after the gene kernels of sweep m
+// and before its hyperparameter step, which reads it:
+//   b     ~ Gamma(a_b + sum_k a_k, rate b_b + sum_k tau_k)             (bit 0)
+//   psi_l ~ N(v sum_k theta_kl / c_kl^2, v), 1/v = 1/c0_l^2 + sum_k 1/c_kl^2 (bit 1)
+// The groups of chain c are the segments k * chains + c, summed over k in
+// order.  Philox (0, kKindTop << 24 | sub, m, chain << 16 | j): psi_l sub = l,
+// Box-Muller on block 0; b sub = 128, a Gamma variate (exact_gamma_draw); when
+// no attempt succeeds b keeps its value.  Lane 0 does the arithmetic (a few
+// dozen FP64 operations per group); the workgroup is one wavefront.
+__global__ __launch_bounds__(64) void top_sweep(const SegInfo *__restrict__ segs, int nseg, int chains,
+                                                 TopState *__restrict__ top, TopPriors P, SweepArgs a0)
+{
+    if (threadIdx.x != 0) return;
+    const SweepArgs a = resolve_args(a0);
+    const int chain = (int)blockIdx.x;
+    TopState &T = top[chain];
+    const uint32_t mm = (uint32_t)a.m;
+    const int L = P.L;
+    if (P.mask & 1u) {
+        double sa = 0.0, st = 0.0;
+        for (int s = chain; s < nseg; s += chains) {
+            sa += segs[s].a;
+            st += segs[s].hyp->tau;
+        }
+        double v = 0.0;
+        const int t = exact_gamma_draw(kKindTop, P.a_b + sa, P.b_b + st, false, __builtin_inf(), P.key0, P.key1, 0,
+                                       128u, mm, (uint32_t)chain, v);
+        if (t > 0) T.b = v;
+        T.tries = t;
+    }
+    if (P.mask & 2u) {
+        for (int l = 0; l < L; ++l) {
+            double prec = 1.0 / (P.c0[l] * P.c0[l]);
+            double sw = 0.0;
+            for (int s = chain; s < nseg; s += chains) {
+                const double ckl = segs[s].c[l];
+                prec += 1.0 / (ckl * ckl);
+                sw += segs[s].hyp->theta[l] / (ckl * ckl);
+            }
+            const uint4 r = philox4x32_10(draw_counter(0, kKindTop, (uint32_t)l, mm, (uint32_t)chain, 0), P.key0,
+                                          P.key1);
+            const double zn = ::sqrt(-2.0 * ::log(u01<double>(r.x))) * ::cos(6.283185307179586 * u01<double>(r.y));
+            T.psi[l] = sw / prec + zn / ::sqrt(prec);
+        }
+    }
+    if (a.m > a.burnin) {
+        welford(T.mom[0], T.b, a.inv_k);
+        for (int l = 0; l < L; ++l) welford(T.mom[1 + l], T.psi[l], a.inv_k);
+    }
+}
+
+hipError_t launch_top(const SegInfo *segs, int nseg, int chains, TopState *top, const TopPriors &P,
+                      const SweepArgs &a, hipStream_t st)
+{
+    hipLaunchKernelGGL(top_sweep, dim3(chains), dim3(64), 0, st, segs, nseg, chains, top, P, a);
+    return hipGetLastError();
 }
 
 __global__ __launch_bounds__(kHyperThreads) void hyper_sweep(const SegInfo *__restrict__ segs, SweepArgs a0, int *err)

@@ -14,8 +14,28 @@ constexpr int kTile = 64;      // genes per wavefront tile
 constexpr int kMaxParts = 2 + 2 * kMaxL;
 constexpr int kKindShift = 11;  // Philox kind and update_mask bit of the shift step
 constexpr int kKindExact = 12;  // update_mask bit of the exact conjugate draws (gamma, tau, sigma^2)
+constexpr int kKindTop = 13;    // Philox kind of the top-level draws (three-level form)
 constexpr int kMaxEv = 8;       // contrast events per context
 constexpr int kMaxCtr = 16;     // contrast rows (inequalities) over all events
+
+// Top level of the three-level form (Section 2.3), one per chain: the groups
+// (datasets) of the chain have tau_k ~ Gamma(a_k, rate b) and theta_kl ~
+// N(psi_l, c_kl^2), with b ~ Gamma(a_b, rate b_b) and psi_l ~ N(0, c0_l^2).
+struct TopState {
+    double b;
+    double psi[kMaxL];
+    double2 mom[1 + kMaxL];       // b, psi[L]: running mean and mean of squares after burn-in
+    int32_t tries;                // attempts of the last b draw (0: none succeeded, b kept)
+    int32_t pad;
+};
+
+struct TopPriors {
+    double a_b, b_b;
+    double c0[kMaxL];
+    uint32_t key0, key1;          // Philox key of the top-level draws
+    int32_t L;
+    uint32_t mask;                // bit 0: draw b, bit 1: draw psi
+};
 
 // Per-segment (dataset x chain) description.  Lives in device memory and is
 // read with wavefront-uniform loads.  Arrays of state are gene-contiguous
@@ -78,6 +98,7 @@ struct SegInfo {
     int32_t *imh_count;           // [Gp] accepted IMH steps while counting
     int32_t *imh_last;            // [Gp] last sweep: 1 accepted, 0 rejected, -1 slice
     float *pairs;                 // training pairs [capacity][kPairStride]: features, beta
+    const TopState *top;          // three-level form: the chain's top level (b, psi), else null
 };
 
 constexpr int kPairStride = 32 + kMaxL;   // 32 raw features then L targets

@@ -67,12 +67,17 @@ class fb_summary(C.Structure):
                                    "msq_beta", "mean_hyp", "msq_hyp")] + [("count", C.c_int64)]
 
 
+class fb_top_priors(C.Structure):
+    _fields_ = [("a_b", C.c_double), ("b_b", C.c_double), ("c0", _DP), ("seed", C.c_uint64),
+                ("mask", C.c_uint32)]
+
+
 EXPORTS = [
     "fb_default_options", "fb_create", "fb_create_batch", "fb_destroy", "fb_sweep", "fb_sync",
     "fb_num_segments", "fb_segment_dims", "fb_get_state", "fb_set_state", "fb_summaries",
     "fb_trace_genes", "fb_trace", "fb_trace_reset", "fb_debug_counts", "fb_reductions",
     "fb_philox", "fb_last_sweep_time", "fb_profile", "fb_kernel_times", "fb_set_graph", "fb_get_graph",
-    "fb_set_contrasts", "fb_event_counts",
+    "fb_set_contrasts", "fb_event_counts", "fb_set_top_level", "fb_get_top", "fb_set_top",
     "fb_set_launch",
     "fb_get_launch", "fb_autotune", "fb_last_error",
     "fb_strerror", "fb_default_train_opts", "fb_proposal_collect", "fb_proposal_train",
@@ -123,6 +128,9 @@ def load() -> C.CDLL:
     L.fb_set_graph.argtypes = [vp, C.c_int32]
     L.fb_set_contrasts.argtypes = [vp, i32, i32, C.POINTER(C.c_int32), _DP, _DP]
     L.fb_event_counts.argtypes = [vp, i32, C.POINTER(C.c_int32), C.POINTER(i64)]
+    L.fb_set_top_level.argtypes = [vp, C.POINTER(fb_top_priors)]
+    L.fb_get_top.argtypes = [vp, i32, _DP, _DP, _DP, _DP, C.POINTER(i32)]
+    L.fb_set_top.argtypes = [vp, i32, C.c_double, _DP]
     L.fb_get_graph.argtypes = [vp]
     L.fb_get_graph.restype = C.c_int32
     L.fb_set_launch.argtypes = [vp, i32, i32]
@@ -362,6 +370,35 @@ def fb_event_probs(ctx, n_events: int, seg: int = 0):
     """Posterior probabilities [G, n_events]: counts / sweeps counted."""
     c, n = fb_event_counts(ctx, n_events, seg)
     return c / max(n, 1), n
+
+
+def fb_set_top_level(ctx, a_b=1.0, b_b=1.0, c0=None, seed=0, mask=3, L=None, off=False):
+    """Three-level form (Section 2.3): tie the datasets' tau and theta priors
+    through a top level b ~ Gamma(a_b, rate b_b), psi_l ~ N(0, c0_l^2) per
+    chain (off=True removes it)."""
+    if off:
+        _check(load().fb_set_top_level(ctx, None), ctx)
+        return
+    L = fb_segment_dims(ctx, 0)["L"] if L is None else L
+    c0 = np.ascontiguousarray(np.full(L, 10.0) if c0 is None else c0, dtype=np.float64)
+    p = fb_top_priors(float(a_b), float(b_b), _p(c0), C.c_uint64(int(seed)), C.c_uint32(int(mask)))
+    _check(load().fb_set_top_level(ctx, C.byref(p)), ctx)
+
+
+def fb_get_top(ctx, chain: int = 0):
+    """dict(b, psi [L], mean [1 + L], msq [1 + L], tries) of one chain's top level."""
+    L = fb_segment_dims(ctx, 0)["L"]
+    b = C.c_double()
+    psi, mean, msq = np.zeros(L), np.zeros(1 + L), np.zeros(1 + L)
+    tries = C.c_int32()
+    _check(load().fb_get_top(ctx, int(chain), C.byref(b), _p(psi), _p(mean), _p(msq), C.byref(tries)), ctx,
+           (FB_ENUMERIC,))
+    return dict(b=b.value, psi=psi, mean=mean, msq=msq, tries=int(tries.value))
+
+
+def fb_set_top(ctx, chain: int, b: float, psi):
+    psi = np.ascontiguousarray(psi, dtype=np.float64)
+    _check(load().fb_set_top(ctx, int(chain), float(b), _p(psi)), ctx)
 
 
 def fb_set_graph(ctx, sweeps: int):
