@@ -301,6 +301,42 @@ def run_batched(fbmc, stream, steps=100, burnin=200, graph_sweeps=25):
     return out
 
 
+def run_three_level(fbmc, stream, steps=200, burnin=200):
+    """Secondary measurement: the three-level form (Section 2.3).  The groups
+    are the datasets of the batched workload with N = 16 (paper design, L = 5),
+    one chain; a top level b ~ Gamma(1, rate 1), psi_l ~ N(0, 10^2) ties their
+    tau and theta priors.  The same context without the top level gives the
+    cost of the extra per-sweep draw (one small kernel after the gene kernels)."""
+    import torch
+    from paper_1606_06659_amd import datagen
+    meta = [(G, N) for G, N in datagen.batched_meta(64, seed=0) if N == 16]
+    dss = [datagen.batched_dataset(k + 1, G, N) for k, (G, N) in enumerate(meta)]
+    genes = sum(d.G for d in dss)
+    out = {"workload": f"three-level: {len(dss)} groups (datasets N=16, L=5), {genes} genes, 1 chain",
+           "groups": len(dss), "genes": genes, "steps": steps}
+    for name, top in (("two_level", False), ("three_level", True)):
+        opts = fbmc.fb_default_options(burnin=burnin, tune_start=burnin // 10, precision=fbmc.FB_FP32,
+                                       jitter=0, stream=stream.cuda_stream)
+        ctx = fbmc.fb_create_batch([dict(counts=d.y, X=d.X, h=d.h, seed=k + 1) for k, d in enumerate(dss)], opts)
+        if top:
+            fbmc.fb_set_top_level(ctx, 1.0, 1.0, np.full(5, 10.0), seed=99, mask=3)
+        fbmc.fb_sweep(ctx, burnin + 10)
+        fbmc.fb_sync(ctx)
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        fbmc.fb_sweep(ctx, steps)
+        fbmc.fb_sync(ctx)
+        torch.cuda.synchronize()
+        dt = time.perf_counter() - t0
+        out[f"{name}_sweeps_per_s"] = steps / dt
+        if top:
+            t = fbmc.fb_get_top(ctx, 0)
+            out["top_posterior_mean"] = {"b": float(t["mean"][0]), "psi": [float(v) for v in t["mean"][1:]]}
+        fbmc.fb_destroy(ctx)
+    out["three_level_cost"] = out["two_level_sweeps_per_s"] / out["three_level_sweeps_per_s"] - 1.0
+    return out
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -317,6 +353,8 @@ def main():
                     help="skip the secondary heavy workload (4 chains x G=200k x N=48)")
     ap.add_argument("--heavy-only", action="store_true",
                     help="run only the heavy workload and print its record (profiling runs)")
+    ap.add_argument("--three-level-only", action="store_true",
+                    help="run only the three-level workload and print its record (profiling runs)")
     ap.add_argument("--launch", default="auto",
                     help="'auto' (autotuner) or 'SPW,FUSE': samples per eps wavefront, fused hyper step 0/1")
     ap.add_argument("--burnin", type=int, default=BURNIN,
@@ -350,6 +388,9 @@ def main():
             dst.copy_(src)
         torch.cuda.synchronize()
         del src, dst
+    if args.three_level_only:
+        print(json.dumps({"three_level_workload": run_three_level(fbmc, stream)}), flush=True)
+        return
     if args.heavy_only:
         print(json.dumps({"heavy_workload": run_heavy(fbmc, stream, steps=args.steps, burnin=args.burnin)}),
               flush=True)
@@ -438,6 +479,7 @@ def main():
         line["heavy_workload"] = run_heavy(fbmc, stream)
         line["small_workload"] = run_small(fbmc, stream)
         line["batched_workload"] = run_batched(fbmc, stream)
+        line["three_level_workload"] = run_three_level(fbmc, stream)
     if not args.no_cpu_baseline:
         line["cpu_baseline"] = cpu_baseline(ds)
     print(json.dumps(line), flush=True)

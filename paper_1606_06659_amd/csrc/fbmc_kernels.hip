@@ -1728,47 +1728,80 @@ __device__ inline void hyper_block(const SegInfo &S, const SweepArgs &a, int *er
 // The groups of chain c are the segments k * chains + c, summed over k in
 // order.  Philox (0, kKindTop << 24 | sub, m, chain << 16 | j): psi_l sub = l,
 // Box-Muller on block 0; b sub = 128, a Gamma variate (exact_gamma_draw); when
-// no attempt succeeds b keeps its value.  Lane 0 does the arithmetic (a few
-// dozen FP64 operations per group); the workgroup is one wavefront.
+// no attempt succeeds b keeps its value.  Lane i stages group k0 + i's terms
+// a_k, tau_k, 1/c_kl^2 and theta_kl/c_kl^2 in LDS (loads and FP64 divisions
+// of 64 groups at a time in parallel); then lane l < L adds up psi_l's sums in
+// group order and draws psi_l, and lane kMaxL does the same for b.
 __global__ __launch_bounds__(64) void top_sweep(const SegInfo *__restrict__ segs, int nseg, int chains,
                                                  TopState *__restrict__ top, TopPriors P, SweepArgs a0)
 {
-    if (threadIdx.x != 0) return;
+    __shared__ double va[64], vt[64], vq[64][kMaxL], vp[64][kMaxL];
     const SweepArgs a = resolve_args(a0);
     const int chain = (int)blockIdx.x;
+    const int lane = (int)threadIdx.x;
+    const int L = P.L;
+    const int K = (nseg - chain + chains - 1) / chains;    // groups of this chain: segments k * chains + chain
+    const bool psi_lane = lane < L, b_lane = lane == kMaxL;
+    double c0l = 1.0;
+#pragma unroll
+    for (int l = 0; l < kMaxL; ++l) c0l = l == lane ? P.c0[l] : c0l;
+    // psi lanes: precision and weighted sum of psi_lane; b lane: sum a_k, sum tau_k
+    double s1 = psi_lane ? 1.0 / (c0l * c0l) : 0.0, s2 = 0.0;
+    for (int k0 = 0; k0 < K; k0 += 64) {
+        const int k = k0 + lane;
+        if (k < K) {
+            const SegInfo &S = segs[(int64_t)k * chains + chain];
+            const HyperState *H = S.hyp;
+            va[lane] = S.a;
+            vt[lane] = H->tau;
+#pragma unroll
+            for (int l = 0; l < kMaxL; ++l) {
+                if (l < L) {
+                    const double ckl = S.c[l];
+                    vp[lane][l] = 1.0 / (ckl * ckl);
+                    vq[lane][l] = H->theta[l] / (ckl * ckl);
+                }
+            }
+        }
+        __syncthreads();
+        const int n = K - k0 < 64 ? K - k0 : 64;
+        if (psi_lane) {
+            for (int i = 0; i < n; ++i) {
+                s1 += vp[i][lane];
+                s2 += vq[i][lane];
+            }
+        } else if (b_lane) {
+            for (int i = 0; i < n; ++i) {
+                s1 += va[i];
+                s2 += vt[i];
+            }
+        }
+        __syncthreads();
+    }
     TopState &T = top[chain];
     const uint32_t mm = (uint32_t)a.m;
-    const int L = P.L;
-    if (P.mask & 1u) {
-        double sa = 0.0, st = 0.0;
-        for (int s = chain; s < nseg; s += chains) {
-            sa += segs[s].a;
-            st += segs[s].hyp->tau;
-        }
-        double v = 0.0;
-        const int t = exact_gamma_draw(kKindTop, P.a_b + sa, P.b_b + st, false, __builtin_inf(), P.key0, P.key1, 0,
-                                       128u, mm, (uint32_t)chain, v);
-        if (t > 0) T.b = v;
-        T.tries = t;
-    }
-    if (P.mask & 2u) {
-        for (int l = 0; l < L; ++l) {
-            double prec = 1.0 / (P.c0[l] * P.c0[l]);
-            double sw = 0.0;
-            for (int s = chain; s < nseg; s += chains) {
-                const double ckl = segs[s].c[l];
-                prec += 1.0 / (ckl * ckl);
-                sw += segs[s].hyp->theta[l] / (ckl * ckl);
-            }
-            const uint4 r = philox4x32_10(draw_counter(0, kKindTop, (uint32_t)l, mm, (uint32_t)chain, 0), P.key0,
-                                          P.key1);
+    const bool sampling = a.m > a.burnin;
+    if (psi_lane) {
+        double psi = T.psi[lane];
+        if (P.mask & 2u) {
+            const uint4 r = philox4x32_10(draw_counter(0, kKindTop, (uint32_t)lane, mm, (uint32_t)chain, 0),
+                                          P.key0, P.key1);
             const double zn = ::sqrt(-2.0 * ::log(u01<double>(r.x))) * ::cos(6.283185307179586 * u01<double>(r.y));
-            T.psi[l] = sw / prec + zn / ::sqrt(prec);
+            psi = s2 / s1 + zn / ::sqrt(s1);
+            T.psi[lane] = psi;
         }
-    }
-    if (a.m > a.burnin) {
-        welford(T.mom[0], T.b, a.inv_k);
-        for (int l = 0; l < L; ++l) welford(T.mom[1 + l], T.psi[l], a.inv_k);
+        if (sampling) welford(T.mom[1 + lane], psi, a.inv_k);
+    } else if (b_lane) {
+        double b = T.b;
+        if (P.mask & 1u) {
+            double v = 0.0;
+            const int t = exact_gamma_draw(kKindTop, P.a_b + s1, P.b_b + s2, false, __builtin_inf(), P.key0, P.key1,
+                                           0, 128u, mm, (uint32_t)chain, v);
+            if (t > 0) b = v;
+            T.b = b;
+            T.tries = t;
+        }
+        if (sampling) welford(T.mom[0], b, a.inv_k);
     }
 }
 
