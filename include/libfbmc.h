@@ -331,6 +331,12 @@ int32_t fb_get_graph(const fb_ctx *c);
  *                     involves a hyperparameter); 0: a kernel of its own
  * Defaults: 1 and 1.  FB_EINVAL outside these values. */
 int fb_set_launch(fb_ctx *c, int32_t samples_per_wave, int32_t fuse_hyper);
+/* With the shift step on, the slice sweep runs the gamma, beta and shift draws
+ * of a tile in one kernel (fused = 1, the default: a tile's shift overlaps
+ * other tiles' beta draws) or the shift as a kernel of its own after the
+ * gamma/beta kernel (0).  The learned step always uses the separate kernel.
+ * No choice changes any draw.  Errors: FB_EINVAL. */
+int fb_set_shift_fusion(fb_ctx *c, int32_t fused);
 int fb_get_launch(const fb_ctx *c, int32_t *samples_per_wave, int32_t *fuse_hyper);
 
 /* Autotuner: times trial_sweeps sweeps (after 2 warm-up sweeps) for every

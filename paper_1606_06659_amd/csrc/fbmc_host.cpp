@@ -29,6 +29,8 @@ hipError_t launch_top(const SegInfo *segs, int nseg, int chains, TopState *top, 
                       const SweepArgs &a, hipStream_t st);
 hipError_t launch_shift(int precision, int maxL, const SegInfo *segs, const int2 *tiles, int ntiles,
                         const SweepArgs &a, hipStream_t st);
+hipError_t launch_gb_shift(int precision, int maxL, const SegInfo *segs, const int2 *tiles, int ntiles,
+                           const SweepArgs &a, int *err, hipStream_t st);
 hipError_t launch_mlp_sweep(int precision, const SegInfo *segs, const int2 *tiles, int ntiles, const MlpDev *net,
                             hipStream_t st);
 hipError_t launch_philox(const uint4 *ctr, const uint2 *key, uint4 *out, int64_t n, hipStream_t st);
@@ -133,6 +135,9 @@ struct fb_ctx {
     SweepArgs *h_args[2] = {nullptr, nullptr};
     hipEvent_t gcopied[2] = {nullptr, nullptr};
     int gslot = 0;
+    // the slice sweep with the shift step runs gamma, beta and the shift in
+    // one kernel (true) or the shift in a kernel of its own (false)
+    bool fuse_shift = true;
     // three-level form (fb_set_top_level): one TopState per chain
     bool top_on = false;
     TopState *d_top = nullptr;
@@ -705,10 +710,13 @@ static int launch_sweeps(fb_ctx *c, const SweepArgs *args, int64_t n, const Swee
         const bool prof = !dev && c->prof_every > 0 && c->prof_n < c->prof_cap &&
                           (c->prof_count++ % c->prof_every) == 0;
         const bool shift = (args[i].mask >> kKindShift) & 1u;
+        const int gbm = gb_mode_of(md, args[i]);
+        // the slice sweep with the shift step: one kernel for gamma, beta and the shift
+        const bool fused_shift = shift && gbm == 0 && c->fuse_shift;
         hipEvent_t *pe = prof ? &c->prof_ev[8 * (size_t)c->prof_n] : nullptr;
         if (prof) {
             c->prof_hyp[c->prof_n] = c->fuse ? 0 : 1;
-            c->prof_shift[c->prof_n++] = shift ? 1 : 0;
+            c->prof_shift[c->prof_n++] = (shift && !fused_shift) ? 1 : 0;
         }
         if (pe) HIPCHK(c, hipEventRecord(pe[0], c->st));
         HIPCHK(c, launch_eps(c->prec, c->d_segs, c->d_items, c->nitems, a, pending ? nseg : 0, prev, c->d_err,
@@ -716,10 +724,13 @@ static int launch_sweeps(fb_ctx *c, const SweepArgs *args, int64_t n, const Swee
         if (pe) HIPCHK(c, hipEventRecord(pe[1], c->st));
         if (pe) HIPCHK(c, hipEventRecord(pe[2], c->st));
         if (md.learned) HIPCHK(c, launch_mlp_sweep(c->prec, c->d_segs, c->d_tiles, c->ntiles, c->d_net, c->st));
-        HIPCHK(c, launch_gb(c->prec, gb_mode_of(md, args[i]), c->maxL, c->d_segs, c->d_tiles, c->ntiles,
-                            c->d_fb_items, md.learned ? c->nfb_items : 0, a, c->d_net, c->d_err, c->st));
+        if (fused_shift)
+            HIPCHK(c, launch_gb_shift(c->prec, c->maxL, c->d_segs, c->d_tiles, c->ntiles, a, c->d_err, c->st));
+        else
+            HIPCHK(c, launch_gb(c->prec, gbm, c->maxL, c->d_segs, c->d_tiles, c->ntiles, c->d_fb_items,
+                                md.learned ? c->nfb_items : 0, a, c->d_net, c->d_err, c->st));
         if (pe) HIPCHK(c, hipEventRecord(pe[3], c->st));
-        if (shift) {
+        if (shift && !fused_shift) {
             if (pe) HIPCHK(c, hipEventRecord(pe[6], c->st));
             HIPCHK(c, launch_shift(c->prec, c->maxL, c->d_segs, c->d_tiles, c->ntiles, a, c->st));
             if (pe) HIPCHK(c, hipEventRecord(pe[7], c->st));
@@ -749,6 +760,7 @@ static std::vector<int64_t> graph_signature(const fb_ctx *c, const SweepMode &md
                                 (int64_t)(uintptr_t)c->d_net, (int64_t)(uintptr_t)c->d_err,
                                 (int64_t)(uintptr_t)c->st, md.learned ? 1 : 0, c->top_on ? 1 : 0,
                                 (int64_t)(uintptr_t)c->d_top};
+    sig.push_back(c->fuse_shift ? 1 : 0);
     for (int64_t i = 0; i < n; ++i) {
         sig.push_back(gb_mode_of(md, args[i]));
         sig.push_back((args[i].mask >> kKindShift) & 1u);
@@ -1599,6 +1611,14 @@ int fb_set_launch(fb_ctx *c, int32_t samples_per_wave, int32_t fuse_hyper)
     int rc;
     if (samples_per_wave != c->spw && (rc = build_items(c, samples_per_wave))) return rc;
     c->fuse = fuse_hyper != 0;
+    return FB_OK;
+}
+
+int fb_set_shift_fusion(fb_ctx *c, int32_t fused)
+{
+    if (!c) return fail(nullptr, FB_EINVAL, "NULL context");
+    if (fused != 0 && fused != 1) return fail(c, FB_EINVAL, "fused must be 0 or 1");
+    c->fuse_shift = fused != 0;
     return FB_OK;
 }
 

@@ -1155,6 +1155,38 @@ __global__ __launch_bounds__(256) void shift_sweep(const SegInfo *__restrict__ s
     shift_genes<T, kML>(segs[sidx], tile, a);
 }
 
+// Steps 2 and 5 and the shift step in one launch (the slice sweep with the
+// shift step on): per tile, gamma on wavefront 0 and beta on wavefront 1 as in
+// gb_sweep, a workgroup barrier (the tile's new gamma_g and beta_g are then
+// written and visible to the workgroup), then wavefront 1 shifts the tile.  A
+// tile's shift overlaps other tiles' beta draws instead of waiting for a
+// launch of its own; the arithmetic is that of shift_sweep.  A kernel of its
+// own so that the shift code's registers do not lower the occupancy of
+// gb_sweep.
+template <typename T, int kML>
+__global__ __launch_bounds__(128) void gb_shift_sweep(const SegInfo *__restrict__ segs,
+                                                      const int2 *__restrict__ tiles, int ntiles, SweepArgs a0,
+                                                      int *err)
+{
+    const SweepArgs a = resolve_args(a0);
+    const int wave = __builtin_amdgcn_readfirstlane((int)(threadIdx.x >> 6));
+    const int lane = (int)(threadIdx.x & 63);
+    const int tix = (int)blockIdx.x;
+    if (tix >= ntiles) return;            // the whole workgroup leaves
+    const int2 tt = tiles[tix];
+    const int sidx = __builtin_amdgcn_readfirstlane(tt.x);
+    const int tile = __builtin_amdgcn_readfirstlane(tt.y);
+    const SegInfo &S = segs[sidx];
+    if (wave == 0) {
+        gamma_wave<T, kML>(S, tile, a, err);
+    } else {
+        const int64_t g = (int64_t)tile * kTile + lane;
+        beta_genes<T, 0, kML>(S, g, g < S.G, tile, false, a, nullptr, err);
+    }
+    __syncthreads();
+    if (wave == 1) shift_genes<T, kML>(S, tile, a);
+}
+
 // ---------------------------------------------------------------------------
 // Proposal network inference: one wavefront per 64-gene tile.  Features are
 // standardised, rounded to BF16 and stored row per gene in LDS; each layer is
@@ -1895,6 +1927,21 @@ hipError_t launch_gb(int precision, int mode, int maxL, const SegInfo *segs, con
     if (mode == 0) launch_gb_m<0>(precision, maxL, segs, tiles, ntiles, fb_items, 0, a, net, err, st);
     else if (mode == 1) launch_gb_m<1>(precision, maxL, segs, tiles, ntiles, fb_items, nfb, a, net, err, st);
     else launch_gb_m<2>(precision, maxL, segs, tiles, ntiles, fb_items, nfb, a, net, err, st);
+    return hipGetLastError();
+}
+
+hipError_t launch_gb_shift(int precision, int maxL, const SegInfo *segs, const int2 *tiles, int ntiles,
+                           const SweepArgs &a, int *err, hipStream_t st)
+{
+    if (ntiles <= 0) return hipSuccess;
+    const dim3 grid((unsigned)ntiles), block(128);
+    if (precision == 1) {
+        if (maxL <= 5) hipLaunchKernelGGL((gb_shift_sweep<float, 5>), grid, block, 0, st, segs, tiles, ntiles, a, err);
+        else hipLaunchKernelGGL((gb_shift_sweep<float, kMaxL>), grid, block, 0, st, segs, tiles, ntiles, a, err);
+    } else {
+        if (maxL <= 5) hipLaunchKernelGGL((gb_shift_sweep<double, 5>), grid, block, 0, st, segs, tiles, ntiles, a, err);
+        else hipLaunchKernelGGL((gb_shift_sweep<double, kMaxL>), grid, block, 0, st, segs, tiles, ntiles, a, err);
+    }
     return hipGetLastError();
 }
 

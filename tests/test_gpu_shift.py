@@ -87,3 +87,38 @@ def test_fp32_shift_step_matches_oracle(oracle_lib):
     assert np.max(np.abs(z1 - z0) / (np.abs(z0) + 1.0)) < 1e-5
     np.testing.assert_array_equal(sg["hyp"], so["hyp"])
     F.fb_destroy(g)
+
+
+@pytest.mark.parametrize("precision", [0, 1])
+def test_fused_and_separate_shift_kernels_agree(precision):
+    """The shift step inside the gamma/beta kernel (the default) and in a
+    kernel of its own give the same chain bit for bit, also under graph replay
+    and with events, trace and moments on."""
+    F = require_gpu()
+    ds = datagen.paper_design_16(G=1500, seed=4)
+    opts = F.fb_default_options(burnin=15, tune_start=3, precision=precision, jitter=0,
+                                update_mask=F.FB_UPDATE_ALL | F.FB_SHIFT, thin=1, trace_genes=9,
+                                trace_capacity=60)
+    a = F.fb_create(ds.y, ds.X, ds.h, seed=21, options=opts)
+    b = F.fb_create(ds.y, ds.X, ds.h, seed=21, options=opts)
+    F.fb_set_shift_fusion(b, False)
+    ev = [[(np.array([0.0, 2.0, 0.0, 1.0, 0.0]), 0.0)]]
+    for g in (a, b):
+        F.fb_set_contrasts(g, ev, 5)
+    for i, n in enumerate((12, 9, 20)):
+        if i == 2:
+            F.fb_set_graph(a, 5)
+            F.fb_set_graph(b, 5)
+        say("fused vs separate shift kernel: sweeps", n, "precision", precision)
+        F.fb_sweep(a, n)
+        F.fb_sweep(b, n)
+        sa, sb = F.fb_get_state(a), F.fb_get_state(b)
+        for k in ("eps", "gam", "beta", "hyp", "w_eps", "w_beta"):
+            assert np.array_equal(sa[k], sb[k]), (i, k)
+        ma, mb = F.fb_summaries(a), F.fb_summaries(b)
+        for k in ma:
+            assert np.array_equal(np.asarray(ma[k]), np.asarray(mb[k])), (i, k)
+        assert np.array_equal(F.fb_trace(a)[0], F.fb_trace(b)[0])
+        assert np.array_equal(F.fb_event_counts(a, 1)[0], F.fb_event_counts(b, 1)[0])
+    F.fb_destroy(a)
+    F.fb_destroy(b)
