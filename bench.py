@@ -105,12 +105,16 @@ def cpu_baseline(ds, seconds: float = 15.0):
                        f"(FP64, OpenMP over genes, {dt:.1f} s)")
 
 
-def run_chain(fbmc, diagnostics, ds, args, burnin, post, do_ess, stream, learned, shift=False, exact=False):
+def run_chain(fbmc, diagnostics, ds, args, burnin, post, do_ess, stream, learned, shift=False, exact=False,
+              laplace=False):
     """One chain of the workload: `burnin` sweeps, then `post` post-burn-in
     sweeps of which `steps` (after `warmup`) are timed.  shift=True adds the
     shift step (beta_g + delta, eps_g - X delta, delta from its exact
     conditional) to every sweep; exact=True draws gamma_g, tau and sigma^2
-    directly from their conjugate conditionals.  With learned=True the
+    directly from their conjugate conditionals.  laplace=True takes the
+    independence-MH beta step with the per-gene Laplace approximation alone
+    as the proposal (no network): its last 600 burn-in sweeps calibrate the
+    fallback mask (200 sweeps) and then use the step.  With learned=True the
     last 1,000 burn-in sweeps adapt the learned beta proposal: 400 plain sweeps
     store training pairs (every 4th sweep, 100 x G pairs), the network is
     trained on the GPU, 200 sweeps with the IMH step everywhere calibrate the
@@ -142,6 +146,16 @@ def run_chain(fbmc, diagnostics, ds, args, burnin, post, do_ess, stream, learned
         proposal = {"training_pairs": int(adapt * 2 // 5 // 4) * ds.G, "epochs": 300,
                     "train_seconds": train_s, "loss_first": float(losses[0]), "loss_last": float(losses[-1]),
                     "fallback_fraction": float(fb.mean())}
+    elif laplace:
+        adapt = min(600, burnin)
+        smp.sweep(burnin - adapt)
+        fbmc.fb_set_beta_update(smp.ctx, fbmc.FB_BETA_LAPLACE)
+        fbmc.fb_proposal_calibrate(smp.ctx, adapt // 3, 0.2)
+        smp.sweep(adapt - adapt // 3)
+        smp.sync()
+        fb = fbmc.fb_fallback(smp.ctx)
+        proposal = {"kind": "laplace (no network)", "calibration_sweeps": adapt // 3,
+                    "fallback_fraction": float(fb.mean())}
     else:
         smp.sweep(burnin)
         smp.sync()
@@ -169,7 +183,7 @@ def run_chain(fbmc, diagnostics, ds, args, burnin, post, do_ess, stream, learned
     t1 = time.perf_counter()
     kt = fbmc.fb_kernel_times(smp.ctx)
     fbmc.fb_profile(smp.ctx, 0, 0)
-    if learned:
+    if learned or laplace:
         last = fbmc.fb_imh_last(smp.ctx)
         imh = last >= 0
         proposal["accept_rate_last_sweep"] = float(np.mean(last[imh] == 1)) if imh.any() else None
@@ -395,14 +409,19 @@ def main():
         print(json.dumps({"heavy_workload": run_heavy(fbmc, stream, steps=args.steps, burnin=args.burnin)}),
               flush=True)
         return
-    run = lambda learned, shift, exact=False: run_chain(fbmc, diagnostics, ds, args, burnin, post, do_ess,
-                                                        stream, learned=learned, shift=shift, exact=exact)
+    run = lambda learned, shift, exact=False, laplace=False: run_chain(
+        fbmc, diagnostics, ds, args, burnin, post, do_ess, stream, learned=learned, shift=shift, exact=exact,
+        laplace=laplace)
     plain = run(False, False)
     learned = None if args.no_learned else run(True, False)
     plain_shift = None if args.no_shift else run(False, True)
     learned_shift = None if (args.no_shift or args.no_learned) else run(True, True)
     plain_exact = None if args.no_exact else run(False, False, True)
     plain_shift_exact = None if (args.no_exact or args.no_shift) else run(False, True, True)
+    lap = None if args.no_learned else run(False, False, laplace=True)
+    lap_shift = None if (args.no_learned or args.no_shift) else run(False, True, laplace=True)
+    lap_shift_exact = (None if (args.no_learned or args.no_shift or args.no_exact)
+                       else run(False, True, True, laplace=True))
     sweeps_per_s = plain["sweeps_per_s"]
     ms_per_step = plain["ms_per_sweep"]
     shape = plain["launch"]
@@ -439,7 +458,9 @@ def main():
     learned_info = form(learned, plain)
     forms = {"plain": form(plain, None), "learned": learned_info,
              "plain+shift": form(plain_shift, plain), "learned+shift": form(learned_shift, plain_shift),
-             "plain+exact": form(plain_exact, plain), "plain+shift+exact": form(plain_shift_exact, plain_shift)}
+             "plain+exact": form(plain_exact, plain), "plain+shift+exact": form(plain_shift_exact, plain_shift),
+             "laplace": form(lap, plain), "laplace+shift": form(lap_shift, plain_shift),
+             "laplace+shift+exact": form(lap_shift_exact, plain_shift_exact)}
 
     line = {
         "metric": "Gibbs sweeps/s + min-ESS/s of beta at G=50k,N=16; learned vs plain proposal",
@@ -462,7 +483,9 @@ def main():
         "ess": ess_info,
         "learned_proposal": learned_info,
         "forms": {"note": "ratios: learned vs plain; plain+shift vs plain; learned+shift vs plain+shift; "
-                          "plain+exact vs plain; plain+shift+exact vs plain+shift",
+                          "plain+exact vs plain; plain+shift+exact vs plain+shift; laplace (the IMH step with "
+                          "the Laplace proposal alone, no network) vs plain, laplace+shift vs plain+shift, "
+                          "laplace+shift+exact vs plain+shift+exact",
                   **forms},
         "kernels": kernels,
         "roofline": {"bound": "hbm", "kernel": dom, "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",

@@ -373,7 +373,7 @@ int fb_autotune(fb_ctx *c, int32_t trial_sweeps, int32_t *samples_per_wave, int3
  * Laplace proposal).  Products run on the matrix cores with BF16 operands and
  * FP32 accumulation; parameters are kept in FP32.
  * ---------------------------------------------------------------------- */
-enum fb_beta_update { FB_BETA_SLICE = 0, FB_BETA_LEARNED = 1 };
+enum fb_beta_update { FB_BETA_SLICE = 0, FB_BETA_LEARNED = 1, FB_BETA_LAPLACE = 2 };
 
 /* Host arrays of the network's parameters (FP32, row-major, input index first). */
 typedef struct {
@@ -408,9 +408,14 @@ int fb_proposal_train(fb_ctx *c, const fb_train_opts *o, double *epoch_loss);
 /* Run `sweeps` sweeps in which every gene of every segment takes the IMH
  * step, then set the fallback mask: genes whose acceptance rate was below
  * min_accept keep the slice steps from now on.  Adaptive: call it during
- * burn-in only. */
+ * burn-in only.  With FB_BETA_LAPLACE set it calibrates the Laplace-only
+ * proposal (no network needed), otherwise the network's. */
 int fb_proposal_calibrate(fb_ctx *c, int64_t sweeps, double min_accept);
-/* FB_BETA_SLICE, or FB_BETA_LEARNED (needs a trained or loaded network). */
+/* FB_BETA_SLICE, FB_BETA_LEARNED (needs a trained or loaded network), or
+ * FB_BETA_LAPLACE: the same independence-MH step with the per-gene Laplace
+ * approximation alone as the proposal (the network's correction set to the
+ * identity; no network kernel runs) -- the ablation that shows what the
+ * network adds.  Fallback genes keep the slice steps in either IMH mode. */
 int fb_set_beta_update(fb_ctx *c, int32_t mode);
 /* Copy the network's parameters out, or load new ones (both host arrays). */
 int fb_proposal_get(fb_ctx *c, fb_mlp *out);

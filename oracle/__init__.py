@@ -411,6 +411,8 @@ def _oracle_set_proposal(self, m: dict, fallback_mask=None):
     keep = []
     st = _mlp_struct(m, keep)
     mask = None if fallback_mask is None else np.ascontiguousarray(fallback_mask, dtype=np.int32)
+    if mask is not None and mask.shape != (self.G,):
+        raise ValueError(f"fallback mask must have shape ({self.G},), got {mask.shape}")
     if L.or_set_proposal(self._h, C.byref(st), _p(mask, C.c_int32)) != 0:
         raise ValueError("or_set_proposal failed")
 

@@ -10,6 +10,7 @@
 
 #include <algorithm>
 #include <cmath>
+#include <cstddef>
 #include <cstdio>
 #include <cstring>
 #include <string>
@@ -29,8 +30,8 @@ hipError_t launch_top(const SegInfo *segs, int nseg, int chains, TopState *top, 
                       const SweepArgs &a, hipStream_t st);
 hipError_t launch_shift(int precision, int maxL, const SegInfo *segs, const int2 *tiles, int ntiles,
                         const SweepArgs &a, hipStream_t st);
-hipError_t launch_gb_shift(int precision, int maxL, const SegInfo *segs, const int2 *tiles, int ntiles,
-                           const SweepArgs &a, int *err, hipStream_t st);
+hipError_t launch_gb_shift(int precision, int mode, int maxL, const SegInfo *segs, const int2 *tiles, int ntiles,
+                           const SweepArgs &a, const MlpDev *net, int *err, hipStream_t st);
 hipError_t launch_mlp_sweep(int precision, const SegInfo *segs, const int2 *tiles, int ntiles, const MlpDev *net,
                             hipStream_t st);
 hipError_t launch_philox(const uint4 *ctr, const uint2 *key, uint4 *out, int64_t n, hipStream_t st);
@@ -122,6 +123,7 @@ struct fb_ctx {
     int nfb_items = 0, fb_item_cap = 0;
     float *d_master = nullptr;        // kMlpParams FP32
     MlpDev *d_net = nullptr;          // packed inference copy
+    MlpDev *d_idnet = nullptr;        // output map of the Laplace-only proposal: omean 0, oscale 1
     bool net_ready = false;
     float *d_pairs = nullptr;
     int64_t pair_cap = 0, pair_n = 0, totalG = 0;
@@ -620,6 +622,7 @@ struct SweepMode {
     bool learned = false;         // IMH where the fallback mask is 0
     bool count_imh = false;       // add accepted IMH steps to the counters
     bool no_trace = false;        // trial sweeps of the autotuner: no trace rows
+    bool laplace = false;         // IMH with the Laplace base alone: no network kernel
     int32_t collect_every = 0;
     int64_t collect_slot = 0;
 };
@@ -664,6 +667,7 @@ static SweepArgs next_args(fb_ctx *c, SweepMode &md, int64_t m)
     a.trace_point = -1;
     a.learned = md.learned ? 1 : 0;
     a.count_imh = md.count_imh ? 1 : 0;
+    a.laplace = md.laplace ? 1 : 0;
     a.pair_base = -1;
     a.dev = nullptr;
     a.idx = 0;
@@ -711,8 +715,12 @@ static int launch_sweeps(fb_ctx *c, const SweepArgs *args, int64_t n, const Swee
                           (c->prof_count++ % c->prof_every) == 0;
         const bool shift = (args[i].mask >> kKindShift) & 1u;
         const int gbm = gb_mode_of(md, args[i]);
-        // the slice sweep with the shift step: one kernel for gamma, beta and the shift
-        const bool fused_shift = shift && gbm == 0 && c->fuse_shift;
+        // gamma, beta and the shift in one kernel: the slice steps, or the MH-only
+        // learned kernel when no gene falls back (every beta of a tile is then
+        // drawn by the tile's own workgroup)
+        const bool fused_shift =
+            shift && c->fuse_shift && (gbm == 0 || (gbm == 2 && (!md.learned || c->nfb_items == 0)));
+        const MlpDev *gnet = md.laplace ? c->d_idnet : c->d_net;
         hipEvent_t *pe = prof ? &c->prof_ev[8 * (size_t)c->prof_n] : nullptr;
         if (prof) {
             c->prof_hyp[c->prof_n] = c->fuse ? 0 : 1;
@@ -723,12 +731,14 @@ static int launch_sweeps(fb_ctx *c, const SweepArgs *args, int64_t n, const Swee
                              c->st));
         if (pe) HIPCHK(c, hipEventRecord(pe[1], c->st));
         if (pe) HIPCHK(c, hipEventRecord(pe[2], c->st));
-        if (md.learned) HIPCHK(c, launch_mlp_sweep(c->prec, c->d_segs, c->d_tiles, c->ntiles, c->d_net, c->st));
+        if (md.learned && !md.laplace)
+            HIPCHK(c, launch_mlp_sweep(c->prec, c->d_segs, c->d_tiles, c->ntiles, c->d_net, c->st));
         if (fused_shift)
-            HIPCHK(c, launch_gb_shift(c->prec, c->maxL, c->d_segs, c->d_tiles, c->ntiles, a, c->d_err, c->st));
+            HIPCHK(c, launch_gb_shift(c->prec, gbm, c->maxL, c->d_segs, c->d_tiles, c->ntiles, a, gnet, c->d_err,
+                                      c->st));
         else
             HIPCHK(c, launch_gb(c->prec, gbm, c->maxL, c->d_segs, c->d_tiles, c->ntiles, c->d_fb_items,
-                                md.learned ? c->nfb_items : 0, a, c->d_net, c->d_err, c->st));
+                                md.learned ? c->nfb_items : 0, a, gnet, c->d_err, c->st));
         if (pe) HIPCHK(c, hipEventRecord(pe[3], c->st));
         if (shift && !fused_shift) {
             if (pe) HIPCHK(c, hipEventRecord(pe[6], c->st));
@@ -758,7 +768,8 @@ static std::vector<int64_t> graph_signature(const fb_ctx *c, const SweepMode &md
                                 (int64_t)(uintptr_t)c->d_items, c->nitems, (int64_t)(uintptr_t)c->d_tiles,
                                 c->ntiles, (int64_t)(uintptr_t)c->d_fb_items, md.learned ? c->nfb_items : 0,
                                 (int64_t)(uintptr_t)c->d_net, (int64_t)(uintptr_t)c->d_err,
-                                (int64_t)(uintptr_t)c->st, md.learned ? 1 : 0, c->top_on ? 1 : 0,
+                                (int64_t)(uintptr_t)c->st, md.learned ? 1 : 0, md.laplace ? 1 : 0,
+                                (int64_t)(uintptr_t)c->d_idnet, c->top_on ? 1 : 0,
                                 (int64_t)(uintptr_t)c->d_top};
     sig.push_back(c->fuse_shift ? 1 : 0);
     for (int64_t i = 0; i < n; ++i) {
@@ -865,6 +876,20 @@ int ensure_learned(fb_ctx *c)
     }
     if ((rc = upload_segs(c))) return rc;
     c->learned_ready = true;
+    return FB_OK;
+}
+
+// The output map of the Laplace-only proposal: with no network outputs the
+// independence proposal is the per-gene Laplace base itself (omean 0, oscale
+// 1; the kernels read nothing else of it in that mode).
+int ensure_idnet(fb_ctx *c)
+{
+    if (c->d_idnet) return FB_OK;
+    int rc;
+    if ((rc = dalloc(c, (void **)&c->d_idnet, sizeof(MlpDev)))) return rc;     // zero-filled
+    float one[8];
+    for (float &v : one) v = 1.0f;
+    HIPCHK(c, hipMemcpy((char *)c->d_idnet + offsetof(MlpDev, oscale), one, sizeof(one), hipMemcpyHostToDevice));
     return FB_OK;
 }
 
@@ -1109,8 +1134,9 @@ int fb_sweep(fb_ctx *c, int64_t n)
     if (n < 0) return fail(c, FB_EINVAL, "n must be >= 0");
     if (c->sticky) return c->sticky;
     SweepMode md;
-    md.learned = c->beta_mode == FB_BETA_LEARNED;
+    md.learned = c->beta_mode == FB_BETA_LEARNED || c->beta_mode == FB_BETA_LAPLACE;
     md.learned_kernel = md.learned;
+    md.laplace = c->beta_mode == FB_BETA_LAPLACE;
     return run_sweeps(c, n, md);
 }
 
@@ -1703,8 +1729,9 @@ int fb_autotune(fb_ctx *c, int32_t trial_sweeps, int32_t *samples_per_wave, int3
             if ((rc = build_items(c, spw))) break;
             c->fuse = fz != 0;
             SweepMode md;
-            md.learned = c->beta_mode == FB_BETA_LEARNED;
+            md.learned = c->beta_mode == FB_BETA_LEARNED || c->beta_mode == FB_BETA_LAPLACE;
             md.learned_kernel = md.learned;
+            md.laplace = c->beta_mode == FB_BETA_LAPLACE;
             md.no_trace = true;
             if ((rc = run_sweeps(c, 2, md))) break;               // warm-up
             if ((e = hipStreamSynchronize(c->st)) != hipSuccess) break;
@@ -1869,10 +1896,12 @@ int fb_proposal_calibrate(fb_ctx *c, int64_t sweeps, double min_accept)
 {
     if (!c) return fail(nullptr, FB_EINVAL, "NULL context");
     if (sweeps < 1) return fail(c, FB_EINVAL, "need sweeps >= 1");
-    if (!c->net_ready) return fail(c, FB_ESTATE, "no network: train or load one first");
+    const bool lap = c->beta_mode == FB_BETA_LAPLACE;
+    if (!lap && !c->net_ready) return fail(c, FB_ESTATE, "no network: train or load one first");
     if (c->sticky) return c->sticky;
     int rc;
     if ((rc = ensure_learned(c))) return rc;
+    if (lap && (rc = ensure_idnet(c))) return rc;
     for (auto &S : c->seg) {
         HIPCHK(c, hipMemsetAsync(S.info.fallback, 0, (size_t)S.Gp * sizeof(int32_t), c->st));
         HIPCHK(c, hipMemsetAsync(S.info.imh_count, 0, (size_t)S.Gp * sizeof(int32_t), c->st));
@@ -1881,6 +1910,7 @@ int fb_proposal_calibrate(fb_ctx *c, int64_t sweeps, double min_accept)
     SweepMode md;
     md.learned_kernel = true;
     md.learned = true;
+    md.laplace = lap;
     md.count_imh = true;
     if ((rc = run_sweeps(c, sweeps, md))) return rc;
     HIPCHK(c, hipStreamSynchronize(c->st));
@@ -1896,11 +1926,16 @@ int fb_proposal_calibrate(fb_ctx *c, int64_t sweeps, double min_accept)
 int fb_set_beta_update(fb_ctx *c, int32_t mode)
 {
     if (!c) return fail(nullptr, FB_EINVAL, "NULL context");
-    if (mode != FB_BETA_SLICE && mode != FB_BETA_LEARNED) return fail(c, FB_EINVAL, "unknown beta update");
+    if (mode != FB_BETA_SLICE && mode != FB_BETA_LEARNED && mode != FB_BETA_LAPLACE)
+        return fail(c, FB_EINVAL, "unknown beta update");
     if (mode == FB_BETA_LEARNED) {
         if (!c->net_ready) return fail(c, FB_ESTATE, "no network: train or load one first");
         int rc;
         if ((rc = same_design(c)) || (rc = ensure_learned(c))) return rc;
+    }
+    if (mode == FB_BETA_LAPLACE) {
+        int rc;
+        if ((rc = ensure_learned(c)) || (rc = ensure_idnet(c))) return rc;
     }
     c->beta_mode = mode;
     return FB_OK;

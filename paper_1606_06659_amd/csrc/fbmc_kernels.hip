@@ -889,7 +889,7 @@ __device__ inline void beta_genes(const SegInfo &S, int64_t g, bool active, int6
             }
             // the network's outputs for this gene (mlp_sweep ran before this kernel)
             float om[kMaxL], ol[kMaxL], oo[kMaxOff];
-            const bool use_net = a.learned && mine && upd_beta;
+            const bool use_net = a.learned && mine && upd_beta && !a.laplace;
             const int nof = L * (L - 1) / 2;
 #pragma unroll
             for (int l = 0; l < kMaxL; ++l) {
@@ -1155,19 +1155,21 @@ __global__ __launch_bounds__(256) void shift_sweep(const SegInfo *__restrict__ s
     shift_genes<T, kML>(segs[sidx], tile, a);
 }
 
-// Steps 2 and 5 and the shift step in one launch (the slice sweep with the
-// shift step on): per tile, gamma on wavefront 0 and beta on wavefront 1 as in
-// gb_sweep, a workgroup barrier (the tile's new gamma_g and beta_g are then
-// written and visible to the workgroup), then wavefront 1 shifts the tile.  A
-// tile's shift overlaps other tiles' beta draws instead of waiting for a
-// launch of its own; the arithmetic is that of shift_sweep.  A kernel of its
-// own so that the shift code's registers do not lower the occupancy of
-// gb_sweep.
-template <typename T, int kML>
+// Steps 2 and 5 and the shift step in one launch (the shift step on, with the
+// slice steps (kMode 0) or with the independence-MH beta step when no gene
+// falls back to the slice steps (kMode 2)): per tile, gamma on wavefront 0 and
+// beta on wavefront 1 as in gb_sweep, a workgroup barrier (the tile's new
+// gamma_g and beta_g are then written and visible to the workgroup), then
+// wavefront 1 shifts the tile.  A tile's shift overlaps other tiles' beta
+// draws instead of waiting for a launch of its own; the arithmetic is that of
+// shift_sweep.  A kernel of its own so that the shift code's registers do not
+// lower the occupancy of gb_sweep.
+template <typename T, int kMode, int kML>
 __global__ __launch_bounds__(128) void gb_shift_sweep(const SegInfo *__restrict__ segs,
                                                       const int2 *__restrict__ tiles, int ntiles, SweepArgs a0,
-                                                      int *err)
+                                                      const MlpDev *__restrict__ net, int *err)
 {
+    static_assert(kMode == 0 || kMode == 2, "the fused shift needs every beta of the tile drawn in the tile");
     const SweepArgs a = resolve_args(a0);
     const int wave = __builtin_amdgcn_readfirstlane((int)(threadIdx.x >> 6));
     const int lane = (int)(threadIdx.x & 63);
@@ -1181,7 +1183,7 @@ __global__ __launch_bounds__(128) void gb_shift_sweep(const SegInfo *__restrict_
         gamma_wave<T, kML>(S, tile, a, err);
     } else {
         const int64_t g = (int64_t)tile * kTile + lane;
-        beta_genes<T, 0, kML>(S, g, g < S.G, tile, false, a, nullptr, err);
+        beta_genes<T, kMode, kML>(S, g, g < S.G, tile, false, a, net, err);
     }
     __syncthreads();
     if (wave == 1) shift_genes<T, kML>(S, tile, a);
@@ -1930,18 +1932,35 @@ hipError_t launch_gb(int precision, int mode, int maxL, const SegInfo *segs, con
     return hipGetLastError();
 }
 
-hipError_t launch_gb_shift(int precision, int maxL, const SegInfo *segs, const int2 *tiles, int ntiles,
-                           const SweepArgs &a, int *err, hipStream_t st)
+template <int kMode>
+static void launch_gb_shift_m(int precision, int maxL, const SegInfo *segs, const int2 *tiles, int ntiles,
+                              const SweepArgs &a, const MlpDev *net, int *err, hipStream_t st)
 {
-    if (ntiles <= 0) return hipSuccess;
     const dim3 grid((unsigned)ntiles), block(128);
     if (precision == 1) {
-        if (maxL <= 5) hipLaunchKernelGGL((gb_shift_sweep<float, 5>), grid, block, 0, st, segs, tiles, ntiles, a, err);
-        else hipLaunchKernelGGL((gb_shift_sweep<float, kMaxL>), grid, block, 0, st, segs, tiles, ntiles, a, err);
+        if (maxL <= 5)
+            hipLaunchKernelGGL((gb_shift_sweep<float, kMode, 5>), grid, block, 0, st, segs, tiles, ntiles, a, net, err);
+        else
+            hipLaunchKernelGGL((gb_shift_sweep<float, kMode, kMaxL>), grid, block, 0, st, segs, tiles, ntiles, a, net,
+                               err);
     } else {
-        if (maxL <= 5) hipLaunchKernelGGL((gb_shift_sweep<double, 5>), grid, block, 0, st, segs, tiles, ntiles, a, err);
-        else hipLaunchKernelGGL((gb_shift_sweep<double, kMaxL>), grid, block, 0, st, segs, tiles, ntiles, a, err);
+        if (maxL <= 5)
+            hipLaunchKernelGGL((gb_shift_sweep<double, kMode, 5>), grid, block, 0, st, segs, tiles, ntiles, a, net,
+                               err);
+        else
+            hipLaunchKernelGGL((gb_shift_sweep<double, kMode, kMaxL>), grid, block, 0, st, segs, tiles, ntiles, a,
+                               net, err);
     }
+}
+
+// mode 0: slice steps; 2: the MH-only learned kernel (no fallback groups)
+hipError_t launch_gb_shift(int precision, int mode, int maxL, const SegInfo *segs, const int2 *tiles, int ntiles,
+                           const SweepArgs &a, const MlpDev *net, int *err, hipStream_t st)
+{
+    if (ntiles <= 0) return hipSuccess;
+    if (mode == 0) launch_gb_shift_m<0>(precision, maxL, segs, tiles, ntiles, a, net, err, st);
+    else if (mode == 2) launch_gb_shift_m<2>(precision, maxL, segs, tiles, ntiles, a, net, err, st);
+    else return hipErrorInvalidValue;
     return hipGetLastError();
 }
 

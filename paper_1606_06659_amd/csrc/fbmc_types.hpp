@@ -127,6 +127,7 @@ struct SweepArgs {
     int32_t dbg;          // write per-draw records
     int32_t learned;      // beta by independence MH where the fallback mask is 0
     int32_t count_imh;    // add accepted IMH steps to imh_count
+    int32_t laplace;      // the IMH proposal is the Laplace base alone (no network outputs)
     int64_t pair_base;    // collect (features, beta) pairs at row pair_base + g, or -1
     // graph replay: when dev is set, the kernel takes its arguments from
     // dev[idx] (written before each replay) and ignores the fields above

@@ -509,7 +509,7 @@ class Sampler:
 # ---------------------------------------------------------------------------
 # Learned beta proposal
 # ---------------------------------------------------------------------------
-FB_BETA_SLICE, FB_BETA_LEARNED = 0, 1
+FB_BETA_SLICE, FB_BETA_LEARNED, FB_BETA_LAPLACE = 0, 1, 2
 MLP_F, MLP_H, MLP_O = 32, 128, 64
 
 _FP = C.POINTER(C.c_float)
@@ -609,6 +609,8 @@ def fb_fallback(ctx, seg: int = 0, set_mask=None) -> np.ndarray:
     setp = None
     if set_mask is not None:
         sm = np.ascontiguousarray(set_mask, dtype=np.int32)
+        if sm.shape != (G,):
+            raise ValueError(f"fallback mask must have shape ({G},), got {sm.shape}")
         setp = _p(sm, C.c_int32)
     _check(load().fb_fallback(ctx, seg, _p(get, C.c_int32), setp), ctx)
     return get

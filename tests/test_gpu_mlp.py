@@ -198,13 +198,13 @@ def test_imh_sweep_parity_with_fallback_genes_fp64(oracle_lib, shift):
     off = np.round(np.random.default_rng(13).uniform(-0.3, 0.3, L * (L - 1) // 2) * 64) / 64
     m = constant_model(L, mu, log_s, off=off)
     mask = (np.random.default_rng(14).uniform(size=ds.G) < 0.3).astype(np.int32)
+    upd = F.FB_UPDATE_ALL | (F.FB_SHIFT if shift else 0)
     # hand the state over before the end of burn-in, so that both sides
     # accumulate the running moments over the same post-burn-in sweeps
-    mask = F.FB_UPDATE_ALL | (F.FB_SHIFT if shift else 0)
-    o = oracle_lib.Oracle(ds.y, ds.X, ds.h, seed=19, burnin=10, tune_start=2, update_mask=mask)
+    o = oracle_lib.Oracle(ds.y, ds.X, ds.h, seed=19, burnin=10, tune_start=2, update_mask=upd)
     o.sweep(7)
     opts = F.fb_default_options(precision=0, jitter=0, debug_counts=1, burnin=10, tune_start=2,
-                                update_mask=mask)
+                                update_mask=upd)
     g = F.fb_create(ds.y, ds.X, ds.h, seed=19, options=opts)
     F.fb_set_state(g, o.get_state())
     F.fb_proposal_set(g, to_gpu_params(m, L))
@@ -218,12 +218,103 @@ def test_imh_sweep_parity_with_fallback_genes_fp64(oracle_lib, shift):
         acc_o, _ = o.imh()
         acc_g = F.fb_imh_last(g)
         assert np.array_equal(acc_o, acc_g), (it, np.flatnonzero(acc_o != acc_g)[:5])
-        assert np.all(acc_g[mask == 1] == -1)
+        assert np.all(acc_g[mask == 1] == -1) and np.all(acc_g[mask == 0] >= 0)
         for k in ("eps", "gam", "beta", "hyp", "w_beta", "waux_beta"):
             np.testing.assert_allclose(sg[k], so[k], rtol=1e-9, atol=1e-12, err_msg=f"sweep {it} {k}")
         np.testing.assert_allclose(F.fb_reductions(g), o.reductions(), rtol=1e-9, atol=1e-9)
     sm, om = F.fb_summaries(g), o.moments()
     np.testing.assert_allclose(sm["mean_beta"], om["mean_beta"], rtol=1e-9, atol=1e-12)
+    F.fb_destroy(g)
+
+
+@pytest.mark.parametrize("precision", [0, 1])
+def test_laplace_mode_equals_zero_network(precision):
+    """FB_BETA_LAPLACE (no network kernel) and FB_BETA_LEARNED with a network
+    whose outputs are all zero (omean 0, oscale 1) propose the same Laplace
+    base, so the chains agree bit for bit, fallback genes included."""
+    F = require_gpu()
+    ds = datagen.paper_design_16(G=900, seed=21)
+    L = ds.L
+    opts = F.fb_default_options(precision=precision, jitter=0, burnin=10, tune_start=2)
+    mask = (np.random.default_rng(22).uniform(size=ds.G) < 0.2).astype(np.int32)
+    ctx = []
+    for mode in ("laplace", "zero_net"):
+        g = F.fb_create(ds.y, ds.X, ds.h, seed=23, options=opts)
+        F.fb_sweep(g, 6)
+        if mode == "zero_net":
+            F.fb_proposal_set(g, to_gpu_params(constant_model(L, np.zeros(L), np.zeros(L)), L))
+            F.fb_set_beta_update(g, F.FB_BETA_LEARNED)
+        else:
+            F.fb_set_beta_update(g, F.FB_BETA_LAPLACE)
+        F.fb_fallback(g, 0, mask)
+        ctx.append(g)
+    for n in (5, 9):
+        for g in ctx:
+            F.fb_sweep(g, n)
+        sa, sb = F.fb_get_state(ctx[0]), F.fb_get_state(ctx[1])
+        for k in ("eps", "gam", "beta", "hyp"):
+            assert np.array_equal(sa[k], sb[k]), (n, k)
+        assert np.array_equal(F.fb_imh_last(ctx[0]), F.fb_imh_last(ctx[1]))
+    last = F.fb_imh_last(ctx[0])
+    assert np.all(last[mask == 1] == -1) and np.all(last[mask == 0] >= 0)
+    for g in ctx:
+        F.fb_destroy(g)
+
+
+@pytest.mark.parametrize("shift,frac", [(0, 0.25), (1, 0.25), (1, 0.0)])
+def test_laplace_mode_parity_fp64(oracle_lib, shift, frac):
+    """The Laplace-only proposal against the oracle's IMH step with a
+    zero-output network, with fallback genes (their slice steps in groups of
+    their own) or none (with the shift step: the fused MH and shift kernel),
+    optionally with the shift step."""
+    F = require_gpu()
+    ds = datagen.paper_design_16(G=600, seed=24)
+    L = ds.L
+    m = constant_model(L, np.zeros(L), np.zeros(L))
+    mask = (np.random.default_rng(25).uniform(size=ds.G) < frac).astype(np.int32)
+    upd = F.FB_UPDATE_ALL | (F.FB_SHIFT if shift else 0)
+    o = oracle_lib.Oracle(ds.y, ds.X, ds.h, seed=26, burnin=10, tune_start=2, update_mask=upd)
+    o.sweep(7)
+    opts = F.fb_default_options(precision=0, jitter=0, debug_counts=1, burnin=10, tune_start=2,
+                                update_mask=upd)
+    g = F.fb_create(ds.y, ds.X, ds.h, seed=26, options=opts)
+    F.fb_set_state(g, o.get_state())
+    F.fb_set_beta_update(g, F.FB_BETA_LAPLACE)
+    F.fb_fallback(g, 0, mask)
+    o.set_proposal(m, mask)
+    n_acc = 0
+    for it in range(12):
+        o.sweep(1)
+        F.fb_sweep(g, 1)
+        so, sg = o.get_state(), F.fb_get_state(g)
+        acc_o, _ = o.imh()
+        acc_g = F.fb_imh_last(g)
+        assert np.array_equal(acc_o, acc_g), (it, np.flatnonzero(acc_o != acc_g)[:5])
+        n_acc += int(np.sum(acc_g == 1))
+        for k in ("eps", "gam", "beta", "hyp"):
+            np.testing.assert_allclose(sg[k], so[k], rtol=1e-9, atol=1e-12, err_msg=f"sweep {it} {k}")
+    assert 0 < n_acc < 12 * int((mask == 0).sum())
+    sm, om = F.fb_summaries(g), o.moments()
+    np.testing.assert_allclose(sm["mean_beta"], om["mean_beta"], rtol=1e-9, atol=1e-12)
+    F.fb_destroy(g)
+
+
+def test_laplace_calibration_needs_no_network():
+    F = require_gpu()
+    ds = datagen.paper_design_16(G=800, seed=27)
+    g = F.fb_create(ds.y, ds.X, ds.h, seed=28, options=F.fb_default_options(precision=1, burnin=200,
+                                                                            tune_start=20))
+    F.fb_sweep(g, 100)
+    with pytest.raises(F.FbError):
+        F.fb_proposal_calibrate(g, 20, 0.2)          # the network's proposal: no network yet
+    F.fb_set_beta_update(g, F.FB_BETA_LAPLACE)
+    F.fb_proposal_calibrate(g, 40, 0.2)
+    fb = F.fb_fallback(g)
+    assert set(np.unique(fb)) <= {0, 1}
+    F.fb_sweep(g, 20)
+    last = F.fb_imh_last(g)
+    assert np.all(last[fb == 1] == -1) and np.all(last[fb == 0] >= 0)
+    say("laplace calibration: fallback fraction", fb.mean(), "acceptance", np.mean(last[fb == 0] == 1))
     F.fb_destroy(g)
 
 

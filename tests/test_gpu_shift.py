@@ -89,11 +89,12 @@ def test_fp32_shift_step_matches_oracle(oracle_lib):
     F.fb_destroy(g)
 
 
-@pytest.mark.parametrize("precision", [0, 1])
-def test_fused_and_separate_shift_kernels_agree(precision):
+@pytest.mark.parametrize("precision,beta", [(0, "slice"), (1, "slice"), (0, "laplace"), (1, "laplace")])
+def test_fused_and_separate_shift_kernels_agree(precision, beta):
     """The shift step inside the gamma/beta kernel (the default) and in a
     kernel of its own give the same chain bit for bit, also under graph replay
-    and with events, trace and moments on."""
+    and with events, trace and moments on; with the slice steps and with the
+    independence-MH beta step (Laplace proposal, no fallback genes)."""
     F = require_gpu()
     ds = datagen.paper_design_16(G=1500, seed=4)
     opts = F.fb_default_options(burnin=15, tune_start=3, precision=precision, jitter=0,
@@ -105,6 +106,9 @@ def test_fused_and_separate_shift_kernels_agree(precision):
     ev = [[(np.array([0.0, 2.0, 0.0, 1.0, 0.0]), 0.0)]]
     for g in (a, b):
         F.fb_set_contrasts(g, ev, 5)
+        if beta == "laplace":
+            F.fb_set_beta_update(g, F.FB_BETA_LAPLACE)
+            F.fb_fallback(g, 0, np.zeros(ds.G, np.int32))
     for i, n in enumerate((12, 9, 20)):
         if i == 2:
             F.fb_set_graph(a, 5)
@@ -120,5 +124,8 @@ def test_fused_and_separate_shift_kernels_agree(precision):
             assert np.array_equal(np.asarray(ma[k]), np.asarray(mb[k])), (i, k)
         assert np.array_equal(F.fb_trace(a)[0], F.fb_trace(b)[0])
         assert np.array_equal(F.fb_event_counts(a, 1)[0], F.fb_event_counts(b, 1)[0])
+        if beta == "laplace":
+            assert np.array_equal(F.fb_imh_last(a), F.fb_imh_last(b))
+            assert np.all(F.fb_imh_last(a) >= 0)
     F.fb_destroy(a)
     F.fb_destroy(b)
