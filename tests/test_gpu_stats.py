@@ -51,3 +51,48 @@ def test_posterior_means_within_mcse(oracle_lib):
     r = compare(hyp, gam, beta, *a)
     say("gpu vs oracle", r)
     assert agree(r), r
+
+
+@pytest.mark.parametrize("form", ["shift_exact", "laplace_shift_exact", "three_level_top_fixed"])
+def test_other_forms_agree_with_the_oracle(oracle_lib, form):
+    """The options that leave the posterior invariant -- the shift step with
+    the exact conjugate draws; the same with the Laplace independence step
+    (calibrated during burn-in); a three-level context whose top level is held
+    at the two-level priors (b = 1, psi = 0, one group) -- give posterior means
+    that agree with an oracle chain by the same criteria.  The oracle chain
+    takes the shift step and the exact draws too: over 2,000 sweeps the plain
+    chain's sigma^2 has not mixed (two plain oracle chains already differ by
+    z = 4.4 in sigma_2^2, and plain against shifted oracle chains by 8), while
+    two shifted oracle chains agree to |z| < 3 on every hyperparameter."""
+    F = require_gpu()
+    ds = datagen.small_two_group(G=1000, seed=0)
+    G, L = ds.G, ds.L
+    post = ITERS - BURNIN
+    mask = F.FB_UPDATE_ALL | F.FB_SHIFT | F.FB_EXACT
+    a = oracle_draws(oracle_lib.Oracle(ds.y, ds.X, ds.h, seed=31, burnin=BURNIN, tune_start=BURNIN // 10,
+                                       threads=min(8, os.cpu_count() or 1), update_mask=mask), ds)
+    opts = F.fb_default_options(burnin=BURNIN, tune_start=BURNIN // 10, precision=1, jitter=0, thin=1,
+                                trace_genes=G, trace_after_burnin=1, trace_capacity=post, update_mask=mask)
+    if form == "three_level_top_fixed":
+        g = F.fb_create_batch([dict(counts=ds.y, X=ds.X, h=ds.h, seed=32)], opts)
+        F.fb_set_top_level(g, 1.0, 1.0, np.full(L, 10.0), 33, 0)
+    else:
+        g = F.fb_create(ds.y, ds.X, ds.h, seed=32, options=opts)
+    say("gpu chain", form, ITERS, "sweeps")
+    if form == "laplace_shift_exact":
+        F.fb_sweep(g, BURNIN - 300)
+        F.fb_set_beta_update(g, F.FB_BETA_LAPLACE)
+        F.fb_proposal_calibrate(g, 100, 0.2)
+        F.fb_sweep(g, ITERS - (BURNIN - 300) - 100)
+        say("laplace fallback fraction", F.fb_fallback(g).mean())
+    else:
+        F.fb_sweep(g, ITERS)
+    tr, dropped = F.fb_trace(g)
+    F.fb_destroy(g)
+    assert tr.shape[0] == post and dropped == 0
+    tr = tr.astype(np.float64)
+    hyp = tr[:, :2 + 2 * L]
+    genes = tr[:, 2 + 2 * L:].reshape(post, G, L + 1)
+    r = compare(hyp, genes[:, :, 0], genes[:, :, 1:], *a)
+    say("gpu", form, "vs oracle", r)
+    assert agree(r), r

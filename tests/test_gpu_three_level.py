@@ -160,3 +160,26 @@ def test_top_level_argument_errors():
     with pytest.raises(F.FbError):
         F.fb_set_top_level(g, 1.0, 1.0, np.ones(2), 0, 3)
     F.fb_destroy(g)
+
+
+@pytest.mark.parametrize("precision", [0, 1])
+def test_top_level_at_the_two_level_priors_reproduces_the_two_level_chain(precision):
+    """A top level held at b = the datasets' prior rate and psi = 0 (mask 0)
+    changes nothing: the chain equals the two-level context's bit for bit."""
+    F = require_gpu()
+    dss = _datasets()
+    opts = F.fb_default_options(burnin=10, tune_start=2, precision=precision, jitter=0, chains=2)
+    spec = [dict(counts=d.y, X=d.X, h=d.h, seed=40 + k) for k, d in enumerate(dss)]
+    a = F.fb_create_batch(spec, opts)
+    b = F.fb_create_batch(spec, opts)
+    F.fb_set_top_level(b, 2.0, 3.0, np.array([1.0, 1.0]), 9, 0)
+    F.fb_sweep(a, 25)
+    F.fb_sweep(b, 25)
+    for seg in range(F.fb_num_segments(a)):
+        sa, sb = F.fb_get_state(a, seg), F.fb_get_state(b, seg)
+        for key in STATE_KEYS:
+            assert np.array_equal(sa[key], sb[key]), (seg, key)
+    t = F.fb_get_top(b, 1)
+    assert t["b"] == 1.0 and np.all(t["psi"] == 0.0)
+    F.fb_destroy(a)
+    F.fb_destroy(b)
