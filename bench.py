@@ -161,7 +161,8 @@ def run_chain(fbmc, diagnostics, ds, args, burnin, post, do_ess, stream, learned
         smp.sync()
     if args.launch == "auto":
         spw, fuse, ms, tried = fbmc.fb_autotune(smp.ctx, 50)
-        shape = {"samples_per_wave": spw, "fused_hyper": fuse, "autotuned_ms_per_sweep": ms,
+        shape = {"samples_per_wave": spw, "fused_hyper": fuse, "beta_lanes": fbmc.fb_get_beta_lanes(smp.ctx),
+                 "autotuned_ms_per_sweep": ms,
                  "tried_ms_per_sweep": {f"{k[0]},{k[1]}": v for k, v in tried.items()}}
     else:
         spw, fuse = (int(v) for v in args.launch.split(","))
@@ -265,8 +266,12 @@ def run_small(fbmc, stream, steps=2000, graph_sweeps=50):
         opts = fbmc.fb_default_options(burnin=500, tune_start=50, precision=fbmc.FB_FP64, jitter=0,
                                        stream=stream.cuda_stream)
         smp = fbmc.Sampler(ds.y, ds.X, ds.h, seed=1, **{f: getattr(opts, f) for f, *_ in opts._fields_})
-        fbmc.fb_set_graph(smp.ctx, k)
         smp.sweep(600)
+        smp.sync()
+        spw, fuse, _, _ = fbmc.fb_autotune(smp.ctx, 50)
+        out["launch"] = {"samples_per_wave": spw, "fused_hyper": fuse, "beta_lanes": fbmc.fb_get_beta_lanes(smp.ctx)}
+        fbmc.fb_set_graph(smp.ctx, k)
+        smp.sweep(graph_sweeps)
         smp.sync()
         torch.cuda.synchronize()
         t0 = time.perf_counter()
@@ -297,7 +302,8 @@ def run_batched(fbmc, stream, steps=100, burnin=200, graph_sweeps=25):
     fbmc.fb_sync(ctx)
     spw, fuse, _, _ = fbmc.fb_autotune(ctx, 10)
     out = {"workload": f"batched: 64 datasets, {genes} genes in total, N in {{4, 8, 16}}, 1 chain each",
-           "genes": genes, "steps": steps, "launch": {"samples_per_wave": spw, "fused_hyper": fuse},
+           "genes": genes, "steps": steps,
+           "launch": {"samples_per_wave": spw, "fused_hyper": fuse, "beta_lanes": fbmc.fb_get_beta_lanes(ctx)},
            "graph_sweeps": graph_sweeps}
     for name, k in (("direct", 0), ("graph", graph_sweeps)):
         fbmc.fb_set_graph(ctx, k)

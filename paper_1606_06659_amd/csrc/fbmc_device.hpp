@@ -160,6 +160,76 @@ __device__ inline T slice_draw(F &f, T x0, T w, uint32_t k0, uint32_t k1, uint4 
     return x1;
 }
 
+// The same draw by a pair of lanes (2j and 2j + 1, which hold the same
+// variable and the same f).  The step-out to the left (even lane) and to the
+// right (odd lane) do not depend on each other and run at the same time.  In
+// the shrink phase the even lane evaluates candidate t + 1 and the odd lane
+// candidate t + 2 on the interval that rejecting candidate t + 1 leaves (an
+// update of the interval depends only on the candidate and x0); the first
+// candidate in the slice is the sequential result.  Points, decisions, the
+// result and the counters are those of slice_draw; both lanes return them,
+// and both must call (the mates exchange values with __shfl).
+template <typename T, typename F>
+__device__ inline T slice_draw_pair(F &f, T x0, T w, uint32_t k0, uint32_t k1, uint4 ctr, int K, int cap,
+                                    DrawRec &rec)
+{
+    const int lane = (int)(threadIdx.x & 63);
+    const bool odd = (lane & 1) != 0;
+    const int even_lane = lane & ~1, odd_lane = lane | 1;
+    uint4 r = philox4x32_10(ctr, k0, k1);
+    const T thr = f.base(x0) + dlog(u01<T>(r.x));
+    const T v = w * uwin<T>(r.y);
+    const T L0 = x0 - v;
+    const T R0 = L0 + w;
+    const int KL = (int)(r.y & (uint32_t)K);
+    const int KR = K - KL;
+    // step out: the left end on the even lane, the right end on the odd lane
+    const int kb = odd ? KR : KL;
+    T e = odd ? R0 : L0;
+    int ns = 0;
+    while (ns < kb) {
+        if (!(f(e) > thr)) break;
+        e = odd ? e + w : e - w;
+        ++ns;
+    }
+    T L = __shfl(e, even_lane, 64), R = __shfl(e, odd_lane, 64);
+    const int nl = __shfl(ns, even_lane, 64), nr = __shfl(ns, odd_lane, 64);
+    // shrink: candidates t + 1 and t + 2 read words t + 2 and t + 3 of the
+    // draw's stream (t even, so both sit in one Philox block)
+    T x1 = x0;
+    int t = 0;
+    bool bad = false;
+    uint32_t blk = 0;
+    for (;;) {
+        const uint32_t q = (uint32_t)t + 2u;
+        if ((q >> 2) != blk) {
+            blk = q >> 2;
+            r = philox4x32_10(make_uint4(ctr.x, ctr.y, ctr.z, (ctr.w & 0xFFFF0000u) | blk), k0, k1);
+        }
+        const T ua = u01<T>((q & 2u) ? r.z : r.x), ub = u01<T>((q & 2u) ? r.w : r.y);
+        const T xa = L + ua * (R - L);
+        const bool ga = xa > x0;
+        const T La = ga ? L : xa, Ra = ga ? xa : R;
+        const T xb = La + ub * (Ra - La);
+        const int in = f(odd ? xb : xa) > thr ? 1 : 0;
+        const int in_a = __shfl(in, even_lane, 64), in_b = __shfl(in, odd_lane, 64);
+        if (in_a) { x1 = xa; t += 1; break; }
+        if (t + 1 >= cap) { t += 1; bad = true; break; }
+        if (in_b) { x1 = xb; t += 2; break; }
+        const bool gb = xb > x0;
+        L = gb ? La : xb;
+        R = gb ? xb : Ra;
+        t += 2;
+        if (t >= cap) { bad = true; break; }
+    }
+    rec.kl = KL;
+    rec.nl = nl;
+    rec.nr = nr;
+    rec.nc = t;
+    rec.bad = bad;
+    return x1;
+}
+
 // The same draw by a whole wavefront for one scalar (hyperparameters).  One
 // round of evaluations covers the reference point x0 (lane 63) and the
 // step-out points L - k w (lanes 0..15) and R + k w (lanes 32..47); the first

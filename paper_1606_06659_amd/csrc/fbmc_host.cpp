@@ -32,6 +32,8 @@ hipError_t launch_shift(int precision, int maxL, const SegInfo *segs, const int2
                         const SweepArgs &a, hipStream_t st);
 hipError_t launch_gb_shift(int precision, int mode, int maxL, const SegInfo *segs, const int2 *tiles, int ntiles,
                            const SweepArgs &a, const MlpDev *net, int *err, hipStream_t st);
+hipError_t launch_gb_pair(int precision, int maxL, const SegInfo *segs, const int2 *tiles, int ntiles,
+                          const SweepArgs &a, int *err, hipStream_t st);
 hipError_t launch_mlp_sweep(int precision, const SegInfo *segs, const int2 *tiles, int ntiles, const MlpDev *net,
                             hipStream_t st);
 hipError_t launch_philox(const uint4 *ctr, const uint2 *key, uint4 *out, int64_t n, hipStream_t st);
@@ -140,6 +142,8 @@ struct fb_ctx {
     // the slice sweep with the shift step runs gamma, beta and the shift in
     // one kernel (true) or the shift in a kernel of its own (false)
     bool fuse_shift = true;
+    // lanes per gene in the slice sweep's beta draws (1: gb_sweep, 2: gb_pair_sweep)
+    int beta_lanes = 1;
     // three-level form (fb_set_top_level): one TopState per chain
     bool top_on = false;
     TopState *d_top = nullptr;
@@ -736,6 +740,8 @@ static int launch_sweeps(fb_ctx *c, const SweepArgs *args, int64_t n, const Swee
         if (fused_shift)
             HIPCHK(c, launch_gb_shift(c->prec, gbm, c->maxL, c->d_segs, c->d_tiles, c->ntiles, a, gnet, c->d_err,
                                       c->st));
+        else if (gbm == 0 && !shift && c->beta_lanes == 2)
+            HIPCHK(c, launch_gb_pair(c->prec, c->maxL, c->d_segs, c->d_tiles, c->ntiles, a, c->d_err, c->st));
         else
             HIPCHK(c, launch_gb(c->prec, gbm, c->maxL, c->d_segs, c->d_tiles, c->ntiles, c->d_fb_items,
                                 md.learned ? c->nfb_items : 0, a, gnet, c->d_err, c->st));
@@ -772,6 +778,7 @@ static std::vector<int64_t> graph_signature(const fb_ctx *c, const SweepMode &md
                                 (int64_t)(uintptr_t)c->d_idnet, c->top_on ? 1 : 0,
                                 (int64_t)(uintptr_t)c->d_top};
     sig.push_back(c->fuse_shift ? 1 : 0);
+    sig.push_back(c->beta_lanes);
     for (int64_t i = 0; i < n; ++i) {
         sig.push_back(gb_mode_of(md, args[i]));
         sig.push_back((args[i].mask >> kKindShift) & 1u);
@@ -1640,6 +1647,16 @@ int fb_set_launch(fb_ctx *c, int32_t samples_per_wave, int32_t fuse_hyper)
     return FB_OK;
 }
 
+int fb_set_beta_lanes(fb_ctx *c, int32_t lanes)
+{
+    if (!c) return fail(nullptr, FB_EINVAL, "NULL context");
+    if (lanes != 1 && lanes != 2) return fail(c, FB_EINVAL, "lanes must be 1 or 2");
+    c->beta_lanes = lanes;
+    return FB_OK;
+}
+
+int32_t fb_get_beta_lanes(const fb_ctx *c) { return c ? c->beta_lanes : 0; }
+
 int fb_set_shift_fusion(fb_ctx *c, int32_t fused)
 {
     if (!c) return fail(nullptr, FB_EINVAL, "NULL context");
@@ -1720,32 +1737,50 @@ int fb_autotune(fb_ctx *c, int32_t trial_sweeps, int32_t *samples_per_wave, int3
     bool best_fuse = fuse0;
     double best = 1e300;
     hipError_t e = copy_all(true);
+    // one trial from the saved state: two warm-up sweeps, then trial_sweeps timed
+    auto trial = [&](double &per) -> bool {
+        SweepMode md;
+        md.learned = c->beta_mode == FB_BETA_LEARNED || c->beta_mode == FB_BETA_LAPLACE;
+        md.learned_kernel = md.learned;
+        md.laplace = c->beta_mode == FB_BETA_LAPLACE;
+        md.no_trace = true;
+        if ((rc = run_sweeps(c, 2, md))) return false;
+        if ((e = hipStreamSynchronize(c->st)) != hipSuccess) return false;
+        if ((rc = run_sweeps(c, trial_sweeps, md))) return false;
+        if ((e = hipEventSynchronize(c->ev1)) != hipSuccess) return false;
+        float ms = 0;
+        if ((e = hipEventElapsedTime(&ms, c->ev0, c->ev1)) != hipSuccess) return false;
+        per = ms / trial_sweeps;
+        c->m = m0;
+        e = copy_all(false);
+        return e == hipSuccess;
+    };
     if (table)
         for (int i = 0; i < 8; ++i) table[i] = -1.0;
     for (int k = 0; e == hipSuccess && rc == FB_OK && k < 8; ++k) {
         const int spw = 1 << (k >> 1), fz = k & 1;
         if (spw > std::min(maxN, 8)) continue;
-        {
-            if ((rc = build_items(c, spw))) break;
-            c->fuse = fz != 0;
-            SweepMode md;
-            md.learned = c->beta_mode == FB_BETA_LEARNED || c->beta_mode == FB_BETA_LAPLACE;
-            md.learned_kernel = md.learned;
-            md.laplace = c->beta_mode == FB_BETA_LAPLACE;
-            md.no_trace = true;
-            if ((rc = run_sweeps(c, 2, md))) break;               // warm-up
-            if ((e = hipStreamSynchronize(c->st)) != hipSuccess) break;
-            if ((rc = run_sweeps(c, trial_sweeps, md))) break;
-            if ((e = hipEventSynchronize(c->ev1)) != hipSuccess) break;
-            float ms = 0;
-            if ((e = hipEventElapsedTime(&ms, c->ev0, c->ev1)) != hipSuccess) break;
-            const double per = ms / trial_sweeps;
-            if (table) table[k] = per;
-            if (per < best) { best = per; best_spw = spw; best_fuse = fz != 0; }
-            c->m = m0;
-            e = copy_all(false);
+        if ((rc = build_items(c, spw))) break;
+        c->fuse = fz != 0;
+        double per = 0.0;
+        if (!trial(per)) break;
+        if (table) table[k] = per;
+        if (per < best) { best = per; best_spw = spw; best_fuse = fz != 0; }
+    }
+    // with the slice steps for beta, the other number of lanes per gene at the best shape
+    const int lanes0 = c->beta_lanes;
+    int best_lanes = lanes0;
+    const bool slice_beta = c->beta_mode == FB_BETA_SLICE && !((c->opt.update_mask >> kKindShift) & 1u);
+    if (slice_beta && e == hipSuccess && rc == FB_OK && (rc = build_items(c, best_spw)) == FB_OK) {
+        c->fuse = best_fuse;
+        c->beta_lanes = 3 - lanes0;
+        double per = 0.0;
+        if (trial(per) && per < best) {
+            best = per;
+            best_lanes = c->beta_lanes;
         }
     }
+    c->beta_lanes = best_lanes;
     c->m = m0;
     if (e == hipSuccess) e = copy_all(false);
     (void)hipFree(snap);

@@ -77,7 +77,7 @@ EXPORTS = [
     "fb_num_segments", "fb_segment_dims", "fb_get_state", "fb_set_state", "fb_summaries",
     "fb_trace_genes", "fb_trace", "fb_trace_reset", "fb_debug_counts", "fb_reductions",
     "fb_philox", "fb_last_sweep_time", "fb_profile", "fb_kernel_times", "fb_set_graph", "fb_get_graph",
-    "fb_set_contrasts", "fb_event_counts", "fb_set_top_level", "fb_get_top", "fb_set_top", "fb_set_shift_fusion",
+    "fb_set_contrasts", "fb_event_counts", "fb_set_top_level", "fb_get_top", "fb_set_top", "fb_set_shift_fusion", "fb_set_beta_lanes", "fb_get_beta_lanes",
     "fb_set_launch",
     "fb_get_launch", "fb_autotune", "fb_last_error",
     "fb_strerror", "fb_default_train_opts", "fb_proposal_collect", "fb_proposal_train",
@@ -132,6 +132,9 @@ def load() -> C.CDLL:
     L.fb_get_top.argtypes = [vp, i32, _DP, _DP, _DP, _DP, C.POINTER(i32)]
     L.fb_set_top.argtypes = [vp, i32, C.c_double, _DP]
     L.fb_set_shift_fusion.argtypes = [vp, i32]
+    L.fb_set_beta_lanes.argtypes = [vp, i32]
+    L.fb_get_beta_lanes.argtypes = [vp]
+    L.fb_get_beta_lanes.restype = i32
     L.fb_get_graph.argtypes = [vp]
     L.fb_get_graph.restype = C.c_int32
     L.fb_set_launch.argtypes = [vp, i32, i32]
@@ -405,6 +408,15 @@ def fb_set_top(ctx, chain: int, b: float, psi):
 def fb_set_shift_fusion(ctx, fused: bool):
     """Shift step in the gamma/beta kernel (True, default) or in a kernel of its own."""
     _check(load().fb_set_shift_fusion(ctx, 1 if fused else 0), ctx)
+
+
+def fb_set_beta_lanes(ctx, lanes: int):
+    """Lanes per gene (1 or 2) in the beta draws of the slice sweep."""
+    _check(load().fb_set_beta_lanes(ctx, int(lanes)), ctx)
+
+
+def fb_get_beta_lanes(ctx) -> int:
+    return int(load().fb_get_beta_lanes(ctx))
 
 
 def fb_set_graph(ctx, sweeps: int):
