@@ -58,3 +58,18 @@ def test_defaults_and_errors_without_device():
     with pytest.raises(fbmc.FbError):
         fbmc.fb_create(np.zeros((3, 9), np.int32), many_rows, np.zeros(9))
     fbmc.fb_destroy(None)   # no-op
+
+
+def test_new_entry_points_reject_a_null_context():
+    """Launch choices, the three-level calls and the Laplace mode fail cleanly
+    (FB_EINVAL) on a NULL context, before any device call."""
+    import ctypes as C
+    from paper_1606_06659_amd import fbmc
+    lib = fbmc.load()
+    assert lib.fb_set_beta_lanes(None, 2) == fbmc.FB_EINVAL
+    assert lib.fb_get_beta_lanes(None) == 0
+    assert lib.fb_set_shift_fusion(None, 1) == fbmc.FB_EINVAL
+    assert lib.fb_set_top_level(None, None) == fbmc.FB_EINVAL
+    assert lib.fb_set_top(None, 0, C.c_double(1.0), None) == fbmc.FB_EINVAL
+    assert lib.fb_get_top(None, 0, None, None, None, None, None) == fbmc.FB_EINVAL
+    assert lib.fb_set_beta_update(None, fbmc.FB_BETA_LAPLACE) == fbmc.FB_EINVAL
