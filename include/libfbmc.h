@@ -337,8 +337,9 @@ int fb_set_launch(fb_ctx *c, int32_t samples_per_wave, int32_t fuse_hyper);
  * gamma/beta kernel (0).  The learned step always uses the separate kernel.
  * No choice changes any draw.  Errors: FB_EINVAL. */
 int fb_set_shift_fusion(fb_ctx *c, int32_t fused);
-/* Lanes per gene in the beta draws of the slice sweep without the shift
- * step: 1 (one lane per gene) or 2 (a pair of lanes: both step-out
+/* Lanes per gene in the beta draws of the slice sweep (with the shift step
+ * when it runs inside the gamma/beta kernel): 1 (one lane per gene) or 2 (a
+ * pair of lanes: both step-out
  * directions at once and shrink candidates two at a time -- fewer dependent
  * trips per gene where few tiles share the chip, more work per gene where
  * many do).  fb_autotune tries both.  No choice changes any draw.
@@ -355,9 +356,10 @@ int fb_get_launch(const fb_ctx *c, int32_t *samples_per_wave, int32_t *fuse_hype
  * fb_last_sweep_time is the last trial's).  Outputs (each may be NULL): the
  * chosen shape, its time per sweep (ms), and table[8], the time per sweep of shape
  * k = 2 log2(samples_per_wave) + fuse_hyper, -1 if not tried (all with the
- * current beta lanes).  With the slice steps for beta and no shift step it
- * then times the other number of beta lanes (fb_set_beta_lanes) at the chosen
- * shape and keeps the faster; ms_per_sweep is the time of the final choice.
+ * current beta lanes).  With the slice steps for beta (and the shift step,
+ * if on, inside the gamma/beta kernel) it then times the other number of beta
+ * lanes (fb_set_beta_lanes) at the chosen shape and keeps the faster;
+ * ms_per_sweep is the time of the final choice.
  * Needs device memory for one copy of the state. */
 int fb_autotune(fb_ctx *c, int32_t trial_sweeps, int32_t *samples_per_wave, int32_t *fuse_hyper,
                 double *ms_per_sweep, double *table);

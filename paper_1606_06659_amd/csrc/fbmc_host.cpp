@@ -32,7 +32,7 @@ hipError_t launch_shift(int precision, int maxL, const SegInfo *segs, const int2
                         const SweepArgs &a, hipStream_t st);
 hipError_t launch_gb_shift(int precision, int mode, int maxL, const SegInfo *segs, const int2 *tiles, int ntiles,
                            const SweepArgs &a, const MlpDev *net, int *err, hipStream_t st);
-hipError_t launch_gb_pair(int precision, int maxL, const SegInfo *segs, const int2 *tiles, int ntiles,
+hipError_t launch_gb_pair(int precision, int maxL, bool shift, const SegInfo *segs, const int2 *tiles, int ntiles,
                           const SweepArgs &a, int *err, hipStream_t st);
 hipError_t launch_mlp_sweep(int precision, const SegInfo *segs, const int2 *tiles, int ntiles, const MlpDev *net,
                             hipStream_t st);
@@ -737,11 +737,12 @@ static int launch_sweeps(fb_ctx *c, const SweepArgs *args, int64_t n, const Swee
         if (pe) HIPCHK(c, hipEventRecord(pe[2], c->st));
         if (md.learned && !md.laplace)
             HIPCHK(c, launch_mlp_sweep(c->prec, c->d_segs, c->d_tiles, c->ntiles, c->d_net, c->st));
-        if (fused_shift)
+        if (gbm == 0 && c->beta_lanes == 2 && (!shift || fused_shift))
+            HIPCHK(c, launch_gb_pair(c->prec, c->maxL, shift, c->d_segs, c->d_tiles, c->ntiles, a, c->d_err,
+                                     c->st));
+        else if (fused_shift)
             HIPCHK(c, launch_gb_shift(c->prec, gbm, c->maxL, c->d_segs, c->d_tiles, c->ntiles, a, gnet, c->d_err,
                                       c->st));
-        else if (gbm == 0 && !shift && c->beta_lanes == 2)
-            HIPCHK(c, launch_gb_pair(c->prec, c->maxL, c->d_segs, c->d_tiles, c->ntiles, a, c->d_err, c->st));
         else
             HIPCHK(c, launch_gb(c->prec, gbm, c->maxL, c->d_segs, c->d_tiles, c->ntiles, c->d_fb_items,
                                 md.learned ? c->nfb_items : 0, a, gnet, c->d_err, c->st));
@@ -1770,7 +1771,8 @@ int fb_autotune(fb_ctx *c, int32_t trial_sweeps, int32_t *samples_per_wave, int3
     // with the slice steps for beta, the other number of lanes per gene at the best shape
     const int lanes0 = c->beta_lanes;
     int best_lanes = lanes0;
-    const bool slice_beta = c->beta_mode == FB_BETA_SLICE && !((c->opt.update_mask >> kKindShift) & 1u);
+    const bool slice_beta = c->beta_mode == FB_BETA_SLICE &&
+                            (!((c->opt.update_mask >> kKindShift) & 1u) || c->fuse_shift);
     if (slice_beta && e == hipSuccess && rc == FB_OK && (rc = build_items(c, best_spw)) == FB_OK) {
         c->fuse = best_fuse;
         c->beta_lanes = 3 - lanes0;

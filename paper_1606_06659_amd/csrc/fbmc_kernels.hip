@@ -1206,8 +1206,10 @@ __global__ __launch_bounds__(128) void gb_shift_sweep(const SegInfo *__restrict_
 // The new beta goes through LDS to wavefront 0, which (with the moments
 // prefetched while the draws ran) takes the moments, trace, events and tile
 // partials with beta_finish, in the order of gb_sweep: the chains are the same
-// bit for bit.
-template <typename T, int kML>
+// bit for bit.  kShift: the shift step on -- wavefront 1 then shifts the tile
+// after the barrier (shift_genes, which takes the moments, trace, events and
+// partials), as in gb_shift_sweep.
+template <typename T, int kML, bool kShift = false>
 __global__ __launch_bounds__(192) void gb_pair_sweep(const SegInfo *__restrict__ segs,
                                                      const int2 *__restrict__ tiles, int ntiles, SweepArgs a0,
                                                      int *err)
@@ -1296,6 +1298,10 @@ __global__ __launch_bounds__(192) void gb_pair_sweep(const SegInfo *__restrict__
         if (bad) raise_flag(err, 2);
     }
     __syncthreads();
+    if constexpr (kShift) {
+        if (wave == 1) shift_genes<T, kML>(S, tile, a);
+        return;
+    }
     if (wave == 0 && !((a.mask >> kKindShift) & 1u)) {
         const int64_t g = (int64_t)tile * kTile + lane;
         T beta[kMaxL];
@@ -2069,18 +2075,32 @@ static void launch_gb_shift_m(int precision, int maxL, const SegInfo *segs, cons
     }
 }
 
-hipError_t launch_gb_pair(int precision, int maxL, const SegInfo *segs, const int2 *tiles, int ntiles,
+template <bool kShift>
+static void launch_gb_pair_s(int precision, int maxL, const SegInfo *segs, const int2 *tiles, int ntiles,
+                             const SweepArgs &a, int *err, hipStream_t st)
+{
+    const dim3 grid((unsigned)ntiles), block(192);
+    if (precision == 1) {
+        if (maxL <= 5)
+            hipLaunchKernelGGL((gb_pair_sweep<float, 5, kShift>), grid, block, 0, st, segs, tiles, ntiles, a, err);
+        else
+            hipLaunchKernelGGL((gb_pair_sweep<float, kMaxL, kShift>), grid, block, 0, st, segs, tiles, ntiles, a,
+                               err);
+    } else {
+        if (maxL <= 5)
+            hipLaunchKernelGGL((gb_pair_sweep<double, 5, kShift>), grid, block, 0, st, segs, tiles, ntiles, a, err);
+        else
+            hipLaunchKernelGGL((gb_pair_sweep<double, kMaxL, kShift>), grid, block, 0, st, segs, tiles, ntiles, a,
+                               err);
+    }
+}
+
+hipError_t launch_gb_pair(int precision, int maxL, bool shift, const SegInfo *segs, const int2 *tiles, int ntiles,
                           const SweepArgs &a, int *err, hipStream_t st)
 {
     if (ntiles <= 0) return hipSuccess;
-    const dim3 grid((unsigned)ntiles), block(192);
-    if (precision == 1) {
-        if (maxL <= 5) hipLaunchKernelGGL((gb_pair_sweep<float, 5>), grid, block, 0, st, segs, tiles, ntiles, a, err);
-        else hipLaunchKernelGGL((gb_pair_sweep<float, kMaxL>), grid, block, 0, st, segs, tiles, ntiles, a, err);
-    } else {
-        if (maxL <= 5) hipLaunchKernelGGL((gb_pair_sweep<double, 5>), grid, block, 0, st, segs, tiles, ntiles, a, err);
-        else hipLaunchKernelGGL((gb_pair_sweep<double, kMaxL>), grid, block, 0, st, segs, tiles, ntiles, a, err);
-    }
+    if (shift) launch_gb_pair_s<true>(precision, maxL, segs, tiles, ntiles, a, err, st);
+    else launch_gb_pair_s<false>(precision, maxL, segs, tiles, ntiles, a, err, st);
     return hipGetLastError();
 }
 

@@ -35,12 +35,14 @@ def _same(F, a, b, label, seg=0, events=0):
         assert np.array_equal(F.fb_event_counts(a, events, seg)[0], F.fb_event_counts(b, events, seg)[0]), label
 
 
-@pytest.mark.parametrize("precision", [0, 1])
-def test_two_lanes_give_the_one_lane_chain(precision):
+@pytest.mark.parametrize("precision,shift", [(0, 0), (1, 0), (0, 1), (1, 1)])
+def test_two_lanes_give_the_one_lane_chain(precision, shift):
+    """Also with the shift step, which then runs inside the pair kernel."""
     F = require_gpu()
     ds = datagen.paper_design_16(G=1500, seed=41)
     opts = F.fb_default_options(burnin=15, tune_start=3, precision=precision, jitter=0, debug_counts=1, thin=1,
-                                trace_genes=11, trace_capacity=80)
+                                trace_genes=11, trace_capacity=80,
+                                update_mask=F.FB_UPDATE_ALL | (F.FB_SHIFT if shift else 0))
     a = F.fb_create(ds.y, ds.X, ds.h, seed=42, options=opts)
     b = F.fb_create(ds.y, ds.X, ds.h, seed=42, options=opts)
     F.fb_set_beta_lanes(b, 2)
@@ -52,7 +54,7 @@ def test_two_lanes_give_the_one_lane_chain(precision):
         if i == 2:
             F.fb_set_graph(a, 6)
             F.fb_set_graph(b, 6)
-        say("one vs two beta lanes: sweeps", n, "precision", precision)
+        say("one vs two beta lanes: sweeps", n, "precision", precision, "shift", shift)
         F.fb_sweep(a, n)
         F.fb_sweep(b, n)
         _same(F, a, b, f"call {i}", events=2)
@@ -110,6 +112,19 @@ def test_two_lanes_fp64_parity_edge_cases(oracle_lib, name, ds, kw):
         o.sweep(1)
         F.fb_sweep(g, 1)
         _compare_fp64(F, g, o, f"{name} sweep {it + 1}")
+    F.fb_destroy(g)
+
+
+def test_two_lanes_fp64_parity_with_shift_step(oracle_lib):
+    ds = datagen.paper_design_16(G=700, seed=47)
+    F, g, o = _make_pair(oracle_lib, ds, seed=48, burnin=20, tune_start=3, precision=0,
+                         update_mask=0xFE | (1 << 11))
+    F.fb_set_beta_lanes(g, 2)
+    F.fb_set_state(g, o.get_state())
+    for it in range(30):
+        assert o.sweep(1) == 0
+        F.fb_sweep(g, 1)
+        _compare_fp64(F, g, o, f"two lanes with shift, sweep {it + 1}")
     F.fb_destroy(g)
 
 
