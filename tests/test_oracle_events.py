@@ -10,13 +10,11 @@ answer is known (always, never, an event and its complement).
 import numpy as np
 
 from paper_1606_06659_amd import datagen
+from tests.test_golden import heterosis_events
 
 # the paper's high- and low-parent heterosis events for the design of Section 5
 # (coefficients 2, 3, 4 in the paper's 1-based numbering are l = 1, 2, 3 here)
-HETEROSIS = [
-    [([0, 2, 0, 1, 0], 0.0), ([0, 0, 2, 1, 0], 0.0)],
-    [([0, -2, 0, -1, 0], 0.0), ([0, 0, -2, -1, 0], 0.0)],
-]
+HETEROSIS = heterosis_events()      # Section 5 (tests/golden/heterosis_events.txt)
 
 
 def _recount(states, events, L):
