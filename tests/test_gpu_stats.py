@@ -96,3 +96,39 @@ def test_other_forms_agree_with_the_oracle(oracle_lib, form):
     r = compare(hyp, genes[:, :, 0], genes[:, :, 1:], *a)
     say("gpu", form, "vs oracle", r)
     assert agree(r), r
+
+
+def test_rhat_from_device_moments():
+    """Section 3.1's convergence check from the device's running moments
+    alone: four overdispersed chains (with the shift step and the exact draws,
+    which mix fast enough for 1,500 post-burn-in sweeps) give R-hat near 1 for
+    the genes and the hyperparameters, and the device moments give the same
+    R-hat as the traced draws of the traced genes."""
+    from paper_1606_06659_amd import diagnostics
+    F = require_gpu()
+    ds = datagen.small_two_group(G=1000, seed=0)
+    G, L, C = ds.G, ds.L, 4
+    post = ITERS - BURNIN
+    T = 50
+    opts = F.fb_default_options(burnin=BURNIN, tune_start=BURNIN // 10, precision=1, jitter=1, chains=C, thin=1,
+                                trace_genes=T, trace_after_burnin=1, trace_capacity=post,
+                                update_mask=F.FB_UPDATE_ALL | F.FB_SHIFT | F.FB_EXACT)
+    g = F.fb_create(ds.y, ds.X, ds.h, seed=61, options=opts)
+    F.fb_sweep(g, ITERS)
+    summ = [F.fb_summaries(g, c) for c in range(C)]
+    traces = [F.fb_trace(g, c)[0].astype(np.float64) for c in range(C)]
+    genes = F.fb_trace_genes(g)
+    F.fb_destroy(g)
+    assert all(s["count"] == post for s in summ)
+    st = lambda k: np.stack([s[k] for s in summ])
+    r_beta = diagnostics.rhat_from_moments(st("mean_beta"), st("msq_beta"), post)
+    r_gam = diagnostics.rhat_from_moments(st("mean_gam"), st("msq_gam"), post)
+    r_hyp = diagnostics.rhat_from_moments(st("mean_hyp"), st("msq_hyp"), post)
+    say("R-hat: beta 99th pct", np.percentile(r_beta, 99), "gamma 99th pct", np.percentile(r_gam, 99),
+        "hyper max", r_hyp.max())
+    assert np.mean(r_beta > 1.1) < 0.01 and np.mean(r_gam > 1.1) < 0.01
+    assert np.all(r_hyp < 1.2), r_hyp
+    # the same factor from the traced draws of the traced genes
+    tb = np.stack([t[:, 2 + 2 * L:].reshape(post, T, L + 1)[:, :, 1:] for t in traces])     # [C, M, T, L]
+    r_tr = diagnostics.rhat_from_moments(tb.mean(1), (tb ** 2).mean(1), post)
+    np.testing.assert_allclose(r_tr, r_beta[genes], rtol=1e-4)
