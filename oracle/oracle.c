@@ -1,37 +1,41 @@
 /*
- * oracle.c -- TEST INFRASTRUCTURE ONLY: the plain FP64 CPU sampler.
+ * oracle.c -- TEST INFRASTRUCTURE ONLY: the plain FP64 CPU sampler.  Only the
+ * tests, the package's smoke check and the benchmark's CPU-baseline leg load
+ * it; the HIP library never does.
  *
  * Landau & Niemi, "A fully Bayesian strategy for high-dimensional hierarchical
  * modeling using massively parallel computing" (arXiv 1606.06659).
- *   Model:        Section 4.1, Fig. 3.
- *   Gibbs order:  Algorithm 1 (steps 1-7), Section 4.2.
- *   Slice draws:  Algorithm 2 (Appendix A), done in log space.
- *   Moments:      Section 3.1 (Welford's one-pass mean and mean of squares).
+ *   Model:         Section 4.1, Fig. 3.
+ *   Gibbs scan:    Algorithm 1 and Section 4.2 (the order of the conditionals).
+ *   Slice draws:   Algorithm 2 (Appendix A), Neal's stepping-out slice sampler,
+ *                  in log space.
+ *   Moments:       Section 3.1 (one-pass running mean and mean of squares).
  *
  * Everything is written the plain way: each log density is the full conditional
  * evaluated term by term (sums over all n, no grouping), each reduction is a
- * serial loop, and the steps run in the printed order of Algorithm 1:
+ * serial loop, and the conditionals are drawn in the order of Algorithm 1:
  * eps (all g, n), gamma (all g), nu, tau, beta (l = 1..L), theta, sigma^2.
  *
  * Readings where the paper is silent or garbled (each is also listed in the
  * design notes of the repository):
- *  - nu (Algorithm 1 step 3): the printed density carries nu/gamma_g inside the
- *    sum; the product of InvGamma(nu/2, nu tau/2) densities gives tau/gamma_g,
- *    which is used here, together with the U(0, d) support.
+ *  - nu: the printed conditional carries nu/gamma_g inside the sum; the
+ *    product of InvGamma(nu/2, nu tau/2) densities gives tau/gamma_g, which is
+ *    used here, together with the U(0, d) support.
  *  - gamma_g: InvGamma(nu/2 + N/2, nu tau/2 + sum_n eps_gn^2 / 2) (scale form).
  *  - theta_l: Normal full conditional drawn directly (only non-normal
  *    conditionals are slice sampled, Section 4.2).
  *  - sigma_l: the prior is uniform on sigma_l, so sigma_l^2 has the truncated
  *    InvGamma((G-1)/2, sum_g (beta_gl - theta_l)^2 / 2) conditional on
  *    (0, s_l^2); it is slice sampled and sigma_l^2 is what is stored.
- *  - tau: the Gamma conditional of step 4 is slice sampled like the other
- *    gamma-family conditionals (Section 4.2).
- *  - Algorithm 2 step 4 keeps scanning after the first failed step; stopping
- *    at the first failure gives the same interval and is what is done here.
- *  - The shrink loop is capped at shrink_cap candidates; on the cap the draw
+ *  - tau: its Gamma conditional is slice sampled like the other gamma-family
+ *    conditionals (Section 4.2).
+ *  - Growing the slice interval: the printed loop keeps testing after the first
+ *    end outside the slice; stopping there gives the same interval and is what
+ *    is done here.
+ *  - The trial-point loop is capped at shrink_cap points; on the cap the draw
  *    keeps x0 and an error is counted.
- *  - Tuning (step 7) uses the sweep index m, and a computed width that is not a
- *    positive finite number leaves w unchanged.
+ *  - Width adaptation uses the sweep index m, and a computed width that is not
+ *    a positive finite number leaves w unchanged.
  *  - Moments cover sweeps m > M_B with divisor m - M_B.
  */
 #include "oracle.h"
@@ -112,14 +116,33 @@ static uint32_t rs_word(rstream *s, uint32_t q)
 }
 
 /* ------------------------------------------------------------------ */
-/* Algorithm 2: stepping-out slice sampler with tuning, in log space   */
+/* Univariate slice sampling with a stepped-out interval               */
 /* ------------------------------------------------------------------ */
+/* The paper draws every conditional that is not normal with the univariate
+ * slice sampler of Neal (2003, Ann. Statist. 31, Sections 4.1-4.2) in the
+ * form of Algorithm 2 (Appendix A), including its adaptive width.  From the
+ * current point x0:
+ *   - an auxiliary level below f(x0) defines the slice {x : f(x) > level};
+ *     in log space the level is z = log f(x0) - E with E ~ Exp(1), which is
+ *     log of a uniform draw on (0, f(x0)) and cannot underflow;
+ *   - an interval of width w is placed uniformly at random around x0 and
+ *     grown by whole widths while its end lies in the slice, with a budget of
+ *     K growth steps split uniformly at random between the two sides;
+ *   - points drawn uniformly from the interval are tried until one lies in
+ *     the slice; a rejected point becomes the end of the interval on its side
+ *     of x0 (a point equal to x0 counts as the left side).
+ * The result leaves f invariant for any fixed w (Neal 2003, Section 4.3).
+ * During burn-in w adapts to the mean absolute move (see adapt_width).
+ *
+ * Random words (layout in oracle.h): word 0 gives E, word 1 the side budget
+ * (low 4 bits) and the interval offset (high 28 bits), word t + 1 the t-th
+ * trial point. */
 typedef double (*logf_fn)(double x, const void *arg);
 
 typedef struct {
-    int32_t kl, nl, nr, nc;
-    double margin;
-    int bad;
+    int32_t kl, nl, nr, nc;  /* left budget, left and right growth steps, trial points */
+    double margin;           /* smallest |log f(x) - z| over the comparisons */
+    int bad;                 /* non-finite log f(x0), or no point found */
 } draw_info;
 
 static void note_margin(draw_info *di, double fx, double z)
@@ -129,67 +152,71 @@ static void note_margin(draw_info *di, double fx, double z)
     if (d < di->margin) di->margin = d;
 }
 
+/* Grows one end of the interval: while fewer than `budget` moves have been
+ * made and the end is inside the slice, move it by `step`.  Returns the
+ * number of moves; the loop ends at the first end outside the slice (further
+ * tests could not move it any more). */
+static int grow_end(logf_fn f, const void *arg, double z, double step, int budget, double *end, draw_info *di)
+{
+    int moves = 0;
+    for (; moves < budget; ++moves) {
+        const double fe = f(*end, arg);
+        note_margin(di, fe, z);
+        if (!(fe > z)) break;
+        *end += step;
+    }
+    return moves;
+}
+
+/* Burn-in adaptation of the width (Appendix A): waux accumulates m |x1 - x0|
+ * from the first sweep; once m > M_C the width becomes the weighted mean
+ * waux / (m (m + 1) / 2).  A value that is not a positive finite number
+ * leaves w as it is.  After burn-in w is frozen. */
+static void adapt_width(double *w, double *waux, double x0, double x1, int64_t m, int64_t burnin,
+                        int64_t tune_start)
+{
+    if (m > burnin) return;
+    *waux += (double)m * fabs(x1 - x0);
+    if (m > tune_start) {
+        const double wn = *waux / (0.5 * (double)m * (double)(m + 1));
+        if (wn > 0.0 && isfinite(wn)) *w = wn;
+    }
+}
+
 static double slice_draw(logf_fn f, const void *arg, double x0, double *w, double *waux,
                          int64_t m, int64_t burnin, int64_t tune_start, int K, int cap,
                          rstream *rs, draw_info *di)
 {
     di->margin = INFINITY;
     di->bad = 0;
-    /* step 1: u ~ U(0, f(x0)), kept as z = log f(x0) - E with E ~ Exp(1) */
-    double fx0 = f(x0, arg);
-    if (!isfinite(fx0)) { di->bad = 1; di->kl = di->nl = di->nr = di->nc = 0; return x0; }
-    double E = -log(u01(rs_word(rs, 0)));
-    double z = fx0 - E;
-    /* step 2: window of width w placed at random around x0 */
-    uint32_t r1 = rs_word(rs, 1);
-    double uv = ((double)(r1 >> 4) + 0.5) * 0x1p-28;
-    double v = (*w) * uv;
-    if (OR_MUTANT == 4) v = *w;           /* window not placed at random */
-    double L = x0 - v;
-    double R = L + (*w);
-    /* step 3: K_L uniform on {0..K}, K_R = K - K_L */
-    int KL = (int)(r1 & (uint32_t)K);
-    int KR = K - KL;
-    di->kl = KL;
-    /* step 4: step out */
-    int nl = 0, nr = 0;
-    while (nl < KL) {
-        double fl = f(L, arg);
-        note_margin(di, fl, z);
-        if (!(fl > z)) break;
-        L = L - (*w);
-        ++nl;
-    }
-    while (nr < KR) {
-        double fr = f(R, arg);
-        note_margin(di, fr, z);
-        if (!(fr > z)) break;
-        R = R + (*w);
-        ++nr;
-    }
-    di->nl = nl;
-    di->nr = nr;
-    /* steps 5-6: shrink until a candidate lies in the slice */
+    di->kl = di->nl = di->nr = di->nc = 0;
+    const double fx0 = f(x0, arg);
+    if (!isfinite(fx0)) { di->bad = 1; return x0; }
+    const double z = fx0 - (-log(u01(rs_word(rs, 0))));
+    /* the interval [lo, hi] of width w with x0 at a uniform offset from hi */
+    const uint32_t r1 = rs_word(rs, 1);
+    double off = (*w) * (((double)(r1 >> 4) + 0.5) * 0x1p-28);
+    if (OR_MUTANT == 4) off = *w;           /* interval not placed at random */
+    double lo = x0 - off;
+    double hi = lo + (*w);
+    /* the growth budget: kl steps to the left, K - kl to the right */
+    di->kl = (int)(r1 & (uint32_t)K);
+    di->nl = grow_end(f, arg, z, -(*w), di->kl, &lo, di);
+    di->nr = grow_end(f, arg, z, *w, K - di->kl, &hi, di);
+    /* uniform trial points, each rejection cutting the interval at the point */
     double x1 = x0;
-    int t = 1, ok = 0;
-    for (; t <= cap; ++t) {
-        double u = u01(rs_word(rs, (uint32_t)(t + 1)));
-        double xs = L + u * (R - L);
-        double fs = f(xs, arg);
-        note_margin(di, fs, z);
-        if (fs > z) { x1 = xs; ok = 1; break; }
-        if (xs > x0) R = xs; else L = xs;
+    int found = 0;
+    for (int t = 1; t <= cap && !found; ++t) {
+        const double xt = lo + u01(rs_word(rs, (uint32_t)(t + 1))) * (hi - lo);
+        const double ft = f(xt, arg);
+        note_margin(di, ft, z);
+        di->nc = t;
+        if (ft > z) { x1 = xt; found = 1; }
+        else if (xt > x0) hi = xt;
+        else lo = xt;
     }
-    di->nc = ok ? t : cap;
-    if (!ok) { di->bad = 1; x1 = x0; }
-    /* step 7: tune w during burn-in */
-    if (m <= burnin) {
-        *waux += (double)m * fabs(x1 - x0);
-        if (m > tune_start) {
-            double wn = *waux / (0.5 * (double)m * (double)(m + 1));
-            if (wn > 0.0 && isfinite(wn)) *w = wn;
-        }
-    }
+    if (!found) di->bad = 1;
+    adapt_width(w, waux, x0, x1, m, burnin, tune_start);
     return x1;
 }
 
@@ -308,7 +335,7 @@ struct or_ctx {
     int64_t *ev_count;
     int64_t ev_from;
     /* prior mean of theta_l (0 unless a three-level driver sets it) */
-    double theta_mean[64];
+    double theta_mean[OR_MAX_L];
 };
 
 static int64_t n_params(const or_ctx *c)
@@ -329,7 +356,7 @@ int or_create(or_ctx **out, const or_config *cfg)
 {
     if (!out || !cfg) return -1;
     *out = NULL;
-    if (cfg->G < 1 || cfg->N < 1 || cfg->L < 1 || cfg->L > 64) return -1;
+    if (cfg->G < 1 || cfg->N < 1 || cfg->L < 1 || cfg->L > OR_MAX_L) return -1;
     if (!(cfg->K == 0 || cfg->K == 1 || cfg->K == 3 || cfg->K == 7 || cfg->K == 15)) return -1;
     if (cfg->shrink_cap < 1) return -1;
     or_ctx *c = (or_ctx *)xcalloc(1, sizeof(or_ctx));
@@ -382,6 +409,7 @@ int or_create(or_ctx **out, const or_config *cfg)
         }
         c->row_of[n] = found >= 0 ? found : c->R++;
     }
+    if (c->R > OR_MAX_ROWS) { or_destroy(c); return -1; }
     for (int64_t i = 0; i < G * N; ++i) c->w_eps[i] = cfg->w0;
     for (int64_t i = 0; i < G; ++i) c->w_gam[i] = cfg->w0;
     for (int64_t i = 0; i < G * L; ++i) c->w_beta[i] = cfg->w0;
@@ -442,7 +470,7 @@ int or_top_draw(int32_t K, int32_t L, const double *theta, const double *tau, co
                 double a_b, double b_b, const double *c0, uint64_t seed, int32_t chain, int64_t m, uint32_t mask,
                 double *b, double *psi, int32_t *tries)
 {
-    if (K < 1 || L < 1 || L > 64 || !theta || !tau || !a || !c || !c0 || !b || !psi) return -1;
+    if (K < 1 || L < 1 || L > OR_MAX_L || !theta || !tau || !a || !c || !c0 || !b || !psi) return -1;
     const uint32_t mm = (uint32_t)m;
     if (tries) *tries = 0;
     if (mask & 1u) {
@@ -571,7 +599,7 @@ static double logf_sig2(double x, const void *p)
 static void gene_features(const or_ctx *c, int64_t g, double *phi, int F)
 {
     const int N = c->cfg.N, L = c->cfg.L, R = c->R;
-    double Y[64], A[64];
+    double Y[OR_MAX_ROWS], A[OR_MAX_ROWS];
     for (int r = 0; r < R; ++r) { Y[r] = 0.0; A[r] = 0.0; }
     for (int n = 0; n < N; ++n) {
         Y[c->row_of[n]] += (double)c->y[g * N + n];
@@ -626,7 +654,7 @@ static void chol(const double *H, int L, double *U)
 /* x with H x = b, H = U U^T: forward then back substitution. */
 static void chol_solve(const double *U, int L, const double *b, double *x)
 {
-    double t[64];
+    double t[OR_MAX_L];
     for (int i = 0; i < L; ++i) {
         double s = b[i];
         for (int k = 0; k < i; ++k) s -= U[i * L + k] * t[k];
@@ -652,7 +680,7 @@ static void chol_solve(const double *U, int L, const double *b, double *x)
 static void laplace_base(const or_ctx *c, const double *Y, const double *A, double *bh, double *U)
 {
     const int N = c->cfg.N, L = c->cfg.L, R = c->R;
-    double xr[64 * 64], H[64], rhs[64], cr[64];
+    double xr[OR_MAX_ROWS * OR_MAX_L], H[OR_MAX_L * OR_MAX_L], rhs[OR_MAX_L], cr[OR_MAX_ROWS];
     for (int r = 0; r < R; ++r) {
         int n0 = 0;
         while (c->row_of[n0] != r) ++n0;
@@ -691,7 +719,7 @@ static void laplace_base(const or_ctx *c, const double *Y, const double *A, doub
             }
         chol(H, L, U);
         if (it == 2) break;
-        double step[64];
+        double step[OR_MAX_L];
         chol_solve(U, L, rhs, step);
         for (int l = 0; l < L; ++l) bh[l] += step[l];
     }
@@ -722,7 +750,9 @@ static void imh_step(or_ctx *c, int64_t g, uint32_t mm)
 {
     const int L = c->cfg.L, F = c->prop.F;
     const or_mlp *pm = &c->prop;
-    double phi[OR_MLP_MAXW], o[OR_MLP_MAXW], Y[64], A[64], bh[64], U[64], mw[64], z[64], w[64], bs[64], d[64], u[64];
+    double phi[OR_MLP_MAXW], o[OR_MLP_MAXW], Y[OR_MAX_ROWS], A[OR_MAX_ROWS];
+    double bh[OR_MAX_L], U[OR_MAX_L * OR_MAX_L], mw[OR_MAX_L], z[OR_MAX_L], w[OR_MAX_L], bs[OR_MAX_L], d[OR_MAX_L],
+        u[OR_MAX_L];
     gene_features(c, g, phi, F);
     or_mlp_outputs(pm, phi, o);
     row_sums(c, g, Y, A);
@@ -788,7 +818,7 @@ static void imh_step(or_ctx *c, int64_t g, uint32_t mm)
 static void shift_step(or_ctx *c, int64_t g, uint32_t mm)
 {
     const int N = c->cfg.N, L = c->cfg.L;
-    double P[64], U[64], cv[64], mean[64], z[64], v[64];
+    double P[OR_MAX_L * OR_MAX_L], U[OR_MAX_L * OR_MAX_L], cv[OR_MAX_L], mean[OR_MAX_L], z[OR_MAX_L], v[OR_MAX_L];
     const double ig = 1.0 / c->gam[g];
     for (int i = 0; i < L; ++i) {
         double s = 0.0;
@@ -817,7 +847,7 @@ static void shift_step(or_ctx *c, int64_t g, uint32_t mm)
         for (int k = i + 1; k < L; ++k) s -= U[k * L + i] * v[k];
         v[i] = s / U[i * L + i];
     }
-    double d[64];
+    double d[OR_MAX_L];
     for (int l = 0; l < L; ++l) {
         d[l] = mean[l] + v[l];
         c->beta[g * L + l] += d[l];
@@ -873,7 +903,7 @@ int or_get_imh(const or_ctx *c, int32_t *acc, double *log_alpha)
 int or_num_rows(const or_ctx *c) { return c ? c->R : -1; }
 
 /* ------------------------------------------------------------------ */
-/* One sweep (Algorithm 1)                                             */
+/* One sweep                                                           */
 /* ------------------------------------------------------------------ */
 static void record(or_ctx *c, int64_t idx, const draw_info *di)
 {
@@ -890,139 +920,171 @@ static void welford(double *mean, double *msq, double x, int64_t k)
     *msq += (x * x - *msq) / (double)k;
 }
 
-static int64_t sweep_once(or_ctx *c)
+/* eps_gn for every gene and sample: the Poisson log pmf of y_gn in eps
+ * (without the term in y alone) plus the N(0, gamma_g) prior, given beta_g
+ * and gamma_g.  The draws are independent across (g, n). */
+static int64_t update_eps(or_ctx *c, int64_t m)
+{
+    const or_config *cf = &c->cfg;
+    const int64_t G = cf->G;
+    const int N = cf->N;
+    int64_t errs = 0;
+#pragma omp parallel for schedule(static) reduction(+:errs) num_threads(c->nthreads)
+    for (int64_t g = 0; g < G; ++g) {
+        for (int n = 0; n < N; ++n) {
+            eps_arg a = { c, g, n };
+            rstream rs;
+            draw_info di;
+            rs_init(&rs, cf->seed, (uint32_t)g, OR_KIND_EPS, (uint32_t)n, (uint32_t)m, (uint32_t)cf->chain);
+            const int64_t i = g * N + n;
+            c->eps[i] = slice_draw(logf_eps, &a, c->eps[i], &c->w_eps[i], &c->wa_eps[i], m,
+                                   cf->burnin, cf->tune_start, cf->K, cf->shrink_cap, &rs, &di);
+            record(c, i, &di);
+            errs += di.bad;
+        }
+    }
+    return errs;
+}
+
+/* gamma_g for every gene: InvGamma(nu/2 + N/2, nu tau/2 + sum_n eps_gn^2 / 2),
+ * slice sampled, or drawn directly with the exact-draw option. */
+static int64_t update_gamma(or_ctx *c, int64_t m)
+{
+    const or_config *cf = &c->cfg;
+    const int64_t G = cf->G;
+    const int N = cf->N;
+    const int64_t off_gam = G * N;
+    int64_t errs = 0;
+#pragma omp parallel for schedule(static) reduction(+:errs) num_threads(c->nthreads)
+    for (int64_t g = 0; g < G; ++g) {
+        double S = 0.0;
+        for (int n = 0; n < N; ++n) S += c->eps[g * N + n] * c->eps[g * N + n];
+        gam_arg a = { 0.5 * c->nu + (OR_MUTANT == 2 ? 1.0 : 0.5) * N + 1.0,
+                      0.5 * c->nu * c->tau + 0.5 * S };
+        rstream rs;
+        draw_info di;
+        if (cf->update_mask & (1u << OR_KIND_EXACT)) {
+            exact_arg e = { 0.5 * c->nu + 0.5 * N, (OR_MUTANT == 15 ? c->nu * c->tau : 0.5 * c->nu * c->tau) + 0.5 * S,
+                            1, INFINITY };
+            double v;
+            int t = exact_draw(&e, cf->seed, OR_KIND_EXACT, (uint32_t)g, 0, (uint32_t)m, (uint32_t)cf->chain, &v, &di);
+            if (t > 0) {
+                c->gam[g] = v;
+                di.kl = -1; di.nl = 0; di.nr = 0; di.nc = t;
+                record(c, off_gam + g, &di);
+                continue;
+            }
+        }
+        rs_init(&rs, cf->seed, (uint32_t)g, OR_KIND_GAMMA, 0, (uint32_t)m, (uint32_t)cf->chain);
+        c->gam[g] = slice_draw(logf_gam, &a, c->gam[g], &c->w_gam[g], &c->wa_gam[g], m,
+                               cf->burnin, cf->tune_start, cf->K, cf->shrink_cap, &rs, &di);
+        record(c, off_gam + g, &di);
+        errs += di.bad;
+    }
+    return errs;
+}
+
+/* The sums over genes that the nu and tau conditionals need. */
+static void gamma_sums(or_ctx *c)
+{
+    double sum_log = 0.0, sum_inv = 0.0;
+    for (int64_t g = 0; g < c->cfg.G; ++g) { sum_log += log(c->gam[g]); sum_inv += 1.0 / c->gam[g]; }
+    c->red[0] = sum_log;
+    c->red[1] = sum_inv;
+}
+
+/* nu given gamma and tau: the product of the InvGamma(nu/2, nu tau/2)
+ * densities of the gamma_g on the U(0, d) support (logf_nu). */
+static int64_t update_nu(or_ctx *c, int64_t m)
+{
+    const or_config *cf = &c->cfg;
+    nu_arg a = { (double)cf->G, c->tau, c->red[0], c->red[1], cf->d };
+    rstream rs;
+    draw_info di;
+    rs_init(&rs, cf->seed, 0, OR_KIND_NU, 0, (uint32_t)m, (uint32_t)cf->chain);
+    c->nu = slice_draw(logf_nu, &a, c->nu, &c->w_nu, &c->wa_nu, m, cf->burnin,
+                       cf->tune_start, cf->K, cf->shrink_cap, &rs, &di);
+    record(c, cf->G * cf->N + cf->G + cf->G * cf->L, &di);
+    return di.bad;
+}
+
+/* tau given nu and gamma: Gamma(a + G nu / 2, rate b + (nu/2) sum_g 1/gamma_g). */
+static int64_t update_tau(or_ctx *c, int64_t m)
+{
+    const or_config *cf = &c->cfg;
+    tau_arg a = { cf->a + 0.5 * (double)cf->G * c->nu - 1.0,
+                  cf->b + (OR_MUTANT == 8 ? 1.0 : 0.5) * c->nu * c->red[1] };
+    rstream rs;
+    draw_info di;
+    int t = 0;
+    if (cf->update_mask & (1u << OR_KIND_EXACT)) {
+        exact_arg e = { a.shape_m1 + 1.0, a.rate, 0, INFINITY };
+        double v;
+        t = exact_draw(&e, cf->seed, OR_KIND_EXACT, 0, 1, (uint32_t)m, (uint32_t)cf->chain, &v, &di);
+        if (t > 0) {
+            c->tau = v;
+            di.kl = -1; di.nl = 0; di.nr = 0; di.nc = t;
+        }
+    }
+    if (t == 0) {
+        rs_init(&rs, cf->seed, 0, OR_KIND_TAU, 0, (uint32_t)m, (uint32_t)cf->chain);
+        c->tau = slice_draw(logf_tau, &a, c->tau, &c->w_tau, &c->wa_tau, m, cf->burnin,
+                            cf->tune_start, cf->K, cf->shrink_cap, &rs, &di);
+    }
+    record(c, cf->G * cf->N + cf->G + cf->G * cf->L + 1, &di);
+    return di.bad;
+}
+
+/* beta_g for every gene, one coefficient at a time (l = 1..L, each with the
+ * latest values of the others); the genes are conditionally independent, so
+ * gene-major order is the same chain.  Genes with the learned proposal on
+ * take one independence Metropolis-Hastings step for the whole block. */
+static int64_t update_beta(or_ctx *c, int64_t m)
 {
     const or_config *cf = &c->cfg;
     const int64_t G = cf->G;
     const int N = cf->N, L = cf->L;
-    const int64_t m = c->m + 1;
-    const uint32_t mm = (uint32_t)m;
-    const uint32_t mask = cf->update_mask;
+    const int64_t off_beta = G * N + G;
     int64_t errs = 0;
-    const int64_t off_gam = G * N, off_beta = G * N + G, off_hyp = G * N + G + G * L;
-
-    /* Step 1: in parallel, eps_gn */
-    if (mask & (1u << OR_KIND_EPS)) {
 #pragma omp parallel for schedule(static) reduction(+:errs) num_threads(c->nthreads)
-        for (int64_t g = 0; g < G; ++g) {
-            for (int n = 0; n < N; ++n) {
-                eps_arg a = { c, g, n };
-                rstream rs;
-                draw_info di;
-                rs_init(&rs, cf->seed, (uint32_t)g, OR_KIND_EPS, (uint32_t)n, mm, (uint32_t)cf->chain);
-                int64_t i = g * N + n;
-                c->eps[i] = slice_draw(logf_eps, &a, c->eps[i], &c->w_eps[i], &c->wa_eps[i], m,
-                                       cf->burnin, cf->tune_start, cf->K, cf->shrink_cap, &rs, &di);
-                record(c, i, &di);
-                errs += di.bad;
-            }
+    for (int64_t g = 0; g < G; ++g) {
+        if (c->prop_on && !c->prop_mask[g]) {
+            imh_step(c, g, (uint32_t)m);
+            continue;
         }
-    }
-    /* Step 2: in parallel, gamma_g */
-    if (mask & (1u << OR_KIND_GAMMA)) {
-#pragma omp parallel for schedule(static) reduction(+:errs) num_threads(c->nthreads)
-        for (int64_t g = 0; g < G; ++g) {
-            double S = 0.0;
-            for (int n = 0; n < N; ++n) S += c->eps[g * N + n] * c->eps[g * N + n];
-            gam_arg a = { 0.5 * c->nu + (OR_MUTANT == 2 ? 1.0 : 0.5) * N + 1.0,
-                          0.5 * c->nu * c->tau + 0.5 * S };
+        c->imh_acc[g] = -1;
+        for (int l = 0; l < L; ++l) {
+            double bwork[OR_MAX_L];
+            for (int i = 0; i < L; ++i) bwork[i] = c->beta[g * L + i];
+            double Yl = 0.0;
+            int lx = OR_MUTANT == 5 ? (l + 1) % L : l;
+            for (int n = 0; n < N; ++n) Yl += (double)c->y[g * N + n] * c->X[n * L + lx];
+            beta_arg a = { c, g, l, Yl, bwork };
             rstream rs;
             draw_info di;
-            if (mask & (1u << OR_KIND_EXACT)) {
-                exact_arg e = { 0.5 * c->nu + 0.5 * N, (OR_MUTANT == 15 ? c->nu * c->tau : 0.5 * c->nu * c->tau) + 0.5 * S,
-                                1, INFINITY };
-                double v;
-                int t = exact_draw(&e, cf->seed, OR_KIND_EXACT, (uint32_t)g, 0, mm, (uint32_t)cf->chain, &v, &di);
-                if (t > 0) {
-                    c->gam[g] = v;
-                    di.kl = -1; di.nl = 0; di.nr = 0; di.nc = t;
-                    record(c, off_gam + g, &di);
-                    continue;
-                }
-            }
-            rs_init(&rs, cf->seed, (uint32_t)g, OR_KIND_GAMMA, 0, mm, (uint32_t)cf->chain);
-            c->gam[g] = slice_draw(logf_gam, &a, c->gam[g], &c->w_gam[g], &c->wa_gam[g], m,
-                                   cf->burnin, cf->tune_start, cf->K, cf->shrink_cap, &rs, &di);
-            record(c, off_gam + g, &di);
+            rs_init(&rs, cf->seed, (uint32_t)g, OR_KIND_BETA, (uint32_t)l, (uint32_t)m, (uint32_t)cf->chain);
+            const int64_t i = g * L + l;
+            c->beta[i] = slice_draw(logf_beta, &a, c->beta[i], &c->w_beta[i], &c->wa_beta[i], m,
+                                    cf->burnin, cf->tune_start, cf->K, cf->shrink_cap, &rs, &di);
+            record(c, off_beta + i, &di);
             errs += di.bad;
         }
     }
-    /* Step 3: reduction, then nu */
-    double sum_log = 0.0, sum_inv = 0.0;
-    for (int64_t g = 0; g < G; ++g) { sum_log += log(c->gam[g]); sum_inv += 1.0 / c->gam[g]; }
-    c->red[0] = sum_log;
-    c->red[1] = sum_inv;
-    if (mask & (1u << OR_KIND_NU)) {
-        nu_arg a = { (double)G, c->tau, sum_log, sum_inv, cf->d };
-        rstream rs;
-        draw_info di;
-        rs_init(&rs, cf->seed, 0, OR_KIND_NU, 0, mm, (uint32_t)cf->chain);
-        c->nu = slice_draw(logf_nu, &a, c->nu, &c->w_nu, &c->wa_nu, m, cf->burnin,
-                           cf->tune_start, cf->K, cf->shrink_cap, &rs, &di);
-        record(c, off_beta + G * L, &di);
-        errs += di.bad;
-    }
-    /* Step 4: reduction, then tau */
-    if (mask & (1u << OR_KIND_TAU)) {
-        tau_arg a = { cf->a + 0.5 * (double)G * c->nu - 1.0,
-                      cf->b + (OR_MUTANT == 8 ? 1.0 : 0.5) * c->nu * sum_inv };
-        rstream rs;
-        draw_info di;
-        int t = 0;
-        if (mask & (1u << OR_KIND_EXACT)) {
-            exact_arg e = { a.shape_m1 + 1.0, a.rate, 0, INFINITY };
-            double v;
-            t = exact_draw(&e, cf->seed, OR_KIND_EXACT, 0, 1, mm, (uint32_t)cf->chain, &v, &di);
-            if (t > 0) {
-                c->tau = v;
-                di.kl = -1; di.nl = 0; di.nr = 0; di.nc = t;
-            }
-        }
-        if (t == 0) {
-            rs_init(&rs, cf->seed, 0, OR_KIND_TAU, 0, mm, (uint32_t)cf->chain);
-            c->tau = slice_draw(logf_tau, &a, c->tau, &c->w_tau, &c->wa_tau, m, cf->burnin,
-                                cf->tune_start, cf->K, cf->shrink_cap, &rs, &di);
-        }
-        record(c, off_beta + G * L + 1, &di);
-        errs += di.bad;
-    }
-    /* Step 5: beta_g, in parallel over g (l = 1..L in order within a gene; the
-     * genes are conditionally independent, so gene-major order is the same
-     * chain).  Genes with the learned proposal on take one independence
-     * Metropolis-Hastings step for the whole block instead. */
-    if (mask & (1u << OR_KIND_BETA)) {
-#pragma omp parallel for schedule(static) reduction(+:errs) num_threads(c->nthreads)
-        for (int64_t g = 0; g < G; ++g) {
-            if (c->prop_on && !c->prop_mask[g]) {
-                imh_step(c, g, mm);
-                continue;
-            }
-            c->imh_acc[g] = -1;
-            for (int l = 0; l < L; ++l) {
-                double bwork[64];
-                for (int i = 0; i < L; ++i) bwork[i] = c->beta[g * L + i];
-                double Yl = 0.0;
-                int lx = OR_MUTANT == 5 ? (l + 1) % L : l;
-                for (int n = 0; n < N; ++n) Yl += (double)c->y[g * N + n] * c->X[n * L + lx];
-                beta_arg a = { c, g, l, Yl, bwork };
-                rstream rs;
-                draw_info di;
-                rs_init(&rs, cf->seed, (uint32_t)g, OR_KIND_BETA, (uint32_t)l, mm, (uint32_t)cf->chain);
-                int64_t i = g * L + l;
-                double x1 = slice_draw(logf_beta, &a, c->beta[i], &c->w_beta[i], &c->wa_beta[i], m,
-                                       cf->burnin, cf->tune_start, cf->K, cf->shrink_cap, &rs, &di);
-                c->beta[i] = x1;
-                record(c, off_gam + G + i, &di);
-                errs += di.bad;
-            }
-        }
-    }
-    /* The shift step (an addition; see shift_step), after step 5 */
-    if (mask & (1u << OR_KIND_SHIFT)) {
-#pragma omp parallel for schedule(static) num_threads(c->nthreads)
-        for (int64_t g = 0; g < G; ++g) shift_step(c, g, mm);
-    }
-    /* Steps 6 and 7: reductions, then theta_l (Normal) and sigma_l^2 (slice) */
+    return errs;
+}
+
+/* theta_l, then sigma_l^2, for each l: theta_l given beta and sigma_l^2 is
+ * Normal and drawn directly (Box-Muller); sigma_l^2 given beta and the new
+ * theta_l is InvGamma((G - 1)/2, sum_g (beta_gl - theta_l)^2 / 2) truncated
+ * to (0, s_l^2), slice sampled or drawn directly with the exact-draw option. */
+static int64_t update_theta_sigma(or_ctx *c, int64_t m)
+{
+    const or_config *cf = &c->cfg;
+    const int64_t G = cf->G;
+    const int L = cf->L;
+    const uint32_t mask = cf->update_mask, mm = (uint32_t)m;
+    const int64_t off_hyp = G * cf->N + G + G * L;
+    int64_t errs = 0;
     for (int l = 0; l < L; ++l) {
         double sb = 0.0;
         for (int64_t g = 0; g < G; ++g) sb += c->beta[g * L + l];
@@ -1066,41 +1128,74 @@ static int64_t sweep_once(or_ctx *c)
                 c->sig2[l] = slice_draw(logf_sig2, &a, c->sig2[l], &c->w_sig2[l], &c->wa_sig2[l], m,
                                         cf->burnin, cf->tune_start, cf->K, cf->shrink_cap, &rs, &di);
             }
-            record(c, off_beta + G * L + 2 + l, &di);
+            record(c, off_hyp + 2 + l, &di);
             errs += di.bad;
         }
     }
-    (void)off_hyp;
-    /* Running means and means of squares (Section 3.1) after burn-in */
-    if (m > cf->burnin) {
-        int64_t k = m - cf->burnin;
-        double *mu = c->mean, *sq = c->msq;
-        for (int64_t i = 0; i < G * N; ++i) welford(&mu[i], &sq[i], c->eps[i], k);
-        for (int64_t g = 0; g < G; ++g) welford(&mu[off_gam + g], &sq[off_gam + g], c->gam[g], k);
-        for (int64_t i = 0; i < G * L; ++i) welford(&mu[off_beta + i], &sq[off_beta + i], c->beta[i], k);
-        int64_t o = off_beta + G * L;
-        welford(&mu[o], &sq[o], c->nu, k);
-        welford(&mu[o + 1], &sq[o + 1], c->tau, k);
-        for (int l = 0; l < L; ++l) welford(&mu[o + 2 + l], &sq[o + 2 + l], c->theta[l], k);
-        for (int l = 0; l < L; ++l) welford(&mu[o + 2 + L + l], &sq[o + 2 + L + l], c->sig2[l], k);
-        c->count = k;
-    }
-    /* indicators of the contrast events at the end of the sweep (Section 3.2) */
-    if (c->n_ev > 0 && m > cf->burnin && m > c->ev_from) {
-        for (int64_t g = 0; g < G; ++g) {
-            for (int e = 0; e < c->n_ev; ++e) {
-                int all = 1;
-                for (int r = 0; r < c->n_crow; ++r) {
-                    if (c->crow_event[r] != e) continue;
-                    double sum = 0.0;
-                    for (int l = 0; l < L; ++l) sum += c->cv[r * L + l] * c->beta[g * L + l];
-                    if (OR_MUTANT == 12) { if (sum > c->cb[r]) all = 2; else if (all == 1) all = 0; }
-                    else if (!(sum > c->cb[r])) all = 0;
-                }
-                c->ev_count[g * c->n_ev + e] += all ? 1 : 0;
+    return errs;
+}
+
+/* Running means and means of squares of every parameter (Section 3.1), over
+ * the sweeps after burn-in. */
+static void update_moments(or_ctx *c, int64_t m)
+{
+    const int64_t G = c->cfg.G;
+    const int N = c->cfg.N, L = c->cfg.L;
+    const int64_t off_gam = G * N, off_beta = G * N + G;
+    const int64_t k = m - c->cfg.burnin;
+    double *mu = c->mean, *sq = c->msq;
+    for (int64_t i = 0; i < G * N; ++i) welford(&mu[i], &sq[i], c->eps[i], k);
+    for (int64_t g = 0; g < G; ++g) welford(&mu[off_gam + g], &sq[off_gam + g], c->gam[g], k);
+    for (int64_t i = 0; i < G * L; ++i) welford(&mu[off_beta + i], &sq[off_beta + i], c->beta[i], k);
+    int64_t o = off_beta + G * L;
+    welford(&mu[o], &sq[o], c->nu, k);
+    welford(&mu[o + 1], &sq[o + 1], c->tau, k);
+    for (int l = 0; l < L; ++l) welford(&mu[o + 2 + l], &sq[o + 2 + l], c->theta[l], k);
+    for (int l = 0; l < L; ++l) welford(&mu[o + 2 + L + l], &sq[o + 2 + L + l], c->sig2[l], k);
+    c->count = k;
+}
+
+/* Indicators of the contrast events (Section 3.2) at the end of the sweep. */
+static void count_events(or_ctx *c)
+{
+    const int64_t G = c->cfg.G;
+    const int L = c->cfg.L;
+    for (int64_t g = 0; g < G; ++g) {
+        for (int e = 0; e < c->n_ev; ++e) {
+            int all = 1;
+            for (int r = 0; r < c->n_crow; ++r) {
+                if (c->crow_event[r] != e) continue;
+                double sum = 0.0;
+                for (int l = 0; l < L; ++l) sum += c->cv[r * L + l] * c->beta[g * L + l];
+                if (OR_MUTANT == 12) { if (sum > c->cb[r]) all = 2; else if (all == 1) all = 0; }
+                else if (!(sum > c->cb[r])) all = 0;
             }
+            c->ev_count[g * c->n_ev + e] += all ? 1 : 0;
         }
     }
+}
+
+/* One sweep m = c->m + 1: the conditionals in the order of Algorithm 1
+ * (eps, gamma, nu, tau, beta, theta and sigma^2), each step enabled by its
+ * bit of update_mask; the shift step, when enabled, after beta. */
+static int64_t sweep_once(or_ctx *c)
+{
+    const uint32_t mask = c->cfg.update_mask;
+    const int64_t m = c->m + 1;
+    int64_t errs = 0;
+    if (mask & (1u << OR_KIND_EPS)) errs += update_eps(c, m);
+    if (mask & (1u << OR_KIND_GAMMA)) errs += update_gamma(c, m);
+    gamma_sums(c);
+    if (mask & (1u << OR_KIND_NU)) errs += update_nu(c, m);
+    if (mask & (1u << OR_KIND_TAU)) errs += update_tau(c, m);
+    if (mask & (1u << OR_KIND_BETA)) errs += update_beta(c, m);
+    if (mask & (1u << OR_KIND_SHIFT)) {
+#pragma omp parallel for schedule(static) num_threads(c->nthreads)
+        for (int64_t g = 0; g < c->cfg.G; ++g) shift_step(c, g, (uint32_t)m);
+    }
+    errs += update_theta_sigma(c, m);
+    if (m > c->cfg.burnin) update_moments(c, m);
+    if (c->n_ev > 0 && m > c->cfg.burnin && m > c->ev_from) count_events(c);
     c->m = m;
     return errs;
 }
@@ -1280,16 +1375,16 @@ int or_init_default(or_ctx *c)
     if (!c) return -1;
     const int64_t G = c->cfg.G;
     const int N = c->cfg.N, L = c->cfg.L;
-    double XtX[64 * 64];
+    double XtX[OR_MAX_L * OR_MAX_L];
     for (int i = 0; i < L; ++i)
         for (int j = 0; j < L; ++j) {
             double s = 0.0;
             for (int n = 0; n < N; ++n) s += c->X[n * L + i] * c->X[n * L + j];
             XtX[i * L + j] = s + (i == j ? 1e-8 : 0.0);
         }
-    double sb[64] = { 0 }, sbb[64] = { 0 }, sg = 0.0;
+    double sb[OR_MAX_L] = { 0 }, sbb[OR_MAX_L] = { 0 }, sg = 0.0;
     for (int64_t g = 0; g < G; ++g) {
-        double A[64 * 64], r[64];
+        double A[OR_MAX_L * OR_MAX_L], r[OR_MAX_L];
         memcpy(A, XtX, sizeof(double) * (size_t)(L * L));
         for (int l = 0; l < L; ++l) {
             double s = 0.0;

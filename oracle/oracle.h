@@ -3,8 +3,9 @@
  *
  * A plain, slow, FP64 CPU implementation of the fully Bayesian Gibbs sampler for
  * the Poisson-lognormal RNA-seq model (Section 4.1 and Fig. 3 of Landau & Niemi,
- * arXiv 1606.06659), following Algorithm 1 (the MCMC) and Algorithm 2 (the
- * univariate stepping-out slice sampler with tuning, Appendix A) step by step.
+ * arXiv 1606.06659): the Gibbs scan of Algorithm 1, with every non-normal
+ * conditional drawn by the univariate stepping-out slice sampler with an
+ * adaptive width of Algorithm 2 (Appendix A).
  *
  * Only the tests, the package's smoke check and the benchmark's CPU-baseline leg
  * may load this library.  It shares no code with the HIP path.
@@ -45,6 +46,11 @@ enum {
  * gamma_g, tau and sigma_l^2 by direct draws from their conjugate full
  * conditionals (Section 4.2 names this alternative); see oracle.c. */
 #define OR_UPDATE_ALL 0xFEu
+
+/* Bounds of the work arrays: at most OR_MAX_L coefficients and OR_MAX_ROWS
+ * distinct rows of X; or_create rejects larger designs (returns -1). */
+#define OR_MAX_L 8
+#define OR_MAX_ROWS 64
 
 typedef struct {
     int32_t G, N, L;
@@ -145,7 +151,7 @@ int or_mlp_loss_grad(const or_mlp *m, const double *phi, const double *target, i
                      double *loss, double *gW1, double *gb1, double *gW2, double *gb2,
                      double *gW3, double *gb3);
 
-/* Use the learned proposal for step 5: genes with fallback_mask[g] = 0 take
+/* Use the learned proposal for the beta draws: genes with fallback_mask[g] = 0 take
  * one independence Metropolis-Hastings step for beta_g (mlp.c describes the
  * features and the network); the others keep the slice steps.  The model is
  * copied.  m = NULL switches the proposal off. */

@@ -174,8 +174,6 @@ def test_imh_sweep_parity_fp64(oracle_lib):
         acc_o, la_o = o.imh()
         acc_g = F.fb_imh_last(g)
         flips = np.flatnonzero(acc_o != acc_g)
-        # a flipped decision must sit on a tie of the log acceptance ratio
-        assert np.all(np.abs(la_o[flips] - np.log(0.5)) < np.inf)
         assert flips.size == 0, (it, flips[:5], la_o[flips[:5]])
         n_acc += int(np.sum(acc_o == 1))
         for k in ("eps", "gam", "beta", "hyp"):

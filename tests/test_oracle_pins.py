@@ -95,7 +95,8 @@ TARGETS = [
 @pytest.mark.parametrize("name,target,params,dist,w", TARGETS, ids=[t[0] for t in TARGETS])
 def test_slice_step_is_stationary(oracle_lib, name, target, params, dist, w):
     n = 60000
-    rng = np.random.default_rng(hash(name) % 2 ** 32)
+    # a fixed seed per target, so pass/fail is the same in every run
+    rng = np.random.default_rng(1000 + [t[0] for t in TARGETS].index(name))
     x0 = dist.rvs(size=n, random_state=rng)
     x1 = oracle_lib.slice_test(target, params, x0, w, K=15, seed=77, m=3)
     # two steps from stationarity must still be stationary
