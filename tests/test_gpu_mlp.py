@@ -5,7 +5,7 @@
 * The network's outputs (proposal mean, log-diagonal and lower triangle of
   its factor) and the training gradients match the FP64 oracle on the same
   BF16-rounded weights and inputs (BF16 activations on the GPU: per-tensor
-  relative error <= 3e-2, cosine > 0.999).
+  relative error <= 2e-2, cosine > 0.999).
 * The features of every gene match the oracle's.
 * A full sweep with the IMH beta step (Laplace approximation corrected by a
   shift, a scale and a correlated factor) matches the oracle draw for draw in
@@ -89,8 +89,9 @@ def test_mlp_forward_matches_oracle(oracle_lib):
     # feed the oracle the rounded standardised inputs through an identity standardisation
     mo = dict(mr, fmean=np.zeros(32), fscale=np.ones(32))
     mu_o, ls_o, off_o = oracle_lib.mlp_forward(mo, x)
-    for g, o in ((mu_g, mu_o), (ls_g, ls_o), (off_g, off_o)):
-        assert _rel(g, o) < 3e-2, _rel(g, o)
+    for name, g, o in (("mu", mu_g, mu_o), ("ls", ls_g, ls_o), ("off", off_g, off_o)):
+        say(name, "rel", _rel(g, o), "cos", _cos(g - g.mean(0), o - o.mean(0)))
+        assert _rel(g, o) < 2e-2, _rel(g, o)
         assert _cos(g - g.mean(0), o - o.mean(0)) > 0.999
 
 
@@ -123,7 +124,7 @@ def test_mlp_gradients_match_oracle(oracle_lib):
         g = grads_g[k][:, :O] if k == "W3" else (grads_g[k][:O] if k == "b3" else grads_g[k])
         o = grads_o[k]
         say(k, "rel", _rel(g, o), "cos", _cos(g, o))
-        assert _rel(g, o) < 3e-2, (k, _rel(g, o))
+        assert _rel(g, o) < 2e-2, (k, _rel(g, o))
         assert _cos(g, o) > 0.999, (k, _cos(g, o))
     O = F.mlp_outputs(L)
     assert np.all(grads_g["W3"][:, O:] == 0) and np.all(grads_g["b3"][O:] == 0)
