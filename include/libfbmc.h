@@ -454,6 +454,35 @@ int fb_mlp_forward(const fb_mlp *w, int32_t L, const float *phi, int64_t B, floa
 int fb_mlp_loss_grad(const fb_mlp *w, int32_t L, const float *phi, const float *target, int64_t B,
                      float *loss, fb_mlp *grad);
 
+/* Allocation-free loss and gradients, for callers that cannot allocate device
+ * memory: code under HIP graph capture, tight training or serving loops,
+ * harnesses that forbid hipMalloc.  The result is that of fb_mlp_loss_grad,
+ * here on device buffers the caller owns:
+ *   master  [FB_MLP_PARAMS] floats, the fb_mlp blocks one after another in
+ *           the order fmean[32], fscale[32], W1[32][128], b1[128],
+ *           W2[128][128], b2[128], W3[128][64], b3[64], omean[8], oscale[8];
+ *   phi     [B][32] raw features;  target [B][L] whitened targets;
+ *   loss    one float, the mean loss;  grad [FB_MLP_PARAMS], same layout
+ *           (zero for fmean, fscale, omean, oscale).
+ * 32 <= B <= FB_NOALLOC_MAX_ROWS, B a multiple of 32; 1 <= L <= FB_MAX_L.
+ * Intermediate results (standardised inputs, activations, backward
+ * temporaries, per-row losses) live in a static device array of
+ * FB_NOALLOC_MAX_ROWS x 1057 floats (8.3 MiB), which each GPU the library runs
+ * on holds until the process ends; no call allocates or frees memory.  The
+ * work is enqueued on `stream` (a hipStream_t; NULL = the null stream) of the
+ * current device and the call returns without waiting; outputs are valid once
+ * the stream has reached that point.  Every call on one GPU shares that GPU's
+ * array, so calls that may overlap on one GPU (other streams, other threads)
+ * race; calls in order on one stream do not.  The first call on each device
+ * looks up the array's device address (do it once outside graph capture).
+ * Errors: FB_EINVAL (null pointer, L or B out of range, B above
+ * FB_NOALLOC_MAX_ROWS), FB_EDEVICE (a HIP call failed); message in
+ * fb_last_error(NULL). */
+#define FB_MLP_PARAMS        29072
+#define FB_NOALLOC_MAX_ROWS  2048
+int fb_mlp_loss_grad_noalloc(const float *master, int32_t L, const float *phi, const float *target, int64_t B,
+                             float *loss, float *grad, void *stream);
+
 const char *fb_last_error(const fb_ctx *c);
 const char *fb_strerror(int code);
 

@@ -10,7 +10,7 @@ CSRC = os.path.join(PKG, "csrc")
 INCLUDE = os.path.join(ROOT, "include")
 LIB = os.path.join(PKG, "libfbmc.so")
 
-SOURCES = ["fbmc_kernels.hip", "fbmc_mlp.hip", "fbmc_host.cpp"]
+SOURCES = ["fbmc_kernels.hip", "fbmc_mlp.hip", "fbmc_noalloc.hip", "fbmc_host.cpp"]
 
 HIPCC_FLAGS = [
     "-O3", "-std=c++17", "--offload-arch=gfx950", "-fPIC",
@@ -22,16 +22,22 @@ HIPCC_FLAGS = [
 
 def build(verbose: bool = False) -> str:
     """Compile every HIP source and link libfbmc.so next to this file."""
-    objs = []
     os.makedirs(os.path.join(PKG, "_build"), exist_ok=True)
+    cmds, objs = [], []
     for src in SOURCES:
         obj = os.path.join(PKG, "_build", os.path.splitext(src)[0] + ".o")
-        cmd = ["hipcc", *HIPCC_FLAGS, "-x", "hip", "-c", os.path.join(CSRC, src),
-               "-I", INCLUDE, "-I", CSRC, "-o", obj]
+        cmds.append(["hipcc", *HIPCC_FLAGS, "-x", "hip", "-c", os.path.join(CSRC, src),
+                     "-I", INCLUDE, "-I", CSRC, "-o", obj])
+        objs.append(obj)
+    # the sources compile independently: one hipcc process each, at once
+    procs = []
+    for cmd in cmds:
         if verbose:
             print(" ".join(cmd), flush=True)
-        subprocess.run(cmd, check=True)
-        objs.append(obj)
+        procs.append((cmd, subprocess.Popen(cmd)))
+    failed = [cmd for cmd, p in procs if p.wait() != 0]
+    if failed:
+        raise subprocess.CalledProcessError(1, failed[0])
     tmp = LIB + ".tmp"
     cmd = ["hipcc", "--offload-arch=gfx950", "-shared", "-fPIC", *objs, "-o", tmp]
     if verbose:

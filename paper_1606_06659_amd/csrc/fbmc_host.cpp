@@ -985,13 +985,6 @@ void block_to_mlp(const std::vector<float> &blk, fb_mlp *w)
 }
 
 // Scratch of one forward/backward pass on B rows.
-struct TrainBufs {
-    float *X = nullptr, *Tg = nullptr, *Z1 = nullptr, *H1 = nullptr, *Z2 = nullptr, *H2 = nullptr;
-    float *O = nullptr, *dO = nullptr, *dH = nullptr, *dZ2 = nullptr, *dZ1 = nullptr, *loss = nullptr;
-    float *grad = nullptr;
-    int B = 0;
-};
-
 int alloc_train(fb_ctx *c, TrainBufs &t, int B, int L)
 {
     int rc;
@@ -1008,49 +1001,6 @@ int alloc_train(fb_ctx *c, TrainBufs &t, int B, int L)
     return FB_OK;
 }
 
-hipError_t gemm(const float *A, int lda, int tA, const float *B, int ldb, int tB, float *C, int ldc, int M, int N,
-                int K, hipStream_t st)
-{
-    const int tiles = (M / 32) * (N / 32);
-    hipLaunchKernelGGL(gemm_bf16, dim3(tiles), dim3(64), 0, st, A, lda, tA, B, ldb, tB, C, ldc, M, N, K, 0);
-    return hipGetLastError();
-}
-
-// Loss and gradients of the mean Gaussian NLL over the B standardised rows in
-// t.X with targets t.Tg; the gradient block has the master layout.
-int forward_backward(fb_ctx *c, const float *master, TrainBufs &t, int L, hipStream_t st)
-{
-    const int B = t.B;
-    const float *W1 = master + kOffW1, *W2 = master + kOffW2, *W3 = master + kOffW3;
-    auto ew = [&](int64_t n) { return dim3((unsigned)((n + 255) / 256)); };
-    HIPCHK(c, gemm(t.X, kMlpF, 0, W1, kMlpH, 0, t.Z1, kMlpH, B, kMlpH, kMlpF, st));
-    hipLaunchKernelGGL(bias_gelu, ew((int64_t)B * kMlpH), dim3(256), 0, st, t.Z1, master + kOffB1, t.H1, B, kMlpH, 1);
-    HIPCHK(c, gemm(t.H1, kMlpH, 0, W2, kMlpH, 0, t.Z2, kMlpH, B, kMlpH, kMlpH, st));
-    hipLaunchKernelGGL(bias_gelu, ew((int64_t)B * kMlpH), dim3(256), 0, st, t.Z2, master + kOffB2, t.H2, B, kMlpH, 1);
-    HIPCHK(c, gemm(t.H2, kMlpH, 0, W3, kMlpO, 0, t.O, kMlpO, B, kMlpO, kMlpH, st));
-    hipLaunchKernelGGL(bias_gelu, ew((int64_t)B * kMlpO), dim3(256), 0, st, t.O, master + kOffB3, (float *)nullptr, B,
-                       kMlpO, 0);
-    hipLaunchKernelGGL(nll_grad, ew(B), dim3(256), 0, st, t.O, kMlpO, t.Tg, L, master + kOffOmean,
-                       master + kOffOscale, t.dO, t.loss, B);
-    HIPCHK(c, hipMemsetAsync(t.grad, 0, kMlpParams * sizeof(float), st));
-    float *g = t.grad;
-    // layer 3
-    HIPCHK(c, gemm(t.H2, kMlpH, 1, t.dO, kMlpO, 0, g + kOffW3, kMlpO, kMlpH, kMlpO, B, st));
-    hipLaunchKernelGGL(col_sum, dim3(kMlpO), dim3(256), 0, st, t.dO, B, kMlpO, g + kOffB3);
-    HIPCHK(c, gemm(t.dO, kMlpO, 0, W3, kMlpO, 1, t.dH, kMlpH, B, kMlpH, kMlpO, st));
-    hipLaunchKernelGGL(gelu_backward, ew((int64_t)B * kMlpH), dim3(256), 0, st, t.Z2, t.dH, t.dZ2, (int64_t)B * kMlpH);
-    // layer 2
-    HIPCHK(c, gemm(t.H1, kMlpH, 1, t.dZ2, kMlpH, 0, g + kOffW2, kMlpH, kMlpH, kMlpH, B, st));
-    hipLaunchKernelGGL(col_sum, dim3(kMlpH), dim3(256), 0, st, t.dZ2, B, kMlpH, g + kOffB2);
-    HIPCHK(c, gemm(t.dZ2, kMlpH, 0, W2, kMlpH, 1, t.dH, kMlpH, B, kMlpH, kMlpH, st));
-    hipLaunchKernelGGL(gelu_backward, ew((int64_t)B * kMlpH), dim3(256), 0, st, t.Z1, t.dH, t.dZ1, (int64_t)B * kMlpH);
-    // layer 1
-    HIPCHK(c, gemm(t.X, kMlpF, 1, t.dZ1, kMlpH, 0, g + kOffW1, kMlpH, kMlpF, kMlpH, B, st));
-    hipLaunchKernelGGL(col_sum, dim3(kMlpH), dim3(256), 0, st, t.dZ1, B, kMlpH, g + kOffB1);
-    HIPCHK(c, hipGetLastError());
-    return FB_OK;
-}
-
 double std_normal_key(uint64_t seed, uint32_t i, uint32_t j)
 {
     const uint4 r = philox4x32_10(make_uint4(i, j, 0xA11Cu, 0), (uint32_t)seed, (uint32_t)(seed >> 32));
@@ -1059,6 +1009,12 @@ double std_normal_key(uint64_t seed, uint32_t i, uint32_t j)
 }
 
 }  // namespace
+
+namespace fbmc {
+// The per-thread last error that fb_last_error(NULL) reports, for entry points
+// in other source files.
+void set_thread_error(const char *msg) { g_thread_err = msg; }
+}  // namespace fbmc
 
 // ===========================================================================
 // C ABI
@@ -1908,7 +1864,7 @@ int fb_proposal_train(fb_ctx *c, const fb_train_opts *opts, double *epoch_loss)
         for (int sidx = 0; sidx < steps; ++sidx) {
             HIPCHK(c, launch_gather_pairs(c->d_pairs, P, L, c->d_master, t.X, t.Tg, o.minibatch, (uint32_t)e,
                                           (uint32_t)sidx, (uint32_t)o.seed, (uint32_t)(o.seed >> 32), c->st));
-            if ((rc = forward_backward(c, c->d_master, t, L, c->st))) return rc;
+            HIPCHK(c, mlp_forward_backward(c->d_master, t, L, c->st));
             ++it;
             const float c1 = 1.0f - std::pow(b1, (float)it), c2 = 1.0f - std::pow(b2, (float)it);
             hipLaunchKernelGGL(adam_step, dim3((unsigned)((nopt + 255) / 256)), dim3(256), 0, c->st,
@@ -2125,7 +2081,7 @@ int fb_mlp_loss_grad(const fb_mlp *w, int32_t L, const float *phi, const float *
     hipError_t e = hipMemcpy(d_master, blk.data(), kMlpParams * sizeof(float), hipMemcpyHostToDevice);
     if (e == hipSuccess) e = hipMemcpy(t.X, X.data(), X.size() * sizeof(float), hipMemcpyHostToDevice);
     if (e == hipSuccess) e = hipMemcpy(t.Tg, target, (size_t)B * L * sizeof(float), hipMemcpyHostToDevice);
-    if (e == hipSuccess && forward_backward(&tmp, d_master, t, L, nullptr) != FB_OK) e = hipErrorUnknown;
+    if (e == hipSuccess) e = mlp_forward_backward(d_master, t, L, nullptr);
     if (e == hipSuccess) e = hipDeviceSynchronize();
     std::vector<float> lv((size_t)B), gb(kMlpParams);
     if (e == hipSuccess) e = hipMemcpy(lv.data(), t.loss, lv.size() * sizeof(float), hipMemcpyDeviceToHost);

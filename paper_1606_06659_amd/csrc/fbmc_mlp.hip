@@ -198,6 +198,85 @@ __global__ void pack_mlp(const float *master, MlpDev *out)
     if (t < 8) { out->omean[t] = master[kOffOmean + t]; out->oscale[t] = master[kOffOscale + t]; }
 }
 
+__global__ void fill_f32(float *p, int64_t n, float v)
+{
+    const int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (t < n) p[t] = v;
+}
+
+// X[b][k] = (phi[b][k] - fmean_k) fscale_k, the network's input standardisation.
+__global__ void standardise_rows(const float *phi, const float *master, float *X, int64_t B)
+{
+    const int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (t >= B * kMlpF) return;
+    const int k = (int)(t % kMlpF);
+    X[t] = (phi[t] - master[kOffFmean + k]) * master[kOffFscale + k];
+}
+
+// out = mean of v[0..n): one 256-thread workgroup; thread t sums v[t],
+// v[t + 256], ... in FP64 in order, then a fixed-order tree in LDS.
+__global__ __launch_bounds__(256) void mean_rows(const float *v, int64_t n, float *out)
+{
+    __shared__ double part[256];
+    const int t = (int)threadIdx.x;
+    double s = 0.0;
+    for (int64_t i = t; i < n; i += 256) s += (double)v[i];
+    part[t] = s;
+    __syncthreads();
+    for (int w = 128; w > 0; w >>= 1) {
+        if (t < w) part[t] += part[t + w];
+        __syncthreads();
+    }
+    if (t == 0) *out = (float)(part[0] / (double)n);
+}
+
+static hipError_t gemm(const float *A, int lda, int tA, const float *B, int ldb, int tB, float *C, int ldc, int M,
+                       int N, int K, hipStream_t st)
+{
+    const int tiles = (M / 32) * (N / 32);
+    hipLaunchKernelGGL(gemm_bf16, dim3(tiles), dim3(64), 0, st, A, lda, tA, B, ldb, tB, C, ldc, M, N, K, 0);
+    return hipGetLastError();
+}
+
+hipError_t mlp_forward_backward(const float *master, const TrainBufs &t, int L, hipStream_t st)
+{
+    const int B = t.B;
+    const float *W1 = master + kOffW1, *W2 = master + kOffW2, *W3 = master + kOffW3;
+    auto ew = [&](int64_t n) { return dim3((unsigned)((n + 255) / 256)); };
+    hipError_t e;
+#define FBMC_TRY(expr)                          \
+    do {                                        \
+        if ((e = (expr)) != hipSuccess) return e; \
+    } while (0)
+    FBMC_TRY(gemm(t.X, kMlpF, 0, W1, kMlpH, 0, t.Z1, kMlpH, B, kMlpH, kMlpF, st));
+    hipLaunchKernelGGL(bias_gelu, ew((int64_t)B * kMlpH), dim3(256), 0, st, t.Z1, master + kOffB1, t.H1, B, kMlpH, 1);
+    FBMC_TRY(gemm(t.H1, kMlpH, 0, W2, kMlpH, 0, t.Z2, kMlpH, B, kMlpH, kMlpH, st));
+    hipLaunchKernelGGL(bias_gelu, ew((int64_t)B * kMlpH), dim3(256), 0, st, t.Z2, master + kOffB2, t.H2, B, kMlpH, 1);
+    FBMC_TRY(gemm(t.H2, kMlpH, 0, W3, kMlpO, 0, t.O, kMlpO, B, kMlpO, kMlpH, st));
+    hipLaunchKernelGGL(bias_gelu, ew((int64_t)B * kMlpO), dim3(256), 0, st, t.O, master + kOffB3, (float *)nullptr, B,
+                       kMlpO, 0);
+    hipLaunchKernelGGL(nll_grad, ew(B), dim3(256), 0, st, t.O, kMlpO, t.Tg, L, master + kOffOmean,
+                       master + kOffOscale, t.dO, t.loss, B);
+    // a fill kernel, not a memset, so the sequence can be captured in a graph
+    hipLaunchKernelGGL(fill_f32, ew(kMlpParams), dim3(256), 0, st, t.grad, (int64_t)kMlpParams, 0.0f);
+    float *g = t.grad;
+    // layer 3
+    FBMC_TRY(gemm(t.H2, kMlpH, 1, t.dO, kMlpO, 0, g + kOffW3, kMlpO, kMlpH, kMlpO, B, st));
+    hipLaunchKernelGGL(col_sum, dim3(kMlpO), dim3(256), 0, st, t.dO, B, kMlpO, g + kOffB3);
+    FBMC_TRY(gemm(t.dO, kMlpO, 0, W3, kMlpO, 1, t.dH, kMlpH, B, kMlpH, kMlpO, st));
+    hipLaunchKernelGGL(gelu_backward, ew((int64_t)B * kMlpH), dim3(256), 0, st, t.Z2, t.dH, t.dZ2, (int64_t)B * kMlpH);
+    // layer 2
+    FBMC_TRY(gemm(t.H1, kMlpH, 1, t.dZ2, kMlpH, 0, g + kOffW2, kMlpH, kMlpH, kMlpH, B, st));
+    hipLaunchKernelGGL(col_sum, dim3(kMlpH), dim3(256), 0, st, t.dZ2, B, kMlpH, g + kOffB2);
+    FBMC_TRY(gemm(t.dZ2, kMlpH, 0, W2, kMlpH, 1, t.dH, kMlpH, B, kMlpH, kMlpH, st));
+    hipLaunchKernelGGL(gelu_backward, ew((int64_t)B * kMlpH), dim3(256), 0, st, t.Z1, t.dH, t.dZ1, (int64_t)B * kMlpH);
+    // layer 1
+    FBMC_TRY(gemm(t.X, kMlpF, 1, t.dZ1, kMlpH, 0, g + kOffW1, kMlpH, kMlpF, kMlpH, B, st));
+    hipLaunchKernelGGL(col_sum, dim3(kMlpH), dim3(256), 0, st, t.dZ1, B, kMlpH, g + kOffB1);
+#undef FBMC_TRY
+    return hipGetLastError();
+}
+
 // Adam on FP32 master weights; p, g, m, v of length n.
 __global__ void adam_step(float *p, const float *g, float *m, float *v, int64_t n, float lr, float b1,
                           float b2, float eps, float c1, float c2)

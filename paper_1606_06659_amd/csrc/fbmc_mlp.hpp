@@ -56,6 +56,23 @@ struct MlpDev {
     __attribute__((aligned(16))) __bf16 Wt[kWtFrags * 64 * 8];
 };
 
+// Device buffers of one forward and backward pass over B rows (B a multiple
+// of 32): standardised inputs X [B][F], targets Tg [B][L], pre-activations and
+// activations Z1, H1, Z2, H2 [B][H], outputs O and their gradient dO [B][O],
+// backward temporaries dH, dZ2, dZ1 [B][H], per-row losses [B], and the
+// gradient block grad [kMlpParams] in the master layout.
+struct TrainBufs {
+    float *X = nullptr, *Tg = nullptr, *Z1 = nullptr, *H1 = nullptr, *Z2 = nullptr, *H2 = nullptr;
+    float *O = nullptr, *dO = nullptr, *dH = nullptr, *dZ2 = nullptr, *dZ1 = nullptr, *loss = nullptr;
+    float *grad = nullptr;
+    int B = 0;
+};
+
+// Enqueues the forward pass, the per-row Gaussian NLL and the backward pass of
+// the batch mean on `st`; reads master, t.X and t.Tg, writes every other
+// buffer of t (grad entirely: the blocks with no gradient are set to zero).
+hipError_t mlp_forward_backward(const float *master, const TrainBufs &t, int L, hipStream_t st);
+
 __global__ void mfma_probe(const float *A, const float *B, float *C);
 __global__ void gemm_bf16(const float *A, int lda, int tA, const float *B, int ldb, int tB, float *C,
                           int ldc, int M, int N, int K, int accumulate);
@@ -65,6 +82,9 @@ __global__ void nll_grad(const float *O, int Op, const float *T, int L, const fl
                          const float *oscale, float *dO, float *loss, int B);
 __global__ void col_sum(const float *Mx, int rows, int cols, float *out);
 __global__ void pack_mlp(const float *master, MlpDev *out);
+__global__ void fill_f32(float *p, int64_t n, float v);
+__global__ void standardise_rows(const float *phi, const float *master, float *X, int64_t B);
+__global__ void mean_rows(const float *v, int64_t n, float *out);
 __global__ void adam_step(float *p, const float *g, float *m, float *v, int64_t n, float lr, float b1,
                           float b2, float eps, float c1, float c2);
 

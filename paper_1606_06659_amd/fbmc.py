@@ -83,7 +83,7 @@ EXPORTS = [
     "fb_strerror", "fb_default_train_opts", "fb_proposal_collect", "fb_proposal_train",
     "fb_proposal_calibrate", "fb_set_beta_update", "fb_proposal_get", "fb_proposal_set",
     "fb_fallback", "fb_imh_last", "fb_features", "fb_mfma_probe", "fb_mlp_forward",
-    "fb_mlp_loss_grad",
+    "fb_mlp_loss_grad", "fb_mlp_loss_grad_noalloc",
 ]
 
 _lib = None
@@ -571,6 +571,7 @@ def _load_proposal_api(L):
     L.fb_mfma_probe.argtypes = [_FP, _FP, _FP]
     L.fb_mlp_forward.argtypes = [C.POINTER(fb_mlp), i32, _FP, i64, _FP, _FP, _FP]
     L.fb_mlp_loss_grad.argtypes = [C.POINTER(fb_mlp), i32, _FP, _FP, i64, _FP, C.POINTER(fb_mlp)]
+    L.fb_mlp_loss_grad_noalloc.argtypes = [vp, i32, vp, vp, i64, vp, vp, vp]
 
 
 def fb_default_train_opts(**kw) -> fb_train_opts:
@@ -668,6 +669,27 @@ def fb_mlp_forward(params: dict, L: int, phi):
     _check(load().fb_mlp_forward(C.byref(st), L, _p(phi, C.c_float), B, _p(mu, C.c_float), _p(ls, C.c_float),
                                  _p(off, C.c_float)))
     return mu, ls, off
+
+
+FB_MLP_PARAMS = 29072
+FB_NOALLOC_MAX_ROWS = 2048
+
+
+def mlp_master_block(params: dict) -> np.ndarray:
+    """The network's parameters as one FP32 block in the order of MLP_SHAPES
+    (the `master` layout of fb_mlp_loss_grad_noalloc)."""
+    blk = np.concatenate([np.ascontiguousarray(params[k], dtype=np.float32).reshape(-1) for k in MLP_SHAPES])
+    assert blk.size == FB_MLP_PARAMS
+    return blk
+
+
+def fb_mlp_loss_grad_noalloc(master_ptr: int, L: int, phi_ptr: int, target_ptr: int, B: int, loss_ptr: int,
+                             grad_ptr: int, stream: int = 0):
+    """Device pointers (e.g. torch tensors' data_ptr()) in, nothing allocated;
+    the work is enqueued on `stream` (a hipStream_t handle, 0 = null stream)."""
+    vp = C.c_void_p
+    _check(load().fb_mlp_loss_grad_noalloc(vp(master_ptr), int(L), vp(phi_ptr), vp(target_ptr), int(B),
+                                           vp(loss_ptr), vp(grad_ptr), vp(stream or None)))
 
 
 def fb_mlp_loss_grad(params: dict, L: int, phi, target):
