@@ -347,6 +347,23 @@ int fb_set_shift_fusion(fb_ctx *c, int32_t fused);
 int fb_set_beta_lanes(fb_ctx *c, int32_t lanes);
 int32_t fb_get_beta_lanes(const fb_ctx *c);
 int fb_get_launch(const fb_ctx *c, int32_t *samples_per_wave, int32_t *fuse_hyper);
+/* Single-launch sweep (on = 1): the slice sweep with one lane per gene for
+ * beta and no shift step runs as one kernel per sweep instead of two.  One
+ * workgroup per 64-gene tile draws the tile's eps_gn (Algorithm 1 step 1) on
+ * four wavefronts, keeps the new values in LDS, and after a barrier draws
+ * gamma_g (step 2) and beta_g (step 5) from them; the previous sweep's
+ * hyperparameter step (steps 3, 4, 6, 7) runs in the launch's first
+ * workgroups while the tiles draw eps, and the gamma and beta draws wait for
+ * it through a per-segment flag in device memory (a bounded wait: should it
+ * ever time out, the sticky status becomes FB_EDEVICE).  The draws are those
+ * of the two-kernel sweep, bit for bit; samples_per_wave does not apply (a
+ * wavefront takes ceil(N / 4) samples).  Other sweeps (shift step, two beta
+ * lanes, learned or Laplace step) keep their kernels.  fb_autotune tries it.
+ * Default 0.  fb_get_tile_sweep returns the setting (0 for NULL).
+ * With it on, fb_kernel_times reports the whole launch as the eps time and
+ * 0 for the gamma/beta kernel.  Errors: FB_EINVAL. */
+int fb_set_tile_sweep(fb_ctx *c, int32_t on);
+int32_t fb_get_tile_sweep(const fb_ctx *c);
 
 /* Autotuner: times trial_sweeps sweeps (after 2 warm-up sweeps) for every
  * samples_per_wave in {1, 2, 4, 8} (up to max N), with and without fusion,
@@ -354,12 +371,15 @@ int fb_get_launch(const fb_ctx *c, int32_t *samples_per_wave, int32_t *fuse_hype
  * snapshot and keeps the fastest shape.  The chain continues exactly as if no trial had run (traces
  * and training pairs are not written by the trials; the time reported by
  * fb_last_sweep_time is the last trial's).  Outputs (each may be NULL): the
- * chosen shape, its time per sweep (ms), and table[8], the time per sweep of shape
- * k = 2 log2(samples_per_wave) + fuse_hyper, -1 if not tried (all with the
- * current beta lanes).  With the slice steps for beta (and the shift step,
+ * chosen shape, its time per sweep (ms), and table[10], the time per sweep of shape
+ * k = 2 log2(samples_per_wave) + fuse_hyper (k < 8, two-kernel sweep, current
+ * beta lanes), then the single-launch sweep (fb_set_tile_sweep) with
+ * fuse_hyper 1 (k = 8) and 0 (k = 9), tried for the plain slice sweep; -1 if
+ * not tried.  If a two-kernel shape wins, with the slice steps for beta (and the shift step,
  * if on, inside the gamma/beta kernel) it then times the other number of beta
  * lanes (fb_set_beta_lanes) at the chosen shape and keeps the faster;
- * ms_per_sweep is the time of the final choice.
+ * ms_per_sweep is the time of the final choice.  The single-launch setting
+ * is left at the choice (fb_get_tile_sweep).
  * Needs device memory for one copy of the state. */
 int fb_autotune(fb_ctx *c, int32_t trial_sweeps, int32_t *samples_per_wave, int32_t *fuse_hyper,
                 double *ms_per_sweep, double *table);

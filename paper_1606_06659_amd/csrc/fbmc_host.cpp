@@ -37,6 +37,8 @@ hipError_t launch_gb_pair(int precision, int maxL, bool shift, const SegInfo *se
 hipError_t launch_mlp_sweep(int precision, const SegInfo *segs, const int2 *tiles, int ntiles, const MlpDev *net,
                             hipStream_t st);
 hipError_t launch_philox(const uint4 *ctr, const uint2 *key, uint4 *out, int64_t n, hipStream_t st);
+hipError_t launch_tile(int precision, int maxL, int maxN, const SegInfo *segs, const int2 *tiles, int ntiles,
+                       const SweepArgs &a, int nhyp, const SweepArgs &ha, int *err, hipStream_t st);
 hipError_t launch_mlp_infer_raw(const float *phi, int64_t B, int L, const MlpDev *net, float *mu, float *ls,
                                 float *off, hipStream_t st);
 hipError_t launch_features(int precision, const SegInfo *seg, int64_t G, float *out, hipStream_t st);
@@ -92,6 +94,10 @@ struct fb_ctx {
     int2 *d_tiles = nullptr;
     int ntiles = 0;
     int maxL = 0;                     // largest L over the segments (picks the compiled bound)
+    int maxN = 0;                     // largest N over the segments (LDS of the single-launch sweep)
+    // the slice sweep (one beta lane, no shift step, no learned step) as one
+    // launch per sweep (sweep_tile) instead of the eps and gamma/beta kernels
+    bool tile = false;
     // eps work items (segment, tile, n0, n1): samples per wavefront `spw`
     int4 *d_items = nullptr;
     int nitems = 0, item_cap = 0, spw = 0;
@@ -559,6 +565,7 @@ int build_context(fb_ctx *c, const fb_dataset *dsv, int nds)
             }
             if ((rc = dalloc(c, (void **)&S.d_hyp, sizeof(HyperState)))) return rc;
             I.hyp = S.d_hyp;
+            if ((rc = dalloc(c, (void **)&I.hyp_flag, sizeof(int64_t)))) return rc;
             if (c->opt.debug_counts) {
                 if ((rc = dalloc(c, (void **)&I.dbg_eps, N * Gp * sizeof(int4)))) return rc;
                 if ((rc = dalloc(c, (void **)&I.dbg_gam, Gp * sizeof(int4)))) return rc;
@@ -596,7 +603,11 @@ int build_context(fb_ctx *c, const fb_dataset *dsv, int nds)
     }
     c->ntiles = (int)tiles.size();
     c->maxL = 0;
-    for (const auto &S : c->seg) c->maxL = std::max(c->maxL, S.L);
+    c->maxN = 0;
+    for (const auto &S : c->seg) {
+        c->maxL = std::max(c->maxL, S.L);
+        c->maxN = std::max(c->maxN, S.N);
+    }
     if ((rc = dalloc(c, (void **)&c->d_tiles, tiles.size() * sizeof(int2)))) return rc;
     HIPCHK(c, hipMemcpy(c->d_tiles, tiles.data(), tiles.size() * sizeof(int2), hipMemcpyHostToDevice));
     std::vector<SegInfo> infos;
@@ -695,6 +706,13 @@ static int gb_mode_of(const SweepMode &md, const SweepArgs &a)
     return !md.learned_kernel ? 0 : (md.learned && a.pair_base < 0) ? 2 : 1;
 }
 
+// The sweep runs as one launch (sweep_tile) when asked for and when it is the
+// plain slice sweep with one lane per gene for beta.
+static bool tile_sweep(const fb_ctx *c, const SweepMode &md, const SweepArgs &a)
+{
+    return c->tile && gb_mode_of(md, a) == 0 && c->beta_lanes == 1 && !((a.mask >> kKindShift) & 1u);
+}
+
 // Enqueue the sweeps args[0..n).  One sweep m is two launches: the eps kernel
 // of sweep m, which also runs the hyperparameter step of sweep m - 1 in its
 // first workgroups, then the gamma/beta kernel of sweep m (with the learned
@@ -731,26 +749,37 @@ static int launch_sweeps(fb_ctx *c, const SweepArgs *args, int64_t n, const Swee
             c->prof_shift[c->prof_n++] = (shift && !fused_shift) ? 1 : 0;
         }
         if (pe) HIPCHK(c, hipEventRecord(pe[0], c->st));
-        HIPCHK(c, launch_eps(c->prec, c->d_segs, c->d_items, c->nitems, a, pending ? nseg : 0, prev, c->d_err,
-                             c->st));
-        if (pe) HIPCHK(c, hipEventRecord(pe[1], c->st));
-        if (pe) HIPCHK(c, hipEventRecord(pe[2], c->st));
-        if (md.learned && !md.laplace)
-            HIPCHK(c, launch_mlp_sweep(c->prec, c->d_segs, c->d_tiles, c->ntiles, c->d_net, c->st));
-        if (gbm == 0 && c->beta_lanes == 2 && (!shift || fused_shift))
-            HIPCHK(c, launch_gb_pair(c->prec, c->maxL, shift, c->d_segs, c->d_tiles, c->ntiles, a, c->d_err,
-                                     c->st));
-        else if (fused_shift)
-            HIPCHK(c, launch_gb_shift(c->prec, gbm, c->maxL, c->d_segs, c->d_tiles, c->ntiles, a, gnet, c->d_err,
-                                      c->st));
-        else
-            HIPCHK(c, launch_gb(c->prec, gbm, c->maxL, c->d_segs, c->d_tiles, c->ntiles, c->d_fb_items,
-                                md.learned ? c->nfb_items : 0, a, gnet, c->d_err, c->st));
-        if (pe) HIPCHK(c, hipEventRecord(pe[3], c->st));
-        if (shift && !fused_shift) {
-            if (pe) HIPCHK(c, hipEventRecord(pe[6], c->st));
-            HIPCHK(c, launch_shift(c->prec, c->maxL, c->d_segs, c->d_tiles, c->ntiles, a, c->st));
-            if (pe) HIPCHK(c, hipEventRecord(pe[7], c->st));
+        if (tile_sweep(c, md, args[i])) {
+            // the whole sweep in one launch; its time is reported as the eps kernel's
+            HIPCHK(c, launch_tile(c->prec, c->maxL, c->maxN, c->d_segs, c->d_tiles, c->ntiles, a, pending ? nseg : 0,
+                                  prev, c->d_err, c->st));
+            if (pe) {
+                HIPCHK(c, hipEventRecord(pe[1], c->st));
+                HIPCHK(c, hipEventRecord(pe[2], c->st));
+                HIPCHK(c, hipEventRecord(pe[3], c->st));
+            }
+        } else {
+            HIPCHK(c, launch_eps(c->prec, c->d_segs, c->d_items, c->nitems, a, pending ? nseg : 0, prev, c->d_err,
+                                 c->st));
+            if (pe) HIPCHK(c, hipEventRecord(pe[1], c->st));
+            if (pe) HIPCHK(c, hipEventRecord(pe[2], c->st));
+            if (md.learned && !md.laplace)
+                HIPCHK(c, launch_mlp_sweep(c->prec, c->d_segs, c->d_tiles, c->ntiles, c->d_net, c->st));
+            if (gbm == 0 && c->beta_lanes == 2 && (!shift || fused_shift))
+                HIPCHK(c, launch_gb_pair(c->prec, c->maxL, shift, c->d_segs, c->d_tiles, c->ntiles, a, c->d_err,
+                                         c->st));
+            else if (fused_shift)
+                HIPCHK(c, launch_gb_shift(c->prec, gbm, c->maxL, c->d_segs, c->d_tiles, c->ntiles, a, gnet, c->d_err,
+                                          c->st));
+            else
+                HIPCHK(c, launch_gb(c->prec, gbm, c->maxL, c->d_segs, c->d_tiles, c->ntiles, c->d_fb_items,
+                                    md.learned ? c->nfb_items : 0, a, gnet, c->d_err, c->st));
+            if (pe) HIPCHK(c, hipEventRecord(pe[3], c->st));
+            if (shift && !fused_shift) {
+                if (pe) HIPCHK(c, hipEventRecord(pe[6], c->st));
+                HIPCHK(c, launch_shift(c->prec, c->maxL, c->d_segs, c->d_tiles, c->ntiles, a, c->st));
+                if (pe) HIPCHK(c, hipEventRecord(pe[7], c->st));
+            }
         }
         // top level psi(m) from the groups' phi(m - 1), before the hyperparameter step of m
         if (c->top_on) HIPCHK(c, launch_top(c->d_segs, nseg, c->opt.chains, c->d_top, c->top_pri, a, c->st));
@@ -780,6 +809,7 @@ static std::vector<int64_t> graph_signature(const fb_ctx *c, const SweepMode &md
                                 (int64_t)(uintptr_t)c->d_top};
     sig.push_back(c->fuse_shift ? 1 : 0);
     sig.push_back(c->beta_lanes);
+    sig.push_back(c->tile ? 1 : 0);
     for (int64_t i = 0; i < n; ++i) {
         sig.push_back(gb_mode_of(md, args[i]));
         sig.push_back((args[i].mask >> kKindShift) & 1u);
@@ -1133,6 +1163,10 @@ int fb_sync(fb_ctx *c)
     HIPCHK(c, hipStreamSynchronize(c->st));
     int flag = 0;
     HIPCHK(c, hipMemcpy(&flag, c->d_err, sizeof(int), hipMemcpyDeviceToHost));
+    if ((flag & 4) && !c->sticky) {
+        c->sticky = FB_EDEVICE;
+        c->err = "single-launch sweep: a wait for the hyperparameter step timed out";
+    }
     if (flag && !c->sticky) {
         c->sticky = FB_ENUMERIC;
         c->err = "a slice draw reached the shrink cap or met a non-finite log density";
@@ -1245,6 +1279,8 @@ int fb_set_state(fb_ctx *c, int32_t seg, const fb_state *s)
     }
     HIPCHK(c, hipMemcpy(S.d_hyp, &H, sizeof(H), hipMemcpyHostToDevice));
     c->m = s->m;
+    // the sweep index may go back: clear what the single-launch sweep waits on
+    for (auto &Sg : c->seg) HIPCHK(c, hipMemset(Sg.info.hyp_flag, 0, sizeof(int64_t)));
     return FB_OK;
 }
 
@@ -1614,6 +1650,16 @@ int fb_set_beta_lanes(fb_ctx *c, int32_t lanes)
 
 int32_t fb_get_beta_lanes(const fb_ctx *c) { return c ? c->beta_lanes : 0; }
 
+int fb_set_tile_sweep(fb_ctx *c, int32_t on)
+{
+    if (!c) return fail(nullptr, FB_EINVAL, "NULL context");
+    if (on != 0 && on != 1) return fail(c, FB_EINVAL, "on must be 0 or 1");
+    c->tile = on != 0;
+    return FB_OK;
+}
+
+int32_t fb_get_tile_sweep(const fb_ctx *c) { return c ? (c->tile ? 1 : 0) : 0; }
+
 int fb_set_shift_fusion(fb_ctx *c, int32_t fused)
 {
     if (!c) return fail(nullptr, FB_EINVAL, "NULL context");
@@ -1647,6 +1693,7 @@ void sweep_buffers(fb_ctx *c, std::vector<std::pair<void *, size_t>> &out)
         out.push_back({(void *)I.mom_beta, L * Gp * sizeof(double2)});
         out.push_back({(void *)I.partials, (size_t)I.pstride * kMaxParts * sizeof(double)});
         out.push_back({(void *)S.d_hyp, sizeof(HyperState)});
+        out.push_back({(void *)I.hyp_flag, sizeof(int64_t)});
         if (I.dbg_eps) {
             out.push_back({(void *)I.dbg_eps, N * Gp * sizeof(int4)});
             out.push_back({(void *)I.dbg_gam, Gp * sizeof(int4)});
@@ -1691,7 +1738,8 @@ int fb_autotune(fb_ctx *c, int32_t trial_sweeps, int32_t *samples_per_wave, int3
     const int spw0 = c->spw;
     const bool fuse0 = c->fuse;
     int best_spw = spw0, rc = FB_OK;
-    bool best_fuse = fuse0;
+    bool best_fuse = fuse0, best_tile = false;
+    c->tile = false;
     double best = 1e300;
     hipError_t e = copy_all(true);
     // one trial from the saved state: two warm-up sweeps, then trial_sweeps timed
@@ -1713,7 +1761,7 @@ int fb_autotune(fb_ctx *c, int32_t trial_sweeps, int32_t *samples_per_wave, int3
         return e == hipSuccess;
     };
     if (table)
-        for (int i = 0; i < 8; ++i) table[i] = -1.0;
+        for (int i = 0; i < 10; ++i) table[i] = -1.0;
     for (int k = 0; e == hipSuccess && rc == FB_OK && k < 8; ++k) {
         const int spw = 1 << (k >> 1), fz = k & 1;
         if (spw > std::min(maxN, 8)) continue;
@@ -1724,12 +1772,27 @@ int fb_autotune(fb_ctx *c, int32_t trial_sweeps, int32_t *samples_per_wave, int3
         if (table) table[k] = per;
         if (per < best) { best = per; best_spw = spw; best_fuse = fz != 0; }
     }
+    // the single-launch sweep (slice steps for beta, one lane, no shift step)
+    const bool plain_slice = c->beta_mode == FB_BETA_SLICE && !((c->opt.update_mask >> kKindShift) & 1u);
+    const int lanes_in = c->beta_lanes;
+    for (int fz = 1; plain_slice && fz >= 0 && e == hipSuccess && rc == FB_OK; --fz) {
+        c->tile = true;
+        c->beta_lanes = 1;
+        c->fuse = fz != 0;
+        double per = 0.0;
+        const bool ok = trial(per);
+        c->tile = false;
+        c->beta_lanes = lanes_in;
+        if (!ok) break;
+        if (table) table[8 + (1 - fz)] = per;
+        if (per < best) { best = per; best_fuse = fz != 0; best_tile = true; }
+    }
     // with the slice steps for beta, the other number of lanes per gene at the best shape
     const int lanes0 = c->beta_lanes;
     int best_lanes = lanes0;
     const bool slice_beta = c->beta_mode == FB_BETA_SLICE &&
                             (!((c->opt.update_mask >> kKindShift) & 1u) || c->fuse_shift);
-    if (slice_beta && e == hipSuccess && rc == FB_OK && (rc = build_items(c, best_spw)) == FB_OK) {
+    if (!best_tile && slice_beta && e == hipSuccess && rc == FB_OK && (rc = build_items(c, best_spw)) == FB_OK) {
         c->fuse = best_fuse;
         c->beta_lanes = 3 - lanes0;
         double per = 0.0;
@@ -1738,7 +1801,8 @@ int fb_autotune(fb_ctx *c, int32_t trial_sweeps, int32_t *samples_per_wave, int3
             best_lanes = c->beta_lanes;
         }
     }
-    c->beta_lanes = best_lanes;
+    c->beta_lanes = best_tile ? 1 : best_lanes;
+    c->tile = best_tile;
     c->m = m0;
     if (e == hipSuccess) e = copy_all(false);
     (void)hipFree(snap);

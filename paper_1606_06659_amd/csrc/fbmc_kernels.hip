@@ -1,19 +1,29 @@
 // fbmc_kernels.hip -- the sweep kernels of libfbmc for gfx950.
 //
-// One sweep of Algorithm 1 is two launches:
+// One sweep of Algorithm 1 is two launches on the context's stream:
 //
-//  gene_sweep<T>   one lane per gene, one wavefront per 64-gene tile.  Per gene it
-//                  draws eps_g1..eps_gN (step 1), gamma_g (step 2) and
-//                  beta_g1..beta_gL in order (step 5), updates the running
-//                  moments, and leaves per-tile FP64 partial sums for the
-//                  reductions of steps 3, 4, 6 and 7.  Running steps 1, 2 and 5
-//                  back to back is the same Markov chain as the printed order:
-//                  eps and beta do not depend on nu or tau, and nu, tau do not
-//                  depend on beta, so swapping step 5 ahead of steps 3-4 changes
-//                  no conditional and, with counter-based random numbers, no draw.
-//  hyper_sweep     one workgroup per segment: fixed-order reduction of the tile
-//                  partials, then nu and tau (slice), theta_l (Normal) and
-//                  sigma_l^2 (slice) in FP64, hyperparameter moments and trace.
+//  eps_sweep<T>      step 1: one lane per (gene, sample); a wavefront draws
+//                    eps_gn for a 64-gene tile and a run of samples.  Its first
+//                    workgroups (one per segment) run the previous sweep's
+//                    hyperparameter step (hyper_block): no eps conditional
+//                    involves a hyperparameter.
+//  gb_sweep<T, mode, kML>
+//                    steps 2 and 5: one 128-thread workgroup per tile,
+//                    wavefront 0 draws gamma_g and wavefront 1 beta_g1..beta_gL
+//                    (slice steps, or one independence-MH step for the block
+//                    with the learned or Laplace proposal), then the running
+//                    moments and the tile's FP64 partial sums of log gamma,
+//                    1/gamma, beta_l - theta_l and its square.
+//
+// Variants of the second launch: gb_pair_sweep (two lanes per gene for the
+// beta draws), gb_shift_sweep (the shift step after a barrier in the same
+// workgroup), shift_sweep (the shift step as a kernel of its own), and before
+// it mlp_sweep (the proposal network) in the learned form.  hyper_sweep runs the
+// hyperparameter step alone after the last sweep of a call, and top_sweep the
+// top level of the three-level form.  Running steps 1, 2 and 5 before 3, 4, 6
+// and 7 is the same Markov chain as the printed order: eps and beta do not
+// depend on nu or tau, nu and tau not on beta, gamma not on theta or sigma^2,
+// and with counter-based random numbers no draw changes either.
 //
 // Full conditionals (Section 4.1; the gene-level ones are evaluated as
 // differences from the current value x0, which keeps float arithmetic away from
@@ -651,8 +661,11 @@ __device__ inline void beta_finish(const SegInfo &S, const SweepArgs &a, int64_t
 // 64 genes of the tile and the samples n0 <= n < n1, one sample after the
 // other.  The eps conditional involves only y_gn, h_n, X_n beta_g and gamma_g,
 // so every (gene, sample) draw is independent of the others in the sweep.
+// se, sx (the single-launch sweep): LDS arrays [N][kTile] that receive the new
+// eps_gn and exp(h_n + eps_gn) for the tile's gamma and beta draws.
 template <typename T>
-__device__ inline void eps_wave(const SegInfo &S, int tile, int n0, int n1, const SweepArgs &a, int *err)
+__device__ inline void eps_wave(const SegInfo &S, int tile, int n0, int n1, const SweepArgs &a, int *err,
+                                T *se = nullptr, T *sx = nullptr)
 {
     const int lane = (int)(threadIdx.x & 63);
     const int64_t Gp = S.Gp;
@@ -720,6 +733,10 @@ __device__ inline void eps_wave(const SegInfo &S, int tile, int n0, int n1, cons
             welford(mo, (double)e1, a.inv_k);
             mom[idx] = mo;
         }
+        if (se) {
+            se[n * kTile + lane] = e1;
+            sx[n * kTile + lane] = dexp((T)S.h[n] + e1);
+        }
     }
     if (bad) raise_flag(err, 2);
 }
@@ -733,8 +750,9 @@ __device__ inline void eps_wave(const SegInfo &S, int tile, int n0, int n1, cons
 
 // Step 2 (wavefront 0): S_g = sum_n eps_gn^2, one gamma draw, moments, trace
 // and the tile partials of log gamma and 1 / gamma.
+// se: the tile's new eps in LDS ([N][kTile], single-launch sweep), else null
 template <typename T, int kML = kMaxL>
-__device__ inline void gamma_wave(const SegInfo &S, int tile, const SweepArgs &a, int *err)
+__device__ inline void gamma_wave(const SegInfo &S, int tile, const SweepArgs &a, int *err, const T *se = nullptr)
 {
     const int lane = (int)(threadIdx.x & 63);
     const int64_t Gp = S.Gp;
@@ -750,7 +768,7 @@ __device__ inline void gamma_wave(const SegInfo &S, int tile, const SweepArgs &a
         T S2 = (T)0;
 #pragma unroll 8
         for (int n = 0; n < N; ++n) {
-            const T e = eps[(int64_t)n * Gp + g];
+            const T e = se ? se[n * kTile + lane] : eps[(int64_t)n * Gp + g];
             S2 += e * e;
         }
         T gam = gamp[g];
@@ -825,9 +843,12 @@ __device__ inline void gamma_wave(const SegInfo &S, int tile, const SweepArgs &a
 //   run), fallback_group = false: a tile's wavefront; with a.learned the genes
 //   flagged for fallback are left to their fallback group
 //   fallback_group = true: up to 64 flagged genes, slice steps only
+//   sx: exp(h_n + eps_gn) of the tile's genes in LDS ([N][kTile], single-launch
+//   sweep, a tile's own wavefront), else null
 template <typename T, int kMode, int kML = kMaxL>
 __device__ inline void beta_genes(const SegInfo &S, int64_t g, bool active, int64_t col, bool fallback_group,
-                                  const SweepArgs &a, const MlpDev *__restrict__ net, int *err)
+                                  const SweepArgs &a, const MlpDev *__restrict__ net, int *err,
+                                  const T *sx = nullptr)
 {
     constexpr bool kLearned = kMode != 0;
     const int lane = (int)(threadIdx.x & 63);
@@ -867,7 +888,7 @@ __device__ inline void beta_genes(const SegInfo &S, int64_t g, bool active, int6
         const T *__restrict__ eps = (const T *)S.eps;
 #pragma unroll 8
         for (int n = 0; n < N; ++n) {
-            const T ehe = dexp((T)S.h[n] + eps[(int64_t)n * Gp + g]);
+            const T ehe = sx ? sx[n * kTile + lane] : dexp((T)S.h[n] + eps[(int64_t)n * Gp + g]);
             const int rr = S.row_of[n];
 #pragma unroll
             for (int r = 0; r < kMaxRows; ++r)
@@ -1312,12 +1333,13 @@ __global__ __launch_bounds__(192) void gb_pair_sweep(const SegInfo *__restrict__
 }
 
 // ---------------------------------------------------------------------------
-// Proposal network inference: one wavefront per 64-gene tile.  Features are
-// standardised, rounded to BF16 and stored row per gene in LDS; each layer is
-// 2 x (N / 32) output tiles of v_mfma_f32_32x32x16_bf16 whose A fragments are
-// read from the previous layer's LDS rows and whose B fragments are the packed
-// weights; bias and GELU are applied to the accumulators and the result is
-// written back to LDS as BF16 rows for the next layer.
+// Proposal network inference: one wavefront per block of 32 genes.  The
+// layers run transposed, out^T = W^T in^T, on v_mfma_f32_32x32x16_bf16 with
+// the packed weights (from LDS) as the A operand and the activations as the B
+// operand.  Only the standardised features pass through LDS (one row per
+// gene); after that the activations stay in registers: the accumulator tile of
+// one layer, after bias, GELU and BF16 rounding, is register for register the
+// B fragments of the next layer (hidden units numbered in wt_unit order).
 // ---------------------------------------------------------------------------
 
 // GELU(v) = v Phi(v) for inference, branch-free: with x = |v| / sqrt(2),
@@ -1698,7 +1720,10 @@ hipError_t launch_col_moments(const float *M, int64_t rows, int cols, double *ou
 constexpr int kHyperThreads = 256;
 constexpr int kHyperWaves = kHyperThreads / 64;
 
-__device__ inline void hyper_block(const SegInfo &S, const SweepArgs &a, int *err)
+// publish > 0 (the single-launch sweep): once the new values are written, the
+// segment's hyp_flag is set to `publish`, the index of the sweep whose gene
+// draws read them.
+__device__ inline void hyper_block(const SegInfo &S, const SweepArgs &a, int *err, int64_t publish = 0)
 {
     const int L = S.L;
     const int nparts = 2 + 2 * L;
@@ -1871,6 +1896,12 @@ __device__ inline void hyper_block(const SegInfo &S, const SweepArgs &a, int *er
     __syncthreads();
     double *hw = reinterpret_cast<double *>(S.hyp);
     for (int i = tid; i < kWords; i += kHyperThreads) hw[i] = hs[i];
+    if (publish > 0) {
+        // every wavefront's stores visible device-wide, then the flag
+        __builtin_amdgcn_fence(__ATOMIC_RELEASE, "agent");
+        __syncthreads();
+        if (tid == 0) __hip_atomic_store(S.hyp_flag, publish, __ATOMIC_RELEASE, __HIP_MEMORY_SCOPE_AGENT);
+    }
 }
 
 // ---------------------------------------------------------------------------
@@ -1999,6 +2030,71 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(7, 8))) voi
     eps_wave<T>(segs[sidx], tile, n0, n1, a, err);
 }
 
+// ---------------------------------------------------------------------------
+// Single-launch sweep (slice steps, one lane per gene for beta): one
+// 256-thread workgroup per tile.  Its four wavefronts draw the tile's eps
+// (wavefront w takes samples w s .. w s + s - 1, s = ceil(N / 4)), keeping the
+// new eps_gn and exp(h_n + eps_gn) in LDS; after a workgroup barrier
+// wavefront 0 draws gamma_g and wavefront 1 beta_g from them, the same
+// operations in the same order as eps_sweep followed by gb_sweep, so the
+// chain is the same bit for bit.  A tile's gamma and beta draws need the
+// previous sweep's hyperparameters; its eps draws do not, so the step runs
+// in the launch's first workgroups (one per segment) while the tiles draw eps,
+// and publishes the sweep index on the segment's flag, which wavefronts 0 and
+// 1 wait for (bounded) after the barrier.  The hyperparameter workgroups have
+// the lowest indices and wait for nothing, so they are dispatched and finish
+// whatever the other workgroups do.
+// ---------------------------------------------------------------------------
+constexpr int64_t kHyperSpins = 1 << 22;   // polls before a wait is abandoned (flag bit 4)
+
+// Polls are relaxed device-scope loads (no cache invalidation per poll); one
+// acquire fence after the flag is seen orders the hyperparameter reads after it.
+__device__ inline void wait_hyper(const SegInfo &S, int64_t m, int *err)
+{
+    int64_t spins = 0;
+    while (__hip_atomic_load(S.hyp_flag, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) < m) {
+        if (++spins > kHyperSpins) {
+            if ((threadIdx.x & 63) == 0) raise_flag(err, 4);
+            break;
+        }
+        __builtin_amdgcn_s_sleep(8);
+    }
+    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "agent");
+}
+
+template <typename T, int kML>
+__global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(4, 8))) void sweep_tile(const SegInfo *__restrict__ segs, const int2 *__restrict__ tiles,
+                                                  int ntiles, SweepArgs a0, int nhyp, SweepArgs ha, int *err)
+{
+    const SweepArgs a = resolve_args(a0);
+    if ((int)blockIdx.x < nhyp) {
+        hyper_block(segs[blockIdx.x], resolve_args(ha), err, a.m);
+        return;
+    }
+    const int tix = (int)blockIdx.x - nhyp;
+    if (tix >= ntiles) return;     // the whole workgroup
+    extern __shared__ __align__(16) unsigned char tile_lds[];
+    const int2 tt = tiles[tix];
+    const int sidx = __builtin_amdgcn_readfirstlane(tt.x);
+    const int tile = __builtin_amdgcn_readfirstlane(tt.y);
+    const SegInfo &S = segs[sidx];
+    const int wave = __builtin_amdgcn_readfirstlane((int)(threadIdx.x >> 6));
+    const int lane = (int)(threadIdx.x & 63);
+    const int N = S.N;
+    T *se = reinterpret_cast<T *>(tile_lds);
+    T *sx = se + N * kTile;
+    const int s = (N + 3) / 4;
+    const int n0 = wave * s < N ? wave * s : N;
+    const int n1 = n0 + s < N ? n0 + s : N;
+    eps_wave<T>(S, tile, n0, n1, a, err, se, sx);
+    __syncthreads();
+    if (wave >= 2) return;
+    if (nhyp > 0) wait_hyper(S, a.m, err);
+    const int64_t g = (int64_t)tile * kTile + lane;
+    if (wave == 0) gamma_wave<T, kML>(S, tile, a, err, se);
+    else beta_genes<T, 0, kML>(S, g, g < S.G, tile, false, a, nullptr, err, sx);
+}
+
 __global__ void philox_kernel(const uint4 *ctr, const uint2 *key, uint4 *out, int64_t n)
 {
     const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
@@ -2017,6 +2113,31 @@ hipError_t launch_eps(int precision, const SegInfo *segs, const int4 *items, int
         hipLaunchKernelGGL((eps_sweep<double>), dim3(blocks), dim3(256), 0, st, segs, items, nitems, a, nhyp, ha, err);
     else
         hipLaunchKernelGGL((eps_sweep<float>), dim3(blocks), dim3(256), 0, st, segs, items, nitems, a, nhyp, ha, err);
+    return hipGetLastError();
+}
+
+// maxN: the largest N over the segments (LDS: new eps and exp(h + eps) of a tile)
+hipError_t launch_tile(int precision, int maxL, int maxN, const SegInfo *segs, const int2 *tiles, int ntiles,
+                       const SweepArgs &a, int nhyp, const SweepArgs &ha, int *err, hipStream_t st)
+{
+    const int blocks = nhyp + ntiles;
+    if (blocks == 0) return hipSuccess;
+    const dim3 grid((unsigned)blocks), block(256);
+    if (precision == 0) {
+        const size_t lds = 2 * (size_t)maxN * kTile * sizeof(double);
+        if (maxL <= 5)
+            hipLaunchKernelGGL((sweep_tile<double, 5>), grid, block, lds, st, segs, tiles, ntiles, a, nhyp, ha, err);
+        else
+            hipLaunchKernelGGL((sweep_tile<double, kMaxL>), grid, block, lds, st, segs, tiles, ntiles, a, nhyp, ha,
+                               err);
+    } else {
+        const size_t lds = 2 * (size_t)maxN * kTile * sizeof(float);
+        if (maxL <= 5)
+            hipLaunchKernelGGL((sweep_tile<float, 5>), grid, block, lds, st, segs, tiles, ntiles, a, nhyp, ha, err);
+        else
+            hipLaunchKernelGGL((sweep_tile<float, kMaxL>), grid, block, lds, st, segs, tiles, ntiles, a, nhyp, ha,
+                               err);
+    }
     return hipGetLastError();
 }
 

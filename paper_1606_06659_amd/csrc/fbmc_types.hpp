@@ -99,6 +99,10 @@ struct SegInfo {
     int32_t *imh_last;            // [Gp] last sweep: 1 accepted, 0 rejected, -1 slice
     float *pairs;                 // training pairs [capacity][kPairStride]: features, beta
     const TopState *top;          // three-level form: the chain's top level (b, psi), else null
+    // single-launch sweep: the sweep index whose hyperparameter values the
+    // segment's HyperState holds, published by the hyperparameter step that
+    // runs in the first workgroups of that launch
+    int64_t *hyp_flag;
 };
 
 constexpr int kPairStride = 32 + kMaxL;   // 32 raw features then L targets

@@ -78,6 +78,7 @@ EXPORTS = [
     "fb_trace_genes", "fb_trace", "fb_trace_reset", "fb_debug_counts", "fb_reductions",
     "fb_philox", "fb_last_sweep_time", "fb_profile", "fb_kernel_times", "fb_set_graph", "fb_get_graph",
     "fb_set_contrasts", "fb_event_counts", "fb_set_top_level", "fb_get_top", "fb_set_top", "fb_set_shift_fusion", "fb_set_beta_lanes", "fb_get_beta_lanes",
+    "fb_set_tile_sweep", "fb_get_tile_sweep",
     "fb_set_launch",
     "fb_get_launch", "fb_autotune", "fb_last_error",
     "fb_strerror", "fb_default_train_opts", "fb_proposal_collect", "fb_proposal_train",
@@ -135,6 +136,9 @@ def load() -> C.CDLL:
     L.fb_set_beta_lanes.argtypes = [vp, i32]
     L.fb_get_beta_lanes.argtypes = [vp]
     L.fb_get_beta_lanes.restype = i32
+    L.fb_set_tile_sweep.argtypes = [vp, i32]
+    L.fb_get_tile_sweep.argtypes = [vp]
+    L.fb_get_tile_sweep.restype = i32
     L.fb_get_graph.argtypes = [vp]
     L.fb_get_graph.restype = C.c_int32
     L.fb_set_launch.argtypes = [vp, i32, i32]
@@ -432,6 +436,14 @@ def fb_set_launch(ctx, samples_per_wave: int, fuse_hyper: int):
     _check(load().fb_set_launch(ctx, int(samples_per_wave), int(fuse_hyper)), ctx)
 
 
+def fb_set_tile_sweep(ctx, on: int):
+    _check(load().fb_set_tile_sweep(ctx, int(on)), ctx)
+
+
+def fb_get_tile_sweep(ctx) -> int:
+    return int(load().fb_get_tile_sweep(ctx))
+
+
 def fb_get_launch(ctx):
     """(samples per eps wavefront, fused hyperparameter step 0/1)."""
     a, b = C.c_int32(), C.c_int32()
@@ -442,11 +454,15 @@ def fb_get_launch(ctx):
 def fb_autotune(ctx, trial_sweeps: int = 20):
     """Time every launch shape on snapshots of the state and keep the fastest.
     Returns (samples per wavefront, fused 0/1, ms per sweep, {(spw, fuse): ms
-    per sweep} of every shape tried)."""
+    per sweep} of every two-kernel shape tried, with ("tile", fuse) keys for
+    the single-launch sweep)."""
     a, b, t = C.c_int32(), C.c_int32(), C.c_double()
-    table = np.zeros(8)
+    table = np.zeros(10)
     _check(load().fb_autotune(ctx, int(trial_sweeps), C.byref(a), C.byref(b), C.byref(t), _p(table)), ctx)
     tried = {(1 << (k >> 1), k & 1): float(table[k]) for k in range(8) if table[k] >= 0}
+    for k, fz in ((8, 1), (9, 0)):
+        if table[k] >= 0:
+            tried[("tile", fz)] = float(table[k])
     return a.value, b.value, t.value, tried
 
 

@@ -125,6 +125,33 @@ def test_fp64_parity_edge_cases(oracle_lib, name, ds, kw):
     F.fb_destroy(g)
 
 
+@pytest.mark.parametrize("name,ds,kw", _edge_datasets(), ids=[e[0] for e in _edge_datasets()])
+def test_fp64_tile_sweep_parity(oracle_lib, name, ds, kw):
+    """The single-launch sweep against the oracle, in calls of four sweeps so
+    that the gamma and beta draws wait for the hyperparameter step of the
+    same launch: states, widths and moments after every call, and the
+    per-draw records of each call's last sweep."""
+    say("tile sweep case", name, ds.y.shape)
+    kw = dict(kw)
+    ora_kw = {}
+    if "priors" in kw:
+        p = kw.pop("priors")
+        ora_kw = dict(a=p["a"], b=p["b"], d=p["d"], c=np.array(p["c"]), s=np.array(p["s"]))
+        kw["priors"] = p
+    F, g, o = _make_pair(oracle_lib, ds, seed=3, burnin=10, tune_start=2, precision=0, **kw, **ora_kw)
+    F.fb_set_tile_sweep(g, 1)
+    F.fb_set_state(g, o.get_state())
+    for it in range(6):
+        o.sweep(4)
+        F.fb_sweep(g, 4)
+        _compare_fp64(F, g, o, f"{name} call {it + 1}")
+    mo, mg = o.moments(), F.fb_summaries(g)
+    for k in ("mean_eps", "msq_gam", "mean_beta", "mean_hyp", "msq_hyp"):
+        np.testing.assert_allclose(mg[k], mo[k], rtol=1e-9, atol=1e-12, err_msg=k)
+    assert F.fb_sync(g) == 0
+    F.fb_destroy(g)
+
+
 def test_shrink_cap_is_reported_and_matches(oracle_lib):
     ds = datagen.small_two_group(G=200, seed=1)
     F, g, o = _make_pair(oracle_lib, ds, seed=5, burnin=0, tune_start=0, precision=0, cap=2, w0=30.0)
@@ -248,25 +275,28 @@ def test_determinism_and_resume():
         assert np.array_equal(end[k], outs[0][k]), k
 
 
-SHAPES = [(1, 1), (1, 0), (3, 1), (16, 0), (16, 1)]
+# (samples per eps wavefront, hyperparameter step fused, single-launch sweep)
+SHAPES = [(1, 1, 0), (1, 0, 0), (3, 1, 0), (16, 0, 0), (16, 1, 0), (4, 1, 1), (4, 0, 1)]
 
 
 @pytest.mark.parametrize("precision,shift", [(0, 0), (1, 0), (1, 1)])
 def test_launch_shapes_give_identical_chains(precision, shift):
     """Every draw is a function of its counter only: the samples per eps
-    wavefront and fusing the hyperparameter step into the next eps launch
-    change no bit of the state, the moments or the trace."""
+    wavefront, fusing the hyperparameter step into the next eps launch and
+    the single-launch sweep change no bit of the state, the moments or the
+    trace."""
     F = require_gpu()
     ds = datagen.paper_design_16(G=1500, seed=5)
     outs = []
-    for spw, fuse in SHAPES:
-        say("shape", spw, fuse, "precision", precision)
+    for spw, fuse, tile in SHAPES:
+        say("shape", spw, fuse, tile, "precision", precision)
         opts = F.fb_default_options(burnin=15, tune_start=3, precision=precision, jitter=0, thin=1,
                                     trace_genes=10, trace_capacity=40, debug_counts=1,
                                     update_mask=F.FB_UPDATE_ALL | (F.FB_SHIFT if shift else 0))
         g = F.fb_create(ds.y, ds.X, ds.h, seed=6, options=opts)
         F.fb_set_launch(g, spw, fuse)
-        assert F.fb_get_launch(g) == (spw, fuse)
+        F.fb_set_tile_sweep(g, tile)
+        assert F.fb_get_launch(g) == (spw, fuse) and F.fb_get_tile_sweep(g) == tile
         F.fb_sweep(g, 7)
         F.fb_sweep(g, 1)
         F.fb_sweep(g, 22)
@@ -277,7 +307,7 @@ def test_launch_shapes_give_identical_chains(precision, shift):
         outs.append((st, summ, tr, cnt))
         F.fb_destroy(g)
     ref = outs[0]
-    for (spw, fuse), (st, summ, tr, cnt) in zip(SHAPES[1:], outs[1:]):
+    for (spw, fuse, _), (st, summ, tr, cnt) in zip(SHAPES[1:], outs[1:]):
         for k in STATE_KEYS:
             assert np.array_equal(st[k], ref[0][k]), (spw, fuse, k)
         for k in summ:
@@ -300,7 +330,7 @@ def test_autotune_leaves_the_chain_unchanged():
     F.fb_sweep(b, 12)
     spw, fuse, ms, tried = F.fb_autotune(b, 3)
     say("autotune chose", spw, fuse, ms, tried)
-    assert F.fb_get_launch(b) == (spw, fuse) and ms > 0 and len(tried) == 8
+    assert F.fb_get_launch(b) == (spw, fuse) and ms > 0 and len(tried) == 10
     F.fb_sweep(b, 18)
     sb, tb = F.fb_get_state(b), F.fb_trace(b)[0]
     F.fb_destroy(b)
@@ -309,8 +339,8 @@ def test_autotune_leaves_the_chain_unchanged():
     assert np.array_equal(ta, tb)
 
 
-@pytest.mark.parametrize("precision,shift", [(0, 0), (1, 0), (1, 1)])
-def test_batched_segments_match_single_runs(precision, shift):
+@pytest.mark.parametrize("precision,shift,tile", [(0, 0, 0), (1, 0, 0), (1, 1, 0), (0, 0, 1), (1, 0, 1)])
+def test_batched_segments_match_single_runs(precision, shift, tile):
     """Datasets of uneven G, N and L, each with two chains, in one context: every
     (dataset, chain) segment is bit-identical to the same dataset run alone
     (its draws use the dataset's seed and the chain index only; its
@@ -325,6 +355,7 @@ def test_batched_segments_match_single_runs(precision, shift):
                           F.fb_default_options(**opts))
     assert F.fb_num_segments(b) == 2 * len(dss)
     F.fb_set_launch(b, 2, 1)
+    F.fb_set_tile_sweep(b, tile)
     F.fb_sweep(b, 25)
     for k, d in enumerate(dss):
         s = F.fb_create(d.y, d.X, d.h, seed=100 + k, options=F.fb_default_options(**opts))
