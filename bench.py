@@ -51,6 +51,22 @@ def algorithmic_bytes(N: int, L: int, state_bytes: int, shift: bool = False):
 
 
 PROFILE_SUMMARY = os.path.join(ROOT, "profiles", "sweep_kernels_paper_G50k_N16.md")
+
+
+def progress(msg: str):
+    """A progress line on stderr (the JSON line goes to stdout)."""
+    print(f"[bench {time.strftime('%H:%M:%S')}] {msg}", file=sys.stderr, flush=True)
+
+
+def committed_record(name: str):
+    """A JSON record under profiles/ written from the GPU tests' output
+    (FBMC_RECORDS): FP32-against-FP64 errors and the network-against-Laplace
+    comparison.  None when absent."""
+    try:
+        with open(os.path.join(ROOT, "profiles", name + ".json")) as f:
+            return json.load(f)
+    except (OSError, ValueError):
+        return None
 KERNEL_SOURCES = ("fbmc_kernels.hip", "fbmc_device.hpp", "fbmc_types.hpp")
 
 
@@ -86,11 +102,8 @@ def measured_traffic():
     return rec
 
 
-def cpu_baseline(ds, seconds: float = 15.0):
-    """Time the plain FP64 oracle on the host on a bounded sample of sweeps."""
+def _time_oracle(ds, threads: int, seconds: float):
     import oracle
-    threads = int(os.environ.get("OMP_NUM_THREADS", "0")) or os.cpu_count() or 1
-    threads = min(threads, 16)
     o = oracle.Oracle(ds.y, ds.X, ds.h, seed=1, burnin=10, tune_start=2, threads=threads)
     o.sweep(1)                      # first sweep outside the timing
     n = 0
@@ -100,9 +113,27 @@ def cpu_baseline(ds, seconds: float = 15.0):
         n += 1
     dt = time.perf_counter() - t0
     o.close()
+    return n, dt
+
+
+def cpu_baseline(ds, seconds: float = 8.0):
+    """Time the plain FP64 oracle on the host on a bounded sample of sweeps:
+    once on one thread, once with OpenMP over genes on the cores this process
+    may use (at most 16).  The draws are the same either way (counter-based
+    random numbers), so only the speed differs."""
+    try:
+        avail = len(os.sched_getaffinity(0))
+    except (AttributeError, OSError):
+        avail = os.cpu_count() or 1
+    threads = max(1, min(int(os.environ.get("OMP_NUM_THREADS", "0")) or avail, avail, 16))
+    n1, dt1 = _time_oracle(ds, 1, seconds)
+    n, dt = _time_oracle(ds, threads, seconds)
     return dict(value=n / dt, unit="sweeps/s", cores=threads, kind="oracle",
                 sample=f"{n} sweeps of the G={ds.G}, N={ds.N}, L={ds.L} workload "
-                       f"(FP64, OpenMP over genes, {dt:.1f} s)")
+                       f"(FP64, OpenMP over genes on {threads} threads, {dt:.1f} s)",
+                single_thread={"value": n1 / dt1, "unit": "sweeps/s", "cores": 1,
+                               "sample": f"{n1} sweeps, {dt1:.1f} s"},
+                host={"nproc": os.cpu_count(), "usable_cpus": avail})
 
 
 def run_chain(fbmc, diagnostics, ds, args, burnin, post, do_ess, stream, learned, shift=False, exact=False,
@@ -162,7 +193,7 @@ def run_chain(fbmc, diagnostics, ds, args, burnin, post, do_ess, stream, learned
     if args.launch == "auto":
         spw, fuse, ms, tried = fbmc.fb_autotune(smp.ctx, 50)
         shape = {"samples_per_wave": spw, "fused_hyper": fuse, "beta_lanes": fbmc.fb_get_beta_lanes(smp.ctx),
-                 "autotuned_ms_per_sweep": ms,
+                 "tile_sweep": fbmc.fb_get_tile_sweep(smp.ctx), "autotuned_ms_per_sweep": ms,
                  "tried_ms_per_sweep": {f"{k[0]},{k[1]}": v for k, v in tried.items()}}
     else:
         spw, fuse = (int(v) for v in args.launch.split(","))
@@ -213,6 +244,91 @@ def run_chain(fbmc, diagnostics, ds, args, burnin, post, do_ess, stream, learned
     smp.close()
     return dict(sweeps_per_s=args.steps / (t1 - t0), ms_per_sweep=(t1 - t0) * 1e3 / args.steps,
                 kernel_ms=kt, launch=shape, ess=ess_info, proposal=proposal)
+
+
+def run_heavy_forms(fbmc, diagnostics, stream, iters=10_000, trace_genes=250):
+    """The heavy workload's comparison of beta updates: 4 chains x G = 200,000
+    x N = 48 in one context, FP32 draws with FP64 reductions, `iters`
+    iterations per form (25% burn-in), the beta of `trace_genes` genes per
+    chain traced after burn-in.  Forms: the slice steps (plain), the
+    independence step with the Laplace proposal (laplace) and with the trained
+    network's proposal (learned; pairs from 400 slice sweeps, 100 epochs), each
+    without and with the shift step and exact conjugate draws.  Reports
+    sweeps/s, the multi-chain min-ESS of beta (BDA3 estimator over the 4
+    chains) per second of post-burn-in time, and the algorithmic HBM GB/s."""
+    import torch
+    from paper_1606_06659_amd import datagen
+    ds = datagen.heavy_48(G=200_000, seed=0)
+    N, L, G, C = ds.N, ds.L, ds.G, 4
+    burnin = iters // 4
+    post = iters - burnin
+    out = {"workload": f"heavy G={G} N={N} L={L}, {C} chains in one context, {iters} iterations "
+                       f"({burnin} burn-in), FP32 draws, FP64 reductions and moments",
+           "zero_fraction": float((ds.y == 0).mean()), "forms": {}}
+    for name in ("plain", "laplace", "learned", "plain+shift+exact", "laplace+shift+exact",
+                 "learned+shift+exact"):
+        extra = "+shift+exact" in name
+        base = name.split("+")[0]
+        progress(f"heavy workload: {name}, {iters} iterations")
+        mask = fbmc.FB_UPDATE_ALL | ((fbmc.FB_SHIFT | fbmc.FB_EXACT) if extra else 0)
+        opts = fbmc.fb_default_options(burnin=burnin, tune_start=burnin // 10, precision=fbmc.FB_FP32, jitter=1,
+                                       chains=C, thin=1, trace_genes=trace_genes, trace_after_burnin=1,
+                                       trace_capacity=post, update_mask=mask, stream=stream.cuda_stream)
+        smp = fbmc.Sampler(ds.y, ds.X, ds.h, seed=1, **{k: getattr(opts, k) for k, *_ in opts._fields_})
+        info = {}
+        torch.cuda.synchronize()
+        t_all = time.perf_counter()
+        if base == "learned":
+            smp.sweep(burnin - 600)
+            fbmc.fb_proposal_collect(smp.ctx, 400, every=20)
+            losses = fbmc.fb_proposal_train(smp.ctx, fbmc.fb_default_train_opts(epochs=100))
+            fbmc.fb_proposal_calibrate(smp.ctx, 100, 0.2)
+            fbmc.fb_set_beta_update(smp.ctx, fbmc.FB_BETA_LEARNED)
+            smp.sweep(100)
+            info.update(loss_first=float(losses[0]), loss_last=float(losses[-1]),
+                        fallback_fraction=float(fbmc.fb_fallback(smp.ctx).mean()))
+        elif base == "laplace":
+            smp.sweep(burnin - 300)
+            fbmc.fb_set_beta_update(smp.ctx, fbmc.FB_BETA_LAPLACE)
+            fbmc.fb_proposal_calibrate(smp.ctx, 100, 0.2)
+            smp.sweep(200)
+            info["fallback_fraction"] = float(fbmc.fb_fallback(smp.ctx).mean())
+        else:
+            smp.sweep(burnin)
+        smp.sync()
+        spw, fuse, _, _ = fbmc.fb_autotune(smp.ctx, 10)
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        smp.sweep(post)
+        smp.sync()
+        torch.cuda.synchronize()
+        t1 = time.perf_counter()
+        if base != "plain":
+            last = fbmc.fb_imh_last(smp.ctx)
+            info["accept_last_sweep"] = float(np.mean(last[last >= 0] == 1))
+        tr = np.stack([smp.trace(c)[0] for c in range(C)])              # [C, M, stride]
+        smp.close()
+        M = tr.shape[1]
+        beta = tr[:, :, 2 + 2 * L:].reshape(C, M, trace_genes, L + 1)[:, :, :, 1:].reshape(C, M, -1)
+        ess = diagnostics.ess_batch_chains(np.transpose(beta, (0, 2, 1)))
+        _, _, _, b_sweep = algorithmic_bytes(N, L, 4, shift=extra)
+        per = (t1 - t0) / post
+        out["forms"][name] = {
+            "sweeps_per_s": 1.0 / per, "ms_per_sweep": per * 1e3, "post_burnin_seconds": t1 - t0,
+            "job_seconds": t1 - t_all, "min_ess": float(np.nanmin(ess)), "median_ess": float(np.nanmedian(ess)),
+            "min_ess_per_s": float(np.nanmin(ess)) / (t1 - t0),
+            "median_ess_per_s": float(np.nanmedian(ess)) / (t1 - t0),
+            "sweep_GBs": b_sweep * G * C / per / 1e9, "sweep_hbm_frac": b_sweep * G * C / per / 1e9 / HBM_PEAK_GBS,
+            "launch": {"samples_per_wave": spw, "fused_hyper": fuse}, **info}
+    f = out["forms"]
+    out["ratios"] = {"learned_vs_plain_min_ess_per_s": f["learned"]["min_ess_per_s"] / f["plain"]["min_ess_per_s"],
+                     "laplace_vs_plain_min_ess_per_s": f["laplace"]["min_ess_per_s"] / f["plain"]["min_ess_per_s"],
+                     "learned_vs_laplace_min_ess_per_s": f["learned"]["min_ess_per_s"] / f["laplace"]["min_ess_per_s"],
+                     "learned_vs_laplace_with_shift_min_ess_per_s":
+                         f["learned+shift+exact"]["min_ess_per_s"] / f["laplace+shift+exact"]["min_ess_per_s"],
+                     "learned_vs_plain_with_shift_min_ess_per_s":
+                         f["learned+shift+exact"]["min_ess_per_s"] / f["plain+shift+exact"]["min_ess_per_s"]}
+    return out
 
 
 def run_heavy(fbmc, stream, steps=100, burnin=300):
@@ -284,12 +400,16 @@ def run_small(fbmc, stream, steps=2000, graph_sweeps=50):
     return out
 
 
-def run_batched(fbmc, stream, steps=100, burnin=200, graph_sweeps=25):
+def run_batched(fbmc, stream, iters=5000, graph_sweeps=25):
     """Secondary measurement: the batched workload, 64 datasets (G log-uniform
     on [2,000, 60,000], N from {4, 8, 16} with L = 2, 3, 5; about 1.09M genes)
-    with one chain each, advancing together in one context, FP32.  After a
-    short burn-in the autotuner picks the launch shape; `steps` sweeps are then
-    timed with direct launches and with graph replay."""
+    with one chain each, advancing together in one context, FP32, `iters`
+    iterations in all.  After the burn-in (25%) the autotuner picks the launch
+    shape; the post-burn-in sweeps are timed, the first half with direct
+    launches and the second half with graph replay (chunks of graph_sweeps
+    sweeps from one captured HIP graph)."""
+    burnin = iters // 4
+    steps = (iters - burnin - 2 * graph_sweeps) // 2
     import torch
     from paper_1606_06659_amd import datagen
     meta = datagen.batched_meta(64, seed=0)
@@ -298,11 +418,14 @@ def run_batched(fbmc, stream, steps=100, burnin=200, graph_sweeps=25):
     opts = fbmc.fb_default_options(burnin=burnin, tune_start=burnin // 10, precision=fbmc.FB_FP32, jitter=0,
                                    stream=stream.cuda_stream)
     ctx = fbmc.fb_create_batch([dict(counts=d.y, X=d.X, h=d.h, seed=k + 1) for k, d in enumerate(dss)], opts)
-    fbmc.fb_sweep(ctx, burnin + 10)
+    t_all = time.perf_counter()
+    fbmc.fb_sweep(ctx, burnin)
     fbmc.fb_sync(ctx)
     spw, fuse, _, _ = fbmc.fb_autotune(ctx, 10)
-    out = {"workload": f"batched: 64 datasets, {genes} genes in total, N in {{4, 8, 16}}, 1 chain each",
-           "genes": genes, "steps": steps,
+    out = {"workload": f"batched: 64 datasets, {genes} genes in total, N in {{4, 8, 16}}, 1 chain each, "
+                       f"{iters} iterations ({burnin} burn-in)",
+           "genes": genes, "iterations": iters, "steps": steps,
+           "tile_sweep": fbmc.fb_get_tile_sweep(ctx),
            "launch": {"samples_per_wave": spw, "fused_hyper": fuse, "beta_lanes": fbmc.fb_get_beta_lanes(ctx)},
            "graph_sweeps": graph_sweeps}
     for name, k in (("direct", 0), ("graph", graph_sweeps)):
@@ -317,7 +440,10 @@ def run_batched(fbmc, stream, steps=100, burnin=200, graph_sweeps=25):
         dt = time.perf_counter() - t0
         out[f"{name}_sweeps_per_s"] = steps / dt
         out[f"{name}_gene_sweeps_per_s"] = steps * genes / dt
+    out["sweeps_run"] = int(fbmc.fb_get_state(ctx)["m"])
+    out["job_seconds"] = time.perf_counter() - t_all
     fbmc.fb_destroy(ctx)
+    out["graph_speedup"] = out["graph_sweeps_per_s"] / out["direct_sweeps_per_s"]
     return out
 
 
@@ -371,6 +497,8 @@ def main():
                     help="skip the chains with exact conjugate draws of gamma, tau and sigma^2")
     ap.add_argument("--no-heavy", action="store_true",
                     help="skip the secondary heavy workload (4 chains x G=200k x N=48)")
+    ap.add_argument("--no-heavy-forms", action="store_true",
+                    help="skip the heavy workload's comparison of beta updates (10,000 iterations per form)")
     ap.add_argument("--heavy-only", action="store_true",
                     help="run only the heavy workload and print its record (profiling runs)")
     ap.add_argument("--three-level-only", action="store_true",
@@ -415,9 +543,12 @@ def main():
         print(json.dumps({"heavy_workload": run_heavy(fbmc, stream, steps=args.steps, burnin=args.burnin)}),
               flush=True)
         return
-    run = lambda learned, shift, exact=False, laplace=False: run_chain(
-        fbmc, diagnostics, ds, args, burnin, post, do_ess, stream, learned=learned, shift=shift, exact=exact,
-        laplace=laplace)
+    def run(learned, shift, exact=False, laplace=False):
+        name = ("learned" if learned else "laplace" if laplace else "plain") + ("+shift" if shift else "") + \
+               ("+exact" if exact else "")
+        progress(f"paper design G={G}: {name} chain, {burnin + post} iterations")
+        return run_chain(fbmc, diagnostics, ds, args, burnin, post, do_ess, stream, learned=learned, shift=shift,
+                         exact=exact, laplace=laplace)
     plain = run(False, False)
     learned = None if args.no_learned else run(True, False)
     plain_shift = None if args.no_shift else run(False, True)
@@ -442,8 +573,17 @@ def main():
         "hyper_sweep": {"ms": hyp_ms, "fused_into_eps_sweep": bool(shape["fused_hyper"])},
         "samples": nsamp,
     }
-    dom = "eps_sweep" if eps_ms >= gb_ms else "gb_sweep"
+    if shape.get("tile_sweep"):
+        # the whole sweep is one launch (sweep_tile), timed as the eps kernel
+        kernels = {"sweep_tile": {"ms": eps_ms, "bytes_per_gene": b_sweep, "bytes_per_launch": b_sweep * G,
+                                  "achieved_GBs": gbs(b_sweep * G, eps_ms)},
+                   "hyper_sweep": kernels["hyper_sweep"], "samples": nsamp}
+        dom = "sweep_tile"
+    else:
+        dom = "eps_sweep" if eps_ms >= gb_ms else "gb_sweep"
     traffic = measured_traffic()
+    if traffic is not None and dom not in traffic.get("bytes_per_launch", {}):
+        traffic = None
     achieved = kernels[dom]["achieved_GBs"]
     ess_info = plain["ess"]
 
@@ -504,12 +644,21 @@ def main():
         "sweep_hbm": {"bytes_per_sweep": b_sweep * G, "achieved_GBs": b_sweep * G * sweeps_per_s / 1e9,
                       "frac": b_sweep * G * sweeps_per_s / 1e9 / HBM_PEAK_GBS},
     }
+    line["fp32_error"] = committed_record("fp32_error_paper_design")
+    line["network_vs_laplace"] = committed_record("network_vs_laplace")
     if not args.no_heavy:
+        progress("heavy workload (4 chains x G=200k, N=48), plain sweep timing")
         line["heavy_workload"] = run_heavy(fbmc, stream)
+        progress("small two-group workload")
         line["small_workload"] = run_small(fbmc, stream)
+        progress("batched workload (64 datasets), 5,000 iterations")
         line["batched_workload"] = run_batched(fbmc, stream)
+        progress("three-level workload")
         line["three_level_workload"] = run_three_level(fbmc, stream)
+    if not (args.no_heavy or args.no_heavy_forms or args.no_ess):
+        line["heavy_forms"] = run_heavy_forms(fbmc, diagnostics, stream)
     if not args.no_cpu_baseline:
+        progress("cpu baseline: the FP64 oracle on the host, one thread then all")
         line["cpu_baseline"] = cpu_baseline(ds)
     print(json.dumps(line), flush=True)
 

@@ -433,7 +433,10 @@ void fb_default_train_opts(fb_train_opts *o);
  * of every segment as training pairs (earlier pairs are discarded). */
 int fb_proposal_collect(fb_ctx *c, int64_t sweeps, int32_t every);
 /* Train the network on the stored pairs with the project's own device kernels:
- * standardisation from the pairs' means and sds, seeded initial weights, Adam
+ * input standardisation from the pairs' feature means and sds, the output map
+ * at the identity (omean 0, oscale 1: the targets are already whitened by the
+ * Laplace approximation), seeded initial weights for the hidden layers and a
+ * zero output layer (so the untrained network is the Laplace proposal), Adam
  * on the mean Gaussian negative log likelihood of the whitened beta given the
  * features.
  * epoch_loss (may be NULL) receives the mean training loss of each epoch. */

@@ -42,15 +42,29 @@ __host__ __device__ inline uint4 draw_counter(uint32_t g, uint32_t kind, uint32_
 }
 
 // Uniform (0, 1) from one 32-bit word.  Double: (r + 1/2) 2^-32, exact.  Float:
-// the top 24 bits, (r >> 8 + 1/2) 2^-24, exact in float and strictly inside (0, 1).
+// the top 24 bits, (r >> 8 + 1/2) 2^-24 rounded to float.  For r >> 8 >= 2^23
+// the half is lost to rounding, and the top word (r >> 8 = 2^24 - 1) would round
+// to exactly 1: a slice level log u = 0 then asks for points strictly above
+// log f(x0), which FP32 evaluations near the mode may never give (the draw ran
+// into the shrink cap once in a few 10^10 draws).  That one value is mapped to
+// the largest float below 1, so every result lies strictly inside (0, 1).
 template <typename T> __device__ inline T u01(uint32_t r);
 template <> __device__ inline double u01<double>(uint32_t r) { return ((double)r + 0.5) * 0x1p-32; }
-template <> __device__ inline float u01<float>(uint32_t r) { return ((float)(r >> 8) + 0.5f) * 0x1p-24f; }
+template <> __device__ inline float u01<float>(uint32_t r)
+{
+    const float u = ((float)(r >> 8) + 0.5f) * 0x1p-24f;
+    return u < 1.0f ? u : 0x1.fffffep-1f;
+}
 
-// Window offset: the high 28 bits of the word (the low 4 bits give K_L).
+// Window offset: the high 28 bits of the word (the low 4 bits give K_L); float,
+// as u01<float>, strictly below 1 so x0 lies inside the window.
 template <typename T> __device__ inline T uwin(uint32_t r);
 template <> __device__ inline double uwin<double>(uint32_t r) { return ((double)(r >> 4) + 0.5) * 0x1p-28; }
-template <> __device__ inline float uwin<float>(uint32_t r) { return ((float)(r >> 8) + 0.5f) * 0x1p-24f; }
+template <> __device__ inline float uwin<float>(uint32_t r)
+{
+    const float u = ((float)(r >> 8) + 0.5f) * 0x1p-24f;
+    return u < 1.0f ? u : 0x1.fffffep-1f;
+}
 
 __device__ inline double dlog(double x) { return ::log(x); }
 __device__ inline float dlog(float x) { return ::logf(x); }

@@ -52,6 +52,7 @@ using namespace fbmc;
 namespace {
 
 thread_local std::string g_thread_err;
+constexpr int kErrWordsHost = 8;   // the kernels' error record (kErrWords)
 
 struct Design {
     int R = 0;
@@ -614,7 +615,7 @@ int build_context(fb_ctx *c, const fb_dataset *dsv, int nds)
     for (auto &S : c->seg) infos.push_back(S.info);
     if ((rc = dalloc(c, (void **)&c->d_segs, infos.size() * sizeof(SegInfo)))) return rc;
     HIPCHK(c, hipMemcpy(c->d_segs, infos.data(), infos.size() * sizeof(SegInfo), hipMemcpyHostToDevice));
-    if ((rc = dalloc(c, (void **)&c->d_err, sizeof(int)))) return rc;
+    if ((rc = dalloc(c, (void **)&c->d_err, kErrWordsHost * sizeof(int)))) return rc;
     if (c->opt.stream) {
         c->st = (hipStream_t)c->opt.stream;
     } else {
@@ -1161,8 +1162,9 @@ int fb_sync(fb_ctx *c)
 {
     if (!c) return fail(nullptr, FB_EINVAL, "NULL context");
     HIPCHK(c, hipStreamSynchronize(c->st));
-    int flag = 0;
-    HIPCHK(c, hipMemcpy(&flag, c->d_err, sizeof(int), hipMemcpyDeviceToHost));
+    int e[kErrWordsHost] = {};
+    HIPCHK(c, hipMemcpy(e, c->d_err, sizeof(e), hipMemcpyDeviceToHost));
+    const int flag = e[0];
     if ((flag & 4) && !c->sticky) {
         c->sticky = FB_EDEVICE;
         c->err = "single-launch sweep: a wait for the hyperparameter step timed out";
@@ -1170,6 +1172,14 @@ int fb_sync(fb_ctx *c)
     if (flag && !c->sticky) {
         c->sticky = FB_ENUMERIC;
         c->err = "a slice draw reached the shrink cap or met a non-finite log density";
+        if (e[1]) {
+            static const char *kinds[] = {"?", "eps", "gamma", "hyperparameter", "tau", "beta"};
+            const int k = e[2] >= 1 && e[2] <= 5 ? e[2] : 0;
+            char buf[200];
+            std::snprintf(buf, sizeof buf, " (first: %s draw, dataset %d, chain %d, gene %d, sweep %d, index %d)",
+                          kinds[k], e[3], e[4], e[5], e[6], e[7]);
+            c->err += buf;
+        }
     }
     return c->sticky;
 }
@@ -1704,7 +1714,7 @@ void sweep_buffers(fb_ctx *c, std::vector<std::pair<void *, size_t>> &out)
             out.push_back({(void *)I.imh_last, Gp * sizeof(int32_t)});
         }
     }
-    out.push_back({(void *)c->d_err, sizeof(int)});
+    out.push_back({(void *)c->d_err, kErrWordsHost * sizeof(int)});
 }
 
 }  // namespace
@@ -1892,26 +1902,20 @@ int fb_proposal_train(fb_ctx *c, const fb_train_opts *opts, double *epoch_loss)
         blk[kOffFmean + k] = (float)mu;
         blk[kOffFscale + k] = var > 1e-12 ? (float)(1.0 / std::sqrt(var)) : 0.0f;
     }
+    // The targets are already whitened by the per-gene Laplace approximation,
+    // so the output map stays at the identity (omean 0, oscale 1) and the
+    // output layer starts at zero: the untrained network is exactly the
+    // Laplace proposal, and training only moves it where the pairs show a
+    // departure from it.
     for (int l = 0; l < 8; ++l) {
-        if (l < L) {
-            const double mu = mom[2 * (32 + l)] / (double)P;
-            const double var = std::max(0.0, mom[2 * (32 + l) + 1] / (double)P - mu * mu);
-            blk[kOffOmean + l] = (float)mu;
-            blk[kOffOscale + l] = (float)std::max(std::sqrt(var), 1e-3);
-        } else {
-            blk[kOffOscale + l] = 1.0f;
-        }
+        blk[kOffOmean + l] = 0.0f;
+        blk[kOffOscale + l] = 1.0f;
     }
-    // seeded initial weights: N(0, 1 / fan_in); the output layer starts small
+    // seeded initial weights of the hidden layers: N(0, 1 / fan_in)
     for (int i = 0; i < kMlpF * kMlpH; ++i)
         blk[kOffW1 + i] = (float)(std_normal_key(o.seed, 1, i) / std::sqrt((double)kMlpF));
     for (int i = 0; i < kMlpH * kMlpH; ++i)
         blk[kOffW2 + i] = (float)(std_normal_key(o.seed, 2, i) / std::sqrt((double)kMlpH));
-    for (int i = 0; i < kMlpH * kMlpO; ++i) {
-        const int col = i % kMlpO;
-        blk[kOffW3 + i] =
-            col < mlp_outputs(L) ? (float)(0.1 * std_normal_key(o.seed, 3, i) / std::sqrt((double)kMlpH)) : 0.0f;
-    }
     HIPCHK(c, hipMemcpy(c->d_master, blk.data(), kMlpParams * sizeof(float), hipMemcpyHostToDevice));
     float *d_m = nullptr, *d_v = nullptr;
     if ((rc = dalloc(c, (void **)&d_m, kMlpParams * sizeof(float)))) return rc;
@@ -1943,6 +1947,10 @@ int fb_proposal_train(fb_ctx *c, const fb_train_opts *opts, double *epoch_loss)
         }
         if (epoch_loss) epoch_loss[e] = esum / ((double)steps * o.minibatch);
     }
+    HIPCHK(c, hipMemcpyAsync(blk.data(), c->d_master, kMlpParams * sizeof(float), hipMemcpyDeviceToHost, c->st));
+    HIPCHK(c, hipStreamSynchronize(c->st));
+    for (float v : blk)
+        if (!std::isfinite(v)) return fail(c, FB_ENUMERIC, "training produced non-finite parameters");
     if ((rc = pack_net(c, c->d_master, c->d_net, c->st))) return rc;
     HIPCHK(c, hipStreamSynchronize(c->st));
     c->net_ready = true;

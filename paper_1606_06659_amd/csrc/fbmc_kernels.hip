@@ -157,9 +157,28 @@ __device__ inline void wave_lds_sync()
 template <int kML>
 __device__ inline int seg_L(const SegInfo &S) { return kML >= kMaxL ? S.L : (S.L < kML ? S.L : kML); }
 
+// err[0]: flag bits (2: a slice draw reached the shrink cap, 4: a wait for
+// the hyperparameter step timed out); err[1..7]: the first capped draw --
+// claimed, kind, dataset, chain, gene (-1 for a hyperparameter), sweep, index
+// within the kind (sample n, or -1).
+constexpr int kErrWords = 8;
+
 __device__ inline void raise_flag(int *err, int bit)
 {
     __hip_atomic_fetch_or(err, bit, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+}
+
+__device__ inline void report_cap(int *err, int kind, const SegInfo &S, int64_t g, int64_t m, int sub)
+{
+    raise_flag(err, 2);
+    if (atomicCAS(&err[1], 0, 1) == 0) {
+        err[2] = kind;
+        err[3] = S.dataset;
+        err[4] = S.chain;
+        err[5] = (int)g;
+        err[6] = (int)m;
+        err[7] = sub;
+    }
 }
 
 // ---------------------------------------------------------------------------
@@ -688,7 +707,7 @@ __device__ inline void eps_wave(const SegInfo &S, int tile, int n0, int n1, cons
 #pragma unroll
     for (int l = 0; l < kMaxL; ++l) beta[l] = l < L ? betap[(int64_t)l * Gp + g] : (T)0;
     const T inv_gam = (T)1 / ((const T *)S.gam)[g];
-    int bad = 0;
+    int bad = 0, bad_n = -1;
     // software pipeline: the next sample's inputs are requested before the
     // current draw, so their latency hides behind its slice loop
     int y_nx = 0;
@@ -726,7 +745,10 @@ __device__ inline void eps_wave(const SegInfo &S, int tile, int n0, int n1, cons
                 w_eps[idx] = w;
                 wa_eps[idx] = wa;
             }
-            bad |= rec.bad;
+            if (rec.bad) {
+                bad = 1;
+                bad_n = n;
+            }
             if (a.dbg) S.dbg_eps[idx] = make_int4(rec.kl, rec.nl, rec.nr, rec.nc);
         }
         if (sampling) {
@@ -738,7 +760,7 @@ __device__ inline void eps_wave(const SegInfo &S, int tile, int n0, int n1, cons
             sx[n * kTile + lane] = dexp((T)S.h[n] + e1);
         }
     }
-    if (bad) raise_flag(err, 2);
+    if (bad) report_cap(err, 1, S, g, a.m, bad_n);
 }
 
 // ---------------------------------------------------------------------------
@@ -827,7 +849,7 @@ __device__ inline void gamma_wave(const SegInfo &S, int tile, const SweepArgs &a
         S.partials[tile] = sv[0];
         S.partials[S.pstride + tile] = sv[1];
     }
-    if (bad) raise_flag(err, 2);
+    if (bad) report_cap(err, 2, S, g, a.m, -1);
 }
 
 
@@ -962,7 +984,7 @@ __device__ inline void beta_genes(const SegInfo &S, int64_t g, bool active, int6
     // taken after it (shift_sweep)
     if (!((a.mask >> kKindShift) & 1u))
         beta_finish<T, kML>(S, a, g, Gp, mine, beta, mob, th, col, lane, tslot, trow, sampling);
-    if (bad) raise_flag(err, 2);
+    if (bad) report_cap(err, 5, S, g, a.m, -1);
 }
 
 // Steps 2 and 5: one workgroup per tile (wavefront 0 gamma, wavefront 1
@@ -1316,7 +1338,7 @@ __global__ __launch_bounds__(192) void gb_pair_sweep(const SegInfo *__restrict__
 #pragma unroll
             for (int l = 0; l < kMaxL; ++l) sbeta[l][j] = (double)beta[l];
         }
-        if (bad) raise_flag(err, 2);
+        if (bad) report_cap(err, 5, S, g, a.m, -1);
     }
     __syncthreads();
     if constexpr (kShift) {
@@ -1628,7 +1650,13 @@ __global__ void features_kernel(const SegInfo *__restrict__ seg, float *__restri
 }
 
 // Minibatch gather: row i takes pair (Philox word of (i, step, epoch)) mod P,
-// standardises its features and copies its targets.
+// standardises its features and copies its targets, both clipped to
+// [-kPairClip, kPairClip]: a gene whose Laplace approximation is far off (two
+// Newton steps from a poor start) gives whitened draws in the tens, whose
+// squared residuals would dominate the loss; the proposal stays exact under
+// the MH correction whatever the network learns from them.
+constexpr float kPairClip = 8.0f;
+
 __global__ void gather_pairs(const float *__restrict__ pairs, int64_t P, int L, const float *__restrict__ master,
                              float *X, float *Tg, int B, uint32_t epoch, uint32_t step, uint32_t k0, uint32_t k1)
 {
@@ -1637,8 +1665,11 @@ __global__ void gather_pairs(const float *__restrict__ pairs, int64_t P, int L, 
     const uint4 r = philox4x32_10(make_uint4((uint32_t)i, step, epoch, 0xB0u), k0, k1);
     const int64_t p = (int64_t)(((uint64_t)r.x << 32 | r.y) % (uint64_t)P);
     const float *row = pairs + p * kPairStride;
-    for (int k = 0; k < kMlpF; ++k) X[(int64_t)i * kMlpF + k] = (row[k] - master[kOffFmean + k]) * master[kOffFscale + k];
-    for (int l = 0; l < L; ++l) Tg[(int64_t)i * L + l] = row[32 + l];
+    for (int k = 0; k < kMlpF; ++k) {
+        const float v = (row[k] - master[kOffFmean + k]) * master[kOffFscale + k];
+        X[(int64_t)i * kMlpF + k] = fminf(fmaxf(v, -kPairClip), kPairClip);
+    }
+    for (int l = 0; l < L; ++l) Tg[(int64_t)i * L + l] = fminf(fmaxf(row[32 + l], -kPairClip), kPairClip);
 }
 
 // Column sums and sums of squares (FP64) of a row-major [rows][cols] float array.
@@ -1892,7 +1923,7 @@ __device__ inline void hyper_block(const SegInfo &S, const SweepArgs &a, int *er
             }
         }
     }
-    if (bad && w0) raise_flag(err, 2);
+    if (bad && w0) report_cap(err, 3, S, -1, a.m, wave);
     __syncthreads();
     double *hw = reinterpret_cast<double *>(S.hyp);
     for (int i = tid; i < kWords; i += kHyperThreads) hw[i] = hs[i];

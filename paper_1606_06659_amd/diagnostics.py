@@ -128,3 +128,33 @@ def ess_batch(x, chunk: int = 256) -> np.ndarray:
         e[~np.isfinite(var0[:, 0]) | (var0[:, 0] <= 0)] = np.nan
         out[s:s + chunk] = e
     return out
+
+
+def ess_batch_chains(x, chunk: int = 256) -> np.ndarray:
+    """Multi-chain ESS of many parameters at once: x is [C, P, M] (chain,
+    parameter, draw).  The estimator of ``ess`` (between- and within-chain
+    variance, Geyer's initial monotone sequence), vectorised over parameters."""
+    x = np.asarray(x, dtype=np.float64)
+    C, P, M = x.shape
+    out = np.empty(P)
+    npairs = M // 2
+    for s in range(0, P, chunk):
+        xb = x[:, s:s + chunk]                           # [C, B, M]
+        acov = _autocov(xb)                              # [C, B, M]
+        W = (acov[:, :, 0] * M / (M - 1.0)).mean(axis=0)  # [B]
+        B = M * np.var(xb.mean(axis=2), axis=0, ddof=1) if C > 1 else np.zeros_like(W)
+        var_plus = (M - 1.0) / M * W + B / M
+        with np.errstate(invalid="ignore", divide="ignore"):
+            rho = 1.0 - (W[:, None] - acov.mean(axis=0)) / var_plus[:, None]
+        rho[:, 0] = 1.0
+        pairs = rho[:, 0:2 * npairs:2] + rho[:, 1:2 * npairs:2]
+        neg = pairs < 0
+        first_neg = np.where(neg.any(axis=1), neg.argmax(axis=1), npairs)
+        mono = np.minimum.accumulate(np.where(np.isnan(pairs), 0.0, pairs), axis=1)
+        keep = np.arange(npairs)[None, :] < first_neg[:, None]
+        total = np.sum(np.where(keep, mono, 0.0), axis=1)
+        tau = np.maximum(-1.0 + 2.0 * total, 1.0 / np.log10(max(C * M, 10)))
+        e = C * M / tau
+        e[~(var_plus > 0)] = np.nan
+        out[s:s + chunk] = e
+    return out

@@ -152,6 +152,26 @@ def test_fp64_tile_sweep_parity(oracle_lib, name, ds, kw):
     F.fb_destroy(g)
 
 
+def test_fp32_top_uniform_stays_below_one(oracle_lib):
+    """Regression: in FP32 the uniform of a Philox word with r >> 8 = 2^24 - 1
+    rounded to exactly 1, so the slice level was log f(x0) itself and the draw
+    could find no point above it.  Dataset 53 of the batched workload (G =
+    39,418, N = 16) meets that word in the eps draw of gene 5308, sample 11, at
+    sweep 3294 (Philox counter (5308, 1 << 24 | 11, 3294, 0), key 53), which
+    ran into the shrink cap; the chain must now pass that sweep cleanly, and
+    the failure record names nothing."""
+    F = require_gpu()
+    word = oracle_lib.philox(np.array([5308, (1 << 24) | 11, 3294, 0], np.uint32), np.array([53, 0], np.uint32))
+    assert int(word[0]) >> 8 == (1 << 24) - 1
+    G, N = datagen.batched_meta(64, seed=0)[52]
+    d = datagen.batched_dataset(53, G, N)
+    g = F.fb_create(d.y, d.X, d.h, seed=53,
+                    options=F.fb_default_options(burnin=1250, tune_start=125, precision=1, jitter=0))
+    F.fb_sweep(g, 3300)
+    assert F.fb_sync(g) == 0
+    F.fb_destroy(g)
+
+
 def test_shrink_cap_is_reported_and_matches(oracle_lib):
     ds = datagen.small_two_group(G=200, seed=1)
     F, g, o = _make_pair(oracle_lib, ds, seed=5, burnin=0, tune_start=0, precision=0, cap=2, w0=30.0)
@@ -162,6 +182,16 @@ def test_shrink_cap_is_reported_and_matches(oracle_lib):
     with pytest.raises(F.FbError) as e:
         F.fb_sync(g)
     assert e.value.code == F.FB_ENUMERIC
+    # the message names the first capped draw: one whose record shows the cap
+    msg = str(e.value)
+    say("shrink cap message:", msg)
+    assert "first:" in msg and "sweep 1," in msg
+    cnt = F.fb_debug_counts(g)
+    kind = msg.split("first: ")[1].split(" draw")[0]
+    gene = int(msg.split("gene ")[1].split(",")[0])
+    key = {"eps": "eps", "gamma": "gam", "beta": "beta", "hyperparameter": "hyp"}[kind]
+    rec = np.asarray(cnt[key])
+    assert np.any(rec[..., 3] >= 2) and (kind == "hyperparameter" or np.any(rec[gene][..., 3] >= 2))
     with pytest.raises(F.FbError):
         F.fb_sweep(g, 1)               # the flag is sticky
     _compare_fp64(F, g, o, "shrink cap")   # capped draws keep x0 on both sides

@@ -109,5 +109,14 @@ def test_rhat_and_ess_on_known_chains():
     want = C * 40000 * (1 - rho) / (1 + rho)
     got = diagnostics.ess(ar)
     assert 0.8 * want < got < 1.2 * want, (got, want)
+    # the vectorised multi-chain estimator equals the per-parameter one
+    many = np.stack([ar[:, :6000], 0.5 * ar[:, 6000:12000] + 1.0, iid[:, :6000] if M >= 6000 else
+                     rng.standard_normal((C, 6000))], axis=1)            # [C, 3, 6000]
+    many[1, 1] += 0.3                                                    # one chain off: B > 0
+    got = diagnostics.ess_batch_chains(many)
+    want = [diagnostics.ess(many[:, p]) for p in range(3)]
+    np.testing.assert_allclose(got, want, rtol=1e-10)
+    np.testing.assert_allclose(diagnostics.ess_batch_chains(many[:1]), [diagnostics.ess(many[0, p]) for p in range(3)],
+                               rtol=1e-10)
     lo, hi = diagnostics.normal_interval(0.0, 1.0)
     assert abs(hi - 1.96) < 1e-3 and abs(lo + 1.96) < 1e-3
