@@ -536,6 +536,7 @@ int build_context(fb_ctx *c, const fb_dataset *dsv, int nds)
                 }
             for (int l = 0; l < D.L; ++l) {
                 I.nv[l] = D.des.nv[l];
+                I.pm[l] = (D.des.nv[l] == 2 && D.des.vals[l * kMaxVals + 1] == -D.des.vals[l * kMaxVals]) ? 1 : 0;
                 for (int j = 0; j < kMaxVals; ++j) I.vals[l * kMaxVals + j] = D.des.vals[l * kMaxVals + j];
                 I.c[l] = D.c[l];
                 I.s[l] = D.s[l];

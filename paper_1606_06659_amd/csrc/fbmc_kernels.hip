@@ -35,6 +35,8 @@
 //          where Y_l = sum_n y_gn X_nl and G_k sums exp(h_n + eps_gn + X_n beta_g)
 //          over the samples whose X_nl equals the k-th distinct non-zero value v_k
 //          of column l (exact regrouping of the sum over n).
+#include <type_traits>
+
 #include "fbmc_device.hpp"
 #include "fbmc_mlp.hpp"
 #include "fbmc_types.hpp"
@@ -72,15 +74,26 @@ struct BetaF {
     T Gk[kMaxVals], vk[kMaxVals];
     T em1[kMaxVals];   // expm1(v_k d) at the last evaluated point
     int nv;
+    bool pm;           // the column's non-zero values are exactly v and -v
     __device__ T base(T) const { return (T)0; }
     __device__ T operator()(T x) {
         const T d = x - x0;
         T s = Y * d - d * (dth + (T)0.5 * d) * inv_s2;
+        if (std::is_same<T, float>::value && pm) {
+            // expm1(-v d) = -e / (1 + e) with e = expm1(v d): one exponential
+            // for a +-v column (both rounding errors are a few ulp)
+            const T e = dexpm1(vk[0] * d);
+            em1[0] = e;
+            em1[1] = -e * (T)__builtin_amdgcn_rcpf((float)((T)1 + e));
+            s -= Gk[0] * em1[0];
+            s -= Gk[1] * em1[1];
+        } else {
 #pragma unroll
-        for (int k = 0; k < kMaxVals; ++k) {
-            if (k < nv) {
-                em1[k] = dexpm1(vk[k] * d);
-                s -= Gk[k] * em1[k];
+            for (int k = 0; k < kMaxVals; ++k) {
+                if (k < nv) {
+                    em1[k] = dexpm1(vk[k] * d);
+                    s -= Gk[k] * em1[k];
+                }
             }
         }
         return s;
@@ -251,19 +264,30 @@ __device__ inline void beta_slice_draws(const SegInfo &S, const SweepArgs &a, in
     const int L = seg_L<kML>(S), R = S.R;
     const uint32_t mm = (uint32_t)a.m;
     T *__restrict__ betap = (T *)S.beta;
+    // Y_l = sum_r X_rl Y_r for every l up front: static offsets, so the design
+    // table's loads issue together instead of one dependent load per row and
+    // coefficient inside the loop (the same sums in the same order)
+    T Yl[kMaxL];
+#pragma unroll
+    for (int j = 0; j < kMaxL; ++j) {
+        Yl[j] = (T)0;
+#pragma unroll
+        for (int r = 0; r < kMaxRows; ++r) {
+            const T t = (T)S.Xrow[r * kMaxL + j] * YR[r];
+            Yl[j] = (j < L && r < R) ? Yl[j] + t : Yl[j];
+        }
+    }
     for (int l = 0; l < L; ++l) {
         const int64_t idx = (int64_t)l * Gp + g;
-        T b0 = (T)0, w = (T)1, wa = (T)0;
+        T b0 = (T)0, w = (T)1, wa = (T)0, Y = (T)0;
         double thl = 0.0, s2l = 1.0;
 #pragma unroll
         for (int j = 0; j < kMaxL; ++j)
-            if (j == l) { b0 = beta[j]; w = wb[j]; wa = wab[j]; thl = th[j]; s2l = s2[j]; }
+            if (j == l) { b0 = beta[j]; w = wb[j]; wa = wab[j]; thl = th[j]; s2l = s2[j]; Y = Yl[j]; }
         BetaF<T> f;
-        f.Y = (T)0;
-#pragma unroll
-        for (int r = 0; r < kMaxRows; ++r)
-            if (r < R) f.Y += (T)S.Xrow[r * kMaxL + l] * YR[r];
+        f.Y = Y;
         f.nv = S.nv[l];
+        f.pm = S.pm[l] != 0;
 #pragma unroll
         for (int k = 0; k < kMaxVals; ++k) {
             f.Gk[k] = (T)0;

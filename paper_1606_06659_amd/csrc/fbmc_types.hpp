@@ -59,6 +59,7 @@ struct SegInfo {
     double Xrow[kMaxRows * kMaxL];// [R][L] distinct rows
     int32_t xidx[kMaxRows * kMaxL];// [R][L]: index of X_rl among the column's non-zero values, -1 if 0
     int32_t nv[kMaxL];            // distinct non-zero values of column l
+    int32_t pm[kMaxL];            // 1: those values are exactly {v, -v} (v first)
     double vals[kMaxL * kMaxVals];// [L][kMaxVals]
     double XtX[kMaxL * kMaxL];    // [L][L] sum_n X_n^T X_n (shift step)
     // prior constants (Section 4.1)
