@@ -136,6 +136,29 @@ def cpu_baseline(ds, seconds: float = 8.0):
                 host={"nproc": os.cpu_count(), "usable_cpus": avail})
 
 
+def fp32_error_summary(rec):
+    """The FP32-against-FP64 record in short: per kind of draw the relative
+    error of the draws whose decisions match and the share of flipped
+    decisions; per long run whether the posterior means agree within 3 MCSE and
+    the relative error of the posterior means."""
+    if rec is None:
+        return None
+    pd = rec["per_draw"]
+    out = {"source": rec["source"], "workload": pd["workload"],
+           "kernel_sources_match": rec.get("kernel_sources_sha256") == kernel_sources_digest(),
+           "per_draw": {k: {f: pd[k][f] for f in ("median_rel_err", "p99_rel_err", "max_rel_err", "flipped_fraction")}
+                        for k in ("eps", "gam", "beta", "hyp")},
+           "reductions": pd["reductions"], "long_runs": {}}
+    for form, r in rec["long_runs"].items():
+        rel = r["rel_err_posterior_mean"]
+        out["long_runs"][form] = {"within_3_mcse": r["agree"], "above_3": r["above_3"], "quantities": r["quantities"],
+                                  "binom_p": r["binom_p"], "z_sd": r["z_sd"], "z_mean": r["z_mean"],
+                                  "rel_err_posterior_mean": {"beta_median": rel["beta_median"], "beta_p99": rel["beta_p99"],
+                                                             "log_gamma_median": rel["log_gamma_median"],
+                                                             "hyper_max": max(rel["hyper"].values())}}
+    return out
+
+
 def run_chain(fbmc, diagnostics, ds, args, burnin, post, do_ess, stream, learned, shift=False, exact=False,
               laplace=False):
     """One chain of the workload: `burnin` sweeps, then `post` post-burn-in
@@ -644,7 +667,7 @@ def main():
         "sweep_hbm": {"bytes_per_sweep": b_sweep * G, "achieved_GBs": b_sweep * G * sweeps_per_s / 1e9,
                       "frac": b_sweep * G * sweeps_per_s / 1e9 / HBM_PEAK_GBS},
     }
-    line["fp32_error"] = committed_record("fp32_error_paper_design")
+    line["fp32_error"] = fp32_error_summary(committed_record("fp32_error_paper_design"))
     line["network_vs_laplace"] = committed_record("network_vs_laplace")
     if not args.no_heavy:
         progress("heavy workload (4 chains x G=200k, N=48), plain sweep timing")

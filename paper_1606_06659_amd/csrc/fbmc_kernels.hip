@@ -1463,22 +1463,12 @@ __device__ inline void tile_to_next(const floatx16 &acc, const float *bias, int 
 // ks.  store(u, i, v) receives output u < O of row i (0..31) from lane
 // 32 h + i for the units 8 q + 4 h + t it holds.
 template <typename Store>
-__device__ inline void mlp_block(const float *row, bool active, const MlpLds &P, int O, Store &&store)
+__device__ inline void mlp_block_x(const bf16x8 (&x1)[2], const MlpLds &P, int O, Store &&store)
 {
     const bf16x8 *Wl = P.W;
     const int lane = (int)(threadIdx.x & 63);
     const int h = lane >> 5;
-    bf16x8 x1[2], h1[8], h2[8];
-#pragma unroll
-    for (int ks = 0; ks < 2; ++ks) {
-        float v8[8];
-#pragma unroll
-        for (int j = 0; j < 8; ++j) {
-            const int k = 16 * ks + 8 * h + j;
-            v8[j] = active ? (row[k] - P.fmean[k]) * P.fscale[k] : 0.0f;
-        }
-        x1[ks] = pack_bf16x8(v8);
-    }
+    bf16x8 h1[8], h2[8];
     const int nct3 = (O + 31) >> 5;
 #pragma unroll
     for (int ot = 0; ot < 4; ++ot) {
@@ -1520,6 +1510,26 @@ __device__ inline void mlp_block(const float *row, bool active, const MlpLds &P,
     }
 }
 
+// The same from a raw feature row in LDS: standardised and rounded to BF16
+// here (the layer-1 B fragments of lane 32 h + i).
+template <typename Store>
+__device__ inline void mlp_block(const float *row, bool active, const MlpLds &P, int O, Store &&store)
+{
+    const int h = (int)(threadIdx.x & 63) >> 5;
+    bf16x8 x1[2];
+#pragma unroll
+    for (int ks = 0; ks < 2; ++ks) {
+        float v8[8];
+#pragma unroll
+        for (int j = 0; j < 8; ++j) {
+            const int k = 16 * ks + 8 * h + j;
+            v8[j] = active ? (row[k] - P.fmean[k]) * P.fscale[k] : 0.0f;
+        }
+        x1[ks] = pack_bf16x8(v8);
+    }
+    mlp_block_x(x1, P, O, store);
+}
+
 // Copy of the network's parameters into the workgroup's LDS (all threads call).
 __device__ inline void load_weights(MlpLds &P, const MlpDev *__restrict__ net)
 {
@@ -1542,19 +1552,24 @@ __device__ inline void load_weights(MlpLds &P, const MlpDev *__restrict__ net)
 // Y_r) and the current theta, sigma^2, then the network; output u of gene g
 // goes to mlp_out[u][g].  512 threads: eight wavefronts share the weights in
 // LDS, each taking 32-gene blocks (half tiles) in turn.
-template <typename T>
-__global__ __launch_bounds__(512) void mlp_sweep(const SegInfo *__restrict__ segs, const int2 *__restrict__ tiles,
-                                                 int ntiles, const MlpDev *__restrict__ net)
+constexpr int kFrStrideB = kMlpF + 8;   // BF16 feature-row stride: 80 B, 16-B aligned fragments
+
+template <typename T, int kWaves>
+__global__ __launch_bounds__(512) __attribute__((amdgpu_waves_per_eu(4, 8))) void mlp_sweep(
+    const SegInfo *__restrict__ segs, const int2 *__restrict__ tiles, int ntiles, const MlpDev *__restrict__ net)
 {
     __shared__ MlpLds P;
-    // raw feature rows of each wavefront's 32 genes: written by lanes 0..31 at
-    // positions that depend on the segment's R and L, read back in order
-    __shared__ float fr[8][32 * kFrStride];
+    // standardised feature rows of each wavefront's 32 genes, in BF16 (the
+    // precision the first layer multiplies them in): written by lanes 0..31 at
+    // positions that depend on the segment's R and L, read back as fragments.
+    // BF16 rows keep a workgroup's LDS under half a CU's, so two workgroups
+    // share a CU.
+    __shared__ __align__(16) __bf16 frb[kWaves][32 * kFrStrideB];
     load_weights(P, net);
     const int wave = __builtin_amdgcn_readfirstlane((int)(threadIdx.x >> 6));
     const int lane = (int)(threadIdx.x & 63);
-    float *row = &fr[wave][(lane & 31) * kFrStride];
-    for (int bi = (int)blockIdx.x * 8 + wave; bi < 2 * ntiles; bi += (int)gridDim.x * 8) {
+    __bf16 *rowb = &frb[wave][(lane & 31) * kFrStrideB];
+    for (int bi = (int)blockIdx.x * kWaves + wave; bi < 2 * ntiles; bi += (int)gridDim.x * kWaves) {
         const int2 tt = tiles[bi >> 1];
         const int sidx = __builtin_amdgcn_readfirstlane(tt.x);
         const int tile = __builtin_amdgcn_readfirstlane(tt.y);
@@ -1584,26 +1599,32 @@ __global__ __launch_bounds__(512) void mlp_sweep(const SegInfo *__restrict__ seg
         // theta_l, log sigma_l^2, zero to 32
         wave_lds_sync();                  // earlier readers of the rows are done
         if (lane < 32) {
+            // feature k standardised as (phi_k - fmean_k) fscale_k, then BF16
+            auto put = [&](int k, float v) { rowb[k] = (__bf16)((v - P.fmean[k]) * P.fscale[k]); };
 #pragma unroll
-            for (int k = 0; k < kMlpF; ++k) row[k] = 0.0f;
+            for (int k = 0; k < kMlpF; ++k) put(k, 0.0f);
 #pragma unroll
             for (int r = 0; r < kMaxRows; ++r)
                 if (r < R) {
                     const float y = (float)YR[r] + 0.5f;
-                    row[r] = ::logf(y / (float)A[r]);
-                    row[R + r] = ::logf(y);
+                    put(r, ::logf(y / (float)A[r]));
+                    put(R + r, ::logf(y));
                 }
 #pragma unroll
             for (int l = 0; l < kMaxL; ++l)
                 if (l < L) {
-                    row[2 * R + l] = (float)S.hyp->theta[l];
-                    row[2 * R + L + l] = ::logf((float)S.hyp->sig2[l]);
+                    put(2 * R + l, (float)S.hyp->theta[l]);
+                    put(2 * R + L + l, ::logf((float)S.hyp->sig2[l]));
                 }
         }
         wave_lds_sync();
+        bf16x8 x1[2];
+        const bf16x8 *frag = reinterpret_cast<const bf16x8 *>(rowb);
+#pragma unroll
+        for (int ks = 0; ks < 2; ++ks) x1[ks] = active ? frag[2 * ks + (lane >> 5)] : bf16x8{};
         float *__restrict__ out = S.mlp_out;
         const int64_t G = S.G;
-        mlp_block(row, active, P, mlp_outputs(L), [&](int u, int rw, float v) {
+        mlp_block_x(x1, P, mlp_outputs(L), [&](int u, int rw, float v) {
             if (g0 + rw < G) out[(int64_t)u * Gp + g0 + rw] = v;
         });
     }
@@ -1733,12 +1754,15 @@ hipError_t launch_mlp_sweep(int precision, const SegInfo *segs, const int2 *tile
                             hipStream_t st)
 {
     if (ntiles <= 0) return hipSuccess;
+    // eight wavefronts per workgroup share one copy of the weights (four per
+    // workgroup, which would spread small launches over more CUs, measured
+    // slower at G = 50,000: 53.2 against 50.6 us for network and MH step)
     const int nwg = (2 * ntiles + 7) / 8;
     const dim3 grid((unsigned)(nwg < 512 ? nwg : 512)), block(512);
     if (precision == 1)
-        hipLaunchKernelGGL(mlp_sweep<float>, grid, block, 0, st, segs, tiles, ntiles, net);
+        hipLaunchKernelGGL((mlp_sweep<float, 8>), grid, block, 0, st, segs, tiles, ntiles, net);
     else
-        hipLaunchKernelGGL(mlp_sweep<double>, grid, block, 0, st, segs, tiles, ntiles, net);
+        hipLaunchKernelGGL((mlp_sweep<double, 8>), grid, block, 0, st, segs, tiles, ntiles, net);
     return hipGetLastError();
 }
 
