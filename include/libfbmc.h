@@ -397,7 +397,8 @@ int fb_autotune(fb_ctx *c, int32_t trial_sweeps, int32_t *samples_per_wave, int3
  * w = U^T (b - bh) the network gives w ~ N(mu, Lc Lc^T), so
  * beta* = bh + U^-T (mu + Lc z).  The features never involve beta_g, so one
  * step with exact acceptance probability leaves the beta_g full conditional
- * invariant.  Network: x = (phi - fmean) * fscale; h1 = gelu(x W1 + b1);
+ * invariant.  Network: x = (phi - fmean) * fscale, each element clipped to
+ * [-8, 8] (the range the training inputs are clipped to); h1 = gelu(x W1 + b1);
  * h2 = gelu(h1 W2 + b2); o = h2 W3 + b3 (O = 2L + L(L-1)/2 outputs used);
  *   mu_l = omean_l + oscale_l o_l,
  *   Lc_ll = exp(ls_l), ls_l = log(oscale_l) + o_{L+l},

@@ -10,7 +10,7 @@
  * features (a zero network with omean = 0, oscale = 1 leaves the Laplace
  * proposal):
  *
- *   input   x = (phi - fmean) * fscale                           [F]
+ *   input   x = (phi - fmean) * fscale, clipped to [-8, 8]        [F]
  *   z1 = x W1 + b1,  h1 = gelu(z1)                                [H]
  *   z2 = h1 W2 + b2, h2 = gelu(z2)                                [H]
  *   o  = h2 W3 + b3                                  [O = 2L + L(L-1)/2]
@@ -18,7 +18,8 @@
  *   Lc_ll = exp(ls_l),  ls_l = log(oscale_l) + o_{L+l}
  *   Lc_lj = oscale_l o_{2L + l(l-1)/2 + j}   (j < l; zero above the diagonal)
  *
- * so Lc = diag(oscale) Ls, with Ls the factor in units of oscale.  gelu(z) =
+ * so Lc = diag(oscale) Ls, with Ls the factor in units of oscale.  The clip
+ * keeps the network on the range its training inputs are clipped to.  gelu(z) =
  * z Phi(z) (the erf form).  Weights are row-major with the input index first:
  * z1_j = b1_j + sum_i x_i W1[i][j].
  *
@@ -56,7 +57,7 @@ static void fwd(const or_mlp *m, const double *phi, double *x, double *z1, doubl
                 double *z2, double *h2, double *o)
 {
     const int F = m->F, H = m->H, O = m->O;
-    for (int i = 0; i < F; ++i) x[i] = (phi[i] - m->fmean[i]) * m->fscale[i];
+    for (int i = 0; i < F; ++i) x[i] = fmin(fmax((phi[i] - m->fmean[i]) * m->fscale[i], -8.0), 8.0);
     for (int j = 0; j < H; ++j) {
         double s = m->b1[j];
         for (int i = 0; i < F; ++i) s += x[i] * m->W1[i * H + j];

@@ -2150,7 +2150,8 @@ int fb_mlp_loss_grad(const fb_mlp *w, int32_t L, const float *phi, const float *
     std::vector<float> X((size_t)B * kMlpF);
     for (int64_t b = 0; b < B; ++b)
         for (int k = 0; k < kMlpF; ++k)
-            X[b * kMlpF + k] = (phi[b * 32 + k] - blk[kOffFmean + k]) * blk[kOffFscale + k];
+            X[b * kMlpF + k] = std::min(std::max((phi[b * 32 + k] - blk[kOffFmean + k]) * blk[kOffFscale + k],
+                                                 -kMlpClip), kMlpClip);
     hipError_t e = hipMemcpy(d_master, blk.data(), kMlpParams * sizeof(float), hipMemcpyHostToDevice);
     if (e == hipSuccess) e = hipMemcpy(t.X, X.data(), X.size() * sizeof(float), hipMemcpyHostToDevice);
     if (e == hipSuccess) e = hipMemcpy(t.Tg, target, (size_t)B * L * sizeof(float), hipMemcpyHostToDevice);

@@ -1408,6 +1408,11 @@ __device__ inline float gelu_f(float v)
 // r % 8 of the next layer's B fragment for k-step 2 ot + r / 8 (units in
 // wt_unit order).
 constexpr int kFrStride = kMlpF + 1;   // LDS feature-row stride (floats), odd against bank conflicts
+// Standardised features (and, in training, whitened targets) are clipped to
+// [-kPairClip, kPairClip], in training and in inference alike, so the network
+// is never evaluated on inputs outside the range it was trained on.
+constexpr float kPairClip = kMlpClip;
+__device__ inline float clip_feature(float v) { return fminf(fmaxf(v, -kPairClip), kPairClip); }
 
 // The network's parameters as a workgroup keeps them in LDS: the packed
 // weights, then the feature standardisation and the biases (every per-lane
@@ -1523,7 +1528,7 @@ __device__ inline void mlp_block(const float *row, bool active, const MlpLds &P,
 #pragma unroll
         for (int j = 0; j < 8; ++j) {
             const int k = 16 * ks + 8 * h + j;
-            v8[j] = active ? (row[k] - P.fmean[k]) * P.fscale[k] : 0.0f;
+            v8[j] = active ? clip_feature((row[k] - P.fmean[k]) * P.fscale[k]) : 0.0f;
         }
         x1[ks] = pack_bf16x8(v8);
     }
@@ -1600,7 +1605,7 @@ __global__ __launch_bounds__(512) __attribute__((amdgpu_waves_per_eu(4, 8))) voi
         wave_lds_sync();                  // earlier readers of the rows are done
         if (lane < 32) {
             // feature k standardised as (phi_k - fmean_k) fscale_k, then BF16
-            auto put = [&](int k, float v) { rowb[k] = (__bf16)((v - P.fmean[k]) * P.fscale[k]); };
+            auto put = [&](int k, float v) { rowb[k] = (__bf16)clip_feature((v - P.fmean[k]) * P.fscale[k]); };
 #pragma unroll
             for (int k = 0; k < kMlpF; ++k) put(k, 0.0f);
 #pragma unroll
@@ -1700,8 +1705,6 @@ __global__ void features_kernel(const SegInfo *__restrict__ seg, float *__restri
 // Newton steps from a poor start) gives whitened draws in the tens, whose
 // squared residuals would dominate the loss; the proposal stays exact under
 // the MH correction whatever the network learns from them.
-constexpr float kPairClip = 8.0f;
-
 __global__ void gather_pairs(const float *__restrict__ pairs, int64_t P, int L, const float *__restrict__ master,
                              float *X, float *Tg, int B, uint32_t epoch, uint32_t step, uint32_t k0, uint32_t k1)
 {
@@ -1712,9 +1715,9 @@ __global__ void gather_pairs(const float *__restrict__ pairs, int64_t P, int L, 
     const float *row = pairs + p * kPairStride;
     for (int k = 0; k < kMlpF; ++k) {
         const float v = (row[k] - master[kOffFmean + k]) * master[kOffFscale + k];
-        X[(int64_t)i * kMlpF + k] = fminf(fmaxf(v, -kPairClip), kPairClip);
+        X[(int64_t)i * kMlpF + k] = clip_feature(v);
     }
-    for (int l = 0; l < L; ++l) Tg[(int64_t)i * L + l] = fminf(fmaxf(row[32 + l], -kPairClip), kPairClip);
+    for (int l = 0; l < L; ++l) Tg[(int64_t)i * L + l] = clip_feature(row[32 + l]);
 }
 
 // Column sums and sums of squares (FP64) of a row-major [rows][cols] float array.

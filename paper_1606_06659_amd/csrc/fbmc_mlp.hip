@@ -204,13 +204,15 @@ __global__ void fill_f32(float *p, int64_t n, float v)
     if (t < n) p[t] = v;
 }
 
-// X[b][k] = (phi[b][k] - fmean_k) fscale_k, the network's input standardisation.
+// X[b][k] = (phi[b][k] - fmean_k) fscale_k clipped to [-kMlpClip, kMlpClip], the
+// network's input standardisation.
 __global__ void standardise_rows(const float *phi, const float *master, float *X, int64_t B)
 {
     const int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
     if (t >= B * kMlpF) return;
     const int k = (int)(t % kMlpF);
-    X[t] = (phi[t] - master[kOffFmean + k]) * master[kOffFscale + k];
+    const float v = (phi[t] - master[kOffFmean + k]) * master[kOffFscale + k];
+    X[t] = fminf(fmaxf(v, -kMlpClip), kMlpClip);
 }
 
 // out = mean of v[0..n): one 256-thread workgroup; thread t sums v[t],

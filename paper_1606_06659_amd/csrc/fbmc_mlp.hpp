@@ -11,6 +11,7 @@ typedef float floatx16 __attribute__((ext_vector_type(16)));
 
 constexpr int kMlpF = 32;    // features (zero-padded)
 constexpr int kMlpH = 128;   // hidden width
+constexpr float kMlpClip = 8.0f;   // standardised inputs (and training targets) clipped to +-8
 constexpr int kMlpO = 64;    // outputs: 2L + L(L-1)/2 <= 44 used, padded to two 32-wide tiles
 
 // Outputs of the network for L coefficients: mean, log-diagonal of the factor,
