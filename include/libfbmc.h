@@ -346,6 +346,16 @@ int fb_set_shift_fusion(fb_ctx *c, int32_t fused);
  * fb_get_beta_lanes returns the setting (0 for NULL).  Errors: FB_EINVAL. */
 int fb_set_beta_lanes(fb_ctx *c, int32_t lanes);
 int32_t fb_get_beta_lanes(const fb_ctx *c);
+/* Workgroups of the hyperparameter step (Algorithm 1 steps 3, 4, 6 and 7),
+ * fused into the next eps launch or as its own kernel: on = 1 (the default)
+ * runs 1 + L workgroups per segment, one per chain of draws (nu then tau;
+ * theta_l then sigma_l^2), each reducing only the two partial sums it needs,
+ * so the chains run at once; on = 0 runs the whole step on one workgroup per
+ * segment.  The sums are added in the same order either way, so no choice
+ * changes any draw.  fb_get_hyper_split returns the setting (0 for NULL).
+ * Errors: FB_EINVAL. */
+int fb_set_hyper_split(fb_ctx *c, int32_t on);
+int32_t fb_get_hyper_split(const fb_ctx *c);
 int fb_get_launch(const fb_ctx *c, int32_t *samples_per_wave, int32_t *fuse_hyper);
 /* Single-launch sweep (on = 1): the slice sweep with one lane per gene for
  * beta and no shift step runs as one kernel per sweep instead of two.  One

@@ -22,10 +22,10 @@
 
 namespace fbmc {
 hipError_t launch_eps(int precision, const SegInfo *segs, const int4 *items, int nitems, const SweepArgs &a,
-                      int nhyp, const SweepArgs &ha, int *err, hipStream_t st);
+                      int nhyp_seg, int hsplit, const SweepArgs &ha, int *err, hipStream_t st);
 hipError_t launch_gb(int precision, int mode, int maxL, const SegInfo *segs, const int2 *tiles, int ntiles,
                      const int4 *fb_items, int nfb, const SweepArgs &a, const MlpDev *net, int *err, hipStream_t st);
-hipError_t launch_hyper(const SegInfo *segs, int nseg, const SweepArgs &a, int *err, hipStream_t st);
+hipError_t launch_hyper(const SegInfo *segs, int nseg, int hsplit, const SweepArgs &a, int *err, hipStream_t st);
 hipError_t launch_top(const SegInfo *segs, int nseg, int chains, TopState *top, const TopPriors &P,
                       const SweepArgs &a, hipStream_t st);
 hipError_t launch_shift(int precision, int maxL, const SegInfo *segs, const int2 *tiles, int ntiles,
@@ -151,6 +151,7 @@ struct fb_ctx {
     bool fuse_shift = true;
     // lanes per gene in the slice sweep's beta draws (1: gb_sweep, 2: gb_pair_sweep)
     int beta_lanes = 1;
+    bool hyper_split = true;          // one workgroup per chain of hyperparameter draws
     // three-level form (fb_set_top_level): one TopState per chain
     bool top_on = false;
     TopState *d_top = nullptr;
@@ -724,6 +725,10 @@ static bool tile_sweep(const fb_ctx *c, const SweepMode &md, const SweepArgs &a)
 // sweep ends with its own hyperparameter kernel.  With dev set, every kernel
 // takes sweep i's arguments from dev[i] (graph capture); profiling events are
 // recorded only without it.
+// Workgroups per segment of the hyperparameter step: one per chain of draws
+// (nu then tau; theta_l then sigma_l^2 for each l), or one.
+static int hsplit(const fb_ctx *c) { return c->hyper_split ? 1 + c->maxL : 1; }
+
 static int launch_sweeps(fb_ctx *c, const SweepArgs *args, int64_t n, const SweepMode &md, const SweepArgs *dev)
 {
     const int nseg = (int)c->seg.size();
@@ -761,8 +766,8 @@ static int launch_sweeps(fb_ctx *c, const SweepArgs *args, int64_t n, const Swee
                 HIPCHK(c, hipEventRecord(pe[3], c->st));
             }
         } else {
-            HIPCHK(c, launch_eps(c->prec, c->d_segs, c->d_items, c->nitems, a, pending ? nseg : 0, prev, c->d_err,
-                                 c->st));
+            HIPCHK(c, launch_eps(c->prec, c->d_segs, c->d_items, c->nitems, a, pending ? nseg : 0, hsplit(c), prev,
+                                 c->d_err, c->st));
             if (pe) HIPCHK(c, hipEventRecord(pe[1], c->st));
             if (pe) HIPCHK(c, hipEventRecord(pe[2], c->st));
             if (md.learned && !md.laplace)
@@ -790,11 +795,11 @@ static int launch_sweeps(fb_ctx *c, const SweepArgs *args, int64_t n, const Swee
             pending = true;
         } else {
             if (pe) HIPCHK(c, hipEventRecord(pe[4], c->st));
-            HIPCHK(c, launch_hyper(c->d_segs, nseg, a, c->d_err, c->st));
+            HIPCHK(c, launch_hyper(c->d_segs, nseg, hsplit(c), a, c->d_err, c->st));
             if (pe) HIPCHK(c, hipEventRecord(pe[5], c->st));
         }
     }
-    if (pending) HIPCHK(c, launch_hyper(c->d_segs, nseg, prev, c->d_err, c->st));
+    if (pending) HIPCHK(c, launch_hyper(c->d_segs, nseg, hsplit(c), prev, c->d_err, c->st));
     return FB_OK;
 }
 
@@ -811,6 +816,7 @@ static std::vector<int64_t> graph_signature(const fb_ctx *c, const SweepMode &md
                                 (int64_t)(uintptr_t)c->d_top};
     sig.push_back(c->fuse_shift ? 1 : 0);
     sig.push_back(c->beta_lanes);
+    sig.push_back(c->hyper_split ? 1 : 0);
     sig.push_back(c->tile ? 1 : 0);
     for (int64_t i = 0; i < n; ++i) {
         sig.push_back(gb_mode_of(md, args[i]));
@@ -1660,6 +1666,16 @@ int fb_set_beta_lanes(fb_ctx *c, int32_t lanes)
 }
 
 int32_t fb_get_beta_lanes(const fb_ctx *c) { return c ? c->beta_lanes : 0; }
+
+int fb_set_hyper_split(fb_ctx *c, int32_t on)
+{
+    if (!c) return fail(nullptr, FB_EINVAL, "NULL context");
+    if (on != 0 && on != 1) return fail(c, FB_EINVAL, "on must be 0 or 1");
+    c->hyper_split = on != 0;
+    return FB_OK;
+}
+
+int32_t fb_get_hyper_split(const fb_ctx *c) { return c ? (c->hyper_split ? 1 : 0) : 0; }
 
 int fb_set_tile_sweep(fb_ctx *c, int32_t on)
 {

@@ -4,9 +4,11 @@
 //
 //  eps_sweep<T>      step 1: one lane per (gene, sample); a wavefront draws
 //                    eps_gn for a 64-gene tile and a run of samples.  Its first
-//                    workgroups (one per segment) run the previous sweep's
-//                    hyperparameter step (hyper_block): no eps conditional
-//                    involves a hyperparameter.
+//                    workgroups (1 + L per segment, one per chain of draws:
+//                    nu then tau, theta_l then sigma_l^2 -- hyper_chain -- or
+//                    one per segment, hyper_block) run the previous sweep's
+//                    hyperparameter step: no eps conditional involves a
+//                    hyperparameter.
 //  gb_sweep<T, mode, kML>
 //                    steps 2 and 5: one 128-thread workgroup per tile,
 //                    wavefront 0 draws gamma_g and wavefront 1 beta_g1..beta_gL
@@ -1802,9 +1804,165 @@ hipError_t launch_col_moments(const float *M, int64_t rows, int cols, double *ou
 constexpr int kHyperThreads = 256;
 constexpr int kHyperWaves = kHyperThreads / 64;
 
-// publish > 0 (the single-launch sweep): once the new values are written, the
-// segment's hyp_flag is set to `publish`, the index of the sweep whose gene
-// draws read them.
+// nu, then tau (Algorithm 1 steps 3 and 4) on one wavefront: every lane
+// computes the draws, lane 0 stores.  r0 = sum log gamma_g, r1 = sum 1/gamma_g.
+// Hi holds the state before the step and Ho receives the new values of these
+// two parameters (their widths, moments, reductions and records); the two may
+// be the same object.  Returns whether a draw reached the shrink cap.
+__device__ inline bool draw_nu_tau(const SegInfo &S, const SweepArgs &a, const HyperState &Hi, HyperState &Ho,
+                                   double r0, double r1, double *wd)
+{
+    const double G = (double)S.G;
+    const uint32_t k0 = S.key0, k1 = S.key1;
+    const uint32_t mm = (uint32_t)a.m;
+    const uint32_t chain = (uint32_t)S.chain;
+    const bool exact = (a.mask >> kKindExact) & 1u;
+    const bool w0 = (threadIdx.x & 63) == 0;
+    bool bad = false;
+    DrawRec rec;
+    double nu = Hi.nu, tau = Hi.tau;
+    if ((a.mask >> 3) & 1u) {
+        NuF f{G, tau, r0, r1, S.d};
+        double w = Hi.w_nu, wa = Hi.wa_nu;
+        const double x1 = slice_draw_wave(f, nu, w, k0, k1, draw_counter(0, 3, 0, mm, chain, 0), a.K, a.cap, rec, wd);
+        tune_width<double>(w, wa, nu, x1, a.m, a.burnin, a.tune_start);
+        nu = x1;
+        if (w0) { Ho.nu = x1; Ho.w_nu = w; Ho.wa_nu = wa; }
+        bad |= rec.bad;
+        if (a.dbg && w0) Ho.dbg[0] = make_int4(rec.kl, rec.nl, rec.nr, rec.nc);
+    }
+    if ((a.mask >> 4) & 1u) {
+        // rate of tau's Gamma prior: b, or the top level's b in the three-level form
+        const double rate_b = S.top != nullptr ? S.top->b : S.b;
+        TauF f{S.a + 0.5 * G * nu - 1.0, rate_b + 0.5 * nu * r1};
+        int tries = 0;
+        if (exact) {
+            // exact draw, the same on every lane: tau = X / rate, X ~ Gamma(a + G nu / 2)
+            double v = 0.0;
+            tries = exact_gamma_draw(kKindExact, f.shape_m1 + 1.0, f.rate, false, __builtin_inf(), k0, k1, 0, 1, mm,
+                                     chain, v);
+            if (tries > 0) {
+                tau = v;
+                if (w0) Ho.tau = v;
+                if (a.dbg && w0) Ho.dbg[1] = make_int4(-1, 0, 0, tries);
+            }
+        }
+        if (tries == 0) {
+            double w = Hi.w_tau, wa = Hi.wa_tau;
+            const double x1 = slice_draw_wave(f, tau, w, k0, k1, draw_counter(0, 4, 0, mm, chain, 0), a.K, a.cap,
+                                              rec, wd);
+            tune_width<double>(w, wa, tau, x1, a.m, a.burnin, a.tune_start);
+            tau = x1;
+            if (w0) { Ho.tau = x1; Ho.w_tau = w; Ho.wa_tau = wa; }
+            bad |= rec.bad;
+            if (a.dbg && w0) Ho.dbg[1] = make_int4(rec.kl, rec.nl, rec.nr, rec.nc);
+        }
+    }
+    if (w0) {
+        Ho.red[0] = r0;
+        Ho.red[1] = r1;
+        if (a.m > a.burnin) {
+            double2 m0 = Hi.mom[0], m1 = Hi.mom[1];
+            welford(m0, nu, a.inv_k);
+            welford(m1, tau, a.inv_k);
+            Ho.mom[0] = m0;
+            Ho.mom[1] = m1;
+        }
+        if (a.trace_point >= 0) {
+            float *trow = S.trace + (int64_t)a.trace_point * S.trace_stride;
+            trow[0] = (float)nu;
+            trow[1] = (float)tau;
+        }
+    }
+    return bad;
+}
+
+// theta_l, then sigma_l^2 (Algorithm 1 steps 6 and 7) on one wavefront, as
+// draw_nu_tau.  d1, d2 are the sums of (beta_gl - s) and (beta_gl - s)^2 with
+// the shift s = theta_l before this step.
+__device__ inline bool draw_theta_sig2(const SegInfo &S, const SweepArgs &a, const HyperState &Hi, HyperState &Ho,
+                                       int l, double d1, double d2, double *wd)
+{
+    const int L = S.L;
+    const double G = (double)S.G;
+    const uint32_t k0 = S.key0, k1 = S.key1;
+    const uint32_t mm = (uint32_t)a.m;
+    const uint32_t chain = (uint32_t)S.chain;
+    const bool exact = (a.mask >> kKindExact) & 1u;
+    const bool w0 = (threadIdx.x & 63) == 0;
+    bool bad = false;
+    DrawRec rec;
+    const double s = Hi.theta[l];
+    const double sb = d1 + G * s;
+    const double sig2 = Hi.sig2[l];
+    double th = s;
+    if ((a.mask >> 6) & 1u) {
+        const double cl = S.c[l];
+        const double prec = G / sig2 + 1.0 / (cl * cl);
+        // prior N(0, c_l^2), or N(psi_l, c_l^2) under a top level
+        const double mean = S.top != nullptr ? (sb / sig2 + S.top->psi[l] / (cl * cl)) / prec : (sb / sig2) / prec;
+        const uint4 r = philox4x32_10(draw_counter(0, 6, (uint32_t)l, mm, chain, 0), k0, k1);
+        const double zn = ::sqrt(-2.0 * ::log(u01<double>(r.x))) * ::cos(6.283185307179586 * u01<double>(r.y));
+        th = mean + zn / ::sqrt(prec);
+    }
+    const double dt = th - s;
+    const double Ssq = d2 - 2.0 * dt * d1 + G * dt * dt;
+    double s2new = sig2;
+    double w = Hi.w_sig2[l], wa = Hi.wa_sig2[l];
+    if ((a.mask >> 7) & 1u) {
+        const double sl = S.s[l];
+        int tries = 0;
+        if (exact) {
+            // exact draw: sigma^2 = (S/2) / X, X ~ Gamma((G - 1)/2), kept below s_l^2
+            tries = exact_gamma_draw(kKindExact, 0.5 * (G - 1.0), 0.5 * Ssq, true, sl * sl, k0, k1, 0, 2u + (uint32_t)l,
+                                     mm, chain, s2new);
+            if (tries > 0 && a.dbg && w0) Ho.dbg[2 + l] = make_int4(-1, 0, 0, tries);
+        }
+        if (tries == 0) {
+            Sig2F f{0.5 * (G + 1.0), Ssq, sl * sl};
+            s2new = slice_draw_wave(f, sig2, w, k0, k1, draw_counter(0, 7, (uint32_t)l, mm, chain, 0), a.K, a.cap, rec,
+                                    wd);
+            tune_width<double>(w, wa, sig2, s2new, a.m, a.burnin, a.tune_start);
+            bad |= rec.bad;
+            if (a.dbg && w0) Ho.dbg[2 + l] = make_int4(rec.kl, rec.nl, rec.nr, rec.nc);
+        }
+    }
+    if (w0) {
+        Ho.theta[l] = th;
+        Ho.sig2[l] = s2new;
+        Ho.w_sig2[l] = w;
+        Ho.wa_sig2[l] = wa;
+        Ho.red[2 + 2 * l] = sb;
+        Ho.red[3 + 2 * l] = Ssq;
+        if (a.m > a.burnin) {
+            double2 mt = Hi.mom[2 + l], ms = Hi.mom[2 + L + l];
+            welford(mt, th, a.inv_k);
+            welford(ms, s2new, a.inv_k);
+            Ho.mom[2 + l] = mt;
+            Ho.mom[2 + L + l] = ms;
+        }
+        if (a.trace_point >= 0) {
+            float *trow = S.trace + (int64_t)a.trace_point * S.trace_stride;
+            trow[2 + l] = (float)th;
+            trow[2 + L + l] = (float)s2new;
+        }
+    }
+    return bad;
+}
+
+// Partial columns the reductions add: the tiles, then (learned step) the
+// fallback groups, which hold beta partials of their own unless the shift step
+// takes every gene's partials in its tile column.
+__device__ inline int64_t partial_columns(const SegInfo &S, const SweepArgs &a)
+{
+    return S.ntiles + ((a.learned && !((a.mask >> kKindShift) & 1u)) ? S.nfbw : 0);
+}
+
+// The whole hyperparameter step of one segment on one 256-thread workgroup:
+// the reductions, then (nu, then tau) on wavefront 0 and (theta_l, then
+// sigma_l^2) on wavefront 1 + (l mod 3).  The single-launch sweep runs this
+// form; publish > 0 sets the segment's hyp_flag to `publish`, the index of the
+// sweep whose gene draws read the new values, once they are written.
 __device__ inline void hyper_block(const SegInfo &S, const SweepArgs &a, int *err, int64_t publish = 0)
 {
     const int L = S.L;
@@ -1823,15 +1981,9 @@ __device__ inline void hyper_block(const SegInfo &S, const SweepArgs &a, int *er
     const double *hg = reinterpret_cast<const double *>(S.hyp);
     for (int i = tid; i < kWords; i += kHyperThreads) hs[i] = hg[i];
 
-    // thread t sums tiles t, t + 256, ... in order; a butterfly inside each
-    // wavefront; the wavefronts in order.  The partials are part-major, so a
-    // pass reads consecutive tiles; four parts per pass keep few loads in
-    // flight (this code also runs inside the eps kernel, whose register budget
-    // is set for the eps wavefronts) and few round trips.
-    // columns: the tiles, then (learned step) the fallback groups
-    // fallback groups hold beta partials of their own unless the shift step
-    // takes every gene's partials in its tile column
-    const int64_t nt = S.ntiles + ((a.learned && !((a.mask >> kKindShift) & 1u)) ? S.nfbw : 0);
+    // thread t sums columns t, t + 256, ... in order; a butterfly inside each
+    // wavefront; the wavefronts in order (hyper_chain adds in the same order).
+    const int64_t nt = partial_columns(S, a);
     for (int j0 = 0; j0 < nparts; j0 += 4) {
         double acc[4] = {0.0, 0.0, 0.0, 0.0};
 #pragma unroll 2
@@ -1856,125 +2008,14 @@ __device__ inline void hyper_block(const SegInfo &S, const SweepArgs &a, int *er
     }
     __syncthreads();
 
-    const double G = (double)S.G;
-    const uint32_t k0 = S.key0, k1 = S.key1;
-    const uint32_t mm = (uint32_t)a.m;
-    const uint32_t chain = (uint32_t)S.chain;
-    const bool sampling = a.m > a.burnin;
-    const bool exact = (a.mask >> kKindExact) & 1u;
-    const bool w0 = lane == 0;
-    float *trow = a.trace_point >= 0 ? S.trace + (int64_t)a.trace_point * S.trace_stride : nullptr;
     double *wd = &words[wave][0];
-    int bad = 0;
-    DrawRec rec;
     if (wave == 0) {
-        double nu = H.nu, tau = H.tau;
-        // step 3: nu
-        if ((a.mask >> 3) & 1u) {
-            NuF f{G, tau, red[0], red[1], S.d};
-            double w = H.w_nu, wa = H.wa_nu;
-            const double x1 = slice_draw_wave(f, nu, w, k0, k1, draw_counter(0, 3, 0, mm, chain, 0), a.K, a.cap,
-                                              rec, wd);
-            tune_width<double>(w, wa, nu, x1, a.m, a.burnin, a.tune_start);
-            nu = x1;
-            if (w0) { H.nu = x1; H.w_nu = w; H.wa_nu = wa; }
-            bad |= rec.bad;
-            if (a.dbg && w0) H.dbg[0] = make_int4(rec.kl, rec.nl, rec.nr, rec.nc);
-        }
-        // step 4: tau
-        if ((a.mask >> 4) & 1u) {
-            // rate of tau's Gamma prior: b, or the top level's b in the three-level form
-            const double rate_b = S.top != nullptr ? S.top->b : S.b;
-            TauF f{S.a + 0.5 * G * nu - 1.0, rate_b + 0.5 * nu * red[1]};
-            int tries = 0;
-            if (exact) {
-                // exact draw, the same on every lane: tau = X / rate, X ~ Gamma(a + G nu / 2)
-                double v = 0.0;
-                tries = exact_gamma_draw(kKindExact, f.shape_m1 + 1.0, f.rate, false, __builtin_inf(), k0, k1, 0, 1, mm, chain,
-                                         v);
-                if (tries > 0) {
-                    tau = v;
-                    if (w0) H.tau = v;
-                    if (a.dbg && w0) H.dbg[1] = make_int4(-1, 0, 0, tries);
-                }
-            }
-            if (tries == 0) {
-                double w = H.w_tau, wa = H.wa_tau;
-                const double x1 = slice_draw_wave(f, tau, w, k0, k1, draw_counter(0, 4, 0, mm, chain, 0), a.K,
-                                                  a.cap, rec, wd);
-                tune_width<double>(w, wa, tau, x1, a.m, a.burnin, a.tune_start);
-                tau = x1;
-                if (w0) { H.tau = x1; H.w_tau = w; H.wa_tau = wa; }
-                bad |= rec.bad;
-                if (a.dbg && w0) H.dbg[1] = make_int4(rec.kl, rec.nl, rec.nr, rec.nc);
-            }
-        }
-        if (w0) {
-            H.red[0] = red[0];
-            H.red[1] = red[1];
-            if (sampling) {
-                welford(H.mom[0], nu, a.inv_k);
-                welford(H.mom[1], tau, a.inv_k);
-            }
-            if (trow) { trow[0] = (float)nu; trow[1] = (float)tau; }
-        }
+        if (draw_nu_tau(S, a, H, H, red[0], red[1], wd) && lane == 0) report_cap(err, 3, S, -1, a.m, 0);
     } else {
-        // steps 6 and 7: theta_l then sigma_l^2.  The partials are sums of
-        // (beta - s) and (beta - s)^2 with the shift s = theta_l before this step.
-        for (int l = wave - 1; l < L; l += kHyperWaves - 1) {
-            const double s = H.theta[l];
-            const double d1 = red[2 + 2 * l], d2 = red[3 + 2 * l];
-            const double sb = d1 + G * s;
-            const double sig2 = H.sig2[l];
-            double th = s;
-            if ((a.mask >> 6) & 1u) {
-                const double cl = S.c[l];
-                const double prec = G / sig2 + 1.0 / (cl * cl);
-                // prior N(0, c_l^2), or N(psi_l, c_l^2) under a top level
-                const double mean = S.top != nullptr ? (sb / sig2 + S.top->psi[l] / (cl * cl)) / prec
-                                                     : (sb / sig2) / prec;
-                const uint4 r = philox4x32_10(draw_counter(0, 6, (uint32_t)l, mm, chain, 0), k0, k1);
-                const double zn = ::sqrt(-2.0 * ::log(u01<double>(r.x))) * ::cos(6.283185307179586 * u01<double>(r.y));
-                th = mean + zn / ::sqrt(prec);
-            }
-            const double dt = th - s;
-            const double Ssq = d2 - 2.0 * dt * d1 + G * dt * dt;
-            double s2new = sig2;
-            double w = H.w_sig2[l], wa = H.wa_sig2[l];
-            if ((a.mask >> 7) & 1u) {
-                const double sl = S.s[l];
-                int tries = 0;
-                if (exact) {
-                    // exact draw: sigma^2 = (S/2) / X, X ~ Gamma((G - 1)/2), kept below s_l^2
-                    tries = exact_gamma_draw(kKindExact, 0.5 * (G - 1.0), 0.5 * Ssq, true, sl * sl, k0, k1, 0, 2u + (uint32_t)l,
-                                             mm, chain, s2new);
-                    if (tries > 0 && a.dbg && w0) H.dbg[2 + l] = make_int4(-1, 0, 0, tries);
-                }
-                if (tries == 0) {
-                    Sig2F f{0.5 * (G + 1.0), Ssq, sl * sl};
-                    s2new = slice_draw_wave(f, sig2, w, k0, k1, draw_counter(0, 7, (uint32_t)l, mm, chain, 0),
-                                            a.K, a.cap, rec, wd);
-                    tune_width<double>(w, wa, sig2, s2new, a.m, a.burnin, a.tune_start);
-                    bad |= rec.bad;
-                    if (a.dbg && w0) H.dbg[2 + l] = make_int4(rec.kl, rec.nl, rec.nr, rec.nc);
-                }
-            }
-            if (w0) {
-                H.theta[l] = th;
-                H.sig2[l] = s2new;
-                H.w_sig2[l] = w;
-                H.wa_sig2[l] = wa;
-                H.red[2 + 2 * l] = sb;
-                H.red[3 + 2 * l] = Ssq;
-                if (sampling) {
-                    welford(H.mom[2 + l], th, a.inv_k);
-                    welford(H.mom[2 + L + l], s2new, a.inv_k);
-                }
-                if (trow) { trow[2 + l] = (float)th; trow[2 + L + l] = (float)s2new; }
-            }
-        }
+        for (int l = wave - 1; l < L; l += kHyperWaves - 1)
+            if (draw_theta_sig2(S, a, H, H, l, red[2 + 2 * l], red[3 + 2 * l], wd) && lane == 0)
+                report_cap(err, 3, S, -1, a.m, 1 + l);
     }
-    if (bad && w0) report_cap(err, 3, S, -1, a.m, wave);
     __syncthreads();
     double *hw = reinterpret_cast<double *>(S.hyp);
     for (int i = tid; i < kWords; i += kHyperThreads) hw[i] = hs[i];
@@ -1984,6 +2025,66 @@ __device__ inline void hyper_block(const SegInfo &S, const SweepArgs &a, int *er
         __syncthreads();
         if (tid == 0) __hip_atomic_store(S.hyp_flag, publish, __ATOMIC_RELEASE, __HIP_MEMORY_SCOPE_AGENT);
     }
+}
+
+// One chain of the hyperparameter step on its own 256-thread workgroup:
+// c = 0 draws nu then tau, c = 1 + l draws theta_l then sigma_l^2 (c > L: no
+// work).  The chains are conditionally independent of one another, so 1 + L
+// workgroups per segment run them at once, each reducing only the two partial
+// sums it needs; its loads of all columns of a thread are issued together.
+// The sums are added in hyper_block's order, so the draws are the same bits.
+// The workgroup stages the state in LDS and writes back only its chain's
+// fields to the segment's HyperState.
+__device__ inline void hyper_chain(const SegInfo &S, const SweepArgs &a, int *err, int c)
+{
+    if (c > S.L) return;
+    const int tid = (int)threadIdx.x;
+    const int lane = tid & 63, wave = tid >> 6;
+    __shared__ double part[kHyperWaves][2];
+    __shared__ double words[20];
+    __shared__ HyperState H;
+    constexpr int kWords = (int)(sizeof(HyperState) / sizeof(double));
+    double *hs = reinterpret_cast<double *>(&H);
+    const double *hg = reinterpret_cast<const double *>(S.hyp);
+    for (int i = tid; i < kWords; i += kHyperThreads) hs[i] = hg[i];
+
+    const int64_t nt = partial_columns(S, a);
+    const double *p0 = S.partials + (int64_t)(2 * c) * S.pstride;
+    const double *p1 = p0 + S.pstride;
+    constexpr int kCols = 4;     // columns per thread per round trip
+    double acc0 = 0.0, acc1 = 0.0;
+    for (int64_t t0 = tid; t0 < nt; t0 += kCols * kHyperThreads) {
+        double v0[kCols], v1[kCols];
+#pragma unroll
+        for (int q = 0; q < kCols; ++q) {
+            const int64_t t = t0 + (int64_t)q * kHyperThreads;
+            v0[q] = t < nt ? p0[t] : 0.0;
+            v1[q] = t < nt ? p1[t] : 0.0;
+        }
+        // adding 0.0 past the last column leaves the sum's bits unchanged (it
+        // starts at +0.0, so it is never -0.0)
+#pragma unroll
+        for (int q = 0; q < kCols; ++q) {
+            acc0 += v0[q];
+            acc1 += v1[q];
+        }
+    }
+    const double w0s = wave_sum(acc0), w1s = wave_sum(acc1);
+    if (lane == 0) {
+        part[wave][0] = w0s;
+        part[wave][1] = w1s;
+    }
+    __syncthreads();
+    if (wave != 0) return;
+    double r0 = 0.0, r1 = 0.0;
+    for (int w = 0; w < kHyperWaves; ++w) {
+        r0 += part[w][0];
+        r1 += part[w][1];
+    }
+    HyperState &Ho = *S.hyp;
+    const bool bad = c == 0 ? draw_nu_tau(S, a, H, Ho, r0, r1, words)
+                            : draw_theta_sig2(S, a, H, Ho, c - 1, r0, r1, words);
+    if (bad && lane == 0) report_cap(err, 3, S, -1, a.m, c);
 }
 
 // ---------------------------------------------------------------------------
@@ -2081,23 +2182,32 @@ hipError_t launch_top(const SegInfo *segs, int nseg, int chains, TopState *top, 
     return hipGetLastError();
 }
 
-__global__ __launch_bounds__(kHyperThreads) void hyper_sweep(const SegInfo *__restrict__ segs, SweepArgs a0, int *err)
+// The hyperparameter step as a kernel of its own: hsplit workgroups per
+// segment, one per chain of draws (hyper_chain), or with hsplit = 1 one per
+// segment (hyper_block).
+__global__ __launch_bounds__(kHyperThreads) void hyper_sweep(const SegInfo *__restrict__ segs, SweepArgs a0, int hsplit,
+                                                             int *err)
 {
-    hyper_block(segs[blockIdx.x], resolve_args(a0), err);
+    const int b = (int)blockIdx.x;
+    if (hsplit == 1) hyper_block(segs[b], resolve_args(a0), err);
+    else hyper_chain(segs[b / hsplit], resolve_args(a0), err, b % hsplit);
 }
 
 // Step 1 of sweep a.m over the work items; when nhyp > 0 the first nhyp
-// workgroups run the hyperparameter step of the previous sweep ha.m (one per
-// segment) alongside, since no eps conditional involves a hyperparameter.
+// workgroups run the hyperparameter step of the previous sweep ha.m alongside
+// (hsplit per segment as in hyper_sweep), since no eps conditional involves a
+// hyperparameter.
 // The register budget is set for the eps wavefronts (7 per SIMD); the FP64
 // hyperparameter code, which runs on one workgroup per segment, spills.
 template <typename T>
 __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(7, 8))) void eps_sweep(
     const SegInfo *__restrict__ segs, const int4 *__restrict__ items, int nitems, SweepArgs a0, int nhyp,
-    SweepArgs ha, int *err)
+    int hsplit, SweepArgs ha, int *err)
 {
     if ((int)blockIdx.x < nhyp) {
-        hyper_block(segs[blockIdx.x], resolve_args(ha), err);
+        const int b = (int)blockIdx.x;
+        if (hsplit == 1) hyper_block(segs[b], resolve_args(ha), err);
+        else hyper_chain(segs[b / hsplit], resolve_args(ha), err, b % hsplit);
         return;
     }
     const SweepArgs a = resolve_args(a0);
@@ -2187,14 +2297,17 @@ __global__ void philox_kernel(const uint4 *ctr, const uint2 *key, uint4 *out, in
 // Launchers
 // ---------------------------------------------------------------------------
 hipError_t launch_eps(int precision, const SegInfo *segs, const int4 *items, int nitems, const SweepArgs &a,
-                      int nhyp, const SweepArgs &ha, int *err, hipStream_t st)
+                      int nhyp_seg, int hsplit, const SweepArgs &ha, int *err, hipStream_t st)
 {
+    const int nhyp = nhyp_seg * hsplit;
     const int blocks = nhyp + (nitems + 3) / 4;
     if (blocks == 0) return hipSuccess;
     if (precision == 0)
-        hipLaunchKernelGGL((eps_sweep<double>), dim3(blocks), dim3(256), 0, st, segs, items, nitems, a, nhyp, ha, err);
+        hipLaunchKernelGGL((eps_sweep<double>), dim3(blocks), dim3(256), 0, st, segs, items, nitems, a, nhyp, hsplit,
+                           ha, err);
     else
-        hipLaunchKernelGGL((eps_sweep<float>), dim3(blocks), dim3(256), 0, st, segs, items, nitems, a, nhyp, ha, err);
+        hipLaunchKernelGGL((eps_sweep<float>), dim3(blocks), dim3(256), 0, st, segs, items, nitems, a, nhyp, hsplit,
+                           ha, err);
     return hipGetLastError();
 }
 
@@ -2333,9 +2446,9 @@ hipError_t launch_shift(int precision, int maxL, const SegInfo *segs, const int2
     return hipGetLastError();
 }
 
-hipError_t launch_hyper(const SegInfo *segs, int nseg, const SweepArgs &a, int *err, hipStream_t st)
+hipError_t launch_hyper(const SegInfo *segs, int nseg, int hsplit, const SweepArgs &a, int *err, hipStream_t st)
 {
-    hipLaunchKernelGGL(hyper_sweep, dim3(nseg), dim3(kHyperThreads), 0, st, segs, a, err);
+    hipLaunchKernelGGL(hyper_sweep, dim3(nseg * hsplit), dim3(kHyperThreads), 0, st, segs, a, hsplit, err);
     return hipGetLastError();
 }
 

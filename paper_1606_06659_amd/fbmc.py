@@ -77,7 +77,7 @@ EXPORTS = [
     "fb_num_segments", "fb_segment_dims", "fb_get_state", "fb_set_state", "fb_summaries",
     "fb_trace_genes", "fb_trace", "fb_trace_reset", "fb_debug_counts", "fb_reductions",
     "fb_philox", "fb_last_sweep_time", "fb_profile", "fb_kernel_times", "fb_set_graph", "fb_get_graph",
-    "fb_set_contrasts", "fb_event_counts", "fb_set_top_level", "fb_get_top", "fb_set_top", "fb_set_shift_fusion", "fb_set_beta_lanes", "fb_get_beta_lanes",
+    "fb_set_contrasts", "fb_event_counts", "fb_set_top_level", "fb_get_top", "fb_set_top", "fb_set_shift_fusion", "fb_set_beta_lanes", "fb_get_beta_lanes", "fb_set_hyper_split", "fb_get_hyper_split",
     "fb_set_tile_sweep", "fb_get_tile_sweep",
     "fb_set_launch",
     "fb_get_launch", "fb_autotune", "fb_last_error",
@@ -136,6 +136,9 @@ def load() -> C.CDLL:
     L.fb_set_beta_lanes.argtypes = [vp, i32]
     L.fb_get_beta_lanes.argtypes = [vp]
     L.fb_get_beta_lanes.restype = i32
+    L.fb_set_hyper_split.argtypes = [vp, i32]
+    L.fb_get_hyper_split.argtypes = [vp]
+    L.fb_get_hyper_split.restype = i32
     L.fb_set_tile_sweep.argtypes = [vp, i32]
     L.fb_get_tile_sweep.argtypes = [vp]
     L.fb_get_tile_sweep.restype = i32
@@ -421,6 +424,15 @@ def fb_set_beta_lanes(ctx, lanes: int):
 
 def fb_get_beta_lanes(ctx) -> int:
     return int(load().fb_get_beta_lanes(ctx))
+
+
+def fb_set_hyper_split(ctx, on: int):
+    """One workgroup per chain of hyperparameter draws (1) or per segment (0)."""
+    _check(load().fb_set_hyper_split(ctx, int(on)), ctx)
+
+
+def fb_get_hyper_split(ctx) -> int:
+    return int(load().fb_get_hyper_split(ctx))
 
 
 def fb_set_graph(ctx, sweeps: int):

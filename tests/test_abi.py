@@ -68,6 +68,8 @@ def test_new_entry_points_reject_a_null_context():
     lib = fbmc.load()
     assert lib.fb_set_beta_lanes(None, 2) == fbmc.FB_EINVAL
     assert lib.fb_get_beta_lanes(None) == 0
+    assert lib.fb_set_hyper_split(None, 1) == fbmc.FB_EINVAL
+    assert lib.fb_get_hyper_split(None) == 0
     assert lib.fb_set_shift_fusion(None, 1) == fbmc.FB_EINVAL
     assert lib.fb_set_top_level(None, None) == fbmc.FB_EINVAL
     assert lib.fb_set_top(None, 0, C.c_double(1.0), None) == fbmc.FB_EINVAL

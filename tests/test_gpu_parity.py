@@ -306,27 +306,33 @@ def test_determinism_and_resume():
 
 
 # (samples per eps wavefront, hyperparameter step fused, single-launch sweep)
-SHAPES = [(1, 1, 0), (1, 0, 0), (3, 1, 0), (16, 0, 0), (16, 1, 0), (4, 1, 1), (4, 0, 1)]
+# (samples per eps wavefront, fused hyperparameter step, single-launch sweep,
+# one workgroup per chain of hyperparameter draws)
+SHAPES = [(1, 1, 0, 1), (1, 0, 0, 1), (3, 1, 0, 1), (16, 0, 0, 1), (16, 1, 0, 1), (4, 1, 1, 1), (4, 0, 1, 1),
+          (4, 1, 0, 0), (4, 0, 0, 0)]
 
 
 @pytest.mark.parametrize("precision,shift", [(0, 0), (1, 0), (1, 1)])
 def test_launch_shapes_give_identical_chains(precision, shift):
     """Every draw is a function of its counter only: the samples per eps
-    wavefront, fusing the hyperparameter step into the next eps launch and
-    the single-launch sweep change no bit of the state, the moments or the
+    wavefront, fusing the hyperparameter step into the next eps launch, its
+    workgroups (one per chain of draws or one per segment) and the
+    single-launch sweep change no bit of the state, the moments or the
     trace."""
     F = require_gpu()
     ds = datagen.paper_design_16(G=1500, seed=5)
     outs = []
-    for spw, fuse, tile in SHAPES:
-        say("shape", spw, fuse, tile, "precision", precision)
+    for spw, fuse, tile, split in SHAPES:
+        say("shape", spw, fuse, tile, split, "precision", precision)
         opts = F.fb_default_options(burnin=15, tune_start=3, precision=precision, jitter=0, thin=1,
                                     trace_genes=10, trace_capacity=40, debug_counts=1,
                                     update_mask=F.FB_UPDATE_ALL | (F.FB_SHIFT if shift else 0))
         g = F.fb_create(ds.y, ds.X, ds.h, seed=6, options=opts)
         F.fb_set_launch(g, spw, fuse)
         F.fb_set_tile_sweep(g, tile)
+        F.fb_set_hyper_split(g, split)
         assert F.fb_get_launch(g) == (spw, fuse) and F.fb_get_tile_sweep(g) == tile
+        assert F.fb_get_hyper_split(g) == split
         F.fb_sweep(g, 7)
         F.fb_sweep(g, 1)
         F.fb_sweep(g, 22)
@@ -337,7 +343,7 @@ def test_launch_shapes_give_identical_chains(precision, shift):
         outs.append((st, summ, tr, cnt))
         F.fb_destroy(g)
     ref = outs[0]
-    for (spw, fuse, _), (st, summ, tr, cnt) in zip(SHAPES[1:], outs[1:]):
+    for (spw, fuse, _, _), (st, summ, tr, cnt) in zip(SHAPES[1:], outs[1:]):
         for k in STATE_KEYS:
             assert np.array_equal(st[k], ref[0][k]), (spw, fuse, k)
         for k in summ:
@@ -369,12 +375,14 @@ def test_autotune_leaves_the_chain_unchanged():
     assert np.array_equal(ta, tb)
 
 
-@pytest.mark.parametrize("precision,shift,tile", [(0, 0, 0), (1, 0, 0), (1, 1, 0), (0, 0, 1), (1, 0, 1)])
-def test_batched_segments_match_single_runs(precision, shift, tile):
+@pytest.mark.parametrize("precision,shift,tile,split", [(0, 0, 0, 1), (1, 0, 0, 1), (1, 1, 0, 1), (0, 0, 1, 1),
+                                                       (1, 0, 1, 1), (1, 0, 0, 0), (0, 1, 0, 0)])
+def test_batched_segments_match_single_runs(precision, shift, tile, split):
     """Datasets of uneven G, N and L, each with two chains, in one context: every
     (dataset, chain) segment is bit-identical to the same dataset run alone
     (its draws use the dataset's seed and the chain index only; its
-    reductions cover its own tiles only)."""
+    reductions cover its own tiles only).  The single runs take the default
+    hyperparameter workgroups; the batch takes `split`."""
     F = require_gpu()
     meta = [(300, 4), (1000, 16), (77, 8), (2500, 4), (64, 16)]
     dss = [datagen.batched_dataset(k + 1, G, N) for k, (G, N) in enumerate(meta)]
@@ -386,6 +394,7 @@ def test_batched_segments_match_single_runs(precision, shift, tile):
     assert F.fb_num_segments(b) == 2 * len(dss)
     F.fb_set_launch(b, 2, 1)
     F.fb_set_tile_sweep(b, tile)
+    F.fb_set_hyper_split(b, split)
     F.fb_sweep(b, 25)
     for k, d in enumerate(dss):
         s = F.fb_create(d.y, d.X, d.h, seed=100 + k, options=F.fb_default_options(**opts))
