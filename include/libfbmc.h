@@ -492,9 +492,10 @@ int fb_mlp_loss_grad(const fb_mlp *w, int32_t L, const float *phi, const float *
  * memory: code under HIP graph capture, tight training or serving loops,
  * harnesses that forbid hipMalloc.  The result is that of fb_mlp_loss_grad,
  * here on device buffers the caller owns:
- *   master  [FB_MLP_PARAMS] floats, the fb_mlp blocks one after another in
- *           the order fmean[32], fscale[32], W1[32][128], b1[128],
- *           W2[128][128], b2[128], W3[128][64], b3[64], omean[8], oscale[8];
+ *   master  [FB_MLP_PARAMS] floats, 16-byte aligned, the fb_mlp blocks one
+ *           after another in the order fmean[32], fscale[32], W1[32][128],
+ *           b1[128], W2[128][128], b2[128], W3[128][64], b3[64], omean[8],
+ *           oscale[8];
  *   phi     [B][32] raw features;  target [B][L] whitened targets;
  *   loss    one float, the mean loss;  grad [FB_MLP_PARAMS], same layout
  *           (zero for fmean, fscale, omean, oscale).
@@ -509,9 +510,9 @@ int fb_mlp_loss_grad(const fb_mlp *w, int32_t L, const float *phi, const float *
  * array, so calls that may overlap on one GPU (other streams, other threads)
  * race; calls in order on one stream do not.  The first call on each device
  * looks up the array's device address (do it once outside graph capture).
- * Errors: FB_EINVAL (null pointer, L or B out of range, B above
- * FB_NOALLOC_MAX_ROWS), FB_EDEVICE (a HIP call failed); message in
- * fb_last_error(NULL). */
+ * Errors: FB_EINVAL (null pointer, master not 16-byte aligned, L or B out of
+ * range, B above FB_NOALLOC_MAX_ROWS), FB_EDEVICE (a HIP call failed);
+ * message in fb_last_error(NULL). */
 #define FB_MLP_PARAMS        29072
 #define FB_NOALLOC_MAX_ROWS  2048
 int fb_mlp_loss_grad_noalloc(const float *master, int32_t L, const float *phi, const float *target, int64_t B,

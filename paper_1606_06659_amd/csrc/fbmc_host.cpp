@@ -38,7 +38,7 @@ hipError_t launch_mlp_sweep(int precision, const SegInfo *segs, const int2 *tile
                             hipStream_t st);
 hipError_t launch_philox(const uint4 *ctr, const uint2 *key, uint4 *out, int64_t n, hipStream_t st);
 hipError_t launch_tile(int precision, int maxL, int maxN, const SegInfo *segs, const int2 *tiles, int ntiles,
-                       const SweepArgs &a, int nhyp, const SweepArgs &ha, int *err, hipStream_t st);
+                       const SweepArgs &a, int nhyp_seg, int hsplit, const SweepArgs &ha, int *err, hipStream_t st);
 hipError_t launch_mlp_infer_raw(const float *phi, int64_t B, int L, const MlpDev *net, float *mu, float *ls,
                                 float *off, hipStream_t st);
 hipError_t launch_features(int precision, const SegInfo *seg, int64_t G, float *out, hipStream_t st);
@@ -568,7 +568,7 @@ int build_context(fb_ctx *c, const fb_dataset *dsv, int nds)
             }
             if ((rc = dalloc(c, (void **)&S.d_hyp, sizeof(HyperState)))) return rc;
             I.hyp = S.d_hyp;
-            if ((rc = dalloc(c, (void **)&I.hyp_flag, sizeof(int64_t)))) return rc;
+            if ((rc = dalloc(c, (void **)&I.hyp_flag, kHypFlags * sizeof(int64_t)))) return rc;
             if (c->opt.debug_counts) {
                 if ((rc = dalloc(c, (void **)&I.dbg_eps, N * Gp * sizeof(int4)))) return rc;
                 if ((rc = dalloc(c, (void **)&I.dbg_gam, Gp * sizeof(int4)))) return rc;
@@ -759,7 +759,7 @@ static int launch_sweeps(fb_ctx *c, const SweepArgs *args, int64_t n, const Swee
         if (tile_sweep(c, md, args[i])) {
             // the whole sweep in one launch; its time is reported as the eps kernel's
             HIPCHK(c, launch_tile(c->prec, c->maxL, c->maxN, c->d_segs, c->d_tiles, c->ntiles, a, pending ? nseg : 0,
-                                  prev, c->d_err, c->st));
+                                  hsplit(c), prev, c->d_err, c->st));
             if (pe) {
                 HIPCHK(c, hipEventRecord(pe[1], c->st));
                 HIPCHK(c, hipEventRecord(pe[2], c->st));
@@ -1297,7 +1297,7 @@ int fb_set_state(fb_ctx *c, int32_t seg, const fb_state *s)
     HIPCHK(c, hipMemcpy(S.d_hyp, &H, sizeof(H), hipMemcpyHostToDevice));
     c->m = s->m;
     // the sweep index may go back: clear what the single-launch sweep waits on
-    for (auto &Sg : c->seg) HIPCHK(c, hipMemset(Sg.info.hyp_flag, 0, sizeof(int64_t)));
+    for (auto &Sg : c->seg) HIPCHK(c, hipMemset(Sg.info.hyp_flag, 0, kHypFlags * sizeof(int64_t)));
     return FB_OK;
 }
 
@@ -1720,7 +1720,7 @@ void sweep_buffers(fb_ctx *c, std::vector<std::pair<void *, size_t>> &out)
         out.push_back({(void *)I.mom_beta, L * Gp * sizeof(double2)});
         out.push_back({(void *)I.partials, (size_t)I.pstride * kMaxParts * sizeof(double)});
         out.push_back({(void *)S.d_hyp, sizeof(HyperState)});
-        out.push_back({(void *)I.hyp_flag, sizeof(int64_t)});
+        out.push_back({(void *)I.hyp_flag, kHypFlags * sizeof(int64_t)});
         if (I.dbg_eps) {
             out.push_back({(void *)I.dbg_eps, N * Gp * sizeof(int4)});
             out.push_back({(void *)I.dbg_gam, Gp * sizeof(int4)});

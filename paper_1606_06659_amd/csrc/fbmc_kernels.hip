@@ -1960,9 +1960,9 @@ __device__ inline int64_t partial_columns(const SegInfo &S, const SweepArgs &a)
 
 // The whole hyperparameter step of one segment on one 256-thread workgroup:
 // the reductions, then (nu, then tau) on wavefront 0 and (theta_l, then
-// sigma_l^2) on wavefront 1 + (l mod 3).  The single-launch sweep runs this
-// form; publish > 0 sets the segment's hyp_flag to `publish`, the index of the
-// sweep whose gene draws read the new values, once they are written.
+// sigma_l^2) on wavefront 1 + (l mod 3).  publish > 0 (the single-launch
+// sweep) sets the segment's flags of chains 0..L to `publish`, the index of
+// the sweep whose gene draws read the new values, once they are written.
 __device__ inline void hyper_block(const SegInfo &S, const SweepArgs &a, int *err, int64_t publish = 0)
 {
     const int L = S.L;
@@ -2023,7 +2023,7 @@ __device__ inline void hyper_block(const SegInfo &S, const SweepArgs &a, int *er
         // every wavefront's stores visible device-wide, then the flag
         __builtin_amdgcn_fence(__ATOMIC_RELEASE, "agent");
         __syncthreads();
-        if (tid == 0) __hip_atomic_store(S.hyp_flag, publish, __ATOMIC_RELEASE, __HIP_MEMORY_SCOPE_AGENT);
+        if (tid <= L) __hip_atomic_store(&S.hyp_flag[tid], publish, __ATOMIC_RELEASE, __HIP_MEMORY_SCOPE_AGENT);
     }
 }
 
@@ -2034,8 +2034,9 @@ __device__ inline void hyper_block(const SegInfo &S, const SweepArgs &a, int *er
 // sums it needs; its loads of all columns of a thread are issued together.
 // The sums are added in hyper_block's order, so the draws are the same bits.
 // The workgroup stages the state in LDS and writes back only its chain's
-// fields to the segment's HyperState.
-__device__ inline void hyper_chain(const SegInfo &S, const SweepArgs &a, int *err, int c)
+// fields to the segment's HyperState.  publish > 0 (the single-launch sweep)
+// then sets the chain's flag to `publish`.
+__device__ inline void hyper_chain(const SegInfo &S, const SweepArgs &a, int *err, int c, int64_t publish = 0)
 {
     if (c > S.L) return;
     const int tid = (int)threadIdx.x;
@@ -2085,6 +2086,11 @@ __device__ inline void hyper_chain(const SegInfo &S, const SweepArgs &a, int *er
     const bool bad = c == 0 ? draw_nu_tau(S, a, H, Ho, r0, r1, words)
                             : draw_theta_sig2(S, a, H, Ho, c - 1, r0, r1, words);
     if (bad && lane == 0) report_cap(err, 3, S, -1, a.m, c);
+    if (publish > 0) {
+        // lane 0's stores of the new values visible device-wide, then the flag
+        __builtin_amdgcn_fence(__ATOMIC_RELEASE, "agent");
+        if (lane == 0) __hip_atomic_store(&S.hyp_flag[c], publish, __ATOMIC_RELEASE, __HIP_MEMORY_SCOPE_AGENT);
+    }
 }
 
 // ---------------------------------------------------------------------------
@@ -2231,36 +2237,44 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(7, 8))) voi
 // operations in the same order as eps_sweep followed by gb_sweep, so the
 // chain is the same bit for bit.  A tile's gamma and beta draws need the
 // previous sweep's hyperparameters; its eps draws do not, so the step runs
-// in the launch's first workgroups (one per segment) while the tiles draw eps,
-// and publishes the sweep index on the segment's flag, which wavefronts 0 and
-// 1 wait for (bounded) after the barrier.  The hyperparameter workgroups have
-// the lowest indices and wait for nothing, so they are dispatched and finish
-// whatever the other workgroups do.
+// in the launch's first workgroups (per segment one per chain of draws, or
+// one) while the tiles draw eps, and publishes the sweep index on the
+// segment's flag of each chain; after the barrier wavefront 0 waits (bounded)
+// for the flag of (nu, tau) and wavefront 1 for those of (theta_l, sigma_l^2).
+// The hyperparameter workgroups have the lowest indices and wait for nothing,
+// so they are dispatched and finish whatever the other workgroups do.
 // ---------------------------------------------------------------------------
 constexpr int64_t kHyperSpins = 1 << 22;   // polls before a wait is abandoned (flag bit 4)
 
-// Polls are relaxed device-scope loads (no cache invalidation per poll); one
-// acquire fence after the flag is seen orders the hyperparameter reads after it.
-__device__ inline void wait_hyper(const SegInfo &S, int64_t m, int *err)
+// Waits until the flags of chains c0..c1 hold at least m.  Polls are relaxed
+// device-scope loads (no cache invalidation per poll); one acquire fence after
+// the flags are seen orders the hyperparameter reads after them.
+__device__ inline void wait_hyper(const SegInfo &S, int64_t m, int c0, int c1, int *err)
 {
     int64_t spins = 0;
-    while (__hip_atomic_load(S.hyp_flag, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) < m) {
-        if (++spins > kHyperSpins) {
-            if ((threadIdx.x & 63) == 0) raise_flag(err, 4);
-            break;
+    for (int c = c0; c <= c1; ++c) {
+        while (__hip_atomic_load(&S.hyp_flag[c], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) < m) {
+            if (++spins > kHyperSpins) {
+                if ((threadIdx.x & 63) == 0) raise_flag(err, 4);
+                c = c1;
+                break;
+            }
+            __builtin_amdgcn_s_sleep(8);
         }
-        __builtin_amdgcn_s_sleep(8);
     }
     __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "agent");
 }
 
 template <typename T, int kML>
 __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(4, 8))) void sweep_tile(const SegInfo *__restrict__ segs, const int2 *__restrict__ tiles,
-                                                  int ntiles, SweepArgs a0, int nhyp, SweepArgs ha, int *err)
+                                                  int ntiles, SweepArgs a0, int nhyp, int hsplit, SweepArgs ha,
+                                                  int *err)
 {
     const SweepArgs a = resolve_args(a0);
     if ((int)blockIdx.x < nhyp) {
-        hyper_block(segs[blockIdx.x], resolve_args(ha), err, a.m);
+        const int b = (int)blockIdx.x;
+        if (hsplit == 1) hyper_block(segs[b], resolve_args(ha), err, a.m);
+        else hyper_chain(segs[b / hsplit], resolve_args(ha), err, b % hsplit, a.m);
         return;
     }
     const int tix = (int)blockIdx.x - nhyp;
@@ -2281,7 +2295,10 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(4, 8))) voi
     eps_wave<T>(S, tile, n0, n1, a, err, se, sx);
     __syncthreads();
     if (wave >= 2) return;
-    if (nhyp > 0) wait_hyper(S, a.m, err);
+    if (nhyp > 0) {
+        if (wave == 0) wait_hyper(S, a.m, 0, 0, err);
+        else wait_hyper(S, a.m, 1, S.L, err);
+    }
     const int64_t g = (int64_t)tile * kTile + lane;
     if (wave == 0) gamma_wave<T, kML>(S, tile, a, err, se);
     else beta_genes<T, 0, kML>(S, g, g < S.G, tile, false, a, nullptr, err, sx);
@@ -2313,24 +2330,27 @@ hipError_t launch_eps(int precision, const SegInfo *segs, const int4 *items, int
 
 // maxN: the largest N over the segments (LDS: new eps and exp(h + eps) of a tile)
 hipError_t launch_tile(int precision, int maxL, int maxN, const SegInfo *segs, const int2 *tiles, int ntiles,
-                       const SweepArgs &a, int nhyp, const SweepArgs &ha, int *err, hipStream_t st)
+                       const SweepArgs &a, int nhyp_seg, int hsplit, const SweepArgs &ha, int *err, hipStream_t st)
 {
+    const int nhyp = nhyp_seg * hsplit;
     const int blocks = nhyp + ntiles;
     if (blocks == 0) return hipSuccess;
     const dim3 grid((unsigned)blocks), block(256);
     if (precision == 0) {
         const size_t lds = 2 * (size_t)maxN * kTile * sizeof(double);
         if (maxL <= 5)
-            hipLaunchKernelGGL((sweep_tile<double, 5>), grid, block, lds, st, segs, tiles, ntiles, a, nhyp, ha, err);
+            hipLaunchKernelGGL((sweep_tile<double, 5>), grid, block, lds, st, segs, tiles, ntiles, a, nhyp, hsplit, ha,
+                               err);
         else
-            hipLaunchKernelGGL((sweep_tile<double, kMaxL>), grid, block, lds, st, segs, tiles, ntiles, a, nhyp, ha,
+            hipLaunchKernelGGL((sweep_tile<double, kMaxL>), grid, block, lds, st, segs, tiles, ntiles, a, nhyp, hsplit, ha,
                                err);
     } else {
         const size_t lds = 2 * (size_t)maxN * kTile * sizeof(float);
         if (maxL <= 5)
-            hipLaunchKernelGGL((sweep_tile<float, 5>), grid, block, lds, st, segs, tiles, ntiles, a, nhyp, ha, err);
+            hipLaunchKernelGGL((sweep_tile<float, 5>), grid, block, lds, st, segs, tiles, ntiles, a, nhyp, hsplit, ha,
+                               err);
         else
-            hipLaunchKernelGGL((sweep_tile<float, kMaxL>), grid, block, lds, st, segs, tiles, ntiles, a, nhyp, ha,
+            hipLaunchKernelGGL((sweep_tile<float, kMaxL>), grid, block, lds, st, segs, tiles, ntiles, a, nhyp, hsplit, ha,
                                err);
     }
     return hipGetLastError();

@@ -46,28 +46,56 @@ __global__ void mfma_probe(const float *A, const float *B, float *C)
 
 // C[M][N] = (accumulate ? C : 0) + op(A) op(B), op(A) is M x K, op(B) is K x N.
 // A is [M][lda] (or [K][lda] read transposed when tA), B is [K][ldb] (or [N][ldb]
-// when tB).  M, N multiples of 32 and K a multiple of 16; one wavefront per
-// 32 x 32 tile of C.
-__global__ __launch_bounds__(64) void gemm_bf16(const float *__restrict__ A, int lda, int tA,
-                                                const float *__restrict__ B, int ldb, int tB,
-                                                float *__restrict__ C, int ldc, int M, int N, int K,
-                                                int accumulate)
+// when tB).  M, N multiples of 32 and K a multiple of 16.  One workgroup of
+// kSplit wavefronts per 32 x 32 tile of C: wavefront w takes the k-steps
+// w, w + kSplit, ... (16 columns of op(A) each), and the partial tiles are
+// added in wavefront order through LDS, so a long K (the weight gradients,
+// K = minibatch) runs on kSplit times as many wavefronts in a fixed order.
+template <int kSplit>
+__global__ __launch_bounds__(64 * kSplit) void gemm_bf16(const float *__restrict__ A, int lda, int tA,
+                                                         const float *__restrict__ B, int ldb, int tB,
+                                                         float *__restrict__ C, int ldc, int M, int N, int K,
+                                                         int accumulate)
 {
     const int tilesN = N / 32;
     const int m0 = (int)(blockIdx.x / tilesN) * 32, n0 = (int)(blockIdx.x % tilesN) * 32;
-    if (m0 >= M) return;
-    const int lane = (int)threadIdx.x;
+    if (m0 >= M) return;      // the whole workgroup
+    const int wave = (int)(threadIdx.x >> 6), lane = (int)(threadIdx.x & 63);
     const int i = lane & 31, h = lane >> 5;
     floatx16 acc = {};
-    for (int k0 = 0; k0 < K; k0 += 16) {
+    for (int k0 = 16 * wave; k0 < K; k0 += 16 * kSplit) {
         float a[8], b[8];
+        const int kb = k0 + 8 * h;
+        if (tA) {
 #pragma unroll
-        for (int j = 0; j < 8; ++j) {
-            const int k = k0 + 8 * h + j;
-            a[j] = tA ? A[(int64_t)k * lda + m0 + i] : A[(int64_t)(m0 + i) * lda + k];
-            b[j] = tB ? B[(int64_t)(n0 + i) * ldb + k] : B[(int64_t)k * ldb + n0 + i];
+            for (int j = 0; j < 8; ++j) a[j] = A[(int64_t)(kb + j) * lda + m0 + i];
+        } else {
+            const float4 *p = reinterpret_cast<const float4 *>(A + (int64_t)(m0 + i) * lda + kb);
+            const float4 u = p[0], v = p[1];
+            a[0] = u.x; a[1] = u.y; a[2] = u.z; a[3] = u.w; a[4] = v.x; a[5] = v.y; a[6] = v.z; a[7] = v.w;
+        }
+        if (tB) {
+            const float4 *p = reinterpret_cast<const float4 *>(B + (int64_t)(n0 + i) * ldb + kb);
+            const float4 u = p[0], v = p[1];
+            b[0] = u.x; b[1] = u.y; b[2] = u.z; b[3] = u.w; b[4] = v.x; b[5] = v.y; b[6] = v.z; b[7] = v.w;
+        } else {
+#pragma unroll
+            for (int j = 0; j < 8; ++j) b[j] = B[(int64_t)(kb + j) * ldb + n0 + i];
         }
         acc = __builtin_amdgcn_mfma_f32_32x32x16_bf16(to_bf16x8(a), to_bf16x8(b), acc, 0, 0, 0);
+    }
+    if constexpr (kSplit > 1) {
+        __shared__ float part[kSplit - 1][16][64];
+        if (wave > 0) {
+#pragma unroll
+            for (int r = 0; r < 16; ++r) part[wave - 1][r][lane] = acc[r];
+        }
+        __syncthreads();
+        if (wave > 0) return;
+        for (int w = 0; w < kSplit - 1; ++w) {
+#pragma unroll
+            for (int r = 0; r < 16; ++r) acc[r] += part[w][r][lane];
+        }
     }
 #pragma unroll
     for (int r = 0; r < 16; ++r) {
@@ -117,7 +145,10 @@ __global__ void nll_grad(const float *O, int Op, const float *T, int L, const fl
     const float invB = 1.0f / (float)B;
     const float *o = O + (int64_t)b * Op;
     float *g = dO + (int64_t)b * Op;
-    for (int j = 0; j < Op; ++j) g[j] = 0.0f;
+    // zero the row beyond the used outputs as float4s (Op is a multiple of 4
+    // and rows are 16-byte aligned); the used ones are written below
+    const int used = 2 * L + L * (L - 1) / 2;
+    for (int j = used & ~3; j < Op; j += 4) *reinterpret_cast<float4 *>(g + j) = make_float4(0.0f, 0.0f, 0.0f, 0.0f);
     float u[8], v[8], dg[8];
     float tot = 0.0f;
     for (int l = 0; l < L; ++l) {
@@ -232,11 +263,23 @@ __global__ __launch_bounds__(256) void mean_rows(const float *v, int64_t n, floa
     if (t == 0) *out = (float)(part[0] / (double)n);
 }
 
+// Wavefronts per tile: at least four k-steps each, at most 16.
 static hipError_t gemm(const float *A, int lda, int tA, const float *B, int ldb, int tB, float *C, int ldc, int M,
                        int N, int K, hipStream_t st)
 {
     const int tiles = (M / 32) * (N / 32);
-    hipLaunchKernelGGL(gemm_bf16, dim3(tiles), dim3(64), 0, st, A, lda, tA, B, ldb, tB, C, ldc, M, N, K, 0);
+    const int steps = K / 16;
+    const dim3 grid((unsigned)tiles);
+    if (steps >= 64)
+        hipLaunchKernelGGL(gemm_bf16<16>, grid, dim3(1024), 0, st, A, lda, tA, B, ldb, tB, C, ldc, M, N, K, 0);
+    else if (steps >= 32)
+        hipLaunchKernelGGL(gemm_bf16<8>, grid, dim3(512), 0, st, A, lda, tA, B, ldb, tB, C, ldc, M, N, K, 0);
+    else if (steps >= 16)
+        hipLaunchKernelGGL(gemm_bf16<4>, grid, dim3(256), 0, st, A, lda, tA, B, ldb, tB, C, ldc, M, N, K, 0);
+    else if (steps >= 8)
+        hipLaunchKernelGGL(gemm_bf16<2>, grid, dim3(128), 0, st, A, lda, tA, B, ldb, tB, C, ldc, M, N, K, 0);
+    else
+        hipLaunchKernelGGL(gemm_bf16<1>, grid, dim3(64), 0, st, A, lda, tA, B, ldb, tB, C, ldc, M, N, K, 0);
     return hipGetLastError();
 }
 

@@ -75,8 +75,6 @@ struct TrainBufs {
 hipError_t mlp_forward_backward(const float *master, const TrainBufs &t, int L, hipStream_t st);
 
 __global__ void mfma_probe(const float *A, const float *B, float *C);
-__global__ void gemm_bf16(const float *A, int lda, int tA, const float *B, int ldb, int tB, float *C,
-                          int ldc, int M, int N, int K, int accumulate);
 __global__ void bias_gelu(float *Z, const float *bias, float *H, int rows, int cols, int apply_gelu);
 __global__ void gelu_backward(const float *Z, const float *dH, float *dZ, int64_t n);
 __global__ void nll_grad(const float *O, int Op, const float *T, int L, const float *omean,

@@ -73,6 +73,9 @@ extern "C" int fb_mlp_loss_grad_noalloc(const float *master, int32_t L, const fl
     char msg[160];
     if (!master || !phi || !target || !loss || !grad)
         return fail_noalloc(FB_EINVAL, "fb_mlp_loss_grad_noalloc: a buffer pointer is NULL");
+    // the weight blocks are read as float4 rows
+    if (reinterpret_cast<uintptr_t>(master) % 16 != 0)
+        return fail_noalloc(FB_EINVAL, "fb_mlp_loss_grad_noalloc: master is not 16-byte aligned");
     if (L < 1 || L > FB_MAX_L) {
         std::snprintf(msg, sizeof msg, "fb_mlp_loss_grad_noalloc: L = %d outside 1..%d", (int)L, FB_MAX_L);
         return fail_noalloc(FB_EINVAL, msg);

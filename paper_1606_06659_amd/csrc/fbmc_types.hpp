@@ -12,6 +12,7 @@ constexpr int kMaxRows = 8;    // distinct rows of X
 constexpr int kMaxVals = 4;    // distinct non-zero values per column
 constexpr int kTile = 64;      // genes per wavefront tile
 constexpr int kMaxParts = 2 + 2 * kMaxL;
+constexpr int kHypFlags = 1 + kMaxL;     // chains of hyperparameter draws: (nu, tau), (theta_l, sigma_l^2)
 constexpr int kKindShift = 11;  // Philox kind and update_mask bit of the shift step
 constexpr int kKindExact = 12;  // update_mask bit of the exact conjugate draws (gamma, tau, sigma^2)
 constexpr int kKindTop = 13;    // Philox kind of the top-level draws (three-level form)
@@ -100,9 +101,10 @@ struct SegInfo {
     int32_t *imh_last;            // [Gp] last sweep: 1 accepted, 0 rejected, -1 slice
     float *pairs;                 // training pairs [capacity][kPairStride]: features, beta
     const TopState *top;          // three-level form: the chain's top level (b, psi), else null
-    // single-launch sweep: the sweep index whose hyperparameter values the
-    // segment's HyperState holds, published by the hyperparameter step that
-    // runs in the first workgroups of that launch
+    // single-launch sweep: per chain of hyperparameter draws c (0: nu, tau;
+    // 1 + l: theta_l, sigma_l^2), the sweep index whose values of that chain
+    // the segment's HyperState holds, published by the hyperparameter step
+    // that runs in the first workgroups of that launch ([kHypFlags])
     int64_t *hyp_flag;
 };
 

@@ -73,4 +73,9 @@ def test_noalloc_rejects_sizes_beyond_the_scratch():
     with pytest.raises(F.FbError):
         F.fb_mlp_loss_grad_noalloc(master.data_ptr(), 9, phi.data_ptr(), tgt.data_ptr(), 64, loss.data_ptr(),
                                    grad.data_ptr(), 0)
+    # a weight block that is not 16-byte aligned is rejected on the host
+    with pytest.raises(F.FbError) as ei:
+        F.fb_mlp_loss_grad_noalloc(master.data_ptr() + 4, L, phi.data_ptr(), tgt.data_ptr(), 64, loss.data_ptr(),
+                                   grad.data_ptr(), 0)
+    assert ei.value.code == F.FB_EINVAL
     torch.cuda.synchronize()
