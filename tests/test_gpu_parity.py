@@ -309,7 +309,7 @@ def test_determinism_and_resume():
 # (samples per eps wavefront, fused hyperparameter step, single-launch sweep,
 # one workgroup per chain of hyperparameter draws)
 SHAPES = [(1, 1, 0, 1), (1, 0, 0, 1), (3, 1, 0, 1), (16, 0, 0, 1), (16, 1, 0, 1), (4, 1, 1, 1), (4, 0, 1, 1),
-          (4, 1, 0, 0), (4, 0, 0, 0)]
+          (4, 1, 0, 0), (4, 0, 0, 0), (4, 1, 1, 0)]
 
 
 @pytest.mark.parametrize("precision,shift", [(0, 0), (1, 0), (1, 1)])
