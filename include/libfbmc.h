@@ -123,6 +123,18 @@ typedef struct {
     int32_t debug_counts;   /* 1: keep per-draw integer records of the last sweep */
     int32_t jitter;         /* 1: chains > 0 start from seeded jittered values */
     void *stream;           /* hipStream_t to use, or NULL */
+    /* Device memory of the context (its arrays, and the temporaries of
+     * fb_autotune and fb_features): with both NULL (the default) the library
+     * calls hipMalloc and hipFree; otherwise the caller's allocator, e.g.
+     * PyTorch's caching allocator: dev_alloc(bytes, alloc_user) returns
+     * device memory of the current device, 256-byte aligned, or NULL
+     * (FB_ENOMEM); dev_free(ptr, alloc_user) takes back what dev_alloc gave,
+     * after the context's stream has finished using it (fb_destroy
+     * synchronises first).  Set both or neither (FB_EINVAL).  The functions
+     * must stay callable until fb_destroy returns. */
+    void *(*dev_alloc)(size_t bytes, void *alloc_user);
+    void (*dev_free)(void *ptr, void *alloc_user);
+    void *alloc_user;
 } fb_options;
 
 /* One dataset of a batch: counts [G][N] (row g = gene), X [N][L], h [N]. */

@@ -174,16 +174,43 @@ int fail(fb_ctx *c, int code, const std::string &msg)
             return fail((ctx), FB_EDEVICE, std::string(#expr) + ": " + hipGetErrorString(e_)); \
     } while (0)
 
-int dalloc(fb_ctx *c, void **p, size_t bytes)
+// Device memory from the context's allocator (fb_options.dev_alloc) or hipMalloc.
+static int dmem(fb_ctx *c, void **p, size_t bytes)
 {
     *p = nullptr;
     if (bytes == 0) bytes = 256;
+    if (c->opt.dev_alloc) {
+        *p = c->opt.dev_alloc(bytes, c->opt.alloc_user);
+        if (!*p) return fail(c, FB_ENOMEM, "dev_alloc returned NULL");
+        if (reinterpret_cast<uintptr_t>(*p) % 256 != 0) {
+            c->opt.dev_free(*p, c->opt.alloc_user);
+            *p = nullptr;
+            return fail(c, FB_EINVAL, "dev_alloc returned memory that is not 256-byte aligned");
+        }
+        return FB_OK;
+    }
     hipError_t e = hipMalloc(p, bytes);
     if (e != hipSuccess) {
         *p = nullptr;
         return fail(c, FB_ENOMEM, std::string("hipMalloc: ") + hipGetErrorString(e));
     }
+    return FB_OK;
+}
+
+static void dfree(fb_ctx *c, void *p)
+{
+    if (!p) return;
+    if (c->opt.dev_free) c->opt.dev_free(p, c->opt.alloc_user);
+    else (void)hipFree(p);
+}
+
+int dalloc(fb_ctx *c, void **p, size_t bytes)
+{
+    int rc = dmem(c, p, bytes);
+    if (rc) return rc;
+    if (bytes == 0) bytes = 256;
     c->allocs.push_back(*p);
+    hipError_t e;
     e = hipMemset(*p, 0, bytes);
     if (e != hipSuccess) return fail(c, FB_EDEVICE, std::string("hipMemset: ") + hipGetErrorString(e));
     return FB_OK;
@@ -413,6 +440,10 @@ int validate_options(const fb_options &o, std::string &msg)
     }
     if (!(o.w0 > 0) || !std::isfinite(o.w0)) { msg = "w0 must be a positive finite number"; return FB_EINVAL; }
     if (o.shrink_cap < 1) { msg = "shrink_cap must be >= 1"; return FB_EINVAL; }
+    if ((o.dev_alloc == nullptr) != (o.dev_free == nullptr)) {
+        msg = "set both dev_alloc and dev_free, or neither";
+        return FB_EINVAL;
+    }
     if (o.precision != FB_FP64 && o.precision != FB_FP32) { msg = "unknown precision"; return FB_EINVAL; }
     if (o.thin < 0 || o.trace_genes < 0 || o.trace_capacity < 0) { msg = "negative trace option"; return FB_EINVAL; }
     return FB_OK;
@@ -1123,7 +1154,7 @@ void fb_destroy(fb_ctx *c)
         if (c->gcopied[i]) (void)hipEventDestroy(c->gcopied[i]);
     }
     for (hipEvent_t e : c->prof_ev) (void)hipEventDestroy(e);
-    for (void *p : c->allocs) (void)hipFree(p);
+    for (void *p : c->allocs) dfree(c, p);
     if (c->ev0) (void)hipEventDestroy(c->ev0);
     if (c->ev1) (void)hipEventDestroy(c->ev1);
     if (c->own_stream && c->st) (void)hipStreamDestroy(c->st);
@@ -1748,7 +1779,7 @@ int fb_autotune(fb_ctx *c, int32_t trial_sweeps, int32_t *samples_per_wave, int3
     size_t total = 0;
     for (auto &b : bufs) total += (b.second + 255) / 256 * 256;
     char *snap = nullptr;
-    if (hipMalloc((void **)&snap, total) != hipSuccess) return fail(c, FB_ENOMEM, "hipMalloc (autotune snapshot)");
+    if (int rcm = dmem(c, (void **)&snap, total)) return rcm;
     auto copy_all = [&](bool save) -> hipError_t {
         size_t off = 0;
         for (auto &b : bufs) {
@@ -1832,7 +1863,8 @@ int fb_autotune(fb_ctx *c, int32_t trial_sweeps, int32_t *samples_per_wave, int3
     c->tile = best_tile;
     c->m = m0;
     if (e == hipSuccess) e = copy_all(false);
-    (void)hipFree(snap);
+    if (e == hipSuccess) e = hipStreamSynchronize(c->st);
+    dfree(c, snap);
     if (e != hipSuccess) return fail(c, FB_EDEVICE, std::string("autotune: ") + hipGetErrorString(e));
     if (rc) return rc;
     c->fuse = best_fuse;
@@ -2085,11 +2117,11 @@ int fb_features(fb_ctx *c, int32_t seg, float *phi)
     SegmentH &S = c->seg[seg];
     float *d = nullptr;
     HIPCHK(c, hipStreamSynchronize(c->st));
-    if (hipMalloc((void **)&d, (size_t)S.G * 32 * sizeof(float)) != hipSuccess) return fail(c, FB_ENOMEM, "hipMalloc");
+    if (int rcm = dmem(c, (void **)&d, (size_t)S.G * 32 * sizeof(float))) return rcm;
     hipError_t e = launch_features(c->prec, c->d_segs + seg, S.G, d, c->st);
     if (e == hipSuccess) e = hipStreamSynchronize(c->st);
     if (e == hipSuccess) e = hipMemcpy(phi, d, (size_t)S.G * 32 * sizeof(float), hipMemcpyDeviceToHost);
-    (void)hipFree(d);
+    dfree(c, d);
     if (e != hipSuccess) return fail(c, FB_EDEVICE, std::string("fb_features: ") + hipGetErrorString(e));
     return FB_OK;
 }

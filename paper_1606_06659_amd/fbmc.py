@@ -38,13 +38,37 @@ class fb_priors(C.Structure):
                 ("c", C.POINTER(C.c_double)), ("s", C.POINTER(C.c_double))]
 
 
+DEV_ALLOC_FN = C.CFUNCTYPE(C.c_void_p, C.c_size_t, C.c_void_p)
+DEV_FREE_FN = C.CFUNCTYPE(None, C.c_void_p, C.c_void_p)
+
+
 class fb_options(C.Structure):
     _fields_ = [("chains", C.c_int32), ("burnin", C.c_int64), ("tune_start", C.c_int64),
                 ("max_steps", C.c_int32), ("w0", C.c_double), ("shrink_cap", C.c_int32),
                 ("precision", C.c_int32), ("update_mask", C.c_uint32), ("thin", C.c_int32),
                 ("trace_genes", C.c_int32), ("trace_after_burnin", C.c_int32),
                 ("trace_capacity", C.c_int64), ("debug_counts", C.c_int32),
-                ("jitter", C.c_int32), ("stream", C.c_void_p)]
+                ("jitter", C.c_int32), ("stream", C.c_void_p),
+                ("dev_alloc", DEV_ALLOC_FN), ("dev_free", DEV_FREE_FN), ("alloc_user", C.c_void_p)]
+
+
+def torch_allocator(stream=None):
+    """(dev_alloc, dev_free) for fb_options that take a context's device
+    memory from PyTorch's caching allocator, on `stream` (a torch.cuda.Stream,
+    or None for the current stream).  Keep both objects alive until the
+    context is destroyed (Sampler does)."""
+    import torch
+
+    def _alloc(nbytes, _user):
+        try:
+            return torch.cuda.caching_allocator_alloc(int(nbytes), stream=stream)
+        except RuntimeError:
+            return None
+
+    def _free(ptr, _user):
+        torch.cuda.caching_allocator_delete(ptr)
+
+    return DEV_ALLOC_FN(_alloc), DEV_FREE_FN(_free)
 
 
 class fb_dataset(C.Structure):
@@ -481,8 +505,14 @@ def fb_autotune(ctx, trial_sweeps: int = 20):
 class Sampler:
     """One libfbmc context.  Datasets are (counts, X, h) arrays; see fb_create."""
 
-    def __init__(self, counts=None, X=None, h=None, *, priors=None, seed=0, datasets=None, **options):
+    def __init__(self, counts=None, X=None, h=None, *, priors=None, seed=0, datasets=None, torch_memory=False,
+                 **options):
+        """torch_memory: take the context's device memory from PyTorch's
+        caching allocator (on the options' stream, else the current one)."""
         self.options = fb_default_options(**options)
+        if torch_memory:
+            self._allocator = torch_allocator(self.options.stream or None)
+            self.options.dev_alloc, self.options.dev_free = self._allocator
         if datasets is not None:
             self.ctx = fb_create_batch(datasets, self.options)
         else:

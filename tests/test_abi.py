@@ -75,3 +75,22 @@ def test_new_entry_points_reject_a_null_context():
     assert lib.fb_set_top(None, 0, C.c_double(1.0), None) == fbmc.FB_EINVAL
     assert lib.fb_get_top(None, 0, None, None, None, None, None) == fbmc.FB_EINVAL
     assert lib.fb_set_beta_update(None, fbmc.FB_BETA_LAPLACE) == fbmc.FB_EINVAL
+
+
+def test_allocator_callbacks_must_come_in_pairs():
+    """fb_options.dev_alloc without dev_free (or the reverse) is rejected
+    before any device call."""
+    import numpy as np
+    from paper_1606_06659_amd import fbmc
+    y = np.ones((4, 2), np.int32)
+    X = np.ones((2, 1))
+    h = np.zeros(2)
+    for which in ("dev_alloc", "dev_free"):
+        opts = fbmc.fb_default_options()
+        if which == "dev_alloc":
+            opts.dev_alloc = fbmc.DEV_ALLOC_FN(lambda n, u: None)
+        else:
+            opts.dev_free = fbmc.DEV_FREE_FN(lambda p, u: None)
+        with pytest.raises(fbmc.FbError) as ei:
+            fbmc.fb_create(y, X, h, options=opts)
+        assert ei.value.code == fbmc.FB_EINVAL and "dev_alloc" in str(ei.value)
