@@ -44,7 +44,7 @@ hipError_t launch_mlp_infer_raw(const float *phi, int64_t B, int L, const MlpDev
 hipError_t launch_features(int precision, const SegInfo *seg, int64_t G, float *out, hipStream_t st);
 hipError_t launch_gather_pairs(const float *pairs, int64_t P, int L, const float *master, float *X, float *Tg,
                                int B, uint32_t epoch, uint32_t step, uint32_t k0, uint32_t k1, hipStream_t st);
-hipError_t launch_col_moments(const float *M, int64_t rows, int cols, double *out, hipStream_t st);
+hipError_t launch_col_moments(const float *M, int64_t rows, int cols, double *work, double *out, hipStream_t st);
 }  // namespace fbmc
 
 using namespace fbmc;
@@ -1938,9 +1938,10 @@ int fb_proposal_train(fb_ctx *c, const fb_train_opts *opts, double *epoch_loss)
     const int64_t P = c->pair_n;
     HIPCHK(c, hipStreamSynchronize(c->st));
     // standardisation from the pairs
-    double *d_mom = nullptr;
+    double *d_mom = nullptr, *d_momw = nullptr;
     if ((rc = dalloc(c, (void **)&d_mom, 2 * kPairStride * sizeof(double)))) return rc;
-    HIPCHK(c, launch_col_moments(c->d_pairs, P, kPairStride, d_mom, c->st));
+    if ((rc = dalloc(c, (void **)&d_momw, 2 * (size_t)kPairStride * kColChunks * sizeof(double)))) return rc;
+    HIPCHK(c, launch_col_moments(c->d_pairs, P, kPairStride, d_momw, d_mom, c->st));
     std::vector<double> mom(2 * kPairStride);
     HIPCHK(c, hipMemcpyAsync(mom.data(), d_mom, mom.size() * sizeof(double), hipMemcpyDeviceToHost, c->st));
     HIPCHK(c, hipStreamSynchronize(c->st));
@@ -1974,10 +1975,12 @@ int fb_proposal_train(fb_ctx *c, const fb_train_opts *opts, double *epoch_loss)
     const int steps = o.pairs_per_epoch / o.minibatch;
     const float b1 = 0.9f, b2 = 0.999f, eps = 1e-8f;
     int64_t it = 0;
-    std::vector<float> lossv(o.minibatch);
+    // per-epoch sums of the per-row losses, added on the device after each
+    // step (no host round trip inside the loop)
+    double *d_esum = nullptr;
+    if (epoch_loss && (rc = dalloc(c, (void **)&d_esum, (size_t)o.epochs * sizeof(double)))) return rc;
     const int64_t nopt = kOffOmean - kOffW1;   // W1 .. b3 are trained
     for (int e = 0; e < o.epochs; ++e) {
-        double esum = 0.0;
         for (int sidx = 0; sidx < steps; ++sidx) {
             HIPCHK(c, launch_gather_pairs(c->d_pairs, P, L, c->d_master, t.X, t.Tg, o.minibatch, (uint32_t)e,
                                           (uint32_t)sidx, (uint32_t)o.seed, (uint32_t)(o.seed >> 32), c->st));
@@ -1989,12 +1992,17 @@ int fb_proposal_train(fb_ctx *c, const fb_train_opts *opts, double *epoch_loss)
                                b1, b2, eps, c1, c2);
             HIPCHK(c, hipGetLastError());
             if (epoch_loss) {
-                HIPCHK(c, hipMemcpyAsync(lossv.data(), t.loss, lossv.size() * sizeof(float), hipMemcpyDeviceToHost, c->st));
-                HIPCHK(c, hipStreamSynchronize(c->st));
-                for (float v : lossv) esum += v;
+                hipLaunchKernelGGL(sum_rows_into, dim3(1), dim3(256), 0, c->st, t.loss, (int64_t)o.minibatch,
+                                   d_esum + e);
+                HIPCHK(c, hipGetLastError());
             }
         }
-        if (epoch_loss) epoch_loss[e] = esum / ((double)steps * o.minibatch);
+    }
+    if (epoch_loss) {
+        std::vector<double> es((size_t)o.epochs);
+        HIPCHK(c, hipMemcpyAsync(es.data(), d_esum, es.size() * sizeof(double), hipMemcpyDeviceToHost, c->st));
+        HIPCHK(c, hipStreamSynchronize(c->st));
+        for (int e = 0; e < o.epochs; ++e) epoch_loss[e] = es[(size_t)e] / ((double)steps * o.minibatch);
     }
     HIPCHK(c, hipMemcpyAsync(blk.data(), c->d_master, kMlpParams * sizeof(float), hipMemcpyDeviceToHost, c->st));
     HIPCHK(c, hipStreamSynchronize(c->st));

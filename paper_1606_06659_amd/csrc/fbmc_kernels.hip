@@ -1722,12 +1722,18 @@ __global__ void gather_pairs(const float *__restrict__ pairs, int64_t P, int L, 
     for (int l = 0; l < L; ++l) Tg[(int64_t)i * L + l] = clip_feature(row[32 + l]);
 }
 
-// Column sums and sums of squares (FP64) of a row-major [rows][cols] float array.
-__global__ void col_moments(const float *__restrict__ M, int64_t rows, int cols, double *out)
+// Column sums and sums of squares (FP64) of a row-major [rows][cols] float
+// array, in two passes: block (c, k) sums column c over the k-th of kColChunks
+// row ranges (thread t: rows t, t + 256, ... of the range in order, then a
+// fixed-order tree) into part[(c kColChunks + k) 2 + {0, 1}]; col_moments_sum
+// adds the chunks of a column in order.  The blocks of a row range share its
+// cache lines.
+__global__ __launch_bounds__(256) void col_moments(const float *__restrict__ M, int64_t rows, int cols, double *part)
 {
-    const int c = (int)blockIdx.x;
+    const int c = (int)blockIdx.x, k = (int)blockIdx.y;
+    const int64_t r0 = rows * k / kColChunks, r1 = rows * (k + 1) / kColChunks;
     double s = 0.0, q = 0.0;
-    for (int64_t r = threadIdx.x; r < rows; r += blockDim.x) {
+    for (int64_t r = r0 + threadIdx.x; r < r1; r += blockDim.x) {
         const double v = M[r * cols + c];
         s += v;
         q += v * v;
@@ -1743,7 +1749,23 @@ __global__ void col_moments(const float *__restrict__ M, int64_t rows, int cols,
         }
         __syncthreads();
     }
-    if (threadIdx.x == 0) { out[2 * c] = sh[0][0]; out[2 * c + 1] = sh[1][0]; }
+    if (threadIdx.x == 0) {
+        part[2 * ((int64_t)c * kColChunks + k)] = sh[0][0];
+        part[2 * ((int64_t)c * kColChunks + k) + 1] = sh[1][0];
+    }
+}
+
+__global__ void col_moments_sum(const double *__restrict__ part, int cols, double *out)
+{
+    const int c = (int)(blockIdx.x * blockDim.x + threadIdx.x);
+    if (c >= cols) return;
+    double s = 0.0, q = 0.0;
+    for (int k = 0; k < kColChunks; ++k) {
+        s += part[2 * ((int64_t)c * kColChunks + k)];
+        q += part[2 * ((int64_t)c * kColChunks + k) + 1];
+    }
+    out[2 * c] = s;
+    out[2 * c + 1] = q;
 }
 
 hipError_t launch_mlp_infer_raw(const float *phi, int64_t B, int L, const MlpDev *net, float *mu, float *ls,
@@ -1787,9 +1809,11 @@ hipError_t launch_gather_pairs(const float *pairs, int64_t P, int L, const float
     return hipGetLastError();
 }
 
-hipError_t launch_col_moments(const float *M, int64_t rows, int cols, double *out, hipStream_t st)
+// work: 2 cols kColChunks doubles
+hipError_t launch_col_moments(const float *M, int64_t rows, int cols, double *work, double *out, hipStream_t st)
 {
-    hipLaunchKernelGGL(col_moments, dim3(cols), dim3(256), 0, st, M, rows, cols, out);
+    hipLaunchKernelGGL(col_moments, dim3(cols, kColChunks), dim3(256), 0, st, M, rows, cols, work);
+    hipLaunchKernelGGL(col_moments_sum, dim3((cols + 63) / 64), dim3(64), 0, st, work, cols, out);
     return hipGetLastError();
 }
 

@@ -63,26 +63,46 @@ __global__ __launch_bounds__(64 * kSplit) void gemm_bf16(const float *__restrict
     const int wave = (int)(threadIdx.x >> 6), lane = (int)(threadIdx.x & 63);
     const int i = lane & 31, h = lane >> 5;
     floatx16 acc = {};
-    for (int k0 = 16 * wave; k0 < K; k0 += 16 * kSplit) {
-        float a[8], b[8];
-        const int kb = k0 + 8 * h;
-        if (tA) {
+    // the operands of up to kGroup k-steps are loaded before their MFMAs (as
+    // BF16 fragments), so a wavefront waits for memory once per group rather
+    // than once per step
+    constexpr int kGroup = 4;
+#pragma unroll 1
+    for (int g0 = 16 * wave; g0 < K; g0 += 16 * kSplit * kGroup) {
+        bf16x8 fa[kGroup], fb[kGroup];
 #pragma unroll
-            for (int j = 0; j < 8; ++j) a[j] = A[(int64_t)(kb + j) * lda + m0 + i];
-        } else {
-            const float4 *p = reinterpret_cast<const float4 *>(A + (int64_t)(m0 + i) * lda + kb);
-            const float4 u = p[0], v = p[1];
-            a[0] = u.x; a[1] = u.y; a[2] = u.z; a[3] = u.w; a[4] = v.x; a[5] = v.y; a[6] = v.z; a[7] = v.w;
-        }
-        if (tB) {
-            const float4 *p = reinterpret_cast<const float4 *>(B + (int64_t)(n0 + i) * ldb + kb);
-            const float4 u = p[0], v = p[1];
-            b[0] = u.x; b[1] = u.y; b[2] = u.z; b[3] = u.w; b[4] = v.x; b[5] = v.y; b[6] = v.z; b[7] = v.w;
-        } else {
+        for (int q = 0; q < kGroup; ++q) {
+            const int kb = g0 + 16 * kSplit * q + 8 * h;
+            float a[8], b[8];
 #pragma unroll
-            for (int j = 0; j < 8; ++j) b[j] = B[(int64_t)(kb + j) * ldb + n0 + i];
+            for (int j = 0; j < 8; ++j) {
+                a[j] = 0.0f;
+                b[j] = 0.0f;
+            }
+            if (kb < K) {
+                if (tA) {
+#pragma unroll
+                    for (int j = 0; j < 8; ++j) a[j] = A[(int64_t)(kb + j) * lda + m0 + i];
+                } else {
+                    const float4 *p = reinterpret_cast<const float4 *>(A + (int64_t)(m0 + i) * lda + kb);
+                    const float4 u = p[0], v = p[1];
+                    a[0] = u.x; a[1] = u.y; a[2] = u.z; a[3] = u.w; a[4] = v.x; a[5] = v.y; a[6] = v.z; a[7] = v.w;
+                }
+                if (tB) {
+                    const float4 *p = reinterpret_cast<const float4 *>(B + (int64_t)(n0 + i) * ldb + kb);
+                    const float4 u = p[0], v = p[1];
+                    b[0] = u.x; b[1] = u.y; b[2] = u.z; b[3] = u.w; b[4] = v.x; b[5] = v.y; b[6] = v.z; b[7] = v.w;
+                } else {
+#pragma unroll
+                    for (int j = 0; j < 8; ++j) b[j] = B[(int64_t)(kb + j) * ldb + n0 + i];
+                }
+            }
+            fa[q] = to_bf16x8(a);
+            fb[q] = to_bf16x8(b);
         }
-        acc = __builtin_amdgcn_mfma_f32_32x32x16_bf16(to_bf16x8(a), to_bf16x8(b), acc, 0, 0, 0);
+#pragma unroll
+        for (int q = 0; q < kGroup; ++q)
+            if (g0 + 16 * kSplit * q < K) acc = __builtin_amdgcn_mfma_f32_32x32x16_bf16(fa[q], fb[q], acc, 0, 0, 0);
     }
     if constexpr (kSplit > 1) {
         __shared__ float part[kSplit - 1][16][64];
@@ -263,16 +283,33 @@ __global__ __launch_bounds__(256) void mean_rows(const float *v, int64_t n, floa
     if (t == 0) *out = (float)(part[0] / (double)n);
 }
 
-// Wavefronts per tile: at least four k-steps each, at most 16.
+// Wavefronts per tile: at least four k-steps each, at most 8 (512 threads keep
+// the register budget above what a group of four k-steps needs).
+// *acc += sum of v[0..n): one 256-thread workgroup; thread t sums v[t],
+// v[t + 256], ... in FP64 in order, then a fixed-order tree in LDS.  Training
+// adds each minibatch's per-row losses to its epoch's slot on the device.
+__global__ __launch_bounds__(256) void sum_rows_into(const float *v, int64_t n, double *acc)
+{
+    __shared__ double part[256];
+    const int t = (int)threadIdx.x;
+    double s = 0.0;
+    for (int64_t i = t; i < n; i += 256) s += (double)v[i];
+    part[t] = s;
+    __syncthreads();
+    for (int w = 128; w > 0; w >>= 1) {
+        if (t < w) part[t] += part[t + w];
+        __syncthreads();
+    }
+    if (t == 0) *acc += part[0];
+}
+
 static hipError_t gemm(const float *A, int lda, int tA, const float *B, int ldb, int tB, float *C, int ldc, int M,
                        int N, int K, hipStream_t st)
 {
     const int tiles = (M / 32) * (N / 32);
     const int steps = K / 16;
     const dim3 grid((unsigned)tiles);
-    if (steps >= 64)
-        hipLaunchKernelGGL(gemm_bf16<16>, grid, dim3(1024), 0, st, A, lda, tA, B, ldb, tB, C, ldc, M, N, K, 0);
-    else if (steps >= 32)
+    if (steps >= 32)
         hipLaunchKernelGGL(gemm_bf16<8>, grid, dim3(512), 0, st, A, lda, tA, B, ldb, tB, C, ldc, M, N, K, 0);
     else if (steps >= 16)
         hipLaunchKernelGGL(gemm_bf16<4>, grid, dim3(256), 0, st, A, lda, tA, B, ldb, tB, C, ldc, M, N, K, 0);

@@ -84,6 +84,7 @@ __global__ void pack_mlp(const float *master, MlpDev *out);
 __global__ void fill_f32(float *p, int64_t n, float v);
 __global__ void standardise_rows(const float *phi, const float *master, float *X, int64_t B);
 __global__ void mean_rows(const float *v, int64_t n, float *out);
+__global__ void sum_rows_into(const float *v, int64_t n, double *acc);
 __global__ void adam_step(float *p, const float *g, float *m, float *v, int64_t n, float lr, float b1,
                           float b2, float eps, float c1, float c2);
 

@@ -12,7 +12,8 @@ constexpr int kMaxRows = 8;    // distinct rows of X
 constexpr int kMaxVals = 4;    // distinct non-zero values per column
 constexpr int kTile = 64;      // genes per wavefront tile
 constexpr int kMaxParts = 2 + 2 * kMaxL;
-constexpr int kHypFlags = 1 + kMaxL;     // chains of hyperparameter draws: (nu, tau), (theta_l, sigma_l^2)
+constexpr int kHypFlags = 1 + kMaxL;
+constexpr int kColChunks = 128;          // row ranges of the pairs' column moments (launch_col_moments)     // chains of hyperparameter draws: (nu, tau), (theta_l, sigma_l^2)
 constexpr int kKindShift = 11;  // Philox kind and update_mask bit of the shift step
 constexpr int kKindExact = 12;  // update_mask bit of the exact conjugate draws (gamma, tau, sigma^2)
 constexpr int kKindTop = 13;    // Philox kind of the top-level draws (three-level form)
