@@ -100,9 +100,12 @@ def test_fp64_three_level_partial_top(oracle_lib, top_mask):
 
 
 def test_three_level_graph_replay_matches_direct(oracle_lib):
+    """Graph replay with the hyperparameter step on one workgroup per segment
+    equals direct launches with one workgroup per chain of draws."""
     F, a, _ = _pair(oracle_lib, chains=2)
     _, b, _ = _pair(oracle_lib, chains=2)
     F.fb_set_graph(b, 6)
+    F.fb_set_hyper_split(b, 0)
     for n in (12, 7, 13):
         F.fb_sweep(a, n)
         F.fb_sweep(b, n)
