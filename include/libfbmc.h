@@ -364,8 +364,9 @@ int32_t fb_get_beta_lanes(const fb_ctx *c);
  * theta_l then sigma_l^2), each reducing only the two partial sums it needs,
  * so the chains run at once; on = 0 runs the whole step on one workgroup per
  * segment.  The sums are added in the same order either way, so no choice
- * changes any draw.  fb_get_hyper_split returns the setting (0 for NULL).
- * Errors: FB_EINVAL. */
+ * changes any draw.  fb_autotune leaves the setting as it is (the split was
+ * faster or level at every measured shape).  fb_get_hyper_split returns the
+ * setting (0 for NULL).  Errors: FB_EINVAL. */
 int fb_set_hyper_split(fb_ctx *c, int32_t on);
 int32_t fb_get_hyper_split(const fb_ctx *c);
 int fb_get_launch(const fb_ctx *c, int32_t *samples_per_wave, int32_t *fuse_hyper);
