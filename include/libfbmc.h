@@ -181,7 +181,11 @@ void fb_destroy(fb_ctx *c);
  * by n).  Returns FB_ENUMERIC if an earlier sweep raised the numeric flag. */
 int fb_sweep(fb_ctx *c, int64_t n);
 
-/* Wait for all enqueued work; returns the sticky error status. */
+/* Wait for all enqueued work; returns the sticky error status.  When a slice
+ * draw reached the shrink cap (FB_ENUMERIC), fb_last_error names the first
+ * such draw: its kind (eps, gamma, beta, hyperparameter), dataset, chain,
+ * gene, sweep and index (the sample n for eps; for a hyperparameter 0 for
+ * the (nu, tau) draws, 1 + l for (theta_l, sigma_l^2)). */
 int fb_sync(fb_ctx *c);
 
 /* Number of segments, and the shape of segment seg. */
