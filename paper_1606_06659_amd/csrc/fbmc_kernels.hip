@@ -1034,6 +1034,10 @@ __global__ __launch_bounds__(128) void gb_sweep(const SegInfo *__restrict__ segs
         if (wave == 0) {
             gamma_wave<T, kML>(S, tile, a, err);
         } else {
+            // the beta wavefront is the workgroup's longer chain: it gets the
+            // SIMD's issue slots first (paper design G = 50,000: 34.0 -> 33.5 us;
+            // with the shift step, gb_shift_sweep, no gain, so not there)
+            __builtin_amdgcn_s_setprio(3);
             const int64_t g = (int64_t)tile * kTile + lane;
             beta_genes<T, kMode, kML>(S, g, g < S.G, tile, false, a, net, err);
         }
