@@ -1053,6 +1053,24 @@ void block_to_mlp(const std::vector<float> &blk, fb_mlp *w)
     put(w->oscale, kOffOscale, 8);
 }
 
+// Device memory that one call allocates for its own use (dalloc after the
+// scope opens) and gives back when the call returns, after the stream has
+// finished with it.
+struct TempScope {
+    fb_ctx *c;
+    size_t mark;
+    explicit TempScope(fb_ctx *ctx) : c(ctx), mark(ctx->allocs.size()) {}
+    ~TempScope()
+    {
+        if (c->allocs.size() <= mark) return;
+        if (c->st) (void)hipStreamSynchronize(c->st);
+        for (size_t i = mark; i < c->allocs.size(); ++i) dfree(c, c->allocs[i]);
+        c->allocs.resize(mark);
+    }
+    TempScope(const TempScope &) = delete;
+    TempScope &operator=(const TempScope &) = delete;
+};
+
 // Scratch of one forward/backward pass on B rows.
 int alloc_train(fb_ctx *c, TrainBufs &t, int B, int L)
 {
@@ -1934,6 +1952,9 @@ int fb_proposal_train(fb_ctx *c, const fb_train_opts *opts, double *epoch_loss)
     if (c->pair_n < 2) return fail(c, FB_ESTATE, "no training pairs: call fb_proposal_collect first");
     int rc;
     if ((rc = ensure_net(c))) return rc;
+    // the moments, Adam state, minibatch buffers and loss sums of this call
+    // are given back when it returns
+    TempScope scratch_of_call(c);
     const int L = c->seg[0].L;
     const int64_t P = c->pair_n;
     HIPCHK(c, hipStreamSynchronize(c->st));

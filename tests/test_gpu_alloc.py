@@ -83,3 +83,23 @@ def test_allocator_failures_are_errors():
     assert ei.value.code == F.FB_EINVAL
     assert not held
     torch.cuda.synchronize()
+
+
+def test_training_gives_its_scratch_back():
+    """fb_proposal_train's temporaries (moments, Adam state, minibatch buffers,
+    loss sums) go back to the allocator when the call returns: training twice
+    on a context on PyTorch's memory leaves the same amount allocated."""
+    F = require_gpu()
+    import torch
+    ds = datagen.paper_design_16(G=2000, seed=3)
+    s = F.Sampler(ds.y, ds.X, ds.h, seed=5, burnin=100, tune_start=10, precision=1, torch_memory=True)
+    s.sweep(50)
+    F.fb_proposal_collect(s.ctx, 40, every=2)
+    opts = F.fb_default_train_opts(epochs=3)
+    F.fb_proposal_train(s.ctx, opts)
+    torch.cuda.synchronize()
+    after_first = torch.cuda.memory_allocated()
+    F.fb_proposal_train(s.ctx, opts)
+    torch.cuda.synchronize()
+    assert torch.cuda.memory_allocated() == after_first
+    s.close()
