@@ -130,8 +130,11 @@ typedef struct {
      * device memory of the current device, 256-byte aligned, or NULL
      * (FB_ENOMEM); dev_free(ptr, alloc_user) takes back what dev_alloc gave,
      * after the context's stream has finished using it (fb_destroy
-     * synchronises first).  Set both or neither (FB_EINVAL).  The functions
-     * must stay callable until fb_destroy returns. */
+     * synchronises first).  The library synchronises the device after each
+     * dev_alloc, so a block that a caching allocator hands out while work of
+     * its previous user is still queued on another stream is safe to use.
+     * Set both or neither (FB_EINVAL).  The functions must stay callable
+     * until fb_destroy returns. */
     void *(*dev_alloc)(size_t bytes, void *alloc_user);
     void (*dev_free)(void *ptr, void *alloc_user);
     void *alloc_user;

@@ -187,6 +187,16 @@ static int dmem(fb_ctx *c, void **p, size_t bytes)
             *p = nullptr;
             return fail(c, FB_EINVAL, "dev_alloc returned memory that is not 256-byte aligned");
         }
+        // a caching allocator may hand out a block whose previous user's work
+        // is still queued on another stream: let it finish before this
+        // context's stream (or a synchronous copy) touches the block
+        // (allocations are rare: context set-up, autotuning, training)
+        const hipError_t e = hipDeviceSynchronize();
+        if (e != hipSuccess) {
+            c->opt.dev_free(*p, c->opt.alloc_user);
+            *p = nullptr;
+            return fail(c, FB_EDEVICE, std::string("hipDeviceSynchronize: ") + hipGetErrorString(e));
+        }
         return FB_OK;
     }
     hipError_t e = hipMalloc(p, bytes);
