@@ -238,16 +238,17 @@ def run_chain(fbmc, diagnostics, ds, args, burnin, post, do_ess, stream, learned
     t1 = time.perf_counter()
     kt = fbmc.fb_kernel_times(smp.ctx)
     fbmc.fb_profile(smp.ctx, 0, 0)
-    if learned or laplace:
-        last = fbmc.fb_imh_last(smp.ctx)
-        imh = last >= 0
-        proposal["accept_rate_last_sweep"] = float(np.mean(last[imh] == 1)) if imh.any() else None
     rest = post - args.warmup - args.steps
     if rest > 0:
         smp.sweep(rest)
     smp.sync()
     torch.cuda.synchronize()
     t_post1 = time.perf_counter()
+    if learned or laplace:
+        # IMH acceptance over every post-burn-in sweep (the library's counts)
+        sm = fbmc.fb_summaries(smp.ctx)
+        steps = int(sm["imh_steps"].sum())
+        proposal["accept_rate"] = float(sm["imh_accepts"].sum()) / steps if steps else None
     ess_info = None
     if do_ess:
         tr, dropped = smp.trace()
@@ -327,8 +328,9 @@ def run_heavy_forms(fbmc, diagnostics, stream, iters=10_000, trace_genes=250):
         torch.cuda.synchronize()
         t1 = time.perf_counter()
         if base != "plain":
-            last = fbmc.fb_imh_last(smp.ctx)
-            info["accept_last_sweep"] = float(np.mean(last[last >= 0] == 1))
+            sms = [fbmc.fb_summaries(smp.ctx, c) for c in range(C)]
+            steps = sum(int(m["imh_steps"].sum()) for m in sms)
+            info["accept_rate"] = sum(float(m["imh_accepts"].sum()) for m in sms) / steps if steps else None
         tr = np.stack([smp.trace(c)[0] for c in range(C)])              # [C, M, stride]
         smp.close()
         M = tr.shape[1]

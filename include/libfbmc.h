@@ -215,11 +215,20 @@ int fb_set_state(fb_ctx *c, int32_t seg, const fb_state *s);
 
 /* Running means and means of squares (FP64) of one segment, same shapes as
  * fb_state; count = number of sweeps averaged (m - M_B once m > M_B).  Clears
- * nothing.  NULL pointers skip a block. */
+ * nothing.  NULL pointers skip a block.
+ * Acceptance statistics of the independence-MH beta step (Section 2.1's
+ * remark on independence proposals; fb_set_beta_update), per gene [G]:
+ * imh_steps = sampling sweeps (m > M_B) in which beta_g took the IMH step,
+ * imh_accepts = how many of those steps accepted the proposal; their ratio is
+ * the gene's acceptance rate.  Genes on the slice steps (plain sweep, fallback
+ * genes) count no steps; the slice draws themselves always move.  The counts
+ * restart, as the moments do, with the first sampling sweep after fb_set_state
+ * sets m <= M_B; zero before the IMH step is first configured. */
 typedef struct {
     double *mean_eps, *msq_eps, *mean_gam, *msq_gam, *mean_beta, *msq_beta;
     double *mean_hyp, *msq_hyp;
     int64_t count;
+    int64_t *imh_steps, *imh_accepts;
 } fb_summary;
 
 int fb_summaries(fb_ctx *c, int32_t seg, fb_summary *s);

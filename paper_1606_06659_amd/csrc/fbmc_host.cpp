@@ -956,6 +956,7 @@ int ensure_learned(fb_ctx *c)
         if ((rc = dalloc(c, (void **)&I.fallback, Gp * sizeof(int32_t)))) return rc;
         if ((rc = dalloc(c, (void **)&I.imh_count, Gp * sizeof(int32_t)))) return rc;
         if ((rc = dalloc(c, (void **)&I.imh_last, Gp * sizeof(int32_t)))) return rc;
+        if ((rc = dalloc(c, (void **)&I.imh_stat, Gp * sizeof(int2)))) return rc;
         if ((rc = dalloc(c, (void **)&I.fb_genes, Gp * sizeof(int32_t)))) return rc;
         if ((rc = dalloc(c, (void **)&I.mlp_out, Gp * (size_t)mlp_outputs(S.L) * sizeof(float)))) return rc;
         I.nfbw = 0;
@@ -1357,6 +1358,11 @@ int fb_set_state(fb_ctx *c, int32_t seg, const fb_state *s)
     c->m = s->m;
     // the sweep index may go back: clear what the single-launch sweep waits on
     for (auto &Sg : c->seg) HIPCHK(c, hipMemset(Sg.info.hyp_flag, 0, kHypFlags * sizeof(int64_t)));
+    // back in burn-in: the acceptance counts restart with the next sampling
+    // sweep, as the running moments do
+    if (c->m <= c->opt.burnin)
+        for (auto &Sg : c->seg)
+            if (Sg.info.imh_stat) HIPCHK(c, hipMemset(Sg.info.imh_stat, 0, (size_t)Sg.Gp * sizeof(int2)));
     return FB_OK;
 }
 
@@ -1387,6 +1393,15 @@ int fb_summaries(fb_ctx *c, int32_t seg, fb_summary *s)
     for (int j = 0; j < 2 + 2 * L; ++j) {
         if (s->mean_hyp) s->mean_hyp[j] = H.mom[j].x;
         if (s->msq_hyp) s->msq_hyp[j] = H.mom[j].y;
+    }
+    if (s->imh_steps || s->imh_accepts) {
+        std::vector<int2> st((size_t)G, make_int2(0, 0));
+        if (S.info.imh_stat)
+            HIPCHK(c, hipMemcpy(st.data(), S.info.imh_stat, st.size() * sizeof(int2), hipMemcpyDeviceToHost));
+        for (int64_t g = 0; g < G; ++g) {
+            if (s->imh_steps) s->imh_steps[g] = st[(size_t)g].x;
+            if (s->imh_accepts) s->imh_accepts[g] = st[(size_t)g].y;
+        }
     }
     s->count = c->m > c->opt.burnin ? c->m - c->opt.burnin : 0;
     return c->sticky;
@@ -1788,6 +1803,7 @@ void sweep_buffers(fb_ctx *c, std::vector<std::pair<void *, size_t>> &out)
         if (I.imh_last) {
             out.push_back({(void *)I.imh_count, Gp * sizeof(int32_t)});
             out.push_back({(void *)I.imh_last, Gp * sizeof(int32_t)});
+            out.push_back({(void *)I.imh_stat, Gp * sizeof(int2)});
         }
     }
     out.push_back({(void *)c->d_err, kErrWordsHost * sizeof(int)});

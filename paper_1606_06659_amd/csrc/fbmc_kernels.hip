@@ -990,6 +990,12 @@ __device__ inline void beta_genes(const SegInfo &S, int64_t g, bool active, int6
                         beta_imh_draw<T, kML>(S, a, g, Gp, beta, thT, is2, C, YR, bh, U, dinv, net, om, ol, oo);
                     S.imh_last[g] = acc;
                     if (a.count_imh) S.imh_count[g] += acc;
+                    if (a.m > a.burnin) {        // acceptance statistics of the sampling sweeps
+                        int2 st = S.imh_stat[g];
+                        st.x += 1;
+                        st.y += acc;
+                        S.imh_stat[g] = st;
+                    }
                 } else {
                     beta_slice_draws<T, kML>(S, a, g, Gp, true, beta, wb, wab, th, s2, C, YR, tuning, bad);
                     S.imh_last[g] = -1;

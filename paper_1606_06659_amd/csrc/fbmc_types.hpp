@@ -100,6 +100,7 @@ struct SegInfo {
     int32_t *fallback;            // [Gp] 1 = slice step for beta_g
     int32_t *imh_count;           // [Gp] accepted IMH steps while counting
     int32_t *imh_last;            // [Gp] last sweep: 1 accepted, 0 rejected, -1 slice
+    int2 *imh_stat;               // [Gp] over the sweeps m > M_B: (IMH steps taken, accepted)
     float *pairs;                 // training pairs [capacity][kPairStride]: features, beta
     const TopState *top;          // three-level form: the chain's top level (b, psi), else null
     // single-launch sweep: per chain of hyperparameter draws c (0: nu, tau;

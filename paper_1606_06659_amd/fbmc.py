@@ -88,7 +88,8 @@ class fb_state(C.Structure):
 
 class fb_summary(C.Structure):
     _fields_ = [(k, _DP) for k in ("mean_eps", "msq_eps", "mean_gam", "msq_gam", "mean_beta",
-                                   "msq_beta", "mean_hyp", "msq_hyp")] + [("count", C.c_int64)]
+                                   "msq_beta", "mean_hyp", "msq_hyp")] + [("count", C.c_int64)] + \
+                [(k, C.POINTER(C.c_int64)) for k in ("imh_steps", "imh_accepts")]
 
 
 class fb_top_priors(C.Structure):
@@ -306,9 +307,11 @@ def fb_summaries(ctx, seg: int = 0) -> dict:
                mean_hyp=np.empty(2 + 2 * L), msq_hyp=np.empty(2 + 2 * L))
     keys = ("mean_eps", "msq_eps", "mean_gam", "msq_gam", "mean_beta", "msq_beta", "mean_hyp",
             "msq_hyp")
-    s = fb_summary(*[_p(out[k]) for k in keys], 0)
+    steps, accepts = np.empty(G, np.int64), np.empty(G, np.int64)
+    s = fb_summary(*[_p(out[k]) for k in keys], 0, _p(steps, C.c_int64), _p(accepts, C.c_int64))
     _check(load().fb_summaries(ctx, seg, C.byref(s)), ctx, (FB_ENUMERIC,))
     out["count"] = int(s.count)
+    out["imh_steps"], out["imh_accepts"] = steps, accepts
     return out
 
 

@@ -170,6 +170,7 @@ def test_imh_sweep_parity_fp64(oracle_lib):
     F.fb_set_beta_update(g, F.FB_BETA_LEARNED)
     o.set_proposal(m, np.zeros(ds.G, np.int32))
     n_acc = 0
+    acc_gene = np.zeros(ds.G, np.int64)
     for it in range(20):
         o.sweep(1)
         F.fb_sweep(g, 1)
@@ -179,9 +180,14 @@ def test_imh_sweep_parity_fp64(oracle_lib):
         flips = np.flatnonzero(acc_o != acc_g)
         assert flips.size == 0, (it, flips[:5], la_o[flips[:5]])
         n_acc += int(np.sum(acc_o == 1))
+        acc_gene += acc_o == 1
         for k in ("eps", "gam", "beta", "hyp"):
             np.testing.assert_allclose(sg[k], so[k], rtol=1e-9, atol=1e-12, err_msg=f"sweep {it} {k}")
     assert 0 < n_acc < 20 * ds.G
+    # acceptance statistics: all 20 sweeps are past burn-in, every gene took the IMH step
+    sm = F.fb_summaries(g)
+    assert np.all(sm["imh_steps"] == 20)
+    assert np.array_equal(sm["imh_accepts"], acc_gene)
     F.fb_destroy(g)
 
 
@@ -212,6 +218,7 @@ def test_imh_sweep_parity_with_fallback_genes_fp64(oracle_lib, shift):
     F.fb_fallback(g, 0, mask)
     F.fb_set_beta_update(g, F.FB_BETA_LEARNED)
     o.set_proposal(m, mask)
+    steps, accepts = np.zeros(ds.G, np.int64), np.zeros(ds.G, np.int64)
     for it in range(12):
         o.sweep(1)
         F.fb_sweep(g, 1)
@@ -220,11 +227,22 @@ def test_imh_sweep_parity_with_fallback_genes_fp64(oracle_lib, shift):
         acc_g = F.fb_imh_last(g)
         assert np.array_equal(acc_o, acc_g), (it, np.flatnonzero(acc_o != acc_g)[:5])
         assert np.all(acc_g[mask == 1] == -1) and np.all(acc_g[mask == 0] >= 0)
+        if 8 + it > 10:          # sweeps m > M_B count toward the acceptance statistics
+            steps += acc_o >= 0
+            accepts += acc_o == 1
         for k in ("eps", "gam", "beta", "hyp", "w_beta", "waux_beta"):
             np.testing.assert_allclose(sg[k], so[k], rtol=1e-9, atol=1e-12, err_msg=f"sweep {it} {k}")
         np.testing.assert_allclose(F.fb_reductions(g), o.reductions(), rtol=1e-9, atol=1e-9)
     sm, om = F.fb_summaries(g), o.moments()
     np.testing.assert_allclose(sm["mean_beta"], om["mean_beta"], rtol=1e-9, atol=1e-12)
+    # the oracle's decisions over the sampling sweeps; fallback genes take no IMH step
+    assert np.array_equal(sm["imh_steps"], steps) and np.array_equal(sm["imh_accepts"], accepts)
+    assert np.all(steps[mask == 1] == 0) and np.all(steps[mask == 0] == 9)
+    # back to burn-in: the counts restart
+    st = F.fb_get_state(g)
+    st["m"] = 5
+    F.fb_set_state(g, st)
+    assert not F.fb_summaries(g)["imh_steps"].any()
     F.fb_destroy(g)
 
 
