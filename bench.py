@@ -356,7 +356,7 @@ def run_heavy_forms(fbmc, diagnostics, stream, iters=10_000, trace_genes=250):
     return out
 
 
-def run_heavy(fbmc, stream, steps=100, burnin=300):
+def run_heavy(fbmc, stream, steps=100, burnin=300, launch="auto"):
     """Secondary measurement: the large heavy-tailed workload, 4 chains x
     G = 200,000 x N = 48 (about 30% zero counts), one context, FP32; a short
     burn-in tunes the widths, the autotuner picks the launch shape, then
@@ -371,7 +371,11 @@ def run_heavy(fbmc, stream, steps=100, burnin=300):
     smp = fbmc.Sampler(ds.y, ds.X, ds.h, seed=1, **{k: getattr(opts, k) for k, *_ in opts._fields_})
     smp.sweep(burnin + 10)
     smp.sync()
-    spw, fuse, _, _ = fbmc.fb_autotune(smp.ctx, 10)
+    if launch == "auto":
+        spw, fuse, _, _ = fbmc.fb_autotune(smp.ctx, 10)
+    else:
+        spw, fuse = (int(v) for v in launch.split(","))
+        fbmc.fb_set_launch(smp.ctx, spw, fuse)
     fbmc.fb_profile(smp.ctx, 5, steps // 5 + 1)
     smp.sync()
     torch.cuda.synchronize()
@@ -529,7 +533,8 @@ def main():
     ap.add_argument("--three-level-only", action="store_true",
                     help="run only the three-level workload and print its record (profiling runs)")
     ap.add_argument("--launch", default="auto",
-                    help="'auto' (autotuner) or 'SPW,FUSE': samples per eps wavefront, fused hyper step 0/1")
+                    help="'auto' (autotuner) or 'SPW,FUSE': samples per eps wavefront, fused hyper step 0/1 "
+                         "(the paper-design chains; with --heavy-only the heavy workload)")
     ap.add_argument("--burnin", type=int, default=BURNIN,
                     help="burn-in sweeps (profiling runs shorten it; the bench line uses the default)")
     ap.add_argument("--copy-mib", type=int, default=0,
@@ -565,7 +570,8 @@ def main():
         print(json.dumps({"three_level_workload": run_three_level(fbmc, stream)}), flush=True)
         return
     if args.heavy_only:
-        print(json.dumps({"heavy_workload": run_heavy(fbmc, stream, steps=args.steps, burnin=args.burnin)}),
+        print(json.dumps({"heavy_workload": run_heavy(fbmc, stream, steps=args.steps, burnin=args.burnin,
+                                                      launch=args.launch)}),
               flush=True)
         return
     def run(learned, shift, exact=False, laplace=False):
