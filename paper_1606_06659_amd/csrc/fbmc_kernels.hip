@@ -70,7 +70,10 @@ struct GamF {
     }
 };
 
-template <typename T>
+// kForm fixes the column's form at compile time so the slice loop carries no
+// branch on it: 0 reads nv and pm at run time, 1 one non-zero value, -1 the
+// +-v form (float); the arithmetic is the same in every form.
+template <typename T, int kForm = 0>
 struct BetaF {
     T Y, x0, dth, inv_s2;
     T Gk[kMaxVals], vk[kMaxVals];
@@ -81,7 +84,10 @@ struct BetaF {
     __device__ T operator()(T x) {
         const T d = x - x0;
         T s = Y * d - d * (dth + (T)0.5 * d) * inv_s2;
-        if (std::is_same<T, float>::value && pm) {
+        if constexpr (kForm == 1) {
+            em1[0] = dexpm1(vk[0] * d);
+            s -= Gk[0] * em1[0];
+        } else if (std::is_same<T, float>::value && (kForm == -1 || (kForm == 0 && pm))) {
             // expm1(-v d) = -e / (1 + e) with e = expm1(v d): one exponential
             // for a +-v column (both rounding errors are a few ulp)
             const T e = dexpm1(vk[0] * d);
@@ -252,6 +258,31 @@ __device__ inline void gene_features(const SegInfo &S, const T (&A)[kMaxRows], c
     }
 }
 
+// One slice draw of a beta coefficient with the column's form fixed (kForm of
+// BetaF); em1 at the accepted point is handed back in f.
+template <int kForm, typename T>
+__device__ inline T beta_draw_as(BetaF<T> &f, T b0, T w, uint32_t k0, uint32_t k1, uint4 ctr, int K, int cap,
+                                 DrawRec &rec)
+{
+    BetaF<T, kForm> h;
+    h.Y = f.Y;
+    h.x0 = f.x0;
+    h.dth = f.dth;
+    h.inv_s2 = f.inv_s2;
+    h.nv = f.nv;
+    h.pm = f.pm;
+#pragma unroll
+    for (int k = 0; k < kMaxVals; ++k) {
+        h.Gk[k] = f.Gk[k];
+        h.vk[k] = f.vk[k];
+        h.em1[k] = f.em1[k];
+    }
+    const T b1 = slice_draw<T>(h, b0, w, k0, k1, ctr, K, cap, rec);
+#pragma unroll
+    for (int k = 0; k < kMaxVals; ++k) f.em1[k] = h.em1[k];
+    return b1;
+}
+
 // Algorithm 1 step 5 by slice draws: beta_g1..beta_gL in order, each moving
 // the row sums C_r to the new coefficient; only `lead` lanes store.  kPair:
 // two lanes per gene draw together (slice_draw_pair); the factor
@@ -309,8 +340,16 @@ __device__ inline void beta_slice_draws(const SegInfo &S, const SweepArgs &a, in
         DrawRec rec;
         const uint4 ctr = draw_counter((uint32_t)g, 5, (uint32_t)l, mm, (uint32_t)S.chain, 0);
         T b1;
-        if constexpr (kPair) b1 = slice_draw_pair<T>(f, b0, w, S.key0, S.key1, ctr, a.K, a.cap, rec);
-        else b1 = slice_draw<T>(f, b0, w, S.key0, S.key1, ctr, a.K, a.cap, rec);
+        if constexpr (kPair) {
+            b1 = slice_draw_pair<T>(f, b0, w, S.key0, S.key1, ctr, a.K, a.cap, rec);
+        } else if constexpr (std::is_same<T, float>::value) {
+            // the column's form is uniform over the wavefront: pick the loop once
+            if (f.pm) b1 = beta_draw_as<-1>(f, b0, w, S.key0, S.key1, ctr, a.K, a.cap, rec);
+            else if (f.nv == 1) b1 = beta_draw_as<1>(f, b0, w, S.key0, S.key1, ctr, a.K, a.cap, rec);
+            else b1 = slice_draw<T>(f, b0, w, S.key0, S.key1, ctr, a.K, a.cap, rec);
+        } else {
+            b1 = slice_draw<T>(f, b0, w, S.key0, S.key1, ctr, a.K, a.cap, rec);
+        }
         if (tuning) {
             tune_width<T>(w, wa, b0, b1, a.m, a.burnin, a.tune_start);
             if (lead) {
