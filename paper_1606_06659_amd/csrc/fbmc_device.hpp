@@ -174,6 +174,40 @@ __device__ inline T slice_draw(F &f, T x0, T w, uint32_t k0, uint32_t k1, uint4 
     return x1;
 }
 
+// The value held by the even (odd) lane of this lane's pair (2j, 2j + 1):
+// DPP quad permutations [0, 0, 2, 2] and [1, 1, 3, 3], a register move inside
+// each group of four lanes instead of a round trip through the LDS crossbar.
+__device__ inline uint32_t pair_even_u32(uint32_t v)
+{
+    return (uint32_t)__builtin_amdgcn_update_dpp(0, (int)v, 0xA0, 0xF, 0xF, false);
+}
+__device__ inline uint32_t pair_odd_u32(uint32_t v)
+{
+    return (uint32_t)__builtin_amdgcn_update_dpp(0, (int)v, 0xF5, 0xF, 0xF, false);
+}
+template <typename T> __device__ inline T pair_even(T v)
+{
+    if constexpr (sizeof(T) == 4) {
+        return __builtin_bit_cast(T, pair_even_u32(__builtin_bit_cast(uint32_t, v)));
+    } else {
+        uint2 u = __builtin_bit_cast(uint2, v);
+        u.x = pair_even_u32(u.x);
+        u.y = pair_even_u32(u.y);
+        return __builtin_bit_cast(T, u);
+    }
+}
+template <typename T> __device__ inline T pair_odd(T v)
+{
+    if constexpr (sizeof(T) == 4) {
+        return __builtin_bit_cast(T, pair_odd_u32(__builtin_bit_cast(uint32_t, v)));
+    } else {
+        uint2 u = __builtin_bit_cast(uint2, v);
+        u.x = pair_odd_u32(u.x);
+        u.y = pair_odd_u32(u.y);
+        return __builtin_bit_cast(T, u);
+    }
+}
+
 // The same draw by a pair of lanes (2j and 2j + 1, which hold the same
 // variable and the same f).  The step-out to the left (even lane) and to the
 // right (odd lane) do not depend on each other and run at the same time.  In
@@ -182,14 +216,13 @@ __device__ inline T slice_draw(F &f, T x0, T w, uint32_t k0, uint32_t k1, uint4 
 // update of the interval depends only on the candidate and x0); the first
 // candidate in the slice is the sequential result.  Points, decisions, the
 // result and the counters are those of slice_draw; both lanes return them,
-// and both must call (the mates exchange values with __shfl).
+// and both must call (the mates exchange values by DPP, pair_even / pair_odd).
 template <typename T, typename F>
 __device__ inline T slice_draw_pair(F &f, T x0, T w, uint32_t k0, uint32_t k1, uint4 ctr, int K, int cap,
                                     DrawRec &rec)
 {
     const int lane = (int)(threadIdx.x & 63);
     const bool odd = (lane & 1) != 0;
-    const int even_lane = lane & ~1, odd_lane = lane | 1;
     uint4 r = philox4x32_10(ctr, k0, k1);
     const T thr = f.base(x0) + dlog(u01<T>(r.x));
     const T v = w * uwin<T>(r.y);
@@ -206,8 +239,8 @@ __device__ inline T slice_draw_pair(F &f, T x0, T w, uint32_t k0, uint32_t k1, u
         e = odd ? e + w : e - w;
         ++ns;
     }
-    T L = __shfl(e, even_lane, 64), R = __shfl(e, odd_lane, 64);
-    const int nl = __shfl(ns, even_lane, 64), nr = __shfl(ns, odd_lane, 64);
+    T L = pair_even(e), R = pair_odd(e);
+    const int nl = (int)pair_even_u32((uint32_t)ns), nr = (int)pair_odd_u32((uint32_t)ns);
     // shrink: candidates t + 1 and t + 2 read words t + 2 and t + 3 of the
     // draw's stream (t even, so both sit in one Philox block)
     T x1 = x0;
@@ -226,7 +259,7 @@ __device__ inline T slice_draw_pair(F &f, T x0, T w, uint32_t k0, uint32_t k1, u
         const T La = ga ? L : xa, Ra = ga ? xa : R;
         const T xb = La + ub * (Ra - La);
         const int in = f(odd ? xb : xa) > thr ? 1 : 0;
-        const int in_a = __shfl(in, even_lane, 64), in_b = __shfl(in, odd_lane, 64);
+        const int in_a = (int)pair_even_u32((uint32_t)in), in_b = (int)pair_odd_u32((uint32_t)in);
         if (in_a) { x1 = xa; t += 1; break; }
         if (t + 1 >= cap) { t += 1; bad = true; break; }
         if (in_b) { x1 = xb; t += 2; break; }

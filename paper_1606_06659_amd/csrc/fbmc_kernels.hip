@@ -260,7 +260,7 @@ __device__ inline void gene_features(const SegInfo &S, const T (&A)[kMaxRows], c
 
 // One slice draw of a beta coefficient with the column's form fixed (kForm of
 // BetaF); em1 at the accepted point is handed back in f.
-template <int kForm, typename T>
+template <int kForm, bool kPair, typename T>
 __device__ inline T beta_draw_as(BetaF<T> &f, T b0, T w, uint32_t k0, uint32_t k1, uint4 ctr, int K, int cap,
                                  DrawRec &rec)
 {
@@ -277,7 +277,9 @@ __device__ inline T beta_draw_as(BetaF<T> &f, T b0, T w, uint32_t k0, uint32_t k
         h.vk[k] = f.vk[k];
         h.em1[k] = f.em1[k];
     }
-    const T b1 = slice_draw<T>(h, b0, w, k0, k1, ctr, K, cap, rec);
+    T b1;
+    if constexpr (kPair) b1 = slice_draw_pair<T>(h, b0, w, k0, k1, ctr, K, cap, rec);
+    else b1 = slice_draw<T>(h, b0, w, k0, k1, ctr, K, cap, rec);
 #pragma unroll
     for (int k = 0; k < kMaxVals; ++k) f.em1[k] = h.em1[k];
     return b1;
@@ -340,15 +342,13 @@ __device__ inline void beta_slice_draws(const SegInfo &S, const SweepArgs &a, in
         DrawRec rec;
         const uint4 ctr = draw_counter((uint32_t)g, 5, (uint32_t)l, mm, (uint32_t)S.chain, 0);
         T b1;
-        if constexpr (kPair) {
-            b1 = slice_draw_pair<T>(f, b0, w, S.key0, S.key1, ctr, a.K, a.cap, rec);
-        } else if constexpr (std::is_same<T, float>::value) {
+        if constexpr (std::is_same<T, float>::value) {
             // the column's form is uniform over the wavefront: pick the loop once
-            if (f.pm) b1 = beta_draw_as<-1>(f, b0, w, S.key0, S.key1, ctr, a.K, a.cap, rec);
-            else if (f.nv == 1) b1 = beta_draw_as<1>(f, b0, w, S.key0, S.key1, ctr, a.K, a.cap, rec);
-            else b1 = slice_draw<T>(f, b0, w, S.key0, S.key1, ctr, a.K, a.cap, rec);
+            if (f.pm) b1 = beta_draw_as<-1, kPair>(f, b0, w, S.key0, S.key1, ctr, a.K, a.cap, rec);
+            else if (f.nv == 1) b1 = beta_draw_as<1, kPair>(f, b0, w, S.key0, S.key1, ctr, a.K, a.cap, rec);
+            else b1 = beta_draw_as<0, kPair>(f, b0, w, S.key0, S.key1, ctr, a.K, a.cap, rec);
         } else {
-            b1 = slice_draw<T>(f, b0, w, S.key0, S.key1, ctr, a.K, a.cap, rec);
+            b1 = beta_draw_as<0, kPair>(f, b0, w, S.key0, S.key1, ctr, a.K, a.cap, rec);
         }
         if (tuning) {
             tune_width<T>(w, wa, b0, b1, a.m, a.burnin, a.tune_start);
@@ -366,6 +366,13 @@ __device__ inline void beta_slice_draws(const SegInfo &S, const SweepArgs &a, in
         for (int k = 0; k < kMaxVals; ++k) {
             if constexpr (kPair) fac[k] = (rec.bad || k >= f.nv) ? (T)1 : (T)1 + dexpm1(f.vk[k] * (b1 - b0));
             else fac[k] = rec.bad ? (T)1 : (T)1 + f.em1[k];
+        }
+        if constexpr (kPair && std::is_same<T, float>::value) {
+            // a +-v column: the second factor by the evaluation's own route
+            if (f.pm && !rec.bad) {
+                const T e = dexpm1(f.vk[0] * (b1 - b0));
+                fac[1] = (T)1 + -e * (T)__builtin_amdgcn_rcpf((float)((T)1 + e));
+            }
         }
 #pragma unroll
         for (int r = 0; r < kMaxRows; ++r) {
